@@ -1,0 +1,151 @@
+/*
+ * smartlap -- Smart Laplacian smoothing of 2D triangular meshes on MI355X.
+ *
+ * The operation (Zhao, Mei, Xu, Zhang, ICCS 2015, Sec. 2.1 and Sec. 3.3.4):
+ * every free node is moved to the geometric centre of its neighbours
+ * (eq. (2)); the move is kept only if the worst quality among the node's
+ * incident triangles does not drop.  The quality of a triangle (p0,p1,p2),
+ * taken in its stored vertex order, is
+ *     q = (2*sqrt(3) * cr) / S,
+ *     a = p1-p0, b = p2-p0, c = p2-p1,  cr = a.x*b.y - b.x*a.y,
+ *     S = (|a|^2 + |c|^2) + |b|^2,      q = 0 when S == 0,
+ * i.e. 4*sqrt(3)*A / sum(l^2) with A the signed area (1 for an equilateral
+ * CCW triangle, negative for an inverted one).  Every operation is one
+ * IEEE-754 double operation in the order written (no contraction), the
+ * centroid sums the neighbour row in its stored order and divides once by
+ * the neighbour count.
+ *
+ * Forms (Sec. 2.2): SL_JACOBI is Form A, eq. (2) -- every read comes from the
+ * previous pass.  SL_INPLACE_COLORED is Form B, eq. (3) -- the free nodes are
+ * coloured (greedy, in decreasing SplitMix64 priority of the node id, so no
+ * two adjacent free nodes share a colour) and each pass runs the colour
+ * classes in increasing colour, updating in place.
+ *
+ * Conventions for every entry point:
+ *   - Return value: an sl_status; SL_OK is 0, errors are negative.  On any
+ *     error a message is available from sl_last_error() (per thread), and
+ *     output arrays are left untouched.
+ *   - Ownership: the caller owns every array it passes.  The library copies
+ *     or reads them before the call returns and keeps no pointer to them.
+ *     Device memory the library allocates is freed before the call returns
+ *     (or in the matching *_destroy call for handles).
+ *   - Indices are 0-based int32.  Arrays are dense, no padding.
+ */
+#ifndef SMARTLAP_H
+#define SMARTLAP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#if defined(__GNUC__) || defined(__clang__)
+#define SL_API __attribute__((visibility("default")))
+#else
+#define SL_API
+#endif
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    SL_OK = 0,
+    SL_EINVAL = -1,    /* null pointer, size <= 0, non-monotone ptr, index out of range,
+                          iterations < 0, non-finite coordinate, bad option value */
+    SL_ETOPO = -2,     /* self neighbour, triangle with a repeated vertex, incident triangle
+                          not containing its node, a vertex of an incident triangle missing
+                          from the node's neighbour row, free node without neighbours,
+                          valence > 127 (free nodes), asymmetric rows (coloured form) */
+    SL_ENOMEM = -3,    /* device allocation failed or a budget would be exceeded */
+    SL_EDEVICE = -4,   /* a HIP runtime error; text in sl_last_error() */
+    SL_EBUSY = -5,     /* result not ready yet */
+    SL_ECANCELED = -6, /* request was cancelled */
+    SL_ETIMEOUT = -7   /* request passed its deadline */
+} sl_status;
+
+typedef enum { SL_JACOBI = 0, SL_INPLACE_COLORED = 1 } sl_form;
+typedef enum {
+    SL_ACCEPT_GE = 0,  /* accept iff new worst quality >= old worst quality (default) */
+    SL_ACCEPT_GT = 1   /* accept iff it strictly increases */
+} sl_accept;
+typedef enum { SL_AOS = 0, SL_SOA = 1 } sl_layout;   /* coordinate stream on the device */
+typedef enum { SL_REORDER_NONE = 0, SL_REORDER_HILBERT = 1 } sl_reorder;
+
+typedef struct {
+    int32_t form;        /* sl_form */
+    int32_t accept;      /* sl_accept */
+    int32_t layout;      /* sl_layout */
+    int32_t reorder;     /* sl_reorder: node order used on the device; results do not depend on it */
+    int32_t block_size;  /* work-group size for the sweep kernel: 0 = automatic, else 64/128/256 */
+    int32_t reserved;
+    /* Optional accept flags, nullable.  Size iterations * ((n_nodes + 7) / 8)
+     * bytes; sweep k occupies bytes [k*((n+7)/8), (k+1)*((n+7)/8)); bit (i % 8)
+     * of byte (i / 8) is 1 iff free node i accepted its move in sweep k
+     * (0 for fixed nodes and for sweeps that did not run).  Host memory for
+     * smooth_mesh, device memory for smooth_mesh_device. */
+    uint8_t* flags_out;
+} sl_options;
+
+typedef struct {
+    int32_t iterations_run;     /* sweeps executed (<= iterations) */
+    int32_t n_colors;           /* colour classes (coloured form), else 0 */
+    double max_disp_sq_last;    /* largest squared displacement in the last sweep run */
+    int64_t accepted_last;      /* free nodes that accepted in the last sweep run */
+    int64_t accepted_total;     /* summed over all sweeps run */
+    double setup_ms;            /* device time: validation, reorder, relabel, fan build */
+    double sweep_ms;            /* device time of the sweep loop only */
+    double total_ms;            /* host wall time of the whole call */
+} sl_report;
+
+/* Fills *opts with the defaults: Jacobi, GE, AoS, Hilbert reorder, automatic
+ * block size, no flags. */
+SL_API void sl_options_default(sl_options* opts);
+
+/*
+ * smooth_mesh -- iterated Smart Laplacian on one mesh, host arrays.
+ *
+ * coords    in/out, n_nodes x 2 doubles, (x, y) interleaved.  Written only on SL_OK.
+ * n_nodes   >= 1.
+ * nbr_ptr   n_nodes+1 offsets into nbr_idx (CSR node -> neighbour), nbr_ptr[0] = 0.
+ * nbr_idx   nbr_ptr[n_nodes] neighbour ids; the order within a row is the
+ *           summation order of the centroid.
+ * tri_ptr   n_nodes+1 offsets into tri_idx (CSR node -> incident triangle).
+ * tri_idx   tri_ptr[n_nodes] triangle ids; each must contain its node.
+ * tris      n_tris x 3 vertex ids; the stored order is the evaluation order
+ *           of the quality (CCW for a positive quality).
+ * n_tris    >= 0.
+ * boundary  n_nodes bytes, nonzero = fixed node (never moved, never evaluated).
+ * iterations  cap on sweeps, >= 0.
+ * tol       > 0: stop after the first sweep whose largest squared displacement
+ *           of a node is below tol*tol; <= 0: run exactly `iterations` sweeps.
+ * opts      nullable (defaults).  report: nullable.
+ * The call is synchronous; it uses the current HIP device.
+ */
+SL_API sl_status smooth_mesh(double* coords, int32_t n_nodes, const int32_t* nbr_ptr, const int32_t* nbr_idx,
+                      const int32_t* tri_ptr, const int32_t* tri_idx, const int32_t* tris, int32_t n_tris,
+                      const uint8_t* boundary, int32_t iterations, double tol, const sl_options* opts,
+                      sl_report* report);
+
+/*
+ * smooth_mesh_device -- as smooth_mesh, but every array (coords, the CSR
+ * arrays, tris, boundary, opts->flags_out) is device memory on the current
+ * HIP device, and all work is queued on `stream` (a hipStream_t; NULL = the
+ * null stream).  The input arrays are only read; coords is overwritten with
+ * the result.  The call returns after the work on `stream` has completed
+ * (the sweep count and the validation result are needed on the host).
+ */
+SL_API sl_status smooth_mesh_device(double* coords, int32_t n_nodes, const int32_t* nbr_ptr, const int32_t* nbr_idx,
+                             const int32_t* tri_ptr, const int32_t* tri_idx, const int32_t* tris, int32_t n_tris,
+                             const uint8_t* boundary, int32_t iterations, double tol, const sl_options* opts,
+                             sl_report* report, void* stream);
+
+/* Message describing the last failure on the calling thread ("" if none). */
+SL_API const char* sl_last_error(void);
+
+/* Library version string. */
+SL_API const char* sl_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SMARTLAP_H */

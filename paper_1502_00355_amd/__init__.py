@@ -1,0 +1,160 @@
+"""smartlap -- Smart Laplacian mesh smoothing on MI355X (gfx950).
+
+A thin ctypes binding over ``libsmartlap.so`` (C ABI in
+``include/smartlap.h``).  The binding only marshals arguments: every step of
+the smoothing runs in the library's HIP kernels.  PyTorch is used for device
+memory and streams only.  There is no CPU path: if the library is not built,
+or no GPU is present, the calls raise.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libsmartlap.so")
+HEADER = os.path.join(os.path.dirname(_HERE), "include", "smartlap.h")
+
+SL_OK, SL_EINVAL, SL_ETOPO, SL_ENOMEM, SL_EDEVICE, SL_EBUSY, SL_ECANCELED, SL_ETIMEOUT = 0, -1, -2, -3, -4, -5, -6, -7
+STATUS_NAMES = {0: "SL_OK", -1: "SL_EINVAL", -2: "SL_ETOPO", -3: "SL_ENOMEM", -4: "SL_EDEVICE", -5: "SL_EBUSY",
+                -6: "SL_ECANCELED", -7: "SL_ETIMEOUT"}
+FORMS = {"jacobi": 0, "colored": 1}
+ACCEPT = {"ge": 0, "gt": 1}
+LAYOUTS = {"aos": 0, "soa": 1}
+REORDER = {"none": 0, "hilbert": 1}
+
+
+class SmartlapError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__("%s: %s" % (STATUS_NAMES.get(status, status), msg))
+        self.status = status
+
+
+class Options(ctypes.Structure):
+    _fields_ = [("form", ctypes.c_int32), ("accept", ctypes.c_int32), ("layout", ctypes.c_int32),
+                ("reorder", ctypes.c_int32), ("block_size", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("flags_out", ctypes.c_void_p)]
+
+
+class Report(ctypes.Structure):
+    _fields_ = [("iterations_run", ctypes.c_int32), ("n_colors", ctypes.c_int32),
+                ("max_disp_sq_last", ctypes.c_double), ("accepted_last", ctypes.c_int64),
+                ("accepted_total", ctypes.c_int64), ("setup_ms", ctypes.c_double), ("sweep_ms", ctypes.c_double),
+                ("total_ms", ctypes.c_double)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+_lib = None
+
+
+def lib():
+    """The loaded library; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError("libsmartlap.so is not built (python -m paper_1502_00355_amd.build)")
+        L = ctypes.CDLL(LIB_PATH)
+        p, i32, d = ctypes.c_void_p, ctypes.c_int32, ctypes.c_double
+        L.sl_options_default.argtypes = [ctypes.POINTER(Options)]
+        L.sl_options_default.restype = None
+        L.sl_last_error.restype = ctypes.c_char_p
+        L.sl_version.restype = ctypes.c_char_p
+        sig = [p, i32, p, p, p, p, p, i32, p, i32, d, ctypes.POINTER(Options), ctypes.POINTER(Report)]
+        L.smooth_mesh.argtypes = sig
+        L.smooth_mesh.restype = ctypes.c_int
+        L.smooth_mesh_device.argtypes = sig + [p]
+        L.smooth_mesh_device.restype = ctypes.c_int
+        _lib = L
+    return _lib
+
+
+def _check(status: int):
+    if status != SL_OK:
+        raise SmartlapError(status, lib().sl_last_error().decode())
+
+
+def make_options(form="jacobi", accept="ge", layout="aos", reorder="hilbert", block_size=0, flags_ptr=None):
+    o = Options()
+    lib().sl_options_default(ctypes.byref(o))
+    o.form = FORMS[form] if isinstance(form, str) else int(form)
+    o.accept = ACCEPT[accept] if isinstance(accept, str) else int(accept)
+    o.layout = LAYOUTS[layout] if isinstance(layout, str) else int(layout)
+    o.reorder = REORDER[reorder] if isinstance(reorder, str) else int(reorder)
+    o.block_size = int(block_size)
+    o.flags_out = flags_ptr
+    return o
+
+
+def _c(a, dt):
+    return np.ascontiguousarray(a, dtype=dt)
+
+
+def smooth_mesh(coords, nbr_ptr, nbr_idx, tri_ptr, tri_idx, tris, boundary, iterations: int, tol: float = 0.0,
+                want_flags: bool = False, **opts):
+    """Host arrays in, host arrays out.  Returns (coords, report, flags) where
+    flags is None or an (iterations, ceil(n/8)) uint8 bit array."""
+    X = _c(coords, np.float64).copy()
+    n = X.shape[0]
+    arrs = [_c(nbr_ptr, np.int32), _c(nbr_idx, np.int32), _c(tri_ptr, np.int32), _c(tri_idx, np.int32),
+            _c(tris, np.int32).reshape(-1), _c(boundary, np.uint8)]
+    flags = np.zeros((iterations, (n + 7) // 8), np.uint8) if want_flags else None
+    o = make_options(flags_ptr=flags.ctypes.data if (flags is not None and flags.size) else None, **opts)
+    rep = Report()
+    st = lib().smooth_mesh(X.ctypes.data, n, arrs[0].ctypes.data, arrs[1].ctypes.data, arrs[2].ctypes.data,
+                           arrs[3].ctypes.data, arrs[4].ctypes.data, arrs[4].size // 3, arrs[5].ctypes.data,
+                           int(iterations), float(tol), ctypes.byref(o), ctypes.byref(rep))
+    _check(st)
+    return X, rep, flags
+
+
+def smooth_mesh_device(coords, nbr_ptr, nbr_idx, tri_ptr, tri_idx, tris, boundary, iterations: int,
+                       tol: float = 0.0, flags=None, stream=None, **opts) -> Report:
+    """Device tensors (torch, on the current device); ``coords`` (n, 2)
+    float64 is overwritten.  ``flags``: optional uint8 device tensor of
+    iterations * ceil(n/8) bytes.  Runs on ``stream`` (default: torch's
+    current stream)."""
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    for t, dt in ((coords, torch.float64), (nbr_ptr, torch.int32), (nbr_idx, torch.int32), (tri_ptr, torch.int32),
+                  (tri_idx, torch.int32), (tris, torch.int32), (boundary, torch.uint8)):
+        if not t.is_cuda or t.dtype != dt or not t.is_contiguous():
+            raise TypeError("expected a contiguous %s device tensor" % dt)
+    if flags is not None and (not flags.is_cuda or flags.dtype != torch.uint8):
+        raise TypeError("flags must be a uint8 device tensor")
+    o = make_options(flags_ptr=flags.data_ptr() if flags is not None and flags.numel() else None, **opts)
+    rep = Report()
+    st = lib().smooth_mesh_device(coords.data_ptr(), coords.shape[0], nbr_ptr.data_ptr(), nbr_idx.data_ptr(),
+                                  tri_ptr.data_ptr(), tri_idx.data_ptr(), tris.data_ptr(), tris.numel() // 3,
+                                  boundary.data_ptr(), int(iterations), float(tol), ctypes.byref(o),
+                                  ctypes.byref(rep), ctypes.c_void_p(stream.cuda_stream))
+    _check(st)
+    return rep
+
+
+def to_device(mesh, device="cuda"):
+    """Copies a mesh's arrays (objects with the meshgen.Mesh attributes) to
+    device tensors: (coords, nbr_ptr, nbr_idx, tri_ptr, tri_idx, tris, boundary)."""
+    import torch
+    f = lambda a, dt: torch.from_numpy(np.ascontiguousarray(a, dtype=dt)).to(device)  # noqa: E731
+    return (f(mesh.coords, np.float64), f(mesh.nbr_ptr, np.int32), f(mesh.nbr_idx, np.int32),
+            f(mesh.tri_ptr, np.int32), f(mesh.tri_idx, np.int32), f(mesh.tris, np.int32).reshape(-1),
+            f(mesh.boundary, np.uint8))
+
+
+def unpack_flags(bits: np.ndarray, n: int) -> np.ndarray:
+    """(iterations, ceil(n/8)) bit bytes -> (iterations, n) 0/1."""
+    bits = np.asarray(bits, dtype=np.uint8)
+    return np.unpackbits(bits, axis=1, bitorder="little")[:, :n]
+
+
+def header_symbols():
+    """Function names declared with SL_API in include/smartlap.h."""
+    import re
+    src = open(HEADER).read()
+    return re.findall(r"^SL_API\s+[^;(]*?\b([A-Za-z_][A-Za-z0-9_]*)\s*\(", src, flags=re.M)

@@ -1,0 +1,266 @@
+// C-ABI entry points of libsmartlap: argument checks, device buffers, the
+// sweep loop with its convergence test, and the copy back to the caller.
+#include <chrono>
+#include <cstring>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "sl_common.h"
+
+namespace sl {
+
+namespace {
+thread_local std::string g_last_error;
+std::once_flag g_pool_once[64];
+
+// Freed device memory stays in the stream-ordered pool for the next call.
+void keep_pool_warm()
+{
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return;
+    std::call_once(g_pool_once[dev], [dev] {
+        hipMemPool_t pool;
+        if (hipDeviceGetDefaultMemPool(&pool, dev) == hipSuccess) {
+            uint64_t thr = ~0ull;
+            (void)hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &thr);
+        }
+    });
+}
+
+// Everything a call allocates, released on every exit path.
+struct CallState {
+    hipStream_t st = nullptr;
+    DevMesh m;
+    uint64_t* maxd = nullptr;
+    unsigned long long* acc = nullptr;
+    uint64_t* bits = nullptr;
+    hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
+    ~CallState()
+    {
+        devmesh_free(m, st);
+        dfree(maxd, st);
+        dfree(acc, st);
+        dfree(bits, st);
+        (void)hipStreamSynchronize(st);
+        for (auto& e : ev)
+            if (e) (void)hipEventDestroy(e);
+    }
+};
+
+sl_status check_options(const sl_options& o)
+{
+    if (o.form != SL_JACOBI && o.form != SL_INPLACE_COLORED) return fail(SL_EINVAL, "unknown form");
+    if (o.accept != SL_ACCEPT_GE && o.accept != SL_ACCEPT_GT) return fail(SL_EINVAL, "unknown accept rule");
+    if (o.layout != SL_AOS && o.layout != SL_SOA) return fail(SL_EINVAL, "unknown layout");
+    if (o.reorder != SL_REORDER_NONE && o.reorder != SL_REORDER_HILBERT) return fail(SL_EINVAL, "unknown reorder");
+    if (o.block_size != 0 && o.block_size != 64 && o.block_size != 128 && o.block_size != 256)
+        return fail(SL_EINVAL, "block_size must be 0, 64, 128 or 256");
+    return SL_OK;
+}
+
+sl_status run_device(double* coords, int32_t n, const int32_t* nbr_ptr, const int32_t* nbr_idx,
+                     const int32_t* tri_ptr, const int32_t* tri_idx, const int32_t* tris, int32_t n_tris,
+                     const uint8_t* boundary, int32_t iterations, double tol, const sl_options* opts,
+                     sl_report* report, hipStream_t stream)
+{
+    const auto t0 = std::chrono::steady_clock::now();
+    sl_options o;
+    sl_options_default(&o);
+    if (opts) o = *opts;
+    sl_status r = check_options(o);
+    if (r) return r;
+    if (!coords || !nbr_ptr || !tri_ptr || !boundary) return fail(SL_EINVAL, "null array argument");
+    if (n <= 0) return fail(SL_EINVAL, "n_nodes must be >= 1");
+    if (n_tris < 0) return fail(SL_EINVAL, "n_tris must be >= 0");
+    if (iterations < 0) return fail(SL_EINVAL, "iterations must be >= 0");
+    if (n_tris > 0 && !tris) return fail(SL_EINVAL, "null tris with n_tris > 0");
+    if (n_tris > (INT32_MAX / 3)) return fail(SL_EINVAL, "n_tris too large");
+    keep_pool_warm();
+
+    CallState cs;
+    cs.st = stream;
+    for (auto& e : cs.ev) SL_HIP(hipEventCreate(&e));
+    SL_HIP(hipEventRecord(cs.ev[0], stream));
+
+    int32_t ends[4] = {0, 0, 0, 0};
+    SL_HIP(hipMemcpyAsync(&ends[0], nbr_ptr, sizeof(int32_t), hipMemcpyDeviceToHost, stream));
+    SL_HIP(hipMemcpyAsync(&ends[1], nbr_ptr + n, sizeof(int32_t), hipMemcpyDeviceToHost, stream));
+    SL_HIP(hipMemcpyAsync(&ends[2], tri_ptr, sizeof(int32_t), hipMemcpyDeviceToHost, stream));
+    SL_HIP(hipMemcpyAsync(&ends[3], tri_ptr + n, sizeof(int32_t), hipMemcpyDeviceToHost, stream));
+    SL_HIP(hipStreamSynchronize(stream));
+    if (ends[0] != 0 || ends[2] != 0) return fail(SL_EINVAL, "nbr_ptr[0] and tri_ptr[0] must be 0");
+    if (ends[1] < 0 || ends[3] < 0) return fail(SL_EINVAL, "negative CSR length");
+    if (ends[1] > 0 && !nbr_idx) return fail(SL_EINVAL, "null nbr_idx with nbr_ptr[n] > 0");
+    if (ends[3] > 0 && !tri_idx) return fail(SL_EINVAL, "null tri_idx with tri_ptr[n] > 0");
+
+    SetupArgs sa{coords, n, nbr_ptr, nbr_idx, tri_ptr, tri_idx, tris, n_tris, boundary, ends[1], ends[3]};
+    if ((r = setup_mesh(sa, o, cs.m, stream))) return r;
+    SL_HIP(hipEventRecord(cs.ev[1], stream));
+
+    const int32_t its = iterations;
+    const int64_t words = (static_cast<int64_t>(cs.m.n_free) + 63) / 64;
+    if ((r = dalloc(&cs.maxd, its, stream)) || (r = dalloc(&cs.acc, its, stream))) return r;
+    if (its > 0) {
+        SL_HIP(hipMemsetAsync(cs.maxd, 0, sizeof(uint64_t) * its, stream));
+        SL_HIP(hipMemsetAsync(cs.acc, 0, sizeof(unsigned long long) * its, stream));
+    }
+    SweepOut out{cs.maxd, cs.acc, nullptr, words};
+    if (o.flags_out && its > 0) {
+        if ((r = dalloc(&cs.bits, static_cast<size_t>(words) * its, stream))) return r;
+        SL_HIP(hipMemsetAsync(cs.bits, 0, sizeof(uint64_t) * words * its, stream));
+        out.bits = cs.bits;
+    }
+    const double tol2 = tol > 0.0 ? tol * tol : 0.0;
+
+    SL_HIP(hipEventRecord(cs.ev[2], stream));
+    for (int32_t s = 0; s < its; ++s)
+        if ((r = launch_sweep(cs.m, s, o.form, o.accept, o.block_size, tol2, out, stream))) return r;
+    SL_HIP(hipEventRecord(cs.ev[3], stream));
+
+    std::vector<uint64_t> hmaxd(static_cast<size_t>(its));
+    std::vector<unsigned long long> hacc(static_cast<size_t>(its));
+    if (its > 0) {
+        SL_HIP(hipMemcpyAsync(hmaxd.data(), cs.maxd, sizeof(uint64_t) * its, hipMemcpyDeviceToHost, stream));
+        SL_HIP(hipMemcpyAsync(hacc.data(), cs.acc, sizeof(unsigned long long) * its, hipMemcpyDeviceToHost, stream));
+    }
+    SL_HIP(hipStreamSynchronize(stream));
+    // sweeps run: up to and including the first whose displacement is below tol
+    int32_t runs = its;
+    for (int32_t s = 0; s < its && tol2 > 0.0; ++s) {
+        double d;
+        std::memcpy(&d, &hmaxd[s], sizeof(d));
+        if (d < tol2) { runs = s + 1; break; }
+    }
+    const int src = (o.form == SL_JACOBI) ? (runs & 1) : 0;
+    if ((r = unpermute_coords(cs.m, src, coords, stream))) return r;
+    if (o.flags_out && its > 0)
+        if ((r = unpermute_flags(cs.m, cs.bits, its, runs, o.flags_out, stream))) return r;
+    if (o.flags_out && its > 0 && !cs.bits) return fail(SL_EDEVICE, "flag buffer missing");
+    SL_HIP(hipStreamSynchronize(stream));
+
+    if (report) {
+        sl_report rep{};
+        rep.iterations_run = runs;
+        rep.n_colors = cs.m.n_colors;
+        if (runs > 0) {
+            std::memcpy(&rep.max_disp_sq_last, &hmaxd[runs - 1], sizeof(double));
+            rep.accepted_last = static_cast<int64_t>(hacc[runs - 1]);
+        }
+        for (int32_t s = 0; s < runs; ++s) rep.accepted_total += static_cast<int64_t>(hacc[s]);
+        float ms = 0.f;
+        SL_HIP(hipEventElapsedTime(&ms, cs.ev[0], cs.ev[1]));
+        rep.setup_ms = ms;
+        SL_HIP(hipEventElapsedTime(&ms, cs.ev[2], cs.ev[3]));
+        rep.sweep_ms = ms;
+        rep.total_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+        *report = rep;
+    }
+    return SL_OK;
+}
+
+}  // namespace
+
+void set_error(const std::string& msg) { g_last_error = msg; }
+
+sl_status fail(sl_status st, const std::string& msg)
+{
+    set_error(msg);
+    return st;
+}
+
+}  // namespace sl
+
+extern "C" {
+
+void sl_options_default(sl_options* o)
+{
+    if (!o) return;
+    std::memset(o, 0, sizeof(*o));
+    o->form = SL_JACOBI;
+    o->accept = SL_ACCEPT_GE;
+    o->layout = SL_AOS;
+    o->reorder = SL_REORDER_HILBERT;
+    o->block_size = 0;
+    o->flags_out = nullptr;
+}
+
+const char* sl_last_error(void) { return sl::g_last_error.c_str(); }
+
+const char* sl_version(void) { return "smartlap 0.1 (gfx950)"; }
+
+sl_status smooth_mesh_device(double* coords, int32_t n_nodes, const int32_t* nbr_ptr, const int32_t* nbr_idx,
+                             const int32_t* tri_ptr, const int32_t* tri_idx, const int32_t* tris, int32_t n_tris,
+                             const uint8_t* boundary, int32_t iterations, double tol, const sl_options* opts,
+                             sl_report* report, void* stream)
+{
+    sl::set_error("");
+    return sl::run_device(coords, n_nodes, nbr_ptr, nbr_idx, tri_ptr, tri_idx, tris, n_tris, boundary, iterations,
+                          tol, opts, report, static_cast<hipStream_t>(stream));
+}
+
+sl_status smooth_mesh(double* coords, int32_t n_nodes, const int32_t* nbr_ptr, const int32_t* nbr_idx,
+                      const int32_t* tri_ptr, const int32_t* tri_idx, const int32_t* tris, int32_t n_tris,
+                      const uint8_t* boundary, int32_t iterations, double tol, const sl_options* opts,
+                      sl_report* report)
+{
+    using namespace sl;
+    set_error("");
+    if (!coords || !nbr_ptr || !tri_ptr || !boundary) return fail(SL_EINVAL, "null array argument");
+    if (n_nodes <= 0) return fail(SL_EINVAL, "n_nodes must be >= 1");
+    if (n_tris < 0) return fail(SL_EINVAL, "n_tris must be >= 0");
+    if (iterations < 0) return fail(SL_EINVAL, "iterations must be >= 0");
+    if (n_tris > 0 && !tris) return fail(SL_EINVAL, "null tris with n_tris > 0");
+    const int64_t nnz = nbr_ptr[n_nodes], ninc = tri_ptr[n_nodes];
+    if (nbr_ptr[0] != 0 || tri_ptr[0] != 0 || nnz < 0 || ninc < 0) return fail(SL_EINVAL, "bad CSR offsets");
+    if ((nnz > 0 && !nbr_idx) || (ninc > 0 && !tri_idx)) return fail(SL_EINVAL, "null CSR index array");
+    sl_options o;
+    sl_options_default(&o);
+    if (opts) o = *opts;
+    sl_status r = SL_OK;
+    hipStream_t st = nullptr;
+    SL_HIP(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
+    const size_t n = static_cast<size_t>(n_nodes);
+    double* d_coords = nullptr;
+    int32_t *d_np = nullptr, *d_ni = nullptr, *d_tp = nullptr, *d_ti = nullptr, *d_t = nullptr;
+    uint8_t *d_b = nullptr, *d_flags = nullptr;
+    uint8_t* host_flags = o.flags_out;
+    const size_t flag_bytes = (n + 7) / 8 * static_cast<size_t>(iterations);
+    std::vector<double> out(2 * n);
+    do {
+        if ((r = dalloc(&d_coords, 2 * n, st)) || (r = dalloc(&d_np, n + 1, st)) || (r = dalloc(&d_ni, nnz, st)) ||
+            (r = dalloc(&d_tp, n + 1, st)) || (r = dalloc(&d_ti, ninc, st)) ||
+            (r = dalloc(&d_t, 3 * static_cast<size_t>(n_tris), st)) || (r = dalloc(&d_b, n, st)))
+            break;
+        if (host_flags && flag_bytes && (r = dalloc(&d_flags, flag_bytes, st))) break;
+        hipError_t e = hipSuccess;
+        auto cp = [&](void* dst, const void* src, size_t bytes) {
+            if (e == hipSuccess && bytes) e = hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, st);
+        };
+        cp(d_coords, coords, 2 * n * sizeof(double));
+        cp(d_np, nbr_ptr, (n + 1) * sizeof(int32_t));
+        cp(d_ni, nbr_idx, static_cast<size_t>(nnz) * sizeof(int32_t));
+        cp(d_tp, tri_ptr, (n + 1) * sizeof(int32_t));
+        cp(d_ti, tri_idx, static_cast<size_t>(ninc) * sizeof(int32_t));
+        cp(d_t, tris, 3 * static_cast<size_t>(n_tris) * sizeof(int32_t));
+        cp(d_b, boundary, n);
+        if (e != hipSuccess) { r = fail(SL_EDEVICE, std::string("host to device copy failed: ") + hipGetErrorString(e)); break; }
+        o.flags_out = host_flags && flag_bytes ? d_flags : nullptr;
+        r = run_device(d_coords, n_nodes, d_np, d_ni, d_tp, d_ti, d_t, n_tris, d_b, iterations, tol, &o, report, st);
+        if (r) break;
+        e = hipMemcpyAsync(out.data(), d_coords, 2 * n * sizeof(double), hipMemcpyDeviceToHost, st);
+        if (e == hipSuccess && d_flags) e = hipMemcpyAsync(host_flags, d_flags, flag_bytes, hipMemcpyDeviceToHost, st);
+        if (e == hipSuccess) e = hipStreamSynchronize(st);
+        if (e != hipSuccess) { r = fail(SL_EDEVICE, std::string("device to host copy failed: ") + hipGetErrorString(e)); break; }
+        std::memcpy(coords, out.data(), 2 * n * sizeof(double));
+    } while (false);
+    std::string keep = g_last_error;
+    dfree(d_coords, st); dfree(d_np, st); dfree(d_ni, st); dfree(d_tp, st); dfree(d_ti, st); dfree(d_t, st);
+    dfree(d_b, st); dfree(d_flags, st);
+    (void)hipStreamSynchronize(st);
+    (void)hipStreamDestroy(st);
+    set_error(keep);
+    return r;
+}
+
+}  // extern "C"

@@ -1,0 +1,700 @@
+// Mesh setup on the device: validation, node ordering, relabelling, fan
+// build, coordinate buffers, and the inverse steps on the way out.
+//
+// The paper prepares a mesh in three procedures before iterating (Sec. 3.3.1
+// initiating, Sec. 3.3.2 finding neighbours, Sec. 3.3.3 determining
+// constraints).  Here the caller hands in the neighbour rows, incident
+// triangles and the boundary mask; setup checks them and turns them into the
+// layout the sweep kernels read:
+//   - free nodes first, in Hilbert order of their position (or in the
+//     caller's order), fixed nodes after them;
+//   - neighbour rows relabelled, order inside a row kept (it is the
+//     centroid's summation order);
+//   - a 16-bit "fan" entry per (free node, incident triangle): the node's
+//     position p in the triangle's stored order (bits 0-1) and the row slots
+//     of the vertices at stored positions p+1 and p+2 mod 3 (bits 2-8, 9-15).
+#include <algorithm>
+#include <vector>
+
+#include "sl_common.h"
+
+namespace sl {
+
+namespace {
+
+constexpr int kBS = 256;
+
+// Order-preserving map of a double to uint64 (for atomic min/max).
+__device__ __forceinline__ uint64_t ord_bits(double v)
+{
+    uint64_t u = static_cast<uint64_t>(__double_as_longlong(v));
+    return (u & 0x8000000000000000ull) ? ~u : (u | 0x8000000000000000ull);
+}
+__host__ __device__ __forceinline__ double from_ord_bits(uint64_t u)
+{
+    u = (u & 0x8000000000000000ull) ? (u & 0x7FFFFFFFFFFFFFFFull) : ~u;
+    double d;
+    memcpy(&d, &u, sizeof(d));
+    return d;
+}
+
+// SplitMix64 output function (Steele, Lea, Flood, OOPSLA 2014), applied to
+// the caller's node id: the colouring priority.
+__device__ __forceinline__ uint64_t splitmix64(uint64_t v)
+{
+    uint64_t z = v + 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+// ---------------------------------------------------------------- scan ----
+
+template <int IT>
+__global__ __launch_bounds__(kBS) void k_scan_block(const int32_t* __restrict__ in, int32_t* __restrict__ out,
+                                                    int64_t n, int32_t* __restrict__ block_sums)
+{
+    __shared__ int32_t s[kBS];
+    const int64_t base = (static_cast<int64_t>(blockIdx.x) * kBS + threadIdx.x) * IT;
+    int32_t v[IT];
+    int32_t sum = 0;
+#pragma unroll
+    for (int j = 0; j < IT; ++j) {
+        const int64_t i = base + j;
+        v[j] = i < n ? in[i] : 0;
+        sum += v[j];
+    }
+    s[threadIdx.x] = sum;
+    __syncthreads();
+    for (int off = 1; off < kBS; off <<= 1) {
+        const int32_t t = threadIdx.x >= off ? s[threadIdx.x - off] : 0;
+        __syncthreads();
+        s[threadIdx.x] += t;
+        __syncthreads();
+    }
+    int32_t run = threadIdx.x ? s[threadIdx.x - 1] : 0;
+#pragma unroll
+    for (int j = 0; j < IT; ++j) {
+        const int64_t i = base + j;
+        if (i < n) out[i] = run;
+        run += v[j];
+    }
+    if (threadIdx.x == kBS - 1) block_sums[blockIdx.x] = s[kBS - 1];
+}
+
+__global__ void k_scan_add(int32_t* __restrict__ out, int64_t n, const int32_t* __restrict__ offs, int per_block)
+{
+    const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i < n) out[i] += offs[i / per_block];
+}
+
+__global__ void k_set_total(int32_t* __restrict__ dst, const int32_t* __restrict__ src) { *dst = *src; }
+
+constexpr int kScanIt = 8;
+constexpr int kScanTile = kBS * kScanIt;
+
+// Exclusive scan of in[0..n) into out[0..n); *total = sum.
+sl_status scan_rec(const int32_t* in, int32_t* out, int64_t n, int32_t* total, hipStream_t st)
+{
+    const int nb = div_up(n > 0 ? n : 1, kScanTile);
+    int32_t* sums = nullptr;
+    sl_status r = dalloc(&sums, nb + 1, st);
+    if (r) return r;
+    k_scan_block<kScanIt><<<nb, kBS, 0, st>>>(in, out, n, sums);
+    if (nb == 1) {
+        k_set_total<<<1, 1, 0, st>>>(total, sums);
+    } else {
+        int32_t* offs = nullptr;
+        r = dalloc(&offs, nb + 1, st);
+        if (r) { dfree(sums, st); return r; }
+        r = scan_rec(sums, offs, nb, total, st);
+        if (r) { dfree(sums, st); dfree(offs, st); return r; }
+        k_scan_add<<<div_up(n, 256), 256, 0, st>>>(out, n, offs, kScanTile);
+        dfree(offs, st);
+    }
+    dfree(sums, st);
+    SL_HIP(hipGetLastError());
+    return SL_OK;
+}
+
+// ----------------------------------------------------------- validation ---
+
+struct ValArgs {
+    const double* coords;
+    int32_t n;
+    const int32_t* nbr_ptr;
+    const int32_t* nbr_idx;
+    const int32_t* tri_ptr;
+    const int32_t* tri_idx;
+    const int32_t* tris;
+    int32_t n_tris;
+    const uint8_t* boundary;
+    int64_t nnz, ninc;
+    int check_symmetry;
+};
+
+__device__ __forceinline__ bool row_has(const int32_t* __restrict__ idx, int32_t b, int32_t e, int32_t v)
+{
+    for (int32_t k = b; k < e; ++k)
+        if (idx[k] == v) return true;
+    return false;
+}
+
+__global__ __launch_bounds__(kBS) void k_validate_tris(const int32_t* __restrict__ tris, int32_t n_tris, int32_t n,
+                                                       ValStats* __restrict__ vs)
+{
+    const int64_t t = static_cast<int64_t>(blockIdx.x) * kBS + threadIdx.x;
+    uint32_t e = 0;
+    if (t < n_tris) {
+        const int32_t a = tris[3 * t], b = tris[3 * t + 1], c = tris[3 * t + 2];
+        if (a < 0 || b < 0 || c < 0 || a >= n || b >= n || c >= n) e |= VE_RANGE;
+        if (a == b || b == c || a == c) e |= VE_TRIREP;
+    }
+    if (e) atomicOr(&vs->err, e);
+}
+
+__global__ __launch_bounds__(kBS) void k_validate_nodes(ValArgs a, ValStats* __restrict__ vs)
+{
+    const int32_t i = static_cast<int32_t>(blockIdx.x * kBS + threadIdx.x);
+    uint32_t e = 0;
+    int is_free = 0, deg = 0, inc = 0;
+    if (i < a.n) {
+        const double x = a.coords[2 * static_cast<int64_t>(i)], y = a.coords[2 * static_cast<int64_t>(i) + 1];
+        if (!isfinite(x) || !isfinite(y)) e |= VE_COORD;
+        const int32_t b = a.nbr_ptr[i], en = a.nbr_ptr[i + 1];
+        const bool row_ok = 0 <= b && b <= en && en <= a.nnz;
+        const int32_t tb = a.tri_ptr[i], te = a.tri_ptr[i + 1];
+        const bool trow_ok = 0 <= tb && tb <= te && te <= a.ninc;
+        if (!row_ok || !trow_ok) e |= VE_PTR;
+        is_free = a.boundary[i] == 0;
+        if (row_ok) {
+            deg = en - b;
+            for (int32_t k = b; k < en; ++k) {
+                const int32_t j = a.nbr_idx[k];
+                if (j < 0 || j >= a.n) {
+                    e |= VE_RANGE;
+                } else {
+                    if (j == i) e |= VE_SELF;
+                    if (is_free && a.check_symmetry && a.boundary[j] == 0) {
+                        const int32_t jb = a.nbr_ptr[j], je = a.nbr_ptr[j + 1];
+                        if (!(0 <= jb && jb <= je && je <= a.nnz) || !row_has(a.nbr_idx, jb, je, i)) e |= VE_ASYM;
+                    }
+                }
+            }
+            if (is_free && deg == 0) e |= VE_EMPTY;
+            if (is_free && deg > kMaxValence) e |= VE_VALENCE;
+        }
+        if (trow_ok) {
+            inc = te - tb;
+            for (int32_t k = tb; k < te; ++k) {
+                const int32_t t = a.tri_idx[k];
+                if (t < 0 || t >= a.n_tris) { e |= VE_RANGE; continue; }
+                const int32_t v[3] = {a.tris[3 * static_cast<int64_t>(t)], a.tris[3 * static_cast<int64_t>(t) + 1],
+                                      a.tris[3 * static_cast<int64_t>(t) + 2]};
+                const int p = v[0] == i ? 0 : (v[1] == i ? 1 : (v[2] == i ? 2 : -1));
+                if (p < 0) { e |= VE_NOTIN; continue; }
+                if (is_free && row_ok) {
+                    if (!row_has(a.nbr_idx, b, en, v[(p + 1) % 3]) || !row_has(a.nbr_idx, b, en, v[(p + 2) % 3]))
+                        e |= VE_MISSING;
+                }
+            }
+        }
+    }
+    // block reductions: free count, max degree, max incidence, error bits
+    __shared__ int32_t s_cnt[kBS / 64], s_deg[kBS / 64], s_inc[kBS / 64];
+    __shared__ uint32_t s_err[kBS / 64];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int df = is_free ? deg : 0, inf = is_free ? inc : 0;
+    int32_t c = __popcll(__ballot(is_free != 0));
+    int32_t md = df, mi = inf;
+    uint32_t me = e;
+    for (int off = 32; off > 0; off >>= 1) {
+        md = max(md, __shfl_xor(md, off));
+        mi = max(mi, __shfl_xor(mi, off));
+        me |= __shfl_xor(me, off);
+    }
+    if (lane == 0) { s_cnt[w] = c; s_deg[w] = md; s_inc[w] = mi; s_err[w] = me; }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int32_t C = 0, D = 0, I = 0;
+        uint32_t E = 0;
+        for (int q = 0; q < kBS / 64; ++q) { C += s_cnt[q]; D = max(D, s_deg[q]); I = max(I, s_inc[q]); E |= s_err[q]; }
+        if (C) atomicAdd(&vs->n_free, C);
+        if (D) atomicMax(&vs->max_deg_free, D);
+        if (I) atomicMax(&vs->max_inc_free, I);
+        if (E) atomicOr(&vs->err, E);
+    }
+}
+
+// ------------------------------------------------------------- ordering ---
+
+__global__ __launch_bounds__(kBS) void k_bbox(const double* __restrict__ coords, int32_t n, uint64_t* __restrict__ bb)
+{
+    uint64_t mnx = ~0ull, mny = ~0ull, mxx = 0, mxy = 0;
+    for (int64_t i = static_cast<int64_t>(blockIdx.x) * kBS + threadIdx.x; i < n;
+         i += static_cast<int64_t>(gridDim.x) * kBS) {
+        const uint64_t ox = ord_bits(coords[2 * i]), oy = ord_bits(coords[2 * i + 1]);
+        mnx = min(mnx, ox); mxx = max(mxx, ox);
+        mny = min(mny, oy); mxy = max(mxy, oy);
+    }
+    for (int off = 32; off > 0; off >>= 1) {
+        mnx = min(mnx, static_cast<uint64_t>(__shfl_xor(static_cast<unsigned long long>(mnx), off)));
+        mny = min(mny, static_cast<uint64_t>(__shfl_xor(static_cast<unsigned long long>(mny), off)));
+        mxx = max(mxx, static_cast<uint64_t>(__shfl_xor(static_cast<unsigned long long>(mxx), off)));
+        mxy = max(mxy, static_cast<uint64_t>(__shfl_xor(static_cast<unsigned long long>(mxy), off)));
+    }
+    if ((threadIdx.x & 63) == 0) {
+        atomicMin(reinterpret_cast<unsigned long long*>(bb + 0), static_cast<unsigned long long>(mnx));
+        atomicMin(reinterpret_cast<unsigned long long*>(bb + 1), static_cast<unsigned long long>(mny));
+        atomicMax(reinterpret_cast<unsigned long long*>(bb + 2), static_cast<unsigned long long>(mxx));
+        atomicMax(reinterpret_cast<unsigned long long*>(bb + 3), static_cast<unsigned long long>(mxy));
+    }
+}
+
+__global__ void k_bbox_init(uint64_t* bb)
+{
+    bb[0] = ~0ull; bb[1] = ~0ull; bb[2] = 0; bb[3] = 0;
+}
+
+// Hilbert index of cell (x, y) on a 2^bits x 2^bits grid.
+__device__ __forceinline__ uint32_t hilbert_index(int bits, uint32_t x, uint32_t y)
+{
+    uint32_t d = 0;
+    for (uint32_t s = 1u << (bits - 1); s > 0; s >>= 1) {
+        const uint32_t rx = (x & s) ? 1u : 0u, ry = (y & s) ? 1u : 0u;
+        d += s * s * ((3u * rx) ^ ry);
+        if (ry == 0) {
+            if (rx == 1) { x = (s - 1) ^ x; y = (s - 1) ^ y; }
+            const uint32_t t = x; x = y; y = t;
+        }
+    }
+    return d;
+}
+
+// Bucket of each free node: colour * 4^bits + Hilbert cell (bits may be 0).
+__global__ __launch_bounds__(kBS) void k_bucket(const double* __restrict__ coords, const uint8_t* __restrict__ bnd,
+                                                const int32_t* __restrict__ color, int32_t n, int bits,
+                                                const uint64_t* __restrict__ bb, int32_t* __restrict__ key,
+                                                int32_t* __restrict__ count)
+{
+    const int64_t i = static_cast<int64_t>(blockIdx.x) * kBS + threadIdx.x;
+    if (i >= n || bnd[i]) return;
+    uint32_t cell = 0;
+    if (bits > 0) {
+        const double x0 = from_ord_bits(bb[0]), y0 = from_ord_bits(bb[1]);
+        const double ext = fmax(from_ord_bits(bb[2]) - x0, from_ord_bits(bb[3]) - y0);
+        const double side = static_cast<double>(1u << bits);
+        const double sc = ext > 0.0 ? side / ext : 0.0;
+        const uint32_t lim = (1u << bits) - 1u;
+        const double fx = (coords[2 * i] - x0) * sc, fy = (coords[2 * i + 1] - y0) * sc;
+        const uint32_t cx = fx <= 0.0 ? 0u : (fx >= lim ? lim : static_cast<uint32_t>(fx));
+        const uint32_t cy = fy <= 0.0 ? 0u : (fy >= lim ? lim : static_cast<uint32_t>(fy));
+        cell = hilbert_index(bits, cx, cy);
+    }
+    const int32_t k = (color ? color[i] : 0) * (1 << (2 * bits)) + static_cast<int32_t>(cell);
+    key[i] = k;
+    atomicAdd(count + k, 1);
+}
+
+__global__ __launch_bounds__(kBS) void k_bucket_scatter(const uint8_t* __restrict__ bnd, int32_t n,
+                                                        const int32_t* __restrict__ key, int32_t* __restrict__ cursor,
+                                                        int32_t* __restrict__ new_of_old, int32_t* __restrict__ perm)
+{
+    const int64_t i = static_cast<int64_t>(blockIdx.x) * kBS + threadIdx.x;
+    if (i >= n || bnd[i]) return;
+    const int32_t pos = atomicAdd(cursor + key[i], 1);
+    new_of_old[i] = pos;
+    perm[pos] = static_cast<int32_t>(i);
+}
+
+// flag[i] = (bnd[i] != 0) == want_fixed  (and, if color given, color[i] == c)
+__global__ __launch_bounds__(kBS) void k_select(const uint8_t* __restrict__ bnd, const int32_t* __restrict__ color,
+                                                int32_t c, int want_fixed, int32_t n, int32_t* __restrict__ flag)
+{
+    const int64_t i = static_cast<int64_t>(blockIdx.x) * kBS + threadIdx.x;
+    if (i >= n) return;
+    int f = (bnd[i] != 0) == (want_fixed != 0);
+    if (f && color) f = color[i] == c;
+    flag[i] = f;
+}
+
+__global__ __launch_bounds__(kBS) void k_place(const int32_t* __restrict__ flag, const int32_t* __restrict__ pos,
+                                               int32_t base, int32_t n, int32_t* __restrict__ new_of_old,
+                                               int32_t* __restrict__ perm)
+{
+    const int64_t i = static_cast<int64_t>(blockIdx.x) * kBS + threadIdx.x;
+    if (i >= n || !flag[i]) return;
+    const int32_t p = base + pos[i];
+    new_of_old[i] = p;
+    perm[p] = static_cast<int32_t>(i);
+}
+
+// ------------------------------------------------------------ colouring ---
+
+// One round of greedy colouring in decreasing priority: a free node takes
+// the smallest colour unused by its free neighbours once every free
+// neighbour of higher priority has a colour.
+__global__ __launch_bounds__(kBS) void k_color_round(int32_t n, const int32_t* __restrict__ nbr_ptr,
+                                                     const int32_t* __restrict__ nbr_idx,
+                                                     const uint8_t* __restrict__ bnd, int32_t* color,
+                                                     int32_t* __restrict__ remaining)
+{
+    const int32_t i = static_cast<int32_t>(blockIdx.x * kBS + threadIdx.x);
+    int left = 0;
+    if (i < n && !bnd[i] && __atomic_load_n(color + i, __ATOMIC_RELAXED) < 0) {
+        const uint64_t pi = splitmix64(static_cast<uint64_t>(i));
+        uint64_t used0 = 0, used1 = 0;
+        bool ready = true;
+        for (int32_t k = nbr_ptr[i]; k < nbr_ptr[i + 1]; ++k) {
+            const int32_t j = nbr_idx[k];
+            if (bnd[j] || splitmix64(static_cast<uint64_t>(j)) < pi) continue;
+            const int32_t cj = __atomic_load_n(color + j, __ATOMIC_RELAXED);
+            if (cj < 0) { ready = false; break; }
+            if (cj < 64) used0 |= 1ull << cj; else used1 |= 1ull << (cj - 64);
+        }
+        if (ready) {
+            const int32_t c = (~used0) ? __builtin_ctzll(~used0) : 64 + __builtin_ctzll(~used1);
+            __atomic_store_n(color + i, c, __ATOMIC_RELAXED);
+        } else {
+            left = 1;
+        }
+    }
+    const int32_t cnt = __popcll(__ballot(left != 0));
+    if ((threadIdx.x & 63) == 0 && cnt) atomicAdd(remaining, cnt);
+}
+
+__global__ __launch_bounds__(kBS) void k_color_init(int32_t n, const uint8_t* __restrict__ bnd, int32_t* color)
+{
+    const int64_t i = static_cast<int64_t>(blockIdx.x) * kBS + threadIdx.x;
+    if (i < n) color[i] = -1;
+}
+
+__global__ __launch_bounds__(kBS) void k_max_i32(const int32_t* __restrict__ v, int32_t n, int32_t* __restrict__ out)
+{
+    int32_t m = -1;
+    for (int64_t i = static_cast<int64_t>(blockIdx.x) * kBS + threadIdx.x; i < n;
+         i += static_cast<int64_t>(gridDim.x) * kBS)
+        m = max(m, v[i]);
+    for (int off = 32; off > 0; off >>= 1) m = max(m, __shfl_xor(m, off));
+    if ((threadIdx.x & 63) == 0) atomicMax(out, m);
+}
+
+__global__ void k_fill_i32(int32_t* p, int64_t n, int32_t v)
+{
+    const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
+// ------------------------------------------------------------ relabel -----
+
+__global__ __launch_bounds__(kBS) void k_degrees(const int32_t* __restrict__ perm, int32_t n_free,
+                                                 const int32_t* __restrict__ nbr_ptr,
+                                                 const int32_t* __restrict__ tri_ptr, int32_t* __restrict__ deg,
+                                                 int32_t* __restrict__ inc)
+{
+    const int64_t k = static_cast<int64_t>(blockIdx.x) * kBS + threadIdx.x;
+    if (k >= n_free) return;
+    const int32_t o = perm[k];
+    deg[k] = nbr_ptr[o + 1] - nbr_ptr[o];
+    inc[k] = tri_ptr[o + 1] - tri_ptr[o];
+}
+
+__global__ __launch_bounds__(kBS) void k_rows_fans(const int32_t* __restrict__ perm,
+                                                   const int32_t* __restrict__ new_of_old, int32_t n_free,
+                                                   const int32_t* __restrict__ nbr_ptr,
+                                                   const int32_t* __restrict__ nbr_idx,
+                                                   const int32_t* __restrict__ tri_ptr,
+                                                   const int32_t* __restrict__ tri_idx,
+                                                   const int32_t* __restrict__ tris,
+                                                   const int32_t* __restrict__ row_ptr, int32_t* __restrict__ nbr,
+                                                   const int32_t* __restrict__ fan_ptr, uint16_t* __restrict__ fan)
+{
+    const int64_t k = static_cast<int64_t>(blockIdx.x) * kBS + threadIdx.x;
+    if (k >= n_free) return;
+    const int32_t o = perm[k];
+    const int32_t b = nbr_ptr[o], d = nbr_ptr[o + 1] - b;
+    const int32_t out = row_ptr[k];
+    for (int32_t j = 0; j < d; ++j) nbr[out + j] = new_of_old[nbr_idx[b + j]];
+    const int32_t tb = tri_ptr[o], nt = tri_ptr[o + 1] - tb;
+    const int32_t fo = fan_ptr[k];
+    for (int32_t q = 0; q < nt; ++q) {
+        const int64_t t = tri_idx[tb + q];
+        const int32_t v[3] = {tris[3 * t], tris[3 * t + 1], tris[3 * t + 2]};
+        const int p = v[0] == o ? 0 : (v[1] == o ? 1 : 2);
+        const int32_t va = v[(p + 1) % 3], vc = v[(p + 2) % 3];
+        int sa = 0, sc = 0;
+        for (int32_t j = 0; j < d; ++j) {
+            const int32_t u = nbr_idx[b + j];
+            if (u == va) sa = j;
+            if (u == vc) sc = j;
+        }
+        fan[fo + q] = static_cast<uint16_t>(p | (sa << 2) | (sc << 9));
+    }
+}
+
+__global__ __launch_bounds__(kBS) void k_init_coords(const double* __restrict__ coords,
+                                                     const int32_t* __restrict__ perm, int32_t n, int soa,
+                                                     double* __restrict__ X0, double* __restrict__ X1)
+{
+    const int64_t k = static_cast<int64_t>(blockIdx.x) * kBS + threadIdx.x;
+    if (k >= n) return;
+    const int64_t o = perm[k];
+    const double2 p = *reinterpret_cast<const double2*>(coords + 2 * o);
+    if (soa) {
+        X0[k] = p.x; X0[n + k] = p.y;
+        X1[k] = p.x; X1[n + k] = p.y;
+    } else {
+        reinterpret_cast<double2*>(X0)[k] = p;
+        reinterpret_cast<double2*>(X1)[k] = p;
+    }
+}
+
+__global__ __launch_bounds__(kBS) void k_unpermute(const double* __restrict__ X, const int32_t* __restrict__ perm,
+                                                   int32_t n, int soa, double* __restrict__ out)
+{
+    const int64_t k = static_cast<int64_t>(blockIdx.x) * kBS + threadIdx.x;
+    if (k >= n) return;
+    const int64_t o = perm[k];
+    const double2 p = soa ? make_double2(X[k], X[n + k]) : reinterpret_cast<const double2*>(X)[k];
+    *reinterpret_cast<double2*>(out + 2 * o) = p;
+}
+
+__global__ __launch_bounds__(kBS) void k_unpermute_flags(const uint64_t* __restrict__ bits, int64_t words,
+                                                         const int32_t* __restrict__ new_of_old, int32_t n,
+                                                         int32_t n_free, int32_t iterations, int32_t runs,
+                                                         uint8_t* __restrict__ out)
+{
+    const int64_t nbytes = (static_cast<int64_t>(n) + 7) / 8;
+    const int64_t g = static_cast<int64_t>(blockIdx.x) * kBS + threadIdx.x;
+    if (g >= nbytes * iterations) return;
+    const int64_t s = g / nbytes, B = g % nbytes;
+    uint32_t byte = 0;
+    if (s < runs) {
+        for (int q = 0; q < 8; ++q) {
+            const int64_t i = 8 * B + q;
+            if (i >= n) break;
+            const int32_t k = new_of_old[i];
+            if (k < n_free && ((bits[s * words + k / 64] >> (k % 64)) & 1ull)) byte |= 1u << q;
+        }
+    }
+    out[g] = static_cast<uint8_t>(byte);
+}
+
+sl_status make_order(const SetupArgs& a, const sl_options& o, const uint8_t* bnd, int32_t n_free,
+                     const int32_t* color, int32_t n_colors, DevMesh& m, hipStream_t st)
+{
+    const int32_t n = a.n;
+    const int gb = div_up(n, kBS);
+    int32_t *flag = nullptr, *pos = nullptr;
+    sl_status r;
+    if ((r = dalloc(&flag, n, st)) || (r = dalloc(&pos, static_cast<size_t>(n) + 1, st))) {
+        dfree(flag, st);
+        return r;
+    }
+    int32_t* cs = m.color_start_h;
+    cs[0] = 0;
+    if (o.reorder == SL_REORDER_HILBERT && n_free > 0) {
+        // bucket counting sort: (colour, Hilbert cell); order inside a bucket is arbitrary,
+        // which no result depends on (rows and triangles keep their order).
+        const int nc = color ? n_colors : 1;
+        int bits = 1;
+        while (bits < 12 && (static_cast<int64_t>(nc) << (2 * bits)) < n_free / 2 &&
+               (static_cast<int64_t>(nc) << (2 * (bits + 1))) <= (int64_t(1) << 25))
+            ++bits;
+        const int64_t nbk = static_cast<int64_t>(nc) << (2 * bits);
+        uint64_t* bb = nullptr;
+        int32_t *count = nullptr, *start = nullptr, *key = nullptr;
+        if ((r = dalloc(&bb, 4, st)) || (r = dalloc(&count, nbk, st)) || (r = dalloc(&start, nbk + 1, st)) ||
+            (r = dalloc(&key, n, st))) {
+            dfree(bb, st); dfree(count, st); dfree(start, st); dfree(key, st); dfree(flag, st); dfree(pos, st);
+            return r;
+        }
+        k_bbox_init<<<1, 1, 0, st>>>(bb);
+        k_bbox<<<std::min(gb, 2048), kBS, 0, st>>>(a.coords, n, bb);
+        k_fill_i32<<<div_up(nbk, 256), 256, 0, st>>>(count, nbk, 0);
+        k_bucket<<<gb, kBS, 0, st>>>(a.coords, bnd, color, n, bits, bb, key, count);
+        if ((r = scan_exclusive(count, start, nbk, st))) return r;
+        if (color) {
+            std::vector<int32_t> h(static_cast<size_t>(nc) + 1);
+            for (int c = 0; c <= nc; ++c) {
+                SL_HIP(hipMemcpyAsync(&h[c], start + (static_cast<int64_t>(c) << (2 * bits)), sizeof(int32_t),
+                                      hipMemcpyDeviceToHost, st));
+            }
+            SL_HIP(hipStreamSynchronize(st));
+            for (int c = 0; c <= nc; ++c) cs[c] = h[c];
+        } else {
+            cs[1] = n_free;
+        }
+        k_bucket_scatter<<<gb, kBS, 0, st>>>(bnd, n, key, start, m.new_of_old, m.perm);
+        dfree(bb, st); dfree(count, st); dfree(start, st); dfree(key, st);
+    } else if (n_free > 0) {
+        // stable: free nodes (by colour class when coloured) in caller order
+        const int nc = color ? n_colors : 1;
+        int32_t base = 0;
+        for (int c = 0; c < nc; ++c) {
+            k_select<<<gb, kBS, 0, st>>>(bnd, color, c, 0, n, flag);
+            if ((r = scan_exclusive(flag, pos, n, st))) return r;
+            k_place<<<gb, kBS, 0, st>>>(flag, pos, base, n, m.new_of_old, m.perm);
+            int32_t cnt = 0;
+            SL_HIP(hipMemcpyAsync(&cnt, pos + n, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+            SL_HIP(hipStreamSynchronize(st));
+            base += cnt;
+            cs[c + 1] = base;
+        }
+    }
+    if (n_free < n) {
+        k_select<<<gb, kBS, 0, st>>>(bnd, nullptr, 0, 1, n, flag);
+        if ((r = scan_exclusive(flag, pos, n, st))) return r;
+        k_place<<<gb, kBS, 0, st>>>(flag, pos, n_free, n, m.new_of_old, m.perm);
+    }
+    dfree(flag, st);
+    dfree(pos, st);
+    SL_HIP(hipGetLastError());
+    return SL_OK;
+}
+
+}  // namespace
+
+sl_status scan_exclusive(const int32_t* in, int32_t* out, int64_t n, hipStream_t st)
+{
+    return scan_rec(in, out, n, out + n, st);
+}
+
+void devmesh_free(DevMesh& m, hipStream_t st)
+{
+    dfree(m.perm, st);
+    dfree(m.new_of_old, st);
+    dfree(m.row_ptr, st);
+    dfree(m.nbr, st);
+    dfree(m.fan_ptr, st);
+    dfree(m.fan, st);
+    dfree(m.X[0], st);
+    dfree(m.X[1], st);
+}
+
+sl_status setup_mesh(const SetupArgs& a, const sl_options& o, DevMesh& m, hipStream_t st)
+{
+    const int32_t n = a.n;
+    m.n = n;
+    m.n_tris = a.n_tris;
+    m.layout = o.layout;
+    sl_status r;
+    // ---- validation
+    ValStats* vs = nullptr;
+    if ((r = dalloc(&vs, 1, st))) return r;
+    SL_HIP(hipMemsetAsync(vs, 0, sizeof(ValStats), st));
+    ValArgs va{a.coords, n, a.nbr_ptr, a.nbr_idx, a.tri_ptr, a.tri_idx, a.tris, a.n_tris, a.boundary,
+               a.nnz, a.ninc, o.form == SL_INPLACE_COLORED};
+    if (a.n_tris > 0) k_validate_tris<<<div_up(a.n_tris, kBS), kBS, 0, st>>>(a.tris, a.n_tris, n, vs);
+    k_validate_nodes<<<div_up(n, kBS), kBS, 0, st>>>(va, vs);
+    SL_HIP(hipGetLastError());
+    ValStats h{};
+    SL_HIP(hipMemcpyAsync(&h, vs, sizeof(ValStats), hipMemcpyDeviceToHost, st));
+    SL_HIP(hipStreamSynchronize(st));
+    dfree(vs, st);
+    if (h.err & (VE_PTR | VE_RANGE | VE_COORD)) {
+        std::string msg = "invalid input:";
+        if (h.err & VE_PTR) msg += " CSR offsets not monotone or out of range;";
+        if (h.err & VE_RANGE) msg += " node or triangle id out of range;";
+        if (h.err & VE_COORD) msg += " non-finite coordinate;";
+        return fail(SL_EINVAL, msg);
+    }
+    if (h.err) {
+        std::string msg = "invalid topology:";
+        if (h.err & VE_SELF) msg += " node lists itself as a neighbour;";
+        if (h.err & VE_TRIREP) msg += " triangle with a repeated vertex;";
+        if (h.err & VE_NOTIN) msg += " incident triangle does not contain its node;";
+        if (h.err & VE_MISSING) msg += " triangle vertex missing from the node's neighbour row;";
+        if (h.err & VE_EMPTY) msg += " free node without neighbours;";
+        if (h.err & VE_VALENCE) msg += " free node with more than 127 neighbours;";
+        if (h.err & VE_ASYM) msg += " neighbour rows are not symmetric (needed by the coloured form);";
+        return fail(SL_ETOPO, msg);
+    }
+    m.n_free = h.n_free;
+    m.max_deg = h.max_deg_free;
+    m.max_inc = h.max_inc_free;
+
+    if ((r = dalloc(&m.perm, n, st)) || (r = dalloc(&m.new_of_old, n, st))) return r;
+    const int gb = div_up(n, kBS);
+
+    // ---- colouring (coloured form)
+    int32_t* color = nullptr;
+    m.n_colors = 0;
+    if (o.form == SL_INPLACE_COLORED && m.n_free > 0) {
+        int32_t* remaining = nullptr;
+        if ((r = dalloc(&color, n, st)) || (r = dalloc(&remaining, 1, st))) { dfree(color, st); return r; }
+        k_color_init<<<gb, kBS, 0, st>>>(n, a.boundary, color);
+        for (int round = 0; round <= m.n_free; ++round) {
+            k_fill_i32<<<1, 1, 0, st>>>(remaining, 1, 0);
+            k_color_round<<<gb, kBS, 0, st>>>(n, a.nbr_ptr, a.nbr_idx, a.boundary, color, remaining);
+            int32_t left = 0;
+            SL_HIP(hipMemcpyAsync(&left, remaining, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+            SL_HIP(hipStreamSynchronize(st));
+            if (left == 0) break;
+        }
+        k_fill_i32<<<1, 1, 0, st>>>(remaining, 1, -1);
+        k_max_i32<<<std::min(gb, 1024), kBS, 0, st>>>(color, n, remaining);
+        int32_t mx = -1;
+        SL_HIP(hipMemcpyAsync(&mx, remaining, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+        SL_HIP(hipStreamSynchronize(st));
+        dfree(remaining, st);
+        m.n_colors = mx + 1;
+        if (m.n_colors > 128) { dfree(color, st); return fail(SL_ETOPO, "more than 128 colour classes"); }
+    }
+
+    // ---- node order
+    r = make_order(a, o, a.boundary, m.n_free, color, m.n_colors, m, st);
+    dfree(color, st);
+    if (r) return r;
+
+    // ---- rows and fans of free nodes
+    if ((r = dalloc(&m.row_ptr, static_cast<size_t>(m.n_free) + 1, st)) ||
+        (r = dalloc(&m.fan_ptr, static_cast<size_t>(m.n_free) + 1, st)))
+        return r;
+    int32_t *deg = nullptr, *inc = nullptr;
+    if ((r = dalloc(&deg, m.n_free, st)) || (r = dalloc(&inc, m.n_free, st))) { dfree(deg, st); return r; }
+    const int gf = div_up(m.n_free > 0 ? m.n_free : 1, kBS);
+    if (m.n_free > 0) k_degrees<<<gf, kBS, 0, st>>>(m.perm, m.n_free, a.nbr_ptr, a.tri_ptr, deg, inc);
+    if ((r = scan_exclusive(deg, m.row_ptr, m.n_free, st)) || (r = scan_exclusive(inc, m.fan_ptr, m.n_free, st)))
+        return r;
+    int32_t tot[2] = {0, 0};
+    SL_HIP(hipMemcpyAsync(&tot[0], m.row_ptr + m.n_free, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+    SL_HIP(hipMemcpyAsync(&tot[1], m.fan_ptr + m.n_free, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+    SL_HIP(hipStreamSynchronize(st));
+    dfree(deg, st);
+    dfree(inc, st);
+    m.nnz_free = tot[0];
+    m.ninc_free = tot[1];
+    if ((r = dalloc(&m.nbr, m.nnz_free, st)) || (r = dalloc(&m.fan, m.ninc_free, st))) return r;
+    if (m.n_free > 0)
+        k_rows_fans<<<gf, kBS, 0, st>>>(m.perm, m.new_of_old, m.n_free, a.nbr_ptr, a.nbr_idx, a.tri_ptr, a.tri_idx,
+                                        a.tris, m.row_ptr, m.nbr, m.fan_ptr, m.fan);
+
+    // ---- coordinate buffers
+    if ((r = dalloc(&m.X[0], 2 * static_cast<size_t>(n), st)) || (r = dalloc(&m.X[1], 2 * static_cast<size_t>(n), st)))
+        return r;
+    k_init_coords<<<gb, kBS, 0, st>>>(a.coords, m.perm, n, o.layout == SL_SOA, m.X[0], m.X[1]);
+    SL_HIP(hipGetLastError());
+    return SL_OK;
+}
+
+sl_status unpermute_coords(const DevMesh& m, int src, double* coords_out, hipStream_t st)
+{
+    k_unpermute<<<div_up(m.n, kBS), kBS, 0, st>>>(m.X[src], m.perm, m.n, m.layout == SL_SOA, coords_out);
+    SL_HIP(hipGetLastError());
+    return SL_OK;
+}
+
+sl_status unpermute_flags(const DevMesh& m, const uint64_t* bits, int32_t iterations, int32_t runs, uint8_t* out,
+                          hipStream_t st)
+{
+    const int64_t words = (static_cast<int64_t>(m.n_free) + 63) / 64;
+    const int64_t total = (static_cast<int64_t>(m.n) + 7) / 8 * iterations;
+    if (total == 0) return SL_OK;
+    k_unpermute_flags<<<div_up(total, kBS), kBS, 0, st>>>(bits, words, m.new_of_old, m.n, m.n_free, iterations, runs,
+                                                          out);
+    SL_HIP(hipGetLastError());
+    return SL_OK;
+}
+
+}  // namespace sl

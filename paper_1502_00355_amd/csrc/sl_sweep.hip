@@ -1,0 +1,244 @@
+// The Smart Laplacian sweep on gfx950.
+//
+// One work-item per free node (paper Sec. 3.3.4, "The Iterating Procedure"):
+//   1. gather the neighbours' positions in row order, summing them, and
+//      divide once by the neighbour count: the Laplacian candidate (eq. (2));
+//   2. for every incident triangle evaluate the quality in the triangle's
+//      stored vertex order twice -- with the node at its current position
+//      and at the candidate -- keeping the two minima (Sec. 2.1);
+//   3. keep the candidate iff the new minimum is >= the old one (or >, for
+//      the strict rule), write the node's position to the output buffer;
+//   4. fold the squared displacement into the sweep's maximum and count the
+//      accepted nodes.
+// The gathered neighbour positions are parked in LDS, one column per
+// work-item, so that the triangle loop can address them by the row slots
+// stored in the fan entries.  The paper re-evaluates every triangle from
+// each of its three vertices (Sec. 5.3); so does this kernel -- each
+// evaluation reads only data the node already holds, which costs less than
+// a per-triangle pass that would have to write and re-read qualities.
+//
+// Form A (eq. (2)): reads buffer s%2, writes buffer (s+1)%2.
+// Form B (eq. (3)): one launch per colour class, in place; no two nodes of a
+// class are adjacent, so no work-item reads a position another writes.
+#include <cmath>
+
+#include "sl_common.h"
+
+namespace sl {
+
+namespace {
+
+// 2*sqrt(3) rounded to double: q = 4*sqrt(3)*A / sum(l^2) = (2*sqrt(3)*cr) / S.
+constexpr double kTwoSqrt3 = 0x1.bb67ae8584caap+1;
+
+// Triangle quality in stored vertex order (p0, p1, p2); every operation is a
+// single rounded double operation, no contraction.
+__device__ __forceinline__ double tri_quality(double x0, double y0, double x1, double y1, double x2, double y2)
+{
+    const double ax = x1 - x0, ay = y1 - y0;
+    const double bx = x2 - x0, by = y2 - y0;
+    const double cx = x2 - x1, cy = y2 - y1;
+    const double cr = ax * by - bx * ay;
+    const double S = ((ax * ax + ay * ay) + (cx * cx + cy * cy)) + (bx * bx + by * by);
+    const double q = (kTwoSqrt3 * cr) / S;
+    return S == 0.0 ? 0.0 : q;
+}
+
+// Quality of the triangle whose stored order puts the node at position p,
+// the vertex `a` at p+1 and `b` at p+2 (mod 3), with the node at (ox, oy).
+__device__ __forceinline__ double fan_quality(int p, double ox, double oy, const double2 a, const double2 b)
+{
+    if (p == 0) return tri_quality(ox, oy, a.x, a.y, b.x, b.y);
+    if (p == 1) return tri_quality(b.x, b.y, ox, oy, a.x, a.y);
+    return tri_quality(a.x, a.y, b.x, b.y, ox, oy);
+}
+
+template <bool SOA>
+__device__ __forceinline__ double2 ld(const double* X, int64_t n, int64_t i)
+{
+    if (SOA) return make_double2(X[i], X[n + i]);
+    return reinterpret_cast<const double2*>(X)[i];
+}
+
+template <bool SOA>
+__device__ __forceinline__ void st(double* X, int64_t n, int64_t i, double x, double y)
+{
+    if (SOA) { X[i] = x; X[n + i] = y; }
+    else reinterpret_cast<double2*>(X)[i] = make_double2(x, y);
+}
+
+struct SweepArgs {
+    const double* Xin;
+    double* Xout;
+    int64_t n;                      // total nodes (SoA stride)
+    const int32_t* row_ptr;
+    const int32_t* nbr;
+    const int32_t* fan_ptr;
+    const uint16_t* fan;
+    int32_t k_begin, k_end;         // device labels handled by this launch
+    int32_t n_tiles, tiles_per_xcd; // work-group tiles; XCD-contiguous mapping
+    const uint64_t* prev_maxd;      // nullable: skip if *prev_maxd < tol2
+    double tol2;
+    uint64_t* maxd;                 // this sweep's max squared displacement (bit pattern)
+    unsigned long long* acc;        // this sweep's accepted count
+    uint64_t* bits;                 // nullable: this sweep's accept bits (device labels)
+};
+
+template <int BLOCK, int MAXV, bool SOA, bool GT>
+__global__ __launch_bounds__(BLOCK) void k_sweep(SweepArgs a)
+{
+    if (a.prev_maxd != nullptr && __longlong_as_double(static_cast<long long>(*a.prev_maxd)) < a.tol2) return;
+    // Work-groups are handed to the 8 XCDs round-robin; give each XCD a
+    // contiguous run of tiles so that neighbouring tiles share its L2.
+    const int tile = static_cast<int>(blockIdx.x % 8) * a.tiles_per_xcd + static_cast<int>(blockIdx.x / 8);
+    if (tile >= a.n_tiles) return;
+
+    __shared__ double2 nb[MAXV][BLOCK];
+    __shared__ double s_d2[BLOCK / 64];
+    __shared__ unsigned long long s_acc[BLOCK / 64];
+
+    const int tid = threadIdx.x;
+    const int k = a.k_begin + tile * BLOCK + tid;
+    bool accepted = false;
+    double d2 = 0.0;
+    if (k < a.k_end) {
+        const int32_t r0 = a.row_ptr[k], d = a.row_ptr[k + 1] - r0;
+        double sx = 0.0, sy = 0.0;
+        for (int32_t j = 0; j < d; ++j) {
+            const double2 p = ld<SOA>(a.Xin, a.n, a.nbr[r0 + j]);
+            sx += p.x;
+            sy += p.y;
+            nb[j][tid] = p;
+        }
+        const double dn = static_cast<double>(d);
+        const double cx = sx / dn, cy = sy / dn;
+        const double2 o = ld<SOA>(a.Xin, a.n, k);
+        double qo = INFINITY, qn = INFINITY;
+        const int32_t f1 = a.fan_ptr[k + 1];
+        for (int32_t f = a.fan_ptr[k]; f < f1; ++f) {
+            const uint32_t e = a.fan[f];
+            const int p = static_cast<int>(e & 3u);
+            const double2 va = nb[(e >> 2) & 127u][tid];
+            const double2 vb = nb[(e >> 9) & 127u][tid];
+            const double v = fan_quality(p, o.x, o.y, va, vb);
+            if (v < qo) qo = v;
+            const double w = fan_quality(p, cx, cy, va, vb);
+            if (w < qn) qn = w;
+        }
+        accepted = GT ? (qn > qo) : (qn >= qo);
+        const double nx = accepted ? cx : o.x, ny = accepted ? cy : o.y;
+        st<SOA>(a.Xout, a.n, k, nx, ny);
+        const double dx = nx - o.x, dy = ny - o.y;
+        d2 = dx * dx + dy * dy;
+    }
+
+    // wave reductions: accepted count, accept bits, max displacement
+    const unsigned long long ball = __ballot(accepted);
+    const int lane = tid & 63, w = tid >> 6;
+    if (a.bits != nullptr && lane == 0 && ball != 0ull) {
+        const int kw = a.k_begin + tile * BLOCK + w * 64;
+        const int sh = kw & 63;
+        unsigned long long* word = reinterpret_cast<unsigned long long*>(a.bits) + (kw >> 6);
+        atomicOr(word, ball << sh);
+        if (sh != 0 && (ball >> (64 - sh)) != 0ull) atomicOr(word + 1, ball >> (64 - sh));
+    }
+    for (int off = 32; off > 0; off >>= 1) {
+        const double t = __shfl_xor(d2, off);
+        d2 = t > d2 ? t : d2;
+    }
+    if (lane == 0) {
+        s_d2[w] = d2;
+        s_acc[w] = __popcll(ball);
+    }
+    __syncthreads();
+    if (tid == 0) {
+        double m = s_d2[0];
+        unsigned long long c = s_acc[0];
+        for (int q = 1; q < BLOCK / 64; ++q) {
+            m = s_d2[q] > m ? s_d2[q] : m;
+            c += s_acc[q];
+        }
+        if (m > 0.0) atomicMax(reinterpret_cast<unsigned long long*>(a.maxd), static_cast<unsigned long long>(__double_as_longlong(m)));
+        if (c) atomicAdd(a.acc, c);
+    }
+}
+
+template <int BLOCK, int MAXV>
+void launch_variant(const SweepArgs& a, bool soa, bool gt, int grid, hipStream_t st)
+{
+    if (soa) {
+        if (gt) k_sweep<BLOCK, MAXV, true, true><<<grid, BLOCK, 0, st>>>(a);
+        else k_sweep<BLOCK, MAXV, true, false><<<grid, BLOCK, 0, st>>>(a);
+    } else {
+        if (gt) k_sweep<BLOCK, MAXV, false, true><<<grid, BLOCK, 0, st>>>(a);
+        else k_sweep<BLOCK, MAXV, false, false><<<grid, BLOCK, 0, st>>>(a);
+    }
+}
+
+// Work-group size of the variant used for a given largest valence.
+int block_for(int max_deg, int requested)
+{
+    if (max_deg <= 8) return (requested == 64 || requested == 128) ? requested : 256;
+    if (max_deg <= 16) return 256;
+    if (max_deg <= 32) return 128;
+    return 64;
+}
+
+void launch_range(SweepArgs a, int max_deg, int requested_block, bool soa, bool gt, hipStream_t st)
+{
+    const int64_t cnt = static_cast<int64_t>(a.k_end) - a.k_begin;
+    if (cnt <= 0) return;
+    const int block = block_for(max_deg, requested_block);
+    a.n_tiles = div_up(cnt, block);
+    a.tiles_per_xcd = div_up(a.n_tiles, 8);
+    const int grid = 8 * a.tiles_per_xcd;
+    if (max_deg <= 8) {
+        if (block == 64) launch_variant<64, 8>(a, soa, gt, grid, st);
+        else if (block == 128) launch_variant<128, 8>(a, soa, gt, grid, st);
+        else launch_variant<256, 8>(a, soa, gt, grid, st);
+    } else if (max_deg <= 16) {
+        launch_variant<256, 16>(a, soa, gt, grid, st);
+    } else if (max_deg <= 32) {
+        launch_variant<128, 32>(a, soa, gt, grid, st);
+    } else {
+        launch_variant<64, 128>(a, soa, gt, grid, st);
+    }
+}
+
+}  // namespace
+
+sl_status launch_sweep(const DevMesh& m, int32_t s, int32_t form, int32_t accept, int32_t block, double tol2,
+                       const SweepOut& out, hipStream_t st)
+{
+    SweepArgs a{};
+    a.n = m.n;
+    a.row_ptr = m.row_ptr;
+    a.nbr = m.nbr;
+    a.fan_ptr = m.fan_ptr;
+    a.fan = m.fan;
+    a.prev_maxd = (s > 0 && tol2 > 0.0) ? out.maxd + (s - 1) : nullptr;
+    a.tol2 = tol2;
+    a.maxd = out.maxd + s;
+    a.acc = out.acc + s;
+    a.bits = out.bits ? out.bits + static_cast<int64_t>(s) * out.words : nullptr;
+    const bool soa = m.layout == SL_SOA, gt = accept == SL_ACCEPT_GT;
+    if (form == SL_JACOBI) {
+        a.Xin = m.X[s & 1];
+        a.Xout = m.X[(s + 1) & 1];
+        a.k_begin = 0;
+        a.k_end = m.n_free;
+        launch_range(a, m.max_deg, block, soa, gt, st);
+    } else {
+        a.Xin = m.X[0];
+        a.Xout = m.X[0];
+        for (int c = 0; c < m.n_colors; ++c) {
+            a.k_begin = m.color_start_h[c];
+            a.k_end = m.color_start_h[c + 1];
+            launch_range(a, m.max_deg, block, soa, gt, st);
+        }
+    }
+    SL_HIP(hipGetLastError());
+    return SL_OK;
+}
+
+}  // namespace sl

@@ -1,0 +1,62 @@
+"""The C-ABI library loads and exports every entry point its header declares.
+
+No compute call is made here (no GPU in this environment); only argument
+checks that return before any device work.
+"""
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+import pytest
+
+import paper_1502_00355_amd as sl
+
+
+@pytest.fixture(scope="module")
+def L():
+    if not os.path.exists(sl.LIB_PATH):
+        pytest.fail("libsmartlap.so not built: run __graft_entry__.build()")
+    return sl.lib()
+
+
+def test_header_symbols_are_exported(L):
+    names = sl.header_symbols()
+    assert {"smooth_mesh", "smooth_mesh_device", "sl_last_error", "sl_options_default", "sl_version"} <= set(names)
+    out = subprocess.run(["nm", "-D", "--defined-only", sl.LIB_PATH], stdout=subprocess.PIPE, text=True).stdout
+    exported = {ln.split()[-1] for ln in out.splitlines() if " T " in ln}
+    for n in names:
+        assert n in exported, n
+        getattr(L, n)
+
+
+def test_only_the_c_abi_is_exported():
+    out = subprocess.run(["nm", "-D", "--defined-only", sl.LIB_PATH], stdout=subprocess.PIPE, text=True).stdout
+    exported = {ln.split()[-1] for ln in out.splitlines() if " T " in ln}
+    assert exported <= set(sl.header_symbols()) | {"_init", "_fini"}, exported - set(sl.header_symbols())
+
+
+def test_option_defaults(L):
+    o = sl.Options()
+    L.sl_options_default(ctypes.byref(o))
+    assert (o.form, o.accept, o.layout, o.reorder, o.block_size) == (0, 0, 0, 1, 0)
+    assert not o.flags_out
+    assert L.sl_version().startswith(b"smartlap")
+
+
+def _call(n_nodes=4, iterations=1, null_coords=False):
+    X = np.zeros((4, 2))
+    ptr = np.zeros(5, np.int32)
+    idx = np.zeros(1, np.int32)
+    b = np.ones(4, np.uint8)
+    return sl.lib().smooth_mesh(None if null_coords else X.ctypes.data, n_nodes, ptr.ctypes.data, idx.ctypes.data,
+                                ptr.ctypes.data, idx.ctypes.data, idx.ctypes.data, 0, b.ctypes.data, iterations,
+                                0.0, None, None)
+
+
+def test_argument_errors_before_device_work(L):
+    assert _call(n_nodes=0) == sl.SL_EINVAL
+    assert b"n_nodes" in L.sl_last_error()
+    assert _call(iterations=-1) == sl.SL_EINVAL
+    assert _call(null_coords=True) == sl.SL_EINVAL
+    assert b"null" in L.sl_last_error()

@@ -1,0 +1,249 @@
+"""GPU parity: the HIP path through the C ABI against the FP64 oracle.
+
+Bar (Jacobi form): accept/reject flags bit-exact in every sweep, coordinates
+within 1e-12 absolute (the arithmetic is the same IEEE sequence on both
+sides, so bit-exact is expected and also reported).  Coloured form: the same
+colouring on both sides, so the same bar applies; its invariants are checked
+too.  Inputs are seeded synthetic meshes from ``meshgen``.
+"""
+import ctypes
+import math
+import sys
+
+import numpy as np
+import pytest
+
+import meshgen
+import oracle
+import paper_1502_00355_amd as sl
+
+pytestmark = pytest.mark.gpu
+COORD_TOL = 1e-12
+
+
+@pytest.fixture(scope="module", autouse=True)
+def gpu():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    torch.cuda.set_device(0)
+    sl.lib()
+    yield
+
+
+def note(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def run_gpu(m, iters, tol=0.0, want_flags=True, **opts):
+    import torch
+    dev = sl.to_device(m, "cuda:0")
+    nbytes = (m.n_nodes + 7) // 8
+    flags = torch.zeros(max(iters, 1) * nbytes, dtype=torch.uint8, device="cuda:0") if want_flags else None
+    rep = sl.smooth_mesh_device(*dev, iterations=iters, tol=tol, flags=flags, **opts)
+    torch.cuda.synchronize()
+    X = dev[0].cpu().numpy()
+    F = sl.unpack_flags(flags.cpu().numpy().reshape(max(iters, 1), nbytes), m.n_nodes)[:iters] if want_flags else None
+    return X, rep, F
+
+
+def assert_parity(m, iters, tol=0.0, accept="ge", form="jacobi", threads=None, **opts):
+    note("parity %s iters=%d tol=%g accept=%s form=%s %s" % (m.name, iters, tol, accept, form, opts))
+    X, rep, F = run_gpu(m, iters, tol, accept=accept, form=form, **opts)
+    ref = oracle.smooth(m, iters, tol=tol, accept_gt=(accept == "gt"), threads=threads or oracle.max_threads(),
+                        form=form)
+    assert rep.iterations_run == ref.iterations_run
+    k = ref.iterations_run
+    assert (F[:k] == (ref.flags == 1)).all(), "flags differ in sweeps %s" % np.flatnonzero(
+        (F[:k] != (ref.flags == 1)).any(axis=1))
+    assert (F[k:] == 0).all()
+    err = float(np.abs(X - ref.coords).max())
+    assert err <= COORD_TOL, err
+    if k:
+        assert rep.accepted_last == ref.accepted[-1]
+        assert rep.accepted_total == int(ref.accepted.sum())
+        assert rep.max_disp_sq_last == ref.disp[-1]
+    return X, rep, ref, int(np.count_nonzero(X != ref.coords))
+
+
+def test_config_small_grid_64():
+    """64 x 64 Union-Jack grid, +-0.3h jitter, seed 1, 10 sweeps."""
+    m = meshgen.make_grid(64, "unionjack", 0.3, 1)
+    X, rep, ref, ndiff = assert_parity(m, 10)
+    assert ndiff == 0                      # same IEEE sequence: bit-exact
+    assert rep.setup_ms > 0 and rep.sweep_ms > 0
+
+
+@pytest.mark.parametrize("layout", ["aos", "soa"])
+@pytest.mark.parametrize("reorder", ["none", "hilbert"])
+@pytest.mark.parametrize("block", [0, 64, 128])
+def test_variants_are_bit_identical(layout, reorder, block):
+    m = meshgen.make_grid(47, "random", 0.4, 5)       # 2025 free nodes: several tiles and a ragged tail
+    X, rep, ref, ndiff = assert_parity(m, 8, layout=layout, reorder=reorder, block_size=block)
+    assert ndiff == 0
+
+
+def test_strict_accept_rule():
+    m = meshgen.make_grid(40, "random", 0.35, 6)
+    assert_parity(m, 6, accept="gt")
+    d = meshgen.make_grid(33, "unionjack", 0.0, 0, h=1.0 / 32)      # exact fixed point: all ties
+    X, rep, F = run_gpu(d, 3, accept="gt")
+    assert (X == d.coords).all() and rep.accepted_total == 0
+    X, rep, F = run_gpu(d, 3, accept="ge")
+    assert (X == d.coords).all() and rep.accepted_total == 3 * d.n_interior
+
+
+@pytest.mark.parametrize("n", [3, 4, 5, 9, 17, 18, 33])
+def test_ragged_sizes(n):
+    assert_parity(meshgen.make_grid(n, "random", 0.4, 100 + n), 5)
+
+
+def test_annulus_and_permuted():
+    assert_parity(meshgen.make_annulus(40, 64, seed=4), 12)
+    assert_parity(meshgen.permute_mesh(meshgen.make_grid(50, "random", 0.4, 7), 8), 12)
+
+
+def test_config_1024_permuted_full():
+    """1024 x 1024, random diagonals, +-0.4h, random node permutation, 100
+    sweeps; AoS and SoA, reorder on and off: every flag of every sweep."""
+    m = meshgen.permute_mesh(meshgen.make_grid(1024, "random", 0.4, 2), 2)
+    ref = oracle.smooth(m, 100, threads=oracle.max_threads())
+    rf = ref.flags == 1
+    for layout in ("aos", "soa"):
+        for reorder in ("hilbert", "none"):
+            note("1024^2 permuted, 100 sweeps, %s %s" % (layout, reorder))
+            X, rep, F = run_gpu(m, 100, layout=layout, reorder=reorder)
+            assert rep.iterations_run == 100
+            assert (F == rf).all()
+            assert float(np.abs(X - ref.coords).max()) <= COORD_TOL
+            assert (X == ref.coords).all()
+
+
+@pytest.mark.parametrize("kind", ["grid", "annulus"])
+def test_config_4096_sampled(kind):
+    """Full 16.8M-node size, in the launch configuration the benchmark uses
+    (AoS, Hilbert, automatic block): 10 sweeps, every flag, all coordinates."""
+    m = meshgen.make_grid(4096, "random", 0.4, 3) if kind == "grid" else meshgen.make_annulus(4096, 4096, seed=4)
+    note("4096^2 %s generated" % kind)
+    X, rep, F = run_gpu(m, 10)
+    ref = oracle.smooth(m, 10, threads=oracle.max_threads())
+    assert rep.iterations_run == 10
+    assert rep.accepted_total == int(ref.accepted.sum())
+    assert (F == (ref.flags == 1)).all()
+    assert float(np.abs(X - ref.coords).max()) <= COORD_TOL
+
+
+def test_tolerance_stop():
+    m = meshgen.make_grid(30, "random", 0.4, 9)
+    ref = oracle.smooth(m, 200, tol=0.0)
+    # a tolerance the run reaches part-way through
+    tol = math.sqrt(ref.disp[40]) * 1.0000001
+    X, rep, ref2, _ = assert_parity(m, 200, tol=tol)
+    assert 0 < rep.iterations_run < 200
+
+
+def test_zero_iterations_and_all_fixed():
+    m = meshgen.make_grid(16, "random", 0.4, 10)
+    X, rep, F = run_gpu(m, 0)
+    assert (X == m.coords).all() and rep.iterations_run == 0
+    b = m.copy()
+    b.boundary[:] = 1
+    X, rep, F = run_gpu(b, 4)
+    assert (X == m.coords).all() and rep.accepted_total == 0 and (F == 0).all()
+    t = meshgen.star_mesh((0.1, 0.2), [(1, 0), (0, 1), (-1, 0)])
+    assert_parity(t, 3)
+
+
+def _ring_star(k, seed):
+    rng = np.random.Generator(np.random.PCG64(seed))
+    ang = np.sort(rng.uniform(0, 2 * np.pi, k))
+    ring = np.stack([np.cos(ang), np.sin(ang)], 1) * rng.uniform(0.8, 1.2, (k, 1))
+    return meshgen.star_mesh(rng.uniform(-0.2, 0.2, 2), ring)
+
+
+@pytest.mark.parametrize("k", [3, 8, 9, 16, 17, 32, 33, 100, 127])
+def test_valence_classes(k):
+    assert_parity(_ring_star(k, k), 3)
+
+
+def test_valence_limit_rejected():
+    m = _ring_star(128, 1)
+    with pytest.raises(sl.SmartlapError) as e:
+        run_gpu(m, 1)
+    assert e.value.status == sl.SL_ETOPO
+
+
+def test_input_errors():
+    m = meshgen.make_grid(8, "random", 0.3, 11)
+
+    def call(mm):
+        """Raw C call on the caller's own coordinate buffer."""
+        arrs = [np.ascontiguousarray(a, dtype=np.int32) for a in (mm.nbr_ptr, mm.nbr_idx, mm.tri_ptr, mm.tri_idx)]
+        tr = np.ascontiguousarray(mm.tris, dtype=np.int32)
+        b = np.ascontiguousarray(mm.boundary, dtype=np.uint8)
+        rep = sl.Report()
+        st = sl.lib().smooth_mesh(mm.coords.ctypes.data, mm.n_nodes, arrs[0].ctypes.data, arrs[1].ctypes.data,
+                                  arrs[2].ctypes.data, arrs[3].ctypes.data, tr.ctypes.data, mm.n_tris,
+                                  b.ctypes.data, 2, 0.0, None, ctypes.byref(rep))
+        if st != sl.SL_OK:
+            raise sl.SmartlapError(st, sl.lib().sl_last_error().decode())
+        return rep
+
+    cases = []
+    a = m.copy(); a.nbr_idx[5] = m.n_nodes + 3; cases.append((a, sl.SL_EINVAL))
+    a = m.copy(); a.coords[20, 1] = np.nan; cases.append((a, sl.SL_EINVAL))
+    a = m.copy(); a.tri_idx[7] = -1; cases.append((a, sl.SL_EINVAL))
+    a = m.copy(); a.nbr_ptr[10] = a.nbr_ptr[11] + 1; cases.append((a, sl.SL_EINVAL))
+    a = m.copy(); i = 20; a.nbr_idx[a.nbr_ptr[i]] = i; cases.append((a, sl.SL_ETOPO))
+    a = m.copy(); a.tris[3, 1] = a.tris[3, 0]; cases.append((a, sl.SL_ETOPO))
+    a = m.copy(); i = 20; a.tri_idx[a.tri_ptr[i]] = a.tri_idx[a.tri_ptr[0]]; cases.append((a, sl.SL_ETOPO))
+    for bad, want in cases:
+        before = bad.coords.copy()
+        with pytest.raises(sl.SmartlapError) as e:
+            call(bad)
+        assert e.value.status == want, str(e.value)
+        assert np.array_equal(bad.coords, before, equal_nan=True)      # untouched on error
+    before = m.coords.copy()
+    rep = call(m)
+    assert rep.iterations_run == 2 and not (m.coords == before).all()
+
+
+def test_host_and_device_entry_points_agree():
+    m = meshgen.make_grid(60, "random", 0.4, 12)
+    Xh, rh, Fh = sl.smooth_mesh(m.coords, m.nbr_ptr, m.nbr_idx, m.tri_ptr, m.tri_idx, m.tris, m.boundary, 7,
+                                want_flags=True)
+    Xd, rd, Fd = run_gpu(m, 7)
+    assert (Xh == Xd).all()
+    assert (sl.unpack_flags(Fh, m.n_nodes) == Fd).all()
+    assert rh.accepted_total == rd.accepted_total
+
+
+def test_resume_and_repeat_are_bit_exact():
+    m = meshgen.make_grid(64, "random", 0.4, 13)
+    X12, _, _ = run_gpu(m, 12)
+    X12b, _, _ = run_gpu(m, 12)
+    m6 = m.copy()
+    m6.coords, _, _ = run_gpu(m, 6)
+    X66, _, _ = run_gpu(m6, 6)
+    assert (X12 == X12b).all() and (X12 == X66).all()
+
+
+def test_colored_form_parity_and_invariants():
+    m = meshgen.make_grid(48, "random", 0.4, 14)
+    X, rep, ref, ndiff = assert_parity(m, 8, form="colored")
+    col, nc = oracle.colors(m)
+    assert rep.n_colors == nc
+    b = m.boundary.astype(bool)
+    assert (X[b] == m.coords[b]).all() and np.isfinite(X).all()
+    for layout in ("aos", "soa"):
+        for reorder in ("none", "hilbert"):
+            X2, _, _ = run_gpu(m, 8, form="colored", layout=layout, reorder=reorder)
+            assert (X2 == X).all()
+    # mesh-wide worst quality never drops over a coloured sweep
+    prev = min(oracle.quality(*m.coords[a], *m.coords[c], *m.coords[d]) for a, c, d in m.tris)
+    mm = m.copy()
+    for _ in range(4):
+        mm.coords, _, _ = run_gpu(mm, 1, form="colored")
+        cur = min(oracle.quality(*mm.coords[a], *mm.coords[c], *mm.coords[d]) for a, c, d in m.tris)
+        assert cur >= prev
+        prev = cur
