@@ -29,7 +29,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-SWEEP_KERNEL = "k_sweep"
+SWEEP_KERNELS = {1: "k_sweep", 2: "k_sweep_tile"}
 
 
 def workload(name: str):
@@ -75,7 +75,7 @@ def traffic_from_profile(kernel_source_hash: str):
 def kernel_source_hash() -> str:
     import hashlib
     h = hashlib.sha256()
-    for f in ("sl_sweep.hip", "sl_common.h"):
+    for f in ("sl_sweep.hip", "sl_tiles.hip", "sl_common.h"):
         with open(os.path.join(ROOT, "paper_1502_00355_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()
@@ -106,6 +106,7 @@ def main():
     ap.add_argument("--workload", default="grid4096")
     ap.add_argument("--layout", default="aos")
     ap.add_argument("--reorder", default="hilbert")
+    ap.add_argument("--kernel", default="auto")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     args = ap.parse_args()
@@ -131,7 +132,7 @@ def main():
     def step():
         work.copy_(X0)
         return sl.smooth_mesh_device(work, *dev[1:], iterations=iters, layout=args.layout, reorder=args.reorder,
-                                     stream=stream)
+                                     kernel=args.kernel, stream=stream)
 
     for w in range(args.warmup):
         r = step()
@@ -165,13 +166,14 @@ def main():
         "dtype": "f64",
         "data": "synthetic",
         "config": {"workload": m.name, "nodes": m.n_nodes, "free_nodes": free, "triangles": m.n_tris,
-                   "sweeps_per_step": iters, "form": "jacobi", "layout": args.layout, "reorder": args.reorder},
+                   "sweeps_per_step": iters, "form": "jacobi", "layout": args.layout, "reorder": args.reorder,
+                   "kernel": {1: "node", 2: "tile"}.get(r.kernel_used, "?")},
         "sweep_only_node_updates_per_s": free / avg_sweep_s,
         "sweep_ms_per_sweep": avg_sweep_s * 1e3,
         "setup_ms_per_step": float(np.mean(setup_ms)),
         "hbm_gbs_algorithmic": achieved,
         "hbm_pct_peak": 100.0 * achieved / HBM_PEAK_GBS,
-        "roofline": {"bound": "hbm", "kernel": SWEEP_KERNEL, "achieved": achieved, "peak": HBM_PEAK_GBS,
+        "roofline": {"bound": "hbm", "kernel": SWEEP_KERNELS.get(r.kernel_used, "?"), "achieved": achieved, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
                      "traffic": traffic, "alg_bytes_per_launch": alg_bytes},
     }

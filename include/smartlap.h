@@ -69,14 +69,20 @@ typedef enum {
 } sl_accept;
 typedef enum { SL_AOS = 0, SL_SOA = 1 } sl_layout;   /* coordinate stream on the device */
 typedef enum { SL_REORDER_NONE = 0, SL_REORDER_HILBERT = 1 } sl_reorder;
+typedef enum {
+    SL_KERNEL_AUTO = 0,  /* tile kernel for Form A when the mesh fits it, else the node kernel */
+    SL_KERNEL_NODE = 1,  /* one work-item per free node, neighbours gathered from HBM/L2 */
+    SL_KERNEL_TILE = 2   /* work-group per tile of free nodes staged in LDS (Form A only;
+                            valence and incidence <= 16), falls back to the node kernel */
+} sl_kernel;
 
 typedef struct {
     int32_t form;        /* sl_form */
     int32_t accept;      /* sl_accept */
     int32_t layout;      /* sl_layout */
     int32_t reorder;     /* sl_reorder: node order used on the device; results do not depend on it */
-    int32_t block_size;  /* work-group size for the sweep kernel: 0 = automatic, else 64/128/256 */
-    int32_t reserved;
+    int32_t block_size;  /* node kernel work-group size: 0 = automatic, else 64/128/256 */
+    int32_t kernel;      /* sl_kernel; results do not depend on it */
     /* Optional accept flags, nullable.  Size iterations * ((n_nodes + 7) / 8)
      * bytes; sweep k occupies bytes [k*((n+7)/8), (k+1)*((n+7)/8)); bit (i % 8)
      * of byte (i / 8) is 1 iff free node i accepted its move in sweep k
@@ -94,10 +100,12 @@ typedef struct {
     double setup_ms;            /* device time: validation, reorder, relabel, fan build */
     double sweep_ms;            /* device time of the sweep loop only */
     double total_ms;            /* host wall time of the whole call */
+    int32_t kernel_used;        /* SL_KERNEL_NODE or SL_KERNEL_TILE */
+    int32_t tile_nodes;         /* free nodes per tile on the tile path, else 0 */
 } sl_report;
 
 /* Fills *opts with the defaults: Jacobi, GE, AoS, Hilbert reorder, automatic
- * block size, no flags. */
+ * block size and kernel, no flags. */
 SL_API void sl_options_default(sl_options* opts);
 
 /*

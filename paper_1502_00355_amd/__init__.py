@@ -25,6 +25,7 @@ FORMS = {"jacobi": 0, "colored": 1}
 ACCEPT = {"ge": 0, "gt": 1}
 LAYOUTS = {"aos": 0, "soa": 1}
 REORDER = {"none": 0, "hilbert": 1}
+KERNELS = {"auto": 0, "node": 1, "tile": 2}
 
 
 class SmartlapError(RuntimeError):
@@ -35,7 +36,7 @@ class SmartlapError(RuntimeError):
 
 class Options(ctypes.Structure):
     _fields_ = [("form", ctypes.c_int32), ("accept", ctypes.c_int32), ("layout", ctypes.c_int32),
-                ("reorder", ctypes.c_int32), ("block_size", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("reorder", ctypes.c_int32), ("block_size", ctypes.c_int32), ("kernel", ctypes.c_int32),
                 ("flags_out", ctypes.c_void_p)]
 
 
@@ -43,7 +44,7 @@ class Report(ctypes.Structure):
     _fields_ = [("iterations_run", ctypes.c_int32), ("n_colors", ctypes.c_int32),
                 ("max_disp_sq_last", ctypes.c_double), ("accepted_last", ctypes.c_int64),
                 ("accepted_total", ctypes.c_int64), ("setup_ms", ctypes.c_double), ("sweep_ms", ctypes.c_double),
-                ("total_ms", ctypes.c_double)]
+                ("total_ms", ctypes.c_double), ("kernel_used", ctypes.c_int32), ("tile_nodes", ctypes.c_int32)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}
@@ -78,7 +79,8 @@ def _check(status: int):
         raise SmartlapError(status, lib().sl_last_error().decode())
 
 
-def make_options(form="jacobi", accept="ge", layout="aos", reorder="hilbert", block_size=0, flags_ptr=None):
+def make_options(form="jacobi", accept="ge", layout="aos", reorder="hilbert", block_size=0, kernel="auto",
+                 flags_ptr=None):
     o = Options()
     lib().sl_options_default(ctypes.byref(o))
     o.form = FORMS[form] if isinstance(form, str) else int(form)
@@ -86,6 +88,7 @@ def make_options(form="jacobi", accept="ge", layout="aos", reorder="hilbert", bl
     o.layout = LAYOUTS[layout] if isinstance(layout, str) else int(layout)
     o.reorder = REORDER[reorder] if isinstance(reorder, str) else int(reorder)
     o.block_size = int(block_size)
+    o.kernel = KERNELS[kernel] if isinstance(kernel, str) else int(kernel)
     o.flags_out = flags_ptr
     return o
 

@@ -56,6 +56,8 @@ sl_status check_options(const sl_options& o)
     if (o.reorder != SL_REORDER_NONE && o.reorder != SL_REORDER_HILBERT) return fail(SL_EINVAL, "unknown reorder");
     if (o.block_size != 0 && o.block_size != 64 && o.block_size != 128 && o.block_size != 256)
         return fail(SL_EINVAL, "block_size must be 0, 64, 128 or 256");
+    if (o.kernel != SL_KERNEL_AUTO && o.kernel != SL_KERNEL_NODE && o.kernel != SL_KERNEL_TILE)
+        return fail(SL_EINVAL, "unknown kernel");
     return SL_OK;
 }
 
@@ -154,6 +156,8 @@ sl_status run_device(double* coords, int32_t n, const int32_t* nbr_ptr, const in
         SL_HIP(hipEventElapsedTime(&ms, cs.ev[2], cs.ev[3]));
         rep.sweep_ms = ms;
         rep.total_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+        rep.kernel_used = cs.m.tile_nodes > 0 ? SL_KERNEL_TILE : SL_KERNEL_NODE;
+        rep.tile_nodes = cs.m.tile_nodes;
         *report = rep;
     }
     return SL_OK;
@@ -182,6 +186,7 @@ void sl_options_default(sl_options* o)
     o->layout = SL_AOS;
     o->reorder = SL_REORDER_HILBERT;
     o->block_size = 0;
+    o->kernel = SL_KERNEL_AUTO;
     o->flags_out = nullptr;
 }
 

@@ -64,9 +64,20 @@ struct DevMesh {
     int32_t* nbr = nullptr;         // [nnz_free] device labels
     int32_t* fan_ptr = nullptr;     // [n_free+1]
     uint16_t* fan = nullptr;        // [ninc_free]
-    int32_t* color_start = nullptr; // host copy [n_colors+1] lives in color_start_h
-    int32_t color_start_h[130] = {0};
+    int32_t color_start_h[130] = {0};    // colour class c: device labels [cs[c], cs[c+1])
     double* X[2] = {nullptr, nullptr};   // AoS: 2n doubles; SoA: x[n] then y[n]
+    // Tile path (Form A): free nodes in tiles of tile_nodes consecutive device
+    // labels; per tile a halo list, local neighbour rows and a local triangle list.
+    int32_t tile_nodes = 0;              // 0: tile path not built
+    int32_t n_tiles = 0;
+    int32_t halo_max = 0;                // largest halo over tiles
+    int32_t rows_max = 0;                // largest row segment (u16 entries, padded to 4) over tiles
+    int4* tile_meta = nullptr;           // [n_tiles] {halo_off, halo_cnt, tri_off, tri_cnt}
+    int2* tile_rows = nullptr;           // [n_tiles] {row segment offset (multiple of 4), padded length}
+    int32_t* halo = nullptr;             // [sum halo] device labels
+    uint16_t* nbr_loc = nullptr;         // tile row segments: local index of each neighbour, row order
+    uint16_t* row_rel = nullptr;         // [n_tiles * (tile_nodes+1)] row start inside the tile's segment
+    uint64_t* tri_loc = nullptr;         // [sum tri] 3 x 16-bit local vertex indices, stored order
 };
 
 // Frees every device array of m (stream-ordered).
@@ -84,6 +95,10 @@ struct SetupArgs {
     const uint8_t* boundary;
     int64_t nnz, ninc;      // nbr_ptr[n], tri_ptr[n] (read by the caller of setup)
 };
+
+// Builds the tile path for Form A (tile_nodes free nodes per tile).  Leaves
+// m.tile_nodes = 0 (node path) when the mesh does not fit it.
+sl_status build_tiles(const SetupArgs& a, DevMesh& m, int tile_nodes, hipStream_t st);
 
 // Validates the inputs, orders the nodes, builds rows and fans and fills both
 // coordinate buffers.  Synchronises `st` (the validation result is needed).
@@ -110,6 +125,10 @@ struct SweepOut {
 // previous sweep's displacement is below tol2 (tol2 > 0).
 sl_status launch_sweep(const DevMesh& m, int32_t s, int32_t form, int32_t accept, int32_t block, double tol2,
                        const SweepOut& out, hipStream_t st);
+
+// Queues sweep `s` on the tile path (Form A).
+sl_status launch_sweep_tiles(const DevMesh& m, int32_t s, int32_t accept, double tol2, const SweepOut& out,
+                             hipStream_t st);
 
 // Exclusive scan of n int32 values; out[n] receives the total (out has n+1).
 sl_status scan_exclusive(const int32_t* in, int32_t* out, int64_t n, hipStream_t st);

@@ -570,6 +570,12 @@ void devmesh_free(DevMesh& m, hipStream_t st)
     dfree(m.fan, st);
     dfree(m.X[0], st);
     dfree(m.X[1], st);
+    dfree(m.tile_meta, st);
+    dfree(m.tile_rows, st);
+    dfree(m.halo, st);
+    dfree(m.nbr_loc, st);
+    dfree(m.row_rel, st);
+    dfree(m.tri_loc, st);
 }
 
 sl_status setup_mesh(const SetupArgs& a, const sl_options& o, DevMesh& m, hipStream_t st)
@@ -665,10 +671,15 @@ sl_status setup_mesh(const SetupArgs& a, const sl_options& o, DevMesh& m, hipStr
     dfree(inc, st);
     m.nnz_free = tot[0];
     m.ninc_free = tot[1];
-    if ((r = dalloc(&m.nbr, m.nnz_free, st)) || (r = dalloc(&m.fan, m.ninc_free, st))) return r;
-    if (m.n_free > 0)
-        k_rows_fans<<<gf, kBS, 0, st>>>(m.perm, m.new_of_old, m.n_free, a.nbr_ptr, a.nbr_idx, a.tri_ptr, a.tri_idx,
-                                        a.tris, m.row_ptr, m.nbr, m.fan_ptr, m.fan);
+    // tile path for Form A; the node path's rows and fans otherwise
+    if (o.form == SL_JACOBI && o.kernel != SL_KERNEL_NODE)
+        if ((r = build_tiles(a, m, 512, st))) return r;
+    if (m.tile_nodes == 0) {
+        if ((r = dalloc(&m.nbr, m.nnz_free, st)) || (r = dalloc(&m.fan, m.ninc_free, st))) return r;
+        if (m.n_free > 0)
+            k_rows_fans<<<gf, kBS, 0, st>>>(m.perm, m.new_of_old, m.n_free, a.nbr_ptr, a.nbr_idx, a.tri_ptr,
+                                            a.tri_idx, a.tris, m.row_ptr, m.nbr, m.fan_ptr, m.fan);
+    }
 
     // ---- coordinate buffers
     if ((r = dalloc(&m.X[0], 2 * static_cast<size_t>(n), st)) || (r = dalloc(&m.X[1], 2 * static_cast<size_t>(n), st)))

@@ -221,6 +221,7 @@ sl_status launch_sweep(const DevMesh& m, int32_t s, int32_t form, int32_t accept
     a.maxd = out.maxd + s;
     a.acc = out.acc + s;
     a.bits = out.bits ? out.bits + static_cast<int64_t>(s) * out.words : nullptr;
+    if (form == SL_JACOBI && m.tile_nodes > 0) return launch_sweep_tiles(m, s, accept, tol2, out, st);
     const bool soa = m.layout == SL_SOA, gt = accept == SL_ACCEPT_GT;
     if (form == SL_JACOBI) {
         a.Xin = m.X[s & 1];

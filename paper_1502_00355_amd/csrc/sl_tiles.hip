@@ -1,0 +1,635 @@
+// Tile path of the Form A (Jacobi) sweep.
+//
+// The free nodes (device order: Hilbert cells) are cut into tiles of T
+// consecutive labels, one work-group per tile.  Per sweep a work-group
+//   1. stages the positions of its own nodes and of its halo (every node an
+//      own node reads) in LDS,
+//   2. computes each own node's Laplacian candidate: the row-order sum of its
+//      neighbours divided by their count (eq. (2)),
+//   3. walks the triangles incident to its own nodes, each once: the quality
+//      in stored order with all vertices at pass-q positions (the "old"
+//      quality, Sec. 2.1), then for every own vertex the quality with that
+//      vertex at its candidate -- the vertex role is fixed in the code, so
+//      no lane selects between stored positions -- folding both into the
+//      vertices' minima with LDS atomics,
+//   4. keeps each own node's candidate iff its new minimum is >= (or >) its
+//      old one and writes the node to the other buffer.
+// A triangle's old quality is evaluated by every tile that owns one of its
+// vertices (the paper evaluates it once per vertex, Sec. 5.3); each
+// (triangle, moved vertex) pair is evaluated exactly once.
+//
+// The tiles are built on the device: one work-group per tile collects the
+// halo and the incident triangles in LDS, sorts and deduplicates them, and
+// rewrites rows and triangles in tile-local indices (own nodes 0..T-1, halo
+// nodes T..T+H-1).
+#include <climits>
+
+#include "sl_common.h"
+
+namespace sl {
+
+namespace {
+
+constexpr double kTwoSqrt3 = 0x1.bb67ae8584caap+1;   // 2*sqrt(3) rounded to double
+constexpr int kTileMaxDeg = 16;                       // valence / incidence limit of the tile path
+constexpr int kBuildBS = 256;
+
+// ------------------------------------------------------ block primitives --
+
+template <int BS>
+__device__ int block_excl_scan(int v, int* total, int* s_warp)
+{
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    int x = v;
+    for (int off = 1; off < 64; off <<= 1) {
+        const int t = __shfl_up(x, off);
+        if (lane >= off) x += t;
+    }
+    if (lane == 63) s_warp[w] = x;
+    __syncthreads();
+    int base = 0, tot = 0;
+    for (int q = 0; q < BS / 64; ++q) {
+        const int c = s_warp[q];
+        if (q < w) base += c;
+        tot += c;
+    }
+    __syncthreads();
+    *total = tot;
+    return base + x - v;
+}
+
+__device__ __forceinline__ int pow2ceil(int n)
+{
+    int p = 1;
+    while (p < n) p <<= 1;
+    return p;
+}
+
+// Bitonic sort of a[0..n) (padded to P, a power of two, with INT_MAX).
+template <int BS>
+__device__ void block_sort(int32_t* a, int n, int P)
+{
+    for (int i = n + threadIdx.x; i < P; i += BS) a[i] = INT_MAX;
+    __syncthreads();
+    for (int k = 2; k <= P; k <<= 1) {
+        for (int j = k >> 1; j > 0; j >>= 1) {
+            for (int i = threadIdx.x; i < P; i += BS) {
+                const int l = i ^ j;
+                if (l > i) {
+                    const int32_t x = a[i], y = a[l];
+                    const bool up = (i & k) == 0;
+                    if ((x > y) == up) { a[i] = y; a[l] = x; }
+                }
+            }
+            __syncthreads();
+        }
+    }
+}
+
+// In-place removal of duplicates from the sorted a[0..n); returns the count.
+template <int BS>
+__device__ int block_unique(int32_t* a, int n, int* s_warp)
+{
+    int out = 0;
+    for (int base = 0; base < n; base += BS) {
+        const int i = base + threadIdx.x;
+        int32_t v = 0;
+        int f = 0;
+        if (i < n) {
+            v = a[i];
+            f = (i == 0) || (v != a[i - 1]);
+        }
+        int tot;
+        const int pos = block_excl_scan<BS>(f, &tot, s_warp);
+        if (f) a[out + pos] = v;
+        out += tot;
+        __syncthreads();
+    }
+    return out;
+}
+
+__device__ __forceinline__ int lower_bound_lds(const int32_t* a, int n, int32_t v)
+{
+    int lo = 0, hi = n;
+    while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (a[mid] < v) lo = mid + 1;
+        else hi = mid;
+    }
+    return lo;
+}
+
+// ------------------------------------------------------------ tile build --
+
+struct TileBuildArgs {
+    const int32_t* perm;
+    const int32_t* new_of_old;
+    const int32_t* nbr_ptr;
+    const int32_t* nbr_idx;
+    const int32_t* tri_ptr;
+    const int32_t* tri_idx;
+    const int32_t* tris;
+    const int32_t* row_ptr;    // device-order rows of the free nodes
+    int32_t n_free;
+    int4* counts;              // pass 0: {halo count, triangle count, padded row length, 0} per tile
+    const int32_t* halo_off;   // pass 1 inputs
+    const int32_t* tri_off;
+    const int32_t* row_off;
+    int32_t* halo;
+    uint16_t* nbr_loc;
+    uint16_t* row_rel;
+    uint64_t* tri_loc;
+    int32_t* err;
+};
+
+// One work-group per tile.  Halo: every neighbour of an own node that is not
+// own, sorted and deduplicated.  Triangles: each triangle incident to an own
+// node, listed once per tile by its own vertex of smallest label.  Rows: the
+// tile's neighbour rows in local indices, one segment padded to 4 entries.
+template <int T>
+__global__ __launch_bounds__(kBuildBS) void k_tile_build(TileBuildArgs a, int pass)
+{
+    constexpr int BS = kBuildBS, CAP = T * kTileMaxDeg, NPT = T / BS;
+    __shared__ int32_t hb[CAP];
+    __shared__ int32_t s_cnt;
+    __shared__ int32_t s_warp[BS / 64];
+    const int tile = blockIdx.x;
+    const int32_t k0 = tile * T;
+    const int nown = min(T, a.n_free - k0);
+    if (threadIdx.x == 0) s_cnt = 0;
+    __syncthreads();
+    for (int i = threadIdx.x; i < nown; i += BS) {
+        const int32_t o = a.perm[k0 + i];
+        for (int32_t q = a.nbr_ptr[o]; q < a.nbr_ptr[o + 1]; ++q) {
+            const int32_t jd = a.new_of_old[a.nbr_idx[q]];
+            if (jd < k0 || jd >= k0 + nown) hb[atomicAdd(&s_cnt, 1)] = jd;
+        }
+    }
+    __syncthreads();
+    const int nh0 = s_cnt;
+    block_sort<BS>(hb, nh0, pow2ceil(nh0));
+    const int H = block_unique<BS>(hb, nh0, s_warp);
+
+    // triangles kept by this tile: the listing node is the smallest own vertex
+    auto kept = [&](int32_t o, int32_t kd, int64_t t) -> bool {
+        for (int s = 0; s < 3; ++s) {
+            const int32_t v = a.tris[3 * t + s];
+            if (v == o) continue;
+            const int32_t vd = a.new_of_old[v];
+            if (vd >= k0 && vd < k0 + nown && vd < kd) return false;
+        }
+        return true;
+    };
+    int c = 0;
+    for (int m = 0; m < NPT; ++m) {
+        const int i = m * BS + threadIdx.x;
+        if (i < nown) {
+            const int32_t o = a.perm[k0 + i];
+            for (int32_t q = a.tri_ptr[o]; q < a.tri_ptr[o + 1]; ++q) c += kept(o, k0 + i, a.tri_idx[q]);
+        }
+    }
+    int R;
+    int tpos = block_excl_scan<BS>(c, &R, s_warp);
+    const int32_t rb = a.row_ptr[k0];
+    const int32_t len = a.row_ptr[k0 + nown] - rb;
+    const int32_t len4 = (len + 3) & ~3;
+    if (pass == 0) {
+        if (threadIdx.x == 0) a.counts[tile] = make_int4(H, R, len4, 0);
+        return;
+    }
+    const int32_t hoff = a.halo_off[tile], toff = a.tri_off[tile], roff = a.row_off[tile];
+    for (int h = threadIdx.x; h < H; h += BS) a.halo[hoff + h] = hb[h];
+    uint16_t* rr = a.row_rel + static_cast<int64_t>(tile) * (T + 1);
+    for (int i = threadIdx.x; i <= T; i += BS) rr[i] = static_cast<uint16_t>(a.row_ptr[k0 + min(i, nown)] - rb);
+    auto local = [&](int32_t jd) -> int {
+        if (jd >= k0 && jd < k0 + nown) return jd - k0;
+        const int h = lower_bound_lds(hb, H, jd);
+        if (h >= H || hb[h] != jd) { atomicOr(a.err, 1); return T; }
+        return T + h;
+    };
+    uint16_t* seg = a.nbr_loc + roff;
+    for (int j = len + threadIdx.x; j < len4; j += BS) seg[j] = 0;
+    for (int m = 0; m < NPT; ++m) {
+        const int i = m * BS + threadIdx.x;
+        if (i >= nown) continue;
+        const int32_t o = a.perm[k0 + i];
+        const int32_t b = a.nbr_ptr[o], d = a.nbr_ptr[o + 1] - b, out = a.row_ptr[k0 + i] - rb;
+        for (int j = 0; j < d; ++j) seg[out + j] = static_cast<uint16_t>(local(a.new_of_old[a.nbr_idx[b + j]]));
+        for (int32_t q = a.tri_ptr[o]; q < a.tri_ptr[o + 1]; ++q) {
+            const int64_t t = a.tri_idx[q];
+            if (!kept(o, k0 + i, t)) continue;
+            uint64_t w = 0;
+            for (int s = 0; s < 3; ++s)
+                w |= static_cast<uint64_t>(local(a.new_of_old[a.tris[3 * t + s]])) << (16 * s);
+            a.tri_loc[toff + tpos++] = w;
+        }
+    }
+}
+
+__global__ void k_split_counts(const int4* __restrict__ c, int n, int32_t* __restrict__ h, int32_t* __restrict__ r,
+                               int32_t* __restrict__ l)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) { h[i] = c[i].x; r[i] = c[i].y; l[i] = c[i].z; }
+}
+
+__global__ void k_tile_meta(const int4* __restrict__ c, const int32_t* __restrict__ hoff,
+                            const int32_t* __restrict__ toff, const int32_t* __restrict__ roff, int n,
+                            int4* __restrict__ meta, int2* __restrict__ rows, int32_t* __restrict__ mx)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    int mh = 0, ml = 0;
+    if (i < n) {
+        meta[i] = make_int4(hoff[i], c[i].x, toff[i], c[i].y);
+        rows[i] = make_int2(roff[i], c[i].z);
+        mh = c[i].x;
+        ml = c[i].z;
+    }
+    for (int off = 32; off > 0; off >>= 1) {
+        mh = max(mh, __shfl_xor(mh, off));
+        ml = max(ml, __shfl_xor(ml, off));
+    }
+    if ((threadIdx.x & 63) == 0) {
+        atomicMax(mx, mh);
+        atomicMax(mx + 1, ml);
+    }
+}
+
+// ------------------------------------------------------------ tile sweep --
+
+// Order-preserving 64-bit key of a double (for LDS atomic minima).
+__device__ __forceinline__ uint64_t okey(double q)
+{
+    const uint64_t b = static_cast<uint64_t>(__double_as_longlong(q));
+    const uint64_t m = static_cast<uint64_t>(static_cast<int64_t>(b) >> 63);
+    return b ^ (m | 0x8000000000000000ull);
+}
+__device__ __forceinline__ double okey_inv(uint64_t k)
+{
+    const uint64_t b = (k >> 63) ? (k & 0x7FFFFFFFFFFFFFFFull) : ~k;
+    return __longlong_as_double(static_cast<long long>(b));
+}
+
+// (2*sqrt(3)*cr)/S, or 0 when S == 0.
+__device__ __forceinline__ double finish_q(double cr, double S)
+{
+    const double q = (kTwoSqrt3 * cr) / S;
+    return S == 0.0 ? 0.0 : q;
+}
+
+template <bool SOA>
+__device__ __forceinline__ double2 ldx(const double* X, int64_t n, int64_t i)
+{
+    if (SOA) return make_double2(X[i], X[n + i]);
+    return reinterpret_cast<const double2*>(X)[i];
+}
+
+struct TileSweepArgs {
+    const double* Xin;
+    double* Xout;
+    int64_t n;
+    const int4* meta;
+    const int2* rows;
+    const uint16_t* row_rel;
+    const uint16_t* nbr_loc;
+    const int32_t* halo;
+    const uint64_t* tri_loc;
+    int32_t n_free, n_tiles, tiles_per_xcd, halo_cap, rows_cap;
+    const uint64_t* prev_maxd;
+    double tol2;
+    uint64_t* maxd;
+    unsigned long long* acc;
+    uint64_t* bits;
+};
+
+// Old quality of one triangle and the new quality for each own vertex,
+// folded into the per-node minima.  Local indices below T are own nodes.
+template <int T>
+__device__ __forceinline__ void tile_triangle(uint64_t w, const double2* Xl, const double2* cand, uint64_t* qo,
+                                              uint64_t* qn)
+{
+    const int l0 = static_cast<int>(w & 0xFFFF), l1 = static_cast<int>((w >> 16) & 0xFFFF),
+              l2 = static_cast<int>((w >> 32) & 0xFFFF);
+    const double2 p0 = Xl[l0], p1 = Xl[l1], p2 = Xl[l2];
+    const double ax = p1.x - p0.x, ay = p1.y - p0.y;
+    const double bx = p2.x - p0.x, by = p2.y - p0.y;
+    const double cx = p2.x - p1.x, cy = p2.y - p1.y;
+    const double La = ax * ax + ay * ay, Lb = bx * bx + by * by, Lc = cx * cx + cy * cy;
+    const uint64_t ko = okey(finish_q(ax * by - bx * ay, (La + Lc) + Lb));
+    if (l0 < T) {
+        atomicMin(reinterpret_cast<unsigned long long*>(qo + l0), static_cast<unsigned long long>(ko));
+        const double2 c = cand[l0];
+        const double ax2 = p1.x - c.x, ay2 = p1.y - c.y, bx2 = p2.x - c.x, by2 = p2.y - c.y;
+        const double q = finish_q(ax2 * by2 - bx2 * ay2, ((ax2 * ax2 + ay2 * ay2) + Lc) + (bx2 * bx2 + by2 * by2));
+        atomicMin(reinterpret_cast<unsigned long long*>(qn + l0), static_cast<unsigned long long>(okey(q)));
+    }
+    if (l1 < T) {
+        atomicMin(reinterpret_cast<unsigned long long*>(qo + l1), static_cast<unsigned long long>(ko));
+        const double2 c = cand[l1];
+        const double ax2 = c.x - p0.x, ay2 = c.y - p0.y, cx2 = p2.x - c.x, cy2 = p2.y - c.y;
+        const double q = finish_q(ax2 * by - bx * ay2, ((ax2 * ax2 + ay2 * ay2) + (cx2 * cx2 + cy2 * cy2)) + Lb);
+        atomicMin(reinterpret_cast<unsigned long long*>(qn + l1), static_cast<unsigned long long>(okey(q)));
+    }
+    if (l2 < T) {
+        atomicMin(reinterpret_cast<unsigned long long*>(qo + l2), static_cast<unsigned long long>(ko));
+        const double2 c = cand[l2];
+        const double bx2 = c.x - p0.x, by2 = c.y - p0.y, cx2 = c.x - p1.x, cy2 = c.y - p1.y;
+        const double q = finish_q(ax * by2 - bx2 * ay, (La + (cx2 * cx2 + cy2 * cy2)) + (bx2 * bx2 + by2 * by2));
+        atomicMin(reinterpret_cast<unsigned long long*>(qn + l2), static_cast<unsigned long long>(okey(q)));
+    }
+}
+
+template <int T, int BS, bool SOA, bool GT>
+__global__ __launch_bounds__(BS) void k_sweep_tile(TileSweepArgs a)
+{
+    constexpr int NPT = T / BS;   // own nodes per work-item
+    constexpr int KPRE = 6;       // triangle entries per work-item loaded with the positions
+    constexpr int HPRE = 1;       // halo nodes per work-item loaded through registers
+    constexpr int RPRE = 4;       // 64-bit row words per work-item loaded through registers
+    if (a.prev_maxd != nullptr && __longlong_as_double(static_cast<long long>(*a.prev_maxd)) < a.tol2) return;
+    // XCD-contiguous tile order: work-groups go to the 8 XCDs round-robin
+    const int tile = static_cast<int>(blockIdx.x % 8) * a.tiles_per_xcd + static_cast<int>(blockIdx.x / 8);
+    if (tile >= a.n_tiles) return;
+
+    extern __shared__ double2 lds[];
+    double2* Xl = lds;                                      // [T + halo_cap]
+    double2* cand = lds + T + a.halo_cap;                   // [T]
+    uint64_t* qo = reinterpret_cast<uint64_t*>(cand + T);   // [T]
+    uint64_t* qn = qo + T;                                  // [T]
+    uint16_t* rows = reinterpret_cast<uint16_t*>(qn + T);   // [rows_cap]
+    __shared__ double s_d2[BS / 64];
+    __shared__ unsigned long long s_acc[BS / 64];
+
+    const int tid = threadIdx.x;
+    const int4 mt = a.meta[tile];
+    const int2 rs = a.rows[tile];
+    const int32_t k0 = tile * T;
+    const int nown = min(T, a.n_free - k0);
+
+    // 1. every global read of the sweep is issued first, into registers:
+    //    own positions, halo ids then halo positions, the row segment, row
+    //    offsets, the first triangle entries; then they are written to LDS.
+    const uint16_t* rr = a.row_rel + static_cast<int64_t>(tile) * (T + 1);
+    const int32_t* hl = a.halo + mt.x;
+    const uint64_t* seg = reinterpret_cast<const uint64_t*>(a.nbr_loc + rs.x);
+    uint64_t* rows64 = reinterpret_cast<uint64_t*>(rows);
+    const uint64_t* tl = a.tri_loc + mt.z;
+    const int nrow64 = rs.y >> 2;
+    int hidx[HPRE];
+#pragma unroll
+    for (int q = 0; q < HPRE; ++q) {
+        const int h = q * BS + tid;
+        hidx[q] = h < mt.y ? hl[h] : -1;
+    }
+    double2 own[NPT];
+    int r0[NPT], r1[NPT];
+#pragma unroll
+    for (int m = 0; m < NPT; ++m) {
+        const int i = m * BS + tid;
+        r0[m] = rr[i];
+        r1[m] = rr[i + 1];
+        own[m] = i < nown ? ldx<SOA>(a.Xin, a.n, k0 + i) : make_double2(0.0, 0.0);
+    }
+    uint64_t rw[RPRE];
+#pragma unroll
+    for (int q = 0; q < RPRE; ++q) {
+        const int j = q * BS + tid;
+        rw[q] = j < nrow64 ? seg[j] : 0ull;
+    }
+    uint64_t tw[KPRE];
+#pragma unroll
+    for (int q = 0; q < KPRE; ++q) {
+        const int r = q * BS + tid;
+        tw[q] = r < mt.w ? tl[r] : 0ull;
+    }
+    double2 hx[HPRE];
+#pragma unroll
+    for (int q = 0; q < HPRE; ++q) hx[q] = hidx[q] >= 0 ? ldx<SOA>(a.Xin, a.n, hidx[q]) : make_double2(0.0, 0.0);
+#pragma unroll
+    for (int m = 0; m < NPT; ++m)
+        if (m * BS + tid < nown) Xl[m * BS + tid] = own[m];
+#pragma unroll
+    for (int q = 0; q < RPRE; ++q)
+        if (q * BS + tid < nrow64) rows64[q * BS + tid] = rw[q];
+#pragma unroll
+    for (int q = 0; q < HPRE; ++q)
+        if (hidx[q] >= 0) Xl[T + q * BS + tid] = hx[q];
+    for (int h = HPRE * BS + tid; h < mt.y; h += BS) Xl[T + h] = ldx<SOA>(a.Xin, a.n, hl[h]);
+    for (int j = RPRE * BS + tid; j < nrow64; j += BS) rows64[j] = seg[j];
+    __syncthreads();
+
+    // 2. candidates: row-order sum of the neighbours, one division by the count
+    constexpr uint64_t kKeyInf = 0xFFF0000000000000ull;     // okey(+inf)
+#pragma unroll
+    for (int m = 0; m < NPT; ++m) {
+        const int i = m * BS + tid;
+        if (i < nown) {
+            double sx = 0.0, sy = 0.0;
+            for (int j = r0[m]; j < r1[m]; ++j) {
+                const double2 p = Xl[rows[j]];
+                sx += p.x;
+                sy += p.y;
+            }
+            const double dn = static_cast<double>(r1[m] - r0[m]);
+            cand[i] = make_double2(sx / dn, sy / dn);
+            qo[i] = kKeyInf;
+            qn[i] = kKeyInf;
+        }
+    }
+    __syncthreads();
+
+    // 3. triangles
+#pragma unroll
+    for (int q = 0; q < KPRE; ++q)
+        if (q * BS + tid < mt.w) tile_triangle<T>(tw[q], Xl, cand, qo, qn);
+    for (int r = KPRE * BS + tid; r < mt.w; r += BS) tile_triangle<T>(tl[r], Xl, cand, qo, qn);
+    __syncthreads();
+
+    // 4. accept, write, reduce
+    const int lane = tid & 63, wv = tid >> 6;
+    double d2max = 0.0;
+    unsigned long long nacc = 0;
+#pragma unroll
+    for (int m = 0; m < NPT; ++m) {
+        const int i = m * BS + tid;
+        bool accepted = false;
+        if (i < nown) {
+            const double vo = okey_inv(qo[i]), vn = okey_inv(qn[i]);
+            accepted = GT ? (vn > vo) : (vn >= vo);
+            const double2 o = Xl[i];
+            const double2 c = cand[i];
+            const double nx = accepted ? c.x : o.x, ny = accepted ? c.y : o.y;
+            if (SOA) {
+                a.Xout[k0 + i] = nx;
+                a.Xout[a.n + k0 + i] = ny;
+            } else {
+                reinterpret_cast<double2*>(a.Xout)[k0 + i] = make_double2(nx, ny);
+            }
+            const double dx = nx - o.x, dy = ny - o.y;
+            const double d2 = dx * dx + dy * dy;
+            d2max = d2 > d2max ? d2 : d2max;
+        }
+        const unsigned long long ball = __ballot(accepted);
+        nacc += __popcll(ball);
+        if (a.bits != nullptr && lane == 0 && ball != 0ull)
+            atomicOr(reinterpret_cast<unsigned long long*>(a.bits) + ((k0 + m * BS + wv * 64) >> 6), ball);
+    }
+    for (int off = 32; off > 0; off >>= 1) {
+        const double t = __shfl_xor(d2max, off);
+        d2max = t > d2max ? t : d2max;
+    }
+    if (lane == 0) {
+        s_d2[wv] = d2max;
+        s_acc[wv] = nacc;
+    }
+    __syncthreads();
+    if (tid == 0) {
+        double mx = s_d2[0];
+        unsigned long long c = s_acc[0];
+        for (int q = 1; q < BS / 64; ++q) {
+            mx = s_d2[q] > mx ? s_d2[q] : mx;
+            c += s_acc[q];
+        }
+        if (mx > 0.0)
+            atomicMax(reinterpret_cast<unsigned long long*>(a.maxd), static_cast<unsigned long long>(__double_as_longlong(mx)));
+        if (c) atomicAdd(a.acc, c);
+    }
+}
+
+constexpr int kTileT = 512;
+constexpr int kTileBS = 256;
+constexpr int kLdsLimit = 160 * 1024 - 4096;
+
+template <int T, int BS, bool SOA, bool GT>
+void launch_tile_variant(const TileSweepArgs& a, int grid, size_t lds, hipStream_t st)
+{
+    if (lds > 64 * 1024) {
+        (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_sweep_tile<T, BS, SOA, GT>),
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds));
+        (void)hipGetLastError();
+    }
+    k_sweep_tile<T, BS, SOA, GT><<<grid, BS, lds, st>>>(a);
+}
+
+}  // namespace
+
+size_t tile_lds_bytes(int tile_nodes, int halo_cap, int rows_cap)
+{
+    return static_cast<size_t>(tile_nodes + halo_cap) * 16 + static_cast<size_t>(tile_nodes) * 32 +
+           static_cast<size_t>(rows_cap) * 2;
+}
+
+sl_status build_tiles(const SetupArgs& a, DevMesh& m, int tile_nodes, hipStream_t st)
+{
+    m.tile_nodes = 0;
+    if (tile_nodes != kTileT || m.n_free == 0 || m.max_deg > kTileMaxDeg || m.max_inc > kTileMaxDeg) return SL_OK;
+    const int T = tile_nodes;
+    const int nt = div_up(m.n_free, T);
+    sl_status r = SL_OK;
+    int4* counts = nullptr;
+    int32_t *hc = nullptr, *rc = nullptr, *lc = nullptr, *hoff = nullptr, *toff = nullptr, *roff = nullptr;
+    int32_t *err = nullptr, *mx = nullptr;
+    auto cleanup = [&] {
+        dfree(counts, st); dfree(hc, st); dfree(rc, st); dfree(lc, st); dfree(hoff, st); dfree(toff, st);
+        dfree(roff, st); dfree(err, st); dfree(mx, st);
+    };
+    const size_t n1 = static_cast<size_t>(nt) + 1;
+    if ((r = dalloc(&counts, nt, st)) || (r = dalloc(&hc, nt, st)) || (r = dalloc(&rc, nt, st)) ||
+        (r = dalloc(&lc, nt, st)) || (r = dalloc(&hoff, n1, st)) || (r = dalloc(&toff, n1, st)) ||
+        (r = dalloc(&roff, n1, st)) || (r = dalloc(&err, 1, st)) || (r = dalloc(&mx, 2, st))) {
+        cleanup();
+        return r;
+    }
+    SL_HIP(hipMemsetAsync(err, 0, sizeof(int32_t), st));
+    SL_HIP(hipMemsetAsync(mx, 0, 2 * sizeof(int32_t), st));
+    TileBuildArgs b{};
+    b.perm = m.perm;
+    b.new_of_old = m.new_of_old;
+    b.nbr_ptr = a.nbr_ptr;
+    b.nbr_idx = a.nbr_idx;
+    b.tri_ptr = a.tri_ptr;
+    b.tri_idx = a.tri_idx;
+    b.tris = a.tris;
+    b.row_ptr = m.row_ptr;
+    b.n_free = m.n_free;
+    b.counts = counts;
+    b.err = err;
+    k_tile_build<kTileT><<<nt, kBuildBS, 0, st>>>(b, 0);
+    k_split_counts<<<div_up(nt, 256), 256, 0, st>>>(counts, nt, hc, rc, lc);
+    if ((r = scan_exclusive(hc, hoff, nt, st)) || (r = scan_exclusive(rc, toff, nt, st)) ||
+        (r = scan_exclusive(lc, roff, nt, st))) {
+        cleanup();
+        return r;
+    }
+    int32_t tot[3] = {0, 0, 0};
+    SL_HIP(hipMemcpyAsync(&tot[0], hoff + nt, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+    SL_HIP(hipMemcpyAsync(&tot[1], toff + nt, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+    SL_HIP(hipMemcpyAsync(&tot[2], roff + nt, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+    SL_HIP(hipStreamSynchronize(st));
+    if ((r = dalloc(&m.tile_meta, nt, st)) || (r = dalloc(&m.tile_rows, nt, st)) ||
+        (r = dalloc(&m.halo, tot[0], st)) || (r = dalloc(&m.nbr_loc, tot[2], st)) ||
+        (r = dalloc(&m.row_rel, static_cast<size_t>(nt) * (T + 1), st)) || (r = dalloc(&m.tri_loc, tot[1], st))) {
+        cleanup();
+        return r;
+    }
+    b.halo_off = hoff;
+    b.tri_off = toff;
+    b.row_off = roff;
+    b.halo = m.halo;
+    b.nbr_loc = m.nbr_loc;
+    b.row_rel = m.row_rel;
+    b.tri_loc = m.tri_loc;
+    k_tile_build<kTileT><<<nt, kBuildBS, 0, st>>>(b, 1);
+    k_tile_meta<<<div_up(nt, 256), 256, 0, st>>>(counts, hoff, toff, roff, nt, m.tile_meta, m.tile_rows, mx);
+    int32_t h[3] = {0, 0, 0};
+    SL_HIP(hipMemcpyAsync(&h[0], err, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+    SL_HIP(hipMemcpyAsync(&h[1], mx, 2 * sizeof(int32_t), hipMemcpyDeviceToHost, st));
+    SL_HIP(hipStreamSynchronize(st));
+    cleanup();
+    if (h[0]) return fail(SL_ETOPO, "triangle vertex outside its tile's neighbourhood");
+    if (tile_lds_bytes(T, h[1], h[2]) > static_cast<size_t>(kLdsLimit)) return SL_OK;   // node path
+    m.halo_max = h[1];
+    m.rows_max = h[2];
+    m.n_tiles = nt;
+    m.tile_nodes = T;
+    return SL_OK;
+}
+
+sl_status launch_sweep_tiles(const DevMesh& m, int32_t s, int32_t accept, double tol2, const SweepOut& out,
+                             hipStream_t st)
+{
+    TileSweepArgs a{};
+    a.Xin = m.X[s & 1];
+    a.Xout = m.X[(s + 1) & 1];
+    a.n = m.n;
+    a.meta = m.tile_meta;
+    a.rows = m.tile_rows;
+    a.row_rel = m.row_rel;
+    a.nbr_loc = m.nbr_loc;
+    a.halo = m.halo;
+    a.tri_loc = m.tri_loc;
+    a.n_free = m.n_free;
+    a.n_tiles = m.n_tiles;
+    a.tiles_per_xcd = div_up(m.n_tiles, 8);
+    a.halo_cap = m.halo_max;
+    a.rows_cap = m.rows_max;
+    a.prev_maxd = (s > 0 && tol2 > 0.0) ? out.maxd + (s - 1) : nullptr;
+    a.tol2 = tol2;
+    a.maxd = out.maxd + s;
+    a.acc = out.acc + s;
+    a.bits = out.bits ? out.bits + static_cast<int64_t>(s) * out.words : nullptr;
+    const int grid = 8 * a.tiles_per_xcd;
+    const size_t lds = tile_lds_bytes(m.tile_nodes, m.halo_max, m.rows_max);
+    const bool soa = m.layout == SL_SOA, gt = accept == SL_ACCEPT_GT;
+    if (soa) {
+        if (gt) launch_tile_variant<kTileT, kTileBS, true, true>(a, grid, lds, st);
+        else launch_tile_variant<kTileT, kTileBS, true, false>(a, grid, lds, st);
+    } else {
+        if (gt) launch_tile_variant<kTileT, kTileBS, false, true>(a, grid, lds, st);
+        else launch_tile_variant<kTileT, kTileBS, false, false>(a, grid, lds, st);
+    }
+    SL_HIP(hipGetLastError());
+    return SL_OK;
+}
+
+}  // namespace sl

@@ -76,11 +76,12 @@ def test_config_small_grid_64():
 
 @pytest.mark.parametrize("layout", ["aos", "soa"])
 @pytest.mark.parametrize("reorder", ["none", "hilbert"])
-@pytest.mark.parametrize("block", [0, 64, 128])
-def test_variants_are_bit_identical(layout, reorder, block):
+@pytest.mark.parametrize("kernel,block", [("tile", 0), ("node", 0), ("node", 64), ("node", 128)])
+def test_variants_are_bit_identical(layout, reorder, kernel, block):
     m = meshgen.make_grid(47, "random", 0.4, 5)       # 2025 free nodes: several tiles and a ragged tail
-    X, rep, ref, ndiff = assert_parity(m, 8, layout=layout, reorder=reorder, block_size=block)
+    X, rep, ref, ndiff = assert_parity(m, 8, layout=layout, reorder=reorder, block_size=block, kernel=kernel)
     assert ndiff == 0
+    assert rep.kernel_used == sl.KERNELS[kernel]
 
 
 def test_strict_accept_rule():
@@ -109,14 +110,14 @@ def test_config_1024_permuted_full():
     m = meshgen.permute_mesh(meshgen.make_grid(1024, "random", 0.4, 2), 2)
     ref = oracle.smooth(m, 100, threads=oracle.max_threads())
     rf = ref.flags == 1
-    for layout in ("aos", "soa"):
-        for reorder in ("hilbert", "none"):
-            note("1024^2 permuted, 100 sweeps, %s %s" % (layout, reorder))
-            X, rep, F = run_gpu(m, 100, layout=layout, reorder=reorder)
-            assert rep.iterations_run == 100
-            assert (F == rf).all()
-            assert float(np.abs(X - ref.coords).max()) <= COORD_TOL
-            assert (X == ref.coords).all()
+    for layout, reorder, kernel in (("aos", "hilbert", "tile"), ("soa", "hilbert", "tile"),
+                                    ("aos", "none", "tile"), ("aos", "hilbert", "node"), ("soa", "none", "node")):
+        note("1024^2 permuted, 100 sweeps, %s %s %s" % (layout, reorder, kernel))
+        X, rep, F = run_gpu(m, 100, layout=layout, reorder=reorder, kernel=kernel)
+        assert rep.iterations_run == 100
+        assert (F == rf).all()
+        assert float(np.abs(X - ref.coords).max()) <= COORD_TOL
+        assert (X == ref.coords).all()
 
 
 @pytest.mark.parametrize("kind", ["grid", "annulus"])
@@ -126,6 +127,7 @@ def test_config_4096_sampled(kind):
     m = meshgen.make_grid(4096, "random", 0.4, 3) if kind == "grid" else meshgen.make_annulus(4096, 4096, seed=4)
     note("4096^2 %s generated" % kind)
     X, rep, F = run_gpu(m, 10)
+    assert rep.kernel_used == sl.KERNELS["tile"]
     ref = oracle.smooth(m, 10, threads=oracle.max_threads())
     assert rep.iterations_run == 10
     assert rep.accepted_total == int(ref.accepted.sum())
@@ -163,7 +165,17 @@ def _ring_star(k, seed):
 
 @pytest.mark.parametrize("k", [3, 8, 9, 16, 17, 32, 33, 100, 127])
 def test_valence_classes(k):
-    assert_parity(_ring_star(k, k), 3)
+    X, rep, ref, _ = assert_parity(_ring_star(k, k), 3)
+    assert rep.kernel_used == (sl.KERNELS["tile"] if k <= 16 else sl.KERNELS["node"])
+    assert_parity(_ring_star(k, k), 3, kernel="node")
+
+
+def test_tile_path_at_every_tile_boundary():
+    """Free-node counts around multiples of the tile size, both kernels."""
+    for n in (24, 25, 26, 34, 35, 47, 48, 49):
+        m = meshgen.make_grid(n, "random", 0.4, 200 + n)
+        X, rep, ref, nd = assert_parity(m, 4)
+        assert nd == 0 and rep.kernel_used == sl.KERNELS["tile"]
 
 
 def test_valence_limit_rejected():
