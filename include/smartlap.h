@@ -146,6 +146,97 @@ SL_API sl_status smooth_mesh_device(double* coords, int32_t n_nodes, const int32
                              const uint8_t* boundary, int32_t iterations, double tol, const sl_options* opts,
                              sl_report* report, void* stream);
 
+/* One mesh of a batch or a served request: host arrays as for smooth_mesh.
+ * coords is in/out (written on SL_OK only). */
+typedef struct {
+    double* coords;
+    int32_t n_nodes;
+    int32_t n_tris;
+    const int32_t* nbr_ptr;
+    const int32_t* nbr_idx;
+    const int32_t* tri_ptr;
+    const int32_t* tri_idx;
+    const int32_t* tris;
+    const uint8_t* boundary;
+} sl_mesh_desc;
+
+typedef struct {
+    double setup_ms;            /* device time of uploads and per-mesh setup */
+    double sweep_ms;            /* device time of the batched sweep loop */
+    double total_ms;            /* host wall time of the whole call */
+    int64_t node_updates;       /* sum over meshes of free nodes x sweeps run */
+    int64_t tiles;              /* tiles in the batched work list */
+    int32_t meshes_on_tile_path;
+    int32_t graph_used;         /* 1 if the sweep loop ran as a captured HIP graph */
+} sl_batch_report;
+
+/*
+ * sl_batch_smooth -- the same smoothing as smooth_mesh, applied to n_meshes
+ * independent meshes at once (host arrays).  All meshes are resident on the
+ * device together; each sweep is one launch over the tiles of every mesh,
+ * and the sweep loop runs as a captured HIP graph.  Every mesh gets exactly
+ * the result a separate smooth_mesh call with the same options would give.
+ * iterations and tol apply to every mesh (each stops on its own).
+ * reports: nullable, n_meshes entries.  batch: nullable.
+ * On an error in mesh i the message names i and no coords are written.
+ */
+SL_API sl_status sl_batch_smooth(const sl_mesh_desc* meshes, int32_t n_meshes, int32_t iterations, double tol,
+                                 const sl_options* opts, sl_report* reports, sl_batch_report* batch);
+
+/* ---- serving ----------------------------------------------------------
+ * A server takes smoothing requests as they arrive and sweeps the admitted
+ * ones together (continuous batching): a request is admitted when a slot is
+ * free and its estimated device footprint fits the HBM budget, joins the
+ * next scheduling step after its setup, and leaves as soon as it reaches its
+ * sweep cap or tolerance.  Its result is exactly that of smooth_mesh with the
+ * same options.  One scheduler thread per server owns the device; the calls
+ * below are thread-safe.
+ * Ownership: the arrays a request's sl_mesh_desc points to are read by the
+ * scheduler thread and must stay valid and unchanged until sl_server_poll
+ * returns something other than SL_EBUSY for that request (or the server is
+ * destroyed); desc->coords is not written (results go to poll's coords_out). */
+typedef struct sl_server sl_server;
+
+typedef struct {
+    size_t hbm_budget_bytes;    /* admission limit on estimated footprints; 0 = 200 GiB */
+    int32_t max_active;         /* requests swept together at most; 0 = 256 */
+    int32_t sweeps_per_step;    /* sweeps between two scheduling decisions; 0 = 8 */
+} sl_server_config;
+
+typedef struct {
+    double submitted_s;         /* server clock (seconds since sl_server_create) */
+    double admitted_s;          /* slot and memory granted */
+    double started_s;           /* setup done, first step next */
+    double done_s;              /* result on the host (or failure recorded) */
+} sl_request_times;
+
+typedef struct {
+    int64_t submitted, completed, failed, steps;
+    int64_t node_updates;       /* free nodes x sweeps of completed requests */
+    int32_t queued, active;
+    size_t hbm_in_use;          /* sum of the admitted requests' estimated footprints */
+} sl_server_stats;
+
+SL_API void sl_server_config_default(sl_server_config* cfg);
+/* opts: as for smooth_mesh (flags_out ignored); nullable. */
+SL_API sl_status sl_server_create(const sl_server_config* cfg, const sl_options* opts, sl_server** out);
+/* Queues a request; deadline_s > 0: fail with SL_ETIMEOUT if not done within
+ * deadline_s seconds of submission.  *request_id identifies it. */
+SL_API sl_status sl_server_submit(sl_server* srv, const sl_mesh_desc* mesh, int32_t iterations, double tol,
+                                  double deadline_s, uint64_t* request_id);
+/* SL_EBUSY while the request is queued or running.  Otherwise returns its
+ * final status once (the id is then released): on SL_OK the positions are
+ * copied to coords_out (n_nodes x 2, nullable) and report/times are filled
+ * (nullable); SL_ECANCELED, SL_ETIMEOUT, SL_ENOMEM or a setup error otherwise
+ * (times still filled). */
+SL_API sl_status sl_server_poll(sl_server* srv, uint64_t request_id, double* coords_out, sl_report* report,
+                                sl_request_times* times);
+/* Asks for a request to stop; it ends with SL_ECANCELED at the next step. */
+SL_API sl_status sl_server_cancel(sl_server* srv, uint64_t request_id);
+SL_API sl_status sl_server_get_stats(sl_server* srv, sl_server_stats* stats);
+/* Stops the scheduler and frees everything; pending requests are dropped. */
+SL_API void sl_server_destroy(sl_server* srv);
+
 /* Message describing the last failure on the calling thread ("" if none). */
 SL_API const char* sl_last_error(void);
 

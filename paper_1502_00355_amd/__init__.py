@@ -50,6 +50,43 @@ class Report(ctypes.Structure):
         return {f: getattr(self, f) for f, _ in self._fields_}
 
 
+class MeshDesc(ctypes.Structure):
+    _fields_ = [("coords", ctypes.c_void_p), ("n_nodes", ctypes.c_int32), ("n_tris", ctypes.c_int32),
+                ("nbr_ptr", ctypes.c_void_p), ("nbr_idx", ctypes.c_void_p), ("tri_ptr", ctypes.c_void_p),
+                ("tri_idx", ctypes.c_void_p), ("tris", ctypes.c_void_p), ("boundary", ctypes.c_void_p)]
+
+
+class BatchReport(ctypes.Structure):
+    _fields_ = [("setup_ms", ctypes.c_double), ("sweep_ms", ctypes.c_double), ("total_ms", ctypes.c_double),
+                ("node_updates", ctypes.c_int64), ("tiles", ctypes.c_int64),
+                ("meshes_on_tile_path", ctypes.c_int32), ("graph_used", ctypes.c_int32)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+class ServerConfig(ctypes.Structure):
+    _fields_ = [("hbm_budget_bytes", ctypes.c_size_t), ("max_active", ctypes.c_int32),
+                ("sweeps_per_step", ctypes.c_int32)]
+
+
+class RequestTimes(ctypes.Structure):
+    _fields_ = [("submitted_s", ctypes.c_double), ("admitted_s", ctypes.c_double), ("started_s", ctypes.c_double),
+                ("done_s", ctypes.c_double)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+class ServerStats(ctypes.Structure):
+    _fields_ = [("submitted", ctypes.c_int64), ("completed", ctypes.c_int64), ("failed", ctypes.c_int64),
+                ("steps", ctypes.c_int64), ("node_updates", ctypes.c_int64), ("queued", ctypes.c_int32),
+                ("active", ctypes.c_int32), ("hbm_in_use", ctypes.c_size_t)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
 _lib = None
 
 
@@ -70,6 +107,23 @@ def lib():
         L.smooth_mesh.restype = ctypes.c_int
         L.smooth_mesh_device.argtypes = sig + [p]
         L.smooth_mesh_device.restype = ctypes.c_int
+        L.sl_batch_smooth.argtypes = [ctypes.POINTER(MeshDesc), i32, i32, d, ctypes.POINTER(Options),
+                                      ctypes.POINTER(Report), ctypes.POINTER(BatchReport)]
+        L.sl_batch_smooth.restype = ctypes.c_int
+        L.sl_server_config_default.argtypes = [ctypes.POINTER(ServerConfig)]
+        L.sl_server_config_default.restype = None
+        L.sl_server_create.argtypes = [ctypes.POINTER(ServerConfig), ctypes.POINTER(Options), ctypes.POINTER(p)]
+        L.sl_server_create.restype = ctypes.c_int
+        L.sl_server_submit.argtypes = [p, ctypes.POINTER(MeshDesc), i32, d, d, ctypes.POINTER(ctypes.c_uint64)]
+        L.sl_server_submit.restype = ctypes.c_int
+        L.sl_server_poll.argtypes = [p, ctypes.c_uint64, p, ctypes.POINTER(Report), ctypes.POINTER(RequestTimes)]
+        L.sl_server_poll.restype = ctypes.c_int
+        L.sl_server_cancel.argtypes = [p, ctypes.c_uint64]
+        L.sl_server_cancel.restype = ctypes.c_int
+        L.sl_server_get_stats.argtypes = [p, ctypes.POINTER(ServerStats)]
+        L.sl_server_get_stats.restype = ctypes.c_int
+        L.sl_server_destroy.argtypes = [p]
+        L.sl_server_destroy.restype = None
         _lib = L
     return _lib
 
@@ -138,6 +192,113 @@ def smooth_mesh_device(coords, nbr_ptr, nbr_idx, tri_ptr, tri_idx, tris, boundar
                                   ctypes.byref(rep), ctypes.c_void_p(stream.cuda_stream))
     _check(st)
     return rep
+
+
+def _desc(mesh):
+    """(MeshDesc, arrays kept alive) for a host mesh; coords copied (output)."""
+    X = _c(mesh.coords, np.float64).copy()
+    keep = [X] + [_c(getattr(mesh, f), np.int32) for f in ("nbr_ptr", "nbr_idx", "tri_ptr", "tri_idx")]
+    tr = _c(mesh.tris, np.int32).reshape(-1)
+    b = _c(mesh.boundary, np.uint8)
+    keep += [tr, b]
+    d = MeshDesc(X.ctypes.data, X.shape[0], tr.size // 3, keep[1].ctypes.data, keep[2].ctypes.data,
+                 keep[3].ctypes.data, keep[4].ctypes.data, tr.ctypes.data, b.ctypes.data)
+    return d, keep
+
+
+def batch_smooth(meshes, iterations: int, tol: float = 0.0, **opts):
+    """Smooths many meshes in one batched run.  Returns (list of result
+    coordinate arrays, list of Report, BatchReport)."""
+    descs, keeps = zip(*[_desc(m) for m in meshes])
+    arr = (MeshDesc * len(descs))(*descs)
+    reps = (Report * len(descs))()
+    br = BatchReport()
+    o = make_options(**opts)
+    st = lib().sl_batch_smooth(arr, len(descs), int(iterations), float(tol), ctypes.byref(o), reps, ctypes.byref(br))
+    _check(st)
+    return [k[0] for k in keeps], list(reps), br
+
+
+class RequestResult:
+    def __init__(self, status, coords, report, times, message=""):
+        self.status = status
+        self.coords = coords
+        self.report = report
+        self.times = times
+        self.message = message
+
+
+class Server:
+    """Continuous-batching smoothing server (sl_server_* in the C ABI).
+    The arrays of a submitted mesh are kept referenced here until its
+    result has been polled."""
+
+    def __init__(self, hbm_budget_bytes=0, max_active=0, sweeps_per_step=0, **opts):
+        cfg = ServerConfig()
+        lib().sl_server_config_default(ctypes.byref(cfg))
+        if hbm_budget_bytes:
+            cfg.hbm_budget_bytes = int(hbm_budget_bytes)
+        if max_active:
+            cfg.max_active = int(max_active)
+        if sweeps_per_step:
+            cfg.sweeps_per_step = int(sweeps_per_step)
+        self.config = cfg
+        o = make_options(**opts)
+        h = ctypes.c_void_p()
+        _check(lib().sl_server_create(ctypes.byref(cfg), ctypes.byref(o), ctypes.byref(h)))
+        self._h = h
+        self._keep = {}
+
+    def submit(self, mesh, iterations: int, tol: float = 0.0, deadline_s: float = 0.0) -> int:
+        d, keep = _desc(mesh)
+        rid = ctypes.c_uint64()
+        _check(lib().sl_server_submit(self._h, ctypes.byref(d), int(iterations), float(tol), float(deadline_s),
+                                      ctypes.byref(rid)))
+        self._keep[rid.value] = (d, keep)
+        return rid.value
+
+    def poll(self, rid: int):
+        """None while the request runs, else a RequestResult."""
+        d, keep = self._keep[rid]
+        out = np.empty((d.n_nodes, 2), np.float64)
+        rep, tm = Report(), RequestTimes()
+        st = lib().sl_server_poll(self._h, rid, out.ctypes.data, ctypes.byref(rep), ctypes.byref(tm))
+        if st == SL_EBUSY:
+            return None
+        del self._keep[rid]
+        msg = lib().sl_last_error().decode() if st != SL_OK else ""
+        return RequestResult(st, out if st == SL_OK else None, rep, tm, msg)
+
+    def wait(self, rid: int, timeout: float = 600.0, interval: float = 0.0005):
+        import time
+        t0 = time.time()
+        while True:
+            r = self.poll(rid)
+            if r is not None:
+                return r
+            if time.time() - t0 > timeout:
+                raise TimeoutError("request %d not done after %g s" % (rid, timeout))
+            time.sleep(interval)
+
+    def cancel(self, rid: int):
+        _check(lib().sl_server_cancel(self._h, rid))
+
+    def stats(self) -> ServerStats:
+        s = ServerStats()
+        _check(lib().sl_server_get_stats(self._h, ctypes.byref(s)))
+        return s
+
+    def close(self):
+        if self._h:
+            lib().sl_server_destroy(self._h)
+            self._h = None
+            self._keep.clear()
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
 
 
 def to_device(mesh, device="cuda"):

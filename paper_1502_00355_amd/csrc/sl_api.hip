@@ -13,6 +13,7 @@ namespace sl {
 namespace {
 thread_local std::string g_last_error;
 std::once_flag g_pool_once[64];
+}  // namespace
 
 // Freed device memory stays in the stream-ordered pool for the next call.
 void keep_pool_warm()
@@ -28,26 +29,6 @@ void keep_pool_warm()
     });
 }
 
-// Everything a call allocates, released on every exit path.
-struct CallState {
-    hipStream_t st = nullptr;
-    DevMesh m;
-    uint64_t* maxd = nullptr;
-    unsigned long long* acc = nullptr;
-    uint64_t* bits = nullptr;
-    hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
-    ~CallState()
-    {
-        devmesh_free(m, st);
-        dfree(maxd, st);
-        dfree(acc, st);
-        dfree(bits, st);
-        (void)hipStreamSynchronize(st);
-        for (auto& e : ev)
-            if (e) (void)hipEventDestroy(e);
-    }
-};
-
 sl_status check_options(const sl_options& o)
 {
     if (o.form != SL_JACOBI && o.form != SL_INPLACE_COLORED) return fail(SL_EINVAL, "unknown form");
@@ -61,6 +42,48 @@ sl_status check_options(const sl_options& o)
     return SL_OK;
 }
 
+sl_status prepare_mesh(const MeshInput& in, const sl_options& o, int32_t mesh_index, DevMesh& m, hipStream_t st)
+{
+    if (!in.coords || !in.nbr_ptr || !in.tri_ptr || !in.boundary) return fail(SL_EINVAL, "null array argument");
+    if (in.n <= 0) return fail(SL_EINVAL, "n_nodes must be >= 1");
+    if (in.n_tris < 0) return fail(SL_EINVAL, "n_tris must be >= 0");
+    if (in.n_tris > 0 && !in.tris) return fail(SL_EINVAL, "null tris with n_tris > 0");
+    if (in.n_tris > (INT32_MAX / 3)) return fail(SL_EINVAL, "n_tris too large");
+    int32_t ends[4] = {0, 0, 0, 0};
+    SL_HIP(hipMemcpyAsync(&ends[0], in.nbr_ptr, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+    SL_HIP(hipMemcpyAsync(&ends[1], in.nbr_ptr + in.n, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+    SL_HIP(hipMemcpyAsync(&ends[2], in.tri_ptr, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+    SL_HIP(hipMemcpyAsync(&ends[3], in.tri_ptr + in.n, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+    SL_HIP(hipStreamSynchronize(st));
+    if (ends[0] != 0 || ends[2] != 0) return fail(SL_EINVAL, "nbr_ptr[0] and tri_ptr[0] must be 0");
+    if (ends[1] < 0 || ends[3] < 0) return fail(SL_EINVAL, "negative CSR length");
+    if (ends[1] > 0 && !in.nbr_idx) return fail(SL_EINVAL, "null nbr_idx with nbr_ptr[n] > 0");
+    if (ends[3] > 0 && !in.tri_idx) return fail(SL_EINVAL, "null tri_idx with tri_ptr[n] > 0");
+    SetupArgs sa{in.coords, in.n, in.nbr_ptr, in.nbr_idx, in.tri_ptr, in.tri_idx, in.tris, in.n_tris, in.boundary,
+                 ends[1], ends[3]};
+    return setup_mesh(sa, o, m, mesh_index, st);
+}
+
+namespace {
+
+// Everything a call allocates, released on every exit path.
+struct CallState {
+    hipStream_t st = nullptr;
+    DevMesh m;
+    MeshState* state = nullptr;
+    uint64_t* bits = nullptr;
+    hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
+    ~CallState()
+    {
+        devmesh_free(m, st);
+        dfree(state, st);
+        dfree(bits, st);
+        (void)hipStreamSynchronize(st);
+        for (auto& e : ev)
+            if (e) (void)hipEventDestroy(e);
+    }
+};
+
 sl_status run_device(double* coords, int32_t n, const int32_t* nbr_ptr, const int32_t* nbr_idx,
                      const int32_t* tri_ptr, const int32_t* tri_idx, const int32_t* tris, int32_t n_tris,
                      const uint8_t* boundary, int32_t iterations, double tol, const sl_options* opts,
@@ -72,84 +95,58 @@ sl_status run_device(double* coords, int32_t n, const int32_t* nbr_ptr, const in
     if (opts) o = *opts;
     sl_status r = check_options(o);
     if (r) return r;
-    if (!coords || !nbr_ptr || !tri_ptr || !boundary) return fail(SL_EINVAL, "null array argument");
-    if (n <= 0) return fail(SL_EINVAL, "n_nodes must be >= 1");
-    if (n_tris < 0) return fail(SL_EINVAL, "n_tris must be >= 0");
     if (iterations < 0) return fail(SL_EINVAL, "iterations must be >= 0");
-    if (n_tris > 0 && !tris) return fail(SL_EINVAL, "null tris with n_tris > 0");
-    if (n_tris > (INT32_MAX / 3)) return fail(SL_EINVAL, "n_tris too large");
     keep_pool_warm();
 
     CallState cs;
     cs.st = stream;
     for (auto& e : cs.ev) SL_HIP(hipEventCreate(&e));
     SL_HIP(hipEventRecord(cs.ev[0], stream));
-
-    int32_t ends[4] = {0, 0, 0, 0};
-    SL_HIP(hipMemcpyAsync(&ends[0], nbr_ptr, sizeof(int32_t), hipMemcpyDeviceToHost, stream));
-    SL_HIP(hipMemcpyAsync(&ends[1], nbr_ptr + n, sizeof(int32_t), hipMemcpyDeviceToHost, stream));
-    SL_HIP(hipMemcpyAsync(&ends[2], tri_ptr, sizeof(int32_t), hipMemcpyDeviceToHost, stream));
-    SL_HIP(hipMemcpyAsync(&ends[3], tri_ptr + n, sizeof(int32_t), hipMemcpyDeviceToHost, stream));
-    SL_HIP(hipStreamSynchronize(stream));
-    if (ends[0] != 0 || ends[2] != 0) return fail(SL_EINVAL, "nbr_ptr[0] and tri_ptr[0] must be 0");
-    if (ends[1] < 0 || ends[3] < 0) return fail(SL_EINVAL, "negative CSR length");
-    if (ends[1] > 0 && !nbr_idx) return fail(SL_EINVAL, "null nbr_idx with nbr_ptr[n] > 0");
-    if (ends[3] > 0 && !tri_idx) return fail(SL_EINVAL, "null tri_idx with tri_ptr[n] > 0");
-
-    SetupArgs sa{coords, n, nbr_ptr, nbr_idx, tri_ptr, tri_idx, tris, n_tris, boundary, ends[1], ends[3]};
-    if ((r = setup_mesh(sa, o, cs.m, stream))) return r;
+    MeshInput in{coords, n, nbr_ptr, nbr_idx, tri_ptr, tri_idx, tris, n_tris, boundary};
+    if ((r = prepare_mesh(in, o, 0, cs.m, stream))) return r;
     SL_HIP(hipEventRecord(cs.ev[1], stream));
 
     const int32_t its = iterations;
     const int64_t words = (static_cast<int64_t>(cs.m.n_free) + 63) / 64;
-    if ((r = dalloc(&cs.maxd, its, stream)) || (r = dalloc(&cs.acc, its, stream))) return r;
-    if (its > 0) {
-        SL_HIP(hipMemsetAsync(cs.maxd, 0, sizeof(uint64_t) * its, stream));
-        SL_HIP(hipMemsetAsync(cs.acc, 0, sizeof(unsigned long long) * its, stream));
-    }
-    SweepOut out{cs.maxd, cs.acc, nullptr, words};
+    const double tol2 = tol > 0.0 ? tol * tol : 0.0;
+    MeshState h0{};
+    h0.iters = its;
+    h0.active = its > 0;
+    h0.tol2 = tol2;
+    if ((r = dalloc(&cs.state, 1, stream))) return r;
+    SL_HIP(hipMemcpyAsync(cs.state, &h0, sizeof(MeshState), hipMemcpyHostToDevice, stream));
     if (o.flags_out && its > 0) {
         if ((r = dalloc(&cs.bits, static_cast<size_t>(words) * its, stream))) return r;
         SL_HIP(hipMemsetAsync(cs.bits, 0, sizeof(uint64_t) * words * its, stream));
-        out.bits = cs.bits;
     }
-    const double tol2 = tol > 0.0 ? tol * tol : 0.0;
+    TileLaunch L{cs.m.work, cs.m.n_tiles, cs.m.tile_nodes, cs.m.halo_max, cs.m.rows_max, o.layout, o.accept, cs.state};
 
     SL_HIP(hipEventRecord(cs.ev[2], stream));
-    for (int32_t s = 0; s < its; ++s)
-        if ((r = launch_sweep(cs.m, s, o.form, o.accept, o.block_size, tol2, out, stream))) return r;
+    for (int32_t s = 0; s < its; ++s) {
+        uint64_t* bits = cs.bits ? cs.bits + static_cast<int64_t>(s) * words : nullptr;
+        if (o.form == SL_JACOBI && cs.m.tile_nodes > 0) r = launch_sweep_tiles(L, s & 1, bits, stream);
+        else r = launch_sweep_nodes(cs.m, s & 1, o.form, o.accept, o.block_size, cs.state, bits, stream);
+        if (r || (r = launch_advance(cs.state, 1, stream))) return r;
+    }
     SL_HIP(hipEventRecord(cs.ev[3], stream));
 
-    std::vector<uint64_t> hmaxd(static_cast<size_t>(its));
-    std::vector<unsigned long long> hacc(static_cast<size_t>(its));
-    if (its > 0) {
-        SL_HIP(hipMemcpyAsync(hmaxd.data(), cs.maxd, sizeof(uint64_t) * its, hipMemcpyDeviceToHost, stream));
-        SL_HIP(hipMemcpyAsync(hacc.data(), cs.acc, sizeof(unsigned long long) * its, hipMemcpyDeviceToHost, stream));
-    }
+    MeshState hs{};
+    SL_HIP(hipMemcpyAsync(&hs, cs.state, sizeof(MeshState), hipMemcpyDeviceToHost, stream));
     SL_HIP(hipStreamSynchronize(stream));
-    // sweeps run: up to and including the first whose displacement is below tol
-    int32_t runs = its;
-    for (int32_t s = 0; s < its && tol2 > 0.0; ++s) {
-        double d;
-        std::memcpy(&d, &hmaxd[s], sizeof(d));
-        if (d < tol2) { runs = s + 1; break; }
-    }
+    const int32_t runs = hs.s;
     const int src = (o.form == SL_JACOBI) ? (runs & 1) : 0;
     if ((r = unpermute_coords(cs.m, src, coords, stream))) return r;
     if (o.flags_out && its > 0)
         if ((r = unpermute_flags(cs.m, cs.bits, its, runs, o.flags_out, stream))) return r;
-    if (o.flags_out && its > 0 && !cs.bits) return fail(SL_EDEVICE, "flag buffer missing");
     SL_HIP(hipStreamSynchronize(stream));
 
     if (report) {
         sl_report rep{};
         rep.iterations_run = runs;
         rep.n_colors = cs.m.n_colors;
-        if (runs > 0) {
-            std::memcpy(&rep.max_disp_sq_last, &hmaxd[runs - 1], sizeof(double));
-            rep.accepted_last = static_cast<int64_t>(hacc[runs - 1]);
-        }
-        for (int32_t s = 0; s < runs; ++s) rep.accepted_total += static_cast<int64_t>(hacc[s]);
+        std::memcpy(&rep.max_disp_sq_last, &hs.maxd_last, sizeof(double));
+        rep.accepted_last = static_cast<int64_t>(hs.acc_last);
+        rep.accepted_total = static_cast<int64_t>(hs.acc_total);
         float ms = 0.f;
         SL_HIP(hipEventElapsedTime(&ms, cs.ev[0], cs.ev[1]));
         rep.setup_ms = ms;

@@ -1,0 +1,239 @@
+// Batched Smart Laplacian: many meshes of uneven size swept together.
+//
+// Every mesh is set up on the device as for a single call (validation,
+// Hilbert order, tiles); the tile descriptors of all meshes form one work
+// list, so one launch of the tile kernel sweeps every mesh once, and the
+// whole sweep loop (tile launches plus the per-mesh state update) is
+// captured once in a HIP graph and replayed.  Meshes that do not fit the
+// tile path, and the coloured form, are swept mesh by mesh on the node path
+// inside the same graph.
+#include <algorithm>
+#include <chrono>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "sl_common.h"
+
+namespace sl {
+
+namespace {
+
+struct BatchState {
+    hipStream_t st = nullptr;
+    std::vector<DevMesh> meshes;
+    TileWork* work = nullptr;
+    MeshState* states = nullptr;
+    double* out = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
+    ~BatchState()
+    {
+        for (auto& m : meshes) devmesh_free(m, st);
+        dfree(work, st);
+        dfree(states, st);
+        dfree(out, st);
+        (void)hipStreamSynchronize(st);
+        if (exec) (void)hipGraphExecDestroy(exec);
+        if (graph) (void)hipGraphDestroy(graph);
+        for (auto& e : ev)
+            if (e) (void)hipEventDestroy(e);
+    }
+};
+
+// Uploads one caller mesh (host arrays) and prepares it; the uploaded
+// inputs are freed once the device copy is built.
+sl_status upload_and_prepare(const sl_mesh_desc& d, const sl_options& o, int32_t index, DevMesh& m, hipStream_t st)
+{
+    if (!d.coords || !d.nbr_ptr || !d.tri_ptr || !d.boundary) return fail(SL_EINVAL, "null array argument");
+    if (d.n_nodes <= 0) return fail(SL_EINVAL, "n_nodes must be >= 1");
+    if (d.n_tris < 0) return fail(SL_EINVAL, "n_tris must be >= 0");
+    if (d.n_tris > 0 && !d.tris) return fail(SL_EINVAL, "null tris with n_tris > 0");
+    const size_t n = static_cast<size_t>(d.n_nodes);
+    const int64_t nnz = d.nbr_ptr[n], ninc = d.tri_ptr[n];
+    if (d.nbr_ptr[0] != 0 || d.tri_ptr[0] != 0 || nnz < 0 || ninc < 0) return fail(SL_EINVAL, "bad CSR offsets");
+    if ((nnz > 0 && !d.nbr_idx) || (ninc > 0 && !d.tri_idx)) return fail(SL_EINVAL, "null CSR index array");
+    double* c = nullptr;
+    int32_t *np = nullptr, *ni = nullptr, *tp = nullptr, *ti = nullptr, *tr = nullptr;
+    uint8_t* b = nullptr;
+    auto cleanup = [&] {
+        dfree(c, st); dfree(np, st); dfree(ni, st); dfree(tp, st); dfree(ti, st); dfree(tr, st); dfree(b, st);
+    };
+    sl_status r;
+    if ((r = dalloc(&c, 2 * n, st)) || (r = dalloc(&np, n + 1, st)) || (r = dalloc(&ni, nnz, st)) ||
+        (r = dalloc(&tp, n + 1, st)) || (r = dalloc(&ti, ninc, st)) ||
+        (r = dalloc(&tr, 3 * static_cast<size_t>(d.n_tris), st)) || (r = dalloc(&b, n, st))) {
+        cleanup();
+        return r;
+    }
+    hipError_t e = hipSuccess;
+    auto cp = [&](void* dst, const void* src, size_t bytes) {
+        if (e == hipSuccess && bytes) e = hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, st);
+    };
+    cp(c, d.coords, 2 * n * sizeof(double));
+    cp(np, d.nbr_ptr, (n + 1) * sizeof(int32_t));
+    cp(ni, d.nbr_idx, static_cast<size_t>(nnz) * sizeof(int32_t));
+    cp(tp, d.tri_ptr, (n + 1) * sizeof(int32_t));
+    cp(ti, d.tri_idx, static_cast<size_t>(ninc) * sizeof(int32_t));
+    cp(tr, d.tris, 3 * static_cast<size_t>(d.n_tris) * sizeof(int32_t));
+    cp(b, d.boundary, n);
+    if (e != hipSuccess) {
+        cleanup();
+        return fail(SL_EDEVICE, std::string("host to device copy failed: ") + hipGetErrorString(e));
+    }
+    MeshInput in{c, d.n_nodes, np, ni, tp, ti, tr, d.n_tris, b};
+    r = prepare_mesh(in, o, index, m, st);
+    cleanup();
+    return r;
+}
+
+}  // namespace
+
+}  // namespace sl
+
+extern "C" {
+
+sl_status sl_batch_smooth(const sl_mesh_desc* meshes, int32_t n_meshes, int32_t iterations, double tol,
+                          const sl_options* opts, sl_report* reports, sl_batch_report* batch)
+{
+    using namespace sl;
+    const auto t0 = std::chrono::steady_clock::now();
+    set_error("");
+    if (!meshes || n_meshes <= 0) return fail(SL_EINVAL, "need at least one mesh");
+    if (iterations < 0) return fail(SL_EINVAL, "iterations must be >= 0");
+    sl_options o;
+    sl_options_default(&o);
+    if (opts) o = *opts;
+    o.flags_out = nullptr;
+    sl_status r = check_options(o);
+    if (r) return r;
+    keep_pool_warm();
+
+    BatchState bs;
+    SL_HIP(hipStreamCreateWithFlags(&bs.st, hipStreamNonBlocking));
+    hipStream_t st = bs.st;
+    for (auto& e : bs.ev) SL_HIP(hipEventCreate(&e));
+    SL_HIP(hipEventRecord(bs.ev[0], st));
+
+    // ---- setup, mesh by mesh
+    bs.meshes.resize(static_cast<size_t>(n_meshes));
+    int64_t total_tiles = 0;
+    int32_t T = 0, halo_cap = 0, rows_cap = 0, on_tiles = 0;
+    size_t max_nodes = 0;
+    for (int32_t i = 0; i < n_meshes; ++i) {
+        if ((r = upload_and_prepare(meshes[i], o, i, bs.meshes[i], st))) {
+            const std::string msg = "mesh " + std::to_string(i) + ": " + sl_last_error();
+            return fail(r, msg);
+        }
+        const DevMesh& m = bs.meshes[i];
+        max_nodes = std::max(max_nodes, static_cast<size_t>(m.n));
+        if (m.tile_nodes > 0) {
+            T = m.tile_nodes;
+            total_tiles += m.n_tiles;
+            halo_cap = std::max(halo_cap, m.halo_max);
+            rows_cap = std::max(rows_cap, m.rows_max);
+            ++on_tiles;
+        }
+    }
+    if (total_tiles > INT32_MAX) return fail(SL_EINVAL, "batch has more than 2^31 tiles");
+
+    // ---- one work list for all tile-path meshes
+    if ((r = dalloc(&bs.work, static_cast<size_t>(std::max<int64_t>(total_tiles, 1)), st))) return r;
+    int64_t off = 0;
+    for (auto& m : bs.meshes) {
+        if (m.tile_nodes == 0) continue;
+        SL_HIP(hipMemcpyAsync(bs.work + off, m.work, sizeof(TileWork) * m.n_tiles, hipMemcpyDeviceToDevice, st));
+        off += m.n_tiles;
+    }
+    std::vector<MeshState> h0(static_cast<size_t>(n_meshes));
+    const double tol2 = tol > 0.0 ? tol * tol : 0.0;
+    for (auto& s : h0) {
+        s = MeshState{};
+        s.iters = iterations;
+        s.active = iterations > 0;
+        s.tol2 = tol2;
+    }
+    if ((r = dalloc(&bs.states, static_cast<size_t>(n_meshes), st))) return r;
+    SL_HIP(hipMemcpyAsync(bs.states, h0.data(), sizeof(MeshState) * h0.size(), hipMemcpyHostToDevice, st));
+    SL_HIP(hipEventRecord(bs.ev[1], st));
+
+    // ---- the sweep loop, captured once and replayed
+    const TileLaunch L{bs.work, static_cast<int32_t>(total_tiles), T, halo_cap, rows_cap, o.layout, o.accept,
+                       bs.states};
+    const bool jacobi = o.form == SL_JACOBI;
+    const int32_t chunk = iterations <= 128 ? iterations + (iterations & 1) : 64;   // even: parity repeats
+    auto enqueue_chunk = [&]() -> sl_status {
+        for (int32_t s = 0; s < chunk; ++s) {
+            sl_status rr = SL_OK;
+            if (jacobi && total_tiles > 0) rr = launch_sweep_tiles(L, s & 1, nullptr, st);
+            for (int32_t i = 0; i < n_meshes && !rr; ++i) {
+                const DevMesh& m = bs.meshes[i];
+                if (jacobi && m.tile_nodes > 0) continue;
+                rr = launch_sweep_nodes(m, s & 1, o.form, o.accept, o.block_size, bs.states + i, nullptr, st);
+            }
+            if (rr || (rr = launch_advance(bs.states, n_meshes, st))) return rr;
+        }
+        return SL_OK;
+    };
+    int32_t graph_used = 0;
+    SL_HIP(hipEventRecord(bs.ev[2], st));
+    if (iterations > 0) {
+        SL_HIP(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+        sl_status cr = enqueue_chunk();
+        hipGraph_t g = nullptr;
+        const hipError_t ce = hipStreamEndCapture(st, &g);
+        bs.graph = g;
+        if (cr) return cr;
+        if (ce != hipSuccess) return fail(SL_EDEVICE, std::string("graph capture failed: ") + hipGetErrorString(ce));
+        SL_HIP(hipGraphInstantiate(&bs.exec, bs.graph, nullptr, nullptr, 0));
+        graph_used = 1;
+        const int32_t replays = (iterations + chunk - 1) / chunk;
+        for (int32_t k = 0; k < replays; ++k) SL_HIP(hipGraphLaunch(bs.exec, st));
+    }
+    SL_HIP(hipEventRecord(bs.ev[3], st));
+
+    // ---- results
+    std::vector<MeshState> hs(static_cast<size_t>(n_meshes));
+    SL_HIP(hipMemcpyAsync(hs.data(), bs.states, sizeof(MeshState) * hs.size(), hipMemcpyDeviceToHost, st));
+    if ((r = dalloc(&bs.out, 2 * max_nodes, st))) return r;
+    SL_HIP(hipStreamSynchronize(st));
+    float setup_ms = 0.f, sweep_ms = 0.f;
+    SL_HIP(hipEventElapsedTime(&setup_ms, bs.ev[0], bs.ev[1]));
+    SL_HIP(hipEventElapsedTime(&sweep_ms, bs.ev[2], bs.ev[3]));
+    int64_t updates = 0;
+    for (int32_t i = 0; i < n_meshes; ++i) {
+        const DevMesh& m = bs.meshes[i];
+        const int src = jacobi ? (hs[i].s & 1) : 0;
+        if ((r = unpermute_coords(m, src, bs.out, st))) return r;
+        SL_HIP(hipMemcpyAsync(meshes[i].coords, bs.out, 2 * sizeof(double) * static_cast<size_t>(m.n),
+                              hipMemcpyDeviceToHost, st));
+        SL_HIP(hipStreamSynchronize(st));
+        updates += static_cast<int64_t>(m.n_free) * hs[i].s;
+        if (reports) {
+            sl_report rep{};
+            rep.iterations_run = hs[i].s;
+            rep.n_colors = m.n_colors;
+            std::memcpy(&rep.max_disp_sq_last, &hs[i].maxd_last, sizeof(double));
+            rep.accepted_last = static_cast<int64_t>(hs[i].acc_last);
+            rep.accepted_total = static_cast<int64_t>(hs[i].acc_total);
+            rep.kernel_used = (jacobi && m.tile_nodes > 0) ? SL_KERNEL_TILE : SL_KERNEL_NODE;
+            rep.tile_nodes = m.tile_nodes;
+            reports[i] = rep;
+        }
+    }
+    if (batch) {
+        sl_batch_report b{};
+        b.setup_ms = setup_ms;
+        b.sweep_ms = sweep_ms;
+        b.total_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+        b.node_updates = updates;
+        b.tiles = total_tiles;
+        b.meshes_on_tile_path = on_tiles;
+        b.graph_used = graph_used;
+        *batch = b;
+    }
+    return SL_OK;
+}
+
+}  // extern "C"

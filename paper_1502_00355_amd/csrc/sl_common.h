@@ -49,9 +49,38 @@ struct ValStats {
 
 // ------------------------------------------------------- device workspace --
 
+// Sweep state of one mesh on the device.  The sweep kernels read `active`
+// and fold into the *_cur fields; k_advance closes a sweep.
+struct MeshState {
+    int32_t s;                      // sweeps completed
+    int32_t iters;                  // cap on sweeps
+    int32_t active;                 // 1 while the next sweep runs
+    int32_t pad;
+    double tol2;                    // > 0: stop after a sweep with max |dx|^2 < tol2
+    unsigned long long maxd_cur;    // bit pattern of the max squared displacement, sweep in progress
+    unsigned long long acc_cur;     // accepted nodes, sweep in progress
+    unsigned long long maxd_last;   // last completed sweep
+    unsigned long long acc_last;
+    unsigned long long acc_total;
+};
+
+// One tile of the tile path: everything a work-group needs to sweep it, with
+// absolute pointers so that tiles of many meshes can share one launch.
+struct alignas(16) TileWork {
+    const double* X;                // the mesh's buffer pair: X[0] at X, X[1] at X + 2n
+    const int32_t* halo;            // halo node ids (mesh device labels)
+    const uint64_t* rows;           // neighbour rows in local indices, 4 x u16 per word
+    const uint64_t* tris;           // triangle entries: 3 x u16 local indices, stored order
+    const uint32_t* rr;             // per own node: row start | row end << 16 within `rows`
+    int32_t own_start, nown;        // own nodes: mesh device labels [own_start, own_start + nown)
+    int32_t halo_cnt, tri_cnt;
+    int32_t row_words, mesh;        // 64-bit row words; index of the mesh's MeshState
+    int64_t n;                      // the mesh's node count (buffer stride)
+};
+static_assert(sizeof(TileWork) == 80, "TileWork layout");
+
 // One mesh prepared for sweeping: free nodes occupy [0, n_free) in the
-// device order, fixed nodes [n_free, n).  Neighbour rows and fans exist for
-// free nodes only and are in device labels.
+// device order, fixed nodes [n_free, n).
 struct DevMesh {
     int32_t n = 0, n_free = 0, n_tris = 0;
     int64_t nnz_free = 0, ninc_free = 0;
@@ -61,23 +90,22 @@ struct DevMesh {
     int32_t* perm = nullptr;        // [n]  device label -> caller label
     int32_t* new_of_old = nullptr;  // [n]  caller label -> device label
     int32_t* row_ptr = nullptr;     // [n_free+1]
-    int32_t* nbr = nullptr;         // [nnz_free] device labels
+    int32_t* nbr = nullptr;         // [nnz_free] device labels (node path)
     int32_t* fan_ptr = nullptr;     // [n_free+1]
-    uint16_t* fan = nullptr;        // [ninc_free]
+    uint16_t* fan = nullptr;        // [ninc_free] (node path)
     int32_t color_start_h[130] = {0};    // colour class c: device labels [cs[c], cs[c+1])
-    double* X[2] = {nullptr, nullptr};   // AoS: 2n doubles; SoA: x[n] then y[n]
-    // Tile path (Form A): free nodes in tiles of tile_nodes consecutive device
-    // labels; per tile a halo list, local neighbour rows and a local triangle list.
+    double* X[2] = {nullptr, nullptr};   // one block of 4n doubles: X[1] = X[0] + 2n;
+                                         // AoS (x,y pairs) or SoA (x[n] then y[n]) inside each
+    // Tile path (Form A)
     int32_t tile_nodes = 0;              // 0: tile path not built
     int32_t n_tiles = 0;
     int32_t halo_max = 0;                // largest halo over tiles
     int32_t rows_max = 0;                // largest row segment (u16 entries, padded to 4) over tiles
-    int4* tile_meta = nullptr;           // [n_tiles] {halo_off, halo_cnt, tri_off, tri_cnt}
-    int2* tile_rows = nullptr;           // [n_tiles] {row segment offset (multiple of 4), padded length}
-    int32_t* halo = nullptr;             // [sum halo] device labels
-    uint16_t* nbr_loc = nullptr;         // tile row segments: local index of each neighbour, row order
-    uint16_t* row_rel = nullptr;         // [n_tiles * (tile_nodes+1)] row start inside the tile's segment
-    uint64_t* tri_loc = nullptr;         // [sum tri] 3 x 16-bit local vertex indices, stored order
+    TileWork* work = nullptr;            // [n_tiles]
+    int32_t* halo = nullptr;             // halo lists of all tiles
+    uint16_t* nbr_loc = nullptr;         // row segments of all tiles
+    uint32_t* row_rel = nullptr;         // [n_tiles * tile_nodes]
+    uint64_t* tri_loc = nullptr;         // triangle entries of all tiles
 };
 
 // Frees every device array of m (stream-ordered).
@@ -96,13 +124,33 @@ struct SetupArgs {
     int64_t nnz, ninc;      // nbr_ptr[n], tri_ptr[n] (read by the caller of setup)
 };
 
-// Builds the tile path for Form A (tile_nodes free nodes per tile).  Leaves
+// Builds the tile path for Form A (tile_nodes free nodes per tile) and
+// writes the tile list to m.work with MeshState index `mesh`.  Leaves
 // m.tile_nodes = 0 (node path) when the mesh does not fit it.
-sl_status build_tiles(const SetupArgs& a, DevMesh& m, int tile_nodes, hipStream_t st);
+sl_status build_tiles(const SetupArgs& a, DevMesh& m, int tile_nodes, int mesh, hipStream_t st);
 
-// Validates the inputs, orders the nodes, builds rows and fans and fills both
-// coordinate buffers.  Synchronises `st` (the validation result is needed).
-sl_status setup_mesh(const SetupArgs& a, const sl_options& o, DevMesh& m, hipStream_t st);
+// Validates the inputs, orders the nodes, builds rows and fans (node path)
+// or tiles (tile path, MeshState index `mesh`) and fills both coordinate
+// buffers.  Synchronises `st` (the validation result is needed).
+sl_status setup_mesh(const SetupArgs& a, const sl_options& o, DevMesh& m, int32_t mesh, hipStream_t st);
+
+// Device arrays of one caller mesh.
+struct MeshInput {
+    const double* coords;
+    int32_t n;
+    const int32_t* nbr_ptr;
+    const int32_t* nbr_idx;
+    const int32_t* tri_ptr;
+    const int32_t* tri_idx;
+    const int32_t* tris;
+    int32_t n_tris;
+    const uint8_t* boundary;
+};
+
+// Argument checks, then setup_mesh.
+sl_status prepare_mesh(const MeshInput& in, const sl_options& o, int32_t mesh, DevMesh& m, hipStream_t st);
+sl_status check_options(const sl_options& o);
+void keep_pool_warm();
 
 // Writes the positions of buffer `src` back to the caller's layout and order.
 sl_status unpermute_coords(const DevMesh& m, int src, double* coords_out, hipStream_t st);
@@ -112,23 +160,31 @@ sl_status unpermute_coords(const DevMesh& m, int src, double* coords_out, hipStr
 sl_status unpermute_flags(const DevMesh& m, const uint64_t* bits, int32_t iterations, int32_t iterations_run,
                           uint8_t* flags_out, hipStream_t st);
 
-// Per-sweep outputs of the sweep kernels.
-struct SweepOut {
-    uint64_t* maxd;            // [iterations] bit pattern of the largest squared displacement
-    unsigned long long* acc;   // [iterations] accepted count
-    uint64_t* bits;            // nullable: [iterations][words] accept bits, device order
-    int64_t words;             // 64-bit words per sweep
+// Queues one Jacobi or coloured sweep of a single mesh on the node path
+// (Form A reads X[parity], writes X[parity^1]; Form B works in place in
+// X[0]).  Skipped on the device when the mesh's state is inactive.  bits:
+// nullable accept bits of this sweep (device labels, 64-bit words).
+sl_status launch_sweep_nodes(const DevMesh& m, int32_t parity, int32_t form, int32_t accept, int32_t block,
+                             MeshState* state, uint64_t* bits, hipStream_t st);
+
+// Queues one sweep of every tile in work[0..n_work) (any number of meshes,
+// all reading X[parity]).  bits: nullable, single-mesh runs only.
+struct TileLaunch {
+    const TileWork* work;
+    int32_t n_work;
+    int32_t tile_nodes;
+    int32_t halo_cap, rows_cap;
+    int32_t layout, accept;
+    MeshState* states;
 };
+sl_status launch_sweep_tiles(const TileLaunch& L, int32_t parity, uint64_t* bits, hipStream_t st);
 
-// Queues sweep `s` of the Jacobi form (reads X[s%2], writes X[(s+1)%2]) or
-// of the coloured form (in place in X[0]); skipped on the device when the
-// previous sweep's displacement is below tol2 (tol2 > 0).
-sl_status launch_sweep(const DevMesh& m, int32_t s, int32_t form, int32_t accept, int32_t block, double tol2,
-                       const SweepOut& out, hipStream_t st);
+// Closes a sweep for states[0..n): counts it for the active meshes and
+// decides whether each runs the next one.
+sl_status launch_advance(MeshState* states, int32_t n, hipStream_t st);
 
-// Queues sweep `s` on the tile path (Form A).
-sl_status launch_sweep_tiles(const DevMesh& m, int32_t s, int32_t accept, double tol2, const SweepOut& out,
-                             hipStream_t st);
+// Work-group count of a tile launch (persistent work-groups, XCD-aware).
+int tile_grid(int n_work, int tile_nodes, int halo_cap, int rows_cap);
 
 // Exclusive scan of n int32 values; out[n] receives the total (out has n+1).
 sl_status scan_exclusive(const int32_t* in, int32_t* out, int64_t n, hipStream_t st);

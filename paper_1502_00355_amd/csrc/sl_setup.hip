@@ -14,6 +14,7 @@
 //     position p in the triangle's stored order (bits 0-1) and the row slots
 //     of the vertices at stored positions p+1 and p+2 mod 3 (bits 2-8, 9-15).
 #include <algorithm>
+#include <cstdlib>
 #include <vector>
 
 #include "sl_common.h"
@@ -569,16 +570,25 @@ void devmesh_free(DevMesh& m, hipStream_t st)
     dfree(m.fan_ptr, st);
     dfree(m.fan, st);
     dfree(m.X[0], st);
-    dfree(m.X[1], st);
-    dfree(m.tile_meta, st);
-    dfree(m.tile_rows, st);
+    m.X[1] = nullptr;
+    dfree(m.work, st);
     dfree(m.halo, st);
     dfree(m.nbr_loc, st);
     dfree(m.row_rel, st);
     dfree(m.tri_loc, st);
 }
 
-sl_status setup_mesh(const SetupArgs& a, const sl_options& o, DevMesh& m, hipStream_t st)
+// Free nodes per tile on the tile path (SMARTLAP_TILE_NODES overrides: 256 or 512).
+static int tile_nodes_for(const sl_options&)
+{
+    if (const char* e = getenv("SMARTLAP_TILE_NODES")) {
+        const int v = atoi(e);
+        if (v == 256 || v == 512) return v;
+    }
+    return 512;
+}
+
+sl_status setup_mesh(const SetupArgs& a, const sl_options& o, DevMesh& m, int32_t mesh, hipStream_t st)
 {
     const int32_t n = a.n;
     m.n = n;
@@ -671,9 +681,13 @@ sl_status setup_mesh(const SetupArgs& a, const sl_options& o, DevMesh& m, hipStr
     dfree(inc, st);
     m.nnz_free = tot[0];
     m.ninc_free = tot[1];
+    // coordinate buffers: one block, X[1] right after X[0]
+    if ((r = dalloc(&m.X[0], 4 * static_cast<size_t>(n), st))) return r;
+    m.X[1] = m.X[0] + 2 * static_cast<size_t>(n);
+    k_init_coords<<<gb, kBS, 0, st>>>(a.coords, m.perm, n, o.layout == SL_SOA, m.X[0], m.X[1]);
     // tile path for Form A; the node path's rows and fans otherwise
     if (o.form == SL_JACOBI && o.kernel != SL_KERNEL_NODE)
-        if ((r = build_tiles(a, m, 512, st))) return r;
+        if ((r = build_tiles(a, m, tile_nodes_for(o), mesh, st))) return r;
     if (m.tile_nodes == 0) {
         if ((r = dalloc(&m.nbr, m.nnz_free, st)) || (r = dalloc(&m.fan, m.ninc_free, st))) return r;
         if (m.n_free > 0)
@@ -682,9 +696,7 @@ sl_status setup_mesh(const SetupArgs& a, const sl_options& o, DevMesh& m, hipStr
     }
 
     // ---- coordinate buffers
-    if ((r = dalloc(&m.X[0], 2 * static_cast<size_t>(n), st)) || (r = dalloc(&m.X[1], 2 * static_cast<size_t>(n), st)))
-        return r;
-    k_init_coords<<<gb, kBS, 0, st>>>(a.coords, m.perm, n, o.layout == SL_SOA, m.X[0], m.X[1]);
+
     SL_HIP(hipGetLastError());
     return SL_OK;
 }

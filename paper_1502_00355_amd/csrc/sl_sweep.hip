@@ -77,17 +77,14 @@ struct SweepArgs {
     const uint16_t* fan;
     int32_t k_begin, k_end;         // device labels handled by this launch
     int32_t n_tiles, tiles_per_xcd; // work-group tiles; XCD-contiguous mapping
-    const uint64_t* prev_maxd;      // nullable: skip if *prev_maxd < tol2
-    double tol2;
-    uint64_t* maxd;                 // this sweep's max squared displacement (bit pattern)
-    unsigned long long* acc;        // this sweep's accepted count
+    MeshState* state;               // skip unless active; max displacement and count fold here
     uint64_t* bits;                 // nullable: this sweep's accept bits (device labels)
 };
 
 template <int BLOCK, int MAXV, bool SOA, bool GT>
 __global__ __launch_bounds__(BLOCK) void k_sweep(SweepArgs a)
 {
-    if (a.prev_maxd != nullptr && __longlong_as_double(static_cast<long long>(*a.prev_maxd)) < a.tol2) return;
+    if (!a.state->active) return;
     // Work-groups are handed to the 8 XCDs round-robin; give each XCD a
     // contiguous run of tiles so that neighbouring tiles share its L2.
     const int tile = static_cast<int>(blockIdx.x % 8) * a.tiles_per_xcd + static_cast<int>(blockIdx.x / 8);
@@ -158,8 +155,8 @@ __global__ __launch_bounds__(BLOCK) void k_sweep(SweepArgs a)
             m = s_d2[q] > m ? s_d2[q] : m;
             c += s_acc[q];
         }
-        if (m > 0.0) atomicMax(reinterpret_cast<unsigned long long*>(a.maxd), static_cast<unsigned long long>(__double_as_longlong(m)));
-        if (c) atomicAdd(a.acc, c);
+        if (m > 0.0) atomicMax(&a.state->maxd_cur, static_cast<unsigned long long>(__double_as_longlong(m)));
+        if (c) atomicAdd(&a.state->acc_cur, c);
     }
 }
 
@@ -205,10 +202,36 @@ void launch_range(SweepArgs a, int max_deg, int requested_block, bool soa, bool 
     }
 }
 
+// Closes a sweep (one work-item per mesh).
+__global__ void k_advance(MeshState* __restrict__ st, int32_t n)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    MeshState m = st[i];
+    if (!m.active) return;
+    m.s += 1;
+    m.maxd_last = m.maxd_cur;
+    m.acc_last = m.acc_cur;
+    m.acc_total += m.acc_cur;
+    m.maxd_cur = 0;
+    m.acc_cur = 0;
+    const double last = __longlong_as_double(static_cast<long long>(m.maxd_last));
+    m.active = (m.s < m.iters) && !(m.tol2 > 0.0 && last < m.tol2);
+    st[i] = m;
+}
+
 }  // namespace
 
-sl_status launch_sweep(const DevMesh& m, int32_t s, int32_t form, int32_t accept, int32_t block, double tol2,
-                       const SweepOut& out, hipStream_t st)
+sl_status launch_advance(MeshState* states, int32_t n, hipStream_t st)
+{
+    if (n <= 0) return SL_OK;
+    k_advance<<<div_up(n, 256), 256, 0, st>>>(states, n);
+    SL_HIP(hipGetLastError());
+    return SL_OK;
+}
+
+sl_status launch_sweep_nodes(const DevMesh& m, int32_t parity, int32_t form, int32_t accept, int32_t block,
+                             MeshState* state, uint64_t* bits, hipStream_t st)
 {
     SweepArgs a{};
     a.n = m.n;
@@ -216,16 +239,12 @@ sl_status launch_sweep(const DevMesh& m, int32_t s, int32_t form, int32_t accept
     a.nbr = m.nbr;
     a.fan_ptr = m.fan_ptr;
     a.fan = m.fan;
-    a.prev_maxd = (s > 0 && tol2 > 0.0) ? out.maxd + (s - 1) : nullptr;
-    a.tol2 = tol2;
-    a.maxd = out.maxd + s;
-    a.acc = out.acc + s;
-    a.bits = out.bits ? out.bits + static_cast<int64_t>(s) * out.words : nullptr;
-    if (form == SL_JACOBI && m.tile_nodes > 0) return launch_sweep_tiles(m, s, accept, tol2, out, st);
+    a.state = state;
+    a.bits = bits;
     const bool soa = m.layout == SL_SOA, gt = accept == SL_ACCEPT_GT;
     if (form == SL_JACOBI) {
-        a.Xin = m.X[s & 1];
-        a.Xout = m.X[(s + 1) & 1];
+        a.Xin = m.X[parity & 1];
+        a.Xout = m.X[(parity + 1) & 1];
         a.k_begin = 0;
         a.k_end = m.n_free;
         launch_range(a, m.max_deg, block, soa, gt, st);

@@ -22,7 +22,9 @@
 // halo and the incident triangles in LDS, sorts and deduplicates them, and
 // rewrites rows and triangles in tile-local indices (own nodes 0..T-1, halo
 // nodes T..T+H-1).
+#include <algorithm>
 #include <climits>
+#include <cstdlib>
 
 #include "sl_common.h"
 
@@ -137,7 +139,7 @@ struct TileBuildArgs {
     const int32_t* row_off;
     int32_t* halo;
     uint16_t* nbr_loc;
-    uint16_t* row_rel;
+    uint32_t* row_rel;
     uint64_t* tri_loc;
     int32_t* err;
 };
@@ -180,9 +182,12 @@ __global__ __launch_bounds__(kBuildBS) void k_tile_build(TileBuildArgs a, int pa
         }
         return true;
     };
+    // triangles are listed in node order (work-item t lists nodes NPT*t ..
+    // NPT*t+NPT-1), so that the lanes of a wave walking the list touch one
+    // compact patch of nodes in LDS
     int c = 0;
     for (int m = 0; m < NPT; ++m) {
-        const int i = m * BS + threadIdx.x;
+        const int i = NPT * threadIdx.x + m;
         if (i < nown) {
             const int32_t o = a.perm[k0 + i];
             for (int32_t q = a.tri_ptr[o]; q < a.tri_ptr[o + 1]; ++q) c += kept(o, k0 + i, a.tri_idx[q]);
@@ -199,8 +204,10 @@ __global__ __launch_bounds__(kBuildBS) void k_tile_build(TileBuildArgs a, int pa
     }
     const int32_t hoff = a.halo_off[tile], toff = a.tri_off[tile], roff = a.row_off[tile];
     for (int h = threadIdx.x; h < H; h += BS) a.halo[hoff + h] = hb[h];
-    uint16_t* rr = a.row_rel + static_cast<int64_t>(tile) * (T + 1);
-    for (int i = threadIdx.x; i <= T; i += BS) rr[i] = static_cast<uint16_t>(a.row_ptr[k0 + min(i, nown)] - rb);
+    uint32_t* rr = a.row_rel + static_cast<int64_t>(tile) * T;
+    for (int i = threadIdx.x; i < T; i += BS)
+        rr[i] = static_cast<uint32_t>(a.row_ptr[k0 + min(i, nown)] - rb) |
+                (static_cast<uint32_t>(a.row_ptr[k0 + min(i + 1, nown)] - rb) << 16);
     auto local = [&](int32_t jd) -> int {
         if (jd >= k0 && jd < k0 + nown) return jd - k0;
         const int h = lower_bound_lds(hb, H, jd);
@@ -215,6 +222,11 @@ __global__ __launch_bounds__(kBuildBS) void k_tile_build(TileBuildArgs a, int pa
         const int32_t o = a.perm[k0 + i];
         const int32_t b = a.nbr_ptr[o], d = a.nbr_ptr[o + 1] - b, out = a.row_ptr[k0 + i] - rb;
         for (int j = 0; j < d; ++j) seg[out + j] = static_cast<uint16_t>(local(a.new_of_old[a.nbr_idx[b + j]]));
+    }
+    for (int m = 0; m < NPT; ++m) {
+        const int i = NPT * threadIdx.x + m;
+        if (i >= nown) continue;
+        const int32_t o = a.perm[k0 + i];
         for (int32_t q = a.tri_ptr[o]; q < a.tri_ptr[o + 1]; ++q) {
             const int64_t t = a.tri_idx[q];
             if (!kept(o, k0 + i, t)) continue;
@@ -233,15 +245,30 @@ __global__ void k_split_counts(const int4* __restrict__ c, int n, int32_t* __res
     if (i < n) { h[i] = c[i].x; r[i] = c[i].y; l[i] = c[i].z; }
 }
 
-__global__ void k_tile_meta(const int4* __restrict__ c, const int32_t* __restrict__ hoff,
-                            const int32_t* __restrict__ toff, const int32_t* __restrict__ roff, int n,
-                            int4* __restrict__ meta, int2* __restrict__ rows, int32_t* __restrict__ mx)
+// Tile descriptors of one mesh, and the largest halo / row segment.
+__global__ void k_tile_work(const int4* __restrict__ c, const int32_t* __restrict__ hoff,
+                            const int32_t* __restrict__ toff, const int32_t* __restrict__ roff, int nt, int T,
+                            int32_t n_free, int64_t n, int32_t mesh, const double* X, const int32_t* halo,
+                            const uint16_t* nbr_loc, const uint64_t* tri_loc, const uint32_t* row_rel,
+                            TileWork* __restrict__ work, int32_t* __restrict__ mx)
 {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     int mh = 0, ml = 0;
-    if (i < n) {
-        meta[i] = make_int4(hoff[i], c[i].x, toff[i], c[i].y);
-        rows[i] = make_int2(roff[i], c[i].z);
+    if (i < nt) {
+        TileWork w;
+        w.X = X;
+        w.halo = halo + hoff[i];
+        w.rows = reinterpret_cast<const uint64_t*>(nbr_loc + roff[i]);
+        w.tris = tri_loc + toff[i];
+        w.rr = row_rel + static_cast<int64_t>(i) * T;
+        w.own_start = i * T;
+        w.nown = min(T, n_free - i * T);
+        w.halo_cnt = c[i].x;
+        w.tri_cnt = c[i].y;
+        w.row_words = c[i].z >> 2;
+        w.mesh = mesh;
+        w.n = n;
+        work[i] = w;
         mh = c[i].x;
         ml = c[i].z;
     }
@@ -285,21 +312,11 @@ __device__ __forceinline__ double2 ldx(const double* X, int64_t n, int64_t i)
 }
 
 struct TileSweepArgs {
-    const double* Xin;
-    double* Xout;
-    int64_t n;
-    const int4* meta;
-    const int2* rows;
-    const uint16_t* row_rel;
-    const uint16_t* nbr_loc;
-    const int32_t* halo;
-    const uint64_t* tri_loc;
-    int32_t n_free, n_tiles, tiles_per_xcd, halo_cap, rows_cap;
-    const uint64_t* prev_maxd;
-    double tol2;
-    uint64_t* maxd;
-    unsigned long long* acc;
-    uint64_t* bits;
+    const TileWork* work;
+    int32_t n_work, tiles_per_xcd, halo_cap, rows_cap;
+    int32_t parity;            // every mesh of the launch reads buffer `parity`
+    MeshState* states;
+    uint64_t* bits;            // nullable: accept bits of this sweep (single mesh)
 };
 
 // Old quality of one triangle and the new quality for each own vertex,
@@ -339,17 +356,134 @@ __device__ __forceinline__ void tile_triangle(uint64_t w, const double2* Xl, con
     }
 }
 
+// Registers holding the global data of the next tile while the current one
+// is computed.  Loaded in two steps, the second a phase after the first:
+// (A) halo ids, own positions, row offsets; (B) halo positions, the row
+// segment, triangle entries.  Tile descriptors are loaded a tile earlier.
+template <int NPT, int RPRE, int KPRE>
+struct TileStage {
+    double2 own[NPT];
+    uint32_t rr[NPT];        // row start | row end << 16, unpacked where used
+    uint64_t rw[RPRE];
+    uint64_t tw[KPRE];
+    int hidx;
+    double2 hx;
+};
+
+// The descriptor is loaded through an index the compiler treats as per-lane,
+// so the loads stay vector loads (counted with the other global loads)
+// instead of scalar loads that the next LDS barrier would wait for.
+__device__ __forceinline__ TileWork load_work(const TileWork* work, int i)
+{
+    int t = i;
+    asm volatile("" : "+v"(t));
+    const __attribute__((address_space(1))) uint64_t* p =
+        reinterpret_cast<const __attribute__((address_space(1))) uint64_t*>(reinterpret_cast<uint64_t>(work)) +
+        static_cast<int64_t>(t) * (sizeof(TileWork) / 8);
+    uint64_t raw[sizeof(TileWork) / 8];
+#pragma unroll
+    for (int q = 0; q < static_cast<int>(sizeof(TileWork) / 8); ++q) raw[q] = p[q];
+    TileWork w;
+    __builtin_memcpy(&w, raw, sizeof(TileWork));
+    return w;
+}
+
+// Global-address-space pointers: loads through them are global loads,
+// counted only by vmcnt (flat loads would also hold lgkmcnt, which every LDS
+// barrier waits for).
+template <typename V>
+using gptr = const __attribute__((address_space(1))) V*;
+
+template <typename V>
+__device__ __forceinline__ gptr<V> to_global(const V* p)
+{
+    return reinterpret_cast<gptr<V>>(reinterpret_cast<uint64_t>(p));
+}
+
+__device__ __forceinline__ TileWork uniform_work(const TileWork& w)
+{
+    auto uv = [](uint64_t v) {
+        const uint32_t lo = __builtin_amdgcn_readfirstlane(static_cast<uint32_t>(v));
+        const uint32_t hi = __builtin_amdgcn_readfirstlane(static_cast<uint32_t>(v >> 32));
+        return (static_cast<uint64_t>(hi) << 32) | lo;
+    };
+    auto u64 = [&](const void* p) { return uv(reinterpret_cast<uint64_t>(p)); };
+    TileWork u;
+    u.X = reinterpret_cast<const double*>(u64(w.X));
+    u.halo = reinterpret_cast<const int32_t*>(u64(w.halo));
+    u.rows = reinterpret_cast<const uint64_t*>(u64(w.rows));
+    u.tris = reinterpret_cast<const uint64_t*>(u64(w.tris));
+    u.rr = reinterpret_cast<const uint32_t*>(u64(w.rr));
+    u.own_start = __builtin_amdgcn_readfirstlane(w.own_start);
+    u.nown = __builtin_amdgcn_readfirstlane(w.nown);
+    u.halo_cnt = __builtin_amdgcn_readfirstlane(w.halo_cnt);
+    u.tri_cnt = __builtin_amdgcn_readfirstlane(w.tri_cnt);
+    u.row_words = __builtin_amdgcn_readfirstlane(w.row_words);
+    u.mesh = __builtin_amdgcn_readfirstlane(w.mesh);
+    u.n = static_cast<int64_t>(uv(static_cast<uint64_t>(w.n)));
+    return u;
+}
+
+template <bool SOA>
+__device__ __forceinline__ double2 ldxg(gptr<double> X, int64_t n, int64_t i)
+{
+    if (SOA) return make_double2(X[i], X[n + i]);
+    return make_double2(X[2 * i], X[2 * i + 1]);
+}
+
+template <int T, int BS, bool SOA, int NPT, int RPRE, int KPRE>
+__device__ __forceinline__ void stage_a(TileStage<NPT, RPRE, KPRE>& s, const TileWork& d, int parity)
+{
+    const int tid = threadIdx.x;
+    const gptr<double> Xin = to_global(d.X) + parity * 2 * d.n;
+    const gptr<int32_t> halo = to_global(d.halo);
+    const gptr<uint32_t> rr = to_global(d.rr);
+    s.hidx = tid < d.halo_cnt ? halo[tid] : -1;
+#pragma unroll
+    for (int m = 0; m < NPT; ++m) {
+        const int i = m * BS + tid;
+        s.rr[m] = rr[i];
+        s.own[m] = i < d.nown ? ldxg<SOA>(Xin, d.n, d.own_start + i) : make_double2(0.0, 0.0);
+    }
+}
+
+template <int T, int BS, bool SOA, int NPT, int RPRE, int KPRE>
+__device__ __forceinline__ void stage_b(TileStage<NPT, RPRE, KPRE>& s, const TileWork& d, int parity)
+{
+    const int tid = threadIdx.x;
+    const gptr<double> Xin = to_global(d.X) + parity * 2 * d.n;
+    const gptr<uint64_t> rows = to_global(d.rows);
+    const gptr<uint64_t> tris = to_global(d.tris);
+    s.hx = s.hidx >= 0 ? ldxg<SOA>(Xin, d.n, s.hidx) : make_double2(0.0, 0.0);
+#pragma unroll
+    for (int q = 0; q < RPRE; ++q) {
+        const int j = q * BS + tid;
+        s.rw[q] = j < d.row_words ? rows[j] : 0ull;
+    }
+#pragma unroll
+    for (int q = 0; q < KPRE; ++q) {
+        const int r = q * BS + tid;
+        s.tw[q] = r < d.tri_cnt ? tris[r] : 0ull;
+    }
+}
+
+// Persistent work-groups: the work list is cut into 8 contiguous ranges, one
+// per XCD (work-groups are dealt to the XCDs round-robin), shared round-robin
+// by the work-groups that XCD runs; each work-group computes one tile while
+// the next one's data is on its way.
 template <int T, int BS, bool SOA, bool GT>
 __global__ __launch_bounds__(BS) void k_sweep_tile(TileSweepArgs a)
 {
     constexpr int NPT = T / BS;   // own nodes per work-item
-    constexpr int KPRE = 6;       // triangle entries per work-item loaded with the positions
-    constexpr int HPRE = 1;       // halo nodes per work-item loaded through registers
-    constexpr int RPRE = 4;       // 64-bit row words per work-item loaded through registers
-    if (a.prev_maxd != nullptr && __longlong_as_double(static_cast<long long>(*a.prev_maxd)) < a.tol2) return;
-    // XCD-contiguous tile order: work-groups go to the 8 XCDs round-robin
-    const int tile = static_cast<int>(blockIdx.x % 8) * a.tiles_per_xcd + static_cast<int>(blockIdx.x / 8);
-    if (tile >= a.n_tiles) return;
+    // per work-item register budget for the next tile: about 2.4 triangles
+    // and 1.5 row words per free node on meshes of valence 6
+    constexpr int KPRE = T == 256 ? 3 : 5;   // triangle entries
+    constexpr int RPRE = T == 256 ? 2 : 4;   // 64-bit row words
+    const int xcd = static_cast<int>(blockIdx.x & 7), nw = static_cast<int>(gridDim.x >> 3);
+    const int t_begin = xcd * a.tiles_per_xcd;
+    const int t_end = min(t_begin + a.tiles_per_xcd, a.n_work);
+    int it = t_begin + static_cast<int>(blockIdx.x >> 3);
+    if (it >= t_end) return;
 
     extern __shared__ double2 lds[];
     double2* Xl = lds;                                      // [T + halo_cap]
@@ -357,146 +491,161 @@ __global__ __launch_bounds__(BS) void k_sweep_tile(TileSweepArgs a)
     uint64_t* qo = reinterpret_cast<uint64_t*>(cand + T);   // [T]
     uint64_t* qn = qo + T;                                  // [T]
     uint16_t* rows = reinterpret_cast<uint16_t*>(qn + T);   // [rows_cap]
+    uint64_t* rows64 = reinterpret_cast<uint64_t*>(rows);
     __shared__ double s_d2[BS / 64];
     __shared__ unsigned long long s_acc[BS / 64];
-
     const int tid = threadIdx.x;
-    const int4 mt = a.meta[tile];
-    const int2 rs = a.rows[tile];
-    const int32_t k0 = tile * T;
-    const int nown = min(T, a.n_free - k0);
-
-    // 1. every global read of the sweep is issued first, into registers:
-    //    own positions, halo ids then halo positions, the row segment, row
-    //    offsets, the first triangle entries; then they are written to LDS.
-    const uint16_t* rr = a.row_rel + static_cast<int64_t>(tile) * (T + 1);
-    const int32_t* hl = a.halo + mt.x;
-    const uint64_t* seg = reinterpret_cast<const uint64_t*>(a.nbr_loc + rs.x);
-    uint64_t* rows64 = reinterpret_cast<uint64_t*>(rows);
-    const uint64_t* tl = a.tri_loc + mt.z;
-    const int nrow64 = rs.y >> 2;
-    int hidx[HPRE];
-#pragma unroll
-    for (int q = 0; q < HPRE; ++q) {
-        const int h = q * BS + tid;
-        hidx[q] = h < mt.y ? hl[h] : -1;
-    }
-    double2 own[NPT];
-    int r0[NPT], r1[NPT];
-#pragma unroll
-    for (int m = 0; m < NPT; ++m) {
-        const int i = m * BS + tid;
-        r0[m] = rr[i];
-        r1[m] = rr[i + 1];
-        own[m] = i < nown ? ldx<SOA>(a.Xin, a.n, k0 + i) : make_double2(0.0, 0.0);
-    }
-    uint64_t rw[RPRE];
-#pragma unroll
-    for (int q = 0; q < RPRE; ++q) {
-        const int j = q * BS + tid;
-        rw[q] = j < nrow64 ? seg[j] : 0ull;
-    }
-    uint64_t tw[KPRE];
-#pragma unroll
-    for (int q = 0; q < KPRE; ++q) {
-        const int r = q * BS + tid;
-        tw[q] = r < mt.w ? tl[r] : 0ull;
-    }
-    double2 hx[HPRE];
-#pragma unroll
-    for (int q = 0; q < HPRE; ++q) hx[q] = hidx[q] >= 0 ? ldx<SOA>(a.Xin, a.n, hidx[q]) : make_double2(0.0, 0.0);
-#pragma unroll
-    for (int m = 0; m < NPT; ++m)
-        if (m * BS + tid < nown) Xl[m * BS + tid] = own[m];
-#pragma unroll
-    for (int q = 0; q < RPRE; ++q)
-        if (q * BS + tid < nrow64) rows64[q * BS + tid] = rw[q];
-#pragma unroll
-    for (int q = 0; q < HPRE; ++q)
-        if (hidx[q] >= 0) Xl[T + q * BS + tid] = hx[q];
-    for (int h = HPRE * BS + tid; h < mt.y; h += BS) Xl[T + h] = ldx<SOA>(a.Xin, a.n, hl[h]);
-    for (int j = RPRE * BS + tid; j < nrow64; j += BS) rows64[j] = seg[j];
-    __syncthreads();
-
-    // 2. candidates: row-order sum of the neighbours, one division by the count
-    constexpr uint64_t kKeyInf = 0xFFF0000000000000ull;     // okey(+inf)
-#pragma unroll
-    for (int m = 0; m < NPT; ++m) {
-        const int i = m * BS + tid;
-        if (i < nown) {
-            double sx = 0.0, sy = 0.0;
-            for (int j = r0[m]; j < r1[m]; ++j) {
-                const double2 p = Xl[rows[j]];
-                sx += p.x;
-                sy += p.y;
-            }
-            const double dn = static_cast<double>(r1[m] - r0[m]);
-            cand[i] = make_double2(sx / dn, sy / dn);
-            qo[i] = kKeyInf;
-            qn[i] = kKeyInf;
-        }
-    }
-    __syncthreads();
-
-    // 3. triangles
-#pragma unroll
-    for (int q = 0; q < KPRE; ++q)
-        if (q * BS + tid < mt.w) tile_triangle<T>(tw[q], Xl, cand, qo, qn);
-    for (int r = KPRE * BS + tid; r < mt.w; r += BS) tile_triangle<T>(tl[r], Xl, cand, qo, qn);
-    __syncthreads();
-
-    // 4. accept, write, reduce
     const int lane = tid & 63, wv = tid >> 6;
-    double d2max = 0.0;
-    unsigned long long nacc = 0;
+    constexpr uint64_t kKeyInf = 0xFFF0000000000000ull;     // okey(+inf)
+    const int parity = a.parity;
+
+    // descriptors run two tiles ahead of the data, data one tile ahead; the
+    // prefetches are unconditional (past the last tile they re-load it) so
+    // that no branch forces them to complete early
+    TileWork dcur = uniform_work(load_work(a.work, it));
+    TileWork dnext = load_work(a.work, it + nw < t_end ? it + nw : it);
+    int act_cur = a.states[dcur.mesh].active;
+    TileStage<NPT, RPRE, KPRE> sg;
+    stage_a<T, BS, SOA>(sg, dcur, parity);
+    stage_b<T, BS, SOA>(sg, dcur, parity);
+    double run_d2 = 0.0;
+    unsigned long long run_acc = 0;
+
+    for (;;) {
+        const int nown = dcur.nown;
+        int r0[NPT], r1[NPT];
+        uint64_t tw[KPRE];
 #pragma unroll
-    for (int m = 0; m < NPT; ++m) {
-        const int i = m * BS + tid;
-        bool accepted = false;
-        if (i < nown) {
-            const double vo = okey_inv(qo[i]), vn = okey_inv(qn[i]);
-            accepted = GT ? (vn > vo) : (vn >= vo);
-            const double2 o = Xl[i];
-            const double2 c = cand[i];
-            const double nx = accepted ? c.x : o.x, ny = accepted ? c.y : o.y;
-            if (SOA) {
-                a.Xout[k0 + i] = nx;
-                a.Xout[a.n + k0 + i] = ny;
-            } else {
-                reinterpret_cast<double2*>(a.Xout)[k0 + i] = make_double2(nx, ny);
+        for (int m = 0; m < NPT; ++m) {
+            r0[m] = static_cast<int>(sg.rr[m] & 0xFFFFu);
+            r1[m] = static_cast<int>(sg.rr[m] >> 16);
+            if (m * BS + tid < nown) Xl[m * BS + tid] = sg.own[m];
+        }
+#pragma unroll
+        for (int q = 0; q < RPRE; ++q)
+            if (q * BS + tid < dcur.row_words) rows64[q * BS + tid] = sg.rw[q];
+#pragma unroll
+        for (int q = 0; q < KPRE; ++q) tw[q] = sg.tw[q];
+        if (sg.hidx >= 0) Xl[T + tid] = sg.hx;
+        {
+            // rare overflow beyond what the registers hold
+            const gptr<double> Xin = to_global(dcur.X) + parity * 2 * dcur.n;
+            const gptr<int32_t> halo = to_global(dcur.halo);
+            const gptr<uint64_t> rws = to_global(dcur.rows);
+            for (int h = BS + tid; h < dcur.halo_cnt; h += BS) Xl[T + h] = ldxg<SOA>(Xin, dcur.n, halo[h]);
+            for (int j = RPRE * BS + tid; j < dcur.row_words; j += BS) rows64[j] = rws[j];
+        }
+        __syncthreads();
+        const int next = it + nw;
+        const bool has_next = next < t_end;
+        dnext = uniform_work(dnext);
+        const int act_next = a.states[dnext.mesh].active;
+        stage_a<T, BS, SOA>(sg, dnext, parity);
+        const bool run = act_cur != 0;
+
+        // candidates: row-order sum of the neighbours, one division by the count
+        if (run) {
+#pragma unroll
+            for (int m = 0; m < NPT; ++m) {
+                const int i = m * BS + tid;
+                if (i < nown) {
+                    double sx = 0.0, sy = 0.0;
+                    for (int j = r0[m]; j < r1[m]; ++j) {
+                        const double2 p = Xl[rows[j]];
+                        sx += p.x;
+                        sy += p.y;
+                    }
+                    const double dn = static_cast<double>(r1[m] - r0[m]);
+                    cand[i] = make_double2(sx / dn, sy / dn);
+                    qo[i] = kKeyInf;
+                    qn[i] = kKeyInf;
+                }
             }
-            const double dx = nx - o.x, dy = ny - o.y;
-            const double d2 = dx * dx + dy * dy;
-            d2max = d2 > d2max ? d2 : d2max;
         }
-        const unsigned long long ball = __ballot(accepted);
-        nacc += __popcll(ball);
-        if (a.bits != nullptr && lane == 0 && ball != 0ull)
-            atomicOr(reinterpret_cast<unsigned long long*>(a.bits) + ((k0 + m * BS + wv * 64) >> 6), ball);
-    }
-    for (int off = 32; off > 0; off >>= 1) {
-        const double t = __shfl_xor(d2max, off);
-        d2max = t > d2max ? t : d2max;
-    }
-    if (lane == 0) {
-        s_d2[wv] = d2max;
-        s_acc[wv] = nacc;
-    }
-    __syncthreads();
-    if (tid == 0) {
-        double mx = s_d2[0];
-        unsigned long long c = s_acc[0];
-        for (int q = 1; q < BS / 64; ++q) {
-            mx = s_d2[q] > mx ? s_d2[q] : mx;
-            c += s_acc[q];
+        __syncthreads();
+        stage_b<T, BS, SOA>(sg, dnext, parity);
+
+        // triangles
+        if (run) {
+#pragma unroll
+            for (int q = 0; q < KPRE; ++q)
+                if (q * BS + tid < dcur.tri_cnt) tile_triangle<T>(tw[q], Xl, cand, qo, qn);
+            const gptr<uint64_t> tris = to_global(dcur.tris);
+            for (int r = KPRE * BS + tid; r < dcur.tri_cnt; r += BS) tile_triangle<T>(tris[r], Xl, cand, qo, qn);
         }
-        if (mx > 0.0)
-            atomicMax(reinterpret_cast<unsigned long long*>(a.maxd), static_cast<unsigned long long>(__double_as_longlong(mx)));
-        if (c) atomicAdd(a.acc, c);
+        __syncthreads();
+        const TileWork dnext2 = load_work(a.work, next + nw < t_end ? next + nw : (has_next ? next : it));
+
+        // accept and write; the displacement maximum and the accepted count
+        // accumulate per work-item over consecutive tiles of one mesh and are
+        // folded into its MeshState when the mesh changes (one pair of
+        // atomics per work-group and mesh)
+        if (run) {
+            __attribute__((address_space(1))) double* Xout =
+                reinterpret_cast<__attribute__((address_space(1))) double*>(reinterpret_cast<uint64_t>(dcur.X)) +
+                (parity ^ 1) * 2 * dcur.n;
+            const int k0 = dcur.own_start;
+#pragma unroll
+            for (int m = 0; m < NPT; ++m) {
+                const int i = m * BS + tid;
+                bool accepted = false;
+                if (i < nown) {
+                    const double vo = okey_inv(qo[i]), vn = okey_inv(qn[i]);
+                    accepted = GT ? (vn > vo) : (vn >= vo);
+                    const double2 o = Xl[i];
+                    const double2 c = cand[i];
+                    const double nx = accepted ? c.x : o.x, ny = accepted ? c.y : o.y;
+                    if (SOA) {
+                        Xout[k0 + i] = nx;
+                        Xout[dcur.n + k0 + i] = ny;
+                    } else {
+                        Xout[2 * (k0 + i)] = nx;
+                        Xout[2 * (k0 + i) + 1] = ny;
+                    }
+                    const double dx = nx - o.x, dy = ny - o.y;
+                    const double d2 = dx * dx + dy * dy;
+                    run_d2 = d2 > run_d2 ? d2 : run_d2;
+                }
+                const unsigned long long ball = __ballot(accepted);
+                run_acc += __popcll(ball);
+                if (a.bits != nullptr && lane == 0 && ball != 0ull)
+                    atomicOr(reinterpret_cast<unsigned long long*>(a.bits) + ((k0 + m * BS + wv * 64) >> 6), ball);
+            }
+        }
+        if (!has_next || dnext.mesh != dcur.mesh) {
+            double d2 = run_d2;
+            for (int off = 32; off > 0; off >>= 1) {
+                const double t = __shfl_xor(d2, off);
+                d2 = t > d2 ? t : d2;
+            }
+            if (lane == 0) {
+                s_d2[wv] = d2;
+                s_acc[wv] = run_acc;
+            }
+            __syncthreads();
+            if (tid == 0) {
+                double mx = s_d2[0];
+                unsigned long long c = s_acc[0];
+                for (int q = 1; q < BS / 64; ++q) {
+                    mx = s_d2[q] > mx ? s_d2[q] : mx;
+                    c += s_acc[q];
+                }
+                MeshState* ms = a.states + dcur.mesh;
+                if (mx > 0.0) atomicMax(&ms->maxd_cur, static_cast<unsigned long long>(__double_as_longlong(mx)));
+                if (c) atomicAdd(&ms->acc_cur, c);
+            }
+            run_d2 = 0.0;
+            run_acc = 0;
+        }
+        if (!has_next) break;
+        it = next;
+        dcur = dnext;
+        dnext = dnext2;
+        act_cur = act_next;
+        __syncthreads();
     }
 }
 
-constexpr int kTileT = 512;
 constexpr int kTileBS = 256;
 constexpr int kLdsLimit = 160 * 1024 - 4096;
 
@@ -511,7 +660,17 @@ void launch_tile_variant(const TileSweepArgs& a, int grid, size_t lds, hipStream
     k_sweep_tile<T, BS, SOA, GT><<<grid, BS, lds, st>>>(a);
 }
 
-}  // namespace
+template <int T>
+void launch_tile_t(const TileSweepArgs& a, bool soa, bool gt, int grid, size_t lds, hipStream_t st)
+{
+    if (soa) {
+        if (gt) launch_tile_variant<T, kTileBS, true, true>(a, grid, lds, st);
+        else launch_tile_variant<T, kTileBS, true, false>(a, grid, lds, st);
+    } else {
+        if (gt) launch_tile_variant<T, kTileBS, false, true>(a, grid, lds, st);
+        else launch_tile_variant<T, kTileBS, false, false>(a, grid, lds, st);
+    }
+}
 
 size_t tile_lds_bytes(int tile_nodes, int halo_cap, int rows_cap)
 {
@@ -519,10 +678,14 @@ size_t tile_lds_bytes(int tile_nodes, int halo_cap, int rows_cap)
            static_cast<size_t>(rows_cap) * 2;
 }
 
-sl_status build_tiles(const SetupArgs& a, DevMesh& m, int tile_nodes, hipStream_t st)
+}  // namespace
+
+sl_status build_tiles(const SetupArgs& a, DevMesh& m, int tile_nodes, int mesh, hipStream_t st)
 {
     m.tile_nodes = 0;
-    if (tile_nodes != kTileT || m.n_free == 0 || m.max_deg > kTileMaxDeg || m.max_inc > kTileMaxDeg) return SL_OK;
+    if ((tile_nodes != 256 && tile_nodes != 512) || m.n_free == 0 || m.max_deg > kTileMaxDeg ||
+        m.max_inc > kTileMaxDeg)
+        return SL_OK;
     const int T = tile_nodes;
     const int nt = div_up(m.n_free, T);
     sl_status r = SL_OK;
@@ -554,7 +717,8 @@ sl_status build_tiles(const SetupArgs& a, DevMesh& m, int tile_nodes, hipStream_
     b.n_free = m.n_free;
     b.counts = counts;
     b.err = err;
-    k_tile_build<kTileT><<<nt, kBuildBS, 0, st>>>(b, 0);
+    if (T == 256) k_tile_build<256><<<nt, kBuildBS, 0, st>>>(b, 0);
+    else k_tile_build<512><<<nt, kBuildBS, 0, st>>>(b, 0);
     k_split_counts<<<div_up(nt, 256), 256, 0, st>>>(counts, nt, hc, rc, lc);
     if ((r = scan_exclusive(hc, hoff, nt, st)) || (r = scan_exclusive(rc, toff, nt, st)) ||
         (r = scan_exclusive(lc, roff, nt, st))) {
@@ -566,9 +730,8 @@ sl_status build_tiles(const SetupArgs& a, DevMesh& m, int tile_nodes, hipStream_
     SL_HIP(hipMemcpyAsync(&tot[1], toff + nt, sizeof(int32_t), hipMemcpyDeviceToHost, st));
     SL_HIP(hipMemcpyAsync(&tot[2], roff + nt, sizeof(int32_t), hipMemcpyDeviceToHost, st));
     SL_HIP(hipStreamSynchronize(st));
-    if ((r = dalloc(&m.tile_meta, nt, st)) || (r = dalloc(&m.tile_rows, nt, st)) ||
-        (r = dalloc(&m.halo, tot[0], st)) || (r = dalloc(&m.nbr_loc, tot[2], st)) ||
-        (r = dalloc(&m.row_rel, static_cast<size_t>(nt) * (T + 1), st)) || (r = dalloc(&m.tri_loc, tot[1], st))) {
+    if ((r = dalloc(&m.work, nt, st)) || (r = dalloc(&m.halo, tot[0], st)) || (r = dalloc(&m.nbr_loc, tot[2], st)) ||
+        (r = dalloc(&m.row_rel, static_cast<size_t>(nt) * T, st)) || (r = dalloc(&m.tri_loc, tot[1], st))) {
         cleanup();
         return r;
     }
@@ -579,8 +742,10 @@ sl_status build_tiles(const SetupArgs& a, DevMesh& m, int tile_nodes, hipStream_
     b.nbr_loc = m.nbr_loc;
     b.row_rel = m.row_rel;
     b.tri_loc = m.tri_loc;
-    k_tile_build<kTileT><<<nt, kBuildBS, 0, st>>>(b, 1);
-    k_tile_meta<<<div_up(nt, 256), 256, 0, st>>>(counts, hoff, toff, roff, nt, m.tile_meta, m.tile_rows, mx);
+    if (T == 256) k_tile_build<256><<<nt, kBuildBS, 0, st>>>(b, 1);
+    else k_tile_build<512><<<nt, kBuildBS, 0, st>>>(b, 1);
+    k_tile_work<<<div_up(nt, 256), 256, 0, st>>>(counts, hoff, toff, roff, nt, T, m.n_free, m.n, mesh, m.X[0],
+                                                 m.halo, m.nbr_loc, m.tri_loc, m.row_rel, m.work, mx);
     int32_t h[3] = {0, 0, 0};
     SL_HIP(hipMemcpyAsync(&h[0], err, sizeof(int32_t), hipMemcpyDeviceToHost, st));
     SL_HIP(hipMemcpyAsync(&h[1], mx, 2 * sizeof(int32_t), hipMemcpyDeviceToHost, st));
@@ -595,39 +760,35 @@ sl_status build_tiles(const SetupArgs& a, DevMesh& m, int tile_nodes, hipStream_
     return SL_OK;
 }
 
-sl_status launch_sweep_tiles(const DevMesh& m, int32_t s, int32_t accept, double tol2, const SweepOut& out,
-                             hipStream_t st)
+int tile_grid(int n_work, int tile_nodes, int halo_cap, int rows_cap)
 {
+    const size_t lds = tile_lds_bytes(tile_nodes, halo_cap, rows_cap);
+    // work-groups per CU that fit the LDS and the waves per SIMD; 32 CUs per
+    // XCD; never more work-groups than tiles on an XCD
+    int per_cu = std::max(1, std::min(static_cast<int>(kLdsLimit / std::max<size_t>(lds, 1)), 4));
+    if (const char* e = getenv("SMARTLAP_TILE_WG_PER_CU")) per_cu = std::max(1, atoi(e));
+    const int tpx = div_up(std::max(n_work, 1), 8);
+    const int nw = std::min(tpx, 32 * per_cu);
+    return 8 * nw;
+}
+
+sl_status launch_sweep_tiles(const TileLaunch& L, int32_t parity, uint64_t* bits, hipStream_t st)
+{
+    if (L.n_work <= 0) return SL_OK;
     TileSweepArgs a{};
-    a.Xin = m.X[s & 1];
-    a.Xout = m.X[(s + 1) & 1];
-    a.n = m.n;
-    a.meta = m.tile_meta;
-    a.rows = m.tile_rows;
-    a.row_rel = m.row_rel;
-    a.nbr_loc = m.nbr_loc;
-    a.halo = m.halo;
-    a.tri_loc = m.tri_loc;
-    a.n_free = m.n_free;
-    a.n_tiles = m.n_tiles;
-    a.tiles_per_xcd = div_up(m.n_tiles, 8);
-    a.halo_cap = m.halo_max;
-    a.rows_cap = m.rows_max;
-    a.prev_maxd = (s > 0 && tol2 > 0.0) ? out.maxd + (s - 1) : nullptr;
-    a.tol2 = tol2;
-    a.maxd = out.maxd + s;
-    a.acc = out.acc + s;
-    a.bits = out.bits ? out.bits + static_cast<int64_t>(s) * out.words : nullptr;
-    const int grid = 8 * a.tiles_per_xcd;
-    const size_t lds = tile_lds_bytes(m.tile_nodes, m.halo_max, m.rows_max);
-    const bool soa = m.layout == SL_SOA, gt = accept == SL_ACCEPT_GT;
-    if (soa) {
-        if (gt) launch_tile_variant<kTileT, kTileBS, true, true>(a, grid, lds, st);
-        else launch_tile_variant<kTileT, kTileBS, true, false>(a, grid, lds, st);
-    } else {
-        if (gt) launch_tile_variant<kTileT, kTileBS, false, true>(a, grid, lds, st);
-        else launch_tile_variant<kTileT, kTileBS, false, false>(a, grid, lds, st);
-    }
+    a.work = L.work;
+    a.n_work = L.n_work;
+    a.tiles_per_xcd = div_up(L.n_work, 8);
+    a.halo_cap = L.halo_cap;
+    a.rows_cap = L.rows_cap;
+    a.parity = parity;
+    a.states = L.states;
+    a.bits = bits;
+    const size_t lds = tile_lds_bytes(L.tile_nodes, L.halo_cap, L.rows_cap);
+    const int grid = tile_grid(L.n_work, L.tile_nodes, L.halo_cap, L.rows_cap);
+    const bool soa = L.layout == SL_SOA, gt = L.accept == SL_ACCEPT_GT;
+    if (L.tile_nodes == 256) launch_tile_t<256>(a, soa, gt, grid, lds, st);
+    else launch_tile_t<512>(a, soa, gt, grid, lds, st);
     SL_HIP(hipGetLastError());
     return SL_OK;
 }

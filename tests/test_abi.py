@@ -60,3 +60,9 @@ def test_argument_errors_before_device_work(L):
     assert _call(iterations=-1) == sl.SL_EINVAL
     assert _call(null_coords=True) == sl.SL_EINVAL
     assert b"null" in L.sl_last_error()
+
+
+def test_server_config_defaults(L):
+    c = sl.ServerConfig()
+    L.sl_server_config_default(ctypes.byref(c))
+    assert c.hbm_budget_bytes == 200 << 30 and c.max_active == 256 and c.sweeps_per_step == 8

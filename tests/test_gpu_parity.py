@@ -259,3 +259,84 @@ def test_colored_form_parity_and_invariants():
         cur = min(oracle.quality(*mm.coords[a], *mm.coords[c], *mm.coords[d]) for a, c, d in m.tris)
         assert cur >= prev
         prev = cur
+
+
+def test_batch_equals_single_and_oracle():
+    """Meshes of uneven size (some below one tile, one node-path star, a
+    permuted mesh) in one batch: each result equals its own single-mesh run
+    and the oracle."""
+    ms = [meshgen.make_grid(n, "random", 0.35, 10000 + n) for n in (24, 31, 40, 57, 90)]
+    ms.append(meshgen.permute_mesh(meshgen.make_grid(33, "random", 0.4, 7), 3))
+    ms.append(_ring_star(20, 5))                      # valence 20: node path
+    ms.append(meshgen.make_annulus(12, 40, seed=9))
+    outs, reps, br = sl.batch_smooth(ms, 9)
+    assert br.graph_used == 1 and br.meshes_on_tile_path == len(ms) - 1
+    for m, X, rep in zip(ms, outs, reps):
+        ref = oracle.smooth(m, 9)
+        assert rep.iterations_run == 9 and rep.accepted_total == int(ref.accepted.sum())
+        assert (X == ref.coords).all(), m.name
+        Xs, rs, _ = run_gpu(m, 9)
+        assert (X == Xs).all()
+
+
+def test_batch_tolerance_and_forms():
+    ms = [meshgen.make_grid(n, "random", 0.4, 300 + n) for n in (20, 28, 45)]
+    ref = [oracle.smooth(m, 400, tol=3e-4) for m in ms]
+    outs, reps, br = sl.batch_smooth(ms, 400, tol=3e-4)
+    for m, X, rep, r in zip(ms, outs, reps, ref):
+        assert rep.iterations_run == r.iterations_run < 400
+        assert (X == r.coords).all()
+    outs, reps, br = sl.batch_smooth(ms, 5, form="colored")
+    for m, X in zip(ms, outs):
+        assert (X == oracle.smooth(m, 5, form="colored").coords).all()
+    outs, reps, br = sl.batch_smooth(ms, 6, accept="gt", layout="soa")
+    for m, X in zip(ms, outs):
+        assert (X == oracle.smooth(m, 6, accept_gt=True).coords).all()
+
+
+def test_server_mix_equals_single_and_oracle():
+    """Requests of different sizes, caps and tolerances, submitted at once
+    and while others run: each result equals its oracle run (and therefore
+    its own single-mesh run)."""
+    import time
+    ms = [meshgen.make_grid(n, "random", 0.4, 500 + n) for n in (20, 33, 64, 120, 257)]
+    ms.append(meshgen.permute_mesh(meshgen.make_grid(40, "random", 0.4, 8), 9))
+    ms.append(_ring_star(24, 3))                                   # node path
+    jobs = [(6, 0.0), (11, 0.0), (25, 0.0), (40, 0.0), (9, 0.0), (300, 2e-4), (4, 0.0)]
+    with sl.Server(sweeps_per_step=3) as srv:
+        ids = []
+        for k, (m, (it, tol)) in enumerate(zip(ms, jobs)):
+            ids.append(srv.submit(m, it, tol))
+            if k == 3:
+                time.sleep(0.05)                                  # later arrivals join running steps
+        res = [srv.wait(i) for i in ids]
+        st = srv.stats()
+    assert st.completed == len(ms) and st.failed == 0
+    for m, (it, tol), r in zip(ms, jobs, res):
+        assert r.status == sl.SL_OK, r.message
+        ref = oracle.smooth(m, it, tol=tol)
+        assert r.report.iterations_run == ref.iterations_run
+        assert (r.coords == ref.coords).all(), m.name
+        t = r.times
+        assert t.submitted_s <= t.admitted_s <= t.started_s <= t.done_s
+
+
+def test_server_cancel_deadline_budget_and_bad_input():
+    big = meshgen.make_grid(300, "random", 0.4, 1)
+    ok = meshgen.make_grid(30, "random", 0.4, 2)
+    bad = ok.copy()
+    bad.nbr_idx[3] = ok.n_nodes + 5
+    with sl.Server(sweeps_per_step=2, hbm_budget_bytes=64 << 20) as srv:
+        a = srv.submit(big, 100000)
+        b = srv.submit(ok, 7)
+        c = srv.submit(bad, 3)
+        d = srv.submit(big, 100000, deadline_s=0.05)
+        huge = meshgen.make_grid(1500, "random", 0.4, 3)            # estimated footprint over 64 MiB
+        e = srv.submit(huge, 2)
+        srv.cancel(a)
+        ra, rb, rc, rd, re = (srv.wait(x) for x in (a, b, c, d, e))
+    assert ra.status == sl.SL_ECANCELED
+    assert rb.status == sl.SL_OK and (rb.coords == oracle.smooth(ok, 7).coords).all()
+    assert rc.status == sl.SL_EINVAL
+    assert rd.status == sl.SL_ETIMEOUT
+    assert re.status == sl.SL_ENOMEM
