@@ -1,27 +1,47 @@
-"""Benchmark: iterated FP64 Smart Laplacian on a 16.8M-node mesh, one MI355X.
+"""Benchmark: iterated FP64 Smart Laplacian on one MI355X.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload grid4096|annulus4096|grid1024]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--mode all|single|batch|serve]
+                    [--workload grid4096|annulus4096|grid1024] [--batch-meshes M] [--serve-rates R,...]
 
-A step is one complete smoothing job through the C ABI
-(``smooth_mesh_device``): validation, Hilbert reordering, relabelling, fan
-build, 100 Jacobi sweeps with the convergence test fused, un-permuting --
-from device-resident inputs to device-resident output.  Each step starts from
-the same input coordinates (a device copy, inside the timed region).
+Headline (``value``): one step is one complete smoothing job through the C
+ABI (``smooth_mesh_device``) on a 4096 x 4096 jittered grid (16.8M nodes,
+33.5M triangles, random diagonals, +-0.4h jitter): validation, Hilbert
+reordering, tile build, 100 Jacobi sweeps with the convergence test fused,
+un-permuting -- from device-resident inputs to device-resident output.  Each
+step starts from the same input coordinates (a device copy, inside the timed
+region).  value = free nodes x sweeps x K / elapsed wall time.
 
-value: node-updates/s = free nodes x sweeps x K / elapsed wall time.
 roofline: the sweep kernel (the dominant kernel), algorithmic bytes per
 launch (sum over free nodes of 36 + 4 d_i + 2 t_i) / its mean duration from
 HIP events on the library's stream, against 8 TB/s.
-cpu_baseline: the FP64 oracle, all host threads, on whole sweeps of the same
-mesh for about 10 s.
+
+batched: M independent jittered grids (side log-uniform in [24, 450],
+random diagonals, +-0.35h, seeds 10000 + m), 50 sweeps each, smoothed by one
+``sl_batch_smooth`` call (one work list, hipGraph-replayed sweep loop) and,
+for comparison, by M plain ``smooth_mesh`` calls one after another.  Both
+take host arrays in and give host arrays out.
+
+serving: Poisson arrivals at each rate of smoothing requests (side
+log-uniform in [32, 2048], random diagonals, +-0.4h; half of the requests
+run 10-200 sweeps, half run to a 1e-8 displacement tolerance with a 1000-sweep
+cap) submitted to the continuous-batching server; latency is completion time
+minus submission time.  The same arrival sequence is also served by a plain
+loop that runs one ``smooth_mesh`` call at a time in arrival order.
+
+cpu_baseline: the FP64 oracle, all host threads, on whole sweeps of the
+headline mesh for about 10 s.
 """
 from __future__ import annotations
 
 import argparse
 import json
+import math
 import os
+import queue
 import sys
+import threading
 import time
+from concurrent.futures import ThreadPoolExecutor
 
 import numpy as np
 
@@ -30,6 +50,11 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 SWEEP_KERNELS = {1: "k_sweep", 2: "k_sweep_tile"}
+GEN_THREADS = 8
+
+
+def log(msg):
+    print("# " + msg, file=sys.stderr, flush=True)
 
 
 def workload(name: str):
@@ -98,27 +123,7 @@ def cpu_baseline(m, seconds: float = 10.0):
             "sample": "%d whole Jacobi sweeps of %s (%d free nodes) in %.1f s" % (sweeps, m.name, free, el)}
 
 
-def main():
-    ap = argparse.ArgumentParser()
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=5)
-    ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="grid4096")
-    ap.add_argument("--layout", default="aos")
-    ap.add_argument("--reorder", default="hilbert")
-    ap.add_argument("--kernel", default="auto")
-    ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-seconds", type=float, default=10.0)
-    args = ap.parse_args()
-    if args.gpus != 1:
-        print("bench.py measures one GPU only: this build runs the smoothing path on a single MI355X; "
-              "run with --gpus 1", file=sys.stderr)
-        sys.exit(2)
-
-    import torch
-    import paper_1502_00355_amd as sl
-
-    torch.cuda.set_device(0)
+def run_single(args, sl, torch):
     m, iters = workload(args.workload)
     free = m.n_interior
     alg_bytes = algorithmic_bytes(m)
@@ -126,8 +131,8 @@ def main():
     X0 = dev[0].clone()
     work = torch.empty_like(X0)
     stream = torch.cuda.current_stream()
-    print("# workload %s: %d nodes, %d free, %d sweeps/step, alg bytes/sweep %d" %
-          (m.name, m.n_nodes, free, iters, alg_bytes), file=sys.stderr, flush=True)
+    log("workload %s: %d nodes, %d free, %d sweeps/step, alg bytes/sweep %d" %
+        (m.name, m.n_nodes, free, iters, alg_bytes))
 
     def step():
         work.copy_(X0)
@@ -136,7 +141,7 @@ def main():
 
     for w in range(args.warmup):
         r = step()
-        print("# warmup %d: setup %.2f ms, sweeps %.2f ms" % (w, r.setup_ms, r.sweep_ms), file=sys.stderr, flush=True)
+        log("warmup %d: setup %.2f ms, sweeps %.2f ms" % (w, r.setup_ms, r.sweep_ms))
     torch.cuda.synchronize()
     sweep_ms, setup_ms = [], []
     t0 = time.perf_counter()
@@ -147,19 +152,17 @@ def main():
         assert r.iterations_run == iters
     torch.cuda.synchronize()
     el = time.perf_counter() - t0
-    ms_per_step = el * 1e3 / args.steps
-    value = free * iters * args.steps / el
+    log("timed %d steps in %.3f s" % (args.steps, el))
     avg_sweep_s = float(np.mean(sweep_ms)) / 1e3 / iters
     achieved = alg_bytes / avg_sweep_s / 1e9
-    traffic = traffic_from_profile(kernel_source_hash())
     out = {
         "metric": "node-updates/s",
-        "value": value,
+        "value": free * iters * args.steps / el,
         "unit": "node-updates/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": ms_per_step,
+        "ms_per_step": el * 1e3 / args.steps,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -173,12 +176,198 @@ def main():
         "setup_ms_per_step": float(np.mean(setup_ms)),
         "hbm_gbs_algorithmic": achieved,
         "hbm_pct_peak": 100.0 * achieved / HBM_PEAK_GBS,
-        "roofline": {"bound": "hbm", "kernel": SWEEP_KERNELS.get(r.kernel_used, "?"), "achieved": achieved, "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": traffic, "alg_bytes_per_launch": alg_bytes},
+        "roofline": {"bound": "hbm", "kernel": SWEEP_KERNELS.get(r.kernel_used, "?"), "achieved": achieved,
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": traffic_from_profile(kernel_source_hash()), "alg_bytes_per_launch": alg_bytes},
     }
-    if not args.no_cpu_baseline:
-        print("# cpu baseline (oracle) ...", file=sys.stderr, flush=True)
+    return out, m
+
+
+def gen_meshes(specs):
+    """specs: list of (side, diag, jitter, seed); generated on host threads."""
+    import meshgen
+    with ThreadPoolExecutor(GEN_THREADS) as ex:
+        return list(ex.map(lambda s: meshgen.make_grid(int(s[0]), s[1], s[2], int(s[3])), specs))
+
+
+def run_batch(args, sl):
+    """Batched (one sl_batch_smooth call) against plain per-mesh calls."""
+    import meshgen
+    M, iters = args.batch_meshes, 50
+    sides = meshgen.batch_sides(M, 24, 450, 10000)
+    t = time.perf_counter()
+    meshes = gen_meshes([(s, "random", 0.35, 10000 + i) for i, s in enumerate(sides)])
+    free = sum(m.n_interior for m in meshes)
+    nodes = sum(m.n_nodes for m in meshes)
+    log("batch: %d meshes, %d nodes, %d free, generated in %.1f s" % (M, nodes, free, time.perf_counter() - t))
+    sl.batch_smooth(meshes[: min(M, 8)], iters)          # warm-up (code objects, memory pool)
+    t = time.perf_counter()
+    _, reps, br = sl.batch_smooth(meshes, iters)
+    el_b = time.perf_counter() - t
+    assert all(r.iterations_run == iters for r in reps)
+    log("batched: %.3f s (setup %.1f ms, sweeps %.1f ms)" % (el_b, br.setup_ms, br.sweep_ms))
+    plain_sweep_ms = 0.0
+    t = time.perf_counter()
+    for m in meshes:
+        _, rep, _ = sl.smooth_mesh(m.coords, m.nbr_ptr, m.nbr_idx, m.tri_ptr, m.tri_idx, m.tris, m.boundary, iters)
+        plain_sweep_ms += rep.sweep_ms
+    el_p = time.perf_counter() - t
+    log("plain: %.3f s (sweeps %.1f ms)" % (el_p, plain_sweep_ms))
+    upd = free * iters
+    return {
+        "workload": "batch%d_grids_side24-450_random_j0.35_seeds10000+" % M,
+        "meshes": M, "nodes": nodes, "free_nodes": free, "sweeps": iters,
+        "batched_node_updates_per_s": upd / el_b, "batched_s": el_b,
+        "batched_setup_ms": br.setup_ms, "batched_sweep_ms": br.sweep_ms,
+        "batched_sweep_node_updates_per_s": upd / (br.sweep_ms / 1e3),
+        "plain_node_updates_per_s": upd / el_p, "plain_s": el_p, "plain_sweep_ms": plain_sweep_ms,
+        "plain_sweep_node_updates_per_s": upd / (plain_sweep_ms / 1e3),
+        "speedup_whole_job": el_p / el_b, "speedup_sweeps": plain_sweep_ms / br.sweep_ms,
+        "tiles": br.tiles, "graph_used": bool(br.graph_used),
+    }
+
+
+def serve_requests(rate, count, pool, rng):
+    """(arrival offsets, pool index, iterations, tol) for one Poisson run."""
+    gaps = rng.exponential(1.0 / rate, size=count)
+    arr = np.cumsum(gaps) - gaps[0]
+    reqs = []
+    for k in range(count):
+        idx = int(rng.integers(len(pool)))
+        if rng.random() < 0.5:
+            reqs.append((float(arr[k]), idx, int(rng.integers(10, 201)), 0.0))
+        else:
+            reqs.append((float(arr[k]), idx, 1000, 1e-8))
+    return reqs
+
+
+def _pct(v, p):
+    return float(np.percentile(np.asarray(v), p)) * 1e3 if len(v) else None
+
+
+def serve_server(sl, pool, reqs):
+    with sl.Server() as S:
+        t0 = time.perf_counter()
+        ids = []
+        for (at, idx, it, tol) in reqs:
+            d = t0 + at - time.perf_counter()
+            if d > 0:
+                time.sleep(d)
+            m = pool[idx]
+            ids.append(S.submit(m, it, tol))
+        lat, upd = [], 0
+        first, last = None, None
+        for rid, (at, idx, it, tol) in zip(ids, reqs):
+            r = S.wait(rid, timeout=300.0)
+            if r.status != sl.SL_OK:
+                raise RuntimeError("request failed: " + r.message)
+            lat.append(r.times.done_s - r.times.submitted_s)
+            upd += pool[idx].n_interior * r.report.iterations_run
+            first = r.times.submitted_s if first is None else min(first, r.times.submitted_s)
+            last = r.times.done_s if last is None else max(last, r.times.done_s)
+        st = S.stats()
+    return lat, upd, last - first, st
+
+
+def serve_plain(sl, pool, reqs):
+    """One smooth_mesh call at a time, in arrival order."""
+    q = queue.Queue()
+    lat = [None] * len(reqs)
+    upd = [0]
+    t0 = time.perf_counter()
+
+    def worker():
+        while True:
+            item = q.get()
+            if item is None:
+                return
+            k, t_sub = item
+            at, idx, it, tol = reqs[k]
+            m = pool[idx]
+            _, rep, _ = sl.smooth_mesh(m.coords, m.nbr_ptr, m.nbr_idx, m.tri_ptr, m.tri_idx, m.tris, m.boundary, it, tol)
+            lat[k] = time.perf_counter() - t_sub
+            upd[0] += m.n_interior * rep.iterations_run
+
+    th = threading.Thread(target=worker)
+    th.start()
+    for k, (at, idx, it, tol) in enumerate(reqs):
+        d = t0 + at - time.perf_counter()
+        if d > 0:
+            time.sleep(d)
+        q.put((k, time.perf_counter()))
+    q.put(None)
+    th.join()
+    return lat, upd[0], time.perf_counter() - t0
+
+
+def run_serve(args, sl):
+    import meshgen
+    P = args.serve_pool
+    sides = meshgen.batch_sides(P, 32, 2048, 20000)
+    t = time.perf_counter()
+    pool = gen_meshes([(s, "random", 0.4, 20000 + i) for i, s in enumerate(sides)])
+    log("serve: pool of %d meshes (%d nodes in total) generated in %.1f s" %
+        (P, sum(m.n_nodes for m in pool), time.perf_counter() - t))
+    rng = np.random.Generator(np.random.PCG64(30000))
+    rates = [float(r) for r in args.serve_rates.split(",") if r]
+    # warm-up: one small request through each path
+    small = min(range(P), key=lambda i: pool[i].n_nodes)
+    serve_server(sl, pool, [(0.0, small, 10, 0.0)])
+    serve_plain(sl, pool, [(0.0, small, 10, 0.0)])
+    rows = []
+    for rate in rates:
+        count = int(min(args.serve_max_requests, max(30, rate * args.serve_seconds)))
+        reqs = serve_requests(rate, count, pool, rng)
+        lat, upd, span, st = serve_server(sl, pool, reqs)
+        log("serve rate %g: %d requests, server p50 %.1f ms p99 %.1f ms, %.3g node-updates/s" %
+            (rate, count, _pct(lat, 50), _pct(lat, 99), upd / span))
+        plat, pupd, pspan = serve_plain(sl, pool, reqs)
+        log("serve rate %g: plain p50 %.1f ms p99 %.1f ms, %.3g node-updates/s" %
+            (rate, _pct(plat, 50), _pct(plat, 99), pupd / pspan))
+        rows.append({"rate_req_per_s": rate, "requests": count,
+                     "p50_ms": _pct(lat, 50), "p99_ms": _pct(lat, 99), "node_updates_per_s": upd / span,
+                     "plain_p50_ms": _pct(plat, 50), "plain_p99_ms": _pct(plat, 99),
+                     "plain_node_updates_per_s": pupd / pspan, "server_steps": st.steps})
+    return {"workload": "serve_grids_side32-2048_random_j0.4_pool%d" % P,
+            "requests_mix": "half 10-200 sweeps, half tol 1e-8 (cap 1000)", "rates": rows}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--mode", default="all", choices=["all", "single", "batch", "serve"])
+    ap.add_argument("--workload", default="grid4096")
+    ap.add_argument("--layout", default="aos")
+    ap.add_argument("--reorder", default="hilbert")
+    ap.add_argument("--kernel", default="auto")
+    ap.add_argument("--batch-meshes", type=int, default=1000)
+    ap.add_argument("--serve-rates", default="10,100,1000,2000")
+    ap.add_argument("--serve-pool", type=int, default=48)
+    ap.add_argument("--serve-seconds", type=float, default=3.0)
+    ap.add_argument("--serve-max-requests", type=int, default=300)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=10.0)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: this build runs the smoothing path on a single MI355X; "
+              "run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_1502_00355_amd as sl
+
+    torch.cuda.set_device(0)
+    out, m = {}, None
+    if args.mode in ("all", "single"):
+        out, m = run_single(args, sl, torch)
+    if args.mode in ("all", "batch"):
+        out["batched"] = run_batch(args, sl)
+    if args.mode in ("all", "serve"):
+        out["serving"] = run_serve(args, sl)
+    if m is not None and not args.no_cpu_baseline:
+        log("cpu baseline (oracle) ...")
         out["cpu_baseline"] = cpu_baseline(m, args.cpu_seconds)
     print(json.dumps(out), flush=True)
 

@@ -50,7 +50,8 @@ extern "C" {
 typedef enum {
     SL_OK = 0,
     SL_EINVAL = -1,    /* null pointer, size <= 0, non-monotone ptr, index out of range,
-                          iterations < 0, non-finite coordinate, bad option value */
+                          iterations < 0, coordinate not finite or of magnitude >= 2^500
+                          (so that no squared length overflows), bad option value */
     SL_ETOPO = -2,     /* self neighbour, triangle with a repeated vertex, incident triangle
                           not containing its node, a vertex of an incident triangle missing
                           from the node's neighbour row, free node without neighbours,
@@ -83,6 +84,12 @@ typedef struct {
     int32_t reorder;     /* sl_reorder: node order used on the device; results do not depend on it */
     int32_t block_size;  /* node kernel work-group size: 0 = automatic, else 64/128/256 */
     int32_t kernel;      /* sl_kernel; results do not depend on it */
+    int32_t tile_nodes;      /* free nodes per tile on the tile path: 0 = automatic (the value
+                              * sl_autotune chose on this device, else 512), or 256 or 512;
+                              * results do not depend on it */
+    int32_t tile_wg_per_cu;  /* tile-kernel work-groups per compute unit: 0 = automatic (the
+                              * value sl_autotune chose, else as many as fit, at most 4), or
+                              * 1..8, capped by what fits in LDS; results do not depend on it */
     /* Optional accept flags, nullable.  Size iterations * ((n_nodes + 7) / 8)
      * bytes; sweep k occupies bytes [k*((n+7)/8), (k+1)*((n+7)/8)); bit (i % 8)
      * of byte (i / 8) is 1 iff free node i accepted its move in sweep k
@@ -182,6 +189,39 @@ typedef struct {
  */
 SL_API sl_status sl_batch_smooth(const sl_mesh_desc* meshes, int32_t n_meshes, int32_t iterations, double tol,
                                  const sl_options* opts, sl_report* reports, sl_batch_report* batch);
+
+/* ---- autotuning ---------------------------------------------------------
+ * The launch shape of the tile kernel -- free nodes per tile (256 or 512)
+ * and work-groups per compute unit -- changes only speed, never results.
+ * sl_autotune times sweeps of every candidate shape on the caller's meshes
+ * (a deterministic sample of them, taken at a stride in index order, of at
+ * most about 8M nodes) and keeps the fastest as the automatic choice of the
+ * current device for the rest of the process: later calls whose options
+ * leave tile_nodes / tile_wg_per_cu at 0 use it.  Form B (coloured) runs on
+ * the node kernel; for it the node-kernel work-group size is tuned and used
+ * where block_size is 0.  Meshes are read, not written.  The caller's opts
+ * give form, accept and layout; their tile fields are ignored.
+ * out: nullable.  Thread-safe; a later call replaces the device's choice. */
+typedef struct {
+    int32_t tile_nodes;          /* chosen, 0 if no sampled mesh fits the tile path */
+    int32_t tile_wg_per_cu;      /* chosen */
+    int32_t block_size;          /* chosen node-kernel work-group size (Form B), else 0 */
+    int32_t n_candidates;        /* entries of the table below that were timed */
+    struct {
+        int32_t tile_nodes;      /* 0 for a node-kernel candidate */
+        int32_t wg_per_cu;       /* or the node-kernel work-group size */
+        double ns_per_update;    /* device time per free-node update */
+    } candidates[16];
+    int32_t sampled_meshes;
+    int64_t sampled_free_nodes;
+    double tune_ms;              /* host wall time of the call */
+} sl_tuning;
+
+SL_API sl_status sl_autotune(const sl_mesh_desc* meshes, int32_t n_meshes, const sl_options* opts, sl_tuning* out);
+
+/* Forgets the current device's tuned choice (automatic values revert to the
+ * built-in defaults). */
+SL_API void sl_autotune_reset(void);
 
 /* ---- serving ----------------------------------------------------------
  * A server takes smoothing requests as they arrive and sweeps the admitted

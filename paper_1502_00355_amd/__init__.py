@@ -37,7 +37,7 @@ class SmartlapError(RuntimeError):
 class Options(ctypes.Structure):
     _fields_ = [("form", ctypes.c_int32), ("accept", ctypes.c_int32), ("layout", ctypes.c_int32),
                 ("reorder", ctypes.c_int32), ("block_size", ctypes.c_int32), ("kernel", ctypes.c_int32),
-                ("flags_out", ctypes.c_void_p)]
+                ("tile_nodes", ctypes.c_int32), ("tile_wg_per_cu", ctypes.c_int32), ("flags_out", ctypes.c_void_p)]
 
 
 class Report(ctypes.Structure):
@@ -63,6 +63,24 @@ class BatchReport(ctypes.Structure):
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+class TuneCandidate(ctypes.Structure):
+    _fields_ = [("tile_nodes", ctypes.c_int32), ("wg_per_cu", ctypes.c_int32), ("ns_per_update", ctypes.c_double)]
+
+
+class Tuning(ctypes.Structure):
+    _fields_ = [("tile_nodes", ctypes.c_int32), ("tile_wg_per_cu", ctypes.c_int32), ("block_size", ctypes.c_int32),
+                ("n_candidates", ctypes.c_int32), ("candidates", TuneCandidate * 16),
+                ("sampled_meshes", ctypes.c_int32), ("sampled_free_nodes", ctypes.c_int64),
+                ("tune_ms", ctypes.c_double)]
+
+    def as_dict(self):
+        return {"tile_nodes": self.tile_nodes, "tile_wg_per_cu": self.tile_wg_per_cu, "block_size": self.block_size,
+                "candidates": [(c.tile_nodes, c.wg_per_cu, c.ns_per_update)
+                               for c in self.candidates[: self.n_candidates]],
+                "sampled_meshes": self.sampled_meshes, "sampled_free_nodes": self.sampled_free_nodes,
+                "tune_ms": self.tune_ms}
 
 
 class ServerConfig(ctypes.Structure):
@@ -110,6 +128,10 @@ def lib():
         L.sl_batch_smooth.argtypes = [ctypes.POINTER(MeshDesc), i32, i32, d, ctypes.POINTER(Options),
                                       ctypes.POINTER(Report), ctypes.POINTER(BatchReport)]
         L.sl_batch_smooth.restype = ctypes.c_int
+        L.sl_autotune.argtypes = [ctypes.POINTER(MeshDesc), i32, ctypes.POINTER(Options), ctypes.POINTER(Tuning)]
+        L.sl_autotune.restype = ctypes.c_int
+        L.sl_autotune_reset.argtypes = []
+        L.sl_autotune_reset.restype = None
         L.sl_server_config_default.argtypes = [ctypes.POINTER(ServerConfig)]
         L.sl_server_config_default.restype = None
         L.sl_server_create.argtypes = [ctypes.POINTER(ServerConfig), ctypes.POINTER(Options), ctypes.POINTER(p)]
@@ -134,7 +156,7 @@ def _check(status: int):
 
 
 def make_options(form="jacobi", accept="ge", layout="aos", reorder="hilbert", block_size=0, kernel="auto",
-                 flags_ptr=None):
+                 tile_nodes=0, tile_wg_per_cu=0, flags_ptr=None):
     o = Options()
     lib().sl_options_default(ctypes.byref(o))
     o.form = FORMS[form] if isinstance(form, str) else int(form)
@@ -143,6 +165,8 @@ def make_options(form="jacobi", accept="ge", layout="aos", reorder="hilbert", bl
     o.reorder = REORDER[reorder] if isinstance(reorder, str) else int(reorder)
     o.block_size = int(block_size)
     o.kernel = KERNELS[kernel] if isinstance(kernel, str) else int(kernel)
+    o.tile_nodes = int(tile_nodes)
+    o.tile_wg_per_cu = int(tile_wg_per_cu)
     o.flags_out = flags_ptr
     return o
 
@@ -194,9 +218,12 @@ def smooth_mesh_device(coords, nbr_ptr, nbr_idx, tri_ptr, tri_idx, tris, boundar
     return rep
 
 
-def _desc(mesh):
-    """(MeshDesc, arrays kept alive) for a host mesh; coords copied (output)."""
-    X = _c(mesh.coords, np.float64).copy()
+def _desc(mesh, copy_coords=True):
+    """(MeshDesc, arrays kept alive) for a host mesh; coords copied (output)
+    unless copy_coords is False (read-only use)."""
+    X = _c(mesh.coords, np.float64)
+    if copy_coords:
+        X = X.copy()
     keep = [X] + [_c(getattr(mesh, f), np.int32) for f in ("nbr_ptr", "nbr_idx", "tri_ptr", "tri_idx")]
     tr = _c(mesh.tris, np.int32).reshape(-1)
     b = _c(mesh.boundary, np.uint8)
@@ -217,6 +244,21 @@ def batch_smooth(meshes, iterations: int, tol: float = 0.0, **opts):
     st = lib().sl_batch_smooth(arr, len(descs), int(iterations), float(tol), ctypes.byref(o), reps, ctypes.byref(br))
     _check(st)
     return [k[0] for k in keeps], list(reps), br
+
+
+def autotune(meshes, **opts) -> Tuning:
+    """Times the sweep launch shapes on (a sample of) these host meshes and
+    makes the fastest the device's automatic choice (sl_autotune)."""
+    descs, keeps = zip(*[_desc(m, copy_coords=False) for m in meshes])
+    arr = (MeshDesc * len(descs))(*descs)
+    t = Tuning()
+    o = make_options(**opts)
+    _check(lib().sl_autotune(arr, len(descs), ctypes.byref(o), ctypes.byref(t)))
+    return t
+
+
+def autotune_reset():
+    lib().sl_autotune_reset()
 
 
 class RequestResult:

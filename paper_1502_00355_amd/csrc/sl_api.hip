@@ -13,7 +13,53 @@ namespace sl {
 namespace {
 thread_local std::string g_last_error;
 std::once_flag g_pool_once[64];
+std::mutex g_tune_mu;
+TunedShape g_tuned[64];
+
+int current_device()
+{
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return -1;
+    return dev;
+}
 }  // namespace
+
+TunedShape tuned_shape()
+{
+    const int dev = current_device();
+    if (dev < 0) return TunedShape{0, 0, 0};
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    return g_tuned[dev];
+}
+
+void set_tuned_shape(const TunedShape& t)
+{
+    const int dev = current_device();
+    if (dev < 0) return;
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_tuned[dev] = t;
+}
+
+void clear_tuned_shape() { set_tuned_shape(TunedShape{0, 0, 0}); }
+
+int32_t resolve_tile_nodes(const sl_options& o)
+{
+    if (o.tile_nodes) return o.tile_nodes;
+    const TunedShape t = tuned_shape();
+    return t.tile_nodes ? t.tile_nodes : 512;
+}
+
+int32_t resolve_wg_per_cu(const sl_options& o)
+{
+    if (o.tile_wg_per_cu) return o.tile_wg_per_cu;
+    return tuned_shape().wg_per_cu;
+}
+
+int32_t resolve_block_size(const sl_options& o)
+{
+    if (o.block_size) return o.block_size;
+    return tuned_shape().block_size;
+}
 
 // Freed device memory stays in the stream-ordered pool for the next call.
 void keep_pool_warm()
@@ -39,6 +85,9 @@ sl_status check_options(const sl_options& o)
         return fail(SL_EINVAL, "block_size must be 0, 64, 128 or 256");
     if (o.kernel != SL_KERNEL_AUTO && o.kernel != SL_KERNEL_NODE && o.kernel != SL_KERNEL_TILE)
         return fail(SL_EINVAL, "unknown kernel");
+    if (o.tile_nodes != 0 && o.tile_nodes != 256 && o.tile_nodes != 512)
+        return fail(SL_EINVAL, "tile_nodes must be 0, 256 or 512");
+    if (o.tile_wg_per_cu < 0 || o.tile_wg_per_cu > 8) return fail(SL_EINVAL, "tile_wg_per_cu must be in 0..8");
     return SL_OK;
 }
 
@@ -66,6 +115,8 @@ sl_status prepare_mesh(const MeshInput& in, const sl_options& o, int32_t mesh_in
 
 namespace {
 
+constexpr int32_t kSweepChunk = 32;   // even
+
 // Everything a call allocates, released on every exit path.
 struct CallState {
     hipStream_t st = nullptr;
@@ -73,12 +124,16 @@ struct CallState {
     MeshState* state = nullptr;
     uint64_t* bits = nullptr;
     hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
     ~CallState()
     {
         devmesh_free(m, st);
         dfree(state, st);
         dfree(bits, st);
         (void)hipStreamSynchronize(st);
+        if (exec) (void)hipGraphExecDestroy(exec);
+        if (graph) (void)hipGraphDestroy(graph);
         for (auto& e : ev)
             if (e) (void)hipEventDestroy(e);
     }
@@ -119,14 +174,50 @@ sl_status run_device(double* coords, int32_t n, const int32_t* nbr_ptr, const in
         if ((r = dalloc(&cs.bits, static_cast<size_t>(words) * its, stream))) return r;
         SL_HIP(hipMemsetAsync(cs.bits, 0, sizeof(uint64_t) * words * its, stream));
     }
-    TileLaunch L{cs.m.work, cs.m.n_tiles, cs.m.tile_nodes, cs.m.halo_max, cs.m.rows_max, o.layout, o.accept, cs.state};
-
-    SL_HIP(hipEventRecord(cs.ev[2], stream));
-    for (int32_t s = 0; s < its; ++s) {
+    const bool tiles = o.form == SL_JACOBI && cs.m.tile_nodes > 0;
+    const int32_t block = resolve_block_size(o);
+    // with a tolerance, a launch on a converged mesh returns at once
+    const TileLaunch L{cs.m.work, cs.m.n_tiles, cs.m.tile_nodes, cs.m.halo_max, cs.m.rows_max, o.layout, o.accept,
+                       cs.state, resolve_wg_per_cu(o), tol2 > 0.0 ? 1 : 0};
+    auto enqueue = [&](int32_t s) -> sl_status {
         uint64_t* bits = cs.bits ? cs.bits + static_cast<int64_t>(s) * words : nullptr;
-        if (o.form == SL_JACOBI && cs.m.tile_nodes > 0) r = launch_sweep_tiles(L, s & 1, bits, stream);
-        else r = launch_sweep_nodes(cs.m, s & 1, o.form, o.accept, o.block_size, cs.state, bits, stream);
-        if (r || (r = launch_advance(cs.state, 1, stream))) return r;
+        sl_status rr = tiles ? launch_sweep_tiles(L, s & 1, bits, stream)
+                             : launch_sweep_nodes(cs.m, s & 1, o.form, o.accept, block, cs.state, bits, stream);
+        return rr ? rr : launch_advance(cs.state, 1, stream);
+    };
+
+    // The sweep loop runs in chunks of kSweepChunk sweeps; a whole chunk is
+    // one replay of a captured HIP graph (the chunk is even, so the buffer
+    // parity of sweep s is s & 1 in every replay).  With a tolerance the host
+    // reads the sweep state after each chunk and stops launching once the
+    // mesh has converged.  Flag output takes per-sweep pointers, so it runs
+    // without the graph.
+    SL_HIP(hipEventRecord(cs.ev[2], stream));
+    const bool use_graph = !cs.bits && its >= 2 * kSweepChunk;
+    if (use_graph) {
+        SL_HIP(hipStreamBeginCapture(stream, hipStreamCaptureModeThreadLocal));
+        sl_status cr = SL_OK;
+        for (int32_t s = 0; s < kSweepChunk && !cr; ++s) cr = enqueue(s);
+        const hipError_t ce = hipStreamEndCapture(stream, &cs.graph);
+        if (cr) return cr;
+        if (ce != hipSuccess) return fail(SL_EDEVICE, std::string("graph capture failed: ") + hipGetErrorString(ce));
+        SL_HIP(hipGraphInstantiate(&cs.exec, cs.graph, nullptr, nullptr, 0));
+    }
+    for (int32_t done = 0; done < its;) {
+        const int32_t c = std::min(kSweepChunk, its - done);
+        if (use_graph && c == kSweepChunk) {
+            SL_HIP(hipGraphLaunch(cs.exec, stream));
+        } else {
+            for (int32_t s = done; s < done + c; ++s)
+                if ((r = enqueue(s))) return r;
+        }
+        done += c;
+        if (tol2 > 0.0 && done < its) {
+            MeshState cur{};
+            SL_HIP(hipMemcpyAsync(&cur, cs.state, sizeof(MeshState), hipMemcpyDeviceToHost, stream));
+            SL_HIP(hipStreamSynchronize(stream));
+            if (!cur.active) break;
+        }
     }
     SL_HIP(hipEventRecord(cs.ev[3], stream));
 
@@ -219,7 +310,8 @@ sl_status smooth_mesh(double* coords, int32_t n_nodes, const int32_t* nbr_ptr, c
     sl_options o;
     sl_options_default(&o);
     if (opts) o = *opts;
-    sl_status r = SL_OK;
+    sl_status r = check_options(o);
+    if (r) return r;
     hipStream_t st = nullptr;
     SL_HIP(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
     const size_t n = static_cast<size_t>(n_nodes);

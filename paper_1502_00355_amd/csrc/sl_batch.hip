@@ -1,16 +1,20 @@
 // Batched Smart Laplacian: many meshes of uneven size swept together.
 //
 // Every mesh is set up on the device as for a single call (validation,
-// Hilbert order, tiles); the tile descriptors of all meshes form one work
-// list, so one launch of the tile kernel sweeps every mesh once, and the
-// whole sweep loop (tile launches plus the per-mesh state update) is
-// captured once in a HIP graph and replayed.  Meshes that do not fit the
-// tile path, and the coloured form, are swept mesh by mesh on the node path
-// inside the same graph.
+// Hilbert order, tiles); setups run on a few host threads, each with a
+// stream of its own, so the short kernels and host round trips of small
+// meshes overlap.  The tile descriptors of all meshes form one work list,
+// so one launch of the tile kernel sweeps every mesh once, and the whole
+// sweep loop (tile launches plus the per-mesh state update) is captured once
+// in a HIP graph and replayed.  Meshes that do not fit the tile path, and
+// the coloured form, are swept mesh by mesh on the node path inside the same
+// graph.
 #include <algorithm>
+#include <atomic>
 #include <chrono>
 #include <cstring>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "sl_common.h"
@@ -19,8 +23,12 @@ namespace sl {
 
 namespace {
 
+constexpr int32_t kSetupThreads = 8;
+constexpr size_t kOutGroupValues = size_t(1) << 27;   // un-permute staging: 1 GiB of doubles
+
 struct BatchState {
     hipStream_t st = nullptr;
+    std::vector<hipStream_t> setup_st;
     std::vector<DevMesh> meshes;
     TileWork* work = nullptr;
     MeshState* states = nullptr;
@@ -35,6 +43,8 @@ struct BatchState {
         dfree(states, st);
         dfree(out, st);
         (void)hipStreamSynchronize(st);
+        for (auto s : setup_st)
+            if (s) (void)hipStreamDestroy(s);
         if (exec) (void)hipGraphExecDestroy(exec);
         if (graph) (void)hipGraphDestroy(graph);
         for (auto& e : ev)
@@ -42,9 +52,9 @@ struct BatchState {
     }
 };
 
-// Uploads one caller mesh (host arrays) and prepares it; the uploaded
-// inputs are freed once the device copy is built.
-sl_status upload_and_prepare(const sl_mesh_desc& d, const sl_options& o, int32_t index, DevMesh& m, hipStream_t st)
+}  // namespace
+
+sl_status upload_and_prepare(const sl_mesh_desc& d, const sl_options& o, int32_t mesh, DevMesh& m, hipStream_t st)
 {
     if (!d.coords || !d.nbr_ptr || !d.tri_ptr || !d.boundary) return fail(SL_EINVAL, "null array argument");
     if (d.n_nodes <= 0) return fail(SL_EINVAL, "n_nodes must be >= 1");
@@ -83,12 +93,10 @@ sl_status upload_and_prepare(const sl_mesh_desc& d, const sl_options& o, int32_t
         return fail(SL_EDEVICE, std::string("host to device copy failed: ") + hipGetErrorString(e));
     }
     MeshInput in{c, d.n_nodes, np, ni, tp, ti, tr, d.n_tris, b};
-    r = prepare_mesh(in, o, index, m, st);
+    r = prepare_mesh(in, o, mesh, m, st);
     cleanup();
     return r;
 }
-
-}  // namespace
 
 }  // namespace sl
 
@@ -108,27 +116,72 @@ sl_status sl_batch_smooth(const sl_mesh_desc* meshes, int32_t n_meshes, int32_t 
     o.flags_out = nullptr;
     sl_status r = check_options(o);
     if (r) return r;
+    // automatic launch shapes are fixed once for the whole batch: every
+    // mesh of one work list has the same tile size
+    o.tile_nodes = resolve_tile_nodes(o);
+    o.tile_wg_per_cu = resolve_wg_per_cu(o);
+    o.block_size = resolve_block_size(o);
     keep_pool_warm();
 
     BatchState bs;
     SL_HIP(hipStreamCreateWithFlags(&bs.st, hipStreamNonBlocking));
     hipStream_t st = bs.st;
     for (auto& e : bs.ev) SL_HIP(hipEventCreate(&e));
-    SL_HIP(hipEventRecord(bs.ev[0], st));
 
-    // ---- setup, mesh by mesh
+    // ---- setup: meshes taken in index order by a few threads
     bs.meshes.resize(static_cast<size_t>(n_meshes));
+    const int32_t n_threads = std::min(n_meshes, kSetupThreads);
+    bs.setup_st.assign(static_cast<size_t>(n_threads), nullptr);
+    for (auto& s : bs.setup_st) SL_HIP(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
+    int device = 0;
+    SL_HIP(hipGetDevice(&device));
+    std::atomic<int32_t> next{0};
+    std::atomic<bool> failed{false};
+    std::vector<sl_status> t_status(static_cast<size_t>(n_threads), SL_OK);
+    std::vector<std::string> t_msg(static_cast<size_t>(n_threads));
+    auto worker = [&](int32_t t) {
+        hipStream_t ts = bs.setup_st[t];
+        if (hipSetDevice(device) != hipSuccess) {
+            t_status[t] = SL_EDEVICE;
+            t_msg[t] = "hipSetDevice failed in a setup thread";
+            failed.store(true);
+            return;
+        }
+        for (;;) {
+            const int32_t i = next.fetch_add(1);
+            if (i >= n_meshes || failed.load()) break;
+            const sl_status rr = upload_and_prepare(meshes[i], o, i, bs.meshes[i], ts);
+            if (rr) {
+                t_status[t] = rr;
+                t_msg[t] = "mesh " + std::to_string(i) + ": " + sl_last_error();
+                failed.store(true);
+                break;
+            }
+        }
+        if (hipStreamSynchronize(ts) != hipSuccess && !t_status[t]) {
+            t_status[t] = SL_EDEVICE;
+            t_msg[t] = "setup stream failed";
+            failed.store(true);
+        }
+    };
+    {
+        std::vector<std::thread> pool;
+        for (int32_t t = 1; t < n_threads; ++t) pool.emplace_back(worker, t);
+        worker(0);
+        for (auto& th : pool) th.join();
+    }
+    for (int32_t t = 0; t < n_threads; ++t)
+        if (t_status[t]) return fail(t_status[t], t_msg[t]);
+
     int64_t total_tiles = 0;
     int32_t T = 0, halo_cap = 0, rows_cap = 0, on_tiles = 0;
-    size_t max_nodes = 0;
+    size_t max_nodes = 0, sum_nodes = 0;
     for (int32_t i = 0; i < n_meshes; ++i) {
-        if ((r = upload_and_prepare(meshes[i], o, i, bs.meshes[i], st))) {
-            const std::string msg = "mesh " + std::to_string(i) + ": " + sl_last_error();
-            return fail(r, msg);
-        }
         const DevMesh& m = bs.meshes[i];
+        sum_nodes += static_cast<size_t>(m.n);
         max_nodes = std::max(max_nodes, static_cast<size_t>(m.n));
         if (m.tile_nodes > 0) {
+            if (T != 0 && m.tile_nodes != T) return fail(SL_EINVAL, "meshes of one batch with different tile sizes");
             T = m.tile_nodes;
             total_tiles += m.n_tiles;
             halo_cap = std::max(halo_cap, m.halo_max);
@@ -156,11 +209,13 @@ sl_status sl_batch_smooth(const sl_mesh_desc* meshes, int32_t n_meshes, int32_t 
     }
     if ((r = dalloc(&bs.states, static_cast<size_t>(n_meshes), st))) return r;
     SL_HIP(hipMemcpyAsync(bs.states, h0.data(), sizeof(MeshState) * h0.size(), hipMemcpyHostToDevice, st));
-    SL_HIP(hipEventRecord(bs.ev[1], st));
+    SL_HIP(hipStreamSynchronize(st));
+    const double setup_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
 
     // ---- the sweep loop, captured once and replayed
     const TileLaunch L{bs.work, static_cast<int32_t>(total_tiles), T, halo_cap, rows_cap, o.layout, o.accept,
-                       bs.states};
+                       bs.states, resolve_wg_per_cu(o), (n_meshes == 1 && tol2 > 0.0) ? 1 : 0};
+    const int32_t block = resolve_block_size(o);
     const bool jacobi = o.form == SL_JACOBI;
     const int32_t chunk = iterations <= 128 ? iterations + (iterations & 1) : 64;   // even: parity repeats
     auto enqueue_chunk = [&]() -> sl_status {
@@ -170,7 +225,7 @@ sl_status sl_batch_smooth(const sl_mesh_desc* meshes, int32_t n_meshes, int32_t 
             for (int32_t i = 0; i < n_meshes && !rr; ++i) {
                 const DevMesh& m = bs.meshes[i];
                 if (jacobi && m.tile_nodes > 0) continue;
-                rr = launch_sweep_nodes(m, s & 1, o.form, o.accept, o.block_size, bs.states + i, nullptr, st);
+                rr = launch_sweep_nodes(m, s & 1, o.form, o.accept, block, bs.states + i, nullptr, st);
             }
             if (rr || (rr = launch_advance(bs.states, n_meshes, st))) return rr;
         }
@@ -193,22 +248,36 @@ sl_status sl_batch_smooth(const sl_mesh_desc* meshes, int32_t n_meshes, int32_t 
     }
     SL_HIP(hipEventRecord(bs.ev[3], st));
 
-    // ---- results
+    // ---- results: un-permuted into a staging buffer a group of meshes at a
+    // time, then copied to the callers' arrays
     std::vector<MeshState> hs(static_cast<size_t>(n_meshes));
     SL_HIP(hipMemcpyAsync(hs.data(), bs.states, sizeof(MeshState) * hs.size(), hipMemcpyDeviceToHost, st));
-    if ((r = dalloc(&bs.out, 2 * max_nodes, st))) return r;
+    const size_t group_values = std::max(2 * max_nodes, std::min(2 * sum_nodes, kOutGroupValues));
+    if ((r = dalloc(&bs.out, group_values, st))) return r;
     SL_HIP(hipStreamSynchronize(st));
-    float setup_ms = 0.f, sweep_ms = 0.f;
-    SL_HIP(hipEventElapsedTime(&setup_ms, bs.ev[0], bs.ev[1]));
+    float sweep_ms = 0.f;
     SL_HIP(hipEventElapsedTime(&sweep_ms, bs.ev[2], bs.ev[3]));
     int64_t updates = 0;
+    for (int32_t first = 0; first < n_meshes;) {
+        int32_t last = first;
+        size_t used = 0;
+        for (; last < n_meshes && used + 2 * static_cast<size_t>(bs.meshes[last].n) <= group_values; ++last) {
+            const DevMesh& m = bs.meshes[last];
+            const int src = jacobi ? (hs[last].s & 1) : 0;
+            if ((r = unpermute_coords(m, src, bs.out + used, st))) return r;
+            used += 2 * static_cast<size_t>(m.n);
+        }
+        used = 0;
+        for (int32_t i = first; i < last; ++i) {
+            const size_t vals = 2 * static_cast<size_t>(bs.meshes[i].n);
+            SL_HIP(hipMemcpyAsync(meshes[i].coords, bs.out + used, sizeof(double) * vals, hipMemcpyDeviceToHost, st));
+            used += vals;
+        }
+        SL_HIP(hipStreamSynchronize(st));
+        first = last;
+    }
     for (int32_t i = 0; i < n_meshes; ++i) {
         const DevMesh& m = bs.meshes[i];
-        const int src = jacobi ? (hs[i].s & 1) : 0;
-        if ((r = unpermute_coords(m, src, bs.out, st))) return r;
-        SL_HIP(hipMemcpyAsync(meshes[i].coords, bs.out, 2 * sizeof(double) * static_cast<size_t>(m.n),
-                              hipMemcpyDeviceToHost, st));
-        SL_HIP(hipStreamSynchronize(st));
         updates += static_cast<int64_t>(m.n_free) * hs[i].s;
         if (reports) {
             sl_report rep{};

@@ -28,7 +28,7 @@ sl_status fail(sl_status st, const std::string& msg);
 enum : uint32_t {
     VE_PTR = 1u << 0,       // CSR offsets not monotone / out of range          -> EINVAL
     VE_RANGE = 1u << 1,     // node or triangle id out of range                 -> EINVAL
-    VE_COORD = 1u << 2,     // non-finite coordinate                            -> EINVAL
+    VE_COORD = 1u << 2,     // coordinate not finite or |x| >= 2^500            -> EINVAL
     VE_SELF = 1u << 3,      // node lists itself as a neighbour                 -> ETOPO
     VE_TRIREP = 1u << 4,    // triangle with a repeated vertex                  -> ETOPO
     VE_NOTIN = 1u << 5,     // incident triangle does not contain its node      -> ETOPO
@@ -152,6 +152,24 @@ sl_status prepare_mesh(const MeshInput& in, const sl_options& o, int32_t mesh, D
 sl_status check_options(const sl_options& o);
 void keep_pool_warm();
 
+// Uploads one caller mesh (host arrays) on `st` and prepares it; the
+// uploaded inputs are released once the device copy is built.
+sl_status upload_and_prepare(const sl_mesh_desc& d, const sl_options& o, int32_t mesh, DevMesh& m, hipStream_t st);
+
+// Launch shapes that sl_autotune chose for a device (zeros: none chosen).
+struct TunedShape {
+    int32_t tile_nodes, wg_per_cu, block_size;
+};
+TunedShape tuned_shape();                       // of the current device
+void set_tuned_shape(const TunedShape& t);      // for the current device
+void clear_tuned_shape();
+// Option value if set, else the tuned value, else the built-in default
+// (512 nodes per tile; 0 = as many work-groups per CU as fit, at most 4;
+// 0 = node-kernel default block).
+int32_t resolve_tile_nodes(const sl_options& o);
+int32_t resolve_wg_per_cu(const sl_options& o);
+int32_t resolve_block_size(const sl_options& o);
+
 // Writes the positions of buffer `src` back to the caller's layout and order.
 sl_status unpermute_coords(const DevMesh& m, int src, double* coords_out, hipStream_t st);
 
@@ -176,6 +194,8 @@ struct TileLaunch {
     int32_t halo_cap, rows_cap;
     int32_t layout, accept;
     MeshState* states;
+    int32_t wg_per_cu;          // 0: as many as fit, at most 4
+    int32_t exit_if_inactive;   // 1: every tile is of one mesh; a launch on it returns at once once it stops
 };
 sl_status launch_sweep_tiles(const TileLaunch& L, int32_t parity, uint64_t* bits, hipStream_t st);
 
@@ -184,7 +204,7 @@ sl_status launch_sweep_tiles(const TileLaunch& L, int32_t parity, uint64_t* bits
 sl_status launch_advance(MeshState* states, int32_t n, hipStream_t st);
 
 // Work-group count of a tile launch (persistent work-groups, XCD-aware).
-int tile_grid(int n_work, int tile_nodes, int halo_cap, int rows_cap);
+int tile_grid(int n_work, int tile_nodes, int halo_cap, int rows_cap, int wg_per_cu);
 
 // Exclusive scan of n int32 values; out[n] receives the total (out has n+1).
 sl_status scan_exclusive(const int32_t* in, int32_t* out, int64_t n, hipStream_t st);

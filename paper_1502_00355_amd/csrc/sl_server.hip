@@ -11,6 +11,11 @@
 // cancelled or passes its deadline).  A request's arithmetic is that of a
 // single smooth_mesh call: tiles only read their own mesh, so the result does
 // not depend on which requests share its launches.
+//
+// The scheduler launches a step asynchronously and admits queued requests
+// while it runs, until the step has finished; admitted requests join at the
+// start of the next step, when their sweep state is written on the compute
+// stream, so a step never sees a request that is half set up.
 #include <algorithm>
 #include <atomic>
 #include <chrono>
@@ -32,6 +37,8 @@ namespace {
 
 using Clock = std::chrono::steady_clock;
 
+constexpr int32_t kMaxActive = 65536;
+
 double seconds_since(Clock::time_point t0, Clock::time_point t)
 {
     return std::chrono::duration<double>(t - t0).count();
@@ -51,6 +58,8 @@ struct Request {
     bool cancel = false;
     int32_t slot = -1;
     int32_t parity0 = 0;              // launch parity when it joined
+    bool joined = false;              // its sweep state is on the device
+    MeshState state0{};               // the sweep state it joins with
     DevMesh mesh;
     std::vector<double> result;       // n x 2, filled when done
     sl_report report{};
@@ -86,6 +95,8 @@ struct sl_server {
     // scheduler-thread state
     hipStream_t st_compute = nullptr, st_setup = nullptr;
     sl::MeshState* states = nullptr;        // [max_active]
+    sl::MeshState* h_states = nullptr;      // [max_active], pinned: read-back after each step
+    sl::MeshState* h_join = nullptr;        // [max_active], pinned: the state a joining request starts from
     sl::TileWork* work = nullptr;
     int64_t work_cap = 0;
     double* out = nullptr;
@@ -115,60 +126,19 @@ void finish(sl_server* S, Request* q, sl_status status, const std::string& err)
 // server carries on.
 sl_status admit(sl_server* S, Request* q, int32_t slot)
 {
-    sl_options o = S->opts;
-    o.flags_out = nullptr;
-    const sl_mesh_desc& d = q->desc;
-    if (!d.coords || !d.nbr_ptr || !d.tri_ptr || !d.boundary || d.n_nodes <= 0 || d.n_tris < 0 ||
-        (d.n_tris > 0 && !d.tris))
-        return fail(SL_EINVAL, "bad mesh arrays");
-    const size_t n = static_cast<size_t>(d.n_nodes);
-    const int64_t nnz = d.nbr_ptr[n], ninc = d.tri_ptr[n];
-    if (d.nbr_ptr[0] != 0 || d.tri_ptr[0] != 0 || nnz < 0 || ninc < 0) return fail(SL_EINVAL, "bad CSR offsets");
     hipStream_t st = S->st_setup;
-    double* c = nullptr;
-    int32_t *np = nullptr, *ni = nullptr, *tp = nullptr, *ti = nullptr, *tr = nullptr;
-    uint8_t* b = nullptr;
-    auto cleanup = [&] {
-        dfree(c, st); dfree(np, st); dfree(ni, st); dfree(tp, st); dfree(ti, st); dfree(tr, st); dfree(b, st);
-    };
-    sl_status r;
-    if ((r = dalloc(&c, 2 * n, st)) || (r = dalloc(&np, n + 1, st)) || (r = dalloc(&ni, nnz, st)) ||
-        (r = dalloc(&tp, n + 1, st)) || (r = dalloc(&ti, ninc, st)) ||
-        (r = dalloc(&tr, 3 * static_cast<size_t>(d.n_tris), st)) || (r = dalloc(&b, n, st))) {
-        cleanup();
-        return r;
-    }
-    hipError_t e = hipSuccess;
-    auto cp = [&](void* dst, const void* src, size_t bytes) {
-        if (e == hipSuccess && bytes) e = hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, st);
-    };
-    cp(c, d.coords, 2 * n * sizeof(double));
-    cp(np, d.nbr_ptr, (n + 1) * sizeof(int32_t));
-    cp(ni, d.nbr_idx, static_cast<size_t>(nnz) * sizeof(int32_t));
-    cp(tp, d.tri_ptr, (n + 1) * sizeof(int32_t));
-    cp(ti, d.tri_idx, static_cast<size_t>(ninc) * sizeof(int32_t));
-    cp(tr, d.tris, 3 * static_cast<size_t>(d.n_tris) * sizeof(int32_t));
-    cp(b, d.boundary, n);
-    if (e != hipSuccess) {
-        cleanup();
-        return fail(SL_EDEVICE, std::string("host to device copy failed: ") + hipGetErrorString(e));
-    }
-    MeshInput in{c, d.n_nodes, np, ni, tp, ti, tr, d.n_tris, b};
-    r = prepare_mesh(in, o, slot, q->mesh, st);
-    cleanup();
+    const sl_status r = upload_and_prepare(q->desc, S->opts, slot, q->mesh, st);
     if (r) {
         devmesh_free(q->mesh, st);
         return r;
     }
-    // the mesh joins at the current launch parity: both buffers hold its
-    // start positions, so any parity reads them
-    MeshState h{};
+    SL_HIP(hipStreamSynchronize(st));
+    MeshState& h = q->state0;
+    h = MeshState{};
     h.iters = q->iterations;
     h.active = q->iterations > 0;
     h.tol2 = q->tol > 0.0 ? q->tol * q->tol : 0.0;
-    SL_HIP(hipMemcpyAsync(S->states + slot, &h, sizeof(MeshState), hipMemcpyHostToDevice, st));
-    SL_HIP(hipStreamSynchronize(st));
-    q->parity0 = S->parity;
+    q->joined = false;
     return SL_OK;
 }
 
@@ -180,7 +150,7 @@ sl_status rebuild_work(sl_server* S, int32_t* n_work, int32_t* T, int32_t* hcap,
     *hcap = 0;
     *rcap = 0;
     for (Request* q : S->slots)
-        if (q && q->mesh.tile_nodes > 0) total += q->mesh.n_tiles;
+        if (q && q->phase == Request::ACTIVE && q->mesh.tile_nodes > 0) total += q->mesh.n_tiles;
     if (total > INT32_MAX) return fail(SL_ENOMEM, "too many tiles in flight");
     if (total > S->work_cap) {
         dfree(S->work, S->st_compute);
@@ -190,10 +160,11 @@ sl_status rebuild_work(sl_server* S, int32_t* n_work, int32_t* T, int32_t* hcap,
     }
     int64_t off = 0;
     for (Request* q : S->slots) {
-        if (!q || q->mesh.tile_nodes == 0) continue;
+        if (!q || q->phase != Request::ACTIVE || q->mesh.tile_nodes == 0) continue;
         SL_HIP(hipMemcpyAsync(S->work + off, q->mesh.work, sizeof(TileWork) * q->mesh.n_tiles,
                               hipMemcpyDeviceToDevice, S->st_compute));
         off += q->mesh.n_tiles;
+        if (*T != 0 && q->mesh.tile_nodes != *T) return fail(SL_EINVAL, "requests with different tile sizes");
         *T = q->mesh.tile_nodes;
         *hcap = std::max(*hcap, q->mesh.halo_max);
         *rcap = std::max(*rcap, q->mesh.rows_max);
@@ -240,102 +211,131 @@ void release(sl_server* S, Request* q)
     q->slot = -1;
 }
 
+// Takes the head of the queue if it can be admitted now (finishing the
+// requests at the head that are cancelled, past their deadline or too large
+// for the budget); nullptr if the queue is empty or the head must wait.
+Request* pop_admissible(sl_server* S)
+{
+    const int32_t max_active = S->cfg.max_active;
+    while (!S->queue.empty()) {
+        Request* q = S->reqs[S->queue.front()].get();
+        if (q->cancel) {
+            S->queue.pop_front();
+            finish(S, q, SL_ECANCELED, "cancelled before admission");
+            continue;
+        }
+        if (q->deadline_s > 0.0 && seconds_since(S->t0, Clock::now()) > q->deadline_s) {
+            S->queue.pop_front();
+            finish(S, q, SL_ETIMEOUT, "deadline passed before admission");
+            continue;
+        }
+        if (q->footprint > S->cfg.hbm_budget_bytes) {
+            S->queue.pop_front();
+            finish(S, q, SL_ENOMEM, "request cannot fit the HBM budget");
+            continue;
+        }
+        int32_t slot = -1;
+        for (int32_t i = 0; i < max_active; ++i)
+            if (!S->slots[i]) { slot = i; break; }
+        if (slot < 0 || S->hbm_in_use + q->footprint > S->cfg.hbm_budget_bytes) return nullptr;
+        S->queue.pop_front();
+        q->slot = slot;
+        S->slots[slot] = q;
+        S->hbm_in_use += q->footprint;
+        q->times.admitted_s = seconds_since(S->t0, Clock::now());
+        return q;
+    }
+    return nullptr;
+}
+
 void scheduler(sl_server* S)
 {
     (void)hipSetDevice(S->device);
     const int32_t max_active = S->cfg.max_active;
-    std::vector<MeshState> hstate(static_cast<size_t>(max_active));
+    const MeshState* hstate = S->h_states;
     bool work_dirty = true;
     int32_t n_work = 0, T = 0, hcap = 0, rcap = 0;
+    const bool jacobi = S->opts.form == SL_JACOBI;
+    const int32_t wg_per_cu = resolve_wg_per_cu(S->opts), block = resolve_block_size(S->opts);
     while (!S->stop.load()) {
-        // ---- admissions (FIFO: the head waits until it fits)
-        std::vector<Request*> admitted;
-        {
-            std::unique_lock<std::mutex> lk(S->mu);
-            bool idle = true;
-            for (Request* q : S->slots) idle = idle && (q == nullptr);
-            if (idle && S->queue.empty())
-                S->cv.wait_for(lk, std::chrono::milliseconds(50), [&] { return S->stop.load() || !S->queue.empty(); });
-            while (!S->queue.empty()) {
-                Request* q = S->reqs[S->queue.front()].get();
-                if (q->cancel) {
-                    S->queue.pop_front();
-                    finish(S, q, SL_ECANCELED, "cancelled before admission");
-                    continue;
-                }
-                if (q->deadline_s > 0.0 && seconds_since(S->t0, Clock::now()) > q->deadline_s) {
-                    S->queue.pop_front();
-                    finish(S, q, SL_ETIMEOUT, "deadline passed before admission");
-                    continue;
-                }
-                if (q->footprint > S->cfg.hbm_budget_bytes) {
-                    S->queue.pop_front();
-                    finish(S, q, SL_ENOMEM, "request cannot fit the HBM budget");
-                    continue;
-                }
-                int32_t slot = -1;
-                for (int32_t i = 0; i < max_active; ++i)
-                    if (!S->slots[i]) { slot = i; break; }
-                if (slot < 0 || S->hbm_in_use + q->footprint > S->cfg.hbm_budget_bytes) break;
-                S->queue.pop_front();
-                q->slot = slot;
-                S->slots[slot] = q;
-                S->hbm_in_use += q->footprint;
-                q->times.admitted_s = seconds_since(S->t0, Clock::now());
-                admitted.push_back(q);
-            }
-        }
-        for (Request* q : admitted) {
-            const sl_status r = admit(S, q, q->slot);
-            std::lock_guard<std::mutex> lk(S->mu);
-            if (r) {
-                const std::string msg = sl_last_error();
-                release(S, q);
-                finish(S, q, r, msg);
-                S->stats.failed++;
-            } else {
-                q->phase = Request::ACTIVE;
-                q->times.started_s = seconds_since(S->t0, Clock::now());
-                work_dirty = true;
-            }
-        }
-        bool any = false;
-        for (Request* q : S->slots) any = any || (q != nullptr);
-        if (!any) continue;
-
-        // ---- one step: a few sweeps over every admitted request
-        if (work_dirty) {
-            if (rebuild_work(S, &n_work, &T, &hcap, &rcap)) {
-                S->fatal = sl_last_error();
-                break;
-            }
-            work_dirty = false;
-        }
-        const bool jacobi = S->opts.form == SL_JACOBI;
-        const TileLaunch L{S->work, n_work, T, hcap, rcap, S->opts.layout, S->opts.accept, S->states};
+        // ---- 1. launch one step (a few sweeps) over every ready request
+        std::vector<Request*> in_step;
+        for (Request* q : S->slots)
+            if (q && q->phase == Request::ACTIVE) in_step.push_back(q);
         sl_status r = SL_OK;
-        for (int32_t k = 0; k < S->cfg.sweeps_per_step && !r; ++k) {
-            if (jacobi && n_work > 0) r = launch_sweep_tiles(L, S->parity, nullptr, S->st_compute);
-            for (int32_t i = 0; i < max_active && !r; ++i) {
-                Request* q = S->slots[i];
-                if (!q || (jacobi && q->mesh.tile_nodes > 0)) continue;
-                r = launch_sweep_nodes(q->mesh, S->parity, S->opts.form, S->opts.accept, S->opts.block_size,
-                                       S->states + i, nullptr, S->st_compute);
+        if (!in_step.empty()) {
+            if (work_dirty) {
+                r = rebuild_work(S, &n_work, &T, &hcap, &rcap);
+                work_dirty = false;
             }
-            if (!r) r = launch_advance(S->states, max_active, S->st_compute);
-            S->parity ^= 1;
+            // joiners start at the current launch parity: both buffers hold
+            // their start positions, so either parity reads them
+            for (Request* q : in_step) {
+                if (r || q->joined) continue;
+                // the pinned entry of a slot is rewritten only when a later
+                // request takes the slot, after this step has been synchronised
+                S->h_join[q->slot] = q->state0;
+                if (hipMemcpyAsync(S->states + q->slot, S->h_join + q->slot, sizeof(MeshState), hipMemcpyHostToDevice,
+                                   S->st_compute) != hipSuccess)
+                    r = fail(SL_EDEVICE, "state upload failed");
+                q->parity0 = S->parity;
+                q->joined = true;
+            }
+            const TileLaunch L{S->work, n_work, T, hcap, rcap, S->opts.layout, S->opts.accept, S->states, wg_per_cu, 0};
+            for (int32_t k = 0; k < S->cfg.sweeps_per_step && !r; ++k) {
+                if (jacobi && n_work > 0) r = launch_sweep_tiles(L, S->parity, nullptr, S->st_compute);
+                for (Request* q : in_step) {
+                    if (r) break;
+                    if (jacobi && q->mesh.tile_nodes > 0) continue;
+                    r = launch_sweep_nodes(q->mesh, S->parity, S->opts.form, S->opts.accept, block,
+                                           S->states + q->slot, nullptr, S->st_compute);
+                }
+                if (!r) r = launch_advance(S->states, max_active, S->st_compute);
+                S->parity ^= 1;
+            }
+            if (!r && hipMemcpyAsync(S->h_states, S->states, sizeof(MeshState) * max_active,
+                                     hipMemcpyDeviceToHost, S->st_compute) != hipSuccess)
+                r = fail(SL_EDEVICE, "state read-back failed");
         }
-        if (!r && hipMemcpyAsync(hstate.data(), S->states, sizeof(MeshState) * max_active, hipMemcpyDeviceToHost,
-                                 S->st_compute) != hipSuccess)
-            r = fail(SL_EDEVICE, "state read-back failed");
+        const bool stepping = !in_step.empty();
+
+        // ---- 2. admissions while the step runs (FIFO: the head waits until
+        // it fits); with no step in flight, one admission starts the next
+        for (;;) {
+            Request* q = nullptr;
+            {
+                std::unique_lock<std::mutex> lk(S->mu);
+                if (!stepping && S->queue.empty())
+                    S->cv.wait_for(lk, std::chrono::milliseconds(50),
+                                   [&] { return S->stop.load() || !S->queue.empty(); });
+                q = pop_admissible(S);
+            }
+            if (!q) break;
+            const sl_status ar = admit(S, q, q->slot);
+            {
+                std::lock_guard<std::mutex> lk(S->mu);
+                if (ar) {
+                    const std::string msg = sl_last_error();
+                    release(S, q);
+                    finish(S, q, ar, msg);
+                    S->stats.failed++;
+                } else {
+                    q->phase = Request::ACTIVE;
+                    q->times.started_s = seconds_since(S->t0, Clock::now());
+                    work_dirty = true;
+                }
+            }
+            if (!stepping || hipStreamQuery(S->st_compute) != hipErrorNotReady) break;
+        }
+        if (!stepping) continue;
+
+        // ---- 3. retire the requests that finished in this step
         if (!r && hipStreamSynchronize(S->st_compute) != hipSuccess) r = fail(SL_EDEVICE, "sweep step failed");
         const double now = seconds_since(S->t0, Clock::now());
         std::lock_guard<std::mutex> lk(S->mu);
         S->stats.steps++;
-        for (int32_t i = 0; i < max_active; ++i) {
-            Request* q = S->slots[i];
-            if (!q) continue;
-            const MeshState& ms = hstate[i];
+        for (Request* q : in_step) {
+            const MeshState& ms = hstate[q->slot];
             sl_status fs = SL_OK;
             std::string msg;
             bool done = false;
@@ -365,7 +365,8 @@ void scheduler(sl_server* S)
             } else {
                 S->stats.failed++;
             }
-            // a slot is reused only after its MeshState is reset at admission
+            // a slot is reused only after its state is rewritten when the
+            // next request joins
             release(S, q);
             finish(S, q, fs, msg);
             work_dirty = true;
@@ -375,6 +376,27 @@ void scheduler(sl_server* S)
             break;
         }
     }
+}
+
+// Streams, the per-slot sweep states and their pinned host mirrors.
+sl_status init_device(sl_server* S)
+{
+    sl_status r;
+    SL_HIP(hipGetDevice(&S->device));
+    SL_HIP(hipStreamCreateWithFlags(&S->st_compute, hipStreamNonBlocking));
+    SL_HIP(hipStreamCreateWithFlags(&S->st_setup, hipStreamNonBlocking));
+    if ((r = dalloc(&S->states, static_cast<size_t>(S->cfg.max_active), S->st_compute))) return r;
+    SL_HIP(hipHostMalloc(reinterpret_cast<void**>(&S->h_states), sizeof(MeshState) * S->cfg.max_active,
+                         hipHostMallocDefault));
+    SL_HIP(hipHostMalloc(reinterpret_cast<void**>(&S->h_join), sizeof(MeshState) * S->cfg.max_active,
+                         hipHostMallocDefault));
+    std::vector<MeshState> zero(static_cast<size_t>(S->cfg.max_active));
+    SL_HIP(hipMemcpyAsync(S->states, zero.data(), sizeof(MeshState) * zero.size(), hipMemcpyHostToDevice,
+                          S->st_compute));
+    SL_HIP(hipStreamSynchronize(S->st_compute));
+    S->slots.assign(static_cast<size_t>(S->cfg.max_active), nullptr);
+    S->t0 = Clock::now();
+    return SL_OK;
 }
 
 }  // namespace
@@ -409,17 +431,18 @@ sl_status sl_server_create(const sl_server_config* cfg, const sl_options* opts, 
     S->opts.flags_out = nullptr;
     sl_status r = check_options(S->opts);
     if (r) return r;
+    if (S->cfg.max_active > kMaxActive) return fail(SL_EINVAL, "max_active must be <= 65536");
+    // automatic launch shapes are fixed when the server starts: every
+    // request of one work list has the same tile size
+    S->opts.tile_nodes = resolve_tile_nodes(S->opts);
+    S->opts.tile_wg_per_cu = resolve_wg_per_cu(S->opts);
+    S->opts.block_size = resolve_block_size(S->opts);
     keep_pool_warm();
-    SL_HIP(hipGetDevice(&S->device));
-    SL_HIP(hipStreamCreateWithFlags(&S->st_compute, hipStreamNonBlocking));
-    SL_HIP(hipStreamCreateWithFlags(&S->st_setup, hipStreamNonBlocking));
-    if ((r = dalloc(&S->states, static_cast<size_t>(S->cfg.max_active), S->st_compute))) return r;
-    std::vector<MeshState> zero(static_cast<size_t>(S->cfg.max_active));
-    SL_HIP(hipMemcpyAsync(S->states, zero.data(), sizeof(MeshState) * zero.size(), hipMemcpyHostToDevice,
-                          S->st_compute));
-    SL_HIP(hipStreamSynchronize(S->st_compute));
-    S->slots.assign(static_cast<size_t>(S->cfg.max_active), nullptr);
-    S->t0 = Clock::now();
+    if ((r = init_device(S.get()))) {
+        const std::string msg = sl_last_error();
+        sl_server_destroy(S.release());
+        return fail(r, msg);
+    }
     sl_server* raw = S.get();
     S->thread = std::thread(scheduler, raw);
     *out = S.release();
@@ -511,10 +534,13 @@ void sl_server_destroy(sl_server* S)
     dfree(S->work, S->st_compute);
     dfree(S->states, S->st_compute);
     dfree(S->out, S->st_compute);
-    (void)hipStreamSynchronize(S->st_compute);
-    (void)hipStreamSynchronize(S->st_setup);
-    (void)hipStreamDestroy(S->st_compute);
-    (void)hipStreamDestroy(S->st_setup);
+    for (hipStream_t st : {S->st_compute, S->st_setup}) {
+        if (!st) continue;
+        (void)hipStreamSynchronize(st);
+        (void)hipStreamDestroy(st);
+    }
+    if (S->h_states) (void)hipHostFree(S->h_states);
+    if (S->h_join) (void)hipHostFree(S->h_join);
     delete S;
 }
 

@@ -161,7 +161,9 @@ __global__ __launch_bounds__(kBS) void k_validate_nodes(ValArgs a, ValStats* __r
     int is_free = 0, deg = 0, inc = 0;
     if (i < a.n) {
         const double x = a.coords[2 * static_cast<int64_t>(i)], y = a.coords[2 * static_cast<int64_t>(i) + 1];
-        if (!isfinite(x) || !isfinite(y)) e |= VE_COORD;
+        // finite and below 2^500 in magnitude: squared edge lengths and cross
+        // products cannot overflow, so every quality is a finite number
+        if (!(fabs(x) < 0x1p500) || !(fabs(y) < 0x1p500)) e |= VE_COORD;
         const int32_t b = a.nbr_ptr[i], en = a.nbr_ptr[i + 1];
         const bool row_ok = 0 <= b && b <= en && en <= a.nnz;
         const int32_t tb = a.tri_ptr[i], te = a.tri_ptr[i + 1];
@@ -579,15 +581,6 @@ void devmesh_free(DevMesh& m, hipStream_t st)
 }
 
 // Free nodes per tile on the tile path (SMARTLAP_TILE_NODES overrides: 256 or 512).
-static int tile_nodes_for(const sl_options&)
-{
-    if (const char* e = getenv("SMARTLAP_TILE_NODES")) {
-        const int v = atoi(e);
-        if (v == 256 || v == 512) return v;
-    }
-    return 512;
-}
-
 sl_status setup_mesh(const SetupArgs& a, const sl_options& o, DevMesh& m, int32_t mesh, hipStream_t st)
 {
     const int32_t n = a.n;
@@ -612,7 +605,7 @@ sl_status setup_mesh(const SetupArgs& a, const sl_options& o, DevMesh& m, int32_
         std::string msg = "invalid input:";
         if (h.err & VE_PTR) msg += " CSR offsets not monotone or out of range;";
         if (h.err & VE_RANGE) msg += " node or triangle id out of range;";
-        if (h.err & VE_COORD) msg += " non-finite coordinate;";
+        if (h.err & VE_COORD) msg += " coordinate not finite or of magnitude >= 2^500;";
         return fail(SL_EINVAL, msg);
     }
     if (h.err) {
@@ -687,7 +680,7 @@ sl_status setup_mesh(const SetupArgs& a, const sl_options& o, DevMesh& m, int32_
     k_init_coords<<<gb, kBS, 0, st>>>(a.coords, m.perm, n, o.layout == SL_SOA, m.X[0], m.X[1]);
     // tile path for Form A; the node path's rows and fans otherwise
     if (o.form == SL_JACOBI && o.kernel != SL_KERNEL_NODE)
-        if ((r = build_tiles(a, m, tile_nodes_for(o), mesh, st))) return r;
+        if ((r = build_tiles(a, m, resolve_tile_nodes(o), mesh, st))) return r;
     if (m.tile_nodes == 0) {
         if ((r = dalloc(&m.nbr, m.nnz_free, st)) || (r = dalloc(&m.fan, m.ninc_free, st))) return r;
         if (m.n_free > 0)

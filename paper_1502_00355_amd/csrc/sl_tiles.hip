@@ -285,16 +285,13 @@ __global__ void k_tile_work(const int4* __restrict__ c, const int32_t* __restric
 // ------------------------------------------------------------ tile sweep --
 
 // Order-preserving 64-bit key of a double (for LDS atomic minima).
-__device__ __forceinline__ uint64_t okey(double q)
+// Minimum into an LDS double (one ds_min_f64).  Qualities are finite --
+// coordinates are validated below 2^500 in magnitude and S == 0 gives 0 --
+// so no NaN reaches it; which zero a min keeps when +0 meets -0 does not
+// matter, the accept test compares them equal.
+__device__ __forceinline__ void lds_min(double* p, double v)
 {
-    const uint64_t b = static_cast<uint64_t>(__double_as_longlong(q));
-    const uint64_t m = static_cast<uint64_t>(static_cast<int64_t>(b) >> 63);
-    return b ^ (m | 0x8000000000000000ull);
-}
-__device__ __forceinline__ double okey_inv(uint64_t k)
-{
-    const uint64_t b = (k >> 63) ? (k & 0x7FFFFFFFFFFFFFFFull) : ~k;
-    return __longlong_as_double(static_cast<long long>(b));
+    __hip_atomic_fetch_min(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
 }
 
 // (2*sqrt(3)*cr)/S, or 0 when S == 0.
@@ -315,6 +312,7 @@ struct TileSweepArgs {
     const TileWork* work;
     int32_t n_work, tiles_per_xcd, halo_cap, rows_cap;
     int32_t parity;            // every mesh of the launch reads buffer `parity`
+    int32_t exit_if_inactive;  // all tiles are of one mesh: return at once if it has stopped
     MeshState* states;
     uint64_t* bits;            // nullable: accept bits of this sweep (single mesh)
 };
@@ -322,8 +320,8 @@ struct TileSweepArgs {
 // Old quality of one triangle and the new quality for each own vertex,
 // folded into the per-node minima.  Local indices below T are own nodes.
 template <int T>
-__device__ __forceinline__ void tile_triangle(uint64_t w, const double2* Xl, const double2* cand, uint64_t* qo,
-                                              uint64_t* qn)
+__device__ __forceinline__ void tile_triangle(uint64_t w, const double2* Xl, const double2* cand, double* qo,
+                                              double* qn)
 {
     const int l0 = static_cast<int>(w & 0xFFFF), l1 = static_cast<int>((w >> 16) & 0xFFFF),
               l2 = static_cast<int>((w >> 32) & 0xFFFF);
@@ -332,27 +330,24 @@ __device__ __forceinline__ void tile_triangle(uint64_t w, const double2* Xl, con
     const double bx = p2.x - p0.x, by = p2.y - p0.y;
     const double cx = p2.x - p1.x, cy = p2.y - p1.y;
     const double La = ax * ax + ay * ay, Lb = bx * bx + by * by, Lc = cx * cx + cy * cy;
-    const uint64_t ko = okey(finish_q(ax * by - bx * ay, (La + Lc) + Lb));
+    const double qold = finish_q(ax * by - bx * ay, (La + Lc) + Lb);
     if (l0 < T) {
-        atomicMin(reinterpret_cast<unsigned long long*>(qo + l0), static_cast<unsigned long long>(ko));
+        lds_min(qo + l0, qold);
         const double2 c = cand[l0];
         const double ax2 = p1.x - c.x, ay2 = p1.y - c.y, bx2 = p2.x - c.x, by2 = p2.y - c.y;
-        const double q = finish_q(ax2 * by2 - bx2 * ay2, ((ax2 * ax2 + ay2 * ay2) + Lc) + (bx2 * bx2 + by2 * by2));
-        atomicMin(reinterpret_cast<unsigned long long*>(qn + l0), static_cast<unsigned long long>(okey(q)));
+        lds_min(qn + l0, finish_q(ax2 * by2 - bx2 * ay2, ((ax2 * ax2 + ay2 * ay2) + Lc) + (bx2 * bx2 + by2 * by2)));
     }
     if (l1 < T) {
-        atomicMin(reinterpret_cast<unsigned long long*>(qo + l1), static_cast<unsigned long long>(ko));
+        lds_min(qo + l1, qold);
         const double2 c = cand[l1];
         const double ax2 = c.x - p0.x, ay2 = c.y - p0.y, cx2 = p2.x - c.x, cy2 = p2.y - c.y;
-        const double q = finish_q(ax2 * by - bx * ay2, ((ax2 * ax2 + ay2 * ay2) + (cx2 * cx2 + cy2 * cy2)) + Lb);
-        atomicMin(reinterpret_cast<unsigned long long*>(qn + l1), static_cast<unsigned long long>(okey(q)));
+        lds_min(qn + l1, finish_q(ax2 * by - bx * ay2, ((ax2 * ax2 + ay2 * ay2) + (cx2 * cx2 + cy2 * cy2)) + Lb));
     }
     if (l2 < T) {
-        atomicMin(reinterpret_cast<unsigned long long*>(qo + l2), static_cast<unsigned long long>(ko));
+        lds_min(qo + l2, qold);
         const double2 c = cand[l2];
         const double bx2 = c.x - p0.x, by2 = c.y - p0.y, cx2 = c.x - p1.x, cy2 = c.y - p1.y;
-        const double q = finish_q(ax * by2 - bx2 * ay, (La + (cx2 * cx2 + cy2 * cy2)) + (bx2 * bx2 + by2 * by2));
-        atomicMin(reinterpret_cast<unsigned long long*>(qn + l2), static_cast<unsigned long long>(okey(q)));
+        lds_min(qn + l2, finish_q(ax * by2 - bx2 * ay, (La + (cx2 * cx2 + cy2 * cy2)) + (bx2 * bx2 + by2 * by2)));
     }
 }
 
@@ -488,15 +483,14 @@ __global__ __launch_bounds__(BS) void k_sweep_tile(TileSweepArgs a)
     extern __shared__ double2 lds[];
     double2* Xl = lds;                                      // [T + halo_cap]
     double2* cand = lds + T + a.halo_cap;                   // [T]
-    uint64_t* qo = reinterpret_cast<uint64_t*>(cand + T);   // [T]
-    uint64_t* qn = qo + T;                                  // [T]
+    double* qo = reinterpret_cast<double*>(cand + T);       // [T] worst old quality per own node
+    double* qn = qo + T;                                    // [T] worst candidate quality
     uint16_t* rows = reinterpret_cast<uint16_t*>(qn + T);   // [rows_cap]
     uint64_t* rows64 = reinterpret_cast<uint64_t*>(rows);
     __shared__ double s_d2[BS / 64];
     __shared__ unsigned long long s_acc[BS / 64];
     const int tid = threadIdx.x;
     const int lane = tid & 63, wv = tid >> 6;
-    constexpr uint64_t kKeyInf = 0xFFF0000000000000ull;     // okey(+inf)
     const int parity = a.parity;
 
     // descriptors run two tiles ahead of the data, data one tile ahead; the
@@ -505,6 +499,7 @@ __global__ __launch_bounds__(BS) void k_sweep_tile(TileSweepArgs a)
     TileWork dcur = uniform_work(load_work(a.work, it));
     TileWork dnext = load_work(a.work, it + nw < t_end ? it + nw : it);
     int act_cur = a.states[dcur.mesh].active;
+    if (a.exit_if_inactive && act_cur == 0) return;
     TileStage<NPT, RPRE, KPRE> sg;
     stage_a<T, BS, SOA>(sg, dcur, parity);
     stage_b<T, BS, SOA>(sg, dcur, parity);
@@ -557,8 +552,8 @@ __global__ __launch_bounds__(BS) void k_sweep_tile(TileSweepArgs a)
                     }
                     const double dn = static_cast<double>(r1[m] - r0[m]);
                     cand[i] = make_double2(sx / dn, sy / dn);
-                    qo[i] = kKeyInf;
-                    qn[i] = kKeyInf;
+                    qo[i] = __builtin_inf();
+                    qn[i] = __builtin_inf();
                 }
             }
         }
@@ -590,7 +585,7 @@ __global__ __launch_bounds__(BS) void k_sweep_tile(TileSweepArgs a)
                 const int i = m * BS + tid;
                 bool accepted = false;
                 if (i < nown) {
-                    const double vo = okey_inv(qo[i]), vn = okey_inv(qn[i]);
+                    const double vo = qo[i], vn = qn[i];
                     accepted = GT ? (vn > vo) : (vn >= vo);
                     const double2 o = Xl[i];
                     const double2 c = cand[i];
@@ -760,13 +755,13 @@ sl_status build_tiles(const SetupArgs& a, DevMesh& m, int tile_nodes, int mesh, 
     return SL_OK;
 }
 
-int tile_grid(int n_work, int tile_nodes, int halo_cap, int rows_cap)
+int tile_grid(int n_work, int tile_nodes, int halo_cap, int rows_cap, int wg_per_cu)
 {
     const size_t lds = tile_lds_bytes(tile_nodes, halo_cap, rows_cap);
-    // work-groups per CU that fit the LDS and the waves per SIMD; 32 CUs per
-    // XCD; never more work-groups than tiles on an XCD
-    int per_cu = std::max(1, std::min(static_cast<int>(kLdsLimit / std::max<size_t>(lds, 1)), 4));
-    if (const char* e = getenv("SMARTLAP_TILE_WG_PER_CU")) per_cu = std::max(1, atoi(e));
+    // work-groups per CU: as requested (else 4), no more than fit the LDS;
+    // 32 CUs per XCD; never more work-groups than tiles on an XCD
+    const int fit = std::max(1, static_cast<int>(kLdsLimit / std::max<size_t>(lds, 1)));
+    const int per_cu = std::min(wg_per_cu > 0 ? wg_per_cu : 4, fit);
     const int tpx = div_up(std::max(n_work, 1), 8);
     const int nw = std::min(tpx, 32 * per_cu);
     return 8 * nw;
@@ -782,10 +777,11 @@ sl_status launch_sweep_tiles(const TileLaunch& L, int32_t parity, uint64_t* bits
     a.halo_cap = L.halo_cap;
     a.rows_cap = L.rows_cap;
     a.parity = parity;
+    a.exit_if_inactive = L.exit_if_inactive;
     a.states = L.states;
     a.bits = bits;
     const size_t lds = tile_lds_bytes(L.tile_nodes, L.halo_cap, L.rows_cap);
-    const int grid = tile_grid(L.n_work, L.tile_nodes, L.halo_cap, L.rows_cap);
+    const int grid = tile_grid(L.n_work, L.tile_nodes, L.halo_cap, L.rows_cap, L.wg_per_cu);
     const bool soa = L.layout == SL_SOA, gt = L.accept == SL_ACCEPT_GT;
     if (L.tile_nodes == 256) launch_tile_t<256>(a, soa, gt, grid, lds, st);
     else launch_tile_t<512>(a, soa, gt, grid, lds, st);

@@ -1,0 +1,250 @@
+// Autotuning of the sweep launch shape.
+//
+// The tile size (free nodes per tile) and the number of persistent
+// work-groups per compute unit change only the speed of a sweep: every tile
+// computes the same per-node results whatever the shape.  The tuner sets up
+// a sample of the caller's meshes once per tile size, times a few sweeps of
+// the batched tile kernel for each work-group count, and keeps the fastest
+// shape as the automatic choice of the device.  For Form B (node kernel) it
+// times the node kernel's work-group sizes instead.
+#include <algorithm>
+#include <chrono>
+#include <climits>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "sl_common.h"
+
+namespace sl {
+
+namespace {
+
+constexpr size_t kTuneNodes = size_t(8) << 20;   // sampled nodes, about
+constexpr int32_t kWarmSweeps = 2;
+constexpr int32_t kTimedSweeps = 6;
+
+// Device state of one tuning pass, released on every exit path.
+struct TunePass {
+    hipStream_t st = nullptr;
+    std::vector<DevMesh> meshes;
+    TileWork* work = nullptr;
+    MeshState* states = nullptr;
+    hipEvent_t ev[2] = {nullptr, nullptr};
+    ~TunePass()
+    {
+        for (auto& m : meshes) devmesh_free(m, st);
+        dfree(work, st);
+        dfree(states, st);
+        (void)hipStreamSynchronize(st);
+        for (auto& e : ev)
+            if (e) (void)hipEventDestroy(e);
+    }
+};
+
+struct Candidate {
+    int32_t tile_nodes, shape;
+    double ns;
+};
+
+// Sets up the sampled meshes with options o and fills the sweep states
+// (every mesh active, no sweep cap in reach).
+sl_status setup_pass(TunePass& p, const sl_mesh_desc* meshes, const std::vector<int32_t>& sample,
+                     const sl_options& o)
+{
+    p.meshes.resize(sample.size());
+    for (size_t k = 0; k < sample.size(); ++k) {
+        const sl_status r = upload_and_prepare(meshes[sample[k]], o, static_cast<int32_t>(k), p.meshes[k], p.st);
+        if (r) return fail(r, "mesh " + std::to_string(sample[k]) + ": " + sl_last_error());
+    }
+    std::vector<MeshState> h(sample.size());
+    for (auto& s : h) {
+        s = MeshState{};
+        s.iters = INT32_MAX;
+        s.active = 1;
+    }
+    sl_status r = dalloc(&p.states, h.size(), p.st);
+    if (r) return r;
+    SL_HIP(hipMemcpyAsync(p.states, h.data(), sizeof(MeshState) * h.size(), hipMemcpyHostToDevice, p.st));
+    for (auto& e : p.ev) SL_HIP(hipEventCreate(&e));
+    return SL_OK;
+}
+
+// Device milliseconds of kTimedSweeps sweeps enqueued by `sweep(parity)`.
+template <typename F>
+sl_status time_sweeps(TunePass& p, int32_t n_states, F sweep, float* ms)
+{
+    sl_status r = SL_OK;
+    for (int32_t s = 0; s < kWarmSweeps + kTimedSweeps && !r; ++s) {
+        if (s == kWarmSweeps) SL_HIP(hipEventRecord(p.ev[0], p.st));
+        r = sweep(s & 1);
+        if (!r) r = launch_advance(p.states, n_states, p.st);
+    }
+    if (r) return r;
+    SL_HIP(hipEventRecord(p.ev[1], p.st));
+    SL_HIP(hipStreamSynchronize(p.st));
+    SL_HIP(hipEventElapsedTime(ms, p.ev[0], p.ev[1]));
+    return SL_OK;
+}
+
+sl_status tune_tiles(const sl_mesh_desc* meshes, const std::vector<int32_t>& sample, const sl_options& base,
+                     hipStream_t st, std::vector<Candidate>& out, int64_t* free_nodes)
+{
+    for (int32_t T : {512, 256}) {
+        sl_options o = base;
+        o.tile_nodes = T;
+        o.kernel = SL_KERNEL_TILE;
+        TunePass p;
+        p.st = st;
+        sl_status r = setup_pass(p, meshes, sample, o);
+        if (r) return r;
+        int64_t tiles = 0, on_tiles = 0;
+        int32_t hcap = 0, rcap = 0;
+        for (const auto& m : p.meshes) {
+            if (m.tile_nodes == 0) continue;
+            tiles += m.n_tiles;
+            on_tiles += m.n_free;
+            hcap = std::max(hcap, m.halo_max);
+            rcap = std::max(rcap, m.rows_max);
+        }
+        if (tiles == 0 || on_tiles == 0) continue;
+        if (tiles > INT32_MAX) return fail(SL_EINVAL, "sample has more than 2^31 tiles");
+        *free_nodes = on_tiles;
+        if ((r = dalloc(&p.work, static_cast<size_t>(tiles), st))) return r;
+        int64_t off = 0;
+        for (const auto& m : p.meshes) {
+            if (m.tile_nodes == 0) continue;
+            SL_HIP(hipMemcpyAsync(p.work + off, m.work, sizeof(TileWork) * m.n_tiles, hipMemcpyDeviceToDevice, st));
+            off += m.n_tiles;
+        }
+        int last_grid = -1;
+        for (int32_t w = 1; w <= 8; ++w) {
+            const int grid = tile_grid(static_cast<int>(tiles), T, hcap, rcap, w);
+            if (grid == last_grid) continue;   // capped by LDS or by the tile count: same launch
+            last_grid = grid;
+            const TileLaunch L{p.work, static_cast<int32_t>(tiles), T, hcap, rcap, o.layout, o.accept, p.states, w, 0};
+            float ms = 0.f;
+            r = time_sweeps(p, static_cast<int32_t>(p.meshes.size()),
+                            [&](int32_t parity) { return launch_sweep_tiles(L, parity, nullptr, st); }, &ms);
+            if (r) return r;
+            out.push_back(Candidate{T, w, 1e6 * ms / (static_cast<double>(kTimedSweeps) * on_tiles)});
+        }
+    }
+    return SL_OK;
+}
+
+sl_status tune_nodes(const sl_mesh_desc* meshes, const std::vector<int32_t>& sample, const sl_options& base,
+                     hipStream_t st, std::vector<Candidate>& out, int64_t* free_nodes)
+{
+    sl_options o = base;
+    o.kernel = SL_KERNEL_NODE;
+    TunePass p;
+    p.st = st;
+    sl_status r = setup_pass(p, meshes, sample, o);
+    if (r) return r;
+    int64_t nfree = 0;
+    for (const auto& m : p.meshes) nfree += m.n_free;
+    if (nfree == 0) return SL_OK;
+    *free_nodes = nfree;
+    for (int32_t bs : {64, 128, 256}) {
+        float ms = 0.f;
+        r = time_sweeps(p, static_cast<int32_t>(p.meshes.size()),
+                        [&](int32_t parity) {
+                            for (size_t k = 0; k < p.meshes.size(); ++k) {
+                                const sl_status rr = launch_sweep_nodes(p.meshes[k], parity, o.form, o.accept, bs,
+                                                                        p.states + k, nullptr, st);
+                                if (rr) return rr;
+                            }
+                            return SL_OK;
+                        },
+                        &ms);
+        if (r) return r;
+        out.push_back(Candidate{0, bs, 1e6 * ms / (static_cast<double>(kTimedSweeps) * nfree)});
+    }
+    return SL_OK;
+}
+
+}  // namespace
+
+}  // namespace sl
+
+extern "C" {
+
+sl_status sl_autotune(const sl_mesh_desc* meshes, int32_t n_meshes, const sl_options* opts, sl_tuning* out)
+{
+    using namespace sl;
+    const auto t0 = std::chrono::steady_clock::now();
+    set_error("");
+    if (!meshes || n_meshes <= 0) return fail(SL_EINVAL, "need at least one mesh");
+    sl_options o;
+    sl_options_default(&o);
+    if (opts) o = *opts;
+    o.flags_out = nullptr;
+    o.tile_nodes = 0;
+    o.tile_wg_per_cu = 0;
+    o.block_size = 0;
+    sl_status r = check_options(o);
+    if (r) return r;
+    size_t total = 0;
+    for (int32_t i = 0; i < n_meshes; ++i) {
+        if (meshes[i].n_nodes <= 0) return fail(SL_EINVAL, "mesh " + std::to_string(i) + ": n_nodes must be >= 1");
+        total += static_cast<size_t>(meshes[i].n_nodes);
+    }
+    // every k-th mesh in index order, k chosen so the sample is about kTuneNodes
+    const int32_t stride = static_cast<int32_t>(std::max<size_t>(1, (total + kTuneNodes - 1) / kTuneNodes));
+    std::vector<int32_t> sample;
+    for (int32_t i = 0; i < n_meshes; i += stride) sample.push_back(i);
+    keep_pool_warm();
+
+    hipStream_t st = nullptr;
+    SL_HIP(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
+    std::vector<Candidate> cands;
+    int64_t free_nodes = 0;
+    r = o.form == SL_JACOBI ? tune_tiles(meshes, sample, o, st, cands, &free_nodes)
+                            : tune_nodes(meshes, sample, o, st, cands, &free_nodes);
+    (void)hipStreamSynchronize(st);
+    (void)hipStreamDestroy(st);
+    if (r) return r;
+
+    TunedShape best{0, 0, 0};
+    double best_ns = 0.0;
+    for (const auto& c : cands) {
+        if (best_ns == 0.0 || c.ns < best_ns) {
+            best_ns = c.ns;
+            best = c.tile_nodes ? TunedShape{c.tile_nodes, c.shape, 0} : TunedShape{0, 0, c.shape};
+        }
+    }
+    if (!cands.empty()) {
+        // a Form B tuning leaves the tile shape as it was, and vice versa
+        const TunedShape prev = tuned_shape();
+        if (o.form == SL_JACOBI) best.block_size = prev.block_size;
+        else {
+            best.tile_nodes = prev.tile_nodes;
+            best.wg_per_cu = prev.wg_per_cu;
+        }
+        set_tuned_shape(best);
+    }
+    if (out) {
+        sl_tuning t;
+        std::memset(&t, 0, sizeof(t));
+        t.tile_nodes = o.form == SL_JACOBI ? best.tile_nodes : 0;
+        t.tile_wg_per_cu = o.form == SL_JACOBI ? best.wg_per_cu : 0;
+        t.block_size = o.form == SL_JACOBI ? 0 : best.block_size;
+        const int32_t cap = static_cast<int32_t>(sizeof(t.candidates) / sizeof(t.candidates[0]));
+        t.n_candidates = std::min(cap, static_cast<int32_t>(cands.size()));
+        for (int32_t k = 0; k < t.n_candidates; ++k) {
+            t.candidates[k].tile_nodes = cands[k].tile_nodes;
+            t.candidates[k].wg_per_cu = cands[k].shape;
+            t.candidates[k].ns_per_update = cands[k].ns;
+        }
+        t.sampled_meshes = static_cast<int32_t>(sample.size());
+        t.sampled_free_nodes = free_nodes;
+        t.tune_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+        *out = t;
+    }
+    return SL_OK;
+}
+
+void sl_autotune_reset(void) { sl::clear_tuned_shape(); }
+
+}  // extern "C"

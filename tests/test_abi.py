@@ -39,7 +39,8 @@ def test_only_the_c_abi_is_exported():
 def test_option_defaults(L):
     o = sl.Options()
     L.sl_options_default(ctypes.byref(o))
-    assert (o.form, o.accept, o.layout, o.reorder, o.block_size) == (0, 0, 0, 1, 0)
+    assert (o.form, o.accept, o.layout, o.reorder, o.block_size, o.kernel) == (0, 0, 0, 1, 0, 0)
+    assert (o.tile_nodes, o.tile_wg_per_cu) == (0, 0)
     assert not o.flags_out
     assert L.sl_version().startswith(b"smartlap")
 
@@ -66,3 +67,30 @@ def test_server_config_defaults(L):
     c = sl.ServerConfig()
     L.sl_server_config_default(ctypes.byref(c))
     assert c.hbm_budget_bytes == 200 << 30 and c.max_active == 256 and c.sweeps_per_step == 8
+
+
+def test_tile_option_errors_before_device_work(L):
+    X = np.zeros((4, 2))
+    ptr = np.zeros(5, np.int32)
+    idx = np.zeros(1, np.int32)
+    b = np.ones(4, np.uint8)
+    for kw in ({"tile_nodes": 384}, {"tile_wg_per_cu": 9}, {"tile_wg_per_cu": -1}, {"block_size": 96},
+               {"kernel": 7}, {"form": 5}):
+        o = sl.make_options(**kw)
+        st = L.smooth_mesh(X.ctypes.data, 4, ptr.ctypes.data, idx.ctypes.data, ptr.ctypes.data, idx.ctypes.data,
+                           idx.ctypes.data, 0, b.ctypes.data, 1, 0.0, ctypes.byref(o), None)
+        assert st == sl.SL_EINVAL, kw
+    assert b"tile_wg_per_cu" in L.sl_last_error() or b"form" in L.sl_last_error()
+
+
+def test_autotune_argument_errors(L):
+    t = sl.Tuning()
+    assert L.sl_autotune(None, 1, None, ctypes.byref(t)) == sl.SL_EINVAL
+    d = sl.MeshDesc()
+    d.n_nodes = 0
+    arr = (sl.MeshDesc * 1)(d)
+    assert L.sl_autotune(arr, 1, None, ctypes.byref(t)) == sl.SL_EINVAL
+    assert b"n_nodes" in L.sl_last_error()
+    o = sl.make_options(form=3)
+    d.n_nodes = 4
+    assert L.sl_autotune(arr, 1, ctypes.byref(o), ctypes.byref(t)) == sl.SL_EINVAL

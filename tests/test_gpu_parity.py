@@ -144,6 +144,63 @@ def test_tolerance_stop():
     assert 0 < rep.iterations_run < 200
 
 
+@pytest.mark.parametrize("iters,tol_at", [(64, None), (77, None), (200, 41), (1000, 5)])
+def test_sweep_loop_in_graph_chunks(iters, tol_at):
+    """Without flag output the sweep loop runs as replays of a captured
+    chunk: whole chunks, a shorter tail, and a tolerance reached inside a
+    chunk (the host stops launching, the rest of the chunk returns at once)."""
+    m = meshgen.make_grid(40, "random", 0.4, 77)
+    tol = 0.0
+    if tol_at is not None:
+        tol = math.sqrt(oracle.smooth(m, tol_at + 1).disp[tol_at]) * 1.0000001
+    note("chunks iters=%d tol=%g" % (iters, tol))
+    ref = oracle.smooth(m, iters, tol=tol)
+    X, rep, _ = run_gpu(m, iters, tol, want_flags=False)
+    assert rep.iterations_run == ref.iterations_run
+    if tol_at is not None:
+        assert rep.iterations_run < iters
+    assert (X == ref.coords).all()
+    assert rep.accepted_total == int(ref.accepted.sum())
+
+
+@pytest.mark.parametrize("tile_nodes,wpc", [(256, 1), (256, 3), (512, 2), (512, 8)])
+def test_tile_shapes_are_bit_identical(tile_nodes, wpc):
+    m = meshgen.make_grid(300, "random", 0.4, 31)
+    X, rep, ref, ndiff = assert_parity(m, 6, kernel="tile", tile_nodes=tile_nodes, tile_wg_per_cu=wpc)
+    assert ndiff == 0 and rep.kernel_used == 2 and rep.tile_nodes == tile_nodes
+
+
+def test_autotune_then_automatic_shape():
+    ms = [meshgen.make_grid(n, "random", 0.35, 500 + n) for n in (30, 64, 120, 250)]
+    try:
+        t = sl.autotune(ms)
+        note("autotune %s" % t.as_dict())
+        assert t.tile_nodes in (256, 512) and 1 <= t.tile_wg_per_cu <= 8 and t.block_size == 0
+        assert t.n_candidates >= 2 and t.sampled_meshes == 4
+        assert t.sampled_free_nodes == sum(m.n_interior for m in ms)
+        cands = list(t.candidates[: t.n_candidates])
+        best = min(c.ns_per_update for c in cands)
+        assert all(c.ns_per_update > 0 for c in cands)
+        assert any(c.tile_nodes == t.tile_nodes and c.wg_per_cu == t.tile_wg_per_cu and c.ns_per_update == best
+                   for c in cands)
+        X, rep, ref, ndiff = assert_parity(ms[3], 5)
+        assert ndiff == 0 and rep.tile_nodes == t.tile_nodes
+        outs, reps, br = sl.batch_smooth(ms, 5)
+        for m, X, r in zip(ms, outs, reps):
+            assert r.tile_nodes == t.tile_nodes
+            assert (X == oracle.smooth(m, 5).coords).all()
+        tc = sl.autotune(ms, form="colored")
+        note("autotune colored %s" % tc.as_dict())
+        assert tc.block_size in (64, 128, 256) and tc.tile_nodes == 0 and tc.n_candidates == 3
+        X, rep, ref, ndiff = assert_parity(ms[2], 4, form="colored")
+        assert ndiff == 0
+        # a coloured tuning keeps the tile shape
+        X, rep, ref, ndiff = assert_parity(ms[1], 3)
+        assert rep.tile_nodes == t.tile_nodes
+    finally:
+        sl.autotune_reset()
+
+
 def test_zero_iterations_and_all_fixed():
     m = meshgen.make_grid(16, "random", 0.4, 10)
     X, rep, F = run_gpu(m, 0)
@@ -204,6 +261,8 @@ def test_input_errors():
     cases = []
     a = m.copy(); a.nbr_idx[5] = m.n_nodes + 3; cases.append((a, sl.SL_EINVAL))
     a = m.copy(); a.coords[20, 1] = np.nan; cases.append((a, sl.SL_EINVAL))
+    a = m.copy(); a.coords[21, 0] = -np.inf; cases.append((a, sl.SL_EINVAL))
+    a = m.copy(); a.coords[22, 0] = 2.0 ** 500; cases.append((a, sl.SL_EINVAL))
     a = m.copy(); a.tri_idx[7] = -1; cases.append((a, sl.SL_EINVAL))
     a = m.copy(); a.nbr_ptr[10] = a.nbr_ptr[11] + 1; cases.append((a, sl.SL_EINVAL))
     a = m.copy(); i = 20; a.nbr_idx[a.nbr_ptr[i]] = i; cases.append((a, sl.SL_ETOPO))
@@ -218,6 +277,18 @@ def test_input_errors():
     before = m.coords.copy()
     rep = call(m)
     assert rep.iterations_run == 2 and not (m.coords == before).all()
+
+
+@pytest.mark.parametrize("exp2", [-520, -40, 40, 498])
+def test_extreme_coordinate_scales(exp2):
+    """The same mesh scaled by a power of two (exact): at 2^-520 squared
+    lengths are subnormal, near 2^498 they approach the largest doubles.  The
+    device follows the oracle at every scale (subnormals are kept by both)."""
+    m = meshgen.make_grid(45, "random", 0.4, 88)
+    m.coords = m.coords * (2.0 ** exp2) + (2.0 ** exp2) * 0.25
+    m.name = "grid45_scaled_2^%d" % exp2
+    X, rep, ref, ndiff = assert_parity(m, 6)
+    assert ndiff == 0
 
 
 def test_host_and_device_entry_points_agree():
@@ -292,6 +363,14 @@ def test_batch_tolerance_and_forms():
     outs, reps, br = sl.batch_smooth(ms, 6, accept="gt", layout="soa")
     for m, X in zip(ms, outs):
         assert (X == oracle.smooth(m, 6, accept_gt=True).coords).all()
+
+
+def test_batch_of_one_with_tolerance():
+    m = meshgen.make_grid(50, "random", 0.4, 71)
+    ref = oracle.smooth(m, 300, tol=3e-4)
+    outs, reps, br = sl.batch_smooth([m], 300, tol=3e-4)
+    assert reps[0].iterations_run == ref.iterations_run < 300
+    assert (outs[0] == ref.coords).all()
 
 
 def test_server_mix_equals_single_and_oracle():
