@@ -23,7 +23,7 @@ take host arrays in and give host arrays out.
 
 serving: Poisson arrivals at each rate of smoothing requests (side
 log-uniform in [32, 2048], random diagonals, +-0.4h; half of the requests
-run 10-200 sweeps, half run to a 1e-8 displacement tolerance with a 1000-sweep
+run 10-200 sweeps, half run to a 1e-8 displacement tolerance with a 10,000-sweep
 cap) submitted to the continuous-batching server; latency is completion time
 minus submission time.  The same arrival sequence is also served by a plain
 loop that runs one ``smooth_mesh`` call at a time in arrival order.
@@ -123,10 +123,19 @@ def cpu_baseline(m, seconds: float = 10.0):
             "sample": "%d whole Jacobi sweeps of %s (%d free nodes) in %.1f s" % (sweeps, m.name, free, el)}
 
 
+def tile_opts(args):
+    return {"tile_nodes": args.tile_nodes, "tile_wg_per_cu": args.wg_per_cu}
+
+
 def run_single(args, sl, torch):
     m, iters = workload(args.workload)
     free = m.n_interior
     alg_bytes = algorithmic_bytes(m)
+    tuning = None
+    if args.autotune:
+        t = sl.autotune([m], layout=args.layout)
+        tuning = t.as_dict()
+        log("autotune: tile_nodes %d, wg/CU %d in %.0f ms" % (t.tile_nodes, t.tile_wg_per_cu, t.tune_ms))
     dev = sl.to_device(m, "cuda:0")
     X0 = dev[0].clone()
     work = torch.empty_like(X0)
@@ -137,7 +146,7 @@ def run_single(args, sl, torch):
     def step():
         work.copy_(X0)
         return sl.smooth_mesh_device(work, *dev[1:], iterations=iters, layout=args.layout, reorder=args.reorder,
-                                     kernel=args.kernel, stream=stream)
+                                     kernel=args.kernel, stream=stream, **tile_opts(args))
 
     for w in range(args.warmup):
         r = step()
@@ -170,7 +179,8 @@ def run_single(args, sl, torch):
         "data": "synthetic",
         "config": {"workload": m.name, "nodes": m.n_nodes, "free_nodes": free, "triangles": m.n_tris,
                    "sweeps_per_step": iters, "form": "jacobi", "layout": args.layout, "reorder": args.reorder,
-                   "kernel": {1: "node", 2: "tile"}.get(r.kernel_used, "?")},
+                   "kernel": {1: "node", 2: "tile"}.get(r.kernel_used, "?"), "tile_nodes": r.tile_nodes},
+        "autotune": tuning,
         "sweep_only_node_updates_per_s": free / avg_sweep_s,
         "sweep_ms_per_sweep": avg_sweep_s * 1e3,
         "setup_ms_per_step": float(np.mean(setup_ms)),
@@ -181,6 +191,46 @@ def run_single(args, sl, torch):
                      "traffic": traffic_from_profile(kernel_source_hash()), "alg_bytes_per_launch": alg_bytes},
     }
     return out, m
+
+
+def run_layouts(args, sl, torch):
+    """The 1024 x 1024 permuted grid (100 sweeps) in AoS and SoA, with and
+    without the Hilbert reorder: sweep-loop rate of each."""
+    import meshgen
+    m = meshgen.permute_mesh(meshgen.make_grid(1024, "random", 0.4, 2), 2)
+    dev = sl.to_device(m, "cuda:0")
+    X0 = dev[0].clone()
+    work = torch.empty_like(X0)
+    rows = []
+    for layout in ("aos", "soa"):
+        for reorder in ("none", "hilbert"):
+            best = None
+            for _ in range(3):
+                work.copy_(X0)
+                r = sl.smooth_mesh_device(work, *dev[1:], iterations=100, layout=layout, reorder=reorder)
+                best = r if best is None or r.sweep_ms < best.sweep_ms else best
+            rows.append({"layout": layout, "reorder": reorder, "kernel": {1: "node", 2: "tile"}[best.kernel_used],
+                         "sweep_ms_per_sweep": best.sweep_ms / 100,
+                         "sweep_node_updates_per_s": m.n_interior * 100 / (best.sweep_ms / 1e3),
+                         "setup_ms": best.setup_ms})
+            log("grid1024 %s/%s: %.4f ms per sweep" % (layout, reorder, best.sweep_ms / 100))
+    return {"workload": "grid1024_random_j0.4_s2_permuted", "free_nodes": m.n_interior, "sweeps": 100,
+            "variants": rows}
+
+
+def run_converge(args, sl, torch):
+    """The headline mesh run until the largest displacement of a sweep is
+    below 1e-9 (cap 100,000 sweeps): the sweep count it takes."""
+    m, _ = workload(args.workload)
+    dev = sl.to_device(m, "cuda:0")
+    r = sl.smooth_mesh_device(*dev, iterations=args.converge_cap, tol=1e-9)
+    torch.cuda.synchronize()
+    log("converge %s: %d sweeps, last max |dx|^2 %.3e, %.1f s of sweeps" %
+        (m.name, r.iterations_run, r.max_disp_sq_last, r.sweep_ms / 1e3))
+    return {"workload": m.name, "tol": 1e-9, "cap": args.converge_cap, "iterations_run": r.iterations_run,
+            "converged": r.iterations_run < args.converge_cap, "max_disp_sq_last": r.max_disp_sq_last,
+            "accepted_last": r.accepted_last, "sweep_ms": r.sweep_ms,
+            "sweep_node_updates_per_s": m.n_interior * r.iterations_run / (r.sweep_ms / 1e3)}
 
 
 def gen_meshes(specs):
@@ -200,6 +250,11 @@ def run_batch(args, sl):
     free = sum(m.n_interior for m in meshes)
     nodes = sum(m.n_nodes for m in meshes)
     log("batch: %d meshes, %d nodes, %d free, generated in %.1f s" % (M, nodes, free, time.perf_counter() - t))
+    tuning = None
+    if args.autotune:
+        t = sl.autotune(meshes)
+        tuning = t.as_dict()
+        log("autotune: tile_nodes %d, wg/CU %d in %.0f ms" % (t.tile_nodes, t.tile_wg_per_cu, t.tune_ms))
     sl.batch_smooth(meshes[: min(M, 8)], iters)          # warm-up (code objects, memory pool)
     t = time.perf_counter()
     _, reps, br = sl.batch_smooth(meshes, iters)
@@ -223,7 +278,7 @@ def run_batch(args, sl):
         "plain_node_updates_per_s": upd / el_p, "plain_s": el_p, "plain_sweep_ms": plain_sweep_ms,
         "plain_sweep_node_updates_per_s": upd / (plain_sweep_ms / 1e3),
         "speedup_whole_job": el_p / el_b, "speedup_sweeps": plain_sweep_ms / br.sweep_ms,
-        "tiles": br.tiles, "graph_used": bool(br.graph_used),
+        "tiles": br.tiles, "graph_used": bool(br.graph_used), "autotune": tuning,
     }
 
 
@@ -237,7 +292,7 @@ def serve_requests(rate, count, pool, rng):
         if rng.random() < 0.5:
             reqs.append((float(arr[k]), idx, int(rng.integers(10, 201)), 0.0))
         else:
-            reqs.append((float(arr[k]), idx, 1000, 1e-8))
+            reqs.append((float(arr[k]), idx, 10000, 1e-8))
     return reqs
 
 
@@ -329,7 +384,7 @@ def run_serve(args, sl):
                      "plain_p50_ms": _pct(plat, 50), "plain_p99_ms": _pct(plat, 99),
                      "plain_node_updates_per_s": pupd / pspan, "server_steps": st.steps})
     return {"workload": "serve_grids_side32-2048_random_j0.4_pool%d" % P,
-            "requests_mix": "half 10-200 sweeps, half tol 1e-8 (cap 1000)", "rates": rows}
+            "requests_mix": "half 10-200 sweeps, half tol 1e-8 (cap 10000)", "rates": rows}
 
 
 def main():
@@ -337,12 +392,16 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--mode", default="all", choices=["all", "single", "batch", "serve"])
+    ap.add_argument("--mode", default="all", choices=["all", "single", "layouts", "batch", "serve", "converge"])
     ap.add_argument("--workload", default="grid4096")
     ap.add_argument("--layout", default="aos")
     ap.add_argument("--reorder", default="hilbert")
     ap.add_argument("--kernel", default="auto")
+    ap.add_argument("--tile-nodes", type=int, default=0)
+    ap.add_argument("--wg-per-cu", type=int, default=0)
+    ap.add_argument("--no-autotune", dest="autotune", action="store_false")
     ap.add_argument("--batch-meshes", type=int, default=1000)
+    ap.add_argument("--converge-cap", type=int, default=100000)
     ap.add_argument("--serve-rates", default="10,100,1000,2000")
     ap.add_argument("--serve-pool", type=int, default=48)
     ap.add_argument("--serve-seconds", type=float, default=3.0)
@@ -362,6 +421,10 @@ def main():
     out, m = {}, None
     if args.mode in ("all", "single"):
         out, m = run_single(args, sl, torch)
+    if args.mode == "converge":
+        out["converge"] = run_converge(args, sl, torch)
+    if args.mode in ("all", "layouts"):
+        out["layouts"] = run_layouts(args, sl, torch)
     if args.mode in ("all", "batch"):
         out["batched"] = run_batch(args, sl)
     if args.mode in ("all", "serve"):

@@ -190,6 +190,40 @@ typedef struct {
 SL_API sl_status sl_batch_smooth(const sl_mesh_desc* meshes, int32_t n_meshes, int32_t iterations, double tol,
                                  const sl_options* opts, sl_report* reports, sl_batch_report* batch);
 
+/* ---- adjacency from a triangle list -------------------------------------
+ * Builds the inputs the smoothing calls take from a bare triangle list, the
+ * way the paper finds neighbours and constraints (Sec. 3.3.2, Sec. 3.3.3):
+ *   tri_ptr/tri_idx  each node's incident triangles, in index order;
+ *   nbr_ptr/nbr_idx  each node's distinct neighbours: the other two vertices
+ *                    of its incident triangles, triangle by triangle in index
+ *                    order and, inside a triangle (v1,v2,v3), v2,v3 for v1,
+ *                    v1,v3 for v2 and v1,v2 for v3, each kept where it first
+ *                    appears (this row order is the centroid's summation
+ *                    order);
+ *   boundary         0 for a node every neighbour of which was seen exactly
+ *                    twice (every edge at the node lies in two triangles),
+ *                    else 1 (also for a node in no triangle).
+ * Sizes: nbr_ptr and tri_ptr n_nodes+1, tri_idx 3*n_tris, boundary n_nodes,
+ * nbr_idx nbr_capacity entries (6*n_tris always suffices); n_tris at most
+ * INT32_MAX/6.  *nnz receives nbr_ptr[n_nodes].  With nbr_idx NULL the call
+ * is a size query: only *nnz is written.
+ * Errors: SL_EINVAL for bad sizes, a null output, a vertex id out of range,
+ * or nbr_capacity < *nnz (then *nnz holds the size needed); SL_ETOPO for a
+ * triangle with a repeated vertex.  The other outputs are written only on
+ * SL_OK.  Work runs on the device; the rows are sorted and deduplicated
+ * there, one work-item per node.
+ * sl_build_adjacency: host arrays, synchronous. */
+SL_API sl_status sl_build_adjacency(const int32_t* tris, int32_t n_tris, int32_t n_nodes, int32_t* nbr_ptr,
+                                    int32_t* nbr_idx, int64_t nbr_capacity, int32_t* tri_ptr, int32_t* tri_idx,
+                                    uint8_t* boundary, int64_t* nnz);
+
+/* The same with every array in device memory (nnz is a host pointer); work
+ * runs on `stream` (a hipStream_t, NULL for the default stream) and is
+ * complete when the call returns. */
+SL_API sl_status sl_build_adjacency_device(const int32_t* tris, int32_t n_tris, int32_t n_nodes, int32_t* nbr_ptr,
+                                           int32_t* nbr_idx, int64_t nbr_capacity, int32_t* tri_ptr,
+                                           int32_t* tri_idx, uint8_t* boundary, int64_t* nnz, void* stream);
+
 /* ---- autotuning ---------------------------------------------------------
  * The launch shape of the tile kernel -- free nodes per tile (256 or 512)
  * and work-groups per compute unit -- changes only speed, never results.

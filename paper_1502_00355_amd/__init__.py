@@ -128,6 +128,11 @@ def lib():
         L.sl_batch_smooth.argtypes = [ctypes.POINTER(MeshDesc), i32, i32, d, ctypes.POINTER(Options),
                                       ctypes.POINTER(Report), ctypes.POINTER(BatchReport)]
         L.sl_batch_smooth.restype = ctypes.c_int
+        adj = [p, i32, i32, p, p, ctypes.c_int64, p, p, p, ctypes.POINTER(ctypes.c_int64)]
+        L.sl_build_adjacency.argtypes = adj
+        L.sl_build_adjacency.restype = ctypes.c_int
+        L.sl_build_adjacency_device.argtypes = adj + [p]
+        L.sl_build_adjacency_device.restype = ctypes.c_int
         L.sl_autotune.argtypes = [ctypes.POINTER(MeshDesc), i32, ctypes.POINTER(Options), ctypes.POINTER(Tuning)]
         L.sl_autotune.restype = ctypes.c_int
         L.sl_autotune_reset.argtypes = []
@@ -244,6 +249,50 @@ def batch_smooth(meshes, iterations: int, tol: float = 0.0, **opts):
     st = lib().sl_batch_smooth(arr, len(descs), int(iterations), float(tol), ctypes.byref(o), reps, ctypes.byref(br))
     _check(st)
     return [k[0] for k in keeps], list(reps), br
+
+
+def build_adjacency(n_nodes: int, tris):
+    """Host triangle list -> (nbr_ptr, nbr_idx, tri_ptr, tri_idx, boundary),
+    built on the device (sl_build_adjacency)."""
+    tr = _c(tris, np.int32).reshape(-1)
+    T = tr.size // 3
+    nnz = ctypes.c_int64(0)
+    _check(lib().sl_build_adjacency(tr.ctypes.data, T, int(n_nodes), None, None, 0, None, None, None,
+                                    ctypes.byref(nnz)))
+    nbr_ptr = np.empty(n_nodes + 1, np.int32)
+    nbr_idx = np.empty(max(nnz.value, 1), np.int32)
+    tri_ptr = np.empty(n_nodes + 1, np.int32)
+    tri_idx = np.empty(max(3 * T, 1), np.int32)
+    bnd = np.empty(n_nodes, np.uint8)
+    _check(lib().sl_build_adjacency(tr.ctypes.data, T, int(n_nodes), nbr_ptr.ctypes.data, nbr_idx.ctypes.data,
+                                    nbr_idx.size, tri_ptr.ctypes.data, tri_idx.ctypes.data, bnd.ctypes.data,
+                                    ctypes.byref(nnz)))
+    return nbr_ptr, nbr_idx[: nnz.value], tri_ptr, tri_idx[: 3 * T], bnd
+
+
+def build_adjacency_device(tris, n_nodes: int, stream=None):
+    """Device int32 triangle tensor (n_tris, 3) or (3*n_tris,) -> device
+    tensors (nbr_ptr, nbr_idx, tri_ptr, tri_idx, boundary)."""
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    if not tris.is_cuda or tris.dtype != torch.int32 or not tris.is_contiguous():
+        raise TypeError("expected a contiguous int32 device tensor")
+    T = tris.numel() // 3
+    dev = tris.device
+    nnz = ctypes.c_int64(0)
+    h = ctypes.c_void_p(stream.cuda_stream)
+    _check(lib().sl_build_adjacency_device(tris.data_ptr(), T, int(n_nodes), None, None, 0, None, None, None,
+                                           ctypes.byref(nnz), h))
+    nbr_ptr = torch.empty(n_nodes + 1, dtype=torch.int32, device=dev)
+    nbr_idx = torch.empty(max(nnz.value, 1), dtype=torch.int32, device=dev)
+    tri_ptr = torch.empty(n_nodes + 1, dtype=torch.int32, device=dev)
+    tri_idx = torch.empty(max(3 * T, 1), dtype=torch.int32, device=dev)
+    bnd = torch.empty(n_nodes, dtype=torch.uint8, device=dev)
+    _check(lib().sl_build_adjacency_device(tris.data_ptr(), T, int(n_nodes), nbr_ptr.data_ptr(), nbr_idx.data_ptr(),
+                                           nbr_idx.numel(), tri_ptr.data_ptr(), tri_idx.data_ptr(), bnd.data_ptr(),
+                                           ctypes.byref(nnz), h))
+    return nbr_ptr, nbr_idx[: nnz.value], tri_ptr, tri_idx[: 3 * T], bnd
 
 
 def autotune(meshes, **opts) -> Tuning:

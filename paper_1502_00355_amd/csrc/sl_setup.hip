@@ -134,6 +134,8 @@ struct ValArgs {
     int check_symmetry;
 };
 
+constexpr int kRowRegs = 16;
+
 __device__ __forceinline__ bool row_has(const int32_t* __restrict__ idx, int32_t b, int32_t e, int32_t v)
 {
     for (int32_t k = b; k < e; ++k)
@@ -170,35 +172,65 @@ __global__ __launch_bounds__(kBS) void k_validate_nodes(ValArgs a, ValStats* __r
         const bool trow_ok = 0 <= tb && tb <= te && te <= a.ninc;
         if (!row_ok || !trow_ok) e |= VE_PTR;
         is_free = a.boundary[i] == 0;
+        // rows of up to kRowRegs entries are held in registers for the
+        // membership tests below; longer rows are searched in memory
+        int32_t rowv[kRowRegs];
+        const bool in_regs = row_ok && en - b <= kRowRegs;
         if (row_ok) {
             deg = en - b;
-            for (int32_t k = b; k < en; ++k) {
-                const int32_t j = a.nbr_idx[k];
+#pragma unroll
+            for (int k = 0; k < kRowRegs; ++k) rowv[k] = (in_regs && k < deg) ? a.nbr_idx[b + k] : -1;
+            auto check = [&](int32_t j) {
                 if (j < 0 || j >= a.n) {
                     e |= VE_RANGE;
-                } else {
-                    if (j == i) e |= VE_SELF;
-                    if (is_free && a.check_symmetry && a.boundary[j] == 0) {
-                        const int32_t jb = a.nbr_ptr[j], je = a.nbr_ptr[j + 1];
-                        if (!(0 <= jb && jb <= je && je <= a.nnz) || !row_has(a.nbr_idx, jb, je, i)) e |= VE_ASYM;
-                    }
+                    return;
                 }
+                if (j == i) e |= VE_SELF;
+                if (is_free && a.check_symmetry && a.boundary[j] == 0) {
+                    const int32_t jb = a.nbr_ptr[j], je = a.nbr_ptr[j + 1];
+                    if (!(0 <= jb && jb <= je && je <= a.nnz) || !row_has(a.nbr_idx, jb, je, i)) e |= VE_ASYM;
+                }
+            };
+            if (in_regs) {
+#pragma unroll
+                for (int k = 0; k < kRowRegs; ++k)
+                    if (k < deg) check(rowv[k]);
+            } else {
+                for (int32_t k = b; k < en; ++k) check(a.nbr_idx[k]);
             }
             if (is_free && deg == 0) e |= VE_EMPTY;
             if (is_free && deg > kMaxValence) e |= VE_VALENCE;
         }
+        auto in_row = [&](int32_t v) -> bool {
+            if (!in_regs) return row_has(a.nbr_idx, b, en, v);
+            bool f = false;
+#pragma unroll
+            for (int k = 0; k < kRowRegs; ++k) f |= rowv[k] == v;
+            return f;
+        };
         if (trow_ok) {
             inc = te - tb;
-            for (int32_t k = tb; k < te; ++k) {
-                const int32_t t = a.tri_idx[k];
-                if (t < 0 || t >= a.n_tris) { e |= VE_RANGE; continue; }
-                const int32_t v[3] = {a.tris[3 * static_cast<int64_t>(t)], a.tris[3 * static_cast<int64_t>(t) + 1],
-                                      a.tris[3 * static_cast<int64_t>(t) + 2]};
-                const int p = v[0] == i ? 0 : (v[1] == i ? 1 : (v[2] == i ? 2 : -1));
-                if (p < 0) { e |= VE_NOTIN; continue; }
-                if (is_free && row_ok) {
-                    if (!row_has(a.nbr_idx, b, en, v[(p + 1) % 3]) || !row_has(a.nbr_idx, b, en, v[(p + 2) % 3]))
-                        e |= VE_MISSING;
+            // incident triangles four at a time: their loads are in flight together
+            for (int32_t k0 = tb; k0 < te; k0 += 4) {
+                int32_t t[4], v[4][3];
+#pragma unroll
+                for (int u = 0; u < 4; ++u) t[u] = k0 + u < te ? a.tri_idx[k0 + u] : -1;
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    const bool ok = t[u] >= 0 && t[u] < a.n_tris;
+                    if (k0 + u < te && !ok) e |= VE_RANGE;
+#pragma unroll
+                    for (int s3 = 0; s3 < 3; ++s3) v[u][s3] = ok ? a.tris[3 * static_cast<int64_t>(t[u]) + s3] : -1;
+                }
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    if (!(t[u] >= 0 && t[u] < a.n_tris)) continue;
+                    const int32_t v0 = v[u][0], v1 = v[u][1], v2 = v[u][2];
+                    if (v0 != i && v1 != i && v2 != i) { e |= VE_NOTIN; continue; }
+                    // the other two vertices, in stored cyclic order after i
+                    const int32_t o1 = v0 == i ? v1 : (v1 == i ? v2 : v0);
+                    const int32_t o2 = v0 == i ? v2 : (v1 == i ? v0 : v1);
+                    if (is_free && row_ok && (!in_row(o1) || !in_row(o2))) e |= VE_MISSING;
                 }
             }
         }
@@ -580,7 +612,6 @@ void devmesh_free(DevMesh& m, hipStream_t st)
     dfree(m.tri_loc, st);
 }
 
-// Free nodes per tile on the tile path (SMARTLAP_TILE_NODES overrides: 256 or 512).
 sl_status setup_mesh(const SetupArgs& a, const sl_options& o, DevMesh& m, int32_t mesh, hipStream_t st)
 {
     const int32_t n = a.n;

@@ -132,24 +132,34 @@ struct TileBuildArgs {
     const int32_t* tri_idx;
     const int32_t* tris;
     const int32_t* row_ptr;    // device-order rows of the free nodes
+    const int32_t* fan_ptr;    // device-order incidence offsets of the free nodes
     int32_t n_free;
-    int4* counts;              // pass 0: {halo count, triangle count, padded row length, 0} per tile
-    const int32_t* halo_off;   // pass 1 inputs
-    const int32_t* tri_off;
-    const int32_t* row_off;
-    int32_t* halo;
-    uint16_t* nbr_loc;
-    uint32_t* row_rel;
-    uint64_t* tri_loc;
+    int32_t mesh;              // MeshState index written into the descriptors
+    int64_t n;
+    const double* X;
+    int32_t* halo;             // [nnz_free]: tile k writes at row_ptr[k0] (halo <= row entries)
+    uint16_t* nbr_loc;         // tile k writes at align4(row_ptr[k0]) + 8k (segments never overlap)
+    uint32_t* row_rel;         // [n_tiles * T]
+    uint64_t* tri_loc;         // [ninc_free]: tile k writes at fan_ptr[k0] (kept <= incidences)
+    TileWork* work;            // [n_tiles]
+    int32_t* mx;               // {largest halo, largest padded row segment}
     int32_t* err;
 };
 
-// One work-group per tile.  Halo: every neighbour of an own node that is not
-// own, sorted and deduplicated.  Triangles: each triangle incident to an own
-// node, listed once per tile by its own vertex of smallest label.  Rows: the
-// tile's neighbour rows in local indices, one segment padded to 4 entries.
+__host__ __device__ __forceinline__ int64_t row_seg_off(int32_t row_start, int32_t tile)
+{
+    return ((static_cast<int64_t>(row_start) + 3) & ~int64_t(3)) + 8 * static_cast<int64_t>(tile);
+}
+
+// One work-group per tile, in one pass: every output of tile k goes to a
+// place fixed by the row and incidence offsets of its first node, so no
+// tile needs another's counts.  Halo: every neighbour of an own node that
+// is not own, sorted and deduplicated.  Triangles: each triangle incident to
+// an own node, listed once per tile by its own vertex of smallest label.
+// Rows: the tile's neighbour rows in local indices, one segment padded to 4
+// entries.
 template <int T>
-__global__ __launch_bounds__(kBuildBS) void k_tile_build(TileBuildArgs a, int pass)
+__global__ __launch_bounds__(kBuildBS) void k_tile_build(TileBuildArgs a)
 {
     constexpr int BS = kBuildBS, CAP = T * kTileMaxDeg, NPT = T / BS;
     __shared__ int32_t hb[CAP];
@@ -182,6 +192,31 @@ __global__ __launch_bounds__(kBuildBS) void k_tile_build(TileBuildArgs a, int pa
         }
         return true;
     };
+    auto local = [&](int32_t jd) -> int {
+        if (jd >= k0 && jd < k0 + nown) return jd - k0;
+        const int h = lower_bound_lds(hb, H, jd);
+        if (h >= H || hb[h] != jd) { atomicOr(a.err, 1); return T; }
+        return T + h;
+    };
+    const int32_t rb = a.row_ptr[k0];
+    const int32_t len = a.row_ptr[k0 + nown] - rb;
+    const int32_t len4 = (len + 3) & ~3;
+    int32_t* halo = a.halo + rb;
+    uint16_t* seg = a.nbr_loc + row_seg_off(rb, tile);
+    uint64_t* tri = a.tri_loc + a.fan_ptr[k0];
+    for (int h = threadIdx.x; h < H; h += BS) halo[h] = hb[h];
+    uint32_t* rr = a.row_rel + static_cast<int64_t>(tile) * T;
+    for (int i = threadIdx.x; i < T; i += BS)
+        rr[i] = static_cast<uint32_t>(a.row_ptr[k0 + min(i, nown)] - rb) |
+                (static_cast<uint32_t>(a.row_ptr[k0 + min(i + 1, nown)] - rb) << 16);
+    for (int j = len + threadIdx.x; j < len4; j += BS) seg[j] = 0;
+    for (int m = 0; m < NPT; ++m) {
+        const int i = m * BS + threadIdx.x;
+        if (i >= nown) continue;
+        const int32_t o = a.perm[k0 + i];
+        const int32_t b = a.nbr_ptr[o], d = a.nbr_ptr[o + 1] - b, out = a.row_ptr[k0 + i] - rb;
+        for (int j = 0; j < d; ++j) seg[out + j] = static_cast<uint16_t>(local(a.new_of_old[a.nbr_idx[b + j]]));
+    }
     // triangles are listed in node order (work-item t lists nodes NPT*t ..
     // NPT*t+NPT-1), so that the lanes of a wave walking the list touch one
     // compact patch of nodes in LDS
@@ -195,34 +230,6 @@ __global__ __launch_bounds__(kBuildBS) void k_tile_build(TileBuildArgs a, int pa
     }
     int R;
     int tpos = block_excl_scan<BS>(c, &R, s_warp);
-    const int32_t rb = a.row_ptr[k0];
-    const int32_t len = a.row_ptr[k0 + nown] - rb;
-    const int32_t len4 = (len + 3) & ~3;
-    if (pass == 0) {
-        if (threadIdx.x == 0) a.counts[tile] = make_int4(H, R, len4, 0);
-        return;
-    }
-    const int32_t hoff = a.halo_off[tile], toff = a.tri_off[tile], roff = a.row_off[tile];
-    for (int h = threadIdx.x; h < H; h += BS) a.halo[hoff + h] = hb[h];
-    uint32_t* rr = a.row_rel + static_cast<int64_t>(tile) * T;
-    for (int i = threadIdx.x; i < T; i += BS)
-        rr[i] = static_cast<uint32_t>(a.row_ptr[k0 + min(i, nown)] - rb) |
-                (static_cast<uint32_t>(a.row_ptr[k0 + min(i + 1, nown)] - rb) << 16);
-    auto local = [&](int32_t jd) -> int {
-        if (jd >= k0 && jd < k0 + nown) return jd - k0;
-        const int h = lower_bound_lds(hb, H, jd);
-        if (h >= H || hb[h] != jd) { atomicOr(a.err, 1); return T; }
-        return T + h;
-    };
-    uint16_t* seg = a.nbr_loc + roff;
-    for (int j = len + threadIdx.x; j < len4; j += BS) seg[j] = 0;
-    for (int m = 0; m < NPT; ++m) {
-        const int i = m * BS + threadIdx.x;
-        if (i >= nown) continue;
-        const int32_t o = a.perm[k0 + i];
-        const int32_t b = a.nbr_ptr[o], d = a.nbr_ptr[o + 1] - b, out = a.row_ptr[k0 + i] - rb;
-        for (int j = 0; j < d; ++j) seg[out + j] = static_cast<uint16_t>(local(a.new_of_old[a.nbr_idx[b + j]]));
-    }
     for (int m = 0; m < NPT; ++m) {
         const int i = NPT * threadIdx.x + m;
         if (i >= nown) continue;
@@ -233,58 +240,31 @@ __global__ __launch_bounds__(kBuildBS) void k_tile_build(TileBuildArgs a, int pa
             uint64_t w = 0;
             for (int s = 0; s < 3; ++s)
                 w |= static_cast<uint64_t>(local(a.new_of_old[a.tris[3 * t + s]])) << (16 * s);
-            a.tri_loc[toff + tpos++] = w;
+            tri[tpos++] = w;
         }
     }
-}
-
-__global__ void k_split_counts(const int4* __restrict__ c, int n, int32_t* __restrict__ h, int32_t* __restrict__ r,
-                               int32_t* __restrict__ l)
-{
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) { h[i] = c[i].x; r[i] = c[i].y; l[i] = c[i].z; }
-}
-
-// Tile descriptors of one mesh, and the largest halo / row segment.
-__global__ void k_tile_work(const int4* __restrict__ c, const int32_t* __restrict__ hoff,
-                            const int32_t* __restrict__ toff, const int32_t* __restrict__ roff, int nt, int T,
-                            int32_t n_free, int64_t n, int32_t mesh, const double* X, const int32_t* halo,
-                            const uint16_t* nbr_loc, const uint64_t* tri_loc, const uint32_t* row_rel,
-                            TileWork* __restrict__ work, int32_t* __restrict__ mx)
-{
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    int mh = 0, ml = 0;
-    if (i < nt) {
+    if (threadIdx.x == 0) {
         TileWork w;
-        w.X = X;
-        w.halo = halo + hoff[i];
-        w.rows = reinterpret_cast<const uint64_t*>(nbr_loc + roff[i]);
-        w.tris = tri_loc + toff[i];
-        w.rr = row_rel + static_cast<int64_t>(i) * T;
-        w.own_start = i * T;
-        w.nown = min(T, n_free - i * T);
-        w.halo_cnt = c[i].x;
-        w.tri_cnt = c[i].y;
-        w.row_words = c[i].z >> 2;
-        w.mesh = mesh;
-        w.n = n;
-        work[i] = w;
-        mh = c[i].x;
-        ml = c[i].z;
-    }
-    for (int off = 32; off > 0; off >>= 1) {
-        mh = max(mh, __shfl_xor(mh, off));
-        ml = max(ml, __shfl_xor(ml, off));
-    }
-    if ((threadIdx.x & 63) == 0) {
-        atomicMax(mx, mh);
-        atomicMax(mx + 1, ml);
+        w.X = a.X;
+        w.halo = halo;
+        w.rows = reinterpret_cast<const uint64_t*>(seg);
+        w.tris = tri;
+        w.rr = rr;
+        w.own_start = k0;
+        w.nown = nown;
+        w.halo_cnt = H;
+        w.tri_cnt = R;
+        w.row_words = len4 >> 2;
+        w.mesh = a.mesh;
+        w.n = a.n;
+        a.work[tile] = w;
+        atomicMax(a.mx, H);
+        atomicMax(a.mx + 1, len4);
     }
 }
 
 // ------------------------------------------------------------ tile sweep --
 
-// Order-preserving 64-bit key of a double (for LDS atomic minima).
 // Minimum into an LDS double (one ds_min_f64).  Qualities are finite --
 // coordinates are validated below 2^500 in magnitude and S == 0 gives 0 --
 // so no NaN reaches it; which zero a min keeps when +0 meets -0 does not
@@ -684,22 +664,16 @@ sl_status build_tiles(const SetupArgs& a, DevMesh& m, int tile_nodes, int mesh, 
     const int T = tile_nodes;
     const int nt = div_up(m.n_free, T);
     sl_status r = SL_OK;
-    int4* counts = nullptr;
-    int32_t *hc = nullptr, *rc = nullptr, *lc = nullptr, *hoff = nullptr, *toff = nullptr, *roff = nullptr;
-    int32_t *err = nullptr, *mx = nullptr;
-    auto cleanup = [&] {
-        dfree(counts, st); dfree(hc, st); dfree(rc, st); dfree(lc, st); dfree(hoff, st); dfree(toff, st);
-        dfree(roff, st); dfree(err, st); dfree(mx, st);
-    };
-    const size_t n1 = static_cast<size_t>(nt) + 1;
-    if ((r = dalloc(&counts, nt, st)) || (r = dalloc(&hc, nt, st)) || (r = dalloc(&rc, nt, st)) ||
-        (r = dalloc(&lc, nt, st)) || (r = dalloc(&hoff, n1, st)) || (r = dalloc(&toff, n1, st)) ||
-        (r = dalloc(&roff, n1, st)) || (r = dalloc(&err, 1, st)) || (r = dalloc(&mx, 2, st))) {
-        cleanup();
+    int32_t* flags = nullptr;   // {err, largest halo, largest row segment}
+    if ((r = dalloc(&flags, 3, st))) return r;
+    SL_HIP(hipMemsetAsync(flags, 0, 3 * sizeof(int32_t), st));
+    if ((r = dalloc(&m.work, nt, st)) || (r = dalloc(&m.halo, std::max<int64_t>(m.nnz_free, 1), st)) ||
+        (r = dalloc(&m.nbr_loc, static_cast<size_t>(m.nnz_free) + 8 * static_cast<size_t>(nt) + 8, st)) ||
+        (r = dalloc(&m.row_rel, static_cast<size_t>(nt) * T, st)) ||
+        (r = dalloc(&m.tri_loc, std::max<int64_t>(m.ninc_free, 1), st))) {
+        dfree(flags, st);
         return r;
     }
-    SL_HIP(hipMemsetAsync(err, 0, sizeof(int32_t), st));
-    SL_HIP(hipMemsetAsync(mx, 0, 2 * sizeof(int32_t), st));
     TileBuildArgs b{};
     b.perm = m.perm;
     b.new_of_old = m.new_of_old;
@@ -709,45 +683,34 @@ sl_status build_tiles(const SetupArgs& a, DevMesh& m, int tile_nodes, int mesh, 
     b.tri_idx = a.tri_idx;
     b.tris = a.tris;
     b.row_ptr = m.row_ptr;
+    b.fan_ptr = m.fan_ptr;
     b.n_free = m.n_free;
-    b.counts = counts;
-    b.err = err;
-    if (T == 256) k_tile_build<256><<<nt, kBuildBS, 0, st>>>(b, 0);
-    else k_tile_build<512><<<nt, kBuildBS, 0, st>>>(b, 0);
-    k_split_counts<<<div_up(nt, 256), 256, 0, st>>>(counts, nt, hc, rc, lc);
-    if ((r = scan_exclusive(hc, hoff, nt, st)) || (r = scan_exclusive(rc, toff, nt, st)) ||
-        (r = scan_exclusive(lc, roff, nt, st))) {
-        cleanup();
-        return r;
-    }
-    int32_t tot[3] = {0, 0, 0};
-    SL_HIP(hipMemcpyAsync(&tot[0], hoff + nt, sizeof(int32_t), hipMemcpyDeviceToHost, st));
-    SL_HIP(hipMemcpyAsync(&tot[1], toff + nt, sizeof(int32_t), hipMemcpyDeviceToHost, st));
-    SL_HIP(hipMemcpyAsync(&tot[2], roff + nt, sizeof(int32_t), hipMemcpyDeviceToHost, st));
-    SL_HIP(hipStreamSynchronize(st));
-    if ((r = dalloc(&m.work, nt, st)) || (r = dalloc(&m.halo, tot[0], st)) || (r = dalloc(&m.nbr_loc, tot[2], st)) ||
-        (r = dalloc(&m.row_rel, static_cast<size_t>(nt) * T, st)) || (r = dalloc(&m.tri_loc, tot[1], st))) {
-        cleanup();
-        return r;
-    }
-    b.halo_off = hoff;
-    b.tri_off = toff;
-    b.row_off = roff;
+    b.mesh = mesh;
+    b.n = m.n;
+    b.X = m.X[0];
     b.halo = m.halo;
     b.nbr_loc = m.nbr_loc;
     b.row_rel = m.row_rel;
     b.tri_loc = m.tri_loc;
-    if (T == 256) k_tile_build<256><<<nt, kBuildBS, 0, st>>>(b, 1);
-    else k_tile_build<512><<<nt, kBuildBS, 0, st>>>(b, 1);
-    k_tile_work<<<div_up(nt, 256), 256, 0, st>>>(counts, hoff, toff, roff, nt, T, m.n_free, m.n, mesh, m.X[0],
-                                                 m.halo, m.nbr_loc, m.tri_loc, m.row_rel, m.work, mx);
+    b.work = m.work;
+    b.err = flags;
+    b.mx = flags + 1;
+    if (T == 256) k_tile_build<256><<<nt, kBuildBS, 0, st>>>(b);
+    else k_tile_build<512><<<nt, kBuildBS, 0, st>>>(b);
+    SL_HIP(hipGetLastError());
     int32_t h[3] = {0, 0, 0};
-    SL_HIP(hipMemcpyAsync(&h[0], err, sizeof(int32_t), hipMemcpyDeviceToHost, st));
-    SL_HIP(hipMemcpyAsync(&h[1], mx, 2 * sizeof(int32_t), hipMemcpyDeviceToHost, st));
+    SL_HIP(hipMemcpyAsync(h, flags, 3 * sizeof(int32_t), hipMemcpyDeviceToHost, st));
     SL_HIP(hipStreamSynchronize(st));
-    cleanup();
+    dfree(flags, st);
     if (h[0]) return fail(SL_ETOPO, "triangle vertex outside its tile's neighbourhood");
-    if (tile_lds_bytes(T, h[1], h[2]) > static_cast<size_t>(kLdsLimit)) return SL_OK;   // node path
+    if (tile_lds_bytes(T, h[1], h[2]) > static_cast<size_t>(kLdsLimit)) {   // too big for LDS: node path
+        dfree(m.work, st);
+        dfree(m.halo, st);
+        dfree(m.nbr_loc, st);
+        dfree(m.row_rel, st);
+        dfree(m.tri_loc, st);
+        return SL_OK;
+    }
     m.halo_max = h[1];
     m.rows_max = h[2];
     m.n_tiles = nt;

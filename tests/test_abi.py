@@ -94,3 +94,20 @@ def test_autotune_argument_errors(L):
     o = sl.make_options(form=3)
     d.n_nodes = 4
     assert L.sl_autotune(arr, 1, ctypes.byref(o), ctypes.byref(t)) == sl.SL_EINVAL
+
+
+def test_adjacency_argument_errors_before_device_work(L):
+    tris = np.array([0, 1, 2], np.int32)
+    nnz = ctypes.c_int64(-1)
+    assert L.sl_build_adjacency(tris.ctypes.data, 1, 0, None, None, 0, None, None, None, ctypes.byref(nnz)) == \
+        sl.SL_EINVAL
+    assert b"n_nodes" in L.sl_last_error()
+    assert L.sl_build_adjacency(tris.ctypes.data, -1, 3, None, None, 0, None, None, None, ctypes.byref(nnz)) == \
+        sl.SL_EINVAL
+    assert L.sl_build_adjacency(None, 1, 3, None, None, 0, None, None, None, ctypes.byref(nnz)) == sl.SL_EINVAL
+    assert L.sl_build_adjacency(tris.ctypes.data, 1, 3, None, None, 0, None, None, None, None) == sl.SL_EINVAL
+    out = np.zeros(8, np.int32)
+    assert L.sl_build_adjacency(tris.ctypes.data, 1, 3, None, out.ctypes.data, 8, None, None, None,
+                                ctypes.byref(nnz)) == sl.SL_EINVAL
+    assert b"null output" in L.sl_last_error()
+    assert nnz.value == -1
