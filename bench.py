@@ -233,6 +233,42 @@ def run_converge(args, sl, torch):
             "sweep_node_updates_per_s": m.n_interior * r.iterations_run / (r.sweep_ms / 1e3)}
 
 
+def run_paper(args, sl, torch):
+    """Meshes like the paper's (Sec. 4, Tables 6-9): Delaunay meshes of
+    1K-100K uniformly random points, 100 sweeps of Form A (AoS and SoA) and
+    Form B, GPU against the oracle on one host thread.  GPU time is the whole
+    smooth_mesh call (host arrays in and out) and, separately, the sweep
+    loop; the paper used FP32 and does not state its sweep counts, so its
+    numbers are context only."""
+    import meshgen
+    import oracle
+    rows = []
+    for n in (1000, 5000, 10000, 50000, 100000):
+        m = meshgen.make_delaunay(n, 11)
+        row = {"points": n, "free_nodes": m.n_interior, "triangles": m.n_tris}
+        for label, opts in (("A_aos", {}), ("A_soa", {"layout": "soa"}), ("B_aos", {"form": "colored"})):
+            best = None
+            for _ in range(3):
+                t = time.perf_counter()
+                _, r, _ = sl.smooth_mesh(m.coords, m.nbr_ptr, m.nbr_idx, m.tri_ptr, m.tri_idx, m.tris, m.boundary,
+                                         100, **opts)
+                el = (time.perf_counter() - t) * 1e3
+                best = (el, r.sweep_ms) if best is None or el < best[0] else best
+            row["gpu_" + label + "_ms"] = best[0]
+            row["gpu_" + label + "_sweep_ms"] = best[1]
+        for label, form in (("A", "jacobi"), ("B", "colored")):
+            t = time.perf_counter()
+            oracle.smooth(m, 100, threads=1, want_flags=False, form=form)
+            row["cpu_" + label + "_ms"] = (time.perf_counter() - t) * 1e3
+        row["speedup_A_aos"] = row["cpu_A_ms"] / row["gpu_A_aos_ms"]
+        row["speedup_B_aos"] = row["cpu_B_ms"] / row["gpu_B_aos_ms"]
+        log("paper mesh %d: GPU A %.2f ms (sweeps %.2f), CPU A %.0f ms, speedup %.1f" %
+            (n, row["gpu_A_aos_ms"], row["gpu_A_aos_sweep_ms"], row["cpu_A_ms"], row["speedup_A_aos"]))
+        rows.append(row)
+    return {"workload": "delaunay_uniform_points_1K-100K_s11", "sweeps": 100, "dtype": "f64", "cpu_threads": 1,
+            "rows": rows}
+
+
 def gen_meshes(specs):
     """specs: list of (side, diag, jitter, seed); generated on host threads."""
     import meshgen
@@ -392,7 +428,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--mode", default="all", choices=["all", "single", "layouts", "batch", "serve", "converge"])
+    ap.add_argument("--mode", default="all", choices=["all", "single", "layouts", "paper", "batch", "serve", "converge"])
     ap.add_argument("--workload", default="grid4096")
     ap.add_argument("--layout", default="aos")
     ap.add_argument("--reorder", default="hilbert")
@@ -425,6 +461,8 @@ def main():
         out["converge"] = run_converge(args, sl, torch)
     if args.mode in ("all", "layouts"):
         out["layouts"] = run_layouts(args, sl, torch)
+    if args.mode in ("all", "paper"):
+        out["paper_tables"] = run_paper(args, sl, torch)
     if args.mode in ("all", "batch"):
         out["batched"] = run_batch(args, sl)
     if args.mode in ("all", "serve"):

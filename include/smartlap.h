@@ -73,8 +73,9 @@ typedef enum { SL_REORDER_NONE = 0, SL_REORDER_HILBERT = 1 } sl_reorder;
 typedef enum {
     SL_KERNEL_AUTO = 0,  /* tile kernel for Form A when the mesh fits it, else the node kernel */
     SL_KERNEL_NODE = 1,  /* one work-item per free node, neighbours gathered from HBM/L2 */
-    SL_KERNEL_TILE = 2   /* work-group per tile of free nodes staged in LDS (Form A only;
-                            valence and incidence <= 16), falls back to the node kernel */
+    SL_KERNEL_TILE = 2   /* work-group per tile of free nodes staged in LDS (Form A only; at
+                            most 16 neighbour entries per node on average over a tile, and
+                            its halo and rows must fit in LDS), else the node kernel */
 } sl_kernel;
 
 typedef struct {

@@ -66,6 +66,8 @@ def _native():
         lib.mg_build_adjacency.argtypes = [ctypes.c_int32, ctypes.c_int32, p, p, p, p, p, p,
                                            ctypes.POINTER(ctypes.c_int64)]
         lib.mg_build_adjacency.restype = ctypes.c_int
+        lib.mg_delaunay.argtypes = [ctypes.c_int32, p, p, p, ctypes.POINTER(ctypes.c_int32)]
+        lib.mg_delaunay.restype = ctypes.c_int
         _lib = lib
     return _lib
 
@@ -246,6 +248,50 @@ def star_mesh(center, ring) -> Mesh:
     tris = np.array([[0, 1 + q, 1 + (q + 1) % k] for q in range(k)], dtype=np.int32)
     nbr_ptr, nbr_idx, tri_ptr, tri_idx, bnd = build_adjacency(k + 1, tris)
     return Mesh(coords, tris, nbr_ptr, nbr_idx, tri_ptr, tri_idx, bnd, name="star%d" % k)
+
+
+LATTICE_BITS = 20
+
+
+def delaunay_triangles(xi: np.ndarray, yi: np.ndarray) -> np.ndarray:
+    """CCW Delaunay triangles of distinct integer lattice points (exact
+    predicates; see mg_delaunay)."""
+    xi = np.ascontiguousarray(xi, dtype=np.int64)
+    yi = np.ascontiguousarray(yi, dtype=np.int64)
+    n = xi.size
+    out = np.zeros(max(3 * (2 * n), 3), np.int32)
+    nt = ctypes.c_int32(0)
+    rc = _native().mg_delaunay(n, xi.ctypes.data, yi.ctypes.data, out.ctypes.data, ctypes.byref(nt))
+    if rc != 0:
+        raise ValueError("mg_delaunay failed (%d)" % rc)
+    return out[: 3 * nt.value].reshape(-1, 3).copy()
+
+
+def random_lattice_points(n: int, seed: int):
+    """n distinct points drawn uniformly from the 2^20 x 2^20 lattice, in
+    draw order: (xi, yi) integers."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    side = 1 << LATTICE_BITS
+    codes = np.empty(0, np.int64)
+    while codes.size < n:
+        draw = rng.integers(0, side * side, size=n + n // 8 + 16, dtype=np.int64)
+        allc = np.concatenate([codes, draw])
+        _, first = np.unique(allc, return_index=True)
+        codes = allc[np.sort(first)]
+    codes = codes[:n]
+    return codes % side, codes // side
+
+
+def make_delaunay(n: int, seed: int = 0, name: str = "") -> Mesh:
+    """Delaunay mesh of n uniformly random points in the unit square (the
+    paper's test meshes, Sec. 4): points on the 2^20 lattice, coordinates
+    lattice / 2^20 (exact), node id = draw order, triangles in construction
+    order; the boundary is the convex hull."""
+    xi, yi = random_lattice_points(n, seed)
+    tris = delaunay_triangles(xi, yi)
+    coords = np.stack([xi, yi], axis=1).astype(np.float64) * (2.0 ** -LATTICE_BITS)
+    nbr_ptr, nbr_idx, tri_ptr, tri_idx, bnd = build_adjacency(n, tris)
+    return Mesh(coords, tris, nbr_ptr, nbr_idx, tri_ptr, tri_idx, bnd, name or "delaunay%d_s%d" % (n, seed))
 
 
 def batch_sides(count: int, lo: int, hi: int, seed: int) -> np.ndarray:

@@ -33,7 +33,7 @@ namespace sl {
 namespace {
 
 constexpr double kTwoSqrt3 = 0x1.bb67ae8584caap+1;   // 2*sqrt(3) rounded to double
-constexpr int kTileMaxDeg = 16;                       // valence / incidence limit of the tile path
+constexpr int kTileMaxDeg = 16;                       // neighbour entries per own node, on average over a tile
 constexpr int kBuildBS = 256;
 
 // ------------------------------------------------------ block primitives --
@@ -168,6 +168,12 @@ __global__ __launch_bounds__(kBuildBS) void k_tile_build(TileBuildArgs a)
     const int tile = blockIdx.x;
     const int32_t k0 = tile * T;
     const int nown = min(T, a.n_free - k0);
+    const int32_t rb = a.row_ptr[k0];
+    const int32_t len = a.row_ptr[k0 + nown] - rb;
+    if (len > CAP) {   // more neighbour entries than the halo staging holds: the mesh takes the node path
+        if (threadIdx.x == 0) atomicOr(a.err, 2);
+        return;
+    }
     if (threadIdx.x == 0) s_cnt = 0;
     __syncthreads();
     for (int i = threadIdx.x; i < nown; i += BS) {
@@ -198,8 +204,6 @@ __global__ __launch_bounds__(kBuildBS) void k_tile_build(TileBuildArgs a)
         if (h >= H || hb[h] != jd) { atomicOr(a.err, 1); return T; }
         return T + h;
     };
-    const int32_t rb = a.row_ptr[k0];
-    const int32_t len = a.row_ptr[k0 + nown] - rb;
     const int32_t len4 = (len + 3) & ~3;
     int32_t* halo = a.halo + rb;
     uint16_t* seg = a.nbr_loc + row_seg_off(rb, tile);
@@ -658,9 +662,7 @@ size_t tile_lds_bytes(int tile_nodes, int halo_cap, int rows_cap)
 sl_status build_tiles(const SetupArgs& a, DevMesh& m, int tile_nodes, int mesh, hipStream_t st)
 {
     m.tile_nodes = 0;
-    if ((tile_nodes != 256 && tile_nodes != 512) || m.n_free == 0 || m.max_deg > kTileMaxDeg ||
-        m.max_inc > kTileMaxDeg)
-        return SL_OK;
+    if ((tile_nodes != 256 && tile_nodes != 512) || m.n_free == 0) return SL_OK;
     const int T = tile_nodes;
     const int nt = div_up(m.n_free, T);
     sl_status r = SL_OK;
@@ -702,8 +704,10 @@ sl_status build_tiles(const SetupArgs& a, DevMesh& m, int tile_nodes, int mesh, 
     SL_HIP(hipMemcpyAsync(h, flags, 3 * sizeof(int32_t), hipMemcpyDeviceToHost, st));
     SL_HIP(hipStreamSynchronize(st));
     dfree(flags, st);
-    if (h[0]) return fail(SL_ETOPO, "triangle vertex outside its tile's neighbourhood");
-    if (tile_lds_bytes(T, h[1], h[2]) > static_cast<size_t>(kLdsLimit)) {   // too big for LDS: node path
+    if (h[0] & 1) return fail(SL_ETOPO, "triangle vertex outside its tile's neighbourhood");
+    // a tile denser than the staging holds, or a halo or row segment too big
+    // for LDS: the node path
+    if ((h[0] & 2) || tile_lds_bytes(T, h[1], h[2]) > static_cast<size_t>(kLdsLimit)) {
         dfree(m.work, st);
         dfree(m.halo, st);
         dfree(m.nbr_loc, st);

@@ -223,8 +223,32 @@ def _ring_star(k, seed):
 @pytest.mark.parametrize("k", [3, 8, 9, 16, 17, 32, 33, 100, 127])
 def test_valence_classes(k):
     X, rep, ref, _ = assert_parity(_ring_star(k, k), 3)
-    assert rep.kernel_used == (sl.KERNELS["tile"] if k <= 16 else sl.KERNELS["node"])
+    assert rep.kernel_used == sl.KERNELS["tile"]
     assert_parity(_ring_star(k, k), 3, kernel="node")
+
+
+def _many_stars(count, k, seed):
+    """count disjoint ring stars of valence k in one mesh: the free nodes are
+    the centres, each with k neighbour entries."""
+    coords, tris, off = [], [], 0
+    for s in range(count):
+        st = _ring_star(k, seed + s)
+        coords.append(st.coords + np.array([3.0 * (s % 40), 3.0 * (s // 40)]))
+        tris.append(st.tris + off)
+        off += st.n_nodes
+    coords = np.concatenate(coords)
+    tris = np.concatenate(tris)
+    nbr_ptr, nbr_idx, tri_ptr, tri_idx, bnd = meshgen.build_adjacency(coords.shape[0], tris)
+    return meshgen.Mesh(coords, tris, nbr_ptr, nbr_idx, tri_ptr, tri_idx, bnd, "stars%dx%d" % (count, k))
+
+
+def test_tiles_too_dense_fall_back_to_the_node_kernel():
+    m = _many_stars(600, 20, 5)            # 512 centres x 20 entries > 16 per node on average
+    X, rep, ref, nd = assert_parity(m, 3)
+    assert nd == 0 and rep.kernel_used == sl.KERNELS["node"]
+    m = _many_stars(600, 12, 5)           # 12 per node: tiles and their halos fit
+    X, rep, ref, nd = assert_parity(m, 3)
+    assert nd == 0 and rep.kernel_used == sl.KERNELS["tile"]
 
 
 def test_tile_path_at_every_tile_boundary():
@@ -288,6 +312,41 @@ def test_extreme_coordinate_scales(exp2):
     m.coords = m.coords * (2.0 ** exp2) + (2.0 ** exp2) * 0.25
     m.name = "grid45_scaled_2^%d" % exp2
     X, rep, ref, ndiff = assert_parity(m, 6)
+    assert ndiff == 0
+
+
+@pytest.mark.parametrize("n", [1000, 10000, 100000])
+def test_delaunay_random_points(n):
+    """The paper's kind of mesh: Delaunay triangulations of uniformly random
+    points (valence up to about 17), Form A on both layouts and Form B."""
+    m = meshgen.make_delaunay(n, 11)
+    X, rep, ref, nd = assert_parity(m, 20)
+    assert nd == 0 and rep.kernel_used == sl.KERNELS["tile"]
+    if n <= 10000:
+        X, rep, ref, nd = assert_parity(m, 20, layout="soa")
+        assert nd == 0
+        X, rep, ref, nd = assert_parity(m, 10, form="colored")
+        assert nd == 0
+
+
+def test_coincident_vertices():
+    """Triangles whose three vertices coincide (S == 0, quality 0) and edges
+    of zero length: the device follows the oracle."""
+    m = meshgen.make_grid(20, "random", 0.3, 41)
+    tris = m.tris
+    free = m.boundary == 0
+    picked = 0
+    for t in range(len(tris)):
+        a, b, c = tris[t]
+        if free[a] and free[b] and free[c]:
+            m.coords[b] = m.coords[a]
+            m.coords[c] = m.coords[a]
+            picked += 1
+            if picked == 3:
+                break
+    m.coords[tris[200][1]] = m.coords[tris[200][0]]      # one zero-length edge
+    m.name = "grid20_coincident"
+    X, rep, ref, ndiff = assert_parity(m, 8)
     assert ndiff == 0
 
 
