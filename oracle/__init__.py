@@ -46,6 +46,11 @@ def _c():
         lib.slref_smooth.restype = i32
         lib.slref_smooth_colored.argtypes = [p, i32, p, p, p, p, p, i32, p, i32, d, ctypes.c_int, p, p, p, p]
         lib.slref_smooth_colored.restype = i32
+        f = ctypes.c_float
+        lib.slref32_quality.argtypes = [f] * 6
+        lib.slref32_quality.restype = f
+        lib.slref32_smooth.argtypes = [p, i32, p, p, p, p, p, i32, p, i32, d, ctypes.c_int, ctypes.c_int, p, p, p]
+        lib.slref32_smooth.restype = i32
         lib.slref_color.argtypes = [i32, p, p, p, p]
         lib.slref_color.restype = i32
         lib.slref_priority.argtypes = [ctypes.c_uint64]
@@ -65,6 +70,11 @@ def quality(x0, y0, x1, y1, x2, y2) -> float:
     return _c().slref_quality(x0, y0, x1, y1, x2, y2)
 
 
+def quality32(x0, y0, x1, y1, x2, y2) -> float:
+    """The same quality in IEEE single precision (arguments rounded to float)."""
+    return _c().slref32_quality(x0, y0, x1, y1, x2, y2)
+
+
 def max_threads() -> int:
     return _c().slref_max_threads()
 
@@ -80,9 +90,11 @@ class Result:
 
 
 def smooth(mesh, iterations: int, tol: float = 0.0, accept_gt: bool = False, threads: int = 1,
-           want_flags: bool = True, form: str = "jacobi") -> Result:
+           want_flags: bool = True, form: str = "jacobi", precision: str = "f64") -> Result:
     """Run the oracle on a ``meshgen.Mesh`` (or any object with the same
-    array attributes).  ``form``: "jacobi" (Form A) or "colored" (Form B)."""
+    array attributes).  ``form``: "jacobi" (Form A) or "colored" (Form B).
+    ``precision``: "f64", or "f32" (Form A in single precision: coordinates
+    rounded to float on entry, float results returned as doubles)."""
     lib = _c()
     X = _arr(mesh.coords, np.float64).copy()
     n = X.shape[0]
@@ -93,7 +105,17 @@ def smooth(mesh, iterations: int, tol: float = 0.0, accept_gt: bool = False, thr
     disp = np.zeros(max(iterations, 1), np.float64)
     acc = np.zeros(max(iterations, 1), np.int64)
     fptr = flags.ctypes.data if flags is not None else None
-    if form == "jacobi":
+    if precision not in ("f64", "f32"):
+        raise ValueError(precision)
+    if precision == "f32":
+        if form != "jacobi":
+            raise ValueError("single precision is Form A only")
+        k = lib.slref32_smooth(X.ctypes.data, n, nbr_ptr.ctypes.data, nbr_idx.ctypes.data, tri_ptr.ctypes.data,
+                               tri_idx.ctypes.data, tris.ctypes.data,
+                               tris.shape[0] if tris.ndim == 2 else len(tris) // 3, bnd.ctypes.data, iterations,
+                               tol, int(accept_gt), threads, fptr, disp.ctypes.data, acc.ctypes.data)
+        colors = None
+    elif form == "jacobi":
         k = lib.slref_smooth(X.ctypes.data, n, nbr_ptr.ctypes.data, nbr_idx.ctypes.data, tri_ptr.ctypes.data,
                              tri_idx.ctypes.data, tris.ctypes.data, tris.shape[0] if tris.ndim == 2 else len(tris) // 3,
                              bnd.ctypes.data, iterations, tol, int(accept_gt), threads, fptr, disp.ctypes.data,

@@ -293,6 +293,121 @@ int32_t slref_smooth_colored(double* coords, int32_t n, const int32_t* nbr_ptr, 
     return k;
 }
 
+/* ---- single precision (the paper's precision, Sec. 4) ------------------ */
+
+/* The same Form A computation carried out in IEEE single precision: the
+ * caller's coordinates are rounded to float once, every operation below is
+ * one float operation in the order written, and the constant is the float
+ * nearest 2*sqrt(3) (sqrtf is correctly rounded, the doubling exact).  The
+ * convergence test widens the float squared displacement to double. */
+static float two_sqrt3f(void) { return 2.0f * sqrtf(3.0f); }
+
+float slref32_quality(float x0, float y0, float x1, float y1, float x2, float y2)
+{
+    float ax = x1 - x0, ay = y1 - y0;
+    float bx = x2 - x0, by = y2 - y0;
+    float cx = x2 - x1, cy = y2 - y1;
+    float cr = ax * by - bx * ay;
+    float la = ax * ax + ay * ay;
+    float lb = bx * bx + by * by;
+    float lc = cx * cx + cy * cy;
+    float S = (la + lc) + lb;
+    if (S == 0.0f) return 0.0f;
+    return (two_sqrt3f() * cr) / S;
+}
+
+static float tri_q32(const float* X, const int32_t* tris, int32_t t, int32_t who, float wx, float wy)
+{
+    float px[3], py[3];
+    for (int s = 0; s < 3; ++s) {
+        int32_t v = tris[3 * (int64_t)t + s];
+        if (v == who) { px[s] = wx; py[s] = wy; }
+        else { px[s] = X[2 * (int64_t)v]; py[s] = X[2 * (int64_t)v + 1]; }
+    }
+    return slref32_quality(px[0], py[0], px[1], py[1], px[2], py[2]);
+}
+
+static int update_node32(const float* X, int32_t i, const int32_t* nbr_ptr, const int32_t* nbr_idx,
+                         const int32_t* tri_ptr, const int32_t* tri_idx, const int32_t* tris, int accept_gt,
+                         float* ox, float* oy)
+{
+    int32_t b = nbr_ptr[i], e = nbr_ptr[i + 1];
+    float sx = 0.0f, sy = 0.0f;
+    for (int32_t k = b; k < e; ++k) {
+        sx += X[2 * (int64_t)nbr_idx[k]];
+        sy += X[2 * (int64_t)nbr_idx[k] + 1];
+    }
+    float dn = (float)(e - b);
+    float cx = sx / dn, cy = sy / dn;
+    float xi = X[2 * (int64_t)i], yi = X[2 * (int64_t)i + 1];
+    float qo = INFINITY, qn = INFINITY;
+    for (int32_t k = tri_ptr[i]; k < tri_ptr[i + 1]; ++k) {
+        int32_t t = tri_idx[k];
+        float v = tri_q32(X, tris, t, -1, 0.0f, 0.0f);
+        if (v < qo) qo = v;
+        float w = tri_q32(X, tris, t, i, cx, cy);
+        if (w < qn) qn = w;
+    }
+    int acc = accept_gt ? (qn > qo) : (qn >= qo);
+    *ox = acc ? cx : xi;
+    *oy = acc ? cy : yi;
+    return acc;
+}
+
+/* Form A in single precision, iterated; arguments and outputs as
+ * slref_smooth.  coords (double, n x 2) are rounded to float on entry and
+ * receive the float results on exit (exactly representable). */
+int32_t slref32_smooth(double* coords, int32_t n, const int32_t* nbr_ptr, const int32_t* nbr_idx,
+                       const int32_t* tri_ptr, const int32_t* tri_idx, const int32_t* tris, int32_t n_tris,
+                       const uint8_t* boundary, int32_t iterations, double tol, int accept_gt, int n_threads,
+                       uint8_t* flags, double* disp, int64_t* accepted)
+{
+    if (iterations < 0) return -1;
+    if (check_inputs(n, nbr_ptr, nbr_idx, tri_ptr, tri_idx, tris, n_tris, boundary)) return -1;
+    float* A = (float*)malloc(sizeof(float) * 2 * (size_t)(n > 0 ? n : 1));
+    float* B = (float*)malloc(sizeof(float) * 2 * (size_t)(n > 0 ? n : 1));
+    if (!A || !B) { free(A); free(B); return -1; }
+    for (int64_t k = 0; k < 2 * (int64_t)n; ++k) A[k] = (float)coords[k];
+    double tol2 = tol * tol;
+    int32_t k = 0;
+    if (n_threads < 1) n_threads = 1;
+    while (k < iterations) {
+        int64_t acc_count = 0;
+        float dmax = 0.0f;
+        uint8_t* fl = flags ? flags + (size_t)k * n : NULL;
+#ifdef _OPENMP
+#pragma omp parallel for num_threads(n_threads) schedule(static) reduction(+ : acc_count) reduction(max : dmax)
+#endif
+        for (int32_t i = 0; i < n; ++i) {
+            float x = A[2 * (int64_t)i], y = A[2 * (int64_t)i + 1];
+            if (boundary[i]) {
+                B[2 * (int64_t)i] = x;
+                B[2 * (int64_t)i + 1] = y;
+                if (fl) fl[i] = 2;
+                continue;
+            }
+            float nx, ny;
+            int acc = update_node32(A, i, nbr_ptr, nbr_idx, tri_ptr, tri_idx, tris, accept_gt, &nx, &ny);
+            B[2 * (int64_t)i] = nx;
+            B[2 * (int64_t)i + 1] = ny;
+            if (fl) fl[i] = (uint8_t)acc;
+            acc_count += acc;
+            float dx = nx - x, dy = ny - y;
+            float d2 = dx * dx + dy * dy;
+            if (d2 > dmax) dmax = d2;
+        }
+        if (disp) disp[k] = (double)dmax;
+        if (accepted) accepted[k] = acc_count;
+        float* t = A; A = B; B = t;
+        ++k;
+        if (tol > 0.0 && (double)dmax < tol2) break;
+    }
+    for (int64_t q = 0; q < 2 * (int64_t)n; ++q) coords[q] = (double)A[q];
+    free(A);
+    free(B);
+    return k;
+}
+
 /* Largest number of threads OpenMP would use (1 without OpenMP). */
 int slref_max_threads(void)
 {

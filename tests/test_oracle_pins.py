@@ -373,3 +373,93 @@ def test_colored_invariants():
         X = Xn
     j = oracle.smooth(m, 6)
     assert not (j.coords == X).all()                # the two forms differ on a real mesh
+
+
+# ------------------------------------------------------ single precision ----
+
+def f32(x):
+    return float(np.float32(x))
+
+
+def test_quality32_closed_forms():
+    k32 = np.float32(2.0) * np.sqrt(np.float32(3.0))          # float nearest 2*sqrt(3)
+    # right isosceles (0,0),(1,0),(0,1): cr = 1, S = 4, q = K/4 exactly
+    assert oracle.quality32(0, 0, 1, 0, 0, 1) == float(k32 / np.float32(4))
+    q = oracle.quality32(0, 0, 1, 0, 0.5, f32(math.sqrt(3) / 2))
+    assert abs(q - 1.0) <= 4 * 2.0 ** -24
+    assert oracle.quality32(0, 0, 1, 0, 0, 1) == -oracle.quality32(0, 0, 0, 1, 1, 0)
+    assert oracle.quality32(1, 1, 1, 1, 1, 1) == 0.0
+    rng = np.random.Generator(np.random.PCG64(5))
+    for _ in range(200):
+        p = [f32(v) for v in rng.uniform(-1, 1, 6)]
+        exact = float(exact_q((p[0], p[1]), (p[2], p[3]), (p[4], p[5])))
+        q32 = oracle.quality32(*p)
+        # a few float roundings of terms no larger than S: absolute error a few ulps of 1
+        assert abs(q32 - exact) <= 64 * 2.0 ** -24 * max(1.0, abs(exact)), (p, q32, exact)
+
+
+def test_f32_dyadic_grids_are_fixed_points():
+    for diag in ("unionjack", "slash"):
+        m = meshgen.make_grid(9, diag, 0.0, 0, h=0.125)
+        r = oracle.smooth(m, 3, precision="f32")
+        assert (r.coords == m.coords).all()
+        assert (r.flags[:, m.boundary == 0] == 1).all()
+        r = oracle.smooth(m, 2, precision="f32", accept_gt=True)
+        assert (r.flags[:, m.boundary == 0] == 0).all()
+
+
+@pytest.mark.parametrize("n,seed", [(6, 31), (8, 32)])
+def test_f32_exact_rational_brute_force(n, seed):
+    """One single-precision sweep from float positions against exact rational
+    arithmetic: decisions agree wherever the exact relative margin exceeds
+    1e-4, accepted positions lie within the float rounding bound of the
+    exact centroid, results are floats."""
+    m = meshgen.make_grid(n, "random", 0.4, seed)
+    m.coords = m.coords.astype(np.float32).astype(np.float64)
+    r = oracle.smooth(m, 1, precision="f32")
+    ex = exact_sweep(m.coords, m.tris.tolist(), m.boundary.tolist())
+    u = 2.0 ** -24
+    checked = 0
+    for i, d in ex.items():
+        if d.rel_margin > Fraction(1, 10 ** 4):
+            assert r.flags[0, i] == int(d.accept_ge), (i, float(d.rel_margin))
+            checked += 1
+        if r.flags[0, i] == 1:
+            nb = m.nbr_idx[m.nbr_ptr[i]:m.nbr_ptr[i + 1]]
+            k = len(nb)
+            bound = (k + 1) * u * float(np.abs(m.coords[nb]).sum(axis=0).max()) / k + 2 * u
+            for ax in range(2):
+                assert abs(Fraction(float(r.coords[i, ax])) - d.centroid[ax]) <= Fraction(bound)
+        else:
+            assert (r.coords[i] == m.coords[i]).all()
+    assert checked > 0.8 * len(ex)
+    assert (r.coords.astype(np.float32).astype(np.float64) == r.coords).all()
+
+
+def test_f32_tracks_f64():
+    """Same decisions as FP64 in the first sweep except at near-ties, and
+    positions within float resolution of the FP64 run over a few sweeps."""
+    m = meshgen.make_grid(40, "random", 0.4, 12)
+    a = oracle.smooth(m, 1, precision="f32")
+    b = oracle.smooth(m, 1)
+    assert (a.flags != b.flags).sum() <= 3
+    a = oracle.smooth(m, 5, precision="f32")
+    b = oracle.smooth(m, 5)
+    assert np.abs(a.coords - b.coords).max() < 1e-3
+    with pytest.raises(ValueError):
+        oracle.smooth(m, 1, precision="f32", form="colored")
+
+
+def test_f32_centroid_sums_in_float_in_row_order():
+    """Neighbour x-coordinates 1, 2^-24, 2^-24, 2^-24 in row order: in float
+    each addition of 2^-24 to 1 is a tie that rounds back to 1, so the sum is
+    exactly 1 and the centroid's x exactly 0.25 (in double the small terms
+    survive).  The move is accepted, so the node lands on it."""
+    t = 2.0 ** -24
+    ring = np.array([[1.0, 0.25], [t, 0.75], [t, 0.25], [t, -0.25]])
+    m = meshgen.star_mesh(np.array([0.1, 0.25]), ring)
+    assert m.nbr_idx[m.nbr_ptr[0]:m.nbr_ptr[1]].tolist() == [1, 2, 3, 4]
+    r = oracle.smooth(m, 1, precision="f32")
+    assert r.flags[0, 0] == 1 and r.coords[0].tolist() == [0.25, 0.25]
+    r64 = oracle.smooth(m, 1)
+    assert r64.flags[0, 0] == 1 and r64.coords[0, 0] == (1 + 3 * t) / 4
