@@ -69,6 +69,15 @@ typedef enum {
     SL_ACCEPT_GT = 1   /* accept iff it strictly increases */
 } sl_accept;
 typedef enum { SL_AOS = 0, SL_SOA = 1 } sl_layout;   /* coordinate stream on the device */
+typedef enum {
+    SL_F64 = 0,          /* every operation in IEEE double precision (default) */
+    SL_F32 = 1           /* the paper's precision (Sec. 4): coordinates rounded to float once
+                            on the device, every operation one IEEE float operation in the same
+                            order, the constant the float nearest 2*sqrt(3); results returned
+                            as doubles (exactly representable).  The squared displacement of
+                            the convergence test is computed in float and compared in double.
+                            Form A on the tile path only (SL_EINVAL otherwise). */
+} sl_precision;
 typedef enum { SL_REORDER_NONE = 0, SL_REORDER_HILBERT = 1 } sl_reorder;
 typedef enum {
     SL_KERNEL_AUTO = 0,  /* tile kernel for Form A when the mesh fits it, else the node kernel */
@@ -91,6 +100,7 @@ typedef struct {
     int32_t tile_wg_per_cu;  /* tile-kernel work-groups per compute unit: 0 = automatic (the
                               * value sl_autotune chose, else as many as fit, at most 4), or
                               * 1..8, capped by what fits in LDS; results do not depend on it */
+    int32_t precision;       /* sl_precision */
     /* Optional accept flags, nullable.  Size iterations * ((n_nodes + 7) / 8)
      * bytes; sweep k occupies bytes [k*((n+7)/8), (k+1)*((n+7)/8)); bit (i % 8)
      * of byte (i / 8) is 1 iff free node i accepted its move in sweep k

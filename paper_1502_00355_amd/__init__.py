@@ -26,6 +26,7 @@ ACCEPT = {"ge": 0, "gt": 1}
 LAYOUTS = {"aos": 0, "soa": 1}
 REORDER = {"none": 0, "hilbert": 1}
 KERNELS = {"auto": 0, "node": 1, "tile": 2}
+PRECISIONS = {"f64": 0, "f32": 1}
 
 
 class SmartlapError(RuntimeError):
@@ -37,7 +38,8 @@ class SmartlapError(RuntimeError):
 class Options(ctypes.Structure):
     _fields_ = [("form", ctypes.c_int32), ("accept", ctypes.c_int32), ("layout", ctypes.c_int32),
                 ("reorder", ctypes.c_int32), ("block_size", ctypes.c_int32), ("kernel", ctypes.c_int32),
-                ("tile_nodes", ctypes.c_int32), ("tile_wg_per_cu", ctypes.c_int32), ("flags_out", ctypes.c_void_p)]
+                ("tile_nodes", ctypes.c_int32), ("tile_wg_per_cu", ctypes.c_int32), ("precision", ctypes.c_int32),
+                ("flags_out", ctypes.c_void_p)]
 
 
 class Report(ctypes.Structure):
@@ -161,7 +163,7 @@ def _check(status: int):
 
 
 def make_options(form="jacobi", accept="ge", layout="aos", reorder="hilbert", block_size=0, kernel="auto",
-                 tile_nodes=0, tile_wg_per_cu=0, flags_ptr=None):
+                 tile_nodes=0, tile_wg_per_cu=0, precision="f64", flags_ptr=None):
     o = Options()
     lib().sl_options_default(ctypes.byref(o))
     o.form = FORMS[form] if isinstance(form, str) else int(form)
@@ -172,6 +174,7 @@ def make_options(form="jacobi", accept="ge", layout="aos", reorder="hilbert", bl
     o.kernel = KERNELS[kernel] if isinstance(kernel, str) else int(kernel)
     o.tile_nodes = int(tile_nodes)
     o.tile_wg_per_cu = int(tile_wg_per_cu)
+    o.precision = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
     o.flags_out = flags_ptr
     return o
 

@@ -88,6 +88,9 @@ sl_status check_options(const sl_options& o)
     if (o.tile_nodes != 0 && o.tile_nodes != 256 && o.tile_nodes != 512)
         return fail(SL_EINVAL, "tile_nodes must be 0, 256 or 512");
     if (o.tile_wg_per_cu < 0 || o.tile_wg_per_cu > 8) return fail(SL_EINVAL, "tile_wg_per_cu must be in 0..8");
+    if (o.precision != SL_F64 && o.precision != SL_F32) return fail(SL_EINVAL, "unknown precision");
+    if (o.precision == SL_F32 && (o.form != SL_JACOBI || o.kernel == SL_KERNEL_NODE))
+        return fail(SL_EINVAL, "single precision runs Form A on the tile kernel only");
     return SL_OK;
 }
 
@@ -178,7 +181,7 @@ sl_status run_device(double* coords, int32_t n, const int32_t* nbr_ptr, const in
     const int32_t block = resolve_block_size(o);
     // with a tolerance, a launch on a converged mesh returns at once
     const TileLaunch L{cs.m.work, cs.m.n_tiles, cs.m.tile_nodes, cs.m.halo_max, cs.m.rows_max, o.layout, o.accept,
-                       cs.state, resolve_wg_per_cu(o), tol2 > 0.0 ? 1 : 0};
+                       cs.state, resolve_wg_per_cu(o), tol2 > 0.0 ? 1 : 0, o.precision};
     auto enqueue = [&](int32_t s) -> sl_status {
         uint64_t* bits = cs.bits ? cs.bits + static_cast<int64_t>(s) * words : nullptr;
         sl_status rr = tiles ? launch_sweep_tiles(L, s & 1, bits, stream)

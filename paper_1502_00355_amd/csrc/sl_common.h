@@ -67,7 +67,7 @@ struct MeshState {
 // One tile of the tile path: everything a work-group needs to sweep it, with
 // absolute pointers so that tiles of many meshes can share one launch.
 struct alignas(16) TileWork {
-    const double* X;                // the mesh's buffer pair: X[0] at X, X[1] at X + 2n
+    const void* X;                  // the mesh's buffer pair (double or float): X[0] at X, X[1] at X + 2n
     const int32_t* halo;            // halo node ids (mesh device labels)
     const uint64_t* rows;           // neighbour rows in local indices, 4 x u16 per word
     const uint64_t* tris;           // triangle entries: 3 x u16 local indices, stored order
@@ -94,7 +94,8 @@ struct DevMesh {
     int32_t* fan_ptr = nullptr;     // [n_free+1]
     uint16_t* fan = nullptr;        // [ninc_free] (node path)
     int32_t color_start_h[130] = {0};    // colour class c: device labels [cs[c], cs[c+1])
-    double* X[2] = {nullptr, nullptr};   // one block of 4n doubles: X[1] = X[0] + 2n;
+    int32_t precision = SL_F64;          // element type of X: double, or float for SL_F32
+    void* X[2] = {nullptr, nullptr};     // one block of 4n elements: X[1] = X[0] + 2n;
                                          // AoS (x,y pairs) or SoA (x[n] then y[n]) inside each
     // Tile path (Form A)
     int32_t tile_nodes = 0;              // 0: tile path not built
@@ -196,6 +197,7 @@ struct TileLaunch {
     MeshState* states;
     int32_t wg_per_cu;          // 0: as many as fit, at most 4
     int32_t exit_if_inactive;   // 1: every tile is of one mesh; a launch on it returns at once once it stops
+    int32_t precision;          // SL_F64 or SL_F32: every mesh of the list has it
 };
 sl_status launch_sweep_tiles(const TileLaunch& L, int32_t parity, uint64_t* bits, hipStream_t st);
 
@@ -204,7 +206,7 @@ sl_status launch_sweep_tiles(const TileLaunch& L, int32_t parity, uint64_t* bits
 sl_status launch_advance(MeshState* states, int32_t n, hipStream_t st);
 
 // Work-group count of a tile launch (persistent work-groups, XCD-aware).
-int tile_grid(int n_work, int tile_nodes, int halo_cap, int rows_cap, int wg_per_cu);
+int tile_grid(int n_work, int tile_nodes, int halo_cap, int rows_cap, int wg_per_cu, int32_t precision);
 
 // Exclusive scan of n int32 values; out[n] receives the total (out has n+1).
 sl_status scan_exclusive(const int32_t* in, int32_t* out, int64_t n, hipStream_t st);

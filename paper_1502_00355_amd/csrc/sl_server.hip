@@ -186,7 +186,7 @@ struct HipExec {
             q->joined = true;
         }
         const bool jacobi = opts.form == SL_JACOBI;
-        const TileLaunch L{work, n_work, T, hcap, rcap, opts.layout, opts.accept, states, wg_per_cu, 0};
+        const TileLaunch L{work, n_work, T, hcap, rcap, opts.layout, opts.accept, states, wg_per_cu, 0, opts.precision};
         for (int32_t k = 0; k < sweeps_per_step && !r; ++k) {
             if (jacobi && n_work > 0) r = launch_sweep_tiles(L, parity, nullptr, st_compute);
             for (Req* q : in_step) {

@@ -467,31 +467,36 @@ __global__ __launch_bounds__(kBS) void k_rows_fans(const int32_t* __restrict__ p
     }
 }
 
+// Both buffers of the ping-pong pair start at the caller's positions,
+// rounded to R (float for the single-precision form).
+template <typename R>
 __global__ __launch_bounds__(kBS) void k_init_coords(const double* __restrict__ coords,
                                                      const int32_t* __restrict__ perm, int32_t n, int soa,
-                                                     double* __restrict__ X0, double* __restrict__ X1)
+                                                     R* __restrict__ X0, R* __restrict__ X1)
 {
     const int64_t k = static_cast<int64_t>(blockIdx.x) * kBS + threadIdx.x;
     if (k >= n) return;
     const int64_t o = perm[k];
     const double2 p = *reinterpret_cast<const double2*>(coords + 2 * o);
+    const R x = static_cast<R>(p.x), y = static_cast<R>(p.y);
     if (soa) {
-        X0[k] = p.x; X0[n + k] = p.y;
-        X1[k] = p.x; X1[n + k] = p.y;
+        X0[k] = x; X0[n + k] = y;
+        X1[k] = x; X1[n + k] = y;
     } else {
-        reinterpret_cast<double2*>(X0)[k] = p;
-        reinterpret_cast<double2*>(X1)[k] = p;
+        X0[2 * k] = x; X0[2 * k + 1] = y;
+        X1[2 * k] = x; X1[2 * k + 1] = y;
     }
 }
 
-__global__ __launch_bounds__(kBS) void k_unpermute(const double* __restrict__ X, const int32_t* __restrict__ perm,
+template <typename R>
+__global__ __launch_bounds__(kBS) void k_unpermute(const R* __restrict__ X, const int32_t* __restrict__ perm,
                                                    int32_t n, int soa, double* __restrict__ out)
 {
     const int64_t k = static_cast<int64_t>(blockIdx.x) * kBS + threadIdx.x;
     if (k >= n) return;
     const int64_t o = perm[k];
-    const double2 p = soa ? make_double2(X[k], X[n + k]) : reinterpret_cast<const double2*>(X)[k];
-    *reinterpret_cast<double2*>(out + 2 * o) = p;
+    const R x = soa ? X[k] : X[2 * k], y = soa ? X[n + k] : X[2 * k + 1];
+    *reinterpret_cast<double2*>(out + 2 * o) = make_double2(static_cast<double>(x), static_cast<double>(y));
 }
 
 __global__ __launch_bounds__(kBS) void k_unpermute_flags(const uint64_t* __restrict__ bits, int64_t words,
@@ -705,13 +710,27 @@ sl_status setup_mesh(const SetupArgs& a, const sl_options& o, DevMesh& m, int32_
     dfree(inc, st);
     m.nnz_free = tot[0];
     m.ninc_free = tot[1];
-    // coordinate buffers: one block, X[1] right after X[0]
-    if ((r = dalloc(&m.X[0], 4 * static_cast<size_t>(n), st))) return r;
-    m.X[1] = m.X[0] + 2 * static_cast<size_t>(n);
-    k_init_coords<<<gb, kBS, 0, st>>>(a.coords, m.perm, n, o.layout == SL_SOA, m.X[0], m.X[1]);
+    // coordinate buffers: one block, X[1] right after X[0], in the sweep's precision
+    m.precision = o.precision;
+    const size_t n2 = 2 * static_cast<size_t>(n);
+    if (m.precision == SL_F32) {
+        float* xf = nullptr;
+        if ((r = dalloc(&xf, 2 * n2, st))) return r;
+        m.X[0] = xf;
+        m.X[1] = xf + n2;
+        k_init_coords<float><<<gb, kBS, 0, st>>>(a.coords, m.perm, n, o.layout == SL_SOA, xf, xf + n2);
+    } else {
+        double* xd = nullptr;
+        if ((r = dalloc(&xd, 2 * n2, st))) return r;
+        m.X[0] = xd;
+        m.X[1] = xd + n2;
+        k_init_coords<double><<<gb, kBS, 0, st>>>(a.coords, m.perm, n, o.layout == SL_SOA, xd, xd + n2);
+    }
     // tile path for Form A; the node path's rows and fans otherwise
     if (o.form == SL_JACOBI && o.kernel != SL_KERNEL_NODE)
         if ((r = build_tiles(a, m, resolve_tile_nodes(o), mesh, st))) return r;
+    if (m.tile_nodes == 0 && m.precision == SL_F32 && m.n_free > 0)
+        return fail(SL_EINVAL, "single precision needs the tile path, and this mesh does not fit it");
     if (m.tile_nodes == 0) {
         if ((r = dalloc(&m.nbr, m.nnz_free, st)) || (r = dalloc(&m.fan, m.ninc_free, st))) return r;
         if (m.n_free > 0)
@@ -727,7 +746,12 @@ sl_status setup_mesh(const SetupArgs& a, const sl_options& o, DevMesh& m, int32_
 
 sl_status unpermute_coords(const DevMesh& m, int src, double* coords_out, hipStream_t st)
 {
-    k_unpermute<<<div_up(m.n, kBS), kBS, 0, st>>>(m.X[src], m.perm, m.n, m.layout == SL_SOA, coords_out);
+    if (m.precision == SL_F32)
+        k_unpermute<float><<<div_up(m.n, kBS), kBS, 0, st>>>(static_cast<const float*>(m.X[src]), m.perm, m.n,
+                                                              m.layout == SL_SOA, coords_out);
+    else
+        k_unpermute<double><<<div_up(m.n, kBS), kBS, 0, st>>>(static_cast<const double*>(m.X[src]), m.perm, m.n,
+                                                               m.layout == SL_SOA, coords_out);
     SL_HIP(hipGetLastError());
     return SL_OK;
 }

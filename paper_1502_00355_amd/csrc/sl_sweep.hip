@@ -243,14 +243,14 @@ sl_status launch_sweep_nodes(const DevMesh& m, int32_t parity, int32_t form, int
     a.bits = bits;
     const bool soa = m.layout == SL_SOA, gt = accept == SL_ACCEPT_GT;
     if (form == SL_JACOBI) {
-        a.Xin = m.X[parity & 1];
-        a.Xout = m.X[(parity + 1) & 1];
+        a.Xin = static_cast<const double*>(m.X[parity & 1]);
+        a.Xout = static_cast<double*>(m.X[(parity + 1) & 1]);
         a.k_begin = 0;
         a.k_end = m.n_free;
         launch_range(a, m.max_deg, block, soa, gt, st);
     } else {
-        a.Xin = m.X[0];
-        a.Xout = m.X[0];
+        a.Xin = static_cast<const double*>(m.X[0]);
+        a.Xout = static_cast<double*>(m.X[0]);
         for (int c = 0; c < m.n_colors; ++c) {
             a.k_begin = m.color_start_h[c];
             a.k_end = m.color_start_h[c + 1];

@@ -136,7 +136,7 @@ struct TileBuildArgs {
     int32_t n_free;
     int32_t mesh;              // MeshState index written into the descriptors
     int64_t n;
-    const double* X;
+    const void* X;
     int32_t* halo;             // [nnz_free]: tile k writes at row_ptr[k0] (halo <= row entries)
     uint16_t* nbr_loc;         // tile k writes at align4(row_ptr[k0]) + 8k (segments never overlap)
     uint32_t* row_rel;         // [n_tiles * T]
@@ -269,27 +269,40 @@ __global__ __launch_bounds__(kBuildBS) void k_tile_build(TileBuildArgs a)
 
 // ------------------------------------------------------------ tile sweep --
 
-// Minimum into an LDS double (one ds_min_f64).  Qualities are finite --
-// coordinates are validated below 2^500 in magnitude and S == 0 gives 0 --
-// so no NaN reaches it; which zero a min keeps when +0 meets -0 does not
-// matter, the accept test compares them equal.
-__device__ __forceinline__ void lds_min(double* p, double v)
+// The sweep runs in the precision of its real type R: double, or float for
+// the single-precision form (every operation then one float operation, the
+// constant the float nearest 2*sqrt(3)).
+template <typename R>
+struct Real;
+template <>
+struct Real<double> {
+    using V2 = double2;
+    static constexpr double k_two_sqrt3 = kTwoSqrt3;
+    __device__ static V2 make(double x, double y) { return make_double2(x, y); }
+};
+template <>
+struct Real<float> {
+    using V2 = float2;
+    static constexpr float k_two_sqrt3 = 0x1.bb67aep+1f;   // 2*sqrt(3) rounded to float
+    __device__ static V2 make(float x, float y) { return make_float2(x, y); }
+};
+
+// Minimum into an LDS value (one ds_min_f64 / ds_min_f32).  Qualities are
+// finite -- coordinates are validated below 2^500 in magnitude and S == 0
+// gives 0 -- so no NaN reaches it; which zero a min keeps when +0 meets -0
+// does not matter, the accept test compares them equal.
+template <typename R>
+__device__ __forceinline__ void lds_min(R* p, R v)
 {
     __hip_atomic_fetch_min(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
 }
 
 // (2*sqrt(3)*cr)/S, or 0 when S == 0.
-__device__ __forceinline__ double finish_q(double cr, double S)
+template <typename R>
+__device__ __forceinline__ R finish_q(R cr, R S)
 {
-    const double q = (kTwoSqrt3 * cr) / S;
-    return S == 0.0 ? 0.0 : q;
-}
-
-template <bool SOA>
-__device__ __forceinline__ double2 ldx(const double* X, int64_t n, int64_t i)
-{
-    if (SOA) return make_double2(X[i], X[n + i]);
-    return reinterpret_cast<const double2*>(X)[i];
+    const R q = (Real<R>::k_two_sqrt3 * cr) / S;
+    return S == R(0) ? R(0) : q;
 }
 
 struct TileSweepArgs {
@@ -303,34 +316,35 @@ struct TileSweepArgs {
 
 // Old quality of one triangle and the new quality for each own vertex,
 // folded into the per-node minima.  Local indices below T are own nodes.
-template <int T>
-__device__ __forceinline__ void tile_triangle(uint64_t w, const double2* Xl, const double2* cand, double* qo,
-                                              double* qn)
+template <int T, typename R>
+__device__ __forceinline__ void tile_triangle(uint64_t w, const typename Real<R>::V2* Xl,
+                                              const typename Real<R>::V2* cand, R* qo, R* qn)
 {
+    using V2 = typename Real<R>::V2;
     const int l0 = static_cast<int>(w & 0xFFFF), l1 = static_cast<int>((w >> 16) & 0xFFFF),
               l2 = static_cast<int>((w >> 32) & 0xFFFF);
-    const double2 p0 = Xl[l0], p1 = Xl[l1], p2 = Xl[l2];
-    const double ax = p1.x - p0.x, ay = p1.y - p0.y;
-    const double bx = p2.x - p0.x, by = p2.y - p0.y;
-    const double cx = p2.x - p1.x, cy = p2.y - p1.y;
-    const double La = ax * ax + ay * ay, Lb = bx * bx + by * by, Lc = cx * cx + cy * cy;
-    const double qold = finish_q(ax * by - bx * ay, (La + Lc) + Lb);
+    const V2 p0 = Xl[l0], p1 = Xl[l1], p2 = Xl[l2];
+    const R ax = p1.x - p0.x, ay = p1.y - p0.y;
+    const R bx = p2.x - p0.x, by = p2.y - p0.y;
+    const R cx = p2.x - p1.x, cy = p2.y - p1.y;
+    const R La = ax * ax + ay * ay, Lb = bx * bx + by * by, Lc = cx * cx + cy * cy;
+    const R qold = finish_q(ax * by - bx * ay, (La + Lc) + Lb);
     if (l0 < T) {
         lds_min(qo + l0, qold);
-        const double2 c = cand[l0];
-        const double ax2 = p1.x - c.x, ay2 = p1.y - c.y, bx2 = p2.x - c.x, by2 = p2.y - c.y;
+        const V2 c = cand[l0];
+        const R ax2 = p1.x - c.x, ay2 = p1.y - c.y, bx2 = p2.x - c.x, by2 = p2.y - c.y;
         lds_min(qn + l0, finish_q(ax2 * by2 - bx2 * ay2, ((ax2 * ax2 + ay2 * ay2) + Lc) + (bx2 * bx2 + by2 * by2)));
     }
     if (l1 < T) {
         lds_min(qo + l1, qold);
-        const double2 c = cand[l1];
-        const double ax2 = c.x - p0.x, ay2 = c.y - p0.y, cx2 = p2.x - c.x, cy2 = p2.y - c.y;
+        const V2 c = cand[l1];
+        const R ax2 = c.x - p0.x, ay2 = c.y - p0.y, cx2 = p2.x - c.x, cy2 = p2.y - c.y;
         lds_min(qn + l1, finish_q(ax2 * by - bx * ay2, ((ax2 * ax2 + ay2 * ay2) + (cx2 * cx2 + cy2 * cy2)) + Lb));
     }
     if (l2 < T) {
         lds_min(qo + l2, qold);
-        const double2 c = cand[l2];
-        const double bx2 = c.x - p0.x, by2 = c.y - p0.y, cx2 = c.x - p1.x, cy2 = c.y - p1.y;
+        const V2 c = cand[l2];
+        const R bx2 = c.x - p0.x, by2 = c.y - p0.y, cx2 = c.x - p1.x, cy2 = c.y - p1.y;
         lds_min(qn + l2, finish_q(ax * by2 - bx2 * ay, (La + (cx2 * cx2 + cy2 * cy2)) + (bx2 * bx2 + by2 * by2)));
     }
 }
@@ -339,14 +353,14 @@ __device__ __forceinline__ void tile_triangle(uint64_t w, const double2* Xl, con
 // is computed.  Loaded in two steps, the second a phase after the first:
 // (A) halo ids, own positions, row offsets; (B) halo positions, the row
 // segment, triangle entries.  Tile descriptors are loaded a tile earlier.
-template <int NPT, int RPRE, int KPRE>
+template <typename R, int NPT, int RPRE, int KPRE>
 struct TileStage {
-    double2 own[NPT];
+    typename Real<R>::V2 own[NPT];
     uint32_t rr[NPT];        // row start | row end << 16, unpacked where used
     uint64_t rw[RPRE];
     uint64_t tw[KPRE];
     int hidx;
-    double2 hx;
+    typename Real<R>::V2 hx;
 };
 
 // The descriptor is loaded through an index the compiler treats as per-lane,
@@ -388,7 +402,7 @@ __device__ __forceinline__ TileWork uniform_work(const TileWork& w)
     };
     auto u64 = [&](const void* p) { return uv(reinterpret_cast<uint64_t>(p)); };
     TileWork u;
-    u.X = reinterpret_cast<const double*>(u64(w.X));
+    u.X = reinterpret_cast<const void*>(u64(w.X));
     u.halo = reinterpret_cast<const int32_t*>(u64(w.halo));
     u.rows = reinterpret_cast<const uint64_t*>(u64(w.rows));
     u.tris = reinterpret_cast<const uint64_t*>(u64(w.tris));
@@ -403,18 +417,25 @@ __device__ __forceinline__ TileWork uniform_work(const TileWork& w)
     return u;
 }
 
-template <bool SOA>
-__device__ __forceinline__ double2 ldxg(gptr<double> X, int64_t n, int64_t i)
+template <bool SOA, typename R>
+__device__ __forceinline__ typename Real<R>::V2 ldxg(gptr<R> X, int64_t n, int64_t i)
 {
-    if (SOA) return make_double2(X[i], X[n + i]);
-    return make_double2(X[2 * i], X[2 * i + 1]);
+    if (SOA) return Real<R>::make(X[i], X[n + i]);
+    return Real<R>::make(X[2 * i], X[2 * i + 1]);
 }
 
-template <int T, int BS, bool SOA, int NPT, int RPRE, int KPRE>
-__device__ __forceinline__ void stage_a(TileStage<NPT, RPRE, KPRE>& s, const TileWork& d, int parity)
+// The buffer `parity` of a tile's mesh.
+template <typename R>
+__device__ __forceinline__ gptr<R> xin(const TileWork& d, int parity)
+{
+    return to_global(static_cast<const R*>(d.X)) + parity * 2 * d.n;
+}
+
+template <int T, int BS, bool SOA, typename R, int NPT, int RPRE, int KPRE>
+__device__ __forceinline__ void stage_a(TileStage<R, NPT, RPRE, KPRE>& s, const TileWork& d, int parity)
 {
     const int tid = threadIdx.x;
-    const gptr<double> Xin = to_global(d.X) + parity * 2 * d.n;
+    const gptr<R> Xin = xin<R>(d, parity);
     const gptr<int32_t> halo = to_global(d.halo);
     const gptr<uint32_t> rr = to_global(d.rr);
     s.hidx = tid < d.halo_cnt ? halo[tid] : -1;
@@ -422,18 +443,18 @@ __device__ __forceinline__ void stage_a(TileStage<NPT, RPRE, KPRE>& s, const Til
     for (int m = 0; m < NPT; ++m) {
         const int i = m * BS + tid;
         s.rr[m] = rr[i];
-        s.own[m] = i < d.nown ? ldxg<SOA>(Xin, d.n, d.own_start + i) : make_double2(0.0, 0.0);
+        s.own[m] = i < d.nown ? ldxg<SOA>(Xin, d.n, d.own_start + i) : Real<R>::make(R(0), R(0));
     }
 }
 
-template <int T, int BS, bool SOA, int NPT, int RPRE, int KPRE>
-__device__ __forceinline__ void stage_b(TileStage<NPT, RPRE, KPRE>& s, const TileWork& d, int parity)
+template <int T, int BS, bool SOA, typename R, int NPT, int RPRE, int KPRE>
+__device__ __forceinline__ void stage_b(TileStage<R, NPT, RPRE, KPRE>& s, const TileWork& d, int parity)
 {
     const int tid = threadIdx.x;
-    const gptr<double> Xin = to_global(d.X) + parity * 2 * d.n;
+    const gptr<R> Xin = xin<R>(d, parity);
     const gptr<uint64_t> rows = to_global(d.rows);
     const gptr<uint64_t> tris = to_global(d.tris);
-    s.hx = s.hidx >= 0 ? ldxg<SOA>(Xin, d.n, s.hidx) : make_double2(0.0, 0.0);
+    s.hx = s.hidx >= 0 ? ldxg<SOA>(Xin, d.n, s.hidx) : Real<R>::make(R(0), R(0));
 #pragma unroll
     for (int q = 0; q < RPRE; ++q) {
         const int j = q * BS + tid;
@@ -450,9 +471,10 @@ __device__ __forceinline__ void stage_b(TileStage<NPT, RPRE, KPRE>& s, const Til
 // per XCD (work-groups are dealt to the XCDs round-robin), shared round-robin
 // by the work-groups that XCD runs; each work-group computes one tile while
 // the next one's data is on its way.
-template <int T, int BS, bool SOA, bool GT>
+template <int T, int BS, bool SOA, bool GT, typename R>
 __global__ __launch_bounds__(BS) void k_sweep_tile(TileSweepArgs a)
 {
+    using V2 = typename Real<R>::V2;
     constexpr int NPT = T / BS;   // own nodes per work-item
     // per work-item register budget for the next tile: about 2.4 triangles
     // and 1.5 row words per free node on meshes of valence 6
@@ -465,10 +487,10 @@ __global__ __launch_bounds__(BS) void k_sweep_tile(TileSweepArgs a)
     if (it >= t_end) return;
 
     extern __shared__ double2 lds[];
-    double2* Xl = lds;                                      // [T + halo_cap]
-    double2* cand = lds + T + a.halo_cap;                   // [T]
-    double* qo = reinterpret_cast<double*>(cand + T);       // [T] worst old quality per own node
-    double* qn = qo + T;                                    // [T] worst candidate quality
+    V2* Xl = reinterpret_cast<V2*>(lds);                    // [T + halo_cap]
+    V2* cand = Xl + T + a.halo_cap;                         // [T]
+    R* qo = reinterpret_cast<R*>(cand + T);                 // [T] worst old quality per own node
+    R* qn = qo + T;                                         // [T] worst candidate quality
     uint16_t* rows = reinterpret_cast<uint16_t*>(qn + T);   // [rows_cap]
     uint64_t* rows64 = reinterpret_cast<uint64_t*>(rows);
     __shared__ double s_d2[BS / 64];
@@ -484,7 +506,7 @@ __global__ __launch_bounds__(BS) void k_sweep_tile(TileSweepArgs a)
     TileWork dnext = load_work(a.work, it + nw < t_end ? it + nw : it);
     int act_cur = a.states[dcur.mesh].active;
     if (a.exit_if_inactive && act_cur == 0) return;
-    TileStage<NPT, RPRE, KPRE> sg;
+    TileStage<R, NPT, RPRE, KPRE> sg;
     stage_a<T, BS, SOA>(sg, dcur, parity);
     stage_b<T, BS, SOA>(sg, dcur, parity);
     double run_d2 = 0.0;
@@ -508,7 +530,7 @@ __global__ __launch_bounds__(BS) void k_sweep_tile(TileSweepArgs a)
         if (sg.hidx >= 0) Xl[T + tid] = sg.hx;
         {
             // rare overflow beyond what the registers hold
-            const gptr<double> Xin = to_global(dcur.X) + parity * 2 * dcur.n;
+            const gptr<R> Xin = xin<R>(dcur, parity);
             const gptr<int32_t> halo = to_global(dcur.halo);
             const gptr<uint64_t> rws = to_global(dcur.rows);
             for (int h = BS + tid; h < dcur.halo_cnt; h += BS) Xl[T + h] = ldxg<SOA>(Xin, dcur.n, halo[h]);
@@ -528,16 +550,16 @@ __global__ __launch_bounds__(BS) void k_sweep_tile(TileSweepArgs a)
             for (int m = 0; m < NPT; ++m) {
                 const int i = m * BS + tid;
                 if (i < nown) {
-                    double sx = 0.0, sy = 0.0;
+                    R sx = R(0), sy = R(0);
                     for (int j = r0[m]; j < r1[m]; ++j) {
-                        const double2 p = Xl[rows[j]];
+                        const V2 p = Xl[rows[j]];
                         sx += p.x;
                         sy += p.y;
                     }
-                    const double dn = static_cast<double>(r1[m] - r0[m]);
-                    cand[i] = make_double2(sx / dn, sy / dn);
-                    qo[i] = __builtin_inf();
-                    qn[i] = __builtin_inf();
+                    const R dn = static_cast<R>(r1[m] - r0[m]);
+                    cand[i] = Real<R>::make(sx / dn, sy / dn);
+                    qo[i] = static_cast<R>(__builtin_inf());
+                    qn[i] = static_cast<R>(__builtin_inf());
                 }
             }
         }
@@ -548,9 +570,9 @@ __global__ __launch_bounds__(BS) void k_sweep_tile(TileSweepArgs a)
         if (run) {
 #pragma unroll
             for (int q = 0; q < KPRE; ++q)
-                if (q * BS + tid < dcur.tri_cnt) tile_triangle<T>(tw[q], Xl, cand, qo, qn);
+                if (q * BS + tid < dcur.tri_cnt) tile_triangle<T, R>(tw[q], Xl, cand, qo, qn);
             const gptr<uint64_t> tris = to_global(dcur.tris);
-            for (int r = KPRE * BS + tid; r < dcur.tri_cnt; r += BS) tile_triangle<T>(tris[r], Xl, cand, qo, qn);
+            for (int r = KPRE * BS + tid; r < dcur.tri_cnt; r += BS) tile_triangle<T, R>(tris[r], Xl, cand, qo, qn);
         }
         __syncthreads();
         const TileWork dnext2 = load_work(a.work, next + nw < t_end ? next + nw : (has_next ? next : it));
@@ -560,8 +582,8 @@ __global__ __launch_bounds__(BS) void k_sweep_tile(TileSweepArgs a)
         // folded into its MeshState when the mesh changes (one pair of
         // atomics per work-group and mesh)
         if (run) {
-            __attribute__((address_space(1))) double* Xout =
-                reinterpret_cast<__attribute__((address_space(1))) double*>(reinterpret_cast<uint64_t>(dcur.X)) +
+            __attribute__((address_space(1))) R* Xout =
+                reinterpret_cast<__attribute__((address_space(1))) R*>(reinterpret_cast<uint64_t>(dcur.X)) +
                 (parity ^ 1) * 2 * dcur.n;
             const int k0 = dcur.own_start;
 #pragma unroll
@@ -569,11 +591,11 @@ __global__ __launch_bounds__(BS) void k_sweep_tile(TileSweepArgs a)
                 const int i = m * BS + tid;
                 bool accepted = false;
                 if (i < nown) {
-                    const double vo = qo[i], vn = qn[i];
+                    const R vo = qo[i], vn = qn[i];
                     accepted = GT ? (vn > vo) : (vn >= vo);
-                    const double2 o = Xl[i];
-                    const double2 c = cand[i];
-                    const double nx = accepted ? c.x : o.x, ny = accepted ? c.y : o.y;
+                    const V2 o = Xl[i];
+                    const V2 c = cand[i];
+                    const R nx = accepted ? c.x : o.x, ny = accepted ? c.y : o.y;
                     if (SOA) {
                         Xout[k0 + i] = nx;
                         Xout[dcur.n + k0 + i] = ny;
@@ -581,8 +603,8 @@ __global__ __launch_bounds__(BS) void k_sweep_tile(TileSweepArgs a)
                         Xout[2 * (k0 + i)] = nx;
                         Xout[2 * (k0 + i) + 1] = ny;
                     }
-                    const double dx = nx - o.x, dy = ny - o.y;
-                    const double d2 = dx * dx + dy * dy;
+                    const R dx = nx - o.x, dy = ny - o.y;
+                    const double d2 = static_cast<double>(dx * dx + dy * dy);   // exact widening
                     run_d2 = d2 > run_d2 ? d2 : run_d2;
                 }
                 const unsigned long long ball = __ballot(accepted);
@@ -628,34 +650,38 @@ __global__ __launch_bounds__(BS) void k_sweep_tile(TileSweepArgs a)
 constexpr int kTileBS = 256;
 constexpr int kLdsLimit = 160 * 1024 - 4096;
 
-template <int T, int BS, bool SOA, bool GT>
+template <int T, int BS, bool SOA, bool GT, typename R>
 void launch_tile_variant(const TileSweepArgs& a, int grid, size_t lds, hipStream_t st)
 {
     if (lds > 64 * 1024) {
-        (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_sweep_tile<T, BS, SOA, GT>),
+        (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_sweep_tile<T, BS, SOA, GT, R>),
                                   hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds));
         (void)hipGetLastError();
     }
-    k_sweep_tile<T, BS, SOA, GT><<<grid, BS, lds, st>>>(a);
+    k_sweep_tile<T, BS, SOA, GT, R><<<grid, BS, lds, st>>>(a);
 }
 
-template <int T>
+template <int T, typename R>
 void launch_tile_t(const TileSweepArgs& a, bool soa, bool gt, int grid, size_t lds, hipStream_t st)
 {
     if (soa) {
-        if (gt) launch_tile_variant<T, kTileBS, true, true>(a, grid, lds, st);
-        else launch_tile_variant<T, kTileBS, true, false>(a, grid, lds, st);
+        if (gt) launch_tile_variant<T, kTileBS, true, true, R>(a, grid, lds, st);
+        else launch_tile_variant<T, kTileBS, true, false, R>(a, grid, lds, st);
     } else {
-        if (gt) launch_tile_variant<T, kTileBS, false, true>(a, grid, lds, st);
-        else launch_tile_variant<T, kTileBS, false, false>(a, grid, lds, st);
+        if (gt) launch_tile_variant<T, kTileBS, false, true, R>(a, grid, lds, st);
+        else launch_tile_variant<T, kTileBS, false, false, R>(a, grid, lds, st);
     }
 }
 
-size_t tile_lds_bytes(int tile_nodes, int halo_cap, int rows_cap)
+// LDS of one work-group: own and halo positions, candidates and the two
+// per-node minima in the sweep's precision (real_bytes 8 or 4), u16 rows.
+size_t tile_lds_bytes(int tile_nodes, int halo_cap, int rows_cap, int real_bytes)
 {
-    return static_cast<size_t>(tile_nodes + halo_cap) * 16 + static_cast<size_t>(tile_nodes) * 32 +
-           static_cast<size_t>(rows_cap) * 2;
+    return static_cast<size_t>(tile_nodes + halo_cap) * 2 * real_bytes +
+           static_cast<size_t>(tile_nodes) * 4 * real_bytes + static_cast<size_t>(rows_cap) * 2;
 }
+
+int real_bytes_of(int32_t precision) { return precision == SL_F32 ? 4 : 8; }
 
 }  // namespace
 
@@ -707,7 +733,7 @@ sl_status build_tiles(const SetupArgs& a, DevMesh& m, int tile_nodes, int mesh, 
     if (h[0] & 1) return fail(SL_ETOPO, "triangle vertex outside its tile's neighbourhood");
     // a tile denser than the staging holds, or a halo or row segment too big
     // for LDS: the node path
-    if ((h[0] & 2) || tile_lds_bytes(T, h[1], h[2]) > static_cast<size_t>(kLdsLimit)) {
+    if ((h[0] & 2) || tile_lds_bytes(T, h[1], h[2], real_bytes_of(m.precision)) > static_cast<size_t>(kLdsLimit)) {
         dfree(m.work, st);
         dfree(m.halo, st);
         dfree(m.nbr_loc, st);
@@ -722,9 +748,9 @@ sl_status build_tiles(const SetupArgs& a, DevMesh& m, int tile_nodes, int mesh, 
     return SL_OK;
 }
 
-int tile_grid(int n_work, int tile_nodes, int halo_cap, int rows_cap, int wg_per_cu)
+int tile_grid(int n_work, int tile_nodes, int halo_cap, int rows_cap, int wg_per_cu, int32_t precision)
 {
-    const size_t lds = tile_lds_bytes(tile_nodes, halo_cap, rows_cap);
+    const size_t lds = tile_lds_bytes(tile_nodes, halo_cap, rows_cap, real_bytes_of(precision));
     // work-groups per CU: as requested (else 4), no more than fit the LDS;
     // 32 CUs per XCD; never more work-groups than tiles on an XCD
     const int fit = std::max(1, static_cast<int>(kLdsLimit / std::max<size_t>(lds, 1)));
@@ -747,11 +773,16 @@ sl_status launch_sweep_tiles(const TileLaunch& L, int32_t parity, uint64_t* bits
     a.exit_if_inactive = L.exit_if_inactive;
     a.states = L.states;
     a.bits = bits;
-    const size_t lds = tile_lds_bytes(L.tile_nodes, L.halo_cap, L.rows_cap);
-    const int grid = tile_grid(L.n_work, L.tile_nodes, L.halo_cap, L.rows_cap, L.wg_per_cu);
+    const size_t lds = tile_lds_bytes(L.tile_nodes, L.halo_cap, L.rows_cap, real_bytes_of(L.precision));
+    const int grid = tile_grid(L.n_work, L.tile_nodes, L.halo_cap, L.rows_cap, L.wg_per_cu, L.precision);
     const bool soa = L.layout == SL_SOA, gt = L.accept == SL_ACCEPT_GT;
-    if (L.tile_nodes == 256) launch_tile_t<256>(a, soa, gt, grid, lds, st);
-    else launch_tile_t<512>(a, soa, gt, grid, lds, st);
+    if (L.precision == SL_F32) {
+        if (L.tile_nodes == 256) launch_tile_t<256, float>(a, soa, gt, grid, lds, st);
+        else launch_tile_t<512, float>(a, soa, gt, grid, lds, st);
+    } else {
+        if (L.tile_nodes == 256) launch_tile_t<256, double>(a, soa, gt, grid, lds, st);
+        else launch_tile_t<512, double>(a, soa, gt, grid, lds, st);
+    }
     SL_HIP(hipGetLastError());
     return SL_OK;
 }

@@ -119,10 +119,11 @@ sl_status tune_tiles(const sl_mesh_desc* meshes, const std::vector<int32_t>& sam
         }
         int last_grid = -1;
         for (int32_t w = 1; w <= 8; ++w) {
-            const int grid = tile_grid(static_cast<int>(tiles), T, hcap, rcap, w);
+            const int grid = tile_grid(static_cast<int>(tiles), T, hcap, rcap, w, o.precision);
             if (grid == last_grid) continue;   // capped by LDS or by the tile count: same launch
             last_grid = grid;
-            const TileLaunch L{p.work, static_cast<int32_t>(tiles), T, hcap, rcap, o.layout, o.accept, p.states, w, 0};
+            const TileLaunch L{p.work, static_cast<int32_t>(tiles), T, hcap, rcap, o.layout, o.accept, p.states, w, 0,
+                               o.precision};
             float ms = 0.f;
             r = time_sweeps(p, static_cast<int32_t>(p.meshes.size()),
                             [&](int32_t parity) { return launch_sweep_tiles(L, parity, nullptr, st); }, &ms);

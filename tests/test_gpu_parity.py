@@ -51,7 +51,7 @@ def assert_parity(m, iters, tol=0.0, accept="ge", form="jacobi", threads=None, *
     note("parity %s iters=%d tol=%g accept=%s form=%s %s" % (m.name, iters, tol, accept, form, opts))
     X, rep, F = run_gpu(m, iters, tol, accept=accept, form=form, **opts)
     ref = oracle.smooth(m, iters, tol=tol, accept_gt=(accept == "gt"), threads=threads or oracle.max_threads(),
-                        form=form)
+                        form=form, precision=opts.get("precision", "f64"))
     assert rep.iterations_run == ref.iterations_run
     k = ref.iterations_run
     assert (F[:k] == (ref.flags == 1)).all(), "flags differ in sweeps %s" % np.flatnonzero(
@@ -478,3 +478,64 @@ def test_server_cancel_deadline_budget_and_bad_input():
     assert rc.status == sl.SL_EINVAL
     assert rd.status == sl.SL_ETIMEOUT
     assert re.status == sl.SL_ENOMEM
+
+
+# ------------------------------------------------------ single precision ----
+
+@pytest.mark.parametrize("make,iters", [
+    (lambda: meshgen.make_grid(64, "unionjack", 0.3, 1), 10),
+    (lambda: meshgen.make_grid(300, "random", 0.4, 31), 12),
+    (lambda: meshgen.make_annulus(40, 90, seed=3), 8),
+    (lambda: meshgen.make_delaunay(10000, 11), 15),
+])
+@pytest.mark.parametrize("layout", ["aos", "soa"])
+def test_f32_parity(make, iters, layout):
+    """Single precision (the paper's): the same float operations on both
+    sides, so flags and coordinates are bit-exact."""
+    m = make()
+    X, rep, ref, nd = assert_parity(m, iters, precision="f32", layout=layout)
+    assert nd == 0 and rep.kernel_used == sl.KERNELS["tile"]
+    assert (X.astype(np.float32).astype(np.float64) == X).all()
+
+
+@pytest.mark.parametrize("tile_nodes,wpc,accept", [(256, 3, "ge"), (512, 2, "gt"), (512, 8, "ge")])
+def test_f32_shapes_and_rules(tile_nodes, wpc, accept):
+    m = meshgen.permute_mesh(meshgen.make_grid(200, "random", 0.4, 8), 4)
+    X, rep, ref, nd = assert_parity(m, 9, precision="f32", accept=accept, tile_nodes=tile_nodes,
+                                    tile_wg_per_cu=wpc)
+    assert nd == 0 and rep.tile_nodes == tile_nodes
+
+
+def test_f32_full_1024_and_tolerance():
+    m = meshgen.permute_mesh(meshgen.make_grid(1024, "random", 0.4, 2), 2)
+    X, rep, ref, nd = assert_parity(m, 30, precision="f32")
+    assert nd == 0
+    small = meshgen.make_grid(30, "random", 0.4, 9)
+    ref = oracle.smooth(small, 300, precision="f32")
+    tol = math.sqrt(ref.disp[50]) * 1.0000001
+    X, rep, ref2, nd = assert_parity(small, 300, tol=tol, precision="f32")
+    assert nd == 0 and rep.iterations_run < 300
+
+
+def test_f32_refused_outside_the_tile_path():
+    m = meshgen.make_grid(20, "random", 0.4, 3)
+    for opts in ({"form": "colored"}, {"kernel": "node"}):
+        with pytest.raises(sl.SmartlapError) as e:
+            run_gpu(m, 2, precision="f32", **opts)
+        assert e.value.status == sl.SL_EINVAL
+    with pytest.raises(sl.SmartlapError) as e:
+        run_gpu(_many_stars(600, 20, 5), 2, precision="f32")    # tiles too dense: node path needed
+    assert e.value.status == sl.SL_EINVAL and "single precision" in str(e.value)
+
+
+def test_f32_batch_and_server():
+    ms = [meshgen.make_grid(n, "random", 0.35, 700 + n) for n in (24, 57, 130)]
+    outs, reps, br = sl.batch_smooth(ms, 7, precision="f32")
+    for m, X in zip(ms, outs):
+        assert (X == oracle.smooth(m, 7, precision="f32").coords).all()
+    with sl.Server(precision="f32") as S:
+        ids = [S.submit(m, 5 + k) for k, m in enumerate(ms)]
+        for k, (m, rid) in enumerate(zip(ms, ids)):
+            r = S.wait(rid)
+            assert r.status == sl.SL_OK
+            assert (r.coords == oracle.smooth(m, 5 + k, precision="f32").coords).all()
