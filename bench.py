@@ -162,6 +162,27 @@ def run_single(args, sl, torch):
     torch.cuda.synchronize()
     el = time.perf_counter() - t0
     log("timed %d steps in %.3f s" % (args.steps, el))
+    f32 = None
+    if args.f32:
+        # the same job in single precision (the paper's precision), reported beside the FP64 headline
+        f_sweep, f_t = [], []
+        for k in range(args.steps + 1):
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            work.copy_(X0)
+            rf = sl.smooth_mesh_device(work, *dev[1:], iterations=iters, layout=args.layout, reorder=args.reorder,
+                                       stream=stream, precision="f32", **tile_opts(args))
+            torch.cuda.synchronize()
+            if k:
+                f_t.append(time.perf_counter() - t)
+                f_sweep.append(rf.sweep_ms)
+        f_sweep_s = float(np.mean(f_sweep)) / 1e3 / iters
+        f_bytes = alg_bytes - 16 * free
+        f32 = {"ms_per_step": 1e3 * float(np.mean(f_t)), "node_updates_per_s": free * iters / float(np.mean(f_t)),
+               "sweep_ms_per_sweep": f_sweep_s * 1e3, "sweep_only_node_updates_per_s": free / f_sweep_s,
+               "alg_bytes_per_launch": f_bytes, "hbm_gbs_algorithmic": f_bytes / f_sweep_s / 1e9,
+               "hbm_pct_peak": 100.0 * f_bytes / f_sweep_s / 1e9 / HBM_PEAK_GBS}
+        log("f32: %.3f ms per sweep, %.1f%% of HBM peak" % (f_sweep_s * 1e3, f32["hbm_pct_peak"]))
     avg_sweep_s = float(np.mean(sweep_ms)) / 1e3 / iters
     achieved = alg_bytes / avg_sweep_s / 1e9
     out = {
@@ -181,6 +202,7 @@ def run_single(args, sl, torch):
                    "sweeps_per_step": iters, "form": "jacobi", "layout": args.layout, "reorder": args.reorder,
                    "kernel": {1: "node", 2: "tile"}.get(r.kernel_used, "?"), "tile_nodes": r.tile_nodes},
         "autotune": tuning,
+        "single_precision": f32,
         "sweep_only_node_updates_per_s": free / avg_sweep_s,
         "sweep_ms_per_sweep": avg_sweep_s * 1e3,
         "setup_ms_per_step": float(np.mean(setup_ms)),
@@ -296,7 +318,8 @@ def run_batch(args, sl):
     _, reps, br = sl.batch_smooth(meshes, iters)
     el_b = time.perf_counter() - t
     assert all(r.iterations_run == iters for r in reps)
-    log("batched: %.3f s (setup %.1f ms, sweeps %.1f ms)" % (el_b, br.setup_ms, br.sweep_ms))
+    log("batched: %.3f s (setup %.1f ms, graph %.1f ms, sweeps %.1f ms, results %.1f ms)" %
+        (el_b, br.setup_ms, br.graph_ms, br.sweep_ms, br.results_ms))
     plain_sweep_ms = 0.0
     t = time.perf_counter()
     for m in meshes:
@@ -309,7 +332,8 @@ def run_batch(args, sl):
         "workload": "batch%d_grids_side24-450_random_j0.35_seeds10000+" % M,
         "meshes": M, "nodes": nodes, "free_nodes": free, "sweeps": iters,
         "batched_node_updates_per_s": upd / el_b, "batched_s": el_b,
-        "batched_setup_ms": br.setup_ms, "batched_sweep_ms": br.sweep_ms,
+        "batched_setup_ms": br.setup_ms, "batched_graph_ms": br.graph_ms, "batched_sweep_ms": br.sweep_ms,
+        "batched_results_ms": br.results_ms,
         "batched_sweep_node_updates_per_s": upd / (br.sweep_ms / 1e3),
         "plain_node_updates_per_s": upd / el_p, "plain_s": el_p, "plain_sweep_ms": plain_sweep_ms,
         "plain_sweep_node_updates_per_s": upd / (plain_sweep_ms / 1e3),
@@ -436,6 +460,7 @@ def main():
     ap.add_argument("--tile-nodes", type=int, default=0)
     ap.add_argument("--wg-per-cu", type=int, default=0)
     ap.add_argument("--no-autotune", dest="autotune", action="store_false")
+    ap.add_argument("--no-f32", dest="f32", action="store_false")
     ap.add_argument("--batch-meshes", type=int, default=1000)
     ap.add_argument("--converge-cap", type=int, default=100000)
     ap.add_argument("--serve-rates", default="10,100,1000,2000")

@@ -179,13 +179,15 @@ typedef struct {
 } sl_mesh_desc;
 
 typedef struct {
-    double setup_ms;            /* device time of uploads and per-mesh setup */
+    double setup_ms;            /* host wall time of uploads and per-mesh setup */
     double sweep_ms;            /* device time of the batched sweep loop */
     double total_ms;            /* host wall time of the whole call */
     int64_t node_updates;       /* sum over meshes of free nodes x sweeps run */
     int64_t tiles;              /* tiles in the batched work list */
     int32_t meshes_on_tile_path;
     int32_t graph_used;         /* 1 if the sweep loop ran as a captured HIP graph */
+    double graph_ms;            /* host wall time of capturing and instantiating the graph */
+    double results_ms;          /* host wall time of un-permuting and copying out the results */
 } sl_batch_report;
 
 /*

@@ -61,7 +61,8 @@ class MeshDesc(ctypes.Structure):
 class BatchReport(ctypes.Structure):
     _fields_ = [("setup_ms", ctypes.c_double), ("sweep_ms", ctypes.c_double), ("total_ms", ctypes.c_double),
                 ("node_updates", ctypes.c_int64), ("tiles", ctypes.c_int64),
-                ("meshes_on_tile_path", ctypes.c_int32), ("graph_used", ctypes.c_int32)]
+                ("meshes_on_tile_path", ctypes.c_int32), ("graph_used", ctypes.c_int32),
+                ("graph_ms", ctypes.c_double), ("results_ms", ctypes.c_double)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}

@@ -192,6 +192,15 @@ sl_status build_adjacency(const int32_t* d_tris, int32_t n_tris, int32_t n, int3
     k_adj_copy<<<gn, kAB, 0, st>>>(n, s.tri_ptr, s.row, s.nbr_ptr, s.nbr_idx);
     SL_HIP(hipGetLastError());
     const size_t n1 = static_cast<size_t>(n) + 1;
+    if (kind == hipMemcpyDeviceToHost) {
+        if ((r = copy_to_host(nbr_ptr, s.nbr_ptr, sizeof(int32_t) * n1, st)) ||
+            (r = copy_to_host(nbr_idx, s.nbr_idx, sizeof(int32_t) * total, st)) ||
+            (r = copy_to_host(tri_ptr, s.tri_ptr, sizeof(int32_t) * n1, st)) ||
+            (r = copy_to_host(tri_idx, s.tri_idx, sizeof(int32_t) * m3, st)) ||
+            (r = copy_to_host(boundary, s.bnd, static_cast<size_t>(n), st)))
+            return r;
+        return SL_OK;
+    }
     SL_HIP(hipMemcpyAsync(nbr_ptr, s.nbr_ptr, sizeof(int32_t) * n1, kind, st));
     if (total) SL_HIP(hipMemcpyAsync(nbr_idx, s.nbr_idx, sizeof(int32_t) * total, kind, st));
     SL_HIP(hipMemcpyAsync(tri_ptr, s.tri_ptr, sizeof(int32_t) * n1, kind, st));
@@ -253,8 +262,7 @@ sl_status sl_build_adjacency(const int32_t* tris, int32_t n_tris, int32_t n_node
     int32_t* d_tris = nullptr;
     const size_t m3 = 3 * static_cast<size_t>(n_tris);
     r = dalloc(&d_tris, std::max<size_t>(m3, 1), st);
-    if (!r && m3 && hipMemcpyAsync(d_tris, tris, sizeof(int32_t) * m3, hipMemcpyHostToDevice, st) != hipSuccess)
-        r = fail(SL_EDEVICE, "host to device copy failed");
+    if (!r) r = copy_to_device(d_tris, tris, sizeof(int32_t) * m3, st);
     if (!r)
         r = build_adjacency(d_tris, n_tris, n_nodes, nbr_ptr, nbr_idx, nbr_capacity, tri_ptr, tri_idx, boundary, nnz,
                             hipMemcpyDeviceToHost, st);

@@ -129,8 +129,10 @@ struct CallState {
     hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
+    hipStream_t capture = nullptr;      // where the sweep chunk is captured
     ~CallState()
     {
+        if (capture) (void)hipStreamDestroy(capture);
         devmesh_free(m, st);
         dfree(state, st);
         dfree(bits, st);
@@ -182,11 +184,11 @@ sl_status run_device(double* coords, int32_t n, const int32_t* nbr_ptr, const in
     // with a tolerance, a launch on a converged mesh returns at once
     const TileLaunch L{cs.m.work, cs.m.n_tiles, cs.m.tile_nodes, cs.m.halo_max, cs.m.rows_max, o.layout, o.accept,
                        cs.state, resolve_wg_per_cu(o), tol2 > 0.0 ? 1 : 0, o.precision};
-    auto enqueue = [&](int32_t s) -> sl_status {
+    auto enqueue = [&](int32_t s, hipStream_t on) -> sl_status {
         uint64_t* bits = cs.bits ? cs.bits + static_cast<int64_t>(s) * words : nullptr;
-        sl_status rr = tiles ? launch_sweep_tiles(L, s & 1, bits, stream)
-                             : launch_sweep_nodes(cs.m, s & 1, o.form, o.accept, block, cs.state, bits, stream);
-        return rr ? rr : launch_advance(cs.state, 1, stream);
+        sl_status rr = tiles ? launch_sweep_tiles(L, s & 1, bits, on)
+                             : launch_sweep_nodes(cs.m, s & 1, o.form, o.accept, block, cs.state, bits, on);
+        return rr ? rr : launch_advance(cs.state, 1, on);
     };
 
     // The sweep loop runs in chunks of kSweepChunk sweeps; a whole chunk is
@@ -194,14 +196,17 @@ sl_status run_device(double* coords, int32_t n, const int32_t* nbr_ptr, const in
     // parity of sweep s is s & 1 in every replay).  With a tolerance the host
     // reads the sweep state after each chunk and stops launching once the
     // mesh has converged.  Flag output takes per-sweep pointers, so it runs
-    // without the graph.
+    // without the graph.  The chunk is captured on a stream of the library's
+    // own (the caller's may be the legacy default stream, which cannot be
+    // captured) and replayed on the caller's stream.
     SL_HIP(hipEventRecord(cs.ev[2], stream));
     const bool use_graph = !cs.bits && its >= 2 * kSweepChunk;
     if (use_graph) {
-        SL_HIP(hipStreamBeginCapture(stream, hipStreamCaptureModeThreadLocal));
+        SL_HIP(hipStreamCreateWithFlags(&cs.capture, hipStreamNonBlocking));
+        SL_HIP(hipStreamBeginCapture(cs.capture, hipStreamCaptureModeThreadLocal));
         sl_status cr = SL_OK;
-        for (int32_t s = 0; s < kSweepChunk && !cr; ++s) cr = enqueue(s);
-        const hipError_t ce = hipStreamEndCapture(stream, &cs.graph);
+        for (int32_t s = 0; s < kSweepChunk && !cr; ++s) cr = enqueue(s, cs.capture);
+        const hipError_t ce = hipStreamEndCapture(cs.capture, &cs.graph);
         if (cr) return cr;
         if (ce != hipSuccess) return fail(SL_EDEVICE, std::string("graph capture failed: ") + hipGetErrorString(ce));
         SL_HIP(hipGraphInstantiate(&cs.exec, cs.graph, nullptr, nullptr, 0));
@@ -212,7 +217,7 @@ sl_status run_device(double* coords, int32_t n, const int32_t* nbr_ptr, const in
             SL_HIP(hipGraphLaunch(cs.exec, stream));
         } else {
             for (int32_t s = done; s < done + c; ++s)
-                if ((r = enqueue(s))) return r;
+                if ((r = enqueue(s, stream))) return r;
         }
         done += c;
         if (tol2 > 0.0 && done < its) {
@@ -330,9 +335,8 @@ sl_status smooth_mesh(double* coords, int32_t n_nodes, const int32_t* nbr_ptr, c
             (r = dalloc(&d_t, 3 * static_cast<size_t>(n_tris), st)) || (r = dalloc(&d_b, n, st)))
             break;
         if (host_flags && flag_bytes && (r = dalloc(&d_flags, flag_bytes, st))) break;
-        hipError_t e = hipSuccess;
         auto cp = [&](void* dst, const void* src, size_t bytes) {
-            if (e == hipSuccess && bytes) e = hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, st);
+            if (!r) r = copy_to_device(dst, src, bytes, st);
         };
         cp(d_coords, coords, 2 * n * sizeof(double));
         cp(d_np, nbr_ptr, (n + 1) * sizeof(int32_t));
@@ -341,14 +345,14 @@ sl_status smooth_mesh(double* coords, int32_t n_nodes, const int32_t* nbr_ptr, c
         cp(d_ti, tri_idx, static_cast<size_t>(ninc) * sizeof(int32_t));
         cp(d_t, tris, 3 * static_cast<size_t>(n_tris) * sizeof(int32_t));
         cp(d_b, boundary, n);
-        if (e != hipSuccess) { r = fail(SL_EDEVICE, std::string("host to device copy failed: ") + hipGetErrorString(e)); break; }
+        if (r) break;
         o.flags_out = host_flags && flag_bytes ? d_flags : nullptr;
         r = run_device(d_coords, n_nodes, d_np, d_ni, d_tp, d_ti, d_t, n_tris, d_b, iterations, tol, &o, report, st);
         if (r) break;
-        e = hipMemcpyAsync(out.data(), d_coords, 2 * n * sizeof(double), hipMemcpyDeviceToHost, st);
-        if (e == hipSuccess && d_flags) e = hipMemcpyAsync(host_flags, d_flags, flag_bytes, hipMemcpyDeviceToHost, st);
-        if (e == hipSuccess) e = hipStreamSynchronize(st);
-        if (e != hipSuccess) { r = fail(SL_EDEVICE, std::string("device to host copy failed: ") + hipGetErrorString(e)); break; }
+        // results land in a staging vector first: the caller's arrays are
+        // written only once every copy has succeeded
+        if ((r = copy_to_host(out.data(), d_coords, 2 * n * sizeof(double), st))) break;
+        if (d_flags && (r = copy_to_host(host_flags, d_flags, flag_bytes, st))) break;
         std::memcpy(coords, out.data(), 2 * n * sizeof(double));
     } while (false);
     std::string keep = g_last_error;

@@ -77,9 +77,9 @@ sl_status upload_and_prepare(const sl_mesh_desc& d, const sl_options& o, int32_t
         cleanup();
         return r;
     }
-    hipError_t e = hipSuccess;
+    sl_status e = SL_OK;
     auto cp = [&](void* dst, const void* src, size_t bytes) {
-        if (e == hipSuccess && bytes) e = hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, st);
+        if (!e) e = copy_to_device(dst, src, bytes, st);
     };
     cp(c, d.coords, 2 * n * sizeof(double));
     cp(np, d.nbr_ptr, (n + 1) * sizeof(int32_t));
@@ -88,9 +88,9 @@ sl_status upload_and_prepare(const sl_mesh_desc& d, const sl_options& o, int32_t
     cp(ti, d.tri_idx, static_cast<size_t>(ninc) * sizeof(int32_t));
     cp(tr, d.tris, 3 * static_cast<size_t>(d.n_tris) * sizeof(int32_t));
     cp(b, d.boundary, n);
-    if (e != hipSuccess) {
+    if (e) {
         cleanup();
-        return fail(SL_EDEVICE, std::string("host to device copy failed: ") + hipGetErrorString(e));
+        return e;
     }
     MeshInput in{c, d.n_nodes, np, ni, tp, ti, tr, d.n_tris, b};
     r = prepare_mesh(in, o, mesh, m, st);
@@ -232,7 +232,8 @@ sl_status sl_batch_smooth(const sl_mesh_desc* meshes, int32_t n_meshes, int32_t 
         return SL_OK;
     };
     int32_t graph_used = 0;
-    SL_HIP(hipEventRecord(bs.ev[2], st));
+    const auto tg0 = std::chrono::steady_clock::now();
+    double graph_ms = 0.0;
     if (iterations > 0) {
         SL_HIP(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
         sl_status cr = enqueue_chunk();
@@ -243,8 +244,12 @@ sl_status sl_batch_smooth(const sl_mesh_desc* meshes, int32_t n_meshes, int32_t 
         if (ce != hipSuccess) return fail(SL_EDEVICE, std::string("graph capture failed: ") + hipGetErrorString(ce));
         SL_HIP(hipGraphInstantiate(&bs.exec, bs.graph, nullptr, nullptr, 0));
         graph_used = 1;
+        graph_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - tg0).count();
+        SL_HIP(hipEventRecord(bs.ev[2], st));
         const int32_t replays = (iterations + chunk - 1) / chunk;
         for (int32_t k = 0; k < replays; ++k) SL_HIP(hipGraphLaunch(bs.exec, st));
+    } else {
+        SL_HIP(hipEventRecord(bs.ev[2], st));
     }
     SL_HIP(hipEventRecord(bs.ev[3], st));
 
@@ -257,6 +262,7 @@ sl_status sl_batch_smooth(const sl_mesh_desc* meshes, int32_t n_meshes, int32_t 
     SL_HIP(hipStreamSynchronize(st));
     float sweep_ms = 0.f;
     SL_HIP(hipEventElapsedTime(&sweep_ms, bs.ev[2], bs.ev[3]));
+    const auto tr0 = std::chrono::steady_clock::now();
     int64_t updates = 0;
     for (int32_t first = 0; first < n_meshes;) {
         int32_t last = first;
@@ -270,7 +276,7 @@ sl_status sl_batch_smooth(const sl_mesh_desc* meshes, int32_t n_meshes, int32_t 
         used = 0;
         for (int32_t i = first; i < last; ++i) {
             const size_t vals = 2 * static_cast<size_t>(bs.meshes[i].n);
-            SL_HIP(hipMemcpyAsync(meshes[i].coords, bs.out + used, sizeof(double) * vals, hipMemcpyDeviceToHost, st));
+            if ((r = copy_to_host(meshes[i].coords, bs.out + used, sizeof(double) * vals, st))) return r;
             used += vals;
         }
         SL_HIP(hipStreamSynchronize(st));
@@ -300,6 +306,8 @@ sl_status sl_batch_smooth(const sl_mesh_desc* meshes, int32_t n_meshes, int32_t 
         b.tiles = total_tiles;
         b.meshes_on_tile_path = on_tiles;
         b.graph_used = graph_used;
+        b.graph_ms = graph_ms;
+        b.results_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - tr0).count();
         *batch = b;
     }
     return SL_OK;

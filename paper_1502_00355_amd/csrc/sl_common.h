@@ -153,6 +153,13 @@ sl_status prepare_mesh(const MeshInput& in, const sl_options& o, int32_t mesh, D
 sl_status check_options(const sl_options& o);
 void keep_pool_warm();
 
+// Copies between caller host memory and the device through pinned staging
+// buffers.  copy_to_device returns once the copy is enqueued on `st` (the
+// source may be reused at once); copy_to_host returns when dst holds the
+// data (it waits for the work enqueued on `st` before it).
+sl_status copy_to_device(void* dst, const void* src, size_t bytes, hipStream_t st);
+sl_status copy_to_host(void* dst, const void* src, size_t bytes, hipStream_t st);
+
 // Uploads one caller mesh (host arrays) on `st` and prepares it; the
 // uploaded inputs are released once the device copy is built.
 sl_status upload_and_prepare(const sl_mesh_desc& d, const sl_options& o, int32_t mesh, DevMesh& m, hipStream_t st);

@@ -237,8 +237,7 @@ struct HipExec {
         sl_status r = unpermute_coords(m, src, out, st_compute);
         if (r) return r;
         q.result.resize(2 * n);
-        SL_HIP(hipMemcpyAsync(q.result.data(), out, 2 * n * sizeof(double), hipMemcpyDeviceToHost, st_compute));
-        SL_HIP(hipStreamSynchronize(st_compute));
+        if ((r = copy_to_host(q.result.data(), out, 2 * n * sizeof(double), st_compute))) return r;
         sl_report rep{};
         rep.iterations_run = ms.s;
         rep.n_colors = m.n_colors;

@@ -1,0 +1,154 @@
+// Copies between callers' host memory and the device through pinned
+// staging buffers.
+//
+// Callers hand in ordinary (pageable) host arrays.  A copy from pageable
+// memory is carried out by the runtime synchronously through its own
+// staging, and copies from several threads serialize there.  Here the data
+// is moved chunk by chunk through two pinned buffers from a pool the library
+// keeps for the life of the process: the host copy into (or out of) one
+// buffer overlaps the DMA of the other, and threads use buffers of their
+// own.  A buffer returned to the pool carries the event of its last DMA;
+// whoever takes it next waits for that event before touching it.
+#include <cstring>
+#include <mutex>
+#include <vector>
+
+#include "sl_common.h"
+
+namespace sl {
+
+namespace {
+
+constexpr size_t kStageBytes = size_t(16) << 20;
+constexpr size_t kDirectBytes = size_t(256) << 10;   // smaller copies go straight to the runtime
+
+struct Stage {
+    unsigned char* ptr = nullptr;
+    hipEvent_t ev = nullptr;
+    bool pending = false;   // ev marks a DMA that may still use the buffer
+};
+
+std::mutex g_stage_mu;
+std::vector<Stage*> g_stage_free[64];
+
+sl_status acquire(int dev, Stage** out)
+{
+    {
+        std::lock_guard<std::mutex> lk(g_stage_mu);
+        if (!g_stage_free[dev].empty()) {
+            *out = g_stage_free[dev].back();
+            g_stage_free[dev].pop_back();
+            return SL_OK;
+        }
+    }
+    auto* s = new Stage;
+    if (hipHostMalloc(reinterpret_cast<void**>(&s->ptr), kStageBytes, hipHostMallocDefault) != hipSuccess) {
+        delete s;
+        return fail(SL_ENOMEM, "pinned staging buffer allocation failed");
+    }
+    if (hipEventCreateWithFlags(&s->ev, hipEventDisableTiming) != hipSuccess) {
+        (void)hipHostFree(s->ptr);
+        delete s;
+        return fail(SL_EDEVICE, "staging event creation failed");
+    }
+    *out = s;
+    return SL_OK;
+}
+
+void release(int dev, Stage* s)
+{
+    std::lock_guard<std::mutex> lk(g_stage_mu);
+    g_stage_free[dev].push_back(s);
+}
+
+// The two buffers of one copy, returned to the pool on every exit path.
+struct StagePair {
+    int dev = -1;
+    Stage* s[2] = {nullptr, nullptr};
+    ~StagePair()
+    {
+        for (Stage* b : s)
+            if (b) release(dev, b);
+    }
+    sl_status init()
+    {
+        if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return fail(SL_EDEVICE, "no current device");
+        sl_status r;
+        if ((r = acquire(dev, &s[0])) || (r = acquire(dev, &s[1]))) return r;
+        return SL_OK;
+    }
+};
+
+// Waits until no DMA uses the buffer any more.
+sl_status quiesce(Stage* b)
+{
+    if (b->pending) {
+        SL_HIP(hipEventSynchronize(b->ev));
+        b->pending = false;
+    }
+    return SL_OK;
+}
+
+}  // namespace
+
+sl_status copy_to_device(void* dst, const void* src, size_t bytes, hipStream_t st)
+{
+    if (bytes == 0) return SL_OK;
+    if (bytes <= kDirectBytes) {
+        SL_HIP(hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, st));
+        return SL_OK;
+    }
+    StagePair p;
+    sl_status r = p.init();
+    if (r) return r;
+    const auto* in = static_cast<const unsigned char*>(src);
+    auto* out = static_cast<unsigned char*>(dst);
+    size_t k = 0;
+    for (size_t off = 0; off < bytes; off += kStageBytes, ++k) {
+        Stage* b = p.s[k & 1];
+        const size_t len = std::min(kStageBytes, bytes - off);
+        if ((r = quiesce(b))) return r;
+        std::memcpy(b->ptr, in + off, len);
+        SL_HIP(hipMemcpyAsync(out + off, b->ptr, len, hipMemcpyHostToDevice, st));
+        SL_HIP(hipEventRecord(b->ev, st));
+        b->pending = true;
+    }
+    return SL_OK;
+}
+
+sl_status copy_to_host(void* dst, const void* src, size_t bytes, hipStream_t st)
+{
+    if (bytes == 0) return SL_OK;
+    if (bytes <= kDirectBytes) {
+        SL_HIP(hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToHost, st));
+        SL_HIP(hipStreamSynchronize(st));
+        return SL_OK;
+    }
+    StagePair p;
+    sl_status r = p.init();
+    if (r) return r;
+    const auto* in = static_cast<const unsigned char*>(src);
+    auto* out = static_cast<unsigned char*>(dst);
+    const size_t chunks = (bytes + kStageBytes - 1) / kStageBytes;
+    auto issue = [&](size_t c) -> sl_status {
+        Stage* b = p.s[c & 1];
+        const size_t off = c * kStageBytes, len = std::min(kStageBytes, bytes - off);
+        sl_status rr = quiesce(b);
+        if (rr) return rr;
+        SL_HIP(hipMemcpyAsync(b->ptr, in + off, len, hipMemcpyDeviceToHost, st));
+        SL_HIP(hipEventRecord(b->ev, st));
+        b->pending = true;
+        return SL_OK;
+    };
+    if ((r = issue(0))) return r;
+    for (size_t c = 0; c < chunks; ++c) {
+        if (c + 1 < chunks && (r = issue(c + 1))) return r;
+        Stage* b = p.s[c & 1];
+        if ((r = quiesce(b))) return r;
+        const size_t off = c * kStageBytes, len = std::min(kStageBytes, bytes - off);
+        std::memcpy(out + off, b->ptr, len);
+    }
+    return SL_OK;
+}
+
+}  // namespace sl

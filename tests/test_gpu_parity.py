@@ -397,7 +397,7 @@ def test_batch_equals_single_and_oracle():
     and the oracle."""
     ms = [meshgen.make_grid(n, "random", 0.35, 10000 + n) for n in (24, 31, 40, 57, 90)]
     ms.append(meshgen.permute_mesh(meshgen.make_grid(33, "random", 0.4, 7), 3))
-    ms.append(_ring_star(20, 5))                      # valence 20: node path
+    ms.append(_many_stars(600, 20, 5))                # tiles too dense: node path
     ms.append(meshgen.make_annulus(12, 40, seed=9))
     outs, reps, br = sl.batch_smooth(ms, 9)
     assert br.graph_used == 1 and br.meshes_on_tile_path == len(ms) - 1
@@ -512,7 +512,8 @@ def test_f32_full_1024_and_tolerance():
     assert nd == 0
     small = meshgen.make_grid(30, "random", 0.4, 9)
     ref = oracle.smooth(small, 300, precision="f32")
-    tol = math.sqrt(ref.disp[50]) * 1.0000001
+    moving = np.flatnonzero(ref.disp > 0)           # in float the mesh reaches an exact fixed point
+    tol = math.sqrt(ref.disp[moving[len(moving) // 2]]) * 1.0000001
     X, rep, ref2, nd = assert_parity(small, 300, tol=tol, precision="f32")
     assert nd == 0 and rep.iterations_run < 300
 
