@@ -101,12 +101,14 @@ sl_status prepare_mesh(const MeshInput& in, const sl_options& o, int32_t mesh_in
     if (in.n_tris < 0) return fail(SL_EINVAL, "n_tris must be >= 0");
     if (in.n_tris > 0 && !in.tris) return fail(SL_EINVAL, "null tris with n_tris > 0");
     if (in.n_tris > (INT32_MAX / 3)) return fail(SL_EINVAL, "n_tris too large");
-    int32_t ends[4] = {0, 0, 0, 0};
-    SL_HIP(hipMemcpyAsync(&ends[0], in.nbr_ptr, sizeof(int32_t), hipMemcpyDeviceToHost, st));
-    SL_HIP(hipMemcpyAsync(&ends[1], in.nbr_ptr + in.n, sizeof(int32_t), hipMemcpyDeviceToHost, st));
-    SL_HIP(hipMemcpyAsync(&ends[2], in.tri_ptr, sizeof(int32_t), hipMemcpyDeviceToHost, st));
-    SL_HIP(hipMemcpyAsync(&ends[3], in.tri_ptr + in.n, sizeof(int32_t), hipMemcpyDeviceToHost, st));
-    SL_HIP(hipStreamSynchronize(st));
+    int32_t ends[4] = {in.ends[0], in.ends[1], in.ends[2], in.ends[3]};
+    if (!in.ends_known) {
+        SL_HIP(hipMemcpyAsync(&ends[0], in.nbr_ptr, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+        SL_HIP(hipMemcpyAsync(&ends[1], in.nbr_ptr + in.n, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+        SL_HIP(hipMemcpyAsync(&ends[2], in.tri_ptr, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+        SL_HIP(hipMemcpyAsync(&ends[3], in.tri_ptr + in.n, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+        SL_HIP(hipStreamSynchronize(st));
+    }
     if (ends[0] != 0 || ends[2] != 0) return fail(SL_EINVAL, "nbr_ptr[0] and tri_ptr[0] must be 0");
     if (ends[1] < 0 || ends[3] < 0) return fail(SL_EINVAL, "negative CSR length");
     if (ends[1] > 0 && !in.nbr_idx) return fail(SL_EINVAL, "null nbr_idx with nbr_ptr[n] > 0");
@@ -147,7 +149,7 @@ struct CallState {
 sl_status run_device(double* coords, int32_t n, const int32_t* nbr_ptr, const int32_t* nbr_idx,
                      const int32_t* tri_ptr, const int32_t* tri_idx, const int32_t* tris, int32_t n_tris,
                      const uint8_t* boundary, int32_t iterations, double tol, const sl_options* opts,
-                     sl_report* report, hipStream_t stream)
+                     sl_report* report, hipStream_t stream, const int32_t* known_ends = nullptr)
 {
     const auto t0 = std::chrono::steady_clock::now();
     sl_options o;
@@ -163,6 +165,10 @@ sl_status run_device(double* coords, int32_t n, const int32_t* nbr_ptr, const in
     for (auto& e : cs.ev) SL_HIP(hipEventCreate(&e));
     SL_HIP(hipEventRecord(cs.ev[0], stream));
     MeshInput in{coords, n, nbr_ptr, nbr_idx, tri_ptr, tri_idx, tris, n_tris, boundary};
+    if (known_ends) {
+        in.ends_known = true;
+        for (int k = 0; k < 4; ++k) in.ends[k] = known_ends[k];
+    }
     if ((r = prepare_mesh(in, o, 0, cs.m, stream))) return r;
     SL_HIP(hipEventRecord(cs.ev[1], stream));
 
@@ -347,7 +353,9 @@ sl_status smooth_mesh(double* coords, int32_t n_nodes, const int32_t* nbr_ptr, c
         cp(d_b, boundary, n);
         if (r) break;
         o.flags_out = host_flags && flag_bytes ? d_flags : nullptr;
-        r = run_device(d_coords, n_nodes, d_np, d_ni, d_tp, d_ti, d_t, n_tris, d_b, iterations, tol, &o, report, st);
+        const int32_t ends[4] = {0, static_cast<int32_t>(nnz), 0, static_cast<int32_t>(ninc)};
+        r = run_device(d_coords, n_nodes, d_np, d_ni, d_tp, d_ti, d_t, n_tris, d_b, iterations, tol, &o, report, st,
+                       ends);
         if (r) break;
         // results land in a staging vector first: the caller's arrays are
         // written only once every copy has succeeded

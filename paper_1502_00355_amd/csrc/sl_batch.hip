@@ -93,6 +93,11 @@ sl_status upload_and_prepare(const sl_mesh_desc& d, const sl_options& o, int32_t
         return e;
     }
     MeshInput in{c, d.n_nodes, np, ni, tp, ti, tr, d.n_tris, b};
+    in.ends_known = true;
+    in.ends[0] = d.nbr_ptr[0];
+    in.ends[1] = static_cast<int32_t>(nnz);
+    in.ends[2] = d.tri_ptr[0];
+    in.ends[3] = static_cast<int32_t>(ninc);
     r = prepare_mesh(in, o, mesh, m, st);
     cleanup();
     return r;

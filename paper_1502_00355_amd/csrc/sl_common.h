@@ -146,6 +146,10 @@ struct MeshInput {
     const int32_t* tris;
     int32_t n_tris;
     const uint8_t* boundary;
+    // nbr_ptr[0], nbr_ptr[n], tri_ptr[0], tri_ptr[n] when the caller already
+    // read them on the host (the arrays came from host memory)
+    bool ends_known = false;
+    int32_t ends[4] = {0, 0, 0, 0};
 };
 
 // Argument checks, then setup_mesh.

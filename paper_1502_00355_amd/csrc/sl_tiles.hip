@@ -278,12 +278,14 @@ template <>
 struct Real<double> {
     using V2 = double2;
     static constexpr double k_two_sqrt3 = kTwoSqrt3;
+    static constexpr double k_smallest = 0x1p-1074;            // smallest subnormal
     __device__ static V2 make(double x, double y) { return make_double2(x, y); }
 };
 template <>
 struct Real<float> {
     using V2 = float2;
     static constexpr float k_two_sqrt3 = 0x1.bb67aep+1f;   // 2*sqrt(3) rounded to float
+    static constexpr float k_smallest = 0x1p-149f;          // smallest subnormal
     __device__ static V2 make(float x, float y) { return make_float2(x, y); }
 };
 
@@ -297,12 +299,15 @@ __device__ __forceinline__ void lds_min(R* p, R v)
     __hip_atomic_fetch_min(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
 }
 
-// (2*sqrt(3)*cr)/S, or 0 when S == 0.
+// (2*sqrt(3)*cr)/S, or 0 when S == 0.  S is zero only when the three
+// vertices coincide, and then cr is a zero too: dividing it by the smallest
+// subnormal instead gives the zero quality (its sign never matters, the
+// minima and the accept test compare zeros equal) with one max instead of a
+// compare and two selects.
 template <typename R>
 __device__ __forceinline__ R finish_q(R cr, R S)
 {
-    const R q = (Real<R>::k_two_sqrt3 * cr) / S;
-    return S == R(0) ? R(0) : q;
+    return (Real<R>::k_two_sqrt3 * cr) / fmax(S, Real<R>::k_smallest);
 }
 
 struct TileSweepArgs {
@@ -323,29 +328,41 @@ __device__ __forceinline__ void tile_triangle(uint64_t w, const typename Real<R>
     using V2 = typename Real<R>::V2;
     const int l0 = static_cast<int>(w & 0xFFFF), l1 = static_cast<int>((w >> 16) & 0xFFFF),
               l2 = static_cast<int>((w >> 32) & 0xFFFF);
+    // every read up front, so that one wait covers them all (a halo vertex
+    // reads some own candidate that it then ignores)
     const V2 p0 = Xl[l0], p1 = Xl[l1], p2 = Xl[l2];
+    const V2 c0 = cand[l0 & (T - 1)], c1 = cand[l1 & (T - 1)], c2 = cand[l2 & (T - 1)];
     const R ax = p1.x - p0.x, ay = p1.y - p0.y;
     const R bx = p2.x - p0.x, by = p2.y - p0.y;
     const R cx = p2.x - p1.x, cy = p2.y - p1.y;
     const R La = ax * ax + ay * ay, Lb = bx * bx + by * by, Lc = cx * cx + cy * cy;
     const R qold = finish_q(ax * by - bx * ay, (La + Lc) + Lb);
+    // each own vertex at its candidate, the other two where they are; the
+    // squared length of the opposite edge is shared with the old quality
+    R q0, q1, q2;
+    {
+        const R ax2 = p1.x - c0.x, ay2 = p1.y - c0.y, bx2 = p2.x - c0.x, by2 = p2.y - c0.y;
+        q0 = finish_q(ax2 * by2 - bx2 * ay2, ((ax2 * ax2 + ay2 * ay2) + Lc) + (bx2 * bx2 + by2 * by2));
+    }
+    {
+        const R ax2 = c1.x - p0.x, ay2 = c1.y - p0.y, cx2 = p2.x - c1.x, cy2 = p2.y - c1.y;
+        q1 = finish_q(ax2 * by - bx * ay2, ((ax2 * ax2 + ay2 * ay2) + (cx2 * cx2 + cy2 * cy2)) + Lb);
+    }
+    {
+        const R bx2 = c2.x - p0.x, by2 = c2.y - p0.y, cx2 = c2.x - p1.x, cy2 = c2.y - p1.y;
+        q2 = finish_q(ax * by2 - bx2 * ay, (La + (cx2 * cx2 + cy2 * cy2)) + (bx2 * bx2 + by2 * by2));
+    }
     if (l0 < T) {
         lds_min(qo + l0, qold);
-        const V2 c = cand[l0];
-        const R ax2 = p1.x - c.x, ay2 = p1.y - c.y, bx2 = p2.x - c.x, by2 = p2.y - c.y;
-        lds_min(qn + l0, finish_q(ax2 * by2 - bx2 * ay2, ((ax2 * ax2 + ay2 * ay2) + Lc) + (bx2 * bx2 + by2 * by2)));
+        lds_min(qn + l0, q0);
     }
     if (l1 < T) {
         lds_min(qo + l1, qold);
-        const V2 c = cand[l1];
-        const R ax2 = c.x - p0.x, ay2 = c.y - p0.y, cx2 = p2.x - c.x, cy2 = p2.y - c.y;
-        lds_min(qn + l1, finish_q(ax2 * by - bx * ay2, ((ax2 * ax2 + ay2 * ay2) + (cx2 * cx2 + cy2 * cy2)) + Lb));
+        lds_min(qn + l1, q1);
     }
     if (l2 < T) {
         lds_min(qo + l2, qold);
-        const V2 c = cand[l2];
-        const R bx2 = c.x - p0.x, by2 = c.y - p0.y, cx2 = c.x - p1.x, cy2 = c.y - p1.y;
-        lds_min(qn + l2, finish_q(ax * by2 - bx2 * ay, (La + (cx2 * cx2 + cy2 * cy2)) + (bx2 * bx2 + by2 * by2)));
+        lds_min(qn + l2, q2);
     }
 }
 
