@@ -100,7 +100,7 @@ def traffic_from_profile(kernel_source_hash: str):
 def kernel_source_hash() -> str:
     import hashlib
     h = hashlib.sha256()
-    for f in ("sl_sweep.hip", "sl_tiles.hip", "sl_common.h"):
+    for f in ("sl_tile_sweep.hip",):
         with open(os.path.join(ROOT, "paper_1502_00355_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()

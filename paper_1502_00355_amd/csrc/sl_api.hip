@@ -134,7 +134,7 @@ struct CallState {
     hipStream_t capture = nullptr;      // where the sweep chunk is captured
     ~CallState()
     {
-        if (capture) (void)hipStreamDestroy(capture);
+        if (capture) give_stream(capture);
         devmesh_free(m, st);
         dfree(state, st);
         dfree(bits, st);
@@ -208,7 +208,7 @@ sl_status run_device(double* coords, int32_t n, const int32_t* nbr_ptr, const in
     SL_HIP(hipEventRecord(cs.ev[2], stream));
     const bool use_graph = !cs.bits && its >= 2 * kSweepChunk;
     if (use_graph) {
-        SL_HIP(hipStreamCreateWithFlags(&cs.capture, hipStreamNonBlocking));
+        if ((r = take_stream(&cs.capture))) return r;
         SL_HIP(hipStreamBeginCapture(cs.capture, hipStreamCaptureModeThreadLocal));
         sl_status cr = SL_OK;
         for (int32_t s = 0; s < kSweepChunk && !cr; ++s) cr = enqueue(s, cs.capture);
@@ -326,48 +326,34 @@ sl_status smooth_mesh(double* coords, int32_t n_nodes, const int32_t* nbr_ptr, c
     if (opts) o = *opts;
     sl_status r = check_options(o);
     if (r) return r;
-    hipStream_t st = nullptr;
-    SL_HIP(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
+    PooledStream ps;
+    if ((r = ps.init())) return r;
+    hipStream_t st = ps.s;
     const size_t n = static_cast<size_t>(n_nodes);
-    double* d_coords = nullptr;
-    int32_t *d_np = nullptr, *d_ni = nullptr, *d_tp = nullptr, *d_ti = nullptr, *d_t = nullptr;
-    uint8_t *d_b = nullptr, *d_flags = nullptr;
     uint8_t* host_flags = o.flags_out;
     const size_t flag_bytes = (n + 7) / 8 * static_cast<size_t>(iterations);
     std::vector<double> out(2 * n);
+    DevInputs di;
     do {
-        if ((r = dalloc(&d_coords, 2 * n, st)) || (r = dalloc(&d_np, n + 1, st)) || (r = dalloc(&d_ni, nnz, st)) ||
-            (r = dalloc(&d_tp, n + 1, st)) || (r = dalloc(&d_ti, ninc, st)) ||
-            (r = dalloc(&d_t, 3 * static_cast<size_t>(n_tris), st)) || (r = dalloc(&d_b, n, st)))
-            break;
-        if (host_flags && flag_bytes && (r = dalloc(&d_flags, flag_bytes, st))) break;
-        auto cp = [&](void* dst, const void* src, size_t bytes) {
-            if (!r) r = copy_to_device(dst, src, bytes, st);
-        };
-        cp(d_coords, coords, 2 * n * sizeof(double));
-        cp(d_np, nbr_ptr, (n + 1) * sizeof(int32_t));
-        cp(d_ni, nbr_idx, static_cast<size_t>(nnz) * sizeof(int32_t));
-        cp(d_tp, tri_ptr, (n + 1) * sizeof(int32_t));
-        cp(d_ti, tri_idx, static_cast<size_t>(ninc) * sizeof(int32_t));
-        cp(d_t, tris, 3 * static_cast<size_t>(n_tris) * sizeof(int32_t));
-        cp(d_b, boundary, n);
-        if (r) break;
-        o.flags_out = host_flags && flag_bytes ? d_flags : nullptr;
+        const sl_mesh_desc d{coords, n_nodes, n_tris, nbr_ptr, nbr_idx, tri_ptr, tri_idx, tris, boundary};
+        const bool want_flags = host_flags && flag_bytes;
+        if ((r = upload_inputs(d, nnz, ninc, want_flags ? Arena::piece(flag_bytes) : 0, di, st))) break;
+        uint8_t* d_flags = nullptr;
+        if (want_flags && (r = di.ar.take(&d_flags, flag_bytes))) break;
+        o.flags_out = d_flags;
         const int32_t ends[4] = {0, static_cast<int32_t>(nnz), 0, static_cast<int32_t>(ninc)};
-        r = run_device(d_coords, n_nodes, d_np, d_ni, d_tp, d_ti, d_t, n_tris, d_b, iterations, tol, &o, report, st,
-                       ends);
+        r = run_device(di.coords, n_nodes, di.nbr_ptr, di.nbr_idx, di.tri_ptr, di.tri_idx, di.tris, n_tris,
+                       di.boundary, iterations, tol, &o, report, st, ends);
         if (r) break;
         // results land in a staging vector first: the caller's arrays are
         // written only once every copy has succeeded
-        if ((r = copy_to_host(out.data(), d_coords, 2 * n * sizeof(double), st))) break;
+        if ((r = copy_to_host(out.data(), di.coords, 2 * n * sizeof(double), st))) break;
         if (d_flags && (r = copy_to_host(host_flags, d_flags, flag_bytes, st))) break;
         std::memcpy(coords, out.data(), 2 * n * sizeof(double));
     } while (false);
     std::string keep = g_last_error;
-    dfree(d_coords, st); dfree(d_np, st); dfree(d_ni, st); dfree(d_tp, st); dfree(d_ti, st); dfree(d_t, st);
-    dfree(d_b, st); dfree(d_flags, st);
+    di.release(st);
     (void)hipStreamSynchronize(st);
-    (void)hipStreamDestroy(st);
     set_error(keep);
     return r;
 }

@@ -44,7 +44,8 @@ struct BatchState {
         dfree(out, st);
         (void)hipStreamSynchronize(st);
         for (auto s : setup_st)
-            if (s) (void)hipStreamDestroy(s);
+            if (s) give_stream(s);
+        if (st) give_stream(st);
         if (exec) (void)hipGraphExecDestroy(exec);
         if (graph) (void)hipGraphDestroy(graph);
         for (auto& e : ev)
@@ -64,42 +65,21 @@ sl_status upload_and_prepare(const sl_mesh_desc& d, const sl_options& o, int32_t
     const int64_t nnz = d.nbr_ptr[n], ninc = d.tri_ptr[n];
     if (d.nbr_ptr[0] != 0 || d.tri_ptr[0] != 0 || nnz < 0 || ninc < 0) return fail(SL_EINVAL, "bad CSR offsets");
     if ((nnz > 0 && !d.nbr_idx) || (ninc > 0 && !d.tri_idx)) return fail(SL_EINVAL, "null CSR index array");
-    double* c = nullptr;
-    int32_t *np = nullptr, *ni = nullptr, *tp = nullptr, *ti = nullptr, *tr = nullptr;
-    uint8_t* b = nullptr;
-    auto cleanup = [&] {
-        dfree(c, st); dfree(np, st); dfree(ni, st); dfree(tp, st); dfree(ti, st); dfree(tr, st); dfree(b, st);
-    };
-    sl_status r;
-    if ((r = dalloc(&c, 2 * n, st)) || (r = dalloc(&np, n + 1, st)) || (r = dalloc(&ni, nnz, st)) ||
-        (r = dalloc(&tp, n + 1, st)) || (r = dalloc(&ti, ninc, st)) ||
-        (r = dalloc(&tr, 3 * static_cast<size_t>(d.n_tris), st)) || (r = dalloc(&b, n, st))) {
-        cleanup();
+    DevInputs di;
+    sl_status r = upload_inputs(d, nnz, ninc, 0, di, st);
+    if (r) {
+        di.release(st);
         return r;
     }
-    sl_status e = SL_OK;
-    auto cp = [&](void* dst, const void* src, size_t bytes) {
-        if (!e) e = copy_to_device(dst, src, bytes, st);
-    };
-    cp(c, d.coords, 2 * n * sizeof(double));
-    cp(np, d.nbr_ptr, (n + 1) * sizeof(int32_t));
-    cp(ni, d.nbr_idx, static_cast<size_t>(nnz) * sizeof(int32_t));
-    cp(tp, d.tri_ptr, (n + 1) * sizeof(int32_t));
-    cp(ti, d.tri_idx, static_cast<size_t>(ninc) * sizeof(int32_t));
-    cp(tr, d.tris, 3 * static_cast<size_t>(d.n_tris) * sizeof(int32_t));
-    cp(b, d.boundary, n);
-    if (e) {
-        cleanup();
-        return e;
-    }
-    MeshInput in{c, d.n_nodes, np, ni, tp, ti, tr, d.n_tris, b};
+    MeshInput in{di.coords, d.n_nodes, di.nbr_ptr, di.nbr_idx, di.tri_ptr, di.tri_idx, di.tris, d.n_tris,
+                 di.boundary};
     in.ends_known = true;
     in.ends[0] = d.nbr_ptr[0];
     in.ends[1] = static_cast<int32_t>(nnz);
     in.ends[2] = d.tri_ptr[0];
     in.ends[3] = static_cast<int32_t>(ninc);
     r = prepare_mesh(in, o, mesh, m, st);
-    cleanup();
+    di.release(st);
     return r;
 }
 
@@ -129,7 +109,7 @@ sl_status sl_batch_smooth(const sl_mesh_desc* meshes, int32_t n_meshes, int32_t 
     keep_pool_warm();
 
     BatchState bs;
-    SL_HIP(hipStreamCreateWithFlags(&bs.st, hipStreamNonBlocking));
+    if ((r = take_stream(&bs.st))) return r;
     hipStream_t st = bs.st;
     for (auto& e : bs.ev) SL_HIP(hipEventCreate(&e));
 
@@ -137,7 +117,8 @@ sl_status sl_batch_smooth(const sl_mesh_desc* meshes, int32_t n_meshes, int32_t 
     bs.meshes.resize(static_cast<size_t>(n_meshes));
     const int32_t n_threads = std::min(n_meshes, kSetupThreads);
     bs.setup_st.assign(static_cast<size_t>(n_threads), nullptr);
-    for (auto& s : bs.setup_st) SL_HIP(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
+    for (auto& s : bs.setup_st)
+        if ((r = take_stream(&s))) return r;
     int device = 0;
     SL_HIP(hipGetDevice(&device));
     std::atomic<int32_t> next{0};

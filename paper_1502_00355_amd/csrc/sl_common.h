@@ -3,6 +3,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cstdint>
 #include <string>
 
@@ -47,6 +48,72 @@ struct ValStats {
     int32_t max_inc_free;
 };
 
+// ------------------------------------------------------ device memory --
+
+template <typename T>
+sl_status dalloc(T** p, size_t count, hipStream_t st)
+{
+    *p = nullptr;
+    if (count == 0) count = 1;
+    hipError_t e = hipMallocAsync(reinterpret_cast<void**>(p), count * sizeof(T), st);
+    if (e != hipSuccess) {
+        *p = nullptr;
+        (void)hipGetLastError();
+        return fail(SL_ENOMEM, std::string("device allocation of ") + std::to_string(count * sizeof(T)) +
+                                   " bytes failed: " + hipGetErrorString(e));
+    }
+    return SL_OK;
+}
+
+template <typename T>
+void dfree(T*& p, hipStream_t st)
+{
+    if (p) (void)hipFreeAsync(p, st);
+    p = nullptr;
+}
+
+inline int div_up(int64_t a, int64_t b) { return static_cast<int>((a + b - 1) / b); }
+
+// Device memory carved out of one stream-ordered allocation, so that a
+// mesh's setup makes a few allocator calls instead of dozens (each call
+// costs tens to hundreds of microseconds of host time).  Pieces are
+// 256-byte aligned.  mark()/rewind() give stack-like reuse for temporaries:
+// work on the stream that used a rewound piece runs before work that uses
+// it again.  A take() past the reservation fails loudly (a sizing error).
+struct Arena {
+    unsigned char* base = nullptr;
+    size_t cap = 0, used = 0;
+
+    static size_t piece(size_t bytes) { return (std::max<size_t>(bytes, 1) + 255) & ~size_t(255); }
+
+    sl_status reserve(size_t bytes, hipStream_t st)
+    {
+        used = 0;
+        cap = bytes;
+        return dalloc(&base, std::max<size_t>(bytes, 256), st);
+    }
+    template <typename T>
+    sl_status take(T** p, size_t count)
+    {
+        const size_t b = piece(count * sizeof(T));
+        if (!base || used + b > cap) {
+            *p = nullptr;
+            return fail(SL_ENOMEM, "arena of " + std::to_string(cap) + " bytes exhausted (" + std::to_string(used) +
+                                       " used, " + std::to_string(b) + " asked)");
+        }
+        *p = reinterpret_cast<T*>(base + used);
+        used += b;
+        return SL_OK;
+    }
+    size_t mark() const { return used; }
+    void rewind(size_t m) { used = m; }
+    void release(hipStream_t st)
+    {
+        dfree(base, st);
+        cap = used = 0;
+    }
+};
+
 // ------------------------------------------------------- device workspace --
 
 // Sweep state of one mesh on the device.  The sweep kernels read `active`
@@ -82,6 +149,7 @@ static_assert(sizeof(TileWork) == 80, "TileWork layout");
 // One mesh prepared for sweeping: free nodes occupy [0, n_free) in the
 // device order, fixed nodes [n_free, n).
 struct DevMesh {
+    unsigned char* block = nullptr;   // one allocation; every array below is carved from it
     int32_t n = 0, n_free = 0, n_tris = 0;
     int64_t nnz_free = 0, ninc_free = 0;
     int32_t max_deg = 0, max_inc = 0;
@@ -128,7 +196,15 @@ struct SetupArgs {
 // Builds the tile path for Form A (tile_nodes free nodes per tile) and
 // writes the tile list to m.work with MeshState index `mesh`.  Leaves
 // m.tile_nodes = 0 (node path) when the mesh does not fit it.
-sl_status build_tiles(const SetupArgs& a, DevMesh& m, int tile_nodes, int mesh, hipStream_t st);
+sl_status build_tiles(const SetupArgs& a, DevMesh& m, int tile_nodes, int mesh, hipStream_t st, Arena& persist,
+                      Arena& scratch);
+// Bytes build_tiles takes from `persist` for a mesh of at most n free nodes
+// with at most nnz neighbour entries and ninc incidences, and from `scratch`.
+size_t tile_bytes(int64_t n, int64_t nnz, int64_t ninc, int tile_nodes);
+size_t tile_scratch_bytes();
+// LDS bytes of one sweep work-group, and the most a work-group may use.
+size_t tile_lds_bytes(int tile_nodes, int halo_cap, int rows_cap, int32_t precision);
+constexpr size_t kTileLdsLimit = 160 * 1024 - 4096;
 
 // Validates the inputs, orders the nodes, builds rows and fans (node path)
 // or tiles (tile path, MeshState index `mesh`) and fills both coordinate
@@ -163,6 +239,38 @@ void keep_pool_warm();
 // data (it waits for the work enqueued on `st` before it).
 sl_status copy_to_device(void* dst, const void* src, size_t bytes, hipStream_t st);
 sl_status copy_to_host(void* dst, const void* src, size_t bytes, hipStream_t st);
+
+// Non-blocking streams of default priority from a per-device pool kept for
+// the life of the process (creating a stream costs hundreds of
+// microseconds).  A stream may go back with work still queued on it; the
+// next user's work then runs after that work.
+sl_status take_stream(hipStream_t* st);
+void give_stream(hipStream_t st);
+struct PooledStream {
+    hipStream_t s = nullptr;
+    PooledStream() = default;
+    PooledStream(const PooledStream&) = delete;
+    PooledStream& operator=(const PooledStream&) = delete;
+    ~PooledStream()
+    {
+        if (s) give_stream(s);
+    }
+    sl_status init() { return take_stream(&s); }
+};
+
+// One caller mesh's host arrays copied into a single device allocation
+// (nnz = nbr_ptr[n], ninc = tri_ptr[n], already read by the caller), with
+// `extra` more bytes left in `ar` for the caller.  release() frees it,
+// stream-ordered.
+struct DevInputs {
+    Arena ar;
+    double* coords = nullptr;
+    int32_t *nbr_ptr = nullptr, *nbr_idx = nullptr, *tri_ptr = nullptr, *tri_idx = nullptr, *tris = nullptr;
+    uint8_t* boundary = nullptr;
+    void release(hipStream_t st) { ar.release(st); }
+};
+sl_status upload_inputs(const sl_mesh_desc& d, int64_t nnz, int64_t ninc, size_t extra, DevInputs& out,
+                        hipStream_t st);
 
 // Uploads one caller mesh (host arrays) on `st` and prepares it; the
 // uploaded inputs are released once the device copy is built.
@@ -220,30 +328,8 @@ sl_status launch_advance(MeshState* states, int32_t n, hipStream_t st);
 int tile_grid(int n_work, int tile_nodes, int halo_cap, int rows_cap, int wg_per_cu, int32_t precision);
 
 // Exclusive scan of n int32 values; out[n] receives the total (out has n+1).
-sl_status scan_exclusive(const int32_t* in, int32_t* out, int64_t n, hipStream_t st);
-
-template <typename T>
-sl_status dalloc(T** p, size_t count, hipStream_t st)
-{
-    *p = nullptr;
-    if (count == 0) count = 1;
-    hipError_t e = hipMallocAsync(reinterpret_cast<void**>(p), count * sizeof(T), st);
-    if (e != hipSuccess) {
-        *p = nullptr;
-        (void)hipGetLastError();
-        return fail(SL_ENOMEM, std::string("device allocation of ") + std::to_string(count * sizeof(T)) +
-                                   " bytes failed: " + hipGetErrorString(e));
-    }
-    return SL_OK;
-}
-
-template <typename T>
-void dfree(T*& p, hipStream_t st)
-{
-    if (p) (void)hipFreeAsync(p, st);
-    p = nullptr;
-}
-
-inline int div_up(int64_t a, int64_t b) { return static_cast<int>((a + b - 1) / b); }
+// Temporaries come from `scratch` when given (and are given back before
+// the call returns), else from the allocator.
+sl_status scan_exclusive(const int32_t* in, int32_t* out, int64_t n, hipStream_t st, Arena* scratch = nullptr);
 
 }  // namespace sl

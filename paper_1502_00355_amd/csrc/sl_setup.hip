@@ -94,28 +94,43 @@ __global__ void k_set_total(int32_t* __restrict__ dst, const int32_t* __restrict
 constexpr int kScanIt = 8;
 constexpr int kScanTile = kBS * kScanIt;
 
-// Exclusive scan of in[0..n) into out[0..n); *total = sum.
-sl_status scan_rec(const int32_t* in, int32_t* out, int64_t n, int32_t* total, hipStream_t st)
+// Exclusive scan of in[0..n) into out[0..n); *total = sum.  Temporaries
+// come from `ar` when given, else from the allocator.
+sl_status scan_rec(const int32_t* in, int32_t* out, int64_t n, int32_t* total, hipStream_t st, Arena* ar)
 {
     const int nb = div_up(n > 0 ? n : 1, kScanTile);
-    int32_t* sums = nullptr;
-    sl_status r = dalloc(&sums, nb + 1, st);
+    auto get = [&](int32_t** p, size_t cnt) { return ar ? ar->take(p, cnt) : dalloc(p, cnt, st); };
+    auto put = [&](int32_t*& p) {
+        if (!ar) dfree(p, st);
+    };
+    int32_t *sums = nullptr, *offs = nullptr;
+    sl_status r = get(&sums, static_cast<size_t>(nb) + 1);
     if (r) return r;
     k_scan_block<kScanIt><<<nb, kBS, 0, st>>>(in, out, n, sums);
     if (nb == 1) {
         k_set_total<<<1, 1, 0, st>>>(total, sums);
-    } else {
-        int32_t* offs = nullptr;
-        r = dalloc(&offs, nb + 1, st);
-        if (r) { dfree(sums, st); return r; }
-        r = scan_rec(sums, offs, nb, total, st);
-        if (r) { dfree(sums, st); dfree(offs, st); return r; }
-        k_scan_add<<<div_up(n, 256), 256, 0, st>>>(out, n, offs, kScanTile);
-        dfree(offs, st);
+    } else if (!(r = get(&offs, static_cast<size_t>(nb) + 1))) {
+        r = scan_rec(sums, offs, nb, total, st, ar);
+        if (!r) k_scan_add<<<div_up(n, 256), 256, 0, st>>>(out, n, offs, kScanTile);
+        put(offs);
     }
-    dfree(sums, st);
+    put(sums);
+    if (r) return r;
     SL_HIP(hipGetLastError());
     return SL_OK;
+}
+
+// Arena bytes the temporaries of a scan of n values take.
+size_t scan_bytes(int64_t n)
+{
+    size_t b = 0;
+    for (int64_t m = n;; ) {
+        const int64_t nb = div_up(m > 0 ? m : 1, kScanTile);
+        b += 2 * Arena::piece(4 * static_cast<size_t>(nb + 1));
+        if (nb == 1) break;
+        m = nb;
+    }
+    return b;
 }
 
 // ----------------------------------------------------------- validation ---
@@ -520,40 +535,54 @@ __global__ __launch_bounds__(kBS) void k_unpermute_flags(const uint64_t* __restr
     out[g] = static_cast<uint8_t>(byte);
 }
 
+// Bits per axis of the Hilbert cells of the counting sort for n_free free
+// nodes in nc colour classes: grown while a class still has about two nodes
+// per cell or more, at most 2^25 buckets.  The bucket count stays below
+// max(4 nc, 2 n_free).
+int hilbert_bits(int64_t n_free, int nc)
+{
+    int bits = 1;
+    while (bits < 12 && (static_cast<int64_t>(nc) << (2 * bits)) < n_free / 2 &&
+           (static_cast<int64_t>(nc) << (2 * (bits + 1))) <= (int64_t(1) << 25))
+        ++bits;
+    return bits;
+}
+
+// Scratch bytes make_order takes for n nodes (at most 128 colour classes).
+size_t order_bytes(int64_t n)
+{
+    const int64_t nbk = std::max<int64_t>(4 * 128, 2 * n);
+    return 3 * Arena::piece(4 * static_cast<size_t>(n + 1)) + Arena::piece(4 * sizeof(uint64_t)) +
+           2 * Arena::piece(4 * static_cast<size_t>(nbk + 1)) + scan_bytes(std::max<int64_t>(n, nbk));
+}
+
 sl_status make_order(const SetupArgs& a, const sl_options& o, const uint8_t* bnd, int32_t n_free,
-                     const int32_t* color, int32_t n_colors, DevMesh& m, hipStream_t st)
+                     const int32_t* color, int32_t n_colors, DevMesh& m, hipStream_t st, Arena& scratch)
 {
     const int32_t n = a.n;
     const int gb = div_up(n, kBS);
+    const size_t mk = scratch.mark();
     int32_t *flag = nullptr, *pos = nullptr;
     sl_status r;
-    if ((r = dalloc(&flag, n, st)) || (r = dalloc(&pos, static_cast<size_t>(n) + 1, st))) {
-        dfree(flag, st);
-        return r;
-    }
+    if ((r = scratch.take(&flag, n)) || (r = scratch.take(&pos, static_cast<size_t>(n) + 1))) return r;
     int32_t* cs = m.color_start_h;
     cs[0] = 0;
     if (o.reorder == SL_REORDER_HILBERT && n_free > 0) {
         // bucket counting sort: (colour, Hilbert cell); order inside a bucket is arbitrary,
         // which no result depends on (rows and triangles keep their order).
         const int nc = color ? n_colors : 1;
-        int bits = 1;
-        while (bits < 12 && (static_cast<int64_t>(nc) << (2 * bits)) < n_free / 2 &&
-               (static_cast<int64_t>(nc) << (2 * (bits + 1))) <= (int64_t(1) << 25))
-            ++bits;
+        const int bits = hilbert_bits(n_free, nc);
         const int64_t nbk = static_cast<int64_t>(nc) << (2 * bits);
         uint64_t* bb = nullptr;
         int32_t *count = nullptr, *start = nullptr, *key = nullptr;
-        if ((r = dalloc(&bb, 4, st)) || (r = dalloc(&count, nbk, st)) || (r = dalloc(&start, nbk + 1, st)) ||
-            (r = dalloc(&key, n, st))) {
-            dfree(bb, st); dfree(count, st); dfree(start, st); dfree(key, st); dfree(flag, st); dfree(pos, st);
+        if ((r = scratch.take(&bb, 4)) || (r = scratch.take(&count, nbk)) || (r = scratch.take(&start, nbk + 1)) ||
+            (r = scratch.take(&key, n)))
             return r;
-        }
         k_bbox_init<<<1, 1, 0, st>>>(bb);
         k_bbox<<<std::min(gb, 2048), kBS, 0, st>>>(a.coords, n, bb);
         k_fill_i32<<<div_up(nbk, 256), 256, 0, st>>>(count, nbk, 0);
         k_bucket<<<gb, kBS, 0, st>>>(a.coords, bnd, color, n, bits, bb, key, count);
-        if ((r = scan_exclusive(count, start, nbk, st))) return r;
+        if ((r = scan_exclusive(count, start, nbk, st, &scratch))) return r;
         if (color) {
             std::vector<int32_t> h(static_cast<size_t>(nc) + 1);
             for (int c = 0; c <= nc; ++c) {
@@ -566,14 +595,13 @@ sl_status make_order(const SetupArgs& a, const sl_options& o, const uint8_t* bnd
             cs[1] = n_free;
         }
         k_bucket_scatter<<<gb, kBS, 0, st>>>(bnd, n, key, start, m.new_of_old, m.perm);
-        dfree(bb, st); dfree(count, st); dfree(start, st); dfree(key, st);
     } else if (n_free > 0) {
         // stable: free nodes (by colour class when coloured) in caller order
         const int nc = color ? n_colors : 1;
         int32_t base = 0;
         for (int c = 0; c < nc; ++c) {
             k_select<<<gb, kBS, 0, st>>>(bnd, color, c, 0, n, flag);
-            if ((r = scan_exclusive(flag, pos, n, st))) return r;
+            if ((r = scan_exclusive(flag, pos, n, st, &scratch))) return r;
             k_place<<<gb, kBS, 0, st>>>(flag, pos, base, n, m.new_of_old, m.perm);
             int32_t cnt = 0;
             SL_HIP(hipMemcpyAsync(&cnt, pos + n, sizeof(int32_t), hipMemcpyDeviceToHost, st));
@@ -584,37 +612,35 @@ sl_status make_order(const SetupArgs& a, const sl_options& o, const uint8_t* bnd
     }
     if (n_free < n) {
         k_select<<<gb, kBS, 0, st>>>(bnd, nullptr, 0, 1, n, flag);
-        if ((r = scan_exclusive(flag, pos, n, st))) return r;
+        if ((r = scan_exclusive(flag, pos, n, st, &scratch))) return r;
         k_place<<<gb, kBS, 0, st>>>(flag, pos, n_free, n, m.new_of_old, m.perm);
     }
-    dfree(flag, st);
-    dfree(pos, st);
+    scratch.rewind(mk);
     SL_HIP(hipGetLastError());
     return SL_OK;
 }
 
 }  // namespace
 
-sl_status scan_exclusive(const int32_t* in, int32_t* out, int64_t n, hipStream_t st)
+sl_status scan_exclusive(const int32_t* in, int32_t* out, int64_t n, hipStream_t st, Arena* scratch)
 {
-    return scan_rec(in, out, n, out + n, st);
+    const size_t mk = scratch ? scratch->mark() : 0;
+    const sl_status r = scan_rec(in, out, n, out + n, st, scratch);
+    if (scratch) scratch->rewind(mk);
+    return r;
 }
 
 void devmesh_free(DevMesh& m, hipStream_t st)
 {
-    dfree(m.perm, st);
-    dfree(m.new_of_old, st);
-    dfree(m.row_ptr, st);
-    dfree(m.nbr, st);
-    dfree(m.fan_ptr, st);
-    dfree(m.fan, st);
-    dfree(m.X[0], st);
-    m.X[1] = nullptr;
-    dfree(m.work, st);
-    dfree(m.halo, st);
-    dfree(m.nbr_loc, st);
-    dfree(m.row_rel, st);
-    dfree(m.tri_loc, st);
+    dfree(m.block, st);
+    m.perm = m.new_of_old = m.row_ptr = m.nbr = m.fan_ptr = nullptr;
+    m.fan = nullptr;
+    m.X[0] = m.X[1] = nullptr;
+    m.work = nullptr;
+    m.halo = nullptr;
+    m.nbr_loc = nullptr;
+    m.row_rel = nullptr;
+    m.tri_loc = nullptr;
 }
 
 sl_status setup_mesh(const SetupArgs& a, const sl_options& o, DevMesh& m, int32_t mesh, hipStream_t st)
@@ -623,10 +649,34 @@ sl_status setup_mesh(const SetupArgs& a, const sl_options& o, DevMesh& m, int32_
     m.n = n;
     m.n_tris = a.n_tris;
     m.layout = o.layout;
+    m.precision = o.precision;
     sl_status r;
+    const bool want_tiles = o.form == SL_JACOBI && o.kernel != SL_KERNEL_NODE;
+    const int T = resolve_tile_nodes(o);
+    const size_t rb = o.precision == SL_F32 ? 4 : 8;
+    const size_t un = static_cast<size_t>(n);
+    // Two reservations: the mesh's own arrays, sized from bounds known before
+    // validation (n >= free nodes, a.nnz and a.ninc >= their rows and fans),
+    // and the setup's temporaries, given back when setup ends.
+    Arena persist, scratch;
+    size_t pb = 2 * Arena::piece(4 * un) + 2 * Arena::piece(4 * (un + 1)) + Arena::piece(4 * un * rb);
+    pb += want_tiles ? tile_bytes(n, a.nnz, a.ninc, T)
+                     : Arena::piece(4 * static_cast<size_t>(a.nnz)) + Arena::piece(2 * static_cast<size_t>(a.ninc));
+    const size_t rows_bytes = 2 * Arena::piece(4 * un) + scan_bytes(n);
+    const size_t sb = Arena::piece(sizeof(ValStats)) + Arena::piece(4 * un) + Arena::piece(4) +
+                      std::max({order_bytes(n), rows_bytes, tile_scratch_bytes()});
+    if ((r = persist.reserve(pb, st))) return r;
+    m.block = persist.base;
+    if ((r = scratch.reserve(sb, st))) return r;
+    struct GiveBack {
+        Arena& ar;
+        hipStream_t st;
+        ~GiveBack() { ar.release(st); }
+    } give_back{scratch, st};
+
     // ---- validation
     ValStats* vs = nullptr;
-    if ((r = dalloc(&vs, 1, st))) return r;
+    if ((r = scratch.take(&vs, 1))) return r;
     SL_HIP(hipMemsetAsync(vs, 0, sizeof(ValStats), st));
     ValArgs va{a.coords, n, a.nbr_ptr, a.nbr_idx, a.tri_ptr, a.tri_idx, a.tris, a.n_tris, a.boundary,
                a.nnz, a.ninc, o.form == SL_INPLACE_COLORED};
@@ -636,7 +686,6 @@ sl_status setup_mesh(const SetupArgs& a, const sl_options& o, DevMesh& m, int32_
     ValStats h{};
     SL_HIP(hipMemcpyAsync(&h, vs, sizeof(ValStats), hipMemcpyDeviceToHost, st));
     SL_HIP(hipStreamSynchronize(st));
-    dfree(vs, st);
     if (h.err & (VE_PTR | VE_RANGE | VE_COORD)) {
         std::string msg = "invalid input:";
         if (h.err & VE_PTR) msg += " CSR offsets not monotone or out of range;";
@@ -659,7 +708,7 @@ sl_status setup_mesh(const SetupArgs& a, const sl_options& o, DevMesh& m, int32_
     m.max_deg = h.max_deg_free;
     m.max_inc = h.max_inc_free;
 
-    if ((r = dalloc(&m.perm, n, st)) || (r = dalloc(&m.new_of_old, n, st))) return r;
+    if ((r = persist.take(&m.perm, n)) || (r = persist.take(&m.new_of_old, n))) return r;
     const int gb = div_up(n, kBS);
 
     // ---- colouring (coloured form)
@@ -667,7 +716,7 @@ sl_status setup_mesh(const SetupArgs& a, const sl_options& o, DevMesh& m, int32_
     m.n_colors = 0;
     if (o.form == SL_INPLACE_COLORED && m.n_free > 0) {
         int32_t* remaining = nullptr;
-        if ((r = dalloc(&color, n, st)) || (r = dalloc(&remaining, 1, st))) { dfree(color, st); return r; }
+        if ((r = scratch.take(&color, n)) || (r = scratch.take(&remaining, 1))) return r;
         k_color_init<<<gb, kBS, 0, st>>>(n, a.boundary, color);
         for (int round = 0; round <= m.n_free; ++round) {
             k_fill_i32<<<1, 1, 0, st>>>(remaining, 1, 0);
@@ -682,64 +731,59 @@ sl_status setup_mesh(const SetupArgs& a, const sl_options& o, DevMesh& m, int32_
         int32_t mx = -1;
         SL_HIP(hipMemcpyAsync(&mx, remaining, sizeof(int32_t), hipMemcpyDeviceToHost, st));
         SL_HIP(hipStreamSynchronize(st));
-        dfree(remaining, st);
         m.n_colors = mx + 1;
-        if (m.n_colors > 128) { dfree(color, st); return fail(SL_ETOPO, "more than 128 colour classes"); }
+        if (m.n_colors > 128) return fail(SL_ETOPO, "more than 128 colour classes");
     }
 
     // ---- node order
-    r = make_order(a, o, a.boundary, m.n_free, color, m.n_colors, m, st);
-    dfree(color, st);
-    if (r) return r;
+    if ((r = make_order(a, o, a.boundary, m.n_free, color, m.n_colors, m, st, scratch))) return r;
 
     // ---- rows and fans of free nodes
-    if ((r = dalloc(&m.row_ptr, static_cast<size_t>(m.n_free) + 1, st)) ||
-        (r = dalloc(&m.fan_ptr, static_cast<size_t>(m.n_free) + 1, st)))
+    if ((r = persist.take(&m.row_ptr, static_cast<size_t>(m.n_free) + 1)) ||
+        (r = persist.take(&m.fan_ptr, static_cast<size_t>(m.n_free) + 1)))
         return r;
+    const size_t mk = scratch.mark();
     int32_t *deg = nullptr, *inc = nullptr;
-    if ((r = dalloc(&deg, m.n_free, st)) || (r = dalloc(&inc, m.n_free, st))) { dfree(deg, st); return r; }
+    if ((r = scratch.take(&deg, m.n_free)) || (r = scratch.take(&inc, m.n_free))) return r;
     const int gf = div_up(m.n_free > 0 ? m.n_free : 1, kBS);
     if (m.n_free > 0) k_degrees<<<gf, kBS, 0, st>>>(m.perm, m.n_free, a.nbr_ptr, a.tri_ptr, deg, inc);
-    if ((r = scan_exclusive(deg, m.row_ptr, m.n_free, st)) || (r = scan_exclusive(inc, m.fan_ptr, m.n_free, st)))
+    if ((r = scan_exclusive(deg, m.row_ptr, m.n_free, st, &scratch)) ||
+        (r = scan_exclusive(inc, m.fan_ptr, m.n_free, st, &scratch)))
         return r;
     int32_t tot[2] = {0, 0};
     SL_HIP(hipMemcpyAsync(&tot[0], m.row_ptr + m.n_free, sizeof(int32_t), hipMemcpyDeviceToHost, st));
     SL_HIP(hipMemcpyAsync(&tot[1], m.fan_ptr + m.n_free, sizeof(int32_t), hipMemcpyDeviceToHost, st));
     SL_HIP(hipStreamSynchronize(st));
-    dfree(deg, st);
-    dfree(inc, st);
+    scratch.rewind(mk);
     m.nnz_free = tot[0];
     m.ninc_free = tot[1];
     // coordinate buffers: one block, X[1] right after X[0], in the sweep's precision
-    m.precision = o.precision;
-    const size_t n2 = 2 * static_cast<size_t>(n);
+    const size_t n2 = 2 * un;
     if (m.precision == SL_F32) {
         float* xf = nullptr;
-        if ((r = dalloc(&xf, 2 * n2, st))) return r;
+        if ((r = persist.take(&xf, 2 * n2))) return r;
         m.X[0] = xf;
         m.X[1] = xf + n2;
         k_init_coords<float><<<gb, kBS, 0, st>>>(a.coords, m.perm, n, o.layout == SL_SOA, xf, xf + n2);
     } else {
         double* xd = nullptr;
-        if ((r = dalloc(&xd, 2 * n2, st))) return r;
+        if ((r = persist.take(&xd, 2 * n2))) return r;
         m.X[0] = xd;
         m.X[1] = xd + n2;
         k_init_coords<double><<<gb, kBS, 0, st>>>(a.coords, m.perm, n, o.layout == SL_SOA, xd, xd + n2);
     }
     // tile path for Form A; the node path's rows and fans otherwise
-    if (o.form == SL_JACOBI && o.kernel != SL_KERNEL_NODE)
-        if ((r = build_tiles(a, m, resolve_tile_nodes(o), mesh, st))) return r;
+    if (want_tiles && (r = build_tiles(a, m, T, mesh, st, persist, scratch))) return r;
     if (m.tile_nodes == 0 && m.precision == SL_F32 && m.n_free > 0)
         return fail(SL_EINVAL, "single precision needs the tile path, and this mesh does not fit it");
     if (m.tile_nodes == 0) {
-        if ((r = dalloc(&m.nbr, m.nnz_free, st)) || (r = dalloc(&m.fan, m.ninc_free, st))) return r;
+        // (a mesh that did not fit the tile path gave the tile arrays' room back,
+        // which bounds this)
+        if ((r = persist.take(&m.nbr, m.nnz_free)) || (r = persist.take(&m.fan, m.ninc_free))) return r;
         if (m.n_free > 0)
             k_rows_fans<<<gf, kBS, 0, st>>>(m.perm, m.new_of_old, m.n_free, a.nbr_ptr, a.nbr_idx, a.tri_ptr,
                                             a.tri_idx, a.tris, m.row_ptr, m.nbr, m.fan_ptr, m.fan);
     }
-
-    // ---- coordinate buffers
-
     SL_HIP(hipGetLastError());
     return SL_OK;
 }

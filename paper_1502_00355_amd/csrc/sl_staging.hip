@@ -1,5 +1,5 @@
 // Copies between callers' host memory and the device through pinned
-// staging buffers.
+// staging buffers, and the library's pool of streams.
 //
 // Callers hand in ordinary (pageable) host arrays.  A copy from pageable
 // memory is carried out by the runtime synchronously through its own
@@ -11,6 +11,7 @@
 // whoever takes it next waits for that event before touching it.
 #include <cstring>
 #include <mutex>
+#include <unordered_map>
 #include <vector>
 
 #include "sl_common.h"
@@ -149,6 +150,67 @@ sl_status copy_to_host(void* dst, const void* src, size_t bytes, hipStream_t st)
         std::memcpy(out + off, b->ptr, len);
     }
     return SL_OK;
+}
+
+sl_status upload_inputs(const sl_mesh_desc& d, int64_t nnz, int64_t ninc, size_t extra, DevInputs& out,
+                        hipStream_t st)
+{
+    const size_t n = static_cast<size_t>(d.n_nodes), t3 = 3 * static_cast<size_t>(d.n_tris);
+    const size_t bytes = Arena::piece(16 * n) + 2 * Arena::piece(4 * (n + 1)) +
+                         Arena::piece(4 * static_cast<size_t>(nnz)) + Arena::piece(4 * static_cast<size_t>(ninc)) +
+                         Arena::piece(4 * t3) + Arena::piece(n) + extra;
+    sl_status r;
+    if ((r = out.ar.reserve(bytes, st))) return r;
+    if ((r = out.ar.take(&out.coords, 2 * n)) || (r = out.ar.take(&out.nbr_ptr, n + 1)) ||
+        (r = out.ar.take(&out.nbr_idx, static_cast<size_t>(nnz))) || (r = out.ar.take(&out.tri_ptr, n + 1)) ||
+        (r = out.ar.take(&out.tri_idx, static_cast<size_t>(ninc))) || (r = out.ar.take(&out.tris, t3)) ||
+        (r = out.ar.take(&out.boundary, n)))
+        return r;
+    if ((r = copy_to_device(out.coords, d.coords, 2 * n * sizeof(double), st)) ||
+        (r = copy_to_device(out.nbr_ptr, d.nbr_ptr, (n + 1) * sizeof(int32_t), st)) ||
+        (r = copy_to_device(out.nbr_idx, d.nbr_idx, static_cast<size_t>(nnz) * sizeof(int32_t), st)) ||
+        (r = copy_to_device(out.tri_ptr, d.tri_ptr, (n + 1) * sizeof(int32_t), st)) ||
+        (r = copy_to_device(out.tri_idx, d.tri_idx, static_cast<size_t>(ninc) * sizeof(int32_t), st)) ||
+        (r = copy_to_device(out.tris, d.tris, t3 * sizeof(int32_t), st)) ||
+        (r = copy_to_device(out.boundary, d.boundary, n, st)))
+        return r;
+    return SL_OK;
+}
+
+namespace {
+
+std::mutex g_stream_mu;
+std::vector<hipStream_t> g_stream_free[64];
+std::unordered_map<hipStream_t, int> g_stream_dev;
+
+}  // namespace
+
+sl_status take_stream(hipStream_t* st)
+{
+    *st = nullptr;
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return fail(SL_EDEVICE, "no current device");
+    {
+        std::lock_guard<std::mutex> lk(g_stream_mu);
+        if (!g_stream_free[dev].empty()) {
+            *st = g_stream_free[dev].back();
+            g_stream_free[dev].pop_back();
+            return SL_OK;
+        }
+    }
+    hipStream_t s = nullptr;
+    SL_HIP(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
+    std::lock_guard<std::mutex> lk(g_stream_mu);
+    g_stream_dev[s] = dev;
+    *st = s;
+    return SL_OK;
+}
+
+void give_stream(hipStream_t st)
+{
+    std::lock_guard<std::mutex> lk(g_stream_mu);
+    auto it = g_stream_dev.find(st);
+    if (it != g_stream_dev.end()) g_stream_free[it->second].push_back(st);
 }
 
 }  // namespace sl

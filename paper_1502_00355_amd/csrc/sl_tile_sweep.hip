@@ -1,4 +1,4 @@
-// Tile path of the Form A (Jacobi) sweep.
+// Tile sweep of the Form A (Jacobi) form.
 //
 // The free nodes (device order: Hilbert cells) are cut into tiles of T
 // consecutive labels, one work-group per tile.  Per sweep a work-group
@@ -17,11 +17,6 @@
 // A triangle's old quality is evaluated by every tile that owns one of its
 // vertices (the paper evaluates it once per vertex, Sec. 5.3); each
 // (triangle, moved vertex) pair is evaluated exactly once.
-//
-// The tiles are built on the device: one work-group per tile collects the
-// halo and the incident triangles in LDS, sorts and deduplicates them, and
-// rewrites rows and triangles in tile-local indices (own nodes 0..T-1, halo
-// nodes T..T+H-1).
 #include <algorithm>
 #include <climits>
 #include <cstdlib>
@@ -33,239 +28,6 @@ namespace sl {
 namespace {
 
 constexpr double kTwoSqrt3 = 0x1.bb67ae8584caap+1;   // 2*sqrt(3) rounded to double
-constexpr int kTileMaxDeg = 16;                       // neighbour entries per own node, on average over a tile
-constexpr int kBuildBS = 256;
-
-// ------------------------------------------------------ block primitives --
-
-template <int BS>
-__device__ int block_excl_scan(int v, int* total, int* s_warp)
-{
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    int x = v;
-    for (int off = 1; off < 64; off <<= 1) {
-        const int t = __shfl_up(x, off);
-        if (lane >= off) x += t;
-    }
-    if (lane == 63) s_warp[w] = x;
-    __syncthreads();
-    int base = 0, tot = 0;
-    for (int q = 0; q < BS / 64; ++q) {
-        const int c = s_warp[q];
-        if (q < w) base += c;
-        tot += c;
-    }
-    __syncthreads();
-    *total = tot;
-    return base + x - v;
-}
-
-__device__ __forceinline__ int pow2ceil(int n)
-{
-    int p = 1;
-    while (p < n) p <<= 1;
-    return p;
-}
-
-// Bitonic sort of a[0..n) (padded to P, a power of two, with INT_MAX).
-template <int BS>
-__device__ void block_sort(int32_t* a, int n, int P)
-{
-    for (int i = n + threadIdx.x; i < P; i += BS) a[i] = INT_MAX;
-    __syncthreads();
-    for (int k = 2; k <= P; k <<= 1) {
-        for (int j = k >> 1; j > 0; j >>= 1) {
-            for (int i = threadIdx.x; i < P; i += BS) {
-                const int l = i ^ j;
-                if (l > i) {
-                    const int32_t x = a[i], y = a[l];
-                    const bool up = (i & k) == 0;
-                    if ((x > y) == up) { a[i] = y; a[l] = x; }
-                }
-            }
-            __syncthreads();
-        }
-    }
-}
-
-// In-place removal of duplicates from the sorted a[0..n); returns the count.
-template <int BS>
-__device__ int block_unique(int32_t* a, int n, int* s_warp)
-{
-    int out = 0;
-    for (int base = 0; base < n; base += BS) {
-        const int i = base + threadIdx.x;
-        int32_t v = 0;
-        int f = 0;
-        if (i < n) {
-            v = a[i];
-            f = (i == 0) || (v != a[i - 1]);
-        }
-        int tot;
-        const int pos = block_excl_scan<BS>(f, &tot, s_warp);
-        if (f) a[out + pos] = v;
-        out += tot;
-        __syncthreads();
-    }
-    return out;
-}
-
-__device__ __forceinline__ int lower_bound_lds(const int32_t* a, int n, int32_t v)
-{
-    int lo = 0, hi = n;
-    while (lo < hi) {
-        const int mid = (lo + hi) >> 1;
-        if (a[mid] < v) lo = mid + 1;
-        else hi = mid;
-    }
-    return lo;
-}
-
-// ------------------------------------------------------------ tile build --
-
-struct TileBuildArgs {
-    const int32_t* perm;
-    const int32_t* new_of_old;
-    const int32_t* nbr_ptr;
-    const int32_t* nbr_idx;
-    const int32_t* tri_ptr;
-    const int32_t* tri_idx;
-    const int32_t* tris;
-    const int32_t* row_ptr;    // device-order rows of the free nodes
-    const int32_t* fan_ptr;    // device-order incidence offsets of the free nodes
-    int32_t n_free;
-    int32_t mesh;              // MeshState index written into the descriptors
-    int64_t n;
-    const void* X;
-    int32_t* halo;             // [nnz_free]: tile k writes at row_ptr[k0] (halo <= row entries)
-    uint16_t* nbr_loc;         // tile k writes at align4(row_ptr[k0]) + 8k (segments never overlap)
-    uint32_t* row_rel;         // [n_tiles * T]
-    uint64_t* tri_loc;         // [ninc_free]: tile k writes at fan_ptr[k0] (kept <= incidences)
-    TileWork* work;            // [n_tiles]
-    int32_t* mx;               // {largest halo, largest padded row segment}
-    int32_t* err;
-};
-
-__host__ __device__ __forceinline__ int64_t row_seg_off(int32_t row_start, int32_t tile)
-{
-    return ((static_cast<int64_t>(row_start) + 3) & ~int64_t(3)) + 8 * static_cast<int64_t>(tile);
-}
-
-// One work-group per tile, in one pass: every output of tile k goes to a
-// place fixed by the row and incidence offsets of its first node, so no
-// tile needs another's counts.  Halo: every neighbour of an own node that
-// is not own, sorted and deduplicated.  Triangles: each triangle incident to
-// an own node, listed once per tile by its own vertex of smallest label.
-// Rows: the tile's neighbour rows in local indices, one segment padded to 4
-// entries.
-template <int T>
-__global__ __launch_bounds__(kBuildBS) void k_tile_build(TileBuildArgs a)
-{
-    constexpr int BS = kBuildBS, CAP = T * kTileMaxDeg, NPT = T / BS;
-    __shared__ int32_t hb[CAP];
-    __shared__ int32_t s_cnt;
-    __shared__ int32_t s_warp[BS / 64];
-    const int tile = blockIdx.x;
-    const int32_t k0 = tile * T;
-    const int nown = min(T, a.n_free - k0);
-    const int32_t rb = a.row_ptr[k0];
-    const int32_t len = a.row_ptr[k0 + nown] - rb;
-    if (len > CAP) {   // more neighbour entries than the halo staging holds: the mesh takes the node path
-        if (threadIdx.x == 0) atomicOr(a.err, 2);
-        return;
-    }
-    if (threadIdx.x == 0) s_cnt = 0;
-    __syncthreads();
-    for (int i = threadIdx.x; i < nown; i += BS) {
-        const int32_t o = a.perm[k0 + i];
-        for (int32_t q = a.nbr_ptr[o]; q < a.nbr_ptr[o + 1]; ++q) {
-            const int32_t jd = a.new_of_old[a.nbr_idx[q]];
-            if (jd < k0 || jd >= k0 + nown) hb[atomicAdd(&s_cnt, 1)] = jd;
-        }
-    }
-    __syncthreads();
-    const int nh0 = s_cnt;
-    block_sort<BS>(hb, nh0, pow2ceil(nh0));
-    const int H = block_unique<BS>(hb, nh0, s_warp);
-
-    // triangles kept by this tile: the listing node is the smallest own vertex
-    auto kept = [&](int32_t o, int32_t kd, int64_t t) -> bool {
-        for (int s = 0; s < 3; ++s) {
-            const int32_t v = a.tris[3 * t + s];
-            if (v == o) continue;
-            const int32_t vd = a.new_of_old[v];
-            if (vd >= k0 && vd < k0 + nown && vd < kd) return false;
-        }
-        return true;
-    };
-    auto local = [&](int32_t jd) -> int {
-        if (jd >= k0 && jd < k0 + nown) return jd - k0;
-        const int h = lower_bound_lds(hb, H, jd);
-        if (h >= H || hb[h] != jd) { atomicOr(a.err, 1); return T; }
-        return T + h;
-    };
-    const int32_t len4 = (len + 3) & ~3;
-    int32_t* halo = a.halo + rb;
-    uint16_t* seg = a.nbr_loc + row_seg_off(rb, tile);
-    uint64_t* tri = a.tri_loc + a.fan_ptr[k0];
-    for (int h = threadIdx.x; h < H; h += BS) halo[h] = hb[h];
-    uint32_t* rr = a.row_rel + static_cast<int64_t>(tile) * T;
-    for (int i = threadIdx.x; i < T; i += BS)
-        rr[i] = static_cast<uint32_t>(a.row_ptr[k0 + min(i, nown)] - rb) |
-                (static_cast<uint32_t>(a.row_ptr[k0 + min(i + 1, nown)] - rb) << 16);
-    for (int j = len + threadIdx.x; j < len4; j += BS) seg[j] = 0;
-    for (int m = 0; m < NPT; ++m) {
-        const int i = m * BS + threadIdx.x;
-        if (i >= nown) continue;
-        const int32_t o = a.perm[k0 + i];
-        const int32_t b = a.nbr_ptr[o], d = a.nbr_ptr[o + 1] - b, out = a.row_ptr[k0 + i] - rb;
-        for (int j = 0; j < d; ++j) seg[out + j] = static_cast<uint16_t>(local(a.new_of_old[a.nbr_idx[b + j]]));
-    }
-    // triangles are listed in node order (work-item t lists nodes NPT*t ..
-    // NPT*t+NPT-1), so that the lanes of a wave walking the list touch one
-    // compact patch of nodes in LDS
-    int c = 0;
-    for (int m = 0; m < NPT; ++m) {
-        const int i = NPT * threadIdx.x + m;
-        if (i < nown) {
-            const int32_t o = a.perm[k0 + i];
-            for (int32_t q = a.tri_ptr[o]; q < a.tri_ptr[o + 1]; ++q) c += kept(o, k0 + i, a.tri_idx[q]);
-        }
-    }
-    int R;
-    int tpos = block_excl_scan<BS>(c, &R, s_warp);
-    for (int m = 0; m < NPT; ++m) {
-        const int i = NPT * threadIdx.x + m;
-        if (i >= nown) continue;
-        const int32_t o = a.perm[k0 + i];
-        for (int32_t q = a.tri_ptr[o]; q < a.tri_ptr[o + 1]; ++q) {
-            const int64_t t = a.tri_idx[q];
-            if (!kept(o, k0 + i, t)) continue;
-            uint64_t w = 0;
-            for (int s = 0; s < 3; ++s)
-                w |= static_cast<uint64_t>(local(a.new_of_old[a.tris[3 * t + s]])) << (16 * s);
-            tri[tpos++] = w;
-        }
-    }
-    if (threadIdx.x == 0) {
-        TileWork w;
-        w.X = a.X;
-        w.halo = halo;
-        w.rows = reinterpret_cast<const uint64_t*>(seg);
-        w.tris = tri;
-        w.rr = rr;
-        w.own_start = k0;
-        w.nown = nown;
-        w.halo_cnt = H;
-        w.tri_cnt = R;
-        w.row_words = len4 >> 2;
-        w.mesh = a.mesh;
-        w.n = a.n;
-        a.work[tile] = w;
-        atomicMax(a.mx, H);
-        atomicMax(a.mx + 1, len4);
-    }
-}
 
 // ------------------------------------------------------------ tile sweep --
 
@@ -665,7 +427,6 @@ __global__ __launch_bounds__(BS) void k_sweep_tile(TileSweepArgs a)
 }
 
 constexpr int kTileBS = 256;
-constexpr int kLdsLimit = 160 * 1024 - 4096;
 
 template <int T, int BS, bool SOA, bool GT, typename R>
 void launch_tile_variant(const TileSweepArgs& a, int grid, size_t lds, hipStream_t st)
@@ -690,87 +451,23 @@ void launch_tile_t(const TileSweepArgs& a, bool soa, bool gt, int grid, size_t l
     }
 }
 
-// LDS of one work-group: own and halo positions, candidates and the two
-// per-node minima in the sweep's precision (real_bytes 8 or 4), u16 rows.
-size_t tile_lds_bytes(int tile_nodes, int halo_cap, int rows_cap, int real_bytes)
-{
-    return static_cast<size_t>(tile_nodes + halo_cap) * 2 * real_bytes +
-           static_cast<size_t>(tile_nodes) * 4 * real_bytes + static_cast<size_t>(rows_cap) * 2;
-}
-
-int real_bytes_of(int32_t precision) { return precision == SL_F32 ? 4 : 8; }
-
 }  // namespace
 
-sl_status build_tiles(const SetupArgs& a, DevMesh& m, int tile_nodes, int mesh, hipStream_t st)
+// LDS of one work-group: own and halo positions, candidates and the two
+// per-node minima in the sweep's precision, u16 rows.
+size_t tile_lds_bytes(int tile_nodes, int halo_cap, int rows_cap, int32_t precision)
 {
-    m.tile_nodes = 0;
-    if ((tile_nodes != 256 && tile_nodes != 512) || m.n_free == 0) return SL_OK;
-    const int T = tile_nodes;
-    const int nt = div_up(m.n_free, T);
-    sl_status r = SL_OK;
-    int32_t* flags = nullptr;   // {err, largest halo, largest row segment}
-    if ((r = dalloc(&flags, 3, st))) return r;
-    SL_HIP(hipMemsetAsync(flags, 0, 3 * sizeof(int32_t), st));
-    if ((r = dalloc(&m.work, nt, st)) || (r = dalloc(&m.halo, std::max<int64_t>(m.nnz_free, 1), st)) ||
-        (r = dalloc(&m.nbr_loc, static_cast<size_t>(m.nnz_free) + 8 * static_cast<size_t>(nt) + 8, st)) ||
-        (r = dalloc(&m.row_rel, static_cast<size_t>(nt) * T, st)) ||
-        (r = dalloc(&m.tri_loc, std::max<int64_t>(m.ninc_free, 1), st))) {
-        dfree(flags, st);
-        return r;
-    }
-    TileBuildArgs b{};
-    b.perm = m.perm;
-    b.new_of_old = m.new_of_old;
-    b.nbr_ptr = a.nbr_ptr;
-    b.nbr_idx = a.nbr_idx;
-    b.tri_ptr = a.tri_ptr;
-    b.tri_idx = a.tri_idx;
-    b.tris = a.tris;
-    b.row_ptr = m.row_ptr;
-    b.fan_ptr = m.fan_ptr;
-    b.n_free = m.n_free;
-    b.mesh = mesh;
-    b.n = m.n;
-    b.X = m.X[0];
-    b.halo = m.halo;
-    b.nbr_loc = m.nbr_loc;
-    b.row_rel = m.row_rel;
-    b.tri_loc = m.tri_loc;
-    b.work = m.work;
-    b.err = flags;
-    b.mx = flags + 1;
-    if (T == 256) k_tile_build<256><<<nt, kBuildBS, 0, st>>>(b);
-    else k_tile_build<512><<<nt, kBuildBS, 0, st>>>(b);
-    SL_HIP(hipGetLastError());
-    int32_t h[3] = {0, 0, 0};
-    SL_HIP(hipMemcpyAsync(h, flags, 3 * sizeof(int32_t), hipMemcpyDeviceToHost, st));
-    SL_HIP(hipStreamSynchronize(st));
-    dfree(flags, st);
-    if (h[0] & 1) return fail(SL_ETOPO, "triangle vertex outside its tile's neighbourhood");
-    // a tile denser than the staging holds, or a halo or row segment too big
-    // for LDS: the node path
-    if ((h[0] & 2) || tile_lds_bytes(T, h[1], h[2], real_bytes_of(m.precision)) > static_cast<size_t>(kLdsLimit)) {
-        dfree(m.work, st);
-        dfree(m.halo, st);
-        dfree(m.nbr_loc, st);
-        dfree(m.row_rel, st);
-        dfree(m.tri_loc, st);
-        return SL_OK;
-    }
-    m.halo_max = h[1];
-    m.rows_max = h[2];
-    m.n_tiles = nt;
-    m.tile_nodes = T;
-    return SL_OK;
+    const size_t rb = precision == SL_F32 ? 4 : 8;
+    return static_cast<size_t>(tile_nodes + halo_cap) * 2 * rb + static_cast<size_t>(tile_nodes) * 4 * rb +
+           static_cast<size_t>(rows_cap) * 2;
 }
 
 int tile_grid(int n_work, int tile_nodes, int halo_cap, int rows_cap, int wg_per_cu, int32_t precision)
 {
-    const size_t lds = tile_lds_bytes(tile_nodes, halo_cap, rows_cap, real_bytes_of(precision));
+    const size_t lds = tile_lds_bytes(tile_nodes, halo_cap, rows_cap, precision);
     // work-groups per CU: as requested (else 4), no more than fit the LDS;
     // 32 CUs per XCD; never more work-groups than tiles on an XCD
-    const int fit = std::max(1, static_cast<int>(kLdsLimit / std::max<size_t>(lds, 1)));
+    const int fit = std::max(1, static_cast<int>(kTileLdsLimit / std::max<size_t>(lds, 1)));
     const int per_cu = std::min(wg_per_cu > 0 ? wg_per_cu : 4, fit);
     const int tpx = div_up(std::max(n_work, 1), 8);
     const int nw = std::min(tpx, 32 * per_cu);
@@ -790,7 +487,7 @@ sl_status launch_sweep_tiles(const TileLaunch& L, int32_t parity, uint64_t* bits
     a.exit_if_inactive = L.exit_if_inactive;
     a.states = L.states;
     a.bits = bits;
-    const size_t lds = tile_lds_bytes(L.tile_nodes, L.halo_cap, L.rows_cap, real_bytes_of(L.precision));
+    const size_t lds = tile_lds_bytes(L.tile_nodes, L.halo_cap, L.rows_cap, L.precision);
     const int grid = tile_grid(L.n_work, L.tile_nodes, L.halo_cap, L.rows_cap, L.wg_per_cu, L.precision);
     const bool soa = L.layout == SL_SOA, gt = L.accept == SL_ACCEPT_GT;
     if (L.precision == SL_F32) {
