@@ -83,8 +83,9 @@ typedef enum {
     SL_KERNEL_AUTO = 0,  /* tile kernel for Form A when the mesh fits it, else the node kernel */
     SL_KERNEL_NODE = 1,  /* one work-item per free node, neighbours gathered from HBM/L2 */
     SL_KERNEL_TILE = 2   /* work-group per tile of free nodes staged in LDS (Form A only; at
-                            most 16 neighbour entries per node on average over a tile, and
-                            its halo and rows must fit in LDS), else the node kernel */
+                            most 16 neighbour entries and 16 incidences per node on average
+                            over a tile, at most 8 distinct outside neighbours per tile node,
+                            and its halo and rows must fit in LDS), else the node kernel */
 } sl_kernel;
 
 typedef struct {
@@ -156,8 +157,10 @@ SL_API sl_status smooth_mesh(double* coords, int32_t n_nodes, const int32_t* nbr
  * arrays, tris, boundary, opts->flags_out) is device memory on the current
  * HIP device, and all work is queued on `stream` (a hipStream_t; NULL = the
  * null stream).  The input arrays are only read; coords is overwritten with
- * the result.  The call returns after the work on `stream` has completed
- * (the sweep count and the validation result are needed on the host).
+ * the result, and must be 16-byte aligned (SL_EINVAL otherwise: the (x, y)
+ * pairs are moved as 16-byte units).  The call returns after the work on
+ * `stream` has completed (the sweep count and the validation result are
+ * needed on the host).
  */
 SL_API sl_status smooth_mesh_device(double* coords, int32_t n_nodes, const int32_t* nbr_ptr, const int32_t* nbr_idx,
                              const int32_t* tri_ptr, const int32_t* tri_idx, const int32_t* tris, int32_t n_tris,

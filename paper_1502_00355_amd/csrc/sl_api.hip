@@ -97,6 +97,8 @@ sl_status check_options(const sl_options& o)
 sl_status prepare_mesh(const MeshInput& in, const sl_options& o, int32_t mesh_index, DevMesh& m, hipStream_t st)
 {
     if (!in.coords || !in.nbr_ptr || !in.tri_ptr || !in.boundary) return fail(SL_EINVAL, "null array argument");
+    // coordinates are read and written as (x, y) pairs of 16 bytes
+    if (reinterpret_cast<uintptr_t>(in.coords) % 16 != 0) return fail(SL_EINVAL, "coords must be 16-byte aligned");
     if (in.n <= 0) return fail(SL_EINVAL, "n_nodes must be >= 1");
     if (in.n_tris < 0) return fail(SL_EINVAL, "n_tris must be >= 0");
     if (in.n_tris > 0 && !in.tris) return fail(SL_EINVAL, "null tris with n_tris > 0");

@@ -171,7 +171,7 @@ __global__ __launch_bounds__(kBS) void k_validate_tris(const int32_t* __restrict
     if (e) atomicOr(&vs->err, e);
 }
 
-__global__ __launch_bounds__(kBS) void k_validate_nodes(ValArgs a, ValStats* __restrict__ vs)
+__global__ __launch_bounds__(kBS) void k_validate_nodes(ValArgs a, ValStats* __restrict__ part)
 {
     const int32_t i = static_cast<int32_t>(blockIdx.x * kBS + threadIdx.x);
     uint32_t e = 0;
@@ -269,41 +269,103 @@ __global__ __launch_bounds__(kBS) void k_validate_nodes(ValArgs a, ValStats* __r
         int32_t C = 0, D = 0, I = 0;
         uint32_t E = 0;
         for (int q = 0; q < kBS / 64; ++q) { C += s_cnt[q]; D = max(D, s_deg[q]); I = max(I, s_inc[q]); E |= s_err[q]; }
-        if (C) atomicAdd(&vs->n_free, C);
-        if (D) atomicMax(&vs->max_deg_free, D);
-        if (I) atomicMax(&vs->max_inc_free, I);
-        if (E) atomicOr(&vs->err, E);
+        part[blockIdx.x] = ValStats{E, C, D, I};
+    }
+}
+
+// Folds the per-block statistics into *vs (whose error bits the triangle
+// check may already have set); one work-group, no atomics.
+__global__ __launch_bounds__(1024) void k_validate_fold(const ValStats* __restrict__ part, int32_t nb,
+                                                        ValStats* __restrict__ vs)
+{
+    __shared__ ValStats s_part[16];
+    uint32_t e = 0;
+    int32_t c = 0, d = 0, in = 0;
+    for (int32_t b = threadIdx.x; b < nb; b += 1024) {
+        const ValStats p = part[b];
+        e |= p.err;
+        c += p.n_free;
+        d = max(d, p.max_deg_free);
+        in = max(in, p.max_inc_free);
+    }
+    for (int off = 32; off > 0; off >>= 1) {
+        e |= __shfl_xor(e, off);
+        c += __shfl_xor(c, off);
+        d = max(d, __shfl_xor(d, off));
+        in = max(in, __shfl_xor(in, off));
+    }
+    if ((threadIdx.x & 63) == 0) s_part[threadIdx.x >> 6] = ValStats{e, c, d, in};
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int q = 1; q < 16; ++q) {
+            e |= s_part[q].err;
+            c += s_part[q].n_free;
+            d = max(d, s_part[q].max_deg_free);
+            in = max(in, s_part[q].max_inc_free);
+        }
+        vs->err |= e;
+        vs->n_free = c;
+        vs->max_deg_free = d;
+        vs->max_inc_free = in;
     }
 }
 
 // ------------------------------------------------------------- ordering ---
 
-__global__ __launch_bounds__(kBS) void k_bbox(const double* __restrict__ coords, int32_t n, uint64_t* __restrict__ bb)
+constexpr int kBboxBlocks = 1024;
+
+// Per-block bounding box of the coordinates, as order-preserving bit
+// patterns {min x, min y, max x, max y}; k_bbox_fold folds the blocks.
+__global__ __launch_bounds__(kBS) void k_bbox(const double* __restrict__ coords, int32_t n, uint64_t* __restrict__ part)
 {
     uint64_t mnx = ~0ull, mny = ~0ull, mxx = 0, mxy = 0;
+    const double2* c2 = reinterpret_cast<const double2*>(coords);
     for (int64_t i = static_cast<int64_t>(blockIdx.x) * kBS + threadIdx.x; i < n;
          i += static_cast<int64_t>(gridDim.x) * kBS) {
-        const uint64_t ox = ord_bits(coords[2 * i]), oy = ord_bits(coords[2 * i + 1]);
+        const double2 p = c2[i];
+        const uint64_t ox = ord_bits(p.x), oy = ord_bits(p.y);
         mnx = min(mnx, ox); mxx = max(mxx, ox);
         mny = min(mny, oy); mxy = max(mxy, oy);
     }
+    __shared__ uint64_t s_bb[kBS / 64][4];
     for (int off = 32; off > 0; off >>= 1) {
         mnx = min(mnx, static_cast<uint64_t>(__shfl_xor(static_cast<unsigned long long>(mnx), off)));
         mny = min(mny, static_cast<uint64_t>(__shfl_xor(static_cast<unsigned long long>(mny), off)));
         mxx = max(mxx, static_cast<uint64_t>(__shfl_xor(static_cast<unsigned long long>(mxx), off)));
         mxy = max(mxy, static_cast<uint64_t>(__shfl_xor(static_cast<unsigned long long>(mxy), off)));
     }
+    const int w = threadIdx.x >> 6;
     if ((threadIdx.x & 63) == 0) {
-        atomicMin(reinterpret_cast<unsigned long long*>(bb + 0), static_cast<unsigned long long>(mnx));
-        atomicMin(reinterpret_cast<unsigned long long*>(bb + 1), static_cast<unsigned long long>(mny));
-        atomicMax(reinterpret_cast<unsigned long long*>(bb + 2), static_cast<unsigned long long>(mxx));
-        atomicMax(reinterpret_cast<unsigned long long*>(bb + 3), static_cast<unsigned long long>(mxy));
+        s_bb[w][0] = mnx; s_bb[w][1] = mny; s_bb[w][2] = mxx; s_bb[w][3] = mxy;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int q = 1; q < kBS / 64; ++q) {
+            mnx = min(mnx, s_bb[q][0]); mny = min(mny, s_bb[q][1]);
+            mxx = max(mxx, s_bb[q][2]); mxy = max(mxy, s_bb[q][3]);
+        }
+        uint64_t* o = part + 4 * static_cast<int64_t>(blockIdx.x);
+        o[0] = mnx; o[1] = mny; o[2] = mxx; o[3] = mxy;
     }
 }
 
-__global__ void k_bbox_init(uint64_t* bb)
+__global__ __launch_bounds__(kBS) void k_bbox_fold(const uint64_t* __restrict__ part, int nb, uint64_t* __restrict__ bb)
 {
-    bb[0] = ~0ull; bb[1] = ~0ull; bb[2] = 0; bb[3] = 0;
+    uint64_t mnx = ~0ull, mny = ~0ull, mxx = 0, mxy = 0;
+    for (int b = threadIdx.x; b < nb; b += kBS) {
+        mnx = min(mnx, part[4 * b]); mny = min(mny, part[4 * b + 1]);
+        mxx = max(mxx, part[4 * b + 2]); mxy = max(mxy, part[4 * b + 3]);
+    }
+    __shared__ uint64_t s_bb[kBS][4];
+    s_bb[threadIdx.x][0] = mnx; s_bb[threadIdx.x][1] = mny; s_bb[threadIdx.x][2] = mxx; s_bb[threadIdx.x][3] = mxy;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int q = 1; q < kBS; ++q) {
+            mnx = min(mnx, s_bb[q][0]); mny = min(mny, s_bb[q][1]);
+            mxx = max(mxx, s_bb[q][2]); mxy = max(mxy, s_bb[q][3]);
+        }
+        bb[0] = mnx; bb[1] = mny; bb[2] = mxx; bb[3] = mxy;
+    }
 }
 
 // Hilbert index of cell (x, y) on a 2^bits x 2^bits grid.
@@ -553,6 +615,7 @@ size_t order_bytes(int64_t n)
 {
     const int64_t nbk = std::max<int64_t>(4 * 128, 2 * n);
     return 3 * Arena::piece(4 * static_cast<size_t>(n + 1)) + Arena::piece(4 * sizeof(uint64_t)) +
+           Arena::piece(4 * sizeof(uint64_t) * kBboxBlocks) +
            2 * Arena::piece(4 * static_cast<size_t>(nbk + 1)) + scan_bytes(std::max<int64_t>(n, nbk));
 }
 
@@ -573,13 +636,14 @@ sl_status make_order(const SetupArgs& a, const sl_options& o, const uint8_t* bnd
         const int nc = color ? n_colors : 1;
         const int bits = hilbert_bits(n_free, nc);
         const int64_t nbk = static_cast<int64_t>(nc) << (2 * bits);
-        uint64_t* bb = nullptr;
+        const int nbb = std::min(gb, kBboxBlocks);
+        uint64_t *bb = nullptr, *bbp = nullptr;
         int32_t *count = nullptr, *start = nullptr, *key = nullptr;
-        if ((r = scratch.take(&bb, 4)) || (r = scratch.take(&count, nbk)) || (r = scratch.take(&start, nbk + 1)) ||
-            (r = scratch.take(&key, n)))
+        if ((r = scratch.take(&bb, 4)) || (r = scratch.take(&bbp, 4 * static_cast<size_t>(nbb))) ||
+            (r = scratch.take(&count, nbk)) || (r = scratch.take(&start, nbk + 1)) || (r = scratch.take(&key, n)))
             return r;
-        k_bbox_init<<<1, 1, 0, st>>>(bb);
-        k_bbox<<<std::min(gb, 2048), kBS, 0, st>>>(a.coords, n, bb);
+        k_bbox<<<nbb, kBS, 0, st>>>(a.coords, n, bbp);
+        k_bbox_fold<<<1, kBS, 0, st>>>(bbp, nbb, bb);
         k_fill_i32<<<div_up(nbk, 256), 256, 0, st>>>(count, nbk, 0);
         k_bucket<<<gb, kBS, 0, st>>>(a.coords, bnd, color, n, bits, bb, key, count);
         if ((r = scan_exclusive(count, start, nbk, st, &scratch))) return r;
@@ -663,7 +727,9 @@ sl_status setup_mesh(const SetupArgs& a, const sl_options& o, DevMesh& m, int32_
     pb += want_tiles ? tile_bytes(n, a.nnz, a.ninc, T)
                      : Arena::piece(4 * static_cast<size_t>(a.nnz)) + Arena::piece(2 * static_cast<size_t>(a.ninc));
     const size_t rows_bytes = 2 * Arena::piece(4 * un) + scan_bytes(n);
-    const size_t sb = Arena::piece(sizeof(ValStats)) + Arena::piece(4 * un) + Arena::piece(4) +
+    const int gb = div_up(n, kBS);
+    const size_t sb = Arena::piece(sizeof(ValStats)) + Arena::piece(sizeof(ValStats) * static_cast<size_t>(gb)) +
+                      Arena::piece(4 * un) + Arena::piece(4) +
                       std::max({order_bytes(n), rows_bytes, tile_scratch_bytes()});
     if ((r = persist.reserve(pb, st))) return r;
     m.block = persist.base;
@@ -675,13 +741,14 @@ sl_status setup_mesh(const SetupArgs& a, const sl_options& o, DevMesh& m, int32_
     } give_back{scratch, st};
 
     // ---- validation
-    ValStats* vs = nullptr;
-    if ((r = scratch.take(&vs, 1))) return r;
+    ValStats *vs = nullptr, *vpart = nullptr;
+    if ((r = scratch.take(&vs, 1)) || (r = scratch.take(&vpart, gb))) return r;
     SL_HIP(hipMemsetAsync(vs, 0, sizeof(ValStats), st));
     ValArgs va{a.coords, n, a.nbr_ptr, a.nbr_idx, a.tri_ptr, a.tri_idx, a.tris, a.n_tris, a.boundary,
                a.nnz, a.ninc, o.form == SL_INPLACE_COLORED};
     if (a.n_tris > 0) k_validate_tris<<<div_up(a.n_tris, kBS), kBS, 0, st>>>(a.tris, a.n_tris, n, vs);
-    k_validate_nodes<<<div_up(n, kBS), kBS, 0, st>>>(va, vs);
+    k_validate_nodes<<<gb, kBS, 0, st>>>(va, vpart);
+    k_validate_fold<<<1, 1024, 0, st>>>(vpart, gb, vs);
     SL_HIP(hipGetLastError());
     ValStats h{};
     SL_HIP(hipMemcpyAsync(&h, vs, sizeof(ValStats), hipMemcpyDeviceToHost, st));
@@ -709,7 +776,6 @@ sl_status setup_mesh(const SetupArgs& a, const sl_options& o, DevMesh& m, int32_
     m.max_inc = h.max_inc_free;
 
     if ((r = persist.take(&m.perm, n)) || (r = persist.take(&m.new_of_old, n))) return r;
-    const int gb = div_up(n, kBS);
 
     // ---- colouring (coloured form)
     int32_t* color = nullptr;

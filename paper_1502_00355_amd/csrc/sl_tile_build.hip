@@ -3,9 +3,9 @@
 // The free nodes (device order: Hilbert cells) are cut into tiles of T
 // consecutive labels; the sweep runs one work-group per tile.  The tiles are
 // built on the device: one work-group per tile collects the halo (every
-// node an own node reads) and the incident triangles in LDS, sorts and
-// deduplicates them, and rewrites rows and triangles in tile-local indices
-// (own nodes 0..T-1, halo nodes T..T+H-1).
+// node an own node reads) in an LDS hash set, lists the incident triangles,
+// and rewrites rows and triangles in tile-local indices (own nodes 0..T-1,
+// halo nodes T..T+H-1).
 #include <algorithm>
 #include <climits>
 #include <cstdlib>
@@ -16,8 +16,9 @@ namespace sl {
 
 namespace {
 
-constexpr int kTileMaxDeg = 16;                       // neighbour entries per own node, on average over a tile
+constexpr int kTileMaxDeg = 16;   // row entries, and incidences, per own node on average over a tile
 constexpr int kBuildBS = 256;
+constexpr int kBuildU = 4;        // entries a work-item takes per chunk: their gathers are in flight together
 
 // ------------------------------------------------------ block primitives --
 
@@ -43,65 +44,37 @@ __device__ int block_excl_scan(int v, int* total, int* s_warp)
     return base + x - v;
 }
 
-__device__ __forceinline__ int pow2ceil(int n)
+// Open-addressing set of node labels in LDS (-1 = empty slot), linear
+// probing from the label's low bits: halo labels come in runs of nearby
+// labels, which then land in nearby slots with few collisions.  Probing
+// stops after HS slots, so a full table reports failure instead of looping.
+template <int HS>
+__device__ bool set_insert(int32_t* tab, int32_t key)
 {
-    int p = 1;
-    while (p < n) p <<= 1;
-    return p;
-}
-
-// Bitonic sort of a[0..n) (padded to P, a power of two, with INT_MAX).
-template <int BS>
-__device__ void block_sort(int32_t* a, int n, int P)
-{
-    for (int i = n + threadIdx.x; i < P; i += BS) a[i] = INT_MAX;
-    __syncthreads();
-    for (int k = 2; k <= P; k <<= 1) {
-        for (int j = k >> 1; j > 0; j >>= 1) {
-            for (int i = threadIdx.x; i < P; i += BS) {
-                const int l = i ^ j;
-                if (l > i) {
-                    const int32_t x = a[i], y = a[l];
-                    const bool up = (i & k) == 0;
-                    if ((x > y) == up) { a[i] = y; a[l] = x; }
-                }
-            }
-            __syncthreads();
+    int s = key & (HS - 1);
+    for (int p = 0; p < HS; ++p) {
+        const int32_t cur = tab[s];
+        if (cur == key) return true;
+        if (cur == -1) {
+            const int32_t prev = atomicCAS(&tab[s], -1, key);
+            if (prev == -1 || prev == key) return true;
         }
+        s = (s + 1) & (HS - 1);
     }
+    return false;
 }
 
-// In-place removal of duplicates from the sorted a[0..n); returns the count.
-template <int BS>
-__device__ int block_unique(int32_t* a, int n, int* s_warp)
+template <int HS>
+__device__ int set_find(const int32_t* tab, int32_t key)
 {
-    int out = 0;
-    for (int base = 0; base < n; base += BS) {
-        const int i = base + threadIdx.x;
-        int32_t v = 0;
-        int f = 0;
-        if (i < n) {
-            v = a[i];
-            f = (i == 0) || (v != a[i - 1]);
-        }
-        int tot;
-        const int pos = block_excl_scan<BS>(f, &tot, s_warp);
-        if (f) a[out + pos] = v;
-        out += tot;
-        __syncthreads();
+    int s = key & (HS - 1);
+    for (int p = 0; p < HS; ++p) {
+        const int32_t cur = tab[s];
+        if (cur == key) return s;
+        if (cur == -1) return -1;
+        s = (s + 1) & (HS - 1);
     }
-    return out;
-}
-
-__device__ __forceinline__ int lower_bound_lds(const int32_t* a, int n, int32_t v)
-{
-    int lo = 0, hi = n;
-    while (lo < hi) {
-        const int mid = (lo + hi) >> 1;
-        if (a[mid] < v) lo = mid + 1;
-        else hi = mid;
-    }
-    return lo;
+    return -1;
 }
 
 // ------------------------------------------------------------ tile build --
@@ -125,7 +98,6 @@ struct TileBuildArgs {
     uint32_t* row_rel;         // [n_tiles * T]
     uint64_t* tri_loc;         // [ninc_free]: tile k writes at fan_ptr[k0] (kept <= incidences)
     TileWork* work;            // [n_tiles]
-    int32_t* mx;               // {largest halo, largest padded row segment}
     int32_t* err;
 };
 
@@ -136,101 +108,176 @@ __host__ __device__ __forceinline__ int64_t row_seg_off(int32_t row_start, int32
 
 // One work-group per tile, in one pass: every output of tile k goes to a
 // place fixed by the row and incidence offsets of its first node, so no
-// tile needs another's counts.  Halo: every neighbour of an own node that
-// is not own, sorted and deduplicated.  Triangles: each triangle incident to
-// an own node, listed once per tile by its own vertex of smallest label.
-// Rows: the tile's neighbour rows in local indices, one segment padded to 4
-// entries.
+// tile needs another's counts.
+//   Halo: every neighbour of an own node that is not own, once, in the
+//   order of an LDS hash set (local index T + position).
+//   Rows: the tile's neighbour rows in local indices, one segment padded to
+//   4 entries.
+//   Triangles: each triangle incident to an own node, listed once per tile,
+//   by its own vertex of smallest label, in incidence order.
+// The tile's row entries and incidences are walked as flat ranges, a few
+// per work-item at a time, through an LDS map from entry to own node; so
+// the dependent gathers (entry -> neighbour or triangle -> device label) of
+// different entries overlap.  Neither the halo order nor the triangle order
+// changes a result: sums run over rows, minima are exact.
 template <int T>
 __global__ __launch_bounds__(kBuildBS) void k_tile_build(TileBuildArgs a)
 {
-    constexpr int BS = kBuildBS, CAP = T * kTileMaxDeg, NPT = T / BS;
-    __shared__ int32_t hb[CAP];
-    __shared__ int32_t s_cnt;
+    constexpr int BS = kBuildBS, U = kBuildU, CAP = T * kTileMaxDeg, HS = 8 * T, SPT = HS / BS;
+    __shared__ int32_t htab[HS];
+    __shared__ uint16_t hidx[HS];
+    __shared__ uint16_t own[CAP];
+    __shared__ int32_t s_nb[T], s_tb[T], s_rs[T + 1], s_fs[T + 1];
     __shared__ int32_t s_warp[BS / 64];
+    __shared__ int32_t s_full;
+    const int tid = threadIdx.x;
     const int tile = blockIdx.x;
     const int32_t k0 = tile * T;
     const int nown = min(T, a.n_free - k0);
-    const int32_t rb = a.row_ptr[k0];
-    const int32_t len = a.row_ptr[k0 + nown] - rb;
-    if (len > CAP) {   // more neighbour entries than the halo staging holds: the mesh takes the node path
-        if (threadIdx.x == 0) atomicOr(a.err, 2);
+    const int32_t rb = a.row_ptr[k0], fb = a.fan_ptr[k0];
+    const int32_t len = a.row_ptr[k0 + nown] - rb, flen = a.fan_ptr[k0 + nown] - fb;
+    if (len > CAP || flen > CAP) {   // denser than the LDS maps hold: the mesh takes the node path
+        if (tid == 0) atomicOr(a.err, 2);
         return;
     }
-    if (threadIdx.x == 0) s_cnt = 0;
-    __syncthreads();
-    for (int i = threadIdx.x; i < nown; i += BS) {
+    for (int s = tid; s < HS; s += BS) htab[s] = -1;
+    if (tid == 0) {
+        s_full = 0;
+        s_rs[nown] = len;
+        s_fs[nown] = flen;
+    }
+    for (int i = tid; i < nown; i += BS) {
         const int32_t o = a.perm[k0 + i];
-        for (int32_t q = a.nbr_ptr[o]; q < a.nbr_ptr[o + 1]; ++q) {
-            const int32_t jd = a.new_of_old[a.nbr_idx[q]];
-            if (jd < k0 || jd >= k0 + nown) hb[atomicAdd(&s_cnt, 1)] = jd;
-        }
+        s_nb[i] = a.nbr_ptr[o];
+        s_tb[i] = a.tri_ptr[o];
+        s_rs[i] = a.row_ptr[k0 + i] - rb;
+        s_fs[i] = a.fan_ptr[k0 + i] - fb;
     }
     __syncthreads();
-    const int nh0 = s_cnt;
-    block_sort<BS>(hb, nh0, pow2ceil(nh0));
-    const int H = block_unique<BS>(hb, nh0, s_warp);
+    for (int i = tid; i < nown; i += BS)
+        for (int j = s_rs[i]; j < s_rs[i + 1]; ++j) own[j] = static_cast<uint16_t>(i);
+    __syncthreads();
 
-    // triangles kept by this tile: the listing node is the smallest own vertex
-    auto kept = [&](int32_t o, int32_t kd, int64_t t) -> bool {
-        for (int s = 0; s < 3; ++s) {
-            const int32_t v = a.tris[3 * t + s];
-            if (v == o) continue;
-            const int32_t vd = a.new_of_old[v];
-            if (vd >= k0 && vd < k0 + nown && vd < kd) return false;
+    auto in_tile = [&](int32_t jd) { return jd >= k0 && jd < k0 + nown; };
+    auto row_label = [&](int j) -> int32_t {
+        const int i = own[j];
+        return a.new_of_old[a.nbr_idx[s_nb[i] + (j - s_rs[i])]];
+    };
+
+    // ---- halo set
+    bool full = false;
+    for (int base = 0; base < len; base += BS * U) {
+        int32_t jd[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int j = base + u * BS + tid;
+            jd[u] = j < len ? row_label(j) : k0;
         }
-        return true;
-    };
-    auto local = [&](int32_t jd) -> int {
-        if (jd >= k0 && jd < k0 + nown) return jd - k0;
-        const int h = lower_bound_lds(hb, H, jd);
-        if (h >= H || hb[h] != jd) { atomicOr(a.err, 1); return T; }
-        return T + h;
-    };
-    const int32_t len4 = (len + 3) & ~3;
-    int32_t* halo = a.halo + rb;
-    uint16_t* seg = a.nbr_loc + row_seg_off(rb, tile);
-    uint64_t* tri = a.tri_loc + a.fan_ptr[k0];
-    for (int h = threadIdx.x; h < H; h += BS) halo[h] = hb[h];
-    uint32_t* rr = a.row_rel + static_cast<int64_t>(tile) * T;
-    for (int i = threadIdx.x; i < T; i += BS)
-        rr[i] = static_cast<uint32_t>(a.row_ptr[k0 + min(i, nown)] - rb) |
-                (static_cast<uint32_t>(a.row_ptr[k0 + min(i + 1, nown)] - rb) << 16);
-    for (int j = len + threadIdx.x; j < len4; j += BS) seg[j] = 0;
-    for (int m = 0; m < NPT; ++m) {
-        const int i = m * BS + threadIdx.x;
-        if (i >= nown) continue;
-        const int32_t o = a.perm[k0 + i];
-        const int32_t b = a.nbr_ptr[o], d = a.nbr_ptr[o + 1] - b, out = a.row_ptr[k0 + i] - rb;
-        for (int j = 0; j < d; ++j) seg[out + j] = static_cast<uint16_t>(local(a.new_of_old[a.nbr_idx[b + j]]));
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+            if (!in_tile(jd[u]) && !set_insert<HS>(htab, jd[u])) full = true;
     }
-    // triangles are listed in node order (work-item t lists nodes NPT*t ..
-    // NPT*t+NPT-1), so that the lanes of a wave walking the list touch one
-    // compact patch of nodes in LDS
+    if (full) s_full = 1;
+    __syncthreads();
+    if (s_full) {   // more distinct halo nodes than the set holds: the node path
+        if (tid == 0) atomicOr(a.err, 2);
+        return;
+    }
     int c = 0;
-    for (int m = 0; m < NPT; ++m) {
-        const int i = NPT * threadIdx.x + m;
-        if (i < nown) {
-            const int32_t o = a.perm[k0 + i];
-            for (int32_t q = a.tri_ptr[o]; q < a.tri_ptr[o + 1]; ++q) c += kept(o, k0 + i, a.tri_idx[q]);
+#pragma unroll
+    for (int q = 0; q < SPT; ++q) c += htab[tid * SPT + q] != -1;
+    int H;
+    int h = block_excl_scan<BS>(c, &H, s_warp);
+    int32_t* halo = a.halo + rb;
+#pragma unroll
+    for (int q = 0; q < SPT; ++q) {
+        const int s = tid * SPT + q;
+        const int32_t key = htab[s];
+        if (key != -1) {
+            hidx[s] = static_cast<uint16_t>(h);
+            halo[h] = key;
+            ++h;
         }
     }
-    int R;
-    int tpos = block_excl_scan<BS>(c, &R, s_warp);
-    for (int m = 0; m < NPT; ++m) {
-        const int i = NPT * threadIdx.x + m;
-        if (i >= nown) continue;
-        const int32_t o = a.perm[k0 + i];
-        for (int32_t q = a.tri_ptr[o]; q < a.tri_ptr[o + 1]; ++q) {
-            const int64_t t = a.tri_idx[q];
-            if (!kept(o, k0 + i, t)) continue;
+    __syncthreads();
+    auto local = [&](int32_t jd) -> int {
+        if (in_tile(jd)) return jd - k0;
+        const int s = set_find<HS>(htab, jd);
+        if (s < 0) {
+            atomicOr(a.err, 1);
+            return T;
+        }
+        return T + hidx[s];
+    };
+
+    // ---- rows in local indices, and their offsets
+    const int32_t len4 = (len + 3) & ~3;
+    uint16_t* seg = a.nbr_loc + row_seg_off(rb, tile);
+    for (int base = 0; base < len; base += BS * U) {
+        int32_t jd[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int j = base + u * BS + tid;
+            jd[u] = j < len ? row_label(j) : k0;
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int j = base + u * BS + tid;
+            if (j < len) seg[j] = static_cast<uint16_t>(local(jd[u]));
+        }
+    }
+    for (int j = len + tid; j < len4; j += BS) seg[j] = 0;
+    uint32_t* rr = a.row_rel + static_cast<int64_t>(tile) * T;
+    for (int i = tid; i < T; i += BS)
+        rr[i] = static_cast<uint32_t>(s_rs[min(i, nown)]) | (static_cast<uint32_t>(s_rs[min(i + 1, nown)]) << 16);
+    __syncthreads();   // the entry map is rebuilt for the incidences
+    for (int i = tid; i < nown; i += BS)
+        for (int f = s_fs[i]; f < s_fs[i + 1]; ++f) own[f] = static_cast<uint16_t>(i);
+    __syncthreads();
+
+    // ---- triangles: work-item t takes incidences U*t .. U*t+U-1 of each
+    // chunk, so that a scan of the per-item counts keeps incidence order
+    uint64_t* tri = a.tri_loc + fb;
+    int R = 0;
+    for (int base = 0; base < flen; base += BS * U) {
+        int32_t v[U][3], kd[U];
+        bool keep[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int f = base + tid * U + u;
+            keep[u] = f < flen;
+            int64_t t = 0;
+            kd[u] = k0;
+            if (keep[u]) {
+                const int i = own[f];
+                kd[u] = k0 + i;
+                t = a.tri_idx[s_tb[i] + (f - s_fs[i])];
+            }
+#pragma unroll
+            for (int q = 0; q < 3; ++q) v[u][q] = keep[u] ? a.new_of_old[a.tris[3 * t + q]] : kd[u];
+        }
+        int cnt = 0;
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            // listed by this incidence iff no other own vertex has a smaller label
+#pragma unroll
+            for (int q = 0; q < 3; ++q)
+                if (v[u][q] != kd[u] && in_tile(v[u][q]) && v[u][q] < kd[u]) keep[u] = false;
+            cnt += keep[u];
+        }
+        int tot;
+        int pos = R + block_excl_scan<BS>(cnt, &tot, s_warp);
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            if (!keep[u]) continue;
             uint64_t w = 0;
-            for (int s = 0; s < 3; ++s)
-                w |= static_cast<uint64_t>(local(a.new_of_old[a.tris[3 * t + s]])) << (16 * s);
-            tri[tpos++] = w;
+#pragma unroll
+            for (int q = 0; q < 3; ++q) w |= static_cast<uint64_t>(local(v[u][q])) << (16 * q);
+            tri[pos++] = w;
         }
+        R += tot;
     }
-    if (threadIdx.x == 0) {
+    if (tid == 0) {
         TileWork w;
         w.X = a.X;
         w.halo = halo;
@@ -245,8 +292,35 @@ __global__ __launch_bounds__(kBuildBS) void k_tile_build(TileBuildArgs a)
         w.mesh = a.mesh;
         w.n = a.n;
         a.work[tile] = w;
-        atomicMax(a.mx, H);
-        atomicMax(a.mx + 1, len4);
+    }
+}
+
+// Largest halo and padded row segment over the tiles (one work-group).
+__global__ __launch_bounds__(1024) void k_tile_caps(const TileWork* __restrict__ work, int32_t nt,
+                                                    int32_t* __restrict__ mx)
+{
+    __shared__ int32_t s_h[16], s_r[16];
+    int32_t h = 0, r = 0;
+    for (int32_t t = threadIdx.x; t < nt; t += 1024) {
+        h = max(h, work[t].halo_cnt);
+        r = max(r, 4 * work[t].row_words);
+    }
+    for (int off = 32; off > 0; off >>= 1) {
+        h = max(h, __shfl_xor(h, off));
+        r = max(r, __shfl_xor(r, off));
+    }
+    if ((threadIdx.x & 63) == 0) {
+        s_h[threadIdx.x >> 6] = h;
+        s_r[threadIdx.x >> 6] = r;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int q = 1; q < 16; ++q) {
+            h = max(h, s_h[q]);
+            r = max(r, s_r[q]);
+        }
+        mx[0] = h;
+        mx[1] = r;
     }
 }
 
@@ -300,9 +374,9 @@ sl_status build_tiles(const SetupArgs& a, DevMesh& m, int tile_nodes, int mesh, 
     b.tri_loc = m.tri_loc;
     b.work = m.work;
     b.err = flags;
-    b.mx = flags + 1;
     if (T == 256) k_tile_build<256><<<nt, kBuildBS, 0, st>>>(b);
     else k_tile_build<512><<<nt, kBuildBS, 0, st>>>(b);
+    k_tile_caps<<<1, 1024, 0, st>>>(m.work, nt, flags + 1);
     SL_HIP(hipGetLastError());
     int32_t h[3] = {0, 0, 0};
     SL_HIP(hipMemcpyAsync(h, flags, 3 * sizeof(int32_t), hipMemcpyDeviceToHost, st));

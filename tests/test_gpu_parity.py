@@ -246,7 +246,10 @@ def test_tiles_too_dense_fall_back_to_the_node_kernel():
     m = _many_stars(600, 20, 5)            # 512 centres x 20 entries > 16 per node on average
     X, rep, ref, nd = assert_parity(m, 3)
     assert nd == 0 and rep.kernel_used == sl.KERNELS["node"]
-    m = _many_stars(600, 12, 5)           # 12 per node: tiles and their halos fit
+    m = _many_stars(600, 12, 5)           # 12 distinct outside neighbours per node > 8: node path
+    X, rep, ref, nd = assert_parity(m, 3)
+    assert nd == 0 and rep.kernel_used == sl.KERNELS["node"]
+    m = _many_stars(600, 7, 5)            # 7 per node: tiles and their halos fit
     X, rep, ref, nd = assert_parity(m, 3)
     assert nd == 0 and rep.kernel_used == sl.KERNELS["tile"]
 
@@ -358,6 +361,20 @@ def test_host_and_device_entry_points_agree():
     assert (Xh == Xd).all()
     assert (sl.unpack_flags(Fh, m.n_nodes) == Fd).all()
     assert rh.accepted_total == rd.accepted_total
+
+
+def test_device_entry_point_refuses_misaligned_coords():
+    import torch
+    m = meshgen.make_grid(12, "random", 0.4, 12)
+    dev = list(sl.to_device(m, "cuda:0"))
+    buf = torch.zeros(2 * m.n_nodes + 1, dtype=torch.float64, device="cuda:0")
+    X = buf[1:].view(m.n_nodes, 2)          # contiguous, 8 bytes past a 16-byte boundary
+    X.copy_(dev[0])
+    assert X.data_ptr() % 16 == 8
+    with pytest.raises(sl.SmartlapError) as e:
+        sl.smooth_mesh_device(X, *dev[1:], iterations=3)
+    assert "aligned" in str(e.value)
+    assert torch.equal(X.cpu(), dev[0].cpu())    # untouched
 
 
 def test_resume_and_repeat_are_bit_exact():
