@@ -41,6 +41,7 @@ struct Real<double> {
     using V2 = double2;
     static constexpr double k_two_sqrt3 = kTwoSqrt3;
     static constexpr double k_smallest = 0x1p-1074;            // smallest subnormal
+    static constexpr double k_step_min = 0x1p-1015;            // 128 x smallest normal
     __device__ static V2 make(double x, double y) { return make_double2(x, y); }
 };
 template <>
@@ -48,6 +49,7 @@ struct Real<float> {
     using V2 = float2;
     static constexpr float k_two_sqrt3 = 0x1.bb67aep+1f;   // 2*sqrt(3) rounded to float
     static constexpr float k_smallest = 0x1p-149f;          // smallest subnormal
+    static constexpr float k_step_min = 0x1p-119f;          // 128 x smallest normal
     __device__ static V2 make(float x, float y) { return make_float2(x, y); }
 };
 
@@ -70,6 +72,25 @@ template <typename R>
 __device__ __forceinline__ R finish_q(R cr, R S)
 {
     return (Real<R>::k_two_sqrt3 * cr) / fmax(S, Real<R>::k_smallest);
+}
+
+// a / d correctly rounded, for an integer count d in [1, 127] and y = 1/d
+// correctly rounded.  q = a*y is within one ulp of a/d, so the remainder
+// a - q*d is exact (a multiple of ulp(q) below 127 ulp(q)), and q + r*y
+// differs from a/d by less than ulp(q)*2^-p (p = 53 or 24).  While a/d is a
+// normal number it is never a rounding midpoint and lies at least ulp/254
+// from one, so that sum rounds to the correctly rounded a/d (Markstein's
+// correction step): three operations instead of a full division.  Quotients
+// that may be subnormal (and a = 0) take the division: there a/d can be a
+// midpoint exactly.
+template <typename R>
+__device__ __forceinline__ R div_by_count(R a, R d, R y)
+{
+    const R q = a * y;
+    const R r = fma(-q, d, a);
+    R res = fma(r, y, q);
+    if (!(fabs(a) >= Real<R>::k_step_min)) res = a / d;
+    return res;
 }
 
 struct TileSweepArgs {
@@ -274,7 +295,10 @@ __global__ __launch_bounds__(BS) void k_sweep_tile(TileSweepArgs a)
     uint64_t* rows64 = reinterpret_cast<uint64_t*>(rows);
     __shared__ double s_d2[BS / 64];
     __shared__ unsigned long long s_acc[BS / 64];
+    __shared__ R s_recip[kMaxValence + 1];
     const int tid = threadIdx.x;
+    // 1/d for every possible row length d, correctly rounded (read after the first barrier)
+    if (tid <= kMaxValence) s_recip[tid] = tid ? R(1) / static_cast<R>(tid) : R(0);
     const int lane = tid & 63, wv = tid >> 6;
     const int parity = a.parity;
 
@@ -335,8 +359,8 @@ __global__ __launch_bounds__(BS) void k_sweep_tile(TileSweepArgs a)
                         sx += p.x;
                         sy += p.y;
                     }
-                    const R dn = static_cast<R>(r1[m] - r0[m]);
-                    cand[i] = Real<R>::make(sx / dn, sy / dn);
+                    const R dn = static_cast<R>(r1[m] - r0[m]), y = s_recip[r1[m] - r0[m]];
+                    cand[i] = Real<R>::make(div_by_count(sx, dn, y), div_by_count(sy, dn, y));
                     qo[i] = static_cast<R>(__builtin_inf());
                     qn[i] = static_cast<R>(__builtin_inf());
                 }

@@ -306,11 +306,14 @@ def test_input_errors():
     assert rep.iterations_run == 2 and not (m.coords == before).all()
 
 
-@pytest.mark.parametrize("exp2", [-520, -40, 40, 498])
+@pytest.mark.parametrize("exp2", [-1040, -1020, -1016, -520, -40, 40, 498])
 def test_extreme_coordinate_scales(exp2):
     """The same mesh scaled by a power of two (exact): at 2^-520 squared
-    lengths are subnormal, near 2^498 they approach the largest doubles.  The
-    device follows the oracle at every scale (subnormals are kept by both)."""
+    lengths are subnormal, near 2^498 they approach the largest doubles.  At
+    2^-1016 the centroid sums stay above the bound of the kernel's
+    division-by-count step, at 2^-1020 they fall below it, and at 2^-1040 the
+    coordinates themselves are subnormal (every quality is 0).  The device
+    follows the oracle at every scale (subnormals are kept by both)."""
     m = meshgen.make_grid(45, "random", 0.4, 88)
     m.coords = m.coords * (2.0 ** exp2) + (2.0 ** exp2) * 0.25
     m.name = "grid45_scaled_2^%d" % exp2
@@ -533,6 +536,18 @@ def test_f32_full_1024_and_tolerance():
     tol = math.sqrt(ref.disp[moving[len(moving) // 2]]) * 1.0000001
     X, rep, ref2, nd = assert_parity(small, 300, tol=tol, precision="f32")
     assert nd == 0 and rep.iterations_run < 300
+
+
+@pytest.mark.parametrize("exp2", [-140, -122, -117, 60])
+def test_f32_extreme_coordinate_scales(exp2):
+    """Single precision at scales where float centroid sums fall below the
+    division-by-count step's bound (2^-122), stay above it (2^-117), or the
+    float coordinates are subnormal (2^-140)."""
+    m = meshgen.make_grid(45, "random", 0.4, 89)
+    m.coords = m.coords * (2.0 ** exp2) + (2.0 ** exp2) * 0.25
+    m.name = "grid45_f32_scaled_2^%d" % exp2
+    X, rep, ref, nd = assert_parity(m, 6, precision="f32")
+    assert nd == 0
 
 
 def test_f32_refused_outside_the_tile_path():
