@@ -295,6 +295,59 @@ __global__ __launch_bounds__(kBuildBS) void k_tile_build(TileBuildArgs a)
     }
 }
 
+// Groups each tile's triangle list by which of its vertices are own nodes
+// (all three first, then the patterns with two, then with one), keeping
+// incidence order inside a group.  The sweep evaluates a vertex's candidate
+// quality only for own vertices; with the list grouped, the lanes of a wave
+// mostly agree on which of the three evaluations to skip.  Lists longer than
+// the LDS staging keep their order (any order gives the same results).
+constexpr int kOrderWords = 4096;
+
+template <int T>
+__global__ __launch_bounds__(256) void k_tile_order(const TileWork* __restrict__ work)
+{
+    constexpr int BS = 256;
+    __shared__ uint64_t s_w[kOrderWords];
+    __shared__ int32_t s_warp[BS / 64];
+    const TileWork d = work[blockIdx.x];
+    const int R = d.tri_cnt;
+    if (R > kOrderWords || R == 0) return;
+    uint64_t* tris = const_cast<uint64_t*>(d.tris);
+    for (int j = threadIdx.x; j < R; j += BS) s_w[j] = tris[j];
+    __syncthreads();
+    // rank of each own-vertex pattern (bit r: vertex r is own) in the output
+    constexpr uint32_t kRank = (0u << 28) | (1u << 12) | (2u << 20) | (3u << 24) | (4u << 4) | (5u << 8) |
+                               (6u << 16) | (7u << 0);
+    auto rank = [&](uint64_t w) -> int {
+        const int p = (static_cast<int>(w & 0xFFFF) < T) | ((static_cast<int>((w >> 16) & 0xFFFF) < T) << 1) |
+                      ((static_cast<int>((w >> 32) & 0xFFFF) < T) << 2);
+        return static_cast<int>((kRank >> (4 * p)) & 7u);
+    };
+    // each work-item takes a contiguous segment; counts per rank packed two to an int
+    const int per = (R + BS - 1) / BS, b = min(R, static_cast<int>(threadIdx.x) * per), e = min(R, b + per);
+    int cnt[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    for (int j = b; j < e; ++j) ++cnt[rank(s_w[j])];
+    int pre[8], tot[8];
+    for (int k = 0; k < 4; ++k) {
+        int t;
+        const int x = block_excl_scan<BS>(cnt[2 * k] | (cnt[2 * k + 1] << 16), &t, s_warp);
+        pre[2 * k] = x & 0xFFFF;
+        pre[2 * k + 1] = x >> 16;
+        tot[2 * k] = t & 0xFFFF;
+        tot[2 * k + 1] = t >> 16;
+    }
+    int base = 0;
+    for (int k = 0; k < 8; ++k) {
+        const int c = tot[k];
+        pre[k] += base;
+        base += c;
+    }
+    for (int j = b; j < e; ++j) {
+        const uint64_t w = s_w[j];
+        tris[pre[rank(w)]++] = w;
+    }
+}
+
 // Largest halo and padded row segment over the tiles (one work-group).
 __global__ __launch_bounds__(1024) void k_tile_caps(const TileWork* __restrict__ work, int32_t nt,
                                                     int32_t* __restrict__ mx)
@@ -394,6 +447,9 @@ sl_status build_tiles(const SetupArgs& a, DevMesh& m, int tile_nodes, int mesh, 
         persist.rewind(pmark);
         return SL_OK;
     }
+    if (T == 256) k_tile_order<256><<<nt, 256, 0, st>>>(m.work);
+    else k_tile_order<512><<<nt, 256, 0, st>>>(m.work);
+    SL_HIP(hipGetLastError());
     m.halo_max = h[1];
     m.rows_max = h[2];
     m.n_tiles = nt;

@@ -112,7 +112,9 @@ __device__ __forceinline__ void tile_triangle(uint64_t w, const typename Real<R>
     const int l0 = static_cast<int>(w & 0xFFFF), l1 = static_cast<int>((w >> 16) & 0xFFFF),
               l2 = static_cast<int>((w >> 32) & 0xFFFF);
     // every read up front, so that one wait covers them all (a halo vertex
-    // reads some own candidate that it then ignores)
+    // reads some own candidate that it then ignores); a candidate quality is
+    // evaluated for own vertices only -- the tile's triangle list is grouped
+    // by which vertices are own, so a wave mostly takes one branch
     const V2 p0 = Xl[l0], p1 = Xl[l1], p2 = Xl[l2];
     const V2 c0 = cand[l0 & (T - 1)], c1 = cand[l1 & (T - 1)], c2 = cand[l2 & (T - 1)];
     const R ax = p1.x - p0.x, ay = p1.y - p0.y;
@@ -122,28 +124,21 @@ __device__ __forceinline__ void tile_triangle(uint64_t w, const typename Real<R>
     const R qold = finish_q(ax * by - bx * ay, (La + Lc) + Lb);
     // each own vertex at its candidate, the other two where they are; the
     // squared length of the opposite edge is shared with the old quality
-    R q0, q1, q2;
-    {
-        const R ax2 = p1.x - c0.x, ay2 = p1.y - c0.y, bx2 = p2.x - c0.x, by2 = p2.y - c0.y;
-        q0 = finish_q(ax2 * by2 - bx2 * ay2, ((ax2 * ax2 + ay2 * ay2) + Lc) + (bx2 * bx2 + by2 * by2));
-    }
-    {
-        const R ax2 = c1.x - p0.x, ay2 = c1.y - p0.y, cx2 = p2.x - c1.x, cy2 = p2.y - c1.y;
-        q1 = finish_q(ax2 * by - bx * ay2, ((ax2 * ax2 + ay2 * ay2) + (cx2 * cx2 + cy2 * cy2)) + Lb);
-    }
-    {
-        const R bx2 = c2.x - p0.x, by2 = c2.y - p0.y, cx2 = c2.x - p1.x, cy2 = c2.y - p1.y;
-        q2 = finish_q(ax * by2 - bx2 * ay, (La + (cx2 * cx2 + cy2 * cy2)) + (bx2 * bx2 + by2 * by2));
-    }
     if (l0 < T) {
+        const R ax2 = p1.x - c0.x, ay2 = p1.y - c0.y, bx2 = p2.x - c0.x, by2 = p2.y - c0.y;
+        const R q0 = finish_q(ax2 * by2 - bx2 * ay2, ((ax2 * ax2 + ay2 * ay2) + Lc) + (bx2 * bx2 + by2 * by2));
         lds_min(qo + l0, qold);
         lds_min(qn + l0, q0);
     }
     if (l1 < T) {
+        const R ax2 = c1.x - p0.x, ay2 = c1.y - p0.y, cx2 = p2.x - c1.x, cy2 = p2.y - c1.y;
+        const R q1 = finish_q(ax2 * by - bx * ay2, ((ax2 * ax2 + ay2 * ay2) + (cx2 * cx2 + cy2 * cy2)) + Lb);
         lds_min(qo + l1, qold);
         lds_min(qn + l1, q1);
     }
     if (l2 < T) {
+        const R bx2 = c2.x - p0.x, by2 = c2.y - p0.y, cx2 = c2.x - p1.x, cy2 = c2.y - p1.y;
+        const R q2 = finish_q(ax * by2 - bx2 * ay, (La + (cx2 * cx2 + cy2 * cy2)) + (bx2 * bx2 + by2 * by2));
         lds_min(qo + l2, qold);
         lds_min(qn + l2, q2);
     }
