@@ -75,22 +75,21 @@ __device__ __forceinline__ R finish_q(R cr, R S)
 }
 
 // a / d correctly rounded, for an integer count d in [1, 127] and y = 1/d
-// correctly rounded.  q = a*y is within one ulp of a/d, so the remainder
-// a - q*d is exact (a multiple of ulp(q) below 127 ulp(q)), and q + r*y
-// differs from a/d by less than ulp(q)*2^-p (p = 53 or 24).  While a/d is a
-// normal number it is never a rounding midpoint and lies at least ulp/254
-// from one, so that sum rounds to the correctly rounded a/d (Markstein's
-// correction step): three operations instead of a full division.  Quotients
-// that may be subnormal (and a = 0) take the division: there a/d can be a
-// midpoint exactly.
+// correctly rounded, while the quotient is a normal number: q = a*y is
+// within one ulp of a/d, so the remainder a - q*d is exact (a multiple of
+// ulp(q) below 127 ulp(q)), and q + r*y differs from a/d by less than
+// ulp(q)*2^-p (p = 53 or 24).  A normal quotient by an integer below 2^7 is
+// never a rounding midpoint and lies at least ulp/254 from one, so that sum
+// rounds to the correctly rounded a/d (Markstein's correction step): three
+// operations instead of a full division.  Below 128 x the smallest normal
+// number (zero included) the caller divides instead: a subnormal quotient
+// can be an exact midpoint.
 template <typename R>
-__device__ __forceinline__ R div_by_count(R a, R d, R y)
+__device__ __forceinline__ R div_step(R a, R d, R y)
 {
     const R q = a * y;
     const R r = fma(-q, d, a);
-    R res = fma(r, y, q);
-    if (!(fabs(a) >= Real<R>::k_step_min)) res = a / d;
-    return res;
+    return fma(r, y, q);
 }
 
 struct TileSweepArgs {
@@ -355,7 +354,17 @@ __global__ __launch_bounds__(BS) void k_sweep_tile(TileSweepArgs a)
                         sy += p.y;
                     }
                     const R dn = static_cast<R>(r1[m] - r0[m]), y = s_recip[r1[m] - r0[m]];
-                    cand[i] = Real<R>::make(div_by_count(sx, dn, y), div_by_count(sy, dn, y));
+                    R cx = div_step(sx, dn, y), cy = div_step(sy, dn, y);
+                    const bool tiny = !(fabs(sx) >= Real<R>::k_step_min) || !(fabs(sy) >= Real<R>::k_step_min);
+                    // a wave-uniform branch, so that the division is skipped, not
+                    // computed and discarded, when no lane needs it
+                    if (__builtin_amdgcn_ballot_w64(tiny) != 0ull) {
+                        if (tiny) {
+                            cx = sx / dn;
+                            cy = sy / dn;
+                        }
+                    }
+                    cand[i] = Real<R>::make(cx, cy);
                     qo[i] = static_cast<R>(__builtin_inf());
                     qn[i] = static_cast<R>(__builtin_inf());
                 }
