@@ -387,7 +387,7 @@ __device__ __forceinline__ uint32_t hilbert_index(int bits, uint32_t x, uint32_t
 __global__ __launch_bounds__(kBS) void k_bucket(const double* __restrict__ coords, const uint8_t* __restrict__ bnd,
                                                 const int32_t* __restrict__ color, int32_t n, int bits,
                                                 const uint64_t* __restrict__ bb, int32_t* __restrict__ key,
-                                                int32_t* __restrict__ count)
+                                                int32_t* __restrict__ count, int32_t* __restrict__ rank)
 {
     const int64_t i = static_cast<int64_t>(blockIdx.x) * kBS + threadIdx.x;
     if (i >= n || bnd[i]) return;
@@ -405,16 +405,18 @@ __global__ __launch_bounds__(kBS) void k_bucket(const double* __restrict__ coord
     }
     const int32_t k = (color ? color[i] : 0) * (1 << (2 * bits)) + static_cast<int32_t>(cell);
     key[i] = k;
-    atomicAdd(count + k, 1);
+    rank[i] = atomicAdd(count + k, 1);   // place inside the bucket (in no particular order)
 }
 
 __global__ __launch_bounds__(kBS) void k_bucket_scatter(const uint8_t* __restrict__ bnd, int32_t n,
-                                                        const int32_t* __restrict__ key, int32_t* __restrict__ cursor,
+                                                        const int32_t* __restrict__ key,
+                                                        const int32_t* __restrict__ rank,
+                                                        const int32_t* __restrict__ start,
                                                         int32_t* __restrict__ new_of_old, int32_t* __restrict__ perm)
 {
     const int64_t i = static_cast<int64_t>(blockIdx.x) * kBS + threadIdx.x;
     if (i >= n || bnd[i]) return;
-    const int32_t pos = atomicAdd(cursor + key[i], 1);
+    const int32_t pos = start[key[i]] + rank[i];
     new_of_old[i] = pos;
     perm[pos] = static_cast<int32_t>(i);
 }
@@ -645,7 +647,7 @@ sl_status make_order(const SetupArgs& a, const sl_options& o, const uint8_t* bnd
         k_bbox<<<nbb, kBS, 0, st>>>(a.coords, n, bbp);
         k_bbox_fold<<<1, kBS, 0, st>>>(bbp, nbb, bb);
         k_fill_i32<<<div_up(nbk, 256), 256, 0, st>>>(count, nbk, 0);
-        k_bucket<<<gb, kBS, 0, st>>>(a.coords, bnd, color, n, bits, bb, key, count);
+        k_bucket<<<gb, kBS, 0, st>>>(a.coords, bnd, color, n, bits, bb, key, count, flag);
         if ((r = scan_exclusive(count, start, nbk, st, &scratch))) return r;
         if (color) {
             std::vector<int32_t> h(static_cast<size_t>(nc) + 1);
@@ -658,7 +660,7 @@ sl_status make_order(const SetupArgs& a, const sl_options& o, const uint8_t* bnd
         } else {
             cs[1] = n_free;
         }
-        k_bucket_scatter<<<gb, kBS, 0, st>>>(bnd, n, key, start, m.new_of_old, m.perm);
+        k_bucket_scatter<<<gb, kBS, 0, st>>>(bnd, n, key, flag, start, m.new_of_old, m.perm);
     } else if (n_free > 0) {
         // stable: free nodes (by colour class when coloured) in caller order
         const int nc = color ? n_colors : 1;

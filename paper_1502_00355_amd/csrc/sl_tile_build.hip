@@ -164,7 +164,10 @@ __global__ __launch_bounds__(kBuildBS) void k_tile_build(TileBuildArgs a)
         return a.new_of_old[a.nbr_idx[s_nb[i] + (j - s_rs[i])]];
     };
 
-    // ---- halo set
+    // ---- halo set; the row entries' device labels are parked in the halo
+    // output (tile k's halo goes to row_ptr[k0], which has room for len
+    // entries) until the rows are rewritten below
+    int32_t* halo = a.halo + rb;
     bool full = false;
     for (int base = 0; base < len; base += BS * U) {
         int32_t jd[U];
@@ -174,8 +177,11 @@ __global__ __launch_bounds__(kBuildBS) void k_tile_build(TileBuildArgs a)
             jd[u] = j < len ? row_label(j) : k0;
         }
 #pragma unroll
-        for (int u = 0; u < U; ++u)
+        for (int u = 0; u < U; ++u) {
+            const int j = base + u * BS + tid;
+            if (j < len) halo[j] = jd[u];
             if (!in_tile(jd[u]) && !set_insert<HS>(htab, jd[u])) full = true;
+        }
     }
     if (full) s_full = 1;
     __syncthreads();
@@ -187,16 +193,13 @@ __global__ __launch_bounds__(kBuildBS) void k_tile_build(TileBuildArgs a)
 #pragma unroll
     for (int q = 0; q < SPT; ++q) c += htab[tid * SPT + q] != -1;
     int H;
-    int h = block_excl_scan<BS>(c, &H, s_warp);
-    int32_t* halo = a.halo + rb;
+    const int h0 = block_excl_scan<BS>(c, &H, s_warp);
+    {
+        int h = h0;
 #pragma unroll
-    for (int q = 0; q < SPT; ++q) {
-        const int s = tid * SPT + q;
-        const int32_t key = htab[s];
-        if (key != -1) {
-            hidx[s] = static_cast<uint16_t>(h);
-            halo[h] = key;
-            ++h;
+        for (int q = 0; q < SPT; ++q) {
+            const int s = tid * SPT + q;
+            if (htab[s] != -1) hidx[s] = static_cast<uint16_t>(h++);
         }
     }
     __syncthreads();
@@ -213,20 +216,17 @@ __global__ __launch_bounds__(kBuildBS) void k_tile_build(TileBuildArgs a)
     // ---- rows in local indices, and their offsets
     const int32_t len4 = (len + 3) & ~3;
     uint16_t* seg = a.nbr_loc + row_seg_off(rb, tile);
-    for (int base = 0; base < len; base += BS * U) {
-        int32_t jd[U];
+    for (int j = tid; j < len; j += BS) seg[j] = static_cast<uint16_t>(local(halo[j]));
+    for (int j = len + tid; j < len4; j += BS) seg[j] = 0;
+    __syncthreads();   // every parked label is read: the halo list takes their place
+    {
+        int h = h0;
 #pragma unroll
-        for (int u = 0; u < U; ++u) {
-            const int j = base + u * BS + tid;
-            jd[u] = j < len ? row_label(j) : k0;
-        }
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-            const int j = base + u * BS + tid;
-            if (j < len) seg[j] = static_cast<uint16_t>(local(jd[u]));
+        for (int q = 0; q < SPT; ++q) {
+            const int32_t key = htab[tid * SPT + q];
+            if (key != -1) halo[h++] = key;
         }
     }
-    for (int j = len + tid; j < len4; j += BS) seg[j] = 0;
     uint32_t* rr = a.row_rel + static_cast<int64_t>(tile) * T;
     for (int i = tid; i < T; i += BS)
         rr[i] = static_cast<uint32_t>(s_rs[min(i, nown)]) | (static_cast<uint32_t>(s_rs[min(i + 1, nown)]) << 16);
