@@ -171,10 +171,7 @@ struct DevMesh {
     int32_t halo_max = 0;                // largest halo over tiles
     int32_t rows_max = 0;                // largest row segment (u16 entries, padded to 4) over tiles
     TileWork* work = nullptr;            // [n_tiles]
-    int32_t* halo = nullptr;             // halo lists of all tiles
-    uint16_t* nbr_loc = nullptr;         // row segments of all tiles
-    uint32_t* row_rel = nullptr;         // [n_tiles * tile_nodes]
-    uint64_t* tri_loc = nullptr;         // triangle entries of all tiles
+    unsigned char* tile_data = nullptr;  // one contiguous record per tile: row offsets, halo, rows, triangles
 };
 
 // Frees every device array of m (stream-ordered).

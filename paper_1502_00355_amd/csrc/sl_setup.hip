@@ -703,10 +703,7 @@ void devmesh_free(DevMesh& m, hipStream_t st)
     m.fan = nullptr;
     m.X[0] = m.X[1] = nullptr;
     m.work = nullptr;
-    m.halo = nullptr;
-    m.nbr_loc = nullptr;
-    m.row_rel = nullptr;
-    m.tri_loc = nullptr;
+    m.tile_data = nullptr;
 }
 
 sl_status setup_mesh(const SetupArgs& a, const sl_options& o, DevMesh& m, int32_t mesh, hipStream_t st)

@@ -93,17 +93,24 @@ struct TileBuildArgs {
     int32_t mesh;              // MeshState index written into the descriptors
     int64_t n;
     const void* X;
-    int32_t* halo;             // [nnz_free]: tile k writes at row_ptr[k0] (halo <= row entries)
-    uint16_t* nbr_loc;         // tile k writes at align4(row_ptr[k0]) + 8k (segments never overlap)
-    uint32_t* row_rel;         // [n_tiles * T]
-    uint64_t* tri_loc;         // [ninc_free]: tile k writes at fan_ptr[k0] (kept <= incidences)
+    unsigned char* data;       // tile k's record at tile_record(k): row offsets, halo, rows, triangles
     TileWork* work;            // [n_tiles]
     int32_t* err;
 };
 
-__host__ __device__ __forceinline__ int64_t row_seg_off(int32_t row_start, int32_t tile)
+__host__ __device__ __forceinline__ int64_t align16(int64_t b) { return (b + 15) & ~int64_t(15); }
+
+// Byte offset of tile k's record, from the row and incidence offsets of its
+// first node.  A record holds T u32 row offsets, then room for len halo ids
+// (len = the tile's row entries; the halo is never longer), the rows (len
+// rounded up to 4 u16), and flen triangle words (flen = its incidences, an
+// upper bound of its triangles), each part 16-byte aligned: at most
+// 4T + 6 len + 8 flen + 36 bytes, which the next record's offset leaves.
+// One record per tile keeps the static data a tile reads in one stream.
+__host__ __device__ __forceinline__ int64_t tile_record(int32_t row_start, int32_t fan_start, int32_t tile, int T)
 {
-    return ((static_cast<int64_t>(row_start) + 3) & ~int64_t(3)) + 8 * static_cast<int64_t>(tile);
+    return static_cast<int64_t>(tile) * (4 * T + 64) +
+           align16(6 * static_cast<int64_t>(row_start) + 8 * static_cast<int64_t>(fan_start));
 }
 
 // One work-group per tile, in one pass: every output of tile k goes to a
@@ -165,9 +172,11 @@ __global__ __launch_bounds__(kBuildBS) void k_tile_build(TileBuildArgs a)
     };
 
     // ---- halo set; the row entries' device labels are parked in the halo
-    // output (tile k's halo goes to row_ptr[k0], which has room for len
-    // entries) until the rows are rewritten below
-    int32_t* halo = a.halo + rb;
+    // part of the record (room for len entries) until the rows are
+    // rewritten below
+    unsigned char* rec = a.data + tile_record(rb, fb, tile, T);
+    uint32_t* rr = reinterpret_cast<uint32_t*>(rec);
+    int32_t* halo = reinterpret_cast<int32_t*>(rec + 4 * T);
     bool full = false;
     for (int base = 0; base < len; base += BS * U) {
         int32_t jd[U];
@@ -215,7 +224,8 @@ __global__ __launch_bounds__(kBuildBS) void k_tile_build(TileBuildArgs a)
 
     // ---- rows in local indices, and their offsets
     const int32_t len4 = (len + 3) & ~3;
-    uint16_t* seg = a.nbr_loc + row_seg_off(rb, tile);
+    const int64_t seg_at = align16(4 * static_cast<int64_t>(T) + 4 * static_cast<int64_t>(len));
+    uint16_t* seg = reinterpret_cast<uint16_t*>(rec + seg_at);
     for (int j = tid; j < len; j += BS) seg[j] = static_cast<uint16_t>(local(halo[j]));
     for (int j = len + tid; j < len4; j += BS) seg[j] = 0;
     __syncthreads();   // every parked label is read: the halo list takes their place
@@ -227,7 +237,6 @@ __global__ __launch_bounds__(kBuildBS) void k_tile_build(TileBuildArgs a)
             if (key != -1) halo[h++] = key;
         }
     }
-    uint32_t* rr = a.row_rel + static_cast<int64_t>(tile) * T;
     for (int i = tid; i < T; i += BS)
         rr[i] = static_cast<uint32_t>(s_rs[min(i, nown)]) | (static_cast<uint32_t>(s_rs[min(i + 1, nown)]) << 16);
     __syncthreads();   // the entry map is rebuilt for the incidences
@@ -237,7 +246,7 @@ __global__ __launch_bounds__(kBuildBS) void k_tile_build(TileBuildArgs a)
 
     // ---- triangles: work-item t takes incidences U*t .. U*t+U-1 of each
     // chunk, so that a scan of the per-item counts keeps incidence order
-    uint64_t* tri = a.tri_loc + fb;
+    uint64_t* tri = reinterpret_cast<uint64_t*>(rec + align16(seg_at + 2 * static_cast<int64_t>(len4)));
     int R = 0;
     for (int base = 0; base < flen; base += BS * U) {
         int32_t v[U][3], kd[U];
@@ -384,8 +393,7 @@ size_t tile_bytes(int64_t n, int64_t nnz, int64_t ninc, int tile_nodes)
     if (tile_nodes != 256 && tile_nodes != 512) return 0;   // build_tiles takes nothing then
     const size_t nt = static_cast<size_t>(div_up(std::max<int64_t>(n, 1), tile_nodes));
     const size_t z = static_cast<size_t>(std::max<int64_t>(nnz, 1)), c = static_cast<size_t>(std::max<int64_t>(ninc, 1));
-    return Arena::piece(sizeof(TileWork) * nt) + Arena::piece(4 * z) + Arena::piece(2 * (z + 8 * nt + 8)) +
-           Arena::piece(4 * nt * tile_nodes) + Arena::piece(8 * c);
+    return Arena::piece(sizeof(TileWork) * nt) + Arena::piece(nt * (4 * tile_nodes + 64) + 6 * z + 8 * c + 16);
 }
 
 size_t tile_scratch_bytes() { return Arena::piece(3 * sizeof(int32_t)); }
@@ -402,11 +410,9 @@ sl_status build_tiles(const SetupArgs& a, DevMesh& m, int tile_nodes, int mesh, 
     int32_t* flags = nullptr;   // {err, largest halo, largest row segment}
     if ((r = scratch.take(&flags, 3))) return r;
     SL_HIP(hipMemsetAsync(flags, 0, 3 * sizeof(int32_t), st));
-    if ((r = persist.take(&m.work, nt)) || (r = persist.take(&m.halo, std::max<int64_t>(m.nnz_free, 1))) ||
-        (r = persist.take(&m.nbr_loc, static_cast<size_t>(m.nnz_free) + 8 * static_cast<size_t>(nt) + 8)) ||
-        (r = persist.take(&m.row_rel, static_cast<size_t>(nt) * T)) ||
-        (r = persist.take(&m.tri_loc, std::max<int64_t>(m.ninc_free, 1))))
-        return r;
+    const size_t data_bytes = static_cast<size_t>(tile_record(static_cast<int32_t>(m.nnz_free),
+                                                              static_cast<int32_t>(m.ninc_free), nt, T));
+    if ((r = persist.take(&m.work, nt)) || (r = persist.take(&m.tile_data, data_bytes))) return r;
     TileBuildArgs b{};
     b.perm = m.perm;
     b.new_of_old = m.new_of_old;
@@ -421,10 +427,7 @@ sl_status build_tiles(const SetupArgs& a, DevMesh& m, int tile_nodes, int mesh, 
     b.mesh = mesh;
     b.n = m.n;
     b.X = m.X[0];
-    b.halo = m.halo;
-    b.nbr_loc = m.nbr_loc;
-    b.row_rel = m.row_rel;
-    b.tri_loc = m.tri_loc;
+    b.data = m.tile_data;
     b.work = m.work;
     b.err = flags;
     if (T == 256) k_tile_build<256><<<nt, kBuildBS, 0, st>>>(b);
@@ -440,10 +443,7 @@ sl_status build_tiles(const SetupArgs& a, DevMesh& m, int tile_nodes, int mesh, 
     // for LDS: the node path, whose arrays reuse the tile arrays' room
     if ((h[0] & 2) || tile_lds_bytes(T, h[1], h[2], m.precision) > kTileLdsLimit) {
         m.work = nullptr;
-        m.halo = nullptr;
-        m.nbr_loc = nullptr;
-        m.row_rel = nullptr;
-        m.tri_loc = nullptr;
+        m.tile_data = nullptr;
         persist.rewind(pmark);
         return SL_OK;
     }
