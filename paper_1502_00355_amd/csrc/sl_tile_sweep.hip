@@ -225,6 +225,10 @@ __device__ __forceinline__ gptr<R> xin(const TileWork& d, int parity)
     return to_global(static_cast<const R*>(d.X)) + parity * 2 * d.n;
 }
 
+// The prefetch loads are unconditional, with indices clamped into the tile
+// (a lane past the end re-loads the last element and its value is not
+// used): straight-line loads let the compiler wait for exactly the ones the
+// next step needs, where loads under per-lane branches made it wait for all.
 template <int T, int BS, bool SOA, typename R, int NPT, int RPRE, int KPRE>
 __device__ __forceinline__ void stage_a(TileStage<R, NPT, RPRE, KPRE>& s, const TileWork& d, int parity)
 {
@@ -232,12 +236,12 @@ __device__ __forceinline__ void stage_a(TileStage<R, NPT, RPRE, KPRE>& s, const 
     const gptr<R> Xin = xin<R>(d, parity);
     const gptr<int32_t> halo = to_global(d.halo);
     const gptr<uint32_t> rr = to_global(d.rr);
-    s.hidx = tid < d.halo_cnt ? halo[tid] : -1;
+    s.hidx = halo[min(tid, max(d.halo_cnt - 1, 0))];   // meaningful for tid < halo_cnt only
 #pragma unroll
     for (int m = 0; m < NPT; ++m) {
         const int i = m * BS + tid;
         s.rr[m] = rr[i];
-        s.own[m] = i < d.nown ? ldxg<SOA>(Xin, d.n, d.own_start + i) : Real<R>::make(R(0), R(0));
+        s.own[m] = ldxg<SOA>(Xin, d.n, d.own_start + min(i, d.nown - 1));
     }
 }
 
@@ -248,17 +252,11 @@ __device__ __forceinline__ void stage_b(TileStage<R, NPT, RPRE, KPRE>& s, const 
     const gptr<R> Xin = xin<R>(d, parity);
     const gptr<uint64_t> rows = to_global(d.rows);
     const gptr<uint64_t> tris = to_global(d.tris);
-    s.hx = s.hidx >= 0 ? ldxg<SOA>(Xin, d.n, s.hidx) : Real<R>::make(R(0), R(0));
+    s.hx = ldxg<SOA>(Xin, d.n, tid < d.halo_cnt ? s.hidx : d.own_start);
 #pragma unroll
-    for (int q = 0; q < RPRE; ++q) {
-        const int j = q * BS + tid;
-        s.rw[q] = j < d.row_words ? rows[j] : 0ull;
-    }
+    for (int q = 0; q < RPRE; ++q) s.rw[q] = rows[min(q * BS + tid, d.row_words - 1)];
 #pragma unroll
-    for (int q = 0; q < KPRE; ++q) {
-        const int r = q * BS + tid;
-        s.tw[q] = r < d.tri_cnt ? tris[r] : 0ull;
-    }
+    for (int q = 0; q < KPRE; ++q) s.tw[q] = tris[min(q * BS + tid, max(d.tri_cnt - 1, 0))];
 }
 
 // Persistent work-groups: the work list is cut into 8 contiguous ranges, one
@@ -324,7 +322,7 @@ __global__ __launch_bounds__(BS) void k_sweep_tile(TileSweepArgs a)
             if (q * BS + tid < dcur.row_words) rows64[q * BS + tid] = sg.rw[q];
 #pragma unroll
         for (int q = 0; q < KPRE; ++q) tw[q] = sg.tw[q];
-        if (sg.hidx >= 0) Xl[T + tid] = sg.hx;
+        if (tid < dcur.halo_cnt) Xl[T + tid] = sg.hx;
         {
             // rare overflow beyond what the registers hold
             const gptr<R> Xin = xin<R>(dcur, parity);
