@@ -84,7 +84,7 @@ typedef enum {
     SL_KERNEL_NODE = 1,  /* one work-item per free node, neighbours gathered from HBM/L2 */
     SL_KERNEL_TILE = 2   /* work-group per tile of free nodes staged in LDS (Form A only; at
                             most 16 neighbour entries and 16 incidences per node on average
-                            over a tile, at most 8 distinct outside neighbours per tile node,
+                            over a tile, at most 4 distinct outside neighbours per tile node,
                             and its halo and rows must fit in LDS), else the node kernel */
 } sl_kernel;
 

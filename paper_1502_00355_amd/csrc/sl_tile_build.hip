@@ -123,17 +123,19 @@ __host__ __device__ __forceinline__ int64_t tile_record(int32_t row_start, int32
 //   Triangles: each triangle incident to an own node, listed once per tile,
 //   by its own vertex of smallest label, in incidence order.
 // The tile's row entries and incidences are walked as flat ranges, a few
-// per work-item at a time, through an LDS map from entry to own node; so
-// the dependent gathers (entry -> neighbour or triangle -> device label) of
-// different entries overlap.  Neither the halo order nor the triangle order
+// per work-item at a time, so the dependent gathers (entry -> neighbour or
+// triangle -> device label) of different entries overlap.  An entry's own
+// node is found from the owner of its 16-entry block, stepping forward over
+// the node offsets (a node has at least one row entry); the small LDS
+// footprint lets more tiles build at once.  Neither the halo order nor the triangle order
 // changes a result: sums run over rows, minima are exact.
 template <int T>
 __global__ __launch_bounds__(kBuildBS) void k_tile_build(TileBuildArgs a)
 {
-    constexpr int BS = kBuildBS, U = kBuildU, CAP = T * kTileMaxDeg, HS = 8 * T, SPT = HS / BS;
+    constexpr int BS = kBuildBS, U = kBuildU, CAP = T * kTileMaxDeg, HS = 4 * T, SPT = HS / BS;
     __shared__ int32_t htab[HS];
     __shared__ uint16_t hidx[HS];
-    __shared__ uint16_t own[CAP];
+    __shared__ uint16_t own[CAP / 16];   // owner of entries 16b, 16b+1, ... starts the search
     __shared__ int32_t s_nb[T], s_tb[T], s_rs[T + 1], s_fs[T + 1];
     __shared__ int32_t s_warp[BS / 64];
     __shared__ int32_t s_full;
@@ -162,12 +164,13 @@ __global__ __launch_bounds__(kBuildBS) void k_tile_build(TileBuildArgs a)
     }
     __syncthreads();
     for (int i = tid; i < nown; i += BS)
-        for (int j = s_rs[i]; j < s_rs[i + 1]; ++j) own[j] = static_cast<uint16_t>(i);
+        for (int b = (s_rs[i] + 15) >> 4; (b << 4) < s_rs[i + 1]; ++b) own[b] = static_cast<uint16_t>(i);
     __syncthreads();
 
     auto in_tile = [&](int32_t jd) { return jd >= k0 && jd < k0 + nown; };
     auto row_label = [&](int j) -> int32_t {
-        const int i = own[j];
+        int i = own[j >> 4];
+        while (s_rs[i + 1] <= j) ++i;
         return a.new_of_old[a.nbr_idx[s_nb[i] + (j - s_rs[i])]];
     };
 
@@ -241,7 +244,7 @@ __global__ __launch_bounds__(kBuildBS) void k_tile_build(TileBuildArgs a)
         rr[i] = static_cast<uint32_t>(s_rs[min(i, nown)]) | (static_cast<uint32_t>(s_rs[min(i + 1, nown)]) << 16);
     __syncthreads();   // the entry map is rebuilt for the incidences
     for (int i = tid; i < nown; i += BS)
-        for (int f = s_fs[i]; f < s_fs[i + 1]; ++f) own[f] = static_cast<uint16_t>(i);
+        for (int b = (s_fs[i] + 15) >> 4; (b << 4) < s_fs[i + 1]; ++b) own[b] = static_cast<uint16_t>(i);
     __syncthreads();
 
     // ---- triangles: work-item t takes incidences U*t .. U*t+U-1 of each
@@ -258,7 +261,8 @@ __global__ __launch_bounds__(kBuildBS) void k_tile_build(TileBuildArgs a)
             int64_t t = 0;
             kd[u] = k0;
             if (keep[u]) {
-                const int i = own[f];
+                int i = own[f >> 4];
+                while (s_fs[i + 1] <= f) ++i;
                 kd[u] = k0 + i;
                 t = a.tri_idx[s_tb[i] + (f - s_fs[i])];
             }

@@ -246,10 +246,10 @@ def test_tiles_too_dense_fall_back_to_the_node_kernel():
     m = _many_stars(600, 20, 5)            # 512 centres x 20 entries > 16 per node on average
     X, rep, ref, nd = assert_parity(m, 3)
     assert nd == 0 and rep.kernel_used == sl.KERNELS["node"]
-    m = _many_stars(600, 12, 5)           # 12 distinct outside neighbours per node > 8: node path
+    m = _many_stars(600, 7, 5)            # 7 distinct outside neighbours per node > 4: node path
     X, rep, ref, nd = assert_parity(m, 3)
     assert nd == 0 and rep.kernel_used == sl.KERNELS["node"]
-    m = _many_stars(600, 7, 5)            # 7 per node: tiles and their halos fit
+    m = _many_stars(600, 3, 5)            # 3 per node: tiles and their halos fit
     X, rep, ref, nd = assert_parity(m, 3)
     assert nd == 0 and rep.kernel_used == sl.KERNELS["tile"]
 
