@@ -317,14 +317,15 @@ __global__ __launch_bounds__(kBuildBS) void k_tile_build(TileBuildArgs a)
 constexpr int kOrderWords = 4096;
 
 template <int T>
-__global__ __launch_bounds__(256) void k_tile_order(const TileWork* __restrict__ work)
+// LDS: room for `cap` triangle words (the longest list, at most kOrderWords).
+__global__ __launch_bounds__(256) void k_tile_order(const TileWork* __restrict__ work, int cap)
 {
     constexpr int BS = 256;
-    __shared__ uint64_t s_w[kOrderWords];
+    extern __shared__ uint64_t s_w[];
     __shared__ int32_t s_warp[BS / 64];
     const TileWork d = work[blockIdx.x];
     const int R = d.tri_cnt;
-    if (R > kOrderWords || R == 0) return;
+    if (R > cap || R == 0) return;
     uint64_t* tris = const_cast<uint64_t*>(d.tris);
     for (int j = threadIdx.x; j < R; j += BS) s_w[j] = tris[j];
     __syncthreads();
@@ -361,32 +362,38 @@ __global__ __launch_bounds__(256) void k_tile_order(const TileWork* __restrict__
     }
 }
 
-// Largest halo and padded row segment over the tiles (one work-group).
+// Largest halo, padded row segment and triangle list over the tiles (one
+// work-group).
 __global__ __launch_bounds__(1024) void k_tile_caps(const TileWork* __restrict__ work, int32_t nt,
                                                     int32_t* __restrict__ mx)
 {
-    __shared__ int32_t s_h[16], s_r[16];
-    int32_t h = 0, r = 0;
+    __shared__ int32_t s_h[16], s_r[16], s_t[16];
+    int32_t h = 0, r = 0, c = 0;
     for (int32_t t = threadIdx.x; t < nt; t += 1024) {
         h = max(h, work[t].halo_cnt);
         r = max(r, 4 * work[t].row_words);
+        c = max(c, work[t].tri_cnt);
     }
     for (int off = 32; off > 0; off >>= 1) {
         h = max(h, __shfl_xor(h, off));
         r = max(r, __shfl_xor(r, off));
+        c = max(c, __shfl_xor(c, off));
     }
     if ((threadIdx.x & 63) == 0) {
         s_h[threadIdx.x >> 6] = h;
         s_r[threadIdx.x >> 6] = r;
+        s_t[threadIdx.x >> 6] = c;
     }
     __syncthreads();
     if (threadIdx.x == 0) {
         for (int q = 1; q < 16; ++q) {
             h = max(h, s_h[q]);
             r = max(r, s_r[q]);
+            c = max(c, s_t[q]);
         }
         mx[0] = h;
         mx[1] = r;
+        mx[2] = c;
     }
 }
 
@@ -400,7 +407,7 @@ size_t tile_bytes(int64_t n, int64_t nnz, int64_t ninc, int tile_nodes)
     return Arena::piece(sizeof(TileWork) * nt) + Arena::piece(nt * (4 * tile_nodes + 64) + 6 * z + 8 * c + 16);
 }
 
-size_t tile_scratch_bytes() { return Arena::piece(3 * sizeof(int32_t)); }
+size_t tile_scratch_bytes() { return Arena::piece(4 * sizeof(int32_t)); }
 
 sl_status build_tiles(const SetupArgs& a, DevMesh& m, int tile_nodes, int mesh, hipStream_t st, Arena& persist,
                       Arena& scratch)
@@ -411,9 +418,9 @@ sl_status build_tiles(const SetupArgs& a, DevMesh& m, int tile_nodes, int mesh, 
     const int nt = div_up(m.n_free, T);
     const size_t pmark = persist.mark(), smark = scratch.mark();
     sl_status r = SL_OK;
-    int32_t* flags = nullptr;   // {err, largest halo, largest row segment}
-    if ((r = scratch.take(&flags, 3))) return r;
-    SL_HIP(hipMemsetAsync(flags, 0, 3 * sizeof(int32_t), st));
+    int32_t* flags = nullptr;   // {err, largest halo, largest row segment, largest triangle list}
+    if ((r = scratch.take(&flags, 4))) return r;
+    SL_HIP(hipMemsetAsync(flags, 0, 4 * sizeof(int32_t), st));
     const size_t data_bytes = static_cast<size_t>(tile_record(static_cast<int32_t>(m.nnz_free),
                                                               static_cast<int32_t>(m.ninc_free), nt, T));
     if ((r = persist.take(&m.work, nt)) || (r = persist.take(&m.tile_data, data_bytes))) return r;
@@ -438,8 +445,8 @@ sl_status build_tiles(const SetupArgs& a, DevMesh& m, int tile_nodes, int mesh, 
     else k_tile_build<512><<<nt, kBuildBS, 0, st>>>(b);
     k_tile_caps<<<1, 1024, 0, st>>>(m.work, nt, flags + 1);
     SL_HIP(hipGetLastError());
-    int32_t h[3] = {0, 0, 0};
-    SL_HIP(hipMemcpyAsync(h, flags, 3 * sizeof(int32_t), hipMemcpyDeviceToHost, st));
+    int32_t h[4] = {0, 0, 0, 0};
+    SL_HIP(hipMemcpyAsync(h, flags, 4 * sizeof(int32_t), hipMemcpyDeviceToHost, st));
     SL_HIP(hipStreamSynchronize(st));
     scratch.rewind(smark);
     if (h[0] & 1) return fail(SL_ETOPO, "triangle vertex outside its tile's neighbourhood");
@@ -451,8 +458,12 @@ sl_status build_tiles(const SetupArgs& a, DevMesh& m, int tile_nodes, int mesh, 
         persist.rewind(pmark);
         return SL_OK;
     }
-    if (T == 256) k_tile_order<256><<<nt, 256, 0, st>>>(m.work);
-    else k_tile_order<512><<<nt, 256, 0, st>>>(m.work);
+    const int cap = std::min(h[3], kOrderWords);
+    if (cap > 0) {
+        const size_t lds = sizeof(uint64_t) * static_cast<size_t>(cap);
+        if (T == 256) k_tile_order<256><<<nt, 256, lds, st>>>(m.work, cap);
+        else k_tile_order<512><<<nt, 256, lds, st>>>(m.work, cap);
+    }
     SL_HIP(hipGetLastError());
     m.halo_max = h[1];
     m.rows_max = h[2];
