@@ -128,7 +128,9 @@ constexpr int32_t kSweepChunk = 32;   // even
 struct CallState {
     hipStream_t st = nullptr;
     DevMesh m;
+    Arena aux;                          // the sweep state, the tile launches' counter, the flag words
     MeshState* state = nullptr;
+    int32_t* close_count = nullptr;
     uint64_t* bits = nullptr;
     hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
     hipGraph_t graph = nullptr;
@@ -138,8 +140,7 @@ struct CallState {
     {
         if (capture) give_stream(capture);
         devmesh_free(m, st);
-        dfree(state, st);
-        dfree(bits, st);
+        aux.release(st);
         (void)hipStreamSynchronize(st);
         if (exec) (void)hipGraphExecDestroy(exec);
         if (graph) (void)hipGraphDestroy(graph);
@@ -181,21 +182,29 @@ sl_status run_device(double* coords, int32_t n, const int32_t* nbr_ptr, const in
     h0.iters = its;
     h0.active = its > 0;
     h0.tol2 = tol2;
-    if ((r = dalloc(&cs.state, 1, stream))) return r;
+    const bool want_bits = o.flags_out && its > 0;
+    const size_t n_bits = want_bits ? static_cast<size_t>(words) * its : 0;
+    if ((r = cs.aux.reserve(Arena::piece(sizeof(MeshState)) + Arena::piece(sizeof(int32_t)) +
+                                (want_bits ? Arena::piece(8 * n_bits) : 0),
+                            stream)) ||
+        (r = cs.aux.take(&cs.state, 1)) || (r = cs.aux.take(&cs.close_count, 1)))
+        return r;
     SL_HIP(hipMemcpyAsync(cs.state, &h0, sizeof(MeshState), hipMemcpyHostToDevice, stream));
-    if (o.flags_out && its > 0) {
-        if ((r = dalloc(&cs.bits, static_cast<size_t>(words) * its, stream))) return r;
-        SL_HIP(hipMemsetAsync(cs.bits, 0, sizeof(uint64_t) * words * its, stream));
+    SL_HIP(hipMemsetAsync(cs.close_count, 0, sizeof(int32_t), stream));
+    if (want_bits) {
+        if ((r = cs.aux.take(&cs.bits, n_bits))) return r;
+        SL_HIP(hipMemsetAsync(cs.bits, 0, sizeof(uint64_t) * n_bits, stream));
     }
     const bool tiles = o.form == SL_JACOBI && cs.m.tile_nodes > 0;
     const int32_t block = resolve_block_size(o);
-    // with a tolerance, a launch on a converged mesh returns at once
+    // with a tolerance, a launch on a converged mesh returns at once; a tile
+    // launch closes its own sweep
     const TileLaunch L{cs.m.work, cs.m.n_tiles, cs.m.tile_nodes, cs.m.halo_max, cs.m.rows_max, o.layout, o.accept,
-                       cs.state, resolve_wg_per_cu(o), tol2 > 0.0 ? 1 : 0, o.precision};
+                       cs.state, resolve_wg_per_cu(o), tol2 > 0.0 ? 1 : 0, o.precision, cs.close_count, 1};
     auto enqueue = [&](int32_t s, hipStream_t on) -> sl_status {
         uint64_t* bits = cs.bits ? cs.bits + static_cast<int64_t>(s) * words : nullptr;
-        sl_status rr = tiles ? launch_sweep_tiles(L, s & 1, bits, on)
-                             : launch_sweep_nodes(cs.m, s & 1, o.form, o.accept, block, cs.state, bits, on);
+        if (tiles) return launch_sweep_tiles(L, s & 1, bits, on);
+        const sl_status rr = launch_sweep_nodes(cs.m, s & 1, o.form, o.accept, block, cs.state, bits, on);
         return rr ? rr : launch_advance(cs.state, 1, on);
     };
 

@@ -32,6 +32,7 @@ struct BatchState {
     std::vector<DevMesh> meshes;
     TileWork* work = nullptr;
     MeshState* states = nullptr;
+    int32_t* close_count = nullptr;
     double* out = nullptr;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
@@ -41,6 +42,7 @@ struct BatchState {
         for (auto& m : meshes) devmesh_free(m, st);
         dfree(work, st);
         dfree(states, st);
+        dfree(close_count, st);
         dfree(out, st);
         (void)hipStreamSynchronize(st);
         for (auto s : setup_st)
@@ -195,14 +197,22 @@ sl_status sl_batch_smooth(const sl_mesh_desc* meshes, int32_t n_meshes, int32_t 
     }
     if ((r = dalloc(&bs.states, static_cast<size_t>(n_meshes), st))) return r;
     SL_HIP(hipMemcpyAsync(bs.states, h0.data(), sizeof(MeshState) * h0.size(), hipMemcpyHostToDevice, st));
+    // with every mesh on the tile path, the tile launch closes each sweep itself
+    const bool jacobi = o.form == SL_JACOBI;
+    bool all_tiles = jacobi && total_tiles > 0;
+    for (int32_t i = 0; i < n_meshes && all_tiles; ++i) all_tiles = bs.meshes[i].tile_nodes > 0;
+    if (all_tiles) {
+        if ((r = dalloc(&bs.close_count, 1, st))) return r;
+        SL_HIP(hipMemsetAsync(bs.close_count, 0, sizeof(int32_t), st));
+    }
     SL_HIP(hipStreamSynchronize(st));
     const double setup_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
 
     // ---- the sweep loop, captured once and replayed
     const TileLaunch L{bs.work, static_cast<int32_t>(total_tiles), T, halo_cap, rows_cap, o.layout, o.accept,
-                       bs.states, resolve_wg_per_cu(o), (n_meshes == 1 && tol2 > 0.0) ? 1 : 0, o.precision};
+                       bs.states, resolve_wg_per_cu(o), (n_meshes == 1 && tol2 > 0.0) ? 1 : 0, o.precision,
+                       bs.close_count, n_meshes};
     const int32_t block = resolve_block_size(o);
-    const bool jacobi = o.form == SL_JACOBI;
     const int32_t chunk = iterations <= 128 ? iterations + (iterations & 1) : 64;   // even: parity repeats
     auto enqueue_chunk = [&]() -> sl_status {
         for (int32_t s = 0; s < chunk; ++s) {
@@ -213,7 +223,8 @@ sl_status sl_batch_smooth(const sl_mesh_desc* meshes, int32_t n_meshes, int32_t 
                 if (jacobi && m.tile_nodes > 0) continue;
                 rr = launch_sweep_nodes(m, s & 1, o.form, o.accept, block, bs.states + i, nullptr, st);
             }
-            if (rr || (rr = launch_advance(bs.states, n_meshes, st))) return rr;
+            if (!rr && !all_tiles) rr = launch_advance(bs.states, n_meshes, st);
+            if (rr) return rr;
         }
         return SL_OK;
     };

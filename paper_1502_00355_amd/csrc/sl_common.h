@@ -72,6 +72,18 @@ void dfree(T*& p, hipStream_t st)
     p = nullptr;
 }
 
+// Large device blocks (the arenas below) come from a per-device cache kept
+// for the life of the process.  A stream-ordered allocation and free cost
+// 0.1-0.7 ms of host time each, during which a device with nothing queued
+// idles; repeated calls on meshes of similar size reuse their blocks
+// instead.  A block given back carries an event recorded on the giving
+// stream after every use of the block; the next taker's stream waits for
+// that event before its first use.  The cache holds at most a few blocks
+// and a bounded number of bytes per device; when an allocation fails, the
+// cached blocks are freed and it is tried once more.
+sl_status block_take(unsigned char** p, size_t bytes, hipStream_t st);
+void block_give(unsigned char*& p, hipStream_t st);
+
 inline int div_up(int64_t a, int64_t b) { return static_cast<int>((a + b - 1) / b); }
 
 // Device memory carved out of one stream-ordered allocation, so that a
@@ -90,7 +102,7 @@ struct Arena {
     {
         used = 0;
         cap = bytes;
-        return dalloc(&base, std::max<size_t>(bytes, 256), st);
+        return block_take(&base, std::max<size_t>(bytes, 256), st);
     }
     template <typename T>
     sl_status take(T** p, size_t count)
@@ -109,7 +121,7 @@ struct Arena {
     void rewind(size_t m) { used = m; }
     void release(hipStream_t st)
     {
-        dfree(base, st);
+        block_give(base, st);
         cap = used = 0;
     }
 };
@@ -117,7 +129,8 @@ struct Arena {
 // ------------------------------------------------------- device workspace --
 
 // Sweep state of one mesh on the device.  The sweep kernels read `active`
-// and fold into the *_cur fields; k_advance closes a sweep.
+// and fold into the *_cur fields; close_state (k_advance, or the last
+// work-group of a tile launch) closes a sweep.
 struct MeshState {
     int32_t s;                      // sweeps completed
     int32_t iters;                  // cap on sweeps
@@ -130,6 +143,27 @@ struct MeshState {
     unsigned long long acc_last;
     unsigned long long acc_total;
 };
+
+// Closes one sweep of one mesh: counts it if the mesh ran it, moves the
+// sweep's folds to the *_last fields and decides whether the next sweep
+// runs.  The *_cur fields are read with atomic loads, since other
+// work-groups of the same launch may have folded into them.
+__device__ __forceinline__ void close_state(MeshState* p)
+{
+    MeshState m = *p;
+    if (!m.active) return;
+    m.maxd_cur = __hip_atomic_load(&p->maxd_cur, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    m.acc_cur = __hip_atomic_load(&p->acc_cur, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    m.s += 1;
+    m.maxd_last = m.maxd_cur;
+    m.acc_last = m.acc_cur;
+    m.acc_total += m.acc_cur;
+    m.maxd_cur = 0;
+    m.acc_cur = 0;
+    const double last = __longlong_as_double(static_cast<long long>(m.maxd_last));
+    m.active = (m.s < m.iters) && !(m.tol2 > 0.0 && last < m.tol2);
+    *p = m;
+}
 
 // One tile of the tile path: everything a work-group needs to sweep it, with
 // absolute pointers so that tiles of many meshes can share one launch.
@@ -314,6 +348,11 @@ struct TileLaunch {
     int32_t wg_per_cu;          // 0: as many as fit, at most 4
     int32_t exit_if_inactive;   // 1: every tile is of one mesh; a launch on it returns at once once it stops
     int32_t precision;          // SL_F64 or SL_F32: every mesh of the list has it
+    // nullable: a zeroed counter; the launch's last work-group then closes
+    // the sweep of states[0..n_close) itself (and zeroes the counter again),
+    // in place of a launch_advance after it
+    int32_t* close_count;
+    int32_t n_close;
 };
 sl_status launch_sweep_tiles(const TileLaunch& L, int32_t parity, uint64_t* bits, hipStream_t st);
 

@@ -698,7 +698,7 @@ sl_status scan_exclusive(const int32_t* in, int32_t* out, int64_t n, hipStream_t
 
 void devmesh_free(DevMesh& m, hipStream_t st)
 {
-    dfree(m.block, st);
+    block_give(m.block, st);
     m.perm = m.new_of_old = m.row_ptr = m.nbr = m.fan_ptr = nullptr;
     m.fan = nullptr;
     m.X[0] = m.X[1] = nullptr;

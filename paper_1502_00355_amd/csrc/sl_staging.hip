@@ -1,5 +1,6 @@
 // Copies between callers' host memory and the device through pinned
-// staging buffers, and the library's pool of streams.
+// staging buffers, the library's pool of streams, and its cache of device
+// blocks.
 //
 // Callers hand in ordinary (pageable) host arrays.  A copy from pageable
 // memory is carried out by the runtime synchronously through its own
@@ -211,6 +212,123 @@ void give_stream(hipStream_t st)
     std::lock_guard<std::mutex> lk(g_stream_mu);
     auto it = g_stream_dev.find(st);
     if (it != g_stream_dev.end()) g_stream_free[it->second].push_back(st);
+}
+
+namespace {
+
+constexpr size_t kCacheBlocks = 8;                       // per device
+constexpr size_t kCacheBytes = size_t(16) << 30;         // per device
+
+struct Cached {
+    unsigned char* ptr;
+    size_t bytes;
+    hipEvent_t ev;   // recorded on the giving stream after the block's last use
+};
+
+std::mutex g_block_mu;
+std::vector<Cached> g_block_cache[64];                               // oldest first
+size_t g_block_cached[64];                                           // bytes held in g_block_cache
+std::unordered_map<void*, std::pair<int, size_t>> g_block_info;      // every block handed out: device, bytes
+std::vector<hipEvent_t> g_block_events[64];                          // events free for reuse
+
+// Frees the oldest cached blocks of `dev` until the cache is within its
+// limits (or empty), ordered on `st` after each block's last use.  The
+// caller holds g_block_mu.
+void trim_blocks(int dev, bool all, hipStream_t st)
+{
+    auto& c = g_block_cache[dev];
+    while (!c.empty() && (all || c.size() > kCacheBlocks || g_block_cached[dev] > kCacheBytes)) {
+        const Cached e = c.front();
+        c.erase(c.begin());
+        g_block_cached[dev] -= e.bytes;
+        (void)hipStreamWaitEvent(st, e.ev, 0);
+        (void)hipFreeAsync(e.ptr, st);
+        g_block_info.erase(e.ptr);
+        g_block_events[dev].push_back(e.ev);
+    }
+}
+
+}  // namespace
+
+sl_status block_take(unsigned char** p, size_t bytes, hipStream_t st)
+{
+    *p = nullptr;
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return fail(SL_EDEVICE, "no current device");
+    {
+        std::lock_guard<std::mutex> lk(g_block_mu);
+        auto& c = g_block_cache[dev];
+        // the smallest cached block that holds `bytes` and is not much larger
+        int best = -1;
+        for (int k = 0; k < static_cast<int>(c.size()); ++k)
+            if (c[k].bytes >= bytes && c[k].bytes <= 2 * bytes + (size_t(1) << 20) &&
+                (best < 0 || c[k].bytes < c[best].bytes))
+                best = k;
+        if (best >= 0) {
+            const Cached e = c[best];
+            SL_HIP(hipStreamWaitEvent(st, e.ev, 0));
+            c.erase(c.begin() + best);
+            g_block_cached[dev] -= e.bytes;
+            g_block_events[dev].push_back(e.ev);
+            *p = e.ptr;
+            return SL_OK;
+        }
+    }
+    hipError_t e = hipMallocAsync(reinterpret_cast<void**>(p), bytes, st);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        {
+            std::lock_guard<std::mutex> lk(g_block_mu);
+            trim_blocks(dev, true, st);
+        }
+        e = hipMallocAsync(reinterpret_cast<void**>(p), bytes, st);
+    }
+    if (e != hipSuccess) {
+        *p = nullptr;
+        (void)hipGetLastError();
+        return fail(SL_ENOMEM, std::string("device allocation of ") + std::to_string(bytes) +
+                                   " bytes failed: " + hipGetErrorString(e));
+    }
+    std::lock_guard<std::mutex> lk(g_block_mu);
+    g_block_info[*p] = {dev, bytes};
+    return SL_OK;
+}
+
+void block_give(unsigned char*& p, hipStream_t st)
+{
+    if (!p) return;
+    unsigned char* q = p;
+    p = nullptr;
+    int dev = -1;
+    (void)hipGetDevice(&dev);
+    std::lock_guard<std::mutex> lk(g_block_mu);
+    const auto it = g_block_info.find(q);
+    // a block of another device, or one too large to keep, is freed at once
+    if (it == g_block_info.end() || it->second.first != dev || it->second.second > kCacheBytes) {
+        if (it != g_block_info.end()) g_block_info.erase(it);
+        (void)hipFreeAsync(q, st);
+        return;
+    }
+    hipEvent_t ev = nullptr;
+    if (!g_block_events[dev].empty()) {
+        ev = g_block_events[dev].back();
+        g_block_events[dev].pop_back();
+    } else if (hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess) {
+        (void)hipGetLastError();
+        g_block_info.erase(it);
+        (void)hipFreeAsync(q, st);
+        return;
+    }
+    if (hipEventRecord(ev, st) != hipSuccess) {
+        (void)hipGetLastError();
+        g_block_events[dev].push_back(ev);
+        g_block_info.erase(it);
+        (void)hipFreeAsync(q, st);
+        return;
+    }
+    g_block_cache[dev].push_back(Cached{q, it->second.second, ev});
+    g_block_cached[dev] += it->second.second;
+    trim_blocks(dev, false, st);
 }
 
 }  // namespace sl

@@ -206,18 +206,7 @@ void launch_range(SweepArgs a, int max_deg, int requested_block, bool soa, bool 
 __global__ void k_advance(MeshState* __restrict__ st, int32_t n)
 {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    MeshState m = st[i];
-    if (!m.active) return;
-    m.s += 1;
-    m.maxd_last = m.maxd_cur;
-    m.acc_last = m.acc_cur;
-    m.acc_total += m.acc_cur;
-    m.maxd_cur = 0;
-    m.acc_cur = 0;
-    const double last = __longlong_as_double(static_cast<long long>(m.maxd_last));
-    m.active = (m.s < m.iters) && !(m.tol2 > 0.0 && last < m.tol2);
-    st[i] = m;
+    if (i < n) close_state(st + i);
 }
 
 }  // namespace

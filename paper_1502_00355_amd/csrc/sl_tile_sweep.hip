@@ -99,6 +99,8 @@ struct TileSweepArgs {
     int32_t exit_if_inactive;  // all tiles are of one mesh: return at once if it has stopped
     MeshState* states;
     uint64_t* bits;            // nullable: accept bits of this sweep (single mesh)
+    int32_t* close_count;      // nullable: the last work-group closes the sweep of states[0..n_close)
+    int32_t n_close;
 };
 
 // Old quality of one triangle and the new quality for each own vertex,
@@ -264,7 +266,7 @@ __device__ __forceinline__ void stage_b(TileStage<R, NPT, RPRE, KPRE>& s, const 
 // by the work-groups that XCD runs; each work-group computes one tile while
 // the next one's data is on its way.
 template <int T, int BS, bool SOA, bool GT, typename R>
-__global__ __launch_bounds__(BS) void k_sweep_tile(TileSweepArgs a)
+__device__ __forceinline__ void sweep_tiles(const TileSweepArgs& a)
 {
     using V2 = typename Real<R>::V2;
     constexpr int NPT = T / BS;   // own nodes per work-item
@@ -452,6 +454,37 @@ __global__ __launch_bounds__(BS) void k_sweep_tile(TileSweepArgs a)
     }
 }
 
+// The last work-group of a launch to finish closes the sweep of states[0..n)
+// and zeroes the counter for the next launch.  A group's folds into the
+// sweep state are device-scope atomics made by its first work-item; the
+// work-group-scope release waits until they have completed, so they are
+// performed before the group's count.  The closing group reads the folds
+// with device-scope atomic loads after it has seen every count.  No
+// device-scope release or acquire is needed: those would write back or
+// invalidate the XCD's L2, once per work-group.
+template <int BS>
+__device__ __forceinline__ void close_launch(int32_t* count, MeshState* states, int32_t n)
+{
+    __shared__ int s_last;
+    __syncthreads();   // every work-item of the group is done with its tiles
+    if (threadIdx.x == 0) {
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+        const int before = __hip_atomic_fetch_add(count, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        s_last = before == static_cast<int>(gridDim.x) - 1;
+    }
+    __syncthreads();
+    if (!s_last) return;
+    for (int i = threadIdx.x; i < n; i += BS) close_state(states + i);
+    if (threadIdx.x == 0) __hip_atomic_store(count, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+template <int T, int BS, bool SOA, bool GT, typename R>
+__global__ __launch_bounds__(BS) void k_sweep_tile(TileSweepArgs a)
+{
+    sweep_tiles<T, BS, SOA, GT, R>(a);
+    if (a.close_count) close_launch<BS>(a.close_count, a.states, a.n_close);
+}
+
 constexpr int kTileBS = 256;
 
 template <int T, int BS, bool SOA, bool GT, typename R>
@@ -502,7 +535,7 @@ int tile_grid(int n_work, int tile_nodes, int halo_cap, int rows_cap, int wg_per
 
 sl_status launch_sweep_tiles(const TileLaunch& L, int32_t parity, uint64_t* bits, hipStream_t st)
 {
-    if (L.n_work <= 0) return SL_OK;
+    if (L.n_work <= 0) return L.close_count ? launch_advance(L.states, L.n_close, st) : SL_OK;
     TileSweepArgs a{};
     a.work = L.work;
     a.n_work = L.n_work;
@@ -513,6 +546,8 @@ sl_status launch_sweep_tiles(const TileLaunch& L, int32_t parity, uint64_t* bits
     a.exit_if_inactive = L.exit_if_inactive;
     a.states = L.states;
     a.bits = bits;
+    a.close_count = L.close_count;
+    a.n_close = L.n_close;
     const size_t lds = tile_lds_bytes(L.tile_nodes, L.halo_cap, L.rows_cap, L.precision);
     const int grid = tile_grid(L.n_work, L.tile_nodes, L.halo_cap, L.rows_cap, L.wg_per_cu, L.precision);
     const bool soa = L.layout == SL_SOA, gt = L.accept == SL_ACCEPT_GT;

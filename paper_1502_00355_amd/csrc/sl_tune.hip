@@ -30,12 +30,14 @@ struct TunePass {
     std::vector<DevMesh> meshes;
     TileWork* work = nullptr;
     MeshState* states = nullptr;
+    int32_t* close_count = nullptr;   // tile launches close their own sweeps
     hipEvent_t ev[2] = {nullptr, nullptr};
     ~TunePass()
     {
         for (auto& m : meshes) devmesh_free(m, st);
         dfree(work, st);
         dfree(states, st);
+        dfree(close_count, st);
         (void)hipStreamSynchronize(st);
         for (auto& e : ev)
             if (e) (void)hipEventDestroy(e);
@@ -64,13 +66,15 @@ sl_status setup_pass(TunePass& p, const sl_mesh_desc* meshes, const std::vector<
         s.active = 1;
     }
     sl_status r = dalloc(&p.states, h.size(), p.st);
-    if (r) return r;
+    if (r || (r = dalloc(&p.close_count, 1, p.st))) return r;
     SL_HIP(hipMemcpyAsync(p.states, h.data(), sizeof(MeshState) * h.size(), hipMemcpyHostToDevice, p.st));
+    SL_HIP(hipMemsetAsync(p.close_count, 0, sizeof(int32_t), p.st));
     for (auto& e : p.ev) SL_HIP(hipEventCreate(&e));
     return SL_OK;
 }
 
-// Device milliseconds of kTimedSweeps sweeps enqueued by `sweep(parity)`.
+// Device milliseconds of kTimedSweeps sweeps enqueued by `sweep(parity)`
+// (n_states > 0: each followed by a launch_advance over that many states).
 template <typename F>
 sl_status time_sweeps(TunePass& p, int32_t n_states, F sweep, float* ms)
 {
@@ -78,7 +82,7 @@ sl_status time_sweeps(TunePass& p, int32_t n_states, F sweep, float* ms)
     for (int32_t s = 0; s < kWarmSweeps + kTimedSweeps && !r; ++s) {
         if (s == kWarmSweeps) SL_HIP(hipEventRecord(p.ev[0], p.st));
         r = sweep(s & 1);
-        if (!r) r = launch_advance(p.states, n_states, p.st);
+        if (!r && n_states > 0) r = launch_advance(p.states, n_states, p.st);
     }
     if (r) return r;
     SL_HIP(hipEventRecord(p.ev[1], p.st));
@@ -123,10 +127,9 @@ sl_status tune_tiles(const sl_mesh_desc* meshes, const std::vector<int32_t>& sam
             if (grid == last_grid) continue;   // capped by LDS or by the tile count: same launch
             last_grid = grid;
             const TileLaunch L{p.work, static_cast<int32_t>(tiles), T, hcap, rcap, o.layout, o.accept, p.states, w, 0,
-                               o.precision};
+                               o.precision, p.close_count, static_cast<int32_t>(p.meshes.size())};
             float ms = 0.f;
-            r = time_sweeps(p, static_cast<int32_t>(p.meshes.size()),
-                            [&](int32_t parity) { return launch_sweep_tiles(L, parity, nullptr, st); }, &ms);
+            r = time_sweeps(p, 0, [&](int32_t parity) { return launch_sweep_tiles(L, parity, nullptr, st); }, &ms);
             if (r) return r;
             out.push_back(Candidate{T, w, 1e6 * ms / (static_cast<double>(kTimedSweeps) * on_tiles)});
         }
