@@ -50,88 +50,144 @@ __device__ __forceinline__ uint64_t splitmix64(uint64_t v)
 }
 
 // ---------------------------------------------------------------- scan ----
+//
+// Reduce, then scan: one pass sums each tile of kScanTile values, one
+// work-group scans the tile sums, and a second pass scans each tile from its
+// offset.  Each work-item holds 16 consecutive values, loaded and stored as
+// four 16-byte vectors when the arrays allow it.
 
-template <int IT>
-__global__ __launch_bounds__(kBS) void k_scan_block(const int32_t* __restrict__ in, int32_t* __restrict__ out,
-                                                    int64_t n, int32_t* __restrict__ block_sums)
+constexpr int kScanPer = 16;
+constexpr int kScanTile = kBS * kScanPer;
+constexpr int kSumsBS = 1024;
+
+// This work-item's values of tile `b` (zeros past n).
+__device__ __forceinline__ void scan_load(const int32_t* __restrict__ in, int64_t n, int64_t base, bool vec,
+                                          int32_t (&v)[kScanPer])
 {
-    __shared__ int32_t s[kBS];
-    const int64_t base = (static_cast<int64_t>(blockIdx.x) * kBS + threadIdx.x) * IT;
-    int32_t v[IT];
-    int32_t sum = 0;
+    if (vec && base + kScanPer <= n) {
+        const int4* p = reinterpret_cast<const int4*>(in + base);
 #pragma unroll
-    for (int j = 0; j < IT; ++j) {
-        const int64_t i = base + j;
-        v[j] = i < n ? in[i] : 0;
-        sum += v[j];
+        for (int q = 0; q < kScanPer / 4; ++q) {
+            const int4 w = p[q];
+            v[4 * q] = w.x;
+            v[4 * q + 1] = w.y;
+            v[4 * q + 2] = w.z;
+            v[4 * q + 3] = w.w;
+        }
+    } else {
+#pragma unroll
+        for (int j = 0; j < kScanPer; ++j) v[j] = base + j < n ? in[base + j] : 0;
     }
-    s[threadIdx.x] = sum;
+}
+
+// Exclusive scan of one value per work-item over a work-group of BS
+// work-items (wave scans, then the wave totals); *total = the group's sum.
+template <int BS>
+__device__ __forceinline__ int32_t group_excl_scan(int32_t x, int32_t* s_wave, int32_t* total)
+{
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    int32_t inc = x;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const int32_t t = __shfl_up(inc, off, 64);
+        if (lane >= off) inc += t;
+    }
+    if (lane == 63) s_wave[wv] = inc;
     __syncthreads();
-    for (int off = 1; off < kBS; off <<= 1) {
-        const int32_t t = threadIdx.x >= off ? s[threadIdx.x - off] : 0;
-        __syncthreads();
-        s[threadIdx.x] += t;
-        __syncthreads();
-    }
-    int32_t run = threadIdx.x ? s[threadIdx.x - 1] : 0;
+    int32_t before = 0, all = 0;
 #pragma unroll
-    for (int j = 0; j < IT; ++j) {
-        const int64_t i = base + j;
-        if (i < n) out[i] = run;
-        run += v[j];
+    for (int w = 0; w < BS / 64; ++w) {
+        const int32_t t = s_wave[w];
+        before += w < wv ? t : 0;
+        all += t;
     }
-    if (threadIdx.x == kBS - 1) block_sums[blockIdx.x] = s[kBS - 1];
+    __syncthreads();   // s_wave may be reused at once
+    *total = all;
+    return before + inc - x;
 }
 
-__global__ void k_scan_add(int32_t* __restrict__ out, int64_t n, const int32_t* __restrict__ offs, int per_block)
+__global__ __launch_bounds__(kBS) void k_scan_sums(const int32_t* __restrict__ in, int64_t n, bool vec,
+                                                   int32_t* __restrict__ sums)
 {
-    const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (i < n) out[i] += offs[i / per_block];
+    __shared__ int32_t s_wave[kBS / 64];
+    int32_t v[kScanPer];
+    scan_load(in, n, (static_cast<int64_t>(blockIdx.x) * kBS + threadIdx.x) * kScanPer, vec, v);
+    int32_t x = 0;
+#pragma unroll
+    for (int j = 0; j < kScanPer; ++j) x += v[j];
+    int32_t total;
+    (void)group_excl_scan<kBS>(x, s_wave, &total);
+    if (threadIdx.x == 0) sums[blockIdx.x] = total;
 }
 
-__global__ void k_set_total(int32_t* __restrict__ dst, const int32_t* __restrict__ src) { *dst = *src; }
+// Exclusive scan of the nb tile sums in place, by one work-group; *total =
+// their sum.
+__global__ __launch_bounds__(kSumsBS) void k_scan_offsets(int32_t* __restrict__ sums, int32_t nb,
+                                                          int32_t* __restrict__ total)
+{
+    __shared__ int32_t s_wave[kSumsBS / 64];
+    const int per = (nb + kSumsBS - 1) / kSumsBS;
+    const int b0 = min(static_cast<int>(threadIdx.x) * per, nb), b1 = min(b0 + per, nb);
+    int32_t x = 0;
+    for (int b = b0; b < b1; ++b) x += sums[b];
+    int32_t all;
+    int32_t run = group_excl_scan<kSumsBS>(x, s_wave, &all);
+    for (int b = b0; b < b1; ++b) {
+        const int32_t t = sums[b];
+        sums[b] = run;
+        run += t;
+    }
+    if (threadIdx.x == 0) *total = all;
+}
 
-constexpr int kScanIt = 8;
-constexpr int kScanTile = kBS * kScanIt;
+__global__ __launch_bounds__(kBS) void k_scan_tiles(const int32_t* __restrict__ in, int32_t* __restrict__ out,
+                                                    int64_t n, bool vec, const int32_t* __restrict__ offs)
+{
+    __shared__ int32_t s_wave[kBS / 64];
+    const int64_t base = (static_cast<int64_t>(blockIdx.x) * kBS + threadIdx.x) * kScanPer;
+    int32_t v[kScanPer];
+    scan_load(in, n, base, vec, v);
+    int32_t x = 0;
+#pragma unroll
+    for (int j = 0; j < kScanPer; ++j) x += v[j];
+    int32_t total;
+    int32_t run = offs[blockIdx.x] + group_excl_scan<kBS>(x, s_wave, &total);
+#pragma unroll
+    for (int j = 0; j < kScanPer; ++j) {
+        const int32_t t = v[j];
+        v[j] = run;
+        run += t;
+    }
+    if (vec && base + kScanPer <= n) {
+        int4* p = reinterpret_cast<int4*>(out + base);
+#pragma unroll
+        for (int q = 0; q < kScanPer / 4; ++q) p[q] = make_int4(v[4 * q], v[4 * q + 1], v[4 * q + 2], v[4 * q + 3]);
+    } else {
+#pragma unroll
+        for (int j = 0; j < kScanPer; ++j)
+            if (base + j < n) out[base + j] = v[j];
+    }
+}
 
-// Exclusive scan of in[0..n) into out[0..n); *total = sum.  Temporaries
+// Exclusive scan of in[0..n) into out[0..n); *total = sum.  The tile sums
 // come from `ar` when given, else from the allocator.
 sl_status scan_rec(const int32_t* in, int32_t* out, int64_t n, int32_t* total, hipStream_t st, Arena* ar)
 {
     const int nb = div_up(n > 0 ? n : 1, kScanTile);
-    auto get = [&](int32_t** p, size_t cnt) { return ar ? ar->take(p, cnt) : dalloc(p, cnt, st); };
-    auto put = [&](int32_t*& p) {
-        if (!ar) dfree(p, st);
-    };
-    int32_t *sums = nullptr, *offs = nullptr;
-    sl_status r = get(&sums, static_cast<size_t>(nb) + 1);
+    int32_t* sums = nullptr;
+    sl_status r = ar ? ar->take(&sums, static_cast<size_t>(nb)) : dalloc(&sums, static_cast<size_t>(nb), st);
     if (r) return r;
-    k_scan_block<kScanIt><<<nb, kBS, 0, st>>>(in, out, n, sums);
-    if (nb == 1) {
-        k_set_total<<<1, 1, 0, st>>>(total, sums);
-    } else if (!(r = get(&offs, static_cast<size_t>(nb) + 1))) {
-        r = scan_rec(sums, offs, nb, total, st, ar);
-        if (!r) k_scan_add<<<div_up(n, 256), 256, 0, st>>>(out, n, offs, kScanTile);
-        put(offs);
-    }
-    put(sums);
-    if (r) return r;
+    const bool vec = ((reinterpret_cast<uintptr_t>(in) | reinterpret_cast<uintptr_t>(out)) & 15) == 0;
+    k_scan_sums<<<nb, kBS, 0, st>>>(in, n, vec, sums);
+    k_scan_offsets<<<1, kSumsBS, 0, st>>>(sums, nb, total);
+    k_scan_tiles<<<nb, kBS, 0, st>>>(in, out, n, vec, sums);
+    if (!ar) dfree(sums, st);
     SL_HIP(hipGetLastError());
     return SL_OK;
 }
 
 // Arena bytes the temporaries of a scan of n values take.
-size_t scan_bytes(int64_t n)
-{
-    size_t b = 0;
-    for (int64_t m = n;; ) {
-        const int64_t nb = div_up(m > 0 ? m : 1, kScanTile);
-        b += 2 * Arena::piece(4 * static_cast<size_t>(nb + 1));
-        if (nb == 1) break;
-        m = nb;
-    }
-    return b;
-}
+size_t scan_bytes(int64_t n) { return Arena::piece(4 * static_cast<size_t>(div_up(n > 0 ? n : 1, kScanTile))); }
 
 // ----------------------------------------------------------- validation ---
 
