@@ -172,7 +172,7 @@ struct alignas(16) TileWork {
     const int32_t* halo;            // halo node ids (mesh device labels)
     const uint64_t* rows;           // neighbour rows in local indices, 4 x u16 per word
     const uint64_t* tris;           // triangle entries: 3 x u16 local indices, stored order
-    const uint32_t* rr;             // per own node: row start | row end << 16 within `rows`
+    const uint16_t* rr;             // T + 1 row starts within `rows`: node i's row is rr[i] .. rr[i+1]
     int32_t own_start, nown;        // own nodes: mesh device labels [own_start, own_start + nown)
     int32_t halo_cnt, tri_cnt;
     int32_t row_words, mesh;        // 64-bit row words; index of the mesh's MeshState

@@ -101,17 +101,19 @@ struct TileBuildArgs {
 __host__ __device__ __forceinline__ int64_t align16(int64_t b) { return (b + 15) & ~int64_t(15); }
 
 // Byte offset of tile k's record, from the row and incidence offsets of its
-// first node.  A record holds T u32 row offsets, then room for len halo ids
-// (len = the tile's row entries; the halo is never longer), the rows (len
-// rounded up to 4 u16), and flen triangle words (flen = its incidences, an
-// upper bound of its triangles), each part 16-byte aligned: at most
-// 4T + 6 len + 8 flen + 36 bytes, which the next record's offset leaves.
-// One record per tile keeps the static data a tile reads in one stream.
+// first node.  A record holds T + 1 u16 row starts (node i's row is entries
+// start[i] .. start[i+1] of the rows), then room for len halo ids (len = the
+// tile's row entries; the halo is never longer), the rows (len rounded up to
+// 4 u16), and flen triangle words (flen = its incidences, an upper bound of
+// its triangles), each part 16-byte aligned: at most 2T + 6 len + 8 flen +
+// 48 bytes, which the next record's offset leaves.  One record per tile
+// keeps the static data a tile reads in one stream.
 __host__ __device__ __forceinline__ int64_t tile_record(int32_t row_start, int32_t fan_start, int32_t tile, int T)
 {
-    return static_cast<int64_t>(tile) * (4 * T + 64) +
+    return static_cast<int64_t>(tile) * (2 * T + 64) +
            align16(6 * static_cast<int64_t>(row_start) + 8 * static_cast<int64_t>(fan_start));
 }
+__host__ __device__ __forceinline__ int64_t halo_at(int T) { return align16(2 * static_cast<int64_t>(T) + 2); }
 
 // One work-group per tile, in one pass: every output of tile k goes to a
 // place fixed by the row and incidence offsets of its first node, so no
@@ -178,8 +180,8 @@ __global__ __launch_bounds__(kBuildBS) void k_tile_build(TileBuildArgs a)
     // part of the record (room for len entries) until the rows are
     // rewritten below
     unsigned char* rec = a.data + tile_record(rb, fb, tile, T);
-    uint32_t* rr = reinterpret_cast<uint32_t*>(rec);
-    int32_t* halo = reinterpret_cast<int32_t*>(rec + 4 * T);
+    uint16_t* rr = reinterpret_cast<uint16_t*>(rec);
+    int32_t* halo = reinterpret_cast<int32_t*>(rec + halo_at(T));
     bool full = false;
     for (int base = 0; base < len; base += BS * U) {
         int32_t jd[U];
@@ -227,7 +229,7 @@ __global__ __launch_bounds__(kBuildBS) void k_tile_build(TileBuildArgs a)
 
     // ---- rows in local indices, and their offsets
     const int32_t len4 = (len + 3) & ~3;
-    const int64_t seg_at = align16(4 * static_cast<int64_t>(T) + 4 * static_cast<int64_t>(len));
+    const int64_t seg_at = align16(halo_at(T) + 4 * static_cast<int64_t>(len));
     uint16_t* seg = reinterpret_cast<uint16_t*>(rec + seg_at);
     for (int j = tid; j < len; j += BS) seg[j] = static_cast<uint16_t>(local(halo[j]));
     for (int j = len + tid; j < len4; j += BS) seg[j] = 0;
@@ -240,8 +242,7 @@ __global__ __launch_bounds__(kBuildBS) void k_tile_build(TileBuildArgs a)
             if (key != -1) halo[h++] = key;
         }
     }
-    for (int i = tid; i < T; i += BS)
-        rr[i] = static_cast<uint32_t>(s_rs[min(i, nown)]) | (static_cast<uint32_t>(s_rs[min(i + 1, nown)]) << 16);
+    for (int i = tid; i <= T; i += BS) rr[i] = static_cast<uint16_t>(s_rs[min(i, nown)]);
     __syncthreads();   // the entry map is rebuilt for the incidences
     for (int i = tid; i < nown; i += BS)
         for (int b = (s_fs[i] + 15) >> 4; (b << 4) < s_fs[i + 1]; ++b) own[b] = static_cast<uint16_t>(i);
@@ -404,7 +405,7 @@ size_t tile_bytes(int64_t n, int64_t nnz, int64_t ninc, int tile_nodes)
     if (tile_nodes != 256 && tile_nodes != 512) return 0;   // build_tiles takes nothing then
     const size_t nt = static_cast<size_t>(div_up(std::max<int64_t>(n, 1), tile_nodes));
     const size_t z = static_cast<size_t>(std::max<int64_t>(nnz, 1)), c = static_cast<size_t>(std::max<int64_t>(ninc, 1));
-    return Arena::piece(sizeof(TileWork) * nt) + Arena::piece(nt * (4 * tile_nodes + 64) + 6 * z + 8 * c + 16);
+    return Arena::piece(sizeof(TileWork) * nt) + Arena::piece(nt * (2 * tile_nodes + 64) + 6 * z + 8 * c + 16);
 }
 
 size_t tile_scratch_bytes() { return Arena::piece(4 * sizeof(int32_t)); }

@@ -152,7 +152,7 @@ __device__ __forceinline__ void tile_triangle(uint64_t w, const typename Real<R>
 template <typename R, int NPT, int RPRE, int KPRE>
 struct TileStage {
     typename Real<R>::V2 own[NPT];
-    uint32_t rr[NPT];        // row start | row end << 16, unpacked where used
+    uint16_t rs[NPT], re[NPT];   // row start and end of each own node
     uint64_t rw[RPRE];
     uint64_t tw[KPRE];
     int hidx;
@@ -202,7 +202,7 @@ __device__ __forceinline__ TileWork uniform_work(const TileWork& w)
     u.halo = reinterpret_cast<const int32_t*>(u64(w.halo));
     u.rows = reinterpret_cast<const uint64_t*>(u64(w.rows));
     u.tris = reinterpret_cast<const uint64_t*>(u64(w.tris));
-    u.rr = reinterpret_cast<const uint32_t*>(u64(w.rr));
+    u.rr = reinterpret_cast<const uint16_t*>(u64(w.rr));
     u.own_start = __builtin_amdgcn_readfirstlane(w.own_start);
     u.nown = __builtin_amdgcn_readfirstlane(w.nown);
     u.halo_cnt = __builtin_amdgcn_readfirstlane(w.halo_cnt);
@@ -237,12 +237,13 @@ __device__ __forceinline__ void stage_a(TileStage<R, NPT, RPRE, KPRE>& s, const 
     const int tid = threadIdx.x;
     const gptr<R> Xin = xin<R>(d, parity);
     const gptr<int32_t> halo = to_global(d.halo);
-    const gptr<uint32_t> rr = to_global(d.rr);
+    const gptr<uint16_t> rr = to_global(d.rr);
     s.hidx = halo[min(tid, max(d.halo_cnt - 1, 0))];   // meaningful for tid < halo_cnt only
 #pragma unroll
     for (int m = 0; m < NPT; ++m) {
         const int i = m * BS + tid;
-        s.rr[m] = rr[i];
+        s.rs[m] = rr[i];
+        s.re[m] = rr[i + 1];
         s.own[m] = ldxg<SOA>(Xin, d.n, d.own_start + min(i, d.nown - 1));
     }
 }
@@ -315,8 +316,8 @@ __device__ __forceinline__ void sweep_tiles(const TileSweepArgs& a)
         uint64_t tw[KPRE];
 #pragma unroll
         for (int m = 0; m < NPT; ++m) {
-            r0[m] = static_cast<int>(sg.rr[m] & 0xFFFFu);
-            r1[m] = static_cast<int>(sg.rr[m] >> 16);
+            r0[m] = sg.rs[m];
+            r1[m] = sg.re[m];
             if (m * BS + tid < nown) Xl[m * BS + tid] = sg.own[m];
         }
 #pragma unroll
