@@ -80,12 +80,19 @@ typedef enum {
 } sl_precision;
 typedef enum { SL_REORDER_NONE = 0, SL_REORDER_HILBERT = 1 } sl_reorder;
 typedef enum {
-    SL_KERNEL_AUTO = 0,  /* tile kernel for Form A when the mesh fits it, else the node kernel */
+    SL_KERNEL_AUTO = 0,  /* Form A: in sl_batch_smooth, the resident kernel for meshes of up to
+                            2048 nodes that fit it; otherwise the tile kernel when the mesh
+                            fits it, else the node kernel.  Form B: the node kernel */
     SL_KERNEL_NODE = 1,  /* one work-item per free node, neighbours gathered from HBM/L2 */
-    SL_KERNEL_TILE = 2   /* work-group per tile of free nodes staged in LDS (Form A only; at
+    SL_KERNEL_TILE = 2,  /* work-group per tile of free nodes staged in LDS (Form A only; at
                             most 16 neighbour entries and 16 incidences per node on average
                             over a tile, at most 4 distinct outside neighbours per tile node,
                             and its halo and rows must fit in LDS), else the node kernel */
+    SL_KERNEL_RESIDENT = 3  /* one work-group runs every sweep of the mesh with both coordinate
+                               buffers, rows and fans in LDS (Form A, double precision, not in
+                               a server): 32 n + 4 (n + 1) + 2 nbr_ptr[n] + 2 tri_ptr[n] bytes
+                               must fit in 159 KB, and n, nbr_ptr[n], tri_ptr[n] <= 65535;
+                               SL_EINVAL otherwise */
 } sl_kernel;
 
 typedef struct {
@@ -119,7 +126,7 @@ typedef struct {
     double setup_ms;            /* device time: validation, reorder, relabel, fan build */
     double sweep_ms;            /* device time of the sweep loop only */
     double total_ms;            /* host wall time of the whole call */
-    int32_t kernel_used;        /* SL_KERNEL_NODE or SL_KERNEL_TILE */
+    int32_t kernel_used;        /* SL_KERNEL_NODE, SL_KERNEL_TILE or SL_KERNEL_RESIDENT */
     int32_t tile_nodes;         /* free nodes per tile on the tile path, else 0 */
 } sl_report;
 
@@ -191,6 +198,8 @@ typedef struct {
     int32_t graph_used;         /* 1 if the sweep loop ran as a captured HIP graph */
     double graph_ms;            /* host wall time of capturing and instantiating the graph */
     double results_ms;          /* host wall time of un-permuting and copying out the results */
+    int32_t meshes_resident;    /* meshes run on the resident kernel (all their sweeps in one launch) */
+    int32_t reserved;
 } sl_batch_report;
 
 /*

@@ -25,7 +25,7 @@ FORMS = {"jacobi": 0, "colored": 1}
 ACCEPT = {"ge": 0, "gt": 1}
 LAYOUTS = {"aos": 0, "soa": 1}
 REORDER = {"none": 0, "hilbert": 1}
-KERNELS = {"auto": 0, "node": 1, "tile": 2}
+KERNELS = {"auto": 0, "node": 1, "tile": 2, "resident": 3}
 PRECISIONS = {"f64": 0, "f32": 1}
 
 
@@ -62,7 +62,8 @@ class BatchReport(ctypes.Structure):
     _fields_ = [("setup_ms", ctypes.c_double), ("sweep_ms", ctypes.c_double), ("total_ms", ctypes.c_double),
                 ("node_updates", ctypes.c_int64), ("tiles", ctypes.c_int64),
                 ("meshes_on_tile_path", ctypes.c_int32), ("graph_used", ctypes.c_int32),
-                ("graph_ms", ctypes.c_double), ("results_ms", ctypes.c_double)]
+                ("graph_ms", ctypes.c_double), ("results_ms", ctypes.c_double),
+                ("meshes_resident", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}

@@ -83,8 +83,11 @@ sl_status check_options(const sl_options& o)
     if (o.reorder != SL_REORDER_NONE && o.reorder != SL_REORDER_HILBERT) return fail(SL_EINVAL, "unknown reorder");
     if (o.block_size != 0 && o.block_size != 64 && o.block_size != 128 && o.block_size != 256)
         return fail(SL_EINVAL, "block_size must be 0, 64, 128 or 256");
-    if (o.kernel != SL_KERNEL_AUTO && o.kernel != SL_KERNEL_NODE && o.kernel != SL_KERNEL_TILE)
+    if (o.kernel != SL_KERNEL_AUTO && o.kernel != SL_KERNEL_NODE && o.kernel != SL_KERNEL_TILE &&
+        o.kernel != SL_KERNEL_RESIDENT)
         return fail(SL_EINVAL, "unknown kernel");
+    if (o.kernel == SL_KERNEL_RESIDENT && (o.form != SL_JACOBI || o.precision != SL_F64))
+        return fail(SL_EINVAL, "the resident kernel runs Form A in double precision only");
     if (o.tile_nodes != 0 && o.tile_nodes != 256 && o.tile_nodes != 512)
         return fail(SL_EINVAL, "tile_nodes must be 0, 256 or 512");
     if (o.tile_wg_per_cu < 0 || o.tile_wg_per_cu > 8) return fail(SL_EINVAL, "tile_wg_per_cu must be in 0..8");
@@ -116,7 +119,7 @@ sl_status prepare_mesh(const MeshInput& in, const sl_options& o, int32_t mesh_in
     if (ends[1] > 0 && !in.nbr_idx) return fail(SL_EINVAL, "null nbr_idx with nbr_ptr[n] > 0");
     if (ends[3] > 0 && !in.tri_idx) return fail(SL_EINVAL, "null tri_idx with tri_ptr[n] > 0");
     SetupArgs sa{in.coords, in.n, in.nbr_ptr, in.nbr_idx, in.tri_ptr, in.tri_idx, in.tris, in.n_tris, in.boundary,
-                 ends[1], ends[3]};
+                 ends[1], ends[3], in.auto_resident};
     return setup_mesh(sa, o, m, mesh_index, st);
 }
 
@@ -185,7 +188,7 @@ sl_status run_device(double* coords, int32_t n, const int32_t* nbr_ptr, const in
     const bool want_bits = o.flags_out && its > 0;
     const size_t n_bits = want_bits ? static_cast<size_t>(words) * its : 0;
     if ((r = cs.aux.reserve(Arena::piece(sizeof(MeshState)) + Arena::piece(sizeof(int32_t)) +
-                                (want_bits ? Arena::piece(8 * n_bits) : 0),
+                                Arena::piece(sizeof(ResidentArgs)) + (want_bits ? Arena::piece(8 * n_bits) : 0),
                             stream)) ||
         (r = cs.aux.take(&cs.state, 1)) || (r = cs.aux.take(&cs.close_count, 1)))
         return r;
@@ -217,7 +220,18 @@ sl_status run_device(double* coords, int32_t n, const int32_t* nbr_ptr, const in
     // own (the caller's may be the legacy default stream, which cannot be
     // captured) and replayed on the caller's stream.
     SL_HIP(hipEventRecord(cs.ev[2], stream));
-    const bool use_graph = !cs.bits && its >= 2 * kSweepChunk;
+    if (cs.m.resident) {
+        // every sweep in one launch
+        const ResidentArgs ra{static_cast<double*>(cs.m.X[0]), cs.m.row_ptr, cs.m.nbr, cs.m.fan_ptr, cs.m.fan,
+                              cs.m.n, cs.m.n_free, static_cast<int32_t>(cs.m.nnz_free),
+                              static_cast<int32_t>(cs.m.ninc_free), its, tol2, cs.state, cs.bits, words};
+        ResidentArgs* d_ra = nullptr;
+        if ((r = cs.aux.take(&d_ra, 1))) return r;
+        SL_HIP(hipMemcpyAsync(d_ra, &ra, sizeof(ra), hipMemcpyHostToDevice, stream));
+        const size_t lds = resident_lds_bytes(cs.m.n, cs.m.n_free, cs.m.nnz_free, cs.m.ninc_free);
+        if ((r = launch_sweep_resident(d_ra, 1, lds, o.layout, o.accept, stream))) return r;
+    }
+    const bool use_graph = !cs.m.resident && !cs.bits && its >= 2 * kSweepChunk;
     if (use_graph) {
         if ((r = take_stream(&cs.capture))) return r;
         SL_HIP(hipStreamBeginCapture(cs.capture, hipStreamCaptureModeThreadLocal));
@@ -228,7 +242,7 @@ sl_status run_device(double* coords, int32_t n, const int32_t* nbr_ptr, const in
         if (ce != hipSuccess) return fail(SL_EDEVICE, std::string("graph capture failed: ") + hipGetErrorString(ce));
         SL_HIP(hipGraphInstantiate(&cs.exec, cs.graph, nullptr, nullptr, 0));
     }
-    for (int32_t done = 0; done < its;) {
+    for (int32_t done = cs.m.resident ? its : 0; done < its;) {
         const int32_t c = std::min(kSweepChunk, its - done);
         if (use_graph && c == kSweepChunk) {
             SL_HIP(hipGraphLaunch(cs.exec, stream));
@@ -269,7 +283,7 @@ sl_status run_device(double* coords, int32_t n, const int32_t* nbr_ptr, const in
         SL_HIP(hipEventElapsedTime(&ms, cs.ev[2], cs.ev[3]));
         rep.sweep_ms = ms;
         rep.total_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
-        rep.kernel_used = cs.m.tile_nodes > 0 ? SL_KERNEL_TILE : SL_KERNEL_NODE;
+        rep.kernel_used = cs.m.resident ? SL_KERNEL_RESIDENT : cs.m.tile_nodes > 0 ? SL_KERNEL_TILE : SL_KERNEL_NODE;
         rep.tile_nodes = cs.m.tile_nodes;
         *report = rep;
     }

@@ -33,6 +33,7 @@ struct BatchState {
     TileWork* work = nullptr;
     MeshState* states = nullptr;
     int32_t* close_count = nullptr;
+    ResidentArgs* res_list = nullptr;   // the resident meshes' kernel arguments
     double* out = nullptr;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
@@ -43,6 +44,7 @@ struct BatchState {
         dfree(work, st);
         dfree(states, st);
         dfree(close_count, st);
+        dfree(res_list, st);
         dfree(out, st);
         (void)hipStreamSynchronize(st);
         for (auto s : setup_st)
@@ -57,7 +59,8 @@ struct BatchState {
 
 }  // namespace
 
-sl_status upload_and_prepare(const sl_mesh_desc& d, const sl_options& o, int32_t mesh, DevMesh& m, hipStream_t st)
+sl_status upload_and_prepare(const sl_mesh_desc& d, const sl_options& o, int32_t mesh, DevMesh& m, hipStream_t st,
+                             bool auto_resident)
 {
     if (!d.coords || !d.nbr_ptr || !d.tri_ptr || !d.boundary) return fail(SL_EINVAL, "null array argument");
     if (d.n_nodes <= 0) return fail(SL_EINVAL, "n_nodes must be >= 1");
@@ -80,6 +83,7 @@ sl_status upload_and_prepare(const sl_mesh_desc& d, const sl_options& o, int32_t
     in.ends[1] = static_cast<int32_t>(nnz);
     in.ends[2] = d.tri_ptr[0];
     in.ends[3] = static_cast<int32_t>(ninc);
+    in.auto_resident = auto_resident;
     r = prepare_mesh(in, o, mesh, m, st);
     di.release(st);
     return r;
@@ -138,7 +142,7 @@ sl_status sl_batch_smooth(const sl_mesh_desc* meshes, int32_t n_meshes, int32_t 
         for (;;) {
             const int32_t i = next.fetch_add(1);
             if (i >= n_meshes || failed.load()) break;
-            const sl_status rr = upload_and_prepare(meshes[i], o, i, bs.meshes[i], ts);
+            const sl_status rr = upload_and_prepare(meshes[i], o, i, bs.meshes[i], ts, true);
             if (rr) {
                 t_status[t] = rr;
                 t_msg[t] = "mesh " + std::to_string(i) + ": " + sl_last_error();
@@ -187,20 +191,43 @@ sl_status sl_batch_smooth(const sl_mesh_desc* meshes, int32_t n_meshes, int32_t 
         SL_HIP(hipMemcpyAsync(bs.work + off, m.work, sizeof(TileWork) * m.n_tiles, hipMemcpyDeviceToDevice, st));
         off += m.n_tiles;
     }
+    // resident meshes run all their sweeps in one launch of their own; their
+    // states start inactive, so that the per-sweep closes pass them over
     std::vector<MeshState> h0(static_cast<size_t>(n_meshes));
     const double tol2 = tol > 0.0 ? tol * tol : 0.0;
-    for (auto& s : h0) {
+    for (int32_t i = 0; i < n_meshes; ++i) {
+        MeshState& s = h0[i];
         s = MeshState{};
         s.iters = iterations;
-        s.active = iterations > 0;
+        s.active = iterations > 0 && !bs.meshes[i].resident;
         s.tol2 = tol2;
     }
     if ((r = dalloc(&bs.states, static_cast<size_t>(n_meshes), st))) return r;
     SL_HIP(hipMemcpyAsync(bs.states, h0.data(), sizeof(MeshState) * h0.size(), hipMemcpyHostToDevice, st));
-    // with every mesh on the tile path, the tile launch closes each sweep itself
+    std::vector<ResidentArgs> res;
+    size_t res_lds = 0;
+    for (int32_t i = 0; i < n_meshes; ++i) {
+        const DevMesh& m = bs.meshes[i];
+        if (!m.resident) continue;
+        res.push_back(ResidentArgs{static_cast<double*>(m.X[0]), m.row_ptr, m.nbr, m.fan_ptr, m.fan, m.n, m.n_free,
+                                   static_cast<int32_t>(m.nnz_free), static_cast<int32_t>(m.ninc_free), iterations,
+                                   tol2, bs.states + i, nullptr, 0});
+        res_lds = std::max(res_lds, resident_lds_bytes(m.n, m.n_free, m.nnz_free, m.ninc_free));
+    }
+    if (!res.empty()) {
+        if ((r = dalloc(&bs.res_list, res.size(), st))) return r;
+        SL_HIP(hipMemcpyAsync(bs.res_list, res.data(), sizeof(ResidentArgs) * res.size(), hipMemcpyHostToDevice, st));
+    }
+    // with every other mesh on the tile path, the tile launch closes each sweep itself
     const bool jacobi = o.form == SL_JACOBI;
     bool all_tiles = jacobi && total_tiles > 0;
-    for (int32_t i = 0; i < n_meshes && all_tiles; ++i) all_tiles = bs.meshes[i].tile_nodes > 0;
+    bool any_node = false;
+    for (int32_t i = 0; i < n_meshes; ++i) {
+        const DevMesh& m = bs.meshes[i];
+        if (m.resident || (jacobi && m.tile_nodes > 0)) continue;
+        all_tiles = false;
+        any_node = true;
+    }
     if (all_tiles) {
         if ((r = dalloc(&bs.close_count, 1, st))) return r;
         SL_HIP(hipMemsetAsync(bs.close_count, 0, sizeof(int32_t), st));
@@ -220,7 +247,7 @@ sl_status sl_batch_smooth(const sl_mesh_desc* meshes, int32_t n_meshes, int32_t 
             if (jacobi && total_tiles > 0) rr = launch_sweep_tiles(L, s & 1, nullptr, st);
             for (int32_t i = 0; i < n_meshes && !rr; ++i) {
                 const DevMesh& m = bs.meshes[i];
-                if (jacobi && m.tile_nodes > 0) continue;
+                if (m.resident || (jacobi && m.tile_nodes > 0)) continue;
                 rr = launch_sweep_nodes(m, s & 1, o.form, o.accept, block, bs.states + i, nullptr, st);
             }
             if (!rr && !all_tiles) rr = launch_advance(bs.states, n_meshes, st);
@@ -231,7 +258,13 @@ sl_status sl_batch_smooth(const sl_mesh_desc* meshes, int32_t n_meshes, int32_t 
     int32_t graph_used = 0;
     const auto tg0 = std::chrono::steady_clock::now();
     double graph_ms = 0.0;
-    if (iterations > 0) {
+    if (iterations > 0 && !res.empty()) {
+        SL_HIP(hipEventRecord(bs.ev[2], st));
+        if ((r = launch_sweep_resident(bs.res_list, static_cast<int32_t>(res.size()), res_lds, o.layout, o.accept,
+                                       st)))
+            return r;
+    }
+    if (iterations > 0 && ((jacobi && total_tiles > 0) || any_node)) {
         SL_HIP(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
         sl_status cr = enqueue_chunk();
         hipGraph_t g = nullptr;
@@ -242,10 +275,10 @@ sl_status sl_batch_smooth(const sl_mesh_desc* meshes, int32_t n_meshes, int32_t 
         SL_HIP(hipGraphInstantiate(&bs.exec, bs.graph, nullptr, nullptr, 0));
         graph_used = 1;
         graph_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - tg0).count();
-        SL_HIP(hipEventRecord(bs.ev[2], st));
+        if (res.empty()) SL_HIP(hipEventRecord(bs.ev[2], st));
         const int32_t replays = (iterations + chunk - 1) / chunk;
         for (int32_t k = 0; k < replays; ++k) SL_HIP(hipGraphLaunch(bs.exec, st));
-    } else {
+    } else if (iterations <= 0 || res.empty()) {
         SL_HIP(hipEventRecord(bs.ev[2], st));
     }
     SL_HIP(hipEventRecord(bs.ev[3], st));
@@ -289,7 +322,8 @@ sl_status sl_batch_smooth(const sl_mesh_desc* meshes, int32_t n_meshes, int32_t 
             std::memcpy(&rep.max_disp_sq_last, &hs[i].maxd_last, sizeof(double));
             rep.accepted_last = static_cast<int64_t>(hs[i].acc_last);
             rep.accepted_total = static_cast<int64_t>(hs[i].acc_total);
-            rep.kernel_used = (jacobi && m.tile_nodes > 0) ? SL_KERNEL_TILE : SL_KERNEL_NODE;
+            rep.kernel_used = m.resident ? SL_KERNEL_RESIDENT
+                                         : (jacobi && m.tile_nodes > 0) ? SL_KERNEL_TILE : SL_KERNEL_NODE;
             rep.tile_nodes = m.tile_nodes;
             reports[i] = rep;
         }
@@ -302,6 +336,7 @@ sl_status sl_batch_smooth(const sl_mesh_desc* meshes, int32_t n_meshes, int32_t 
         b.node_updates = updates;
         b.tiles = total_tiles;
         b.meshes_on_tile_path = on_tiles;
+        b.meshes_resident = static_cast<int32_t>(res.size());
         b.graph_used = graph_used;
         b.graph_ms = graph_ms;
         b.results_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - tr0).count();

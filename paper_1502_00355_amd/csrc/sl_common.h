@@ -199,6 +199,7 @@ struct DevMesh {
     int32_t precision = SL_F64;          // element type of X: double, or float for SL_F32
     void* X[2] = {nullptr, nullptr};     // one block of 4n elements: X[1] = X[0] + 2n;
                                          // AoS (x,y pairs) or SoA (x[n] then y[n]) inside each
+    bool resident = false;               // Form A on the resident kernel (node-path arrays built)
     // Tile path (Form A)
     int32_t tile_nodes = 0;              // 0: tile path not built
     int32_t n_tiles = 0;
@@ -222,6 +223,7 @@ struct SetupArgs {
     int32_t n_tris;
     const uint8_t* boundary;
     int64_t nnz, ninc;      // nbr_ptr[n], tri_ptr[n] (read by the caller of setup)
+    bool auto_resident;     // SL_KERNEL_AUTO may pick the resident kernel
 };
 
 // Builds the tile path for Form A (tile_nodes free nodes per tile) and
@@ -257,6 +259,9 @@ struct MeshInput {
     // read them on the host (the arrays came from host memory)
     bool ends_known = false;
     int32_t ends[4] = {0, 0, 0, 0};
+    // SL_KERNEL_AUTO may pick the resident kernel for a small Form A mesh
+    // (batches: one launch runs all sweeps of all such meshes)
+    bool auto_resident = false;
 };
 
 // Argument checks, then setup_mesh.
@@ -305,7 +310,8 @@ sl_status upload_inputs(const sl_mesh_desc& d, int64_t nnz, int64_t ninc, size_t
 
 // Uploads one caller mesh (host arrays) on `st` and prepares it; the
 // uploaded inputs are released once the device copy is built.
-sl_status upload_and_prepare(const sl_mesh_desc& d, const sl_options& o, int32_t mesh, DevMesh& m, hipStream_t st);
+sl_status upload_and_prepare(const sl_mesh_desc& d, const sl_options& o, int32_t mesh, DevMesh& m, hipStream_t st,
+                             bool auto_resident = false);
 
 // Launch shapes that sl_autotune chose for a device (zeros: none chosen).
 struct TunedShape {
@@ -355,6 +361,33 @@ struct TileLaunch {
     int32_t n_close;
 };
 sl_status launch_sweep_tiles(const TileLaunch& L, int32_t parity, uint64_t* bits, hipStream_t st);
+
+// Resident meshes (Form A, double precision): one work-group runs all the
+// sweeps of one mesh with its coordinates, rows and fans in LDS.  One entry
+// per mesh, in device memory; the launch's dynamic LDS is the largest
+// resident_lds_bytes of the list.  The mesh's state must start at s = 0;
+// the kernel leaves it as the sweep-by-sweep closes would, inactive.
+struct ResidentArgs {
+    double* X;                  // X[0] at X, X[1] at X + 2n (the mesh's layout)
+    const int32_t* row_ptr;     // [n_free + 1]
+    const int32_t* nbr;         // [nnz] device labels
+    const int32_t* fan_ptr;     // [n_free + 1]
+    const uint16_t* fan;        // [ninc]
+    int32_t n, n_free, nnz, ninc;
+    int32_t iters;              // sweeps to run at most
+    double tol2;                // > 0: stop after a sweep with max |dx|^2 < tol2
+    MeshState* state;
+    uint64_t* bits;             // nullable: sweep s's accept bits at bits + s * words
+    int64_t words;
+};
+constexpr size_t kResidentLdsLimit = 160 * 1024 - 1024;
+constexpr int32_t kResidentAutoNodes = 2048;   // SL_KERNEL_AUTO picks it up to this size
+size_t resident_lds_bytes(int64_t n, int64_t n_free, int64_t nnz, int64_t ninc);
+// Whether a mesh of n nodes and nnz, ninc CSR entries in all (bounds of its
+// free rows and fans) fits the resident kernel.
+bool resident_fits(int64_t n, int64_t nnz, int64_t ninc);
+sl_status launch_sweep_resident(const ResidentArgs* list, int32_t count, size_t lds, int32_t layout,
+                                int32_t accept, hipStream_t st);
 
 // Closes a sweep for states[0..n): counts it for the active meshes and
 // decides whether each runs the next one.

@@ -299,6 +299,10 @@ sl_status sl_server_create(const sl_server_config* cfg, const sl_options* opts, 
     o.flags_out = nullptr;
     sl_status r = check_options(o);
     if (r) return r;
+    // requests join a shared step of a few sweeps; the resident kernel runs
+    // a mesh's sweeps all at once, which this schedule has no place for
+    if (o.kernel == SL_KERNEL_RESIDENT) return fail(SL_EINVAL, "a server does not run the resident kernel");
+    if (o.kernel == SL_KERNEL_AUTO && o.form == SL_JACOBI) o.kernel = SL_KERNEL_TILE;
     // automatic launch shapes are fixed when the server starts: every
     // request of one work list has the same tile size
     o.tile_nodes = resolve_tile_nodes(o);

@@ -202,6 +202,134 @@ void launch_range(SweepArgs a, int max_deg, int requested_block, bool soa, bool 
     }
 }
 
+// ------------------------------------------------------- resident meshes --
+//
+// One work-group runs every sweep of one small mesh (Form A) without leaving
+// the launch: both coordinate buffers and the mesh's rows and fans (u16)
+// sit in LDS, a sweep reads one buffer and writes the other, and the
+// group's barrier separates sweeps.  The per-node arithmetic is that of
+// k_sweep, operation for operation; the fan's row slots index the node's row
+// in LDS instead of a column of gathered positions.  The sweep state is
+// written once, at the end, as the per-sweep closes would have left it; the
+// final positions go to buffer (sweeps run) % 2 in global memory.
+
+constexpr int kResBS = 1024;
+
+template <bool SOA, bool GT>
+__global__ __launch_bounds__(kResBS) void k_sweep_resident(const ResidentArgs* __restrict__ list)
+{
+    const ResidentArgs a = list[blockIdx.x];
+    extern __shared__ double2 res_lds[];
+    __shared__ double s_d2[kResBS / 64];
+    __shared__ unsigned long long s_acc[kResBS / 64];
+    const int n = a.n, nf = a.n_free;
+    double2* buf0 = res_lds;
+    double2* buf1 = res_lds + n;
+    uint16_t* rp = reinterpret_cast<uint16_t*>(res_lds + 2 * n);   // [nf + 1] row starts
+    uint16_t* fp = rp + (nf + 1);                                    // [nf + 1] fan starts
+    uint16_t* nb = fp + (nf + 1);                                    // [nnz] neighbours (device labels)
+    uint16_t* fn = nb + a.nnz;                                       // [ninc] fan entries
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+
+    for (int i = tid; i < n; i += kResBS) {
+        const double2 p = ld<SOA>(a.X, n, i);
+        buf0[i] = p;
+        buf1[i] = p;
+    }
+    for (int i = tid; i <= nf; i += kResBS) {
+        rp[i] = static_cast<uint16_t>(a.row_ptr[i]);
+        fp[i] = static_cast<uint16_t>(a.fan_ptr[i]);
+    }
+    for (int k = tid; k < a.nnz; k += kResBS) nb[k] = static_cast<uint16_t>(a.nbr[k]);
+    for (int k = tid; k < a.ninc; k += kResBS) fn[k] = a.fan[k];
+    __syncthreads();
+
+    int s = 0;
+    double maxd = 0.0;
+    unsigned long long acc = 0, acc_total = 0;
+    while (s < a.iters) {
+        const double2* cur = (s & 1) ? buf1 : buf0;
+        double2* nxt = (s & 1) ? buf0 : buf1;
+        double d2 = 0.0;
+        unsigned long long cnt = 0;
+        for (int i0 = 0; i0 < nf; i0 += kResBS) {
+            const int i = i0 + tid;
+            bool accepted = false;
+            if (i < nf) {
+                const int r0 = rp[i], d = rp[i + 1] - r0;
+                double sx = 0.0, sy = 0.0;
+                for (int j = 0; j < d; ++j) {
+                    const double2 p = cur[nb[r0 + j]];
+                    sx += p.x;
+                    sy += p.y;
+                }
+                const double dn = static_cast<double>(d);
+                const double cx = sx / dn, cy = sy / dn;
+                const double2 o = cur[i];
+                double qo = INFINITY, qn = INFINITY;
+                const int f1 = fp[i + 1];
+                for (int f = fp[i]; f < f1; ++f) {
+                    const uint32_t e = fn[f];
+                    const int p = static_cast<int>(e & 3u);
+                    const double2 va = cur[nb[r0 + ((e >> 2) & 127u)]];
+                    const double2 vb = cur[nb[r0 + ((e >> 9) & 127u)]];
+                    const double v = fan_quality(p, o.x, o.y, va, vb);
+                    if (v < qo) qo = v;
+                    const double w = fan_quality(p, cx, cy, va, vb);
+                    if (w < qn) qn = w;
+                }
+                accepted = GT ? (qn > qo) : (qn >= qo);
+                const double nx = accepted ? cx : o.x, ny = accepted ? cy : o.y;
+                nxt[i] = make_double2(nx, ny);
+                const double dx = nx - o.x, dy = ny - o.y;
+                const double t = dx * dx + dy * dy;
+                d2 = t > d2 ? t : d2;
+            }
+            const unsigned long long ball = __ballot(accepted);
+            cnt += __popcll(ball);
+            // i0 + 64 wv is a multiple of 64: the wave's bits are one whole word
+            if (a.bits != nullptr && lane == 0 && ball != 0ull)
+                atomicOr(reinterpret_cast<unsigned long long*>(a.bits) + s * a.words + ((i0 + wv * 64) >> 6), ball);
+        }
+        for (int off = 32; off > 0; off >>= 1) {
+            const double t = __shfl_xor(d2, off);
+            d2 = t > d2 ? t : d2;
+        }
+        if (lane == 0) {
+            s_d2[wv] = d2;
+            s_acc[wv] = cnt;
+        }
+        __syncthreads();   // also: every read of cur and write of nxt of this sweep is done
+        double m = s_d2[0];
+        unsigned long long c = s_acc[0];
+        for (int q = 1; q < kResBS / 64; ++q) {
+            m = s_d2[q] > m ? s_d2[q] : m;
+            c += s_acc[q];
+        }
+        __syncthreads();   // s_d2 and s_acc are rewritten by the next sweep
+        ++s;
+        maxd = m;
+        acc = c;
+        acc_total += c;
+        if (a.tol2 > 0.0 && m < a.tol2) break;
+    }
+
+    const double2* fin = (s & 1) ? buf1 : buf0;
+    double* out = a.X + (s & 1) * 2 * static_cast<int64_t>(n);
+    for (int i = tid; i < nf; i += kResBS) st<SOA>(out, n, i, fin[i].x, fin[i].y);
+    if (tid == 0) {
+        MeshState ms = *a.state;
+        ms.s += s;
+        ms.maxd_last = s > 0 ? static_cast<unsigned long long>(__double_as_longlong(maxd)) : ms.maxd_last;
+        ms.acc_last = s > 0 ? acc : ms.acc_last;
+        ms.acc_total += acc_total;
+        ms.maxd_cur = 0;
+        ms.acc_cur = 0;
+        ms.active = 0;
+        *a.state = ms;
+    }
+}
+
 // Closes a sweep (one work-item per mesh).
 __global__ void k_advance(MeshState* __restrict__ st, int32_t n)
 {
@@ -210,6 +338,43 @@ __global__ void k_advance(MeshState* __restrict__ st, int32_t n)
 }
 
 }  // namespace
+
+size_t resident_lds_bytes(int64_t n, int64_t n_free, int64_t nnz, int64_t ninc)
+{
+    return static_cast<size_t>(32 * n + 2 * (2 * (n_free + 1) + nnz + ninc));
+}
+
+bool resident_fits(int64_t n, int64_t nnz, int64_t ninc)
+{
+    // u16 labels and offsets; the free-node counts are bounded by n
+    return n >= 1 && n <= 65535 && nnz <= 65535 && ninc <= 65535 &&
+           resident_lds_bytes(n, n, nnz, ninc) <= kResidentLdsLimit;
+}
+
+sl_status launch_sweep_resident(const ResidentArgs* list, int32_t count, size_t lds, int32_t layout,
+                                int32_t accept, hipStream_t st)
+{
+    if (count <= 0) return SL_OK;
+    if (lds > kResidentLdsLimit) return fail(SL_EINVAL, "resident mesh does not fit in LDS");
+    const bool soa = layout == SL_SOA, gt = accept == SL_ACCEPT_GT;
+    const void* fn = soa ? (gt ? reinterpret_cast<const void*>(&k_sweep_resident<true, true>)
+                               : reinterpret_cast<const void*>(&k_sweep_resident<true, false>))
+                         : (gt ? reinterpret_cast<const void*>(&k_sweep_resident<false, true>)
+                               : reinterpret_cast<const void*>(&k_sweep_resident<false, false>));
+    if (lds > 64 * 1024) {
+        (void)hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds));
+        (void)hipGetLastError();
+    }
+    if (soa) {
+        if (gt) k_sweep_resident<true, true><<<count, kResBS, lds, st>>>(list);
+        else k_sweep_resident<true, false><<<count, kResBS, lds, st>>>(list);
+    } else {
+        if (gt) k_sweep_resident<false, true><<<count, kResBS, lds, st>>>(list);
+        else k_sweep_resident<false, false><<<count, kResBS, lds, st>>>(list);
+    }
+    SL_HIP(hipGetLastError());
+    return SL_OK;
+}
 
 sl_status launch_advance(MeshState* states, int32_t n, hipStream_t st)
 {

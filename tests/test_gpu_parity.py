@@ -187,7 +187,7 @@ def test_autotune_then_automatic_shape():
         assert ndiff == 0 and rep.tile_nodes == t.tile_nodes
         outs, reps, br = sl.batch_smooth(ms, 5)
         for m, X, r in zip(ms, outs, reps):
-            assert r.tile_nodes == t.tile_nodes
+            assert r.tile_nodes == t.tile_nodes or r.kernel_used == sl.KERNELS["resident"]
             assert (X == oracle.smooth(m, 5).coords).all()
         tc = sl.autotune(ms, form="colored")
         note("autotune colored %s" % tc.as_dict())
@@ -420,7 +420,10 @@ def test_batch_equals_single_and_oracle():
     ms.append(_many_stars(600, 20, 5))                # tiles too dense: node path
     ms.append(meshgen.make_annulus(12, 40, seed=9))
     outs, reps, br = sl.batch_smooth(ms, 9)
-    assert br.graph_used == 1 and br.meshes_on_tile_path == len(ms) - 1
+    # the smallest meshes run on the resident kernel, the star on the node kernel
+    assert br.graph_used == 1 and br.meshes_resident >= 3
+    assert br.meshes_on_tile_path + br.meshes_resident == len(ms) - 1
+    assert sum(r.kernel_used == sl.KERNELS["resident"] for r in reps) == br.meshes_resident
     for m, X, rep in zip(ms, outs, reps):
         ref = oracle.smooth(m, 9)
         assert rep.iterations_run == 9 and rep.accepted_total == int(ref.accepted.sum())
@@ -432,16 +435,97 @@ def test_batch_equals_single_and_oracle():
 def test_batch_tolerance_and_forms():
     ms = [meshgen.make_grid(n, "random", 0.4, 300 + n) for n in (20, 28, 45)]
     ref = [oracle.smooth(m, 400, tol=3e-4) for m in ms]
-    outs, reps, br = sl.batch_smooth(ms, 400, tol=3e-4)
-    for m, X, rep, r in zip(ms, outs, reps, ref):
-        assert rep.iterations_run == r.iterations_run < 400
-        assert (X == r.coords).all()
+    for kernel in ("auto", "tile"):
+        outs, reps, br = sl.batch_smooth(ms, 400, tol=3e-4, kernel=kernel)
+        assert br.meshes_resident == (len(ms) if kernel == "auto" else 0)
+        for m, X, rep, r in zip(ms, outs, reps, ref):
+            assert rep.iterations_run == r.iterations_run < 400
+            assert rep.accepted_total == int(r.accepted.sum())
+            assert (X == r.coords).all()
     outs, reps, br = sl.batch_smooth(ms, 5, form="colored")
     for m, X in zip(ms, outs):
         assert (X == oracle.smooth(m, 5, form="colored").coords).all()
     outs, reps, br = sl.batch_smooth(ms, 6, accept="gt", layout="soa")
     for m, X in zip(ms, outs):
         assert (X == oracle.smooth(m, 6, accept_gt=True).coords).all()
+
+
+RESIDENT_MESHES = {
+    "grid24": lambda: meshgen.make_grid(24, "random", 0.4, 601),               # one node per work-item
+    "grid45_unionjack": lambda: meshgen.make_grid(45, "unionjack", 0.3, 602),  # 2025 nodes: two per work-item
+    "annulus12x40": lambda: meshgen.make_annulus(12, 40, seed=603),
+    "grid33_permuted": lambda: meshgen.permute_mesh(meshgen.make_grid(33, "random", 0.4, 604), 5),
+    "delaunay1000": lambda: meshgen.make_delaunay(1000, 11),
+    "star17": lambda: _ring_star(17, 17),
+}
+
+
+@pytest.mark.parametrize("name", sorted(RESIDENT_MESHES))
+@pytest.mark.parametrize("layout,accept", [("aos", "ge"), ("soa", "gt")])
+def test_resident_kernel_parity(name, layout, accept):
+    """Every sweep of a small mesh in one launch, with the mesh in LDS: the
+    flags of every sweep, the coordinates and the counts equal the oracle's,
+    and the coordinates equal the tile kernel's."""
+    m = RESIDENT_MESHES[name]()
+    X, rep, ref, nd = assert_parity(m, 12, accept=accept, layout=layout, kernel="resident")
+    assert nd == 0 and rep.kernel_used == sl.KERNELS["resident"] and rep.tile_nodes == 0
+    Xt, rt, _ = run_gpu(m, 12, accept=accept, layout=layout, kernel="tile")
+    assert rt.kernel_used == sl.KERNELS["tile"] and (X == Xt).all()
+
+
+def test_resident_tolerance_zero_sweeps_and_fixed_nodes():
+    m = meshgen.make_grid(30, "random", 0.4, 605)
+    X, rep, ref, nd = assert_parity(m, 400, tol=3e-4, kernel="resident")
+    assert nd == 0 and rep.iterations_run < 400
+    X, rep, F = run_gpu(m, 0, kernel="resident")
+    assert (X == m.coords).all() and rep.iterations_run == 0 and rep.accepted_total == 0
+    b = m.copy()
+    b.boundary[:] = 1
+    X, rep, F = run_gpu(b, 4, kernel="resident")
+    assert (X == m.coords).all() and rep.iterations_run == 4 and rep.accepted_total == 0 and (F == 0).all()
+    X, rep, F = run_gpu(b, 50, tol=1e-3, kernel="resident")
+    assert rep.iterations_run == 1 and rep.max_disp_sq_last == 0.0
+
+
+@pytest.mark.parametrize("exp2", [-1040, -1020, -520, 498])
+def test_resident_extreme_coordinate_scales(exp2):
+    m = meshgen.make_grid(30, "random", 0.4, 606)
+    m.coords = m.coords * (2.0 ** exp2) + (2.0 ** exp2) * 0.25
+    m.name = "grid30_scaled_2^%d" % exp2
+    X, rep, ref, nd = assert_parity(m, 5, kernel="resident")
+    assert nd == 0
+
+
+def test_resident_limits():
+    big = meshgen.make_grid(64, "random", 0.4, 607)          # 4096 nodes: both buffers alone take 128 KB
+    with pytest.raises(sl.SmartlapError) as e:
+        run_gpu(big, 2, kernel="resident")
+    assert e.value.status == sl.SL_EINVAL and "resident" in str(e.value)
+    small = meshgen.make_grid(20, "random", 0.4, 608)
+    for opts in ({"form": "colored"}, {"precision": "f32"}):
+        with pytest.raises(sl.SmartlapError) as e:
+            run_gpu(small, 2, kernel="resident", **opts)
+        assert e.value.status == sl.SL_EINVAL
+    with pytest.raises(sl.SmartlapError) as e:
+        sl.Server(kernel="resident")
+    assert e.value.status == sl.SL_EINVAL
+    # a batch member too large for it is refused by name
+    with pytest.raises(sl.SmartlapError) as e:
+        sl.batch_smooth([small, big], 2, kernel="resident")
+    assert e.value.status == sl.SL_EINVAL and "mesh 1" in str(e.value)
+
+
+def test_batch_of_resident_meshes_only():
+    """A batch whose meshes all run on the resident kernel: no sweep graph,
+    one launch."""
+    ms = [meshgen.make_grid(n, "random", 0.35, 620 + n) for n in (5, 12, 24, 31, 45)]
+    outs, reps, br = sl.batch_smooth(ms, 11)
+    assert br.meshes_resident == len(ms) and br.graph_used == 0 and br.tiles == 0
+    for m, X, rep in zip(ms, outs, reps):
+        ref = oracle.smooth(m, 11)
+        assert rep.iterations_run == 11 and rep.accepted_total == int(ref.accepted.sum())
+        assert rep.accepted_last == ref.accepted[-1] and rep.max_disp_sq_last == ref.disp[-1]
+        assert (X == ref.coords).all(), m.name
 
 
 def test_batch_of_one_with_tolerance():
