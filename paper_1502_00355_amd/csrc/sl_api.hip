@@ -119,7 +119,7 @@ sl_status prepare_mesh(const MeshInput& in, const sl_options& o, int32_t mesh_in
     if (ends[1] > 0 && !in.nbr_idx) return fail(SL_EINVAL, "null nbr_idx with nbr_ptr[n] > 0");
     if (ends[3] > 0 && !in.tri_idx) return fail(SL_EINVAL, "null tri_idx with tri_ptr[n] > 0");
     SetupArgs sa{in.coords, in.n, in.nbr_ptr, in.nbr_idx, in.tri_ptr, in.tri_idx, in.tris, in.n_tris, in.boundary,
-                 ends[1], ends[3], in.auto_resident};
+                 ends[1], ends[3]};
     return setup_mesh(sa, o, m, mesh_index, st);
 }
 

@@ -59,8 +59,7 @@ struct BatchState {
 
 }  // namespace
 
-sl_status upload_and_prepare(const sl_mesh_desc& d, const sl_options& o, int32_t mesh, DevMesh& m, hipStream_t st,
-                             bool auto_resident)
+sl_status upload_and_prepare(const sl_mesh_desc& d, const sl_options& o, int32_t mesh, DevMesh& m, hipStream_t st)
 {
     if (!d.coords || !d.nbr_ptr || !d.tri_ptr || !d.boundary) return fail(SL_EINVAL, "null array argument");
     if (d.n_nodes <= 0) return fail(SL_EINVAL, "n_nodes must be >= 1");
@@ -83,7 +82,6 @@ sl_status upload_and_prepare(const sl_mesh_desc& d, const sl_options& o, int32_t
     in.ends[1] = static_cast<int32_t>(nnz);
     in.ends[2] = d.tri_ptr[0];
     in.ends[3] = static_cast<int32_t>(ninc);
-    in.auto_resident = auto_resident;
     r = prepare_mesh(in, o, mesh, m, st);
     di.release(st);
     return r;
@@ -142,7 +140,7 @@ sl_status sl_batch_smooth(const sl_mesh_desc* meshes, int32_t n_meshes, int32_t 
         for (;;) {
             const int32_t i = next.fetch_add(1);
             if (i >= n_meshes || failed.load()) break;
-            const sl_status rr = upload_and_prepare(meshes[i], o, i, bs.meshes[i], ts, true);
+            const sl_status rr = upload_and_prepare(meshes[i], o, i, bs.meshes[i], ts);
             if (rr) {
                 t_status[t] = rr;
                 t_msg[t] = "mesh " + std::to_string(i) + ": " + sl_last_error();

@@ -223,7 +223,6 @@ struct SetupArgs {
     int32_t n_tris;
     const uint8_t* boundary;
     int64_t nnz, ninc;      // nbr_ptr[n], tri_ptr[n] (read by the caller of setup)
-    bool auto_resident;     // SL_KERNEL_AUTO may pick the resident kernel
 };
 
 // Builds the tile path for Form A (tile_nodes free nodes per tile) and
@@ -259,9 +258,6 @@ struct MeshInput {
     // read them on the host (the arrays came from host memory)
     bool ends_known = false;
     int32_t ends[4] = {0, 0, 0, 0};
-    // SL_KERNEL_AUTO may pick the resident kernel for a small Form A mesh
-    // (batches: one launch runs all sweeps of all such meshes)
-    bool auto_resident = false;
 };
 
 // Argument checks, then setup_mesh.
@@ -310,8 +306,7 @@ sl_status upload_inputs(const sl_mesh_desc& d, int64_t nnz, int64_t ninc, size_t
 
 // Uploads one caller mesh (host arrays) on `st` and prepares it; the
 // uploaded inputs are released once the device copy is built.
-sl_status upload_and_prepare(const sl_mesh_desc& d, const sl_options& o, int32_t mesh, DevMesh& m, hipStream_t st,
-                             bool auto_resident = false);
+sl_status upload_and_prepare(const sl_mesh_desc& d, const sl_options& o, int32_t mesh, DevMesh& m, hipStream_t st);
 
 // Launch shapes that sl_autotune chose for a device (zeros: none chosen).
 struct TunedShape {
@@ -381,7 +376,6 @@ struct ResidentArgs {
     int64_t words;
 };
 constexpr size_t kResidentLdsLimit = 160 * 1024 - 1024;
-constexpr int32_t kResidentAutoNodes = 2048;   // SL_KERNEL_AUTO picks it up to this size
 size_t resident_lds_bytes(int64_t n, int64_t n_free, int64_t nnz, int64_t ninc);
 // Whether a mesh of n nodes and nnz, ninc CSR entries in all (bounds of its
 // free rows and fans) fits the resident kernel.

@@ -770,13 +770,11 @@ sl_status setup_mesh(const SetupArgs& a, const sl_options& o, DevMesh& m, int32_
     m.layout = o.layout;
     m.precision = o.precision;
     sl_status r;
-    // the resident kernel, asked for or (automatically) for small meshes,
-    // decided from bounds known before validation
-    const bool res_fit = resident_fits(n, a.nnz, a.ninc);
-    if (o.kernel == SL_KERNEL_RESIDENT && !res_fit)
+    // the resident kernel when asked for, checked against bounds known
+    // before validation (check_options has restricted it to Form A, f64)
+    if (o.kernel == SL_KERNEL_RESIDENT && !resident_fits(n, a.nnz, a.ninc))
         return fail(SL_EINVAL, "mesh too large for the resident kernel");
-    m.resident = o.form == SL_JACOBI && o.precision == SL_F64 &&
-                 (o.kernel == SL_KERNEL_RESIDENT || (o.kernel == SL_KERNEL_AUTO && a.auto_resident && res_fit && n <= kResidentAutoNodes));
+    m.resident = o.kernel == SL_KERNEL_RESIDENT;
     const bool want_tiles = o.form == SL_JACOBI && o.kernel != SL_KERNEL_NODE && !m.resident;
     const int T = resolve_tile_nodes(o);
     const size_t rb = o.precision == SL_F32 ? 4 : 8;

@@ -214,6 +214,8 @@ void launch_range(SweepArgs a, int max_deg, int requested_block, bool soa, bool 
 // final positions go to buffer (sweeps run) % 2 in global memory.
 
 constexpr int kResBS = 1024;
+constexpr int kResRow = 8;   // row entries read together
+constexpr int kResFan = 4;   // fan entries read together
 
 template <bool SOA, bool GT>
 __global__ __launch_bounds__(kResBS) void k_sweep_resident(const ResidentArgs* __restrict__ list)
@@ -256,27 +258,55 @@ __global__ __launch_bounds__(kResBS) void k_sweep_resident(const ResidentArgs* _
             const int i = i0 + tid;
             bool accepted = false;
             if (i < nf) {
-                const int r0 = rp[i], d = rp[i + 1] - r0;
+                // the row and the fan are read a few entries at a time, with
+                // clamped indices, so that their dependent LDS loads overlap;
+                // sums and minima still run in stored order
+                const int r0 = rp[i], d = rp[i + 1] - r0;   // d >= 1: a free node has neighbours
                 double sx = 0.0, sy = 0.0;
-                for (int j = 0; j < d; ++j) {
-                    const double2 p = cur[nb[r0 + j]];
-                    sx += p.x;
-                    sy += p.y;
+                for (int j0 = 0; j0 < d; j0 += kResRow) {
+                    int lab[kResRow];
+#pragma unroll
+                    for (int u = 0; u < kResRow; ++u) lab[u] = nb[r0 + min(j0 + u, d - 1)];
+                    double2 p[kResRow];
+#pragma unroll
+                    for (int u = 0; u < kResRow; ++u) p[u] = cur[lab[u]];
+#pragma unroll
+                    for (int u = 0; u < kResRow; ++u)
+                        if (j0 + u < d) {
+                            sx += p[u].x;
+                            sy += p[u].y;
+                        }
                 }
                 const double dn = static_cast<double>(d);
                 const double cx = sx / dn, cy = sy / dn;
                 const double2 o = cur[i];
                 double qo = INFINITY, qn = INFINITY;
                 const int f1 = fp[i + 1];
-                for (int f = fp[i]; f < f1; ++f) {
-                    const uint32_t e = fn[f];
-                    const int p = static_cast<int>(e & 3u);
-                    const double2 va = cur[nb[r0 + ((e >> 2) & 127u)]];
-                    const double2 vb = cur[nb[r0 + ((e >> 9) & 127u)]];
-                    const double v = fan_quality(p, o.x, o.y, va, vb);
-                    if (v < qo) qo = v;
-                    const double w = fan_quality(p, cx, cy, va, vb);
-                    if (w < qn) qn = w;
+                for (int f0 = fp[i]; f0 < f1; f0 += kResFan) {
+                    uint32_t e[kResFan];
+#pragma unroll
+                    for (int u = 0; u < kResFan; ++u) e[u] = fn[min(f0 + u, f1 - 1)];
+                    int la[kResFan], lb[kResFan];
+#pragma unroll
+                    for (int u = 0; u < kResFan; ++u) {
+                        la[u] = nb[r0 + ((e[u] >> 2) & 127u)];
+                        lb[u] = nb[r0 + ((e[u] >> 9) & 127u)];
+                    }
+                    double2 va[kResFan], vb[kResFan];
+#pragma unroll
+                    for (int u = 0; u < kResFan; ++u) {
+                        va[u] = cur[la[u]];
+                        vb[u] = cur[lb[u]];
+                    }
+#pragma unroll
+                    for (int u = 0; u < kResFan; ++u) {
+                        if (f0 + u >= f1) break;
+                        const int p = static_cast<int>(e[u] & 3u);
+                        const double v = fan_quality(p, o.x, o.y, va[u], vb[u]);
+                        if (v < qo) qo = v;
+                        const double w = fan_quality(p, cx, cy, va[u], vb[u]);
+                        if (w < qn) qn = w;
+                    }
                 }
                 accepted = GT ? (qn > qo) : (qn >= qo);
                 const double nx = accepted ? cx : o.x, ny = accepted ? cy : o.y;

@@ -187,7 +187,7 @@ def test_autotune_then_automatic_shape():
         assert ndiff == 0 and rep.tile_nodes == t.tile_nodes
         outs, reps, br = sl.batch_smooth(ms, 5)
         for m, X, r in zip(ms, outs, reps):
-            assert r.tile_nodes == t.tile_nodes or r.kernel_used == sl.KERNELS["resident"]
+            assert r.tile_nodes == t.tile_nodes
             assert (X == oracle.smooth(m, 5).coords).all()
         tc = sl.autotune(ms, form="colored")
         note("autotune colored %s" % tc.as_dict())
@@ -420,10 +420,7 @@ def test_batch_equals_single_and_oracle():
     ms.append(_many_stars(600, 20, 5))                # tiles too dense: node path
     ms.append(meshgen.make_annulus(12, 40, seed=9))
     outs, reps, br = sl.batch_smooth(ms, 9)
-    # the smallest meshes run on the resident kernel, the star on the node kernel
-    assert br.graph_used == 1 and br.meshes_resident >= 3
-    assert br.meshes_on_tile_path + br.meshes_resident == len(ms) - 1
-    assert sum(r.kernel_used == sl.KERNELS["resident"] for r in reps) == br.meshes_resident
+    assert br.graph_used == 1 and br.meshes_on_tile_path == len(ms) - 1 and br.meshes_resident == 0
     for m, X, rep in zip(ms, outs, reps):
         ref = oracle.smooth(m, 9)
         assert rep.iterations_run == 9 and rep.accepted_total == int(ref.accepted.sum())
@@ -435,9 +432,9 @@ def test_batch_equals_single_and_oracle():
 def test_batch_tolerance_and_forms():
     ms = [meshgen.make_grid(n, "random", 0.4, 300 + n) for n in (20, 28, 45)]
     ref = [oracle.smooth(m, 400, tol=3e-4) for m in ms]
-    for kernel in ("auto", "tile"):
+    for kernel in ("auto", "resident"):
         outs, reps, br = sl.batch_smooth(ms, 400, tol=3e-4, kernel=kernel)
-        assert br.meshes_resident == (len(ms) if kernel == "auto" else 0)
+        assert br.meshes_resident == (len(ms) if kernel == "resident" else 0)
         for m, X, rep, r in zip(ms, outs, reps, ref):
             assert rep.iterations_run == r.iterations_run < 400
             assert rep.accepted_total == int(r.accepted.sum())
@@ -519,8 +516,9 @@ def test_batch_of_resident_meshes_only():
     """A batch whose meshes all run on the resident kernel: no sweep graph,
     one launch."""
     ms = [meshgen.make_grid(n, "random", 0.35, 620 + n) for n in (5, 12, 24, 31, 45)]
-    outs, reps, br = sl.batch_smooth(ms, 11)
+    outs, reps, br = sl.batch_smooth(ms, 11, kernel="resident")
     assert br.meshes_resident == len(ms) and br.graph_used == 0 and br.tiles == 0
+    assert all(r.kernel_used == sl.KERNELS["resident"] for r in reps)
     for m, X, rep in zip(ms, outs, reps):
         ref = oracle.smooth(m, 11)
         assert rep.iterations_run == 11 and rep.accepted_total == int(ref.accepted.sum())
