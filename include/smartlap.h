@@ -254,8 +254,10 @@ SL_API sl_status sl_build_adjacency_device(const int32_t* tris, int32_t n_tris, 
  * and work-groups per compute unit -- changes only speed, never results.
  * sl_autotune times sweeps of every candidate shape on the caller's meshes
  * (a deterministic sample of them, taken at a stride in index order, of at
- * most about 8M nodes) and keeps the fastest as the automatic choice of the
- * current device for the rest of the process: later calls whose options
+ * most about 8M nodes), twice each, interleaved, and keeps the fastest as
+ * the automatic choice of the current device -- or the default shape (512
+ * nodes, 4 work-groups per CU; block size 256) when it is within 1% of the
+ * fastest -- for the rest of the process: later calls whose options
  * leave tile_nodes / tile_wg_per_cu at 0 use it.  Form B (coloured) runs on
  * the node kernel; for it the node-kernel work-group size is tuned and used
  * where block_size is 0.  Meshes are read, not written.  The caller's opts

@@ -181,8 +181,10 @@ def test_autotune_then_automatic_shape():
         cands = list(t.candidates[: t.n_candidates])
         best = min(c.ns_per_update for c in cands)
         assert all(c.ns_per_update > 0 for c in cands)
-        assert any(c.tile_nodes == t.tile_nodes and c.wg_per_cu == t.tile_wg_per_cu and c.ns_per_update == best
-                   for c in cands)
+        chosen = [c for c in cands if c.tile_nodes == t.tile_nodes and c.wg_per_cu == t.tile_wg_per_cu]
+        # the fastest shape, or the default one (512 nodes, 4 per CU) within 1% of it
+        assert len(chosen) == 1 and (chosen[0].ns_per_update == best or (
+            (t.tile_nodes, t.tile_wg_per_cu) == (512, 4) and chosen[0].ns_per_update <= best * 1.01))
         X, rep, ref, ndiff = assert_parity(ms[3], 5)
         assert ndiff == 0 and rep.tile_nodes == t.tile_nodes
         outs, reps, br = sl.batch_smooth(ms, 5)
