@@ -131,9 +131,9 @@ constexpr int32_t kSweepChunk = 32;   // even
 struct CallState {
     hipStream_t st = nullptr;
     DevMesh m;
-    Arena aux;                          // the sweep state, the tile launches' counter, the flag words
+    Arena aux;                          // the sweep state, the tile launches' counters, the flag words
     MeshState* state = nullptr;
-    int32_t* close_count = nullptr;
+    int32_t* sched = nullptr;
     uint64_t* bits = nullptr;
     hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
     hipGraph_t graph = nullptr;
@@ -187,13 +187,13 @@ sl_status run_device(double* coords, int32_t n, const int32_t* nbr_ptr, const in
     h0.tol2 = tol2;
     const bool want_bits = o.flags_out && its > 0;
     const size_t n_bits = want_bits ? static_cast<size_t>(words) * its : 0;
-    if ((r = cs.aux.reserve(Arena::piece(sizeof(MeshState)) + Arena::piece(sizeof(int32_t)) +
+    if ((r = cs.aux.reserve(Arena::piece(sizeof(MeshState)) + Arena::piece(sizeof(int32_t) * kTileSchedInts) +
                                 Arena::piece(sizeof(ResidentArgs)) + (want_bits ? Arena::piece(8 * n_bits) : 0),
                             stream)) ||
-        (r = cs.aux.take(&cs.state, 1)) || (r = cs.aux.take(&cs.close_count, 1)))
+        (r = cs.aux.take(&cs.state, 1)) || (r = cs.aux.take(&cs.sched, kTileSchedInts)))
         return r;
     SL_HIP(hipMemcpyAsync(cs.state, &h0, sizeof(MeshState), hipMemcpyHostToDevice, stream));
-    SL_HIP(hipMemsetAsync(cs.close_count, 0, sizeof(int32_t), stream));
+    SL_HIP(hipMemsetAsync(cs.sched, 0, sizeof(int32_t) * kTileSchedInts, stream));
     if (want_bits) {
         if ((r = cs.aux.take(&cs.bits, n_bits))) return r;
         SL_HIP(hipMemsetAsync(cs.bits, 0, sizeof(uint64_t) * n_bits, stream));
@@ -203,7 +203,7 @@ sl_status run_device(double* coords, int32_t n, const int32_t* nbr_ptr, const in
     // with a tolerance, a launch on a converged mesh returns at once; a tile
     // launch closes its own sweep
     const TileLaunch L{cs.m.work, cs.m.n_tiles, cs.m.tile_nodes, cs.m.halo_max, cs.m.rows_max, o.layout, o.accept,
-                       cs.state, resolve_wg_per_cu(o), tol2 > 0.0 ? 1 : 0, o.precision, cs.close_count, 1};
+                       cs.state, resolve_wg_per_cu(o), tol2 > 0.0 ? 1 : 0, o.precision, cs.sched, 1};
     auto enqueue = [&](int32_t s, hipStream_t on) -> sl_status {
         uint64_t* bits = cs.bits ? cs.bits + static_cast<int64_t>(s) * words : nullptr;
         if (tiles) return launch_sweep_tiles(L, s & 1, bits, on);

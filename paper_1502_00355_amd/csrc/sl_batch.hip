@@ -32,7 +32,7 @@ struct BatchState {
     std::vector<DevMesh> meshes;
     TileWork* work = nullptr;
     MeshState* states = nullptr;
-    int32_t* close_count = nullptr;
+    int32_t* sched = nullptr;           // the tile launches' counters
     ResidentArgs* res_list = nullptr;   // the resident meshes' kernel arguments
     double* out = nullptr;
     hipGraph_t graph = nullptr;
@@ -43,7 +43,7 @@ struct BatchState {
         for (auto& m : meshes) devmesh_free(m, st);
         dfree(work, st);
         dfree(states, st);
-        dfree(close_count, st);
+        dfree(sched, st);
         dfree(res_list, st);
         dfree(out, st);
         (void)hipStreamSynchronize(st);
@@ -226,17 +226,15 @@ sl_status sl_batch_smooth(const sl_mesh_desc* meshes, int32_t n_meshes, int32_t 
         all_tiles = false;
         any_node = true;
     }
-    if (all_tiles) {
-        if ((r = dalloc(&bs.close_count, 1, st))) return r;
-        SL_HIP(hipMemsetAsync(bs.close_count, 0, sizeof(int32_t), st));
-    }
+    if ((r = dalloc(&bs.sched, kTileSchedInts, st))) return r;
+    SL_HIP(hipMemsetAsync(bs.sched, 0, sizeof(int32_t) * kTileSchedInts, st));
     SL_HIP(hipStreamSynchronize(st));
     const double setup_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
 
     // ---- the sweep loop, captured once and replayed
     const TileLaunch L{bs.work, static_cast<int32_t>(total_tiles), T, halo_cap, rows_cap, o.layout, o.accept,
                        bs.states, resolve_wg_per_cu(o), (n_meshes == 1 && tol2 > 0.0) ? 1 : 0, o.precision,
-                       bs.close_count, n_meshes};
+                       bs.sched, all_tiles ? n_meshes : 0};
     const int32_t block = resolve_block_size(o);
     const int32_t chunk = iterations <= 128 ? iterations + (iterations & 1) : 64;   // even: parity repeats
     auto enqueue_chunk = [&]() -> sl_status {

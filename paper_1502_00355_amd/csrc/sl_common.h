@@ -349,12 +349,15 @@ struct TileLaunch {
     int32_t wg_per_cu;          // 0: as many as fit, at most 4
     int32_t exit_if_inactive;   // 1: every tile is of one mesh; a launch on it returns at once once it stops
     int32_t precision;          // SL_F64 or SL_F32: every mesh of the list has it
-    // nullable: a zeroed counter; the launch's last work-group then closes
-    // the sweep of states[0..n_close) itself (and zeroes the counter again),
-    // in place of a launch_advance after it
-    int32_t* close_count;
+    // kTileSchedInts counters, zeroed before the first launch on them; each
+    // launch leaves them zeroed (launches sharing them must not overlap)
+    int32_t* sched;
+    // > 0: the launch's last work-group closes the sweep of
+    // states[0..n_close), in place of a launch_advance after it
     int32_t n_close;
 };
+constexpr int kSchedStride = 32;                    // one 128-byte line per counter
+constexpr int kTileSchedInts = 9 * kSchedStride;
 sl_status launch_sweep_tiles(const TileLaunch& L, int32_t parity, uint64_t* bits, hipStream_t st);
 
 // Resident meshes (Form A, double precision): one work-group runs all the

@@ -58,7 +58,7 @@ struct HipExec {
     int device = 0;
     hipStream_t st_compute = nullptr, st_setup = nullptr;
     MeshState* states = nullptr;        // [max_active]
-    int32_t* close_count = nullptr;     // counter of the tile launches that close their own sweep
+    int32_t* sched = nullptr;           // the tile launches' counters
     MeshState* h_states = nullptr;      // [max_active], pinned: read-back after each step
     MeshState* h_join = nullptr;        // [max_active], pinned: the state a joining request starts from
     TileWork* work = nullptr;
@@ -82,8 +82,8 @@ struct HipExec {
         SL_HIP(hipStreamCreateWithFlags(&st_compute, hipStreamNonBlocking));
         SL_HIP(hipStreamCreateWithFlags(&st_setup, hipStreamNonBlocking));
         if ((r = dalloc(&states, static_cast<size_t>(max_active), st_compute))) return r;
-        if ((r = dalloc(&close_count, 1, st_compute))) return r;
-        SL_HIP(hipMemsetAsync(close_count, 0, sizeof(int32_t), st_compute));
+        if ((r = dalloc(&sched, kTileSchedInts, st_compute))) return r;
+        SL_HIP(hipMemsetAsync(sched, 0, sizeof(int32_t) * kTileSchedInts, st_compute));
         SL_HIP(hipHostMalloc(reinterpret_cast<void**>(&h_states), sizeof(MeshState) * max_active,
                              hipHostMallocDefault));
         SL_HIP(hipHostMalloc(reinterpret_cast<void**>(&h_join), sizeof(MeshState) * max_active,
@@ -99,7 +99,7 @@ struct HipExec {
     {
         dfree(work, st_compute);
         dfree(states, st_compute);
-        dfree(close_count, st_compute);
+        dfree(sched, st_compute);
         dfree(out, st_compute);
         for (hipStream_t st : {st_compute, st_setup}) {
             if (!st) continue;
@@ -195,7 +195,7 @@ struct HipExec {
         bool all_tiles = jacobi && n_work > 0;
         for (Req* q : in_step) all_tiles = all_tiles && q->x.mesh.tile_nodes > 0;
         const TileLaunch L{work,       n_work, T, hcap, rcap, opts.layout, opts.accept, states, wg_per_cu, 0,
-                           opts.precision, all_tiles ? close_count : nullptr, max_active};
+                           opts.precision, sched, all_tiles ? max_active : 0};
         for (int32_t k = 0; k < sweeps_per_step && !r; ++k) {
             if (jacobi && n_work > 0) r = launch_sweep_tiles(L, parity, nullptr, st_compute);
             for (Req* q : in_step) {

@@ -99,8 +99,8 @@ struct TileSweepArgs {
     int32_t exit_if_inactive;  // all tiles are of one mesh: return at once if it has stopped
     MeshState* states;
     uint64_t* bits;            // nullable: accept bits of this sweep (single mesh)
-    int32_t* close_count;      // nullable: the last work-group closes the sweep of states[0..n_close)
-    int32_t n_close;
+    int32_t* sched;            // [kTileSchedInts]: groups done, then one tile counter per XCD, kSchedStride apart
+    int32_t n_close;           // the last work-group closes the sweep of states[0..n_close)
 };
 
 // Old quality of one triangle and the new quality for each own vertex,
@@ -280,6 +280,17 @@ __device__ __forceinline__ void sweep_tiles(const TileSweepArgs& a)
     const int t_end = min(t_begin + a.tiles_per_xcd, a.n_work);
     int it = t_begin + static_cast<int>(blockIdx.x >> 3);
     if (it >= t_end) return;
+    // A group's first two tiles are fixed (its slot, then one slot-row
+    // further); the rest of the XCD's range is dealt one tile at a time from
+    // the XCD's counter.  The SIMDs issue the oldest waves first, so the
+    // groups dispatched first on a CU run faster; with fixed shares they
+    // finished up to 1.6x earlier than the last, leaving the CU part-idle.
+    // Each counter has a 128-byte line of its own: on one shared line the
+    // device-scope atomics of all XCDs queued behind each other.
+    int32_t* const deal = a.sched + kSchedStride * (1 + xcd);
+    const int t_dealt = t_begin + 2 * nw;
+    __shared__ int s_deal;
+    int nxt = it + nw < t_end ? it + nw : -1;
 
     extern __shared__ double2 lds[];
     V2* Xl = reinterpret_cast<V2*>(lds);                    // [T + halo_cap]
@@ -301,7 +312,7 @@ __device__ __forceinline__ void sweep_tiles(const TileSweepArgs& a)
     // prefetches are unconditional (past the last tile they re-load it) so
     // that no branch forces them to complete early
     TileWork dcur = uniform_work(load_work(a.work, it));
-    TileWork dnext = load_work(a.work, it + nw < t_end ? it + nw : it);
+    TileWork dnext = load_work(a.work, nxt >= 0 ? nxt : it);
     int act_cur = a.states[dcur.mesh].active;
     if (a.exit_if_inactive && act_cur == 0) return;
     TileStage<R, NPT, RPRE, KPRE> sg;
@@ -335,8 +346,9 @@ __device__ __forceinline__ void sweep_tiles(const TileSweepArgs& a)
             for (int j = RPRE * BS + tid; j < dcur.row_words; j += BS) rows64[j] = rws[j];
         }
         __syncthreads();
-        const int next = it + nw;
-        const bool has_next = next < t_end;
+        const bool has_next = nxt >= 0;
+        // the tile after next, read after two more barriers
+        if (tid == 0 && has_next) s_deal = t_dealt + atomicAdd(deal, 1);
         dnext = uniform_work(dnext);
         const int act_next = a.states[dnext.mesh].active;
         stage_a<T, BS, SOA>(sg, dnext, parity);
@@ -383,7 +395,12 @@ __device__ __forceinline__ void sweep_tiles(const TileSweepArgs& a)
             for (int r = KPRE * BS + tid; r < dcur.tri_cnt; r += BS) tile_triangle<T, R>(tris[r], Xl, cand, qo, qn);
         }
         __syncthreads();
-        const TileWork dnext2 = load_work(a.work, next + nw < t_end ? next + nw : (has_next ? next : it));
+        int nxt2 = -1;
+        if (has_next) {
+            const int g = s_deal;
+            nxt2 = g < t_end ? g : -1;
+        }
+        const TileWork dnext2 = load_work(a.work, nxt2 >= 0 ? nxt2 : (has_next ? nxt : it));
 
         // accept and write; the displacement maximum and the accepted count
         // accumulate per work-item over consecutive tiles of one mesh and are
@@ -447,7 +464,8 @@ __device__ __forceinline__ void sweep_tiles(const TileSweepArgs& a)
             run_acc = 0;
         }
         if (!has_next) break;
-        it = next;
+        it = nxt;
+        nxt = nxt2;
         dcur = dnext;
         dnext = dnext2;
         act_cur = act_next;
@@ -456,7 +474,7 @@ __device__ __forceinline__ void sweep_tiles(const TileSweepArgs& a)
 }
 
 // The last work-group of a launch to finish closes the sweep of states[0..n)
-// and zeroes the counter for the next launch.  A group's folds into the
+// and zeroes the launch's counters for the next launch.  A group's folds into the
 // sweep state are device-scope atomics made by its first work-item; the
 // work-group-scope release waits until they have completed, so they are
 // performed before the group's count.  The closing group reads the folds
@@ -464,8 +482,9 @@ __device__ __forceinline__ void sweep_tiles(const TileSweepArgs& a)
 // device-scope release or acquire is needed: those would write back or
 // invalidate the XCD's L2, once per work-group.
 template <int BS>
-__device__ __forceinline__ void close_launch(int32_t* count, MeshState* states, int32_t n)
+__device__ __forceinline__ void close_launch(int32_t* sched, MeshState* states, int32_t n)
 {
+    int32_t* const count = sched;
     __shared__ int s_last;
     __syncthreads();   // every work-item of the group is done with its tiles
     if (threadIdx.x == 0) {
@@ -476,14 +495,15 @@ __device__ __forceinline__ void close_launch(int32_t* count, MeshState* states, 
     __syncthreads();
     if (!s_last) return;
     for (int i = threadIdx.x; i < n; i += BS) close_state(states + i);
-    if (threadIdx.x == 0) __hip_atomic_store(count, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (threadIdx.x < 9)
+        __hip_atomic_store(sched + kSchedStride * threadIdx.x, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 template <int T, int BS, bool SOA, bool GT, typename R>
 __global__ __launch_bounds__(BS) void k_sweep_tile(TileSweepArgs a)
 {
     sweep_tiles<T, BS, SOA, GT, R>(a);
-    if (a.close_count) close_launch<BS>(a.close_count, a.states, a.n_close);
+    close_launch<BS>(a.sched, a.states, a.n_close);
 }
 
 constexpr int kTileBS = 256;
@@ -536,7 +556,8 @@ int tile_grid(int n_work, int tile_nodes, int halo_cap, int rows_cap, int wg_per
 
 sl_status launch_sweep_tiles(const TileLaunch& L, int32_t parity, uint64_t* bits, hipStream_t st)
 {
-    if (L.n_work <= 0) return L.close_count ? launch_advance(L.states, L.n_close, st) : SL_OK;
+    if (L.n_work <= 0) return L.n_close > 0 ? launch_advance(L.states, L.n_close, st) : SL_OK;
+    if (!L.sched) return fail(SL_EINVAL, "tile launch without its counters");
     TileSweepArgs a{};
     a.work = L.work;
     a.n_work = L.n_work;
@@ -547,7 +568,7 @@ sl_status launch_sweep_tiles(const TileLaunch& L, int32_t parity, uint64_t* bits
     a.exit_if_inactive = L.exit_if_inactive;
     a.states = L.states;
     a.bits = bits;
-    a.close_count = L.close_count;
+    a.sched = L.sched;
     a.n_close = L.n_close;
     const size_t lds = tile_lds_bytes(L.tile_nodes, L.halo_cap, L.rows_cap, L.precision);
     const int grid = tile_grid(L.n_work, L.tile_nodes, L.halo_cap, L.rows_cap, L.wg_per_cu, L.precision);

@@ -33,14 +33,14 @@ struct TunePass {
     std::vector<DevMesh> meshes;
     TileWork* work = nullptr;
     MeshState* states = nullptr;
-    int32_t* close_count = nullptr;   // tile launches close their own sweeps
+    int32_t* sched = nullptr;   // the tile launches' counters; they close their own sweeps
     hipEvent_t ev[2] = {nullptr, nullptr};
     ~TunePass()
     {
         for (auto& m : meshes) devmesh_free(m, st);
         dfree(work, st);
         dfree(states, st);
-        dfree(close_count, st);
+        dfree(sched, st);
         (void)hipStreamSynchronize(st);
         for (auto& e : ev)
             if (e) (void)hipEventDestroy(e);
@@ -69,9 +69,9 @@ sl_status setup_pass(TunePass& p, const sl_mesh_desc* meshes, const std::vector<
         s.active = 1;
     }
     sl_status r = dalloc(&p.states, h.size(), p.st);
-    if (r || (r = dalloc(&p.close_count, 1, p.st))) return r;
+    if (r || (r = dalloc(&p.sched, kTileSchedInts, p.st))) return r;
     SL_HIP(hipMemcpyAsync(p.states, h.data(), sizeof(MeshState) * h.size(), hipMemcpyHostToDevice, p.st));
-    SL_HIP(hipMemsetAsync(p.close_count, 0, sizeof(int32_t), p.st));
+    SL_HIP(hipMemsetAsync(p.sched, 0, sizeof(int32_t) * kTileSchedInts, p.st));
     for (auto& e : p.ev) SL_HIP(hipEventCreate(&e));
     return SL_OK;
 }
@@ -137,7 +137,7 @@ sl_status tune_tiles(const sl_mesh_desc* meshes, const std::vector<int32_t>& sam
             for (size_t k = 0; k < shapes.size(); ++k) {
                 const int32_t w = shapes[k];
                 const TileLaunch L{p.work, static_cast<int32_t>(tiles), T, hcap, rcap, o.layout, o.accept, p.states,
-                                   w, 0, o.precision, p.close_count, static_cast<int32_t>(p.meshes.size())};
+                                   w, 0, o.precision, p.sched, static_cast<int32_t>(p.meshes.size())};
                 float ms = 0.f;
                 r = time_sweeps(p, 0, [&](int32_t parity) { return launch_sweep_tiles(L, parity, nullptr, st); },
                                 &ms);
