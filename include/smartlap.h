@@ -106,8 +106,9 @@ typedef struct {
                               * sl_autotune chose on this device, else 512), or 256 or 512;
                               * results do not depend on it */
     int32_t tile_wg_per_cu;  /* tile-kernel work-groups per compute unit: 0 = automatic (the
-                              * value sl_autotune chose, else as many as fit, at most 4), or
-                              * 1..8, capped by what fits in LDS; results do not depend on it */
+                              * value sl_autotune chose, else as many as fit, at most 4; at
+                              * most 3 on launches of fewer than 16384 tiles), or 1..8, capped
+                              * by what fits in LDS; results do not depend on it */
     int32_t precision;       /* sl_precision */
     /* Optional accept flags, nullable.  Size iterations * ((n_nodes + 7) / 8)
      * bytes; sweep k occupies bytes [k*((n+7)/8), (k+1)*((n+7)/8)); bit (i % 8)

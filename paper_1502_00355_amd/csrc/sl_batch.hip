@@ -107,6 +107,7 @@ sl_status sl_batch_smooth(const sl_mesh_desc* meshes, int32_t n_meshes, int32_t 
     if (r) return r;
     // automatic launch shapes are fixed once for the whole batch: every
     // mesh of one work list has the same tile size
+    const int32_t wg_auto = o.tile_wg_per_cu == 0 ? 1 : 0;
     o.tile_nodes = resolve_tile_nodes(o);
     o.tile_wg_per_cu = resolve_wg_per_cu(o);
     o.block_size = resolve_block_size(o);
@@ -234,7 +235,7 @@ sl_status sl_batch_smooth(const sl_mesh_desc* meshes, int32_t n_meshes, int32_t 
     // ---- the sweep loop, captured once and replayed
     const TileLaunch L{bs.work, static_cast<int32_t>(total_tiles), T, halo_cap, rows_cap, o.layout, o.accept,
                        bs.states, resolve_wg_per_cu(o), (n_meshes == 1 && tol2 > 0.0) ? 1 : 0, o.precision,
-                       bs.sched, all_tiles ? n_meshes : 0};
+                       bs.sched, all_tiles ? n_meshes : 0, wg_auto};
     const int32_t block = resolve_block_size(o);
     const int32_t chunk = iterations <= 128 ? iterations + (iterations & 1) : 64;   // even: parity repeats
     auto enqueue_chunk = [&]() -> sl_status {

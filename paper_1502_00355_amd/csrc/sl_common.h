@@ -355,7 +355,11 @@ struct TileLaunch {
     // > 0: the launch's last work-group closes the sweep of
     // states[0..n_close), in place of a launch_advance after it
     int32_t n_close;
+    // 1: wg_per_cu is the automatic value (tuned, or 0 for the default),
+    // which launches of fewer than kSmallLaunchTiles tiles cap at 3
+    int32_t wg_auto;
 };
+constexpr int kSmallLaunchTiles = 16384;
 constexpr int kSchedStride = 32;                    // one 128-byte line per counter
 constexpr int kTileSchedInts = 9 * kSchedStride;
 sl_status launch_sweep_tiles(const TileLaunch& L, int32_t parity, uint64_t* bits, hipStream_t st);
@@ -391,7 +395,7 @@ sl_status launch_sweep_resident(const ResidentArgs* list, int32_t count, size_t 
 sl_status launch_advance(MeshState* states, int32_t n, hipStream_t st);
 
 // Work-group count of a tile launch (persistent work-groups, XCD-aware).
-int tile_grid(int n_work, int tile_nodes, int halo_cap, int rows_cap, int wg_per_cu, int32_t precision);
+int tile_grid(int n_work, int tile_nodes, int halo_cap, int rows_cap, int wg_per_cu, int32_t precision, bool wg_auto);
 
 // Exclusive scan of n int32 values; out[n] receives the total (out has n+1).
 // Temporaries come from `scratch` when given (and are given back before

@@ -68,6 +68,7 @@ struct HipExec {
     int32_t parity = 0;
     int32_t n_work = 0, T = 0, hcap = 0, rcap = 0;
     int32_t wg_per_cu = 0, block = 0;
+    int32_t wg_auto = 0;                // wg_per_cu came from the automatic choice
     bool thread_bound = false;
 
     sl_status init(const sl_server_config& cfg, const sl_options& o)
@@ -195,7 +196,7 @@ struct HipExec {
         bool all_tiles = jacobi && n_work > 0;
         for (Req* q : in_step) all_tiles = all_tiles && q->x.mesh.tile_nodes > 0;
         const TileLaunch L{work,       n_work, T, hcap, rcap, opts.layout, opts.accept, states, wg_per_cu, 0,
-                           opts.precision, sched, all_tiles ? max_active : 0};
+                           opts.precision, sched, all_tiles ? max_active : 0, wg_auto};
         for (int32_t k = 0; k < sweeps_per_step && !r; ++k) {
             if (jacobi && n_work > 0) r = launch_sweep_tiles(L, parity, nullptr, st_compute);
             for (Req* q : in_step) {
@@ -305,11 +306,13 @@ sl_status sl_server_create(const sl_server_config* cfg, const sl_options* opts, 
     if (o.kernel == SL_KERNEL_AUTO && o.form == SL_JACOBI) o.kernel = SL_KERNEL_TILE;
     // automatic launch shapes are fixed when the server starts: every
     // request of one work list has the same tile size
+    const int32_t wg_auto = o.tile_wg_per_cu == 0 ? 1 : 0;
     o.tile_nodes = resolve_tile_nodes(o);
     o.tile_wg_per_cu = resolve_wg_per_cu(o);
     o.block_size = resolve_block_size(o);
     keep_pool_warm();
     auto S = std::make_unique<sl_server>();
+    S->exec.wg_auto = wg_auto;
     if ((r = S->exec.init(c, o))) {
         const std::string msg = sl_last_error();
         S->exec.destroy();
