@@ -258,7 +258,8 @@ def run_converge(args, sl, torch):
 def run_paper(args, sl, torch):
     """Meshes like the paper's (Sec. 4, Tables 6-9): Delaunay meshes of
     1K-100K uniformly random points, 100 sweeps of Form A (AoS and SoA) and
-    Form B, GPU against the oracle on one host thread.  GPU time is the whole
+    Form B (and, on meshes small enough, Form A on the resident kernel),
+    GPU against the oracle on one host thread.  GPU time is the whole
     smooth_mesh call (host arrays in and out) and, separately, the sweep
     loop; the paper used FP32 and does not state its sweep counts, so its
     numbers are context only."""
@@ -268,7 +269,10 @@ def run_paper(args, sl, torch):
     for n in (1000, 5000, 10000, 50000, 100000):
         m = meshgen.make_delaunay(n, 11)
         row = {"points": n, "free_nodes": m.n_interior, "triangles": m.n_tris}
-        for label, opts in (("A_aos", {}), ("A_soa", {"layout": "soa"}), ("B_aos", {"form": "colored"})):
+        variants = [("A_aos", {}), ("A_soa", {"layout": "soa"}), ("B_aos", {"form": "colored"})]
+        if m.n_nodes <= 2048:        # the resident kernel (opt-in) holds meshes of about this size
+            variants.append(("A_resident", {"kernel": "resident"}))
+        for label, opts in variants:
             best = None
             for _ in range(3):
                 t = time.perf_counter()

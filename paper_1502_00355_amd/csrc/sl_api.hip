@@ -261,15 +261,14 @@ sl_status run_device(double* coords, int32_t n, const int32_t* nbr_ptr, const in
     }
     SL_HIP(hipEventRecord(cs.ev[3], stream));
 
+    // the result buffer and the sweeps run are read on the device: one wait
+    if ((r = unpermute_coords(cs.m, 0, coords, stream, o.form == SL_JACOBI ? cs.state : nullptr))) return r;
+    if (o.flags_out && its > 0)
+        if ((r = unpermute_flags(cs.m, cs.bits, its, cs.state, o.flags_out, stream))) return r;
     MeshState hs{};
     SL_HIP(hipMemcpyAsync(&hs, cs.state, sizeof(MeshState), hipMemcpyDeviceToHost, stream));
     SL_HIP(hipStreamSynchronize(stream));
     const int32_t runs = hs.s;
-    const int src = (o.form == SL_JACOBI) ? (runs & 1) : 0;
-    if ((r = unpermute_coords(cs.m, src, coords, stream))) return r;
-    if (o.flags_out && its > 0)
-        if ((r = unpermute_flags(cs.m, cs.bits, its, runs, o.flags_out, stream))) return r;
-    SL_HIP(hipStreamSynchronize(stream));
 
     if (report) {
         sl_report rep{};

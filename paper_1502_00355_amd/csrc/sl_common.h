@@ -322,12 +322,16 @@ int32_t resolve_tile_nodes(const sl_options& o);
 int32_t resolve_wg_per_cu(const sl_options& o);
 int32_t resolve_block_size(const sl_options& o);
 
-// Writes the positions of buffer `src` back to the caller's layout and order.
-sl_status unpermute_coords(const DevMesh& m, int src, double* coords_out, hipStream_t st);
+// Writes the positions of buffer `src` -- or, when `runs` is given, of
+// buffer (runs->s % 2), read on the device -- back to the caller's layout
+// and order.
+sl_status unpermute_coords(const DevMesh& m, int src, double* coords_out, hipStream_t st,
+                           const MeshState* runs = nullptr);
 
 // Unpermutes per-sweep accept bits (device order, 64-bit words) into the
-// caller's byte layout; sweeps >= iterations_run are zeroed.
-sl_status unpermute_flags(const DevMesh& m, const uint64_t* bits, int32_t iterations, int32_t iterations_run,
+// caller's byte layout; sweeps >= state->s (the sweeps run, read on the
+// device) are zeroed.
+sl_status unpermute_flags(const DevMesh& m, const uint64_t* bits, int32_t iterations, const MeshState* state,
                           uint8_t* flags_out, hipStream_t st);
 
 // Queues one Jacobi or coloured sweep of a single mesh on the node path

@@ -623,12 +623,16 @@ __global__ __launch_bounds__(kBS) void k_init_coords(const double* __restrict__ 
     }
 }
 
+// Buffer src = X[src], or X[sweeps run % 2] when `runs` is given (Form A,
+// read on the device so that the host need not wait for the sweep loop).
 template <typename R>
-__global__ __launch_bounds__(kBS) void k_unpermute(const R* __restrict__ X, const int32_t* __restrict__ perm,
-                                                   int32_t n, int soa, double* __restrict__ out)
+__global__ __launch_bounds__(kBS) void k_unpermute(const R* __restrict__ X0, int src, const MeshState* __restrict__ runs,
+                                                   const int32_t* __restrict__ perm, int32_t n, int soa,
+                                                   double* __restrict__ out)
 {
     const int64_t k = static_cast<int64_t>(blockIdx.x) * kBS + threadIdx.x;
     if (k >= n) return;
+    const R* X = X0 + 2 * static_cast<int64_t>(n) * (runs ? (runs->s & 1) : src);
     const int64_t o = perm[k];
     const R x = soa ? X[k] : X[2 * k], y = soa ? X[n + k] : X[2 * k + 1];
     *reinterpret_cast<double2*>(out + 2 * o) = make_double2(static_cast<double>(x), static_cast<double>(y));
@@ -636,12 +640,13 @@ __global__ __launch_bounds__(kBS) void k_unpermute(const R* __restrict__ X, cons
 
 __global__ __launch_bounds__(kBS) void k_unpermute_flags(const uint64_t* __restrict__ bits, int64_t words,
                                                          const int32_t* __restrict__ new_of_old, int32_t n,
-                                                         int32_t n_free, int32_t iterations, int32_t runs,
-                                                         uint8_t* __restrict__ out)
+                                                         int32_t n_free, int32_t iterations,
+                                                         const MeshState* __restrict__ state, uint8_t* __restrict__ out)
 {
     const int64_t nbytes = (static_cast<int64_t>(n) + 7) / 8;
     const int64_t g = static_cast<int64_t>(blockIdx.x) * kBS + threadIdx.x;
     if (g >= nbytes * iterations) return;
+    const int32_t runs = state->s;
     const int64_t s = g / nbytes, B = g % nbytes;
     uint32_t byte = 0;
     if (s < runs) {
@@ -914,25 +919,25 @@ sl_status setup_mesh(const SetupArgs& a, const sl_options& o, DevMesh& m, int32_
     return SL_OK;
 }
 
-sl_status unpermute_coords(const DevMesh& m, int src, double* coords_out, hipStream_t st)
+sl_status unpermute_coords(const DevMesh& m, int src, double* coords_out, hipStream_t st, const MeshState* runs)
 {
     if (m.precision == SL_F32)
-        k_unpermute<float><<<div_up(m.n, kBS), kBS, 0, st>>>(static_cast<const float*>(m.X[src]), m.perm, m.n,
-                                                              m.layout == SL_SOA, coords_out);
+        k_unpermute<float><<<div_up(m.n, kBS), kBS, 0, st>>>(static_cast<const float*>(m.X[0]), src, runs, m.perm,
+                                                              m.n, m.layout == SL_SOA, coords_out);
     else
-        k_unpermute<double><<<div_up(m.n, kBS), kBS, 0, st>>>(static_cast<const double*>(m.X[src]), m.perm, m.n,
-                                                               m.layout == SL_SOA, coords_out);
+        k_unpermute<double><<<div_up(m.n, kBS), kBS, 0, st>>>(static_cast<const double*>(m.X[0]), src, runs, m.perm,
+                                                               m.n, m.layout == SL_SOA, coords_out);
     SL_HIP(hipGetLastError());
     return SL_OK;
 }
 
-sl_status unpermute_flags(const DevMesh& m, const uint64_t* bits, int32_t iterations, int32_t runs, uint8_t* out,
-                          hipStream_t st)
+sl_status unpermute_flags(const DevMesh& m, const uint64_t* bits, int32_t iterations, const MeshState* state,
+                          uint8_t* out, hipStream_t st)
 {
     const int64_t words = (static_cast<int64_t>(m.n_free) + 63) / 64;
     const int64_t total = (static_cast<int64_t>(m.n) + 7) / 8 * iterations;
     if (total == 0) return SL_OK;
-    k_unpermute_flags<<<div_up(total, kBS), kBS, 0, st>>>(bits, words, m.new_of_old, m.n, m.n_free, iterations, runs,
+    k_unpermute_flags<<<div_up(total, kBS), kBS, 0, st>>>(bits, words, m.new_of_old, m.n, m.n_free, iterations, state,
                                                           out);
     SL_HIP(hipGetLastError());
     return SL_OK;
