@@ -475,8 +475,8 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU only: this build runs the smoothing path on a single MI355X; "
-              "run with --gpus 1", file=sys.stderr)
+        print("bench.py measures one GPU only: the smoothing path runs on a single MI355X (the multi-GPU "
+              "split is a design, not built); run with --gpus 1", file=sys.stderr)
         sys.exit(2)
 
     import torch
