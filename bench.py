@@ -271,7 +271,7 @@ def run_paper(args, sl, torch):
         row = {"points": n, "free_nodes": m.n_interior, "triangles": m.n_tris}
         variants = [("A_aos", {}), ("A_soa", {"layout": "soa"}), ("B_aos", {"form": "colored"})]
         if m.n_nodes <= 2048:        # the resident kernel (opt-in) holds meshes of about this size
-            variants.append(("A_resident", {"kernel": "resident"}))
+            variants += [("A_resident", {"kernel": "resident"}), ("B_resident", {"form": "colored", "kernel": "resident"})]
         for label, opts in variants:
             best = None
             for _ in range(3):

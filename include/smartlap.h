@@ -80,19 +80,22 @@ typedef enum {
 } sl_precision;
 typedef enum { SL_REORDER_NONE = 0, SL_REORDER_HILBERT = 1 } sl_reorder;
 typedef enum {
-    SL_KERNEL_AUTO = 0,  /* tile kernel for Form A when the mesh fits it, else the node kernel */
+    SL_KERNEL_AUTO = 0,  /* Form A: the tile kernel when the mesh fits it, else the node kernel.
+                            Form B: the resident kernel when the mesh fits it (in a server:
+                            never), else the node kernel */
     SL_KERNEL_NODE = 1,  /* one work-item per free node, neighbours gathered from HBM/L2 */
     SL_KERNEL_TILE = 2,  /* work-group per tile of free nodes staged in LDS (Form A only; at
                             most 16 neighbour entries and 16 incidences per node on average
                             over a tile, at most 4 distinct outside neighbours per tile node,
                             and its halo and rows must fit in LDS), else the node kernel */
     SL_KERNEL_RESIDENT = 3  /* one work-group runs every sweep of the mesh in one launch, with
-                               both coordinate buffers, rows and fans in LDS (Form A, double
-                               precision, not in a server): 32 n + 4 (n + 1) + 2 nbr_ptr[n] +
-                               2 tri_ptr[n] bytes must fit in 159 KB, and n, nbr_ptr[n],
-                               tri_ptr[n] <= 65535; SL_EINVAL otherwise.  Never chosen
-                               automatically: one compute unit outpaces the tile kernel only on
-                               meshes of a few hundred nodes */
+                               the coordinates, rows and fans in LDS (double precision, not in a
+                               server): Form A keeps both buffers, Form B one, updated class by
+                               class.  (32 or 16) n + 4 (n + 1) + 2 nbr_ptr[n] + 2 tri_ptr[n]
+                               bytes must fit in 159 KB, n, nbr_ptr[n], tri_ptr[n] <= 65535 and
+                               Form B has at most 32 colour classes; SL_EINVAL otherwise.  For
+                               Form A one compute unit outpaces the tile kernel only on meshes
+                               of a few hundred nodes, so it is never chosen automatically */
 } sl_kernel;
 
 typedef struct {

@@ -86,8 +86,8 @@ sl_status check_options(const sl_options& o)
     if (o.kernel != SL_KERNEL_AUTO && o.kernel != SL_KERNEL_NODE && o.kernel != SL_KERNEL_TILE &&
         o.kernel != SL_KERNEL_RESIDENT)
         return fail(SL_EINVAL, "unknown kernel");
-    if (o.kernel == SL_KERNEL_RESIDENT && (o.form != SL_JACOBI || o.precision != SL_F64))
-        return fail(SL_EINVAL, "the resident kernel runs Form A in double precision only");
+    if (o.kernel == SL_KERNEL_RESIDENT && o.precision != SL_F64)
+        return fail(SL_EINVAL, "the resident kernel runs in double precision only");
     if (o.tile_nodes != 0 && o.tile_nodes != 256 && o.tile_nodes != 512)
         return fail(SL_EINVAL, "tile_nodes must be 0, 256 or 512");
     if (o.tile_wg_per_cu < 0 || o.tile_wg_per_cu > 8) return fail(SL_EINVAL, "tile_wg_per_cu must be in 0..8");
@@ -223,13 +223,15 @@ sl_status run_device(double* coords, int32_t n, const int32_t* nbr_ptr, const in
     SL_HIP(hipEventRecord(cs.ev[2], stream));
     if (cs.m.resident) {
         // every sweep in one launch
-        const ResidentArgs ra{static_cast<double*>(cs.m.X[0]), cs.m.row_ptr, cs.m.nbr, cs.m.fan_ptr, cs.m.fan,
-                              cs.m.n, cs.m.n_free, static_cast<int32_t>(cs.m.nnz_free),
-                              static_cast<int32_t>(cs.m.ninc_free), its, tol2, cs.state, cs.bits, words};
+        const bool in_place = o.form == SL_INPLACE_COLORED;
+        ResidentArgs ra{static_cast<double*>(cs.m.X[0]), cs.m.row_ptr, cs.m.nbr, cs.m.fan_ptr, cs.m.fan,
+                        cs.m.n, cs.m.n_free, static_cast<int32_t>(cs.m.nnz_free),
+                        static_cast<int32_t>(cs.m.ninc_free), its, tol2, cs.state, cs.bits, words};
+        if ((r = resident_classes(cs.m, in_place, ra))) return r;
         ResidentArgs* d_ra = nullptr;
         if ((r = cs.aux.take(&d_ra, 1))) return r;
         SL_HIP(hipMemcpyAsync(d_ra, &ra, sizeof(ra), hipMemcpyHostToDevice, stream));
-        const size_t lds = resident_lds_bytes(cs.m.n, cs.m.n_free, cs.m.nnz_free, cs.m.ninc_free);
+        const size_t lds = resident_lds_bytes(cs.m.n, cs.m.n_free, cs.m.nnz_free, cs.m.ninc_free, in_place);
         if ((r = launch_sweep_resident(d_ra, 1, lds, o.layout, o.accept, stream))) return r;
     }
     const bool use_graph = !cs.m.resident && !cs.bits && its >= 2 * kSweepChunk;

@@ -208,10 +208,13 @@ sl_status sl_batch_smooth(const sl_mesh_desc* meshes, int32_t n_meshes, int32_t 
     for (int32_t i = 0; i < n_meshes; ++i) {
         const DevMesh& m = bs.meshes[i];
         if (!m.resident) continue;
-        res.push_back(ResidentArgs{static_cast<double*>(m.X[0]), m.row_ptr, m.nbr, m.fan_ptr, m.fan, m.n, m.n_free,
-                                   static_cast<int32_t>(m.nnz_free), static_cast<int32_t>(m.ninc_free), iterations,
-                                   tol2, bs.states + i, nullptr, 0});
-        res_lds = std::max(res_lds, resident_lds_bytes(m.n, m.n_free, m.nnz_free, m.ninc_free));
+        const bool in_place = o.form == SL_INPLACE_COLORED;
+        ResidentArgs ra{static_cast<double*>(m.X[0]), m.row_ptr, m.nbr, m.fan_ptr, m.fan, m.n, m.n_free,
+                        static_cast<int32_t>(m.nnz_free), static_cast<int32_t>(m.ninc_free), iterations,
+                        tol2, bs.states + i, nullptr, 0};
+        if ((r = resident_classes(m, in_place, ra))) return fail(r, "mesh " + std::to_string(i) + ": " + sl_last_error());
+        res.push_back(ra);
+        res_lds = std::max(res_lds, resident_lds_bytes(m.n, m.n_free, m.nnz_free, m.ninc_free, in_place));
     }
     if (!res.empty()) {
         if ((r = dalloc(&bs.res_list, res.size(), st))) return r;

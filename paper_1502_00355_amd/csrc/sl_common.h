@@ -373,6 +373,7 @@ sl_status launch_sweep_tiles(const TileLaunch& L, int32_t parity, uint64_t* bits
 // per mesh, in device memory; the launch's dynamic LDS is the largest
 // resident_lds_bytes of the list.  The mesh's state must start at s = 0;
 // the kernel leaves it as the sweep-by-sweep closes would, inactive.
+constexpr int kResidentClasses = 32;
 struct ResidentArgs {
     double* X;                  // X[0] at X, X[1] at X + 2n (the mesh's layout)
     const int32_t* row_ptr;     // [n_free + 1]
@@ -385,12 +386,18 @@ struct ResidentArgs {
     MeshState* state;
     uint64_t* bits;             // nullable: sweep s's accept bits at bits + s * words
     int64_t words;
+    int32_t in_place;           // 1: Form B, one buffer, the colour classes below in order
+    int32_t n_classes;
+    int32_t class_start[kResidentClasses + 1];   // class c: device labels [class_start[c], class_start[c+1])
 };
 constexpr size_t kResidentLdsLimit = 160 * 1024 - 1024;
-size_t resident_lds_bytes(int64_t n, int64_t n_free, int64_t nnz, int64_t ninc);
+size_t resident_lds_bytes(int64_t n, int64_t n_free, int64_t nnz, int64_t ninc, bool in_place);
 // Whether a mesh of n nodes and nnz, ninc CSR entries in all (bounds of its
-// free rows and fans) fits the resident kernel.
-bool resident_fits(int64_t n, int64_t nnz, int64_t ninc);
+// free rows and fans) fits the resident kernel (Form B keeps one buffer).
+bool resident_fits(int64_t n, int64_t nnz, int64_t ninc, bool in_place);
+// Fills the Form B part of a (the colour classes of m); SL_EINVAL when m
+// has more than kResidentClasses classes.
+sl_status resident_classes(const DevMesh& m, bool in_place, ResidentArgs& a);
 sl_status launch_sweep_resident(const ResidentArgs* list, int32_t count, size_t lds, int32_t layout,
                                 int32_t accept, hipStream_t st);
 

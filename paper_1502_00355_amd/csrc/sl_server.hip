@@ -303,7 +303,7 @@ sl_status sl_server_create(const sl_server_config* cfg, const sl_options* opts, 
     // requests join a shared step of a few sweeps; the resident kernel runs
     // a mesh's sweeps all at once, which this schedule has no place for
     if (o.kernel == SL_KERNEL_RESIDENT) return fail(SL_EINVAL, "a server does not run the resident kernel");
-    if (o.kernel == SL_KERNEL_AUTO && o.form == SL_JACOBI) o.kernel = SL_KERNEL_TILE;
+    if (o.kernel == SL_KERNEL_AUTO) o.kernel = o.form == SL_JACOBI ? SL_KERNEL_TILE : SL_KERNEL_NODE;
     // automatic launch shapes are fixed when the server starts: every
     // request of one work list has the same tile size
     const int32_t wg_auto = o.tile_wg_per_cu == 0 ? 1 : 0;

@@ -775,11 +775,14 @@ sl_status setup_mesh(const SetupArgs& a, const sl_options& o, DevMesh& m, int32_
     m.layout = o.layout;
     m.precision = o.precision;
     sl_status r;
-    // the resident kernel when asked for, checked against bounds known
-    // before validation (check_options has restricted it to Form A, f64)
-    if (o.kernel == SL_KERNEL_RESIDENT && !resident_fits(n, a.nnz, a.ninc))
-        return fail(SL_EINVAL, "mesh too large for the resident kernel");
-    m.resident = o.kernel == SL_KERNEL_RESIDENT;
+    // the resident kernel when asked for, and automatically for Form B
+    // (faster there than the node kernel's launch per colour class),
+    // checked against bounds known before validation (check_options has
+    // restricted it to f64; Form B is f64 only)
+    const bool res_fit = resident_fits(n, a.nnz, a.ninc, o.form == SL_INPLACE_COLORED);
+    if (o.kernel == SL_KERNEL_RESIDENT && !res_fit) return fail(SL_EINVAL, "mesh too large for the resident kernel");
+    m.resident = o.kernel == SL_KERNEL_RESIDENT ||
+                 (o.kernel == SL_KERNEL_AUTO && o.form == SL_INPLACE_COLORED && res_fit);
     const bool want_tiles = o.form == SL_JACOBI && o.kernel != SL_KERNEL_NODE && !m.resident;
     const int T = resolve_tile_nodes(o);
     const size_t rb = o.precision == SL_F32 ? 4 : 8;
@@ -864,6 +867,14 @@ sl_status setup_mesh(const SetupArgs& a, const sl_options& o, DevMesh& m, int32_
         SL_HIP(hipStreamSynchronize(st));
         m.n_colors = mx + 1;
         if (m.n_colors > 128) return fail(SL_ETOPO, "more than 128 colour classes");
+        // the resident kernel holds a bounded number of classes: an automatic
+        // choice falls back to the node kernel, an explicit one fails
+        if (m.resident && m.n_colors > kResidentClasses) {
+            if (o.kernel == SL_KERNEL_RESIDENT)
+                return fail(SL_EINVAL, "the resident kernel holds at most " + std::to_string(kResidentClasses) +
+                                           " colour classes");
+            m.resident = false;
+        }
     }
 
     // ---- node order

@@ -204,18 +204,86 @@ void launch_range(SweepArgs a, int max_deg, int requested_block, bool soa, bool 
 
 // ------------------------------------------------------- resident meshes --
 //
-// One work-group runs every sweep of one small mesh (Form A) without leaving
-// the launch: both coordinate buffers and the mesh's rows and fans (u16)
-// sit in LDS, a sweep reads one buffer and writes the other, and the
-// group's barrier separates sweeps.  The per-node arithmetic is that of
-// k_sweep, operation for operation; the fan's row slots index the node's row
-// in LDS instead of a column of gathered positions.  The sweep state is
-// written once, at the end, as the per-sweep closes would have left it; the
-// final positions go to buffer (sweeps run) % 2 in global memory.
+// One work-group runs every sweep of one small mesh without leaving the
+// launch: the coordinates and the mesh's rows and fans (u16) sit in LDS and
+// the group's barriers separate the steps.  Form A reads one buffer and
+// writes the other; Form B updates one buffer in place, colour class by
+// colour class (no two nodes of a class are adjacent), a barrier after each
+// class.  The per-node arithmetic is that of k_sweep, operation for
+// operation; the fan's row slots index the node's row in LDS instead of a
+// column of gathered positions.  The sweep state is written once, at the
+// end, as the per-sweep closes would have left it; the final positions go to
+// buffer (sweeps run) % 2 (Form A) or buffer 0 (Form B) in global memory.
 
 constexpr int kResBS = 1024;
 constexpr int kResRow = 8;   // row entries read together
 constexpr int kResFan = 4;   // fan entries read together
+
+// Node i's candidate, qualities and decision from positions `cur`; the new
+// position goes to nxt[i].  Returns whether it accepted; *d2 takes the
+// squared displacement.
+template <bool GT>
+__device__ __forceinline__ bool resident_node(int i, const double2* cur, double2* nxt, const uint16_t* rp,
+                                              const uint16_t* fp, const uint16_t* nb, const uint16_t* fn, double* d2)
+{
+    // the row and the fan are read a few entries at a time, with clamped
+    // indices, so that their dependent LDS loads overlap; sums and minima
+    // still run in stored order
+    const int r0 = rp[i], d = rp[i + 1] - r0;   // d >= 1: a free node has neighbours
+    double sx = 0.0, sy = 0.0;
+    for (int j0 = 0; j0 < d; j0 += kResRow) {
+        int lab[kResRow];
+#pragma unroll
+        for (int u = 0; u < kResRow; ++u) lab[u] = nb[r0 + min(j0 + u, d - 1)];
+        double2 p[kResRow];
+#pragma unroll
+        for (int u = 0; u < kResRow; ++u) p[u] = cur[lab[u]];
+#pragma unroll
+        for (int u = 0; u < kResRow; ++u)
+            if (j0 + u < d) {
+                sx += p[u].x;
+                sy += p[u].y;
+            }
+    }
+    const double dn = static_cast<double>(d);
+    const double cx = sx / dn, cy = sy / dn;
+    const double2 o = cur[i];
+    double qo = INFINITY, qn = INFINITY;
+    const int f1 = fp[i + 1];
+    for (int f0 = fp[i]; f0 < f1; f0 += kResFan) {
+        uint32_t e[kResFan];
+#pragma unroll
+        for (int u = 0; u < kResFan; ++u) e[u] = fn[min(f0 + u, f1 - 1)];
+        int la[kResFan], lb[kResFan];
+#pragma unroll
+        for (int u = 0; u < kResFan; ++u) {
+            la[u] = nb[r0 + ((e[u] >> 2) & 127u)];
+            lb[u] = nb[r0 + ((e[u] >> 9) & 127u)];
+        }
+        double2 va[kResFan], vb[kResFan];
+#pragma unroll
+        for (int u = 0; u < kResFan; ++u) {
+            va[u] = cur[la[u]];
+            vb[u] = cur[lb[u]];
+        }
+#pragma unroll
+        for (int u = 0; u < kResFan; ++u) {
+            if (f0 + u >= f1) break;
+            const int p = static_cast<int>(e[u] & 3u);
+            const double v = fan_quality(p, o.x, o.y, va[u], vb[u]);
+            if (v < qo) qo = v;
+            const double w = fan_quality(p, cx, cy, va[u], vb[u]);
+            if (w < qn) qn = w;
+        }
+    }
+    const bool accepted = GT ? (qn > qo) : (qn >= qo);
+    const double nx = accepted ? cx : o.x, ny = accepted ? cy : o.y;
+    nxt[i] = make_double2(nx, ny);
+    const double dx = nx - o.x, dy = ny - o.y;
+    const double t = dx * dx + dy * dy;
+    *d2 = t > *d2 ? t : *d2;
+    return accepted;
+}
 
 template <bool SOA, bool GT>
 __global__ __launch_bounds__(kResBS) void k_sweep_resident(const ResidentArgs* __restrict__ list)
@@ -225,18 +293,20 @@ __global__ __launch_bounds__(kResBS) void k_sweep_resident(const ResidentArgs* _
     __shared__ double s_d2[kResBS / 64];
     __shared__ unsigned long long s_acc[kResBS / 64];
     const int n = a.n, nf = a.n_free;
+    const bool in_place = a.in_place != 0;
+    const int nbuf = in_place ? 1 : 2;
     double2* buf0 = res_lds;
-    double2* buf1 = res_lds + n;
-    uint16_t* rp = reinterpret_cast<uint16_t*>(res_lds + 2 * n);   // [nf + 1] row starts
-    uint16_t* fp = rp + (nf + 1);                                    // [nf + 1] fan starts
-    uint16_t* nb = fp + (nf + 1);                                    // [nnz] neighbours (device labels)
-    uint16_t* fn = nb + a.nnz;                                       // [ninc] fan entries
+    double2* buf1 = in_place ? res_lds : res_lds + n;
+    uint16_t* rp = reinterpret_cast<uint16_t*>(res_lds + nbuf * n);   // [nf + 1] row starts
+    uint16_t* fp = rp + (nf + 1);                                       // [nf + 1] fan starts
+    uint16_t* nb = fp + (nf + 1);                                       // [nnz] neighbours (device labels)
+    uint16_t* fn = nb + a.nnz;                                          // [ninc] fan entries
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
 
     for (int i = tid; i < n; i += kResBS) {
         const double2 p = ld<SOA>(a.X, n, i);
         buf0[i] = p;
-        buf1[i] = p;
+        if (!in_place) buf1[i] = p;
     }
     for (int i = tid; i <= nf; i += kResBS) {
         rp[i] = static_cast<uint16_t>(a.row_ptr[i]);
@@ -246,80 +316,37 @@ __global__ __launch_bounds__(kResBS) void k_sweep_resident(const ResidentArgs* _
     for (int k = tid; k < a.ninc; k += kResBS) fn[k] = a.fan[k];
     __syncthreads();
 
+    // one range of device labels: Form A all free nodes, Form B one class
+    auto sweep_range = [&](int lo, int hi, const double2* cur, double2* nxt, int s, double* d2,
+                           unsigned long long* cnt) {
+        for (int i0 = lo; i0 < hi; i0 += kResBS) {
+            const int i = i0 + tid;
+            const bool accepted = i < hi && resident_node<GT>(i, cur, nxt, rp, fp, nb, fn, d2);
+            const unsigned long long ball = __ballot(accepted);
+            *cnt += __popcll(ball);
+            if (a.bits != nullptr && lane == 0 && ball != 0ull) {
+                // the wave's labels start at kw, which need not be a multiple of 64
+                const int kw = i0 + wv * 64, sh = kw & 63;
+                unsigned long long* word = reinterpret_cast<unsigned long long*>(a.bits) + s * a.words + (kw >> 6);
+                atomicOr(word, ball << sh);
+                if (sh != 0 && (ball >> (64 - sh)) != 0ull) atomicOr(word + 1, ball >> (64 - sh));
+            }
+        }
+    };
+
     int s = 0;
     double maxd = 0.0;
     unsigned long long acc = 0, acc_total = 0;
     while (s < a.iters) {
-        const double2* cur = (s & 1) ? buf1 : buf0;
-        double2* nxt = (s & 1) ? buf0 : buf1;
         double d2 = 0.0;
         unsigned long long cnt = 0;
-        for (int i0 = 0; i0 < nf; i0 += kResBS) {
-            const int i = i0 + tid;
-            bool accepted = false;
-            if (i < nf) {
-                // the row and the fan are read a few entries at a time, with
-                // clamped indices, so that their dependent LDS loads overlap;
-                // sums and minima still run in stored order
-                const int r0 = rp[i], d = rp[i + 1] - r0;   // d >= 1: a free node has neighbours
-                double sx = 0.0, sy = 0.0;
-                for (int j0 = 0; j0 < d; j0 += kResRow) {
-                    int lab[kResRow];
-#pragma unroll
-                    for (int u = 0; u < kResRow; ++u) lab[u] = nb[r0 + min(j0 + u, d - 1)];
-                    double2 p[kResRow];
-#pragma unroll
-                    for (int u = 0; u < kResRow; ++u) p[u] = cur[lab[u]];
-#pragma unroll
-                    for (int u = 0; u < kResRow; ++u)
-                        if (j0 + u < d) {
-                            sx += p[u].x;
-                            sy += p[u].y;
-                        }
-                }
-                const double dn = static_cast<double>(d);
-                const double cx = sx / dn, cy = sy / dn;
-                const double2 o = cur[i];
-                double qo = INFINITY, qn = INFINITY;
-                const int f1 = fp[i + 1];
-                for (int f0 = fp[i]; f0 < f1; f0 += kResFan) {
-                    uint32_t e[kResFan];
-#pragma unroll
-                    for (int u = 0; u < kResFan; ++u) e[u] = fn[min(f0 + u, f1 - 1)];
-                    int la[kResFan], lb[kResFan];
-#pragma unroll
-                    for (int u = 0; u < kResFan; ++u) {
-                        la[u] = nb[r0 + ((e[u] >> 2) & 127u)];
-                        lb[u] = nb[r0 + ((e[u] >> 9) & 127u)];
-                    }
-                    double2 va[kResFan], vb[kResFan];
-#pragma unroll
-                    for (int u = 0; u < kResFan; ++u) {
-                        va[u] = cur[la[u]];
-                        vb[u] = cur[lb[u]];
-                    }
-#pragma unroll
-                    for (int u = 0; u < kResFan; ++u) {
-                        if (f0 + u >= f1) break;
-                        const int p = static_cast<int>(e[u] & 3u);
-                        const double v = fan_quality(p, o.x, o.y, va[u], vb[u]);
-                        if (v < qo) qo = v;
-                        const double w = fan_quality(p, cx, cy, va[u], vb[u]);
-                        if (w < qn) qn = w;
-                    }
-                }
-                accepted = GT ? (qn > qo) : (qn >= qo);
-                const double nx = accepted ? cx : o.x, ny = accepted ? cy : o.y;
-                nxt[i] = make_double2(nx, ny);
-                const double dx = nx - o.x, dy = ny - o.y;
-                const double t = dx * dx + dy * dy;
-                d2 = t > d2 ? t : d2;
+        if (in_place) {
+            for (int c = 0; c < a.n_classes; ++c) {
+                sweep_range(a.class_start[c], a.class_start[c + 1], buf0, buf0, s, &d2, &cnt);
+                __syncthreads();   // the next class reads this one's positions
             }
-            const unsigned long long ball = __ballot(accepted);
-            cnt += __popcll(ball);
-            // i0 + 64 wv is a multiple of 64: the wave's bits are one whole word
-            if (a.bits != nullptr && lane == 0 && ball != 0ull)
-                atomicOr(reinterpret_cast<unsigned long long*>(a.bits) + s * a.words + ((i0 + wv * 64) >> 6), ball);
+        } else {
+            sweep_range(0, nf, (s & 1) ? buf1 : buf0, (s & 1) ? buf0 : buf1, s, &d2, &cnt);
         }
         for (int off = 32; off > 0; off >>= 1) {
             const double t = __shfl_xor(d2, off);
@@ -329,7 +356,7 @@ __global__ __launch_bounds__(kResBS) void k_sweep_resident(const ResidentArgs* _
             s_d2[wv] = d2;
             s_acc[wv] = cnt;
         }
-        __syncthreads();   // also: every read of cur and write of nxt of this sweep is done
+        __syncthreads();   // also: every read and write of this sweep is done
         double m = s_d2[0];
         unsigned long long c = s_acc[0];
         for (int q = 1; q < kResBS / 64; ++q) {
@@ -344,8 +371,9 @@ __global__ __launch_bounds__(kResBS) void k_sweep_resident(const ResidentArgs* _
         if (a.tol2 > 0.0 && m < a.tol2) break;
     }
 
-    const double2* fin = (s & 1) ? buf1 : buf0;
-    double* out = a.X + (s & 1) * 2 * static_cast<int64_t>(n);
+    const int fb = in_place ? 0 : (s & 1);
+    const double2* fin = fb ? buf1 : buf0;
+    double* out = a.X + fb * 2 * static_cast<int64_t>(n);
     for (int i = tid; i < nf; i += kResBS) st<SOA>(out, n, i, fin[i].x, fin[i].y);
     if (tid == 0) {
         MeshState ms = *a.state;
@@ -369,16 +397,29 @@ __global__ void k_advance(MeshState* __restrict__ st, int32_t n)
 
 }  // namespace
 
-size_t resident_lds_bytes(int64_t n, int64_t n_free, int64_t nnz, int64_t ninc)
+size_t resident_lds_bytes(int64_t n, int64_t n_free, int64_t nnz, int64_t ninc, bool in_place)
 {
-    return static_cast<size_t>(32 * n + 2 * (2 * (n_free + 1) + nnz + ninc));
+    return static_cast<size_t>((in_place ? 16 : 32) * n + 2 * (2 * (n_free + 1) + nnz + ninc));
 }
 
-bool resident_fits(int64_t n, int64_t nnz, int64_t ninc)
+bool resident_fits(int64_t n, int64_t nnz, int64_t ninc, bool in_place)
 {
     // u16 labels and offsets; the free-node counts are bounded by n
     return n >= 1 && n <= 65535 && nnz <= 65535 && ninc <= 65535 &&
-           resident_lds_bytes(n, n, nnz, ninc) <= kResidentLdsLimit;
+           resident_lds_bytes(n, n, nnz, ninc, in_place) <= kResidentLdsLimit;
+}
+
+sl_status resident_classes(const DevMesh& m, bool in_place, ResidentArgs& a)
+{
+    a.in_place = in_place ? 1 : 0;
+    a.n_classes = 0;
+    if (!in_place) return SL_OK;
+    if (m.n_colors > kResidentClasses)
+        return fail(SL_EINVAL, "the resident kernel holds at most " + std::to_string(kResidentClasses) +
+                                   " colour classes, this mesh has " + std::to_string(m.n_colors));
+    a.n_classes = m.n_colors;
+    for (int c = 0; c <= m.n_colors; ++c) a.class_start[c] = m.color_start_h[c];
+    return SL_OK;
 }
 
 sl_status launch_sweep_resident(const ResidentArgs* list, int32_t count, size_t lds, int32_t layout,

@@ -392,16 +392,19 @@ def test_resume_and_repeat_are_bit_exact():
     assert (X12 == X12b).all() and (X12 == X66).all()
 
 
-def test_colored_form_parity_and_invariants():
+@pytest.mark.parametrize("kernel", ["auto", "node"])
+def test_colored_form_parity_and_invariants(kernel):
     m = meshgen.make_grid(48, "random", 0.4, 14)
-    X, rep, ref, ndiff = assert_parity(m, 8, form="colored")
+    X, rep, ref, ndiff = assert_parity(m, 8, form="colored", kernel=kernel)
+    # a mesh this small runs Form B on the resident kernel unless told otherwise
+    assert rep.kernel_used == sl.KERNELS["resident" if kernel == "auto" else "node"]
     col, nc = oracle.colors(m)
     assert rep.n_colors == nc
     b = m.boundary.astype(bool)
     assert (X[b] == m.coords[b]).all() and np.isfinite(X).all()
     for layout in ("aos", "soa"):
         for reorder in ("none", "hilbert"):
-            X2, _, _ = run_gpu(m, 8, form="colored", layout=layout, reorder=reorder)
+            X2, _, _ = run_gpu(m, 8, form="colored", layout=layout, reorder=reorder, kernel=kernel)
             assert (X2 == X).all()
     # mesh-wide worst quality never drops over a coloured sweep
     prev = min(oracle.quality(*m.coords[a], *m.coords[c], *m.coords[d]) for a, c, d in m.tris)
@@ -441,9 +444,11 @@ def test_batch_tolerance_and_forms():
             assert rep.iterations_run == r.iterations_run < 400
             assert rep.accepted_total == int(r.accepted.sum())
             assert (X == r.coords).all()
-    outs, reps, br = sl.batch_smooth(ms, 5, form="colored")
-    for m, X in zip(ms, outs):
-        assert (X == oracle.smooth(m, 5, form="colored").coords).all()
+    for kernel in ("auto", "resident", "node"):
+        outs, reps, br = sl.batch_smooth(ms, 5, form="colored", kernel=kernel)
+        assert br.meshes_resident == (0 if kernel == "node" else len(ms))
+        for m, X in zip(ms, outs):
+            assert (X == oracle.smooth(m, 5, form="colored").coords).all()
     outs, reps, br = sl.batch_smooth(ms, 6, accept="gt", layout="soa")
     for m, X in zip(ms, outs):
         assert (X == oracle.smooth(m, 6, accept_gt=True).coords).all()
@@ -460,16 +465,21 @@ RESIDENT_MESHES = {
 
 
 @pytest.mark.parametrize("name", sorted(RESIDENT_MESHES))
-@pytest.mark.parametrize("layout,accept", [("aos", "ge"), ("soa", "gt")])
-def test_resident_kernel_parity(name, layout, accept):
-    """Every sweep of a small mesh in one launch, with the mesh in LDS: the
-    flags of every sweep, the coordinates and the counts equal the oracle's,
-    and the coordinates equal the tile kernel's."""
+@pytest.mark.parametrize("layout,accept,form", [("aos", "ge", "jacobi"), ("soa", "gt", "jacobi"),
+                                                ("aos", "ge", "colored"), ("soa", "gt", "colored")])
+def test_resident_kernel_parity(name, layout, accept, form):
+    """Every sweep of a small mesh in one launch, with the mesh in LDS (Form
+    A: two buffers; Form B: one, class by class): the flags of every sweep,
+    the coordinates and the counts equal the oracle's, and the coordinates
+    equal the other kernels' (tile for Form A, node for Form B)."""
     m = RESIDENT_MESHES[name]()
-    X, rep, ref, nd = assert_parity(m, 12, accept=accept, layout=layout, kernel="resident")
+    X, rep, ref, nd = assert_parity(m, 12, accept=accept, layout=layout, form=form, kernel="resident")
     assert nd == 0 and rep.kernel_used == sl.KERNELS["resident"] and rep.tile_nodes == 0
-    Xt, rt, _ = run_gpu(m, 12, accept=accept, layout=layout, kernel="tile")
-    assert rt.kernel_used == sl.KERNELS["tile"] and (X == Xt).all()
+    other = "tile" if form == "jacobi" else "node"
+    Xt, rt, _ = run_gpu(m, 12, accept=accept, layout=layout, form=form, kernel=other)
+    assert rt.kernel_used == sl.KERNELS[other] and (X == Xt).all()
+    if form == "colored":
+        assert rep.n_colors == rt.n_colors >= 1
 
 
 def test_resident_tolerance_zero_sweeps_and_fixed_nodes():
@@ -501,7 +511,7 @@ def test_resident_limits():
         run_gpu(big, 2, kernel="resident")
     assert e.value.status == sl.SL_EINVAL and "resident" in str(e.value)
     small = meshgen.make_grid(20, "random", 0.4, 608)
-    for opts in ({"form": "colored"}, {"precision": "f32"}):
+    for opts in ({"precision": "f32"}, {"precision": "f32", "form": "colored"}):
         with pytest.raises(sl.SmartlapError) as e:
             run_gpu(small, 2, kernel="resident", **opts)
         assert e.value.status == sl.SL_EINVAL
