@@ -504,14 +504,40 @@ __global__ __launch_bounds__(kBS) void k_place(const int32_t* __restrict__ flag,
 // One round of greedy colouring in decreasing priority: a free node takes
 // the smallest colour unused by its free neighbours once every free
 // neighbour of higher priority has a colour.
-__global__ __launch_bounds__(kBS) void k_color_round(int32_t n, const int32_t* __restrict__ nbr_ptr,
+// Appends v to list[] for every lane of the wave whose `keep` is set: one
+// atomic per wave reserves the wave's places, in lane order.
+__device__ __forceinline__ void append_wave(bool keep, int32_t v, int32_t* __restrict__ list,
+                                            int32_t* __restrict__ count)
+{
+    const unsigned long long mask = __ballot(keep);
+    if (mask == 0ull) return;
+    const int lane = static_cast<int>(threadIdx.x & 63);
+    const int first = __builtin_ctzll(mask);
+    int base = 0;
+    if (lane == first) base = atomicAdd(count, __popcll(mask));
+    base = __shfl(base, first);
+    if (keep) list[base + __popcll(mask & ((1ull << lane) - 1ull))] = v;
+}
+
+constexpr int kColorRounds = 8;
+
+// One Jones-Plassmann round over the listed (uncoloured) free nodes: a node
+// whose neighbours of higher priority are all coloured takes the smallest
+// colour none of them has; the others go to the next list.  The colour a
+// node gets depends only on those neighbours' colours, so neither the
+// round nor the list order changes the result.
+__global__ __launch_bounds__(kBS) void k_color_round(const int32_t* __restrict__ nbr_ptr,
                                                      const int32_t* __restrict__ nbr_idx,
                                                      const uint8_t* __restrict__ bnd, int32_t* color,
-                                                     int32_t* __restrict__ remaining)
+                                                     const int32_t* __restrict__ list, const int32_t* cnt_in,
+                                                     int32_t* __restrict__ next, int32_t* __restrict__ next_cnt)
 {
-    const int32_t i = static_cast<int32_t>(blockIdx.x * kBS + threadIdx.x);
-    int left = 0;
-    if (i < n && !bnd[i] && __atomic_load_n(color + i, __ATOMIC_RELAXED) < 0) {
+    const int32_t cnt = *cnt_in;   // the list's length, left by the previous round
+    const int32_t t = static_cast<int32_t>(blockIdx.x * kBS + threadIdx.x);
+    bool left = false;
+    int32_t i = -1;
+    if (t < cnt) {
+        i = list[t];
         const uint64_t pi = splitmix64(static_cast<uint64_t>(i));
         uint64_t used0 = 0, used1 = 0;
         bool ready = true;
@@ -526,17 +552,19 @@ __global__ __launch_bounds__(kBS) void k_color_round(int32_t n, const int32_t* _
             const int32_t c = (~used0) ? __builtin_ctzll(~used0) : 64 + __builtin_ctzll(~used1);
             __atomic_store_n(color + i, c, __ATOMIC_RELAXED);
         } else {
-            left = 1;
+            left = true;
         }
     }
-    const int32_t cnt = __popcll(__ballot(left != 0));
-    if ((threadIdx.x & 63) == 0 && cnt) atomicAdd(remaining, cnt);
+    append_wave(left, i, next, next_cnt);
 }
 
-__global__ __launch_bounds__(kBS) void k_color_init(int32_t n, const uint8_t* __restrict__ bnd, int32_t* color)
+// Every node uncoloured; the free ones listed (in no particular order).
+__global__ __launch_bounds__(kBS) void k_color_init(int32_t n, const uint8_t* __restrict__ bnd, int32_t* color,
+                                                    int32_t* __restrict__ list, int32_t* __restrict__ count)
 {
     const int64_t i = static_cast<int64_t>(blockIdx.x) * kBS + threadIdx.x;
     if (i < n) color[i] = -1;
+    append_wave(i < n && !bnd[i], static_cast<int32_t>(i), list, count);
 }
 
 __global__ __launch_bounds__(kBS) void k_max_i32(const int32_t* __restrict__ v, int32_t n, int32_t* __restrict__ out)
@@ -798,7 +826,8 @@ sl_status setup_mesh(const SetupArgs& a, const sl_options& o, DevMesh& m, int32_
     const int gb = div_up(n, kBS);
     const size_t sb = Arena::piece(sizeof(ValStats)) + Arena::piece(sizeof(ValStats) * static_cast<size_t>(gb)) +
                       Arena::piece(4 * un) + Arena::piece(4) +
-                      std::max({order_bytes(n), rows_bytes, tile_scratch_bytes()});
+                      std::max({order_bytes(n), rows_bytes, tile_scratch_bytes(),
+                                2 * Arena::piece(4 * un) + Arena::piece(8)});   // the colouring's lists
     if ((r = persist.reserve(pb, st))) return r;
     m.block = persist.base;
     if ((r = scratch.reserve(sb, st))) return r;
@@ -851,15 +880,31 @@ sl_status setup_mesh(const SetupArgs& a, const sl_options& o, DevMesh& m, int32_
     if (o.form == SL_INPLACE_COLORED && m.n_free > 0) {
         int32_t* remaining = nullptr;
         if ((r = scratch.take(&color, n)) || (r = scratch.take(&remaining, 1))) return r;
-        k_color_init<<<gb, kBS, 0, st>>>(n, a.boundary, color);
-        for (int round = 0; round <= m.n_free; ++round) {
-            k_fill_i32<<<1, 1, 0, st>>>(remaining, 1, 0);
-            k_color_round<<<gb, kBS, 0, st>>>(n, a.nbr_ptr, a.nbr_idx, a.boundary, color, remaining);
-            int32_t left = 0;
-            SL_HIP(hipMemcpyAsync(&left, remaining, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+        // rounds over a shrinking list of the uncoloured free nodes
+        const size_t cmark = scratch.mark();
+        int32_t *list = nullptr, *next = nullptr, *cnt2 = nullptr;
+        if ((r = scratch.take(&list, m.n_free)) || (r = scratch.take(&next, m.n_free)) ||
+            (r = scratch.take(&cnt2, 2)))
+            return r;
+        k_fill_i32<<<1, 2, 0, st>>>(cnt2, 2, 0);
+        k_color_init<<<gb, kBS, 0, st>>>(n, a.boundary, color, list, cnt2);
+        // rounds read their list's length on the device; the host looks at
+        // it every kColorRounds rounds (rounds past the last are empty), and
+        // sizes the launches by the last length it saw
+        int32_t left = m.n_free, cur = 0;
+        for (int round = 0; left > 0; round += kColorRounds) {
+            if (round > m.n_free) return fail(SL_EDEVICE, "colouring made no progress");
+            for (int k = 0; k < kColorRounds; ++k) {
+                k_fill_i32<<<1, 1, 0, st>>>(cnt2 + (cur ^ 1), 1, 0);
+                k_color_round<<<div_up(left, kBS), kBS, 0, st>>>(a.nbr_ptr, a.nbr_idx, a.boundary, color, list,
+                                                                cnt2 + cur, next, cnt2 + (cur ^ 1));
+                std::swap(list, next);
+                cur ^= 1;
+            }
+            SL_HIP(hipMemcpyAsync(&left, cnt2 + cur, sizeof(int32_t), hipMemcpyDeviceToHost, st));
             SL_HIP(hipStreamSynchronize(st));
-            if (left == 0) break;
         }
+        scratch.rewind(cmark);
         k_fill_i32<<<1, 1, 0, st>>>(remaining, 1, -1);
         k_max_i32<<<std::min(gb, 1024), kBS, 0, st>>>(color, n, remaining);
         int32_t mx = -1;
