@@ -504,19 +504,29 @@ __global__ __launch_bounds__(kBS) void k_place(const int32_t* __restrict__ flag,
 // One round of greedy colouring in decreasing priority: a free node takes
 // the smallest colour unused by its free neighbours once every free
 // neighbour of higher priority has a colour.
-// Appends v to list[] for every lane of the wave whose `keep` is set: one
-// atomic per wave reserves the wave's places, in lane order.
-__device__ __forceinline__ void append_wave(bool keep, int32_t v, int32_t* __restrict__ list,
-                                            int32_t* __restrict__ count)
+// Appends v to list[] for every work-item of the group whose `keep` is set:
+// one atomic per work-group reserves the group's places (one per wave, or
+// per work-item, on a single counter would queue behind each other).  Every
+// work-item of the group must call it.
+constexpr int kColorBS = 1024;
+__device__ __forceinline__ void append_group(bool keep, int32_t v, int32_t* __restrict__ list,
+                                             int32_t* __restrict__ count, int32_t* s_tmp /* [kColorBS/64 + 1] */)
 {
+    const int lane = static_cast<int>(threadIdx.x & 63), wv = static_cast<int>(threadIdx.x >> 6);
     const unsigned long long mask = __ballot(keep);
-    if (mask == 0ull) return;
-    const int lane = static_cast<int>(threadIdx.x & 63);
-    const int first = __builtin_ctzll(mask);
-    int base = 0;
-    if (lane == first) base = atomicAdd(count, __popcll(mask));
-    base = __shfl(base, first);
-    if (keep) list[base + __popcll(mask & ((1ull << lane) - 1ull))] = v;
+    if (lane == 0) s_tmp[wv] = __popcll(mask);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int32_t tot = 0;
+        for (int w = 0; w < kColorBS / 64; ++w) {
+            const int32_t c = s_tmp[w];
+            s_tmp[w] = tot;
+            tot += c;
+        }
+        s_tmp[kColorBS / 64] = tot ? atomicAdd(count, tot) : 0;
+    }
+    __syncthreads();
+    if (keep) list[s_tmp[kColorBS / 64] + s_tmp[wv] + __popcll(mask & ((1ull << lane) - 1ull))] = v;
 }
 
 constexpr int kColorRounds = 8;
@@ -526,14 +536,15 @@ constexpr int kColorRounds = 8;
 // colour none of them has; the others go to the next list.  The colour a
 // node gets depends only on those neighbours' colours, so neither the
 // round nor the list order changes the result.
-__global__ __launch_bounds__(kBS) void k_color_round(const int32_t* __restrict__ nbr_ptr,
+__global__ __launch_bounds__(kColorBS) void k_color_round(const int32_t* __restrict__ nbr_ptr,
                                                      const int32_t* __restrict__ nbr_idx,
                                                      const uint8_t* __restrict__ bnd, int32_t* color,
                                                      const int32_t* __restrict__ list, const int32_t* cnt_in,
                                                      int32_t* __restrict__ next, int32_t* __restrict__ next_cnt)
 {
+    __shared__ int32_t s_tmp[kColorBS / 64 + 1];
     const int32_t cnt = *cnt_in;   // the list's length, left by the previous round
-    const int32_t t = static_cast<int32_t>(blockIdx.x * kBS + threadIdx.x);
+    const int32_t t = static_cast<int32_t>(blockIdx.x * kColorBS + threadIdx.x);
     bool left = false;
     int32_t i = -1;
     if (t < cnt) {
@@ -555,16 +566,17 @@ __global__ __launch_bounds__(kBS) void k_color_round(const int32_t* __restrict__
             left = true;
         }
     }
-    append_wave(left, i, next, next_cnt);
+    append_group(left, i, next, next_cnt, s_tmp);
 }
 
 // Every node uncoloured; the free ones listed (in no particular order).
-__global__ __launch_bounds__(kBS) void k_color_init(int32_t n, const uint8_t* __restrict__ bnd, int32_t* color,
-                                                    int32_t* __restrict__ list, int32_t* __restrict__ count)
+__global__ __launch_bounds__(kColorBS) void k_color_init(int32_t n, const uint8_t* __restrict__ bnd, int32_t* color,
+                                                         int32_t* __restrict__ list, int32_t* __restrict__ count)
 {
-    const int64_t i = static_cast<int64_t>(blockIdx.x) * kBS + threadIdx.x;
+    __shared__ int32_t s_tmp[kColorBS / 64 + 1];
+    const int64_t i = static_cast<int64_t>(blockIdx.x) * kColorBS + threadIdx.x;
     if (i < n) color[i] = -1;
-    append_wave(i < n && !bnd[i], static_cast<int32_t>(i), list, count);
+    append_group(i < n && !bnd[i], static_cast<int32_t>(i), list, count, s_tmp);
 }
 
 __global__ __launch_bounds__(kBS) void k_max_i32(const int32_t* __restrict__ v, int32_t n, int32_t* __restrict__ out)
@@ -612,21 +624,52 @@ __global__ __launch_bounds__(kBS) void k_rows_fans(const int32_t* __restrict__ p
     const int32_t o = perm[k];
     const int32_t b = nbr_ptr[o], d = nbr_ptr[o + 1] - b;
     const int32_t out = row_ptr[k];
-    for (int32_t j = 0; j < d; ++j) nbr[out + j] = new_of_old[nbr_idx[b + j]];
+    // rows of up to kRowRegs entries are held in registers (their loads in
+    // flight together) for the slot searches below; longer rows are
+    // searched in memory
+    const bool in_regs = d <= kRowRegs;
+    int32_t rowv[kRowRegs];
+#pragma unroll
+    for (int j = 0; j < kRowRegs; ++j) rowv[j] = (in_regs && j < d) ? nbr_idx[b + j] : -1;
+    if (in_regs) {
+#pragma unroll
+        for (int j = 0; j < kRowRegs; ++j)
+            if (j < d) nbr[out + j] = new_of_old[rowv[j]];
+    } else {
+        for (int32_t j = 0; j < d; ++j) nbr[out + j] = new_of_old[nbr_idx[b + j]];
+    }
+    // the row position of u (the last one, should u repeat)
+    auto slot = [&](int32_t u) -> int {
+        int sj = 0;
+        if (in_regs) {
+#pragma unroll
+            for (int j = 0; j < kRowRegs; ++j)
+                if (j < d && rowv[j] == u) sj = j;
+        } else {
+            for (int32_t j = 0; j < d; ++j)
+                if (nbr_idx[b + j] == u) sj = j;
+        }
+        return sj;
+    };
     const int32_t tb = tri_ptr[o], nt = tri_ptr[o + 1] - tb;
     const int32_t fo = fan_ptr[k];
-    for (int32_t q = 0; q < nt; ++q) {
-        const int64_t t = tri_idx[tb + q];
-        const int32_t v[3] = {tris[3 * t], tris[3 * t + 1], tris[3 * t + 2]};
-        const int p = v[0] == o ? 0 : (v[1] == o ? 1 : 2);
-        const int32_t va = v[(p + 1) % 3], vc = v[(p + 2) % 3];
-        int sa = 0, sc = 0;
-        for (int32_t j = 0; j < d; ++j) {
-            const int32_t u = nbr_idx[b + j];
-            if (u == va) sa = j;
-            if (u == vc) sc = j;
+    // incidences four at a time: their loads are in flight together
+    for (int32_t q0 = 0; q0 < nt; q0 += 4) {
+        int64_t t[4];
+        int32_t v[4][3];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) t[u] = q0 + u < nt ? tri_idx[tb + q0 + u] : -1;
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+#pragma unroll
+            for (int c = 0; c < 3; ++c) v[u][c] = t[u] >= 0 ? tris[3 * t[u] + c] : -1;
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            if (q0 + u >= nt) break;
+            const int p = v[u][0] == o ? 0 : (v[u][1] == o ? 1 : 2);
+            const int32_t va = v[u][(p + 1) % 3], vc = v[u][(p + 2) % 3];
+            fan[fo + q0 + u] = static_cast<uint16_t>(p | (slot(va) << 2) | (slot(vc) << 9));
         }
-        fan[fo + q] = static_cast<uint16_t>(p | (sa << 2) | (sc << 9));
     }
 }
 
@@ -887,7 +930,7 @@ sl_status setup_mesh(const SetupArgs& a, const sl_options& o, DevMesh& m, int32_
             (r = scratch.take(&cnt2, 2)))
             return r;
         k_fill_i32<<<1, 2, 0, st>>>(cnt2, 2, 0);
-        k_color_init<<<gb, kBS, 0, st>>>(n, a.boundary, color, list, cnt2);
+        k_color_init<<<div_up(n, kColorBS), kColorBS, 0, st>>>(n, a.boundary, color, list, cnt2);
         // rounds read their list's length on the device; the host looks at
         // it every kColorRounds rounds (rounds past the last are empty), and
         // sizes the launches by the last length it saw
@@ -896,8 +939,8 @@ sl_status setup_mesh(const SetupArgs& a, const sl_options& o, DevMesh& m, int32_
             if (round > m.n_free) return fail(SL_EDEVICE, "colouring made no progress");
             for (int k = 0; k < kColorRounds; ++k) {
                 k_fill_i32<<<1, 1, 0, st>>>(cnt2 + (cur ^ 1), 1, 0);
-                k_color_round<<<div_up(left, kBS), kBS, 0, st>>>(a.nbr_ptr, a.nbr_idx, a.boundary, color, list,
-                                                                cnt2 + cur, next, cnt2 + (cur ^ 1));
+                k_color_round<<<div_up(left, kColorBS), kColorBS, 0, st>>>(a.nbr_ptr, a.nbr_idx, a.boundary, color,
+                                                                          list, cnt2 + cur, next, cnt2 + (cur ^ 1));
                 std::swap(list, next);
                 cur ^= 1;
             }
