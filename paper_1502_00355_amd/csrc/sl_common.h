@@ -78,9 +78,9 @@ void dfree(T*& p, hipStream_t st)
 // idles; repeated calls on meshes of similar size reuse their blocks
 // instead.  A block given back carries an event recorded on the giving
 // stream after every use of the block; the next taker's stream waits for
-// that event before its first use.  The cache holds at most a few blocks
-// and a bounded number of bytes per device; when an allocation fails, the
-// cached blocks are freed and it is tried once more.
+// that event before its first use.  The cache holds a bounded number of
+// bytes per device; when an allocation fails, the cached blocks are freed
+// and it is tried once more.
 sl_status block_take(unsigned char** p, size_t bytes, hipStream_t st);
 void block_give(unsigned char*& p, hipStream_t st);
 

@@ -216,7 +216,10 @@ void give_stream(hipStream_t st)
 
 namespace {
 
-constexpr size_t kCacheBlocks = 8;                       // per device
+// per device; a batch gives back a few blocks per mesh at once, and a
+// free costs about 0.24 ms of host time, so the count bound is loose and
+// the byte bound is what limits the cache
+constexpr size_t kCacheBlocks = 4096;
 constexpr size_t kCacheBytes = size_t(16) << 30;         // per device
 
 struct Cached {
