@@ -303,13 +303,40 @@ sl_status sl_batch_smooth(const sl_mesh_desc* meshes, int32_t n_meshes, int32_t 
             if ((r = unpermute_coords(m, src, bs.out + used, st))) return r;
             used += 2 * static_cast<size_t>(m.n);
         }
-        used = 0;
-        for (int32_t i = first; i < last; ++i) {
-            const size_t vals = 2 * static_cast<size_t>(bs.meshes[i].n);
-            if ((r = copy_to_host(meshes[i].coords, bs.out + used, sizeof(double) * vals, st))) return r;
-            used += vals;
+        SL_HIP(hipStreamSynchronize(st));   // the group's positions are in bs.out
+        // copied out by the setup threads, each on its own stream with its own
+        // staging buffers, so that the host copies run side by side
+        std::vector<size_t> off(static_cast<size_t>(last - first) + 1, 0);
+        for (int32_t i = first; i < last; ++i) off[i - first + 1] = off[i - first] + 2 * static_cast<size_t>(bs.meshes[i].n);
+        std::atomic<int32_t> next_copy{first};
+        std::vector<sl_status> c_status(static_cast<size_t>(n_threads), SL_OK);
+        std::vector<std::string> c_msg(static_cast<size_t>(n_threads));
+        auto copier = [&](int32_t t) {
+            if (hipSetDevice(device) != hipSuccess) {
+                c_status[t] = SL_EDEVICE;
+                c_msg[t] = "hipSetDevice failed in a copy thread";
+                return;
+            }
+            for (;;) {
+                const int32_t i = next_copy.fetch_add(1);
+                if (i >= last) break;
+                const sl_status cr = copy_to_host(meshes[i].coords, bs.out + off[i - first],
+                                                  sizeof(double) * (off[i - first + 1] - off[i - first]), bs.setup_st[t]);
+                if (cr) {
+                    c_status[t] = cr;
+                    c_msg[t] = "mesh " + std::to_string(i) + ": " + sl_last_error();
+                    break;
+                }
+            }
+        };
+        {
+            std::vector<std::thread> pool;
+            for (int32_t t = 1; t < n_threads; ++t) pool.emplace_back(copier, t);
+            copier(0);
+            for (auto& th : pool) th.join();
         }
-        SL_HIP(hipStreamSynchronize(st));
+        for (int32_t t = 0; t < n_threads; ++t)
+            if (c_status[t]) return fail(c_status[t], c_msg[t]);
         first = last;
     }
     for (int32_t i = 0; i < n_meshes; ++i) {
