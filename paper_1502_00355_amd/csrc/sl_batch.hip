@@ -23,7 +23,7 @@ namespace sl {
 
 namespace {
 
-constexpr int32_t kSetupThreads = 8;
+constexpr int32_t kSetupThreads = 16;   // at most; no more than the host's hardware threads
 constexpr size_t kOutGroupValues = size_t(1) << 27;   // un-permute staging: 1 GiB of doubles
 
 struct BatchState {
@@ -120,7 +120,8 @@ sl_status sl_batch_smooth(const sl_mesh_desc* meshes, int32_t n_meshes, int32_t 
 
     // ---- setup: meshes taken in index order by a few threads
     bs.meshes.resize(static_cast<size_t>(n_meshes));
-    const int32_t n_threads = std::min(n_meshes, kSetupThreads);
+    const int32_t hw = static_cast<int32_t>(std::max(1u, std::thread::hardware_concurrency()));
+    const int32_t n_threads = std::min({n_meshes, kSetupThreads, std::max(hw, 4)});
     bs.setup_st.assign(static_cast<size_t>(n_threads), nullptr);
     for (auto& s : bs.setup_st)
         if ((r = take_stream(&s))) return r;
