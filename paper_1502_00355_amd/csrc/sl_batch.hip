@@ -30,6 +30,7 @@ struct BatchState {
     hipStream_t st = nullptr;
     std::vector<hipStream_t> setup_st;
     std::vector<DevMesh> meshes;
+    unsigned char* block = nullptr;     // every mesh's arrays, when one allocation held them
     TileWork* work = nullptr;
     MeshState* states = nullptr;
     int32_t* sched = nullptr;           // the tile launches' counters
@@ -41,6 +42,7 @@ struct BatchState {
     ~BatchState()
     {
         for (auto& m : meshes) devmesh_free(m, st);
+        block_give(block, st);
         dfree(work, st);
         dfree(states, st);
         dfree(sched, st);
@@ -127,6 +129,32 @@ sl_status sl_batch_smooth(const sl_mesh_desc* meshes, int32_t n_meshes, int32_t 
         if ((r = take_stream(&s))) return r;
     int device = 0;
     SL_HIP(hipGetDevice(&device));
+    // Every mesh's own arrays carved from one block, sized from the CSR ends:
+    // one allocation and one release for the batch instead of one each per
+    // mesh (a release beyond what the block cache keeps costs about 0.2 ms of
+    // host time).  Without that block (a bad descriptor, whose setup then
+    // reports it, or no room for it) each mesh allocates its own.
+    if (n_meshes > 1) {
+        std::vector<size_t> sz(static_cast<size_t>(n_meshes), 0);
+        size_t total = 0;
+        bool ok = true;
+        for (int32_t i = 0; i < n_meshes && ok; ++i) {
+            const sl_mesh_desc& d = meshes[i];
+            ok = d.nbr_ptr && d.tri_ptr && d.n_nodes > 0 && d.nbr_ptr[d.n_nodes] >= 0 && d.tri_ptr[d.n_nodes] >= 0;
+            if (ok) sz[i] = mesh_block_bytes(d.n_nodes, d.nbr_ptr[d.n_nodes], d.tri_ptr[d.n_nodes], o);
+            total += sz[i];
+        }
+        if (ok && block_take(&bs.block, total, st) == SL_OK) {
+            size_t at = 0;
+            for (int32_t i = 0; i < n_meshes; ++i) {
+                bs.meshes[i].carve = bs.block + at;
+                bs.meshes[i].carve_bytes = sz[i];
+                at += sz[i];
+            }
+            SL_HIP(hipStreamSynchronize(st));   // the block is the setup streams' from here
+        }
+        set_error("");
+    }
     std::atomic<int32_t> next{0};
     std::atomic<bool> failed{false};
     std::vector<sl_status> t_status(static_cast<size_t>(n_threads), SL_OK);

@@ -117,6 +117,13 @@ struct Arena {
         used += b;
         return SL_OK;
     }
+    // Carves from `bytes` at p, owned by someone else: never release() it.
+    void adopt(unsigned char* p, size_t bytes)
+    {
+        base = p;
+        cap = bytes;
+        used = 0;
+    }
     size_t mark() const { return used; }
     void rewind(size_t m) { used = m; }
     void release(hipStream_t st)
@@ -184,6 +191,11 @@ static_assert(sizeof(TileWork) == 80, "TileWork layout");
 // device order, fixed nodes [n_free, n).
 struct DevMesh {
     unsigned char* block = nullptr;   // one allocation; every array below is carved from it
+    // Set before setup to carve the arrays from a region of a larger block
+    // instead (a batch's; not owned, `block` stays null); at least
+    // mesh_block_bytes() long.
+    unsigned char* carve = nullptr;
+    size_t carve_bytes = 0;
     int32_t n = 0, n_free = 0, n_tris = 0;
     int64_t nnz_free = 0, ninc_free = 0;
     int32_t max_deg = 0, max_inc = 0;
@@ -242,6 +254,9 @@ constexpr size_t kTileLdsLimit = 160 * 1024 - 4096;
 // or tiles (tile path, MeshState index `mesh`) and fills both coordinate
 // buffers.  Synchronises `st` (the validation result is needed).
 sl_status setup_mesh(const SetupArgs& a, const sl_options& o, DevMesh& m, int32_t mesh, hipStream_t st);
+// Bytes of the one allocation setup_mesh makes for a mesh's own arrays,
+// from bounds known before validation (n nodes, nnz and ninc CSR entries).
+size_t mesh_block_bytes(int32_t n, int64_t nnz, int64_t ninc, const sl_options& o);
 
 // Device arrays of one caller mesh.
 struct MeshInput {

@@ -838,6 +838,21 @@ void devmesh_free(DevMesh& m, hipStream_t st)
     m.tile_data = nullptr;
 }
 
+size_t mesh_block_bytes(int32_t n, int64_t nnz, int64_t ninc, const sl_options& o)
+{
+    // the same kernel choice as setup_mesh makes before validation
+    const bool resident = o.kernel == SL_KERNEL_RESIDENT ||
+                          (o.kernel == SL_KERNEL_AUTO && o.form == SL_INPLACE_COLORED &&
+                           resident_fits(n, nnz, ninc, o.form == SL_INPLACE_COLORED));
+    const bool want_tiles = o.form == SL_JACOBI && o.kernel != SL_KERNEL_NODE && !resident;
+    const size_t rb = o.precision == SL_F32 ? 4 : 8;
+    const size_t un = static_cast<size_t>(n);
+    size_t pb = 2 * Arena::piece(4 * un) + 2 * Arena::piece(4 * (un + 1)) + Arena::piece(4 * un * rb);
+    pb += want_tiles ? tile_bytes(n, nnz, ninc, resolve_tile_nodes(o))
+                     : Arena::piece(4 * static_cast<size_t>(nnz)) + Arena::piece(2 * static_cast<size_t>(ninc));
+    return pb;
+}
+
 sl_status setup_mesh(const SetupArgs& a, const sl_options& o, DevMesh& m, int32_t mesh, hipStream_t st)
 {
     const int32_t n = a.n;
@@ -855,24 +870,25 @@ sl_status setup_mesh(const SetupArgs& a, const sl_options& o, DevMesh& m, int32_
     m.resident = o.kernel == SL_KERNEL_RESIDENT ||
                  (o.kernel == SL_KERNEL_AUTO && o.form == SL_INPLACE_COLORED && res_fit);
     const bool want_tiles = o.form == SL_JACOBI && o.kernel != SL_KERNEL_NODE && !m.resident;
-    const int T = resolve_tile_nodes(o);
-    const size_t rb = o.precision == SL_F32 ? 4 : 8;
     const size_t un = static_cast<size_t>(n);
     // Two reservations: the mesh's own arrays, sized from bounds known before
     // validation (n >= free nodes, a.nnz and a.ninc >= their rows and fans),
     // and the setup's temporaries, given back when setup ends.
     Arena persist, scratch;
-    size_t pb = 2 * Arena::piece(4 * un) + 2 * Arena::piece(4 * (un + 1)) + Arena::piece(4 * un * rb);
-    pb += want_tiles ? tile_bytes(n, a.nnz, a.ninc, T)
-                     : Arena::piece(4 * static_cast<size_t>(a.nnz)) + Arena::piece(2 * static_cast<size_t>(a.ninc));
+    const size_t pb = mesh_block_bytes(n, a.nnz, a.ninc, o);
     const size_t rows_bytes = 2 * Arena::piece(4 * un) + scan_bytes(n);
     const int gb = div_up(n, kBS);
     const size_t sb = Arena::piece(sizeof(ValStats)) + Arena::piece(sizeof(ValStats) * static_cast<size_t>(gb)) +
                       Arena::piece(4 * un) + Arena::piece(4) +
                       std::max({order_bytes(n), rows_bytes, tile_scratch_bytes(),
                                 2 * Arena::piece(4 * un) + Arena::piece(8)});   // the colouring's lists
-    if ((r = persist.reserve(pb, st))) return r;
-    m.block = persist.base;
+    if (m.carve) {
+        if (m.carve_bytes < pb) return fail(SL_EINVAL, "internal: mesh region smaller than its arrays");
+        persist.adopt(m.carve, pb);
+    } else {
+        if ((r = persist.reserve(pb, st))) return r;
+        m.block = persist.base;
+    }
     if ((r = scratch.reserve(sb, st))) return r;
     struct GiveBack {
         Arena& ar;
@@ -1003,7 +1019,7 @@ sl_status setup_mesh(const SetupArgs& a, const sl_options& o, DevMesh& m, int32_
         k_init_coords<double><<<gb, kBS, 0, st>>>(a.coords, m.perm, n, o.layout == SL_SOA, xd, xd + n2);
     }
     // tile path for Form A; the node path's rows and fans otherwise
-    if (want_tiles && (r = build_tiles(a, m, T, mesh, st, persist, scratch))) return r;
+    if (want_tiles && (r = build_tiles(a, m, resolve_tile_nodes(o), mesh, st, persist, scratch))) return r;
     if (m.tile_nodes == 0 && m.precision == SL_F32 && m.n_free > 0)
         return fail(SL_EINVAL, "single precision needs the tile path, and this mesh does not fit it");
     if (m.tile_nodes == 0) {
