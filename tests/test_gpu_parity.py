@@ -546,6 +546,26 @@ def test_batch_of_one_with_tolerance():
     assert (outs[0] == ref.coords).all()
 
 
+def test_batch_bad_member_then_batches_in_both_precisions():
+    """The meshes of a batch share one device block: a member that fails
+    validation is named and fails the call, and the batches after it, in
+    double and single precision, still give the oracle's results."""
+    ms = [meshgen.make_grid(n, "random", 0.4, 640 + n) for n in (18, 26, 37)]
+    bad = ms[1].copy()
+    bad.nbr_idx[5] = bad.n_nodes + 7                 # a neighbour id out of range
+    with pytest.raises(sl.SmartlapError) as e:
+        sl.batch_smooth([ms[0], ms[2], bad], 4)
+    assert e.value.status == sl.SL_EINVAL and "mesh 2" in str(e.value)
+    outs, reps, br = sl.batch_smooth(ms, 7)
+    for m, X, rep in zip(ms, outs, reps):
+        ref = oracle.smooth(m, 7)
+        assert rep.accepted_total == int(ref.accepted.sum()) and (X == ref.coords).all()
+    outs, reps, br = sl.batch_smooth(ms[::-1], 7, precision="f32")
+    for m, X, rep in zip(ms[::-1], outs, reps):
+        ref = oracle.smooth(m, 7, precision="f32")
+        assert rep.accepted_total == int(ref.accepted.sum()) and (X == ref.coords).all()
+
+
 def test_server_mix_equals_single_and_oracle():
     """Requests of different sizes, caps and tolerances, submitted at once
     and while others run: each result equals its oracle run (and therefore
