@@ -169,10 +169,58 @@ __global__ __launch_bounds__(kBS) void k_scan_tiles(const int32_t* __restrict__ 
     }
 }
 
+// Exclusive scan of a short in[0..n) by one work-group, kSumsBS*kScanPer
+// values at a time with a running carry: one launch in place of three, for
+// setups whose time goes into launches (a batch of small meshes).  In place
+// (in == out) is allowed: every value is read and written by one work-item.
+__global__ __launch_bounds__(kSumsBS) void k_scan_one(const int32_t* in, int32_t* out, int64_t n, bool vec,
+                                                      int32_t* total)
+{
+    __shared__ int32_t s_wave[kSumsBS / 64];
+    int32_t carry = 0;
+    for (int64_t c0 = 0; c0 < n; c0 += static_cast<int64_t>(kSumsBS) * kScanPer) {
+        const int64_t base = c0 + static_cast<int64_t>(threadIdx.x) * kScanPer;
+        int32_t v[kScanPer];
+        scan_load(in, n, base, vec, v);
+        int32_t x = 0;
+#pragma unroll
+        for (int j = 0; j < kScanPer; ++j) x += v[j];
+        int32_t all;
+        int32_t run = carry + group_excl_scan<kSumsBS>(x, s_wave, &all);
+#pragma unroll
+        for (int j = 0; j < kScanPer; ++j) {
+            const int32_t t = v[j];
+            v[j] = run;
+            run += t;
+        }
+        if (vec && base + kScanPer <= n) {
+            int4* p = reinterpret_cast<int4*>(out + base);
+#pragma unroll
+            for (int q = 0; q < kScanPer / 4; ++q) p[q] = make_int4(v[4 * q], v[4 * q + 1], v[4 * q + 2], v[4 * q + 3]);
+        } else {
+#pragma unroll
+            for (int j = 0; j < kScanPer; ++j)
+                if (base + j < n) out[base + j] = v[j];
+        }
+        carry += all;
+    }
+    if (threadIdx.x == 0) *total = carry;
+}
+
+// Scans this long or shorter take the one-launch path (at most 16 passes of
+// its loop).
+constexpr int64_t kScanOneMax = int64_t(16) * kSumsBS * kScanPer;
+
 // Exclusive scan of in[0..n) into out[0..n); *total = sum.  The tile sums
 // come from `ar` when given, else from the allocator.
 sl_status scan_rec(const int32_t* in, int32_t* out, int64_t n, int32_t* total, hipStream_t st, Arena* ar)
 {
+    if (n <= kScanOneMax) {
+        const bool vec1 = ((reinterpret_cast<uintptr_t>(in) | reinterpret_cast<uintptr_t>(out)) & 15) == 0;
+        k_scan_one<<<1, kSumsBS, 0, st>>>(in, out, n, vec1, total);
+        SL_HIP(hipGetLastError());
+        return SL_OK;
+    }
     const int nb = div_up(n > 0 ? n : 1, kScanTile);
     int32_t* sums = nullptr;
     sl_status r = ar ? ar->take(&sums, static_cast<size_t>(nb)) : dalloc(&sums, static_cast<size_t>(nb), st);

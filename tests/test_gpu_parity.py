@@ -99,6 +99,24 @@ def test_ragged_sizes(n):
     assert_parity(meshgen.make_grid(n, "random", 0.4, 100 + n), 5)
 
 
+@pytest.mark.parametrize("side", [128, 129, 130, 512, 513])
+def test_scan_chunk_boundaries(side):
+    """Sizes where setup's scans (node flags, the node path's rows and fans
+    over free nodes, the adjacency builder's counts) end at or one past a
+    chunk of the one-launch scan (16,384 values: 128^2 nodes, 130^2 with
+    128^2 free), at its limit (262,144 = 512^2) and above it (513^2, the
+    three-pass scan): both kernels equal the oracle, and the device
+    adjacency equals the generators' builder."""
+    m = meshgen.make_grid(side, "random", 0.4, 700 + side)
+    X, rep, ref, nd = assert_parity(m, 3)
+    assert nd == 0
+    Xn, rn, _ = run_gpu(m, 3, kernel="node")
+    assert rn.kernel_used == sl.KERNELS["node"] and (Xn == X).all()
+    got = sl.build_adjacency(m.n_nodes, m.tris)
+    want = (m.nbr_ptr, m.nbr_idx, m.tri_ptr, m.tri_idx, m.boundary)
+    assert all(np.array_equal(np.asarray(g), np.asarray(w)) for g, w in zip(got, want))
+
+
 def test_annulus_and_permuted():
     assert_parity(meshgen.make_annulus(40, 64, seed=4), 12)
     assert_parity(meshgen.permute_mesh(meshgen.make_grid(50, "random", 0.4, 7), 8), 12)
