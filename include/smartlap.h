@@ -213,6 +213,9 @@ typedef struct {
  * and the sweep loop runs as a captured HIP graph.  Every mesh gets exactly
  * the result a separate smooth_mesh call with the same options would give.
  * iterations and tol apply to every mesh (each stops on its own).
+ * Device memory: the meshes' own arrays are taken as one allocation (about
+ * 135 bytes per node in double precision), or one per mesh when that single
+ * allocation fails; setup temporaries are per mesh and short-lived.
  * reports: nullable, n_meshes entries.  batch: nullable.
  * On an error in mesh i the message names i and no coords are written.
  */
