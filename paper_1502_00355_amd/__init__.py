@@ -246,7 +246,14 @@ def _desc(mesh, copy_coords=True):
 def batch_smooth(meshes, iterations: int, tol: float = 0.0, **opts):
     """Smooths many meshes in one batched run.  Returns (list of result
     coordinate arrays, list of Report, BatchReport)."""
-    descs, keeps = zip(*[_desc(m) for m in meshes])
+    if len(meshes) > 64:
+        # the output copies on host threads (numpy copies run without the
+        # GIL): a first copy into fresh pages is bound by page faults
+        from concurrent.futures import ThreadPoolExecutor
+        with ThreadPoolExecutor(max(1, min(16, os.cpu_count() or 1))) as ex:
+            descs, keeps = zip(*ex.map(_desc, meshes, chunksize=16))
+    else:
+        descs, keeps = zip(*[_desc(m) for m in meshes])
     arr = (MeshDesc * len(descs))(*descs)
     reps = (Report * len(descs))()
     br = BatchReport()
