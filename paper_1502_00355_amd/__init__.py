@@ -251,7 +251,7 @@ def batch_smooth(meshes, iterations: int, tol: float = 0.0, **opts):
         # GIL): a first copy into fresh pages is bound by page faults
         from concurrent.futures import ThreadPoolExecutor
         with ThreadPoolExecutor(max(1, min(16, os.cpu_count() or 1))) as ex:
-            descs, keeps = zip(*ex.map(_desc, meshes, chunksize=16))
+            descs, keeps = zip(*ex.map(_desc, meshes))
     else:
         descs, keeps = zip(*[_desc(m) for m in meshes])
     arr = (MeshDesc * len(descs))(*descs)
