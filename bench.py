@@ -330,6 +330,19 @@ def run_batch(args, sl):
     _, _, br2 = sl.batch_smooth(meshes, iters)
     el_b2 = time.perf_counter() - t
     log("batched again: %.3f s (setup %.1f ms, results %.1f ms)" % (el_b2, br2.setup_ms, br2.results_ms))
+    upd = free * iters
+    out = {
+        "workload": "batch%d_grids_side24-450_random_j0.35_seeds10000+" % M,
+        "meshes": M, "nodes": nodes, "free_nodes": free, "sweeps": iters,
+        "batched_node_updates_per_s": upd / el_b, "batched_s": el_b,
+        "batched_setup_ms": br.setup_ms, "batched_graph_ms": br.graph_ms, "batched_sweep_ms": br.sweep_ms,
+        "batched_results_ms": br.results_ms,
+        "batched_sweep_node_updates_per_s": upd / (br.sweep_ms / 1e3),
+        "batched_repeat_s": el_b2, "batched_repeat_setup_ms": br2.setup_ms,
+        "tiles": br.tiles, "graph_used": bool(br.graph_used), "autotune": tuning,
+    }
+    if not args.plain:
+        return out
     plain_sweep_ms = 0.0
     t = time.perf_counter()
     for m in meshes:
@@ -337,7 +350,6 @@ def run_batch(args, sl):
         plain_sweep_ms += rep.sweep_ms
     el_p = time.perf_counter() - t
     log("plain: %.3f s (sweeps %.1f ms)" % (el_p, plain_sweep_ms))
-    upd = free * iters
     return {
         "workload": "batch%d_grids_side24-450_random_j0.35_seeds10000+" % M,
         "meshes": M, "nodes": nodes, "free_nodes": free, "sweeps": iters,
@@ -474,6 +486,8 @@ def main():
     ap.add_argument("--no-autotune", dest="autotune", action="store_false")
     ap.add_argument("--no-f32", dest="f32", action="store_false")
     ap.add_argument("--batch-meshes", type=int, default=1000)
+    ap.add_argument("--no-plain", dest="plain", action="store_false",
+                    help="batch mode: skip the separate-calls comparison")
     ap.add_argument("--converge-cap", type=int, default=100000)
     ap.add_argument("--serve-rates", default="10,100,1000,2000")
     ap.add_argument("--serve-pool", type=int, default=48)
