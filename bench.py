@@ -350,20 +350,13 @@ def run_batch(args, sl):
         plain_sweep_ms += rep.sweep_ms
     el_p = time.perf_counter() - t
     log("plain: %.3f s (sweeps %.1f ms)" % (el_p, plain_sweep_ms))
-    return {
-        "workload": "batch%d_grids_side24-450_random_j0.35_seeds10000+" % M,
-        "meshes": M, "nodes": nodes, "free_nodes": free, "sweeps": iters,
-        "batched_node_updates_per_s": upd / el_b, "batched_s": el_b,
-        "batched_setup_ms": br.setup_ms, "batched_graph_ms": br.graph_ms, "batched_sweep_ms": br.sweep_ms,
-        "batched_results_ms": br.results_ms,
-        "batched_sweep_node_updates_per_s": upd / (br.sweep_ms / 1e3),
+    out.update({
         "plain_node_updates_per_s": upd / el_p, "plain_s": el_p, "plain_sweep_ms": plain_sweep_ms,
         "plain_sweep_node_updates_per_s": upd / (plain_sweep_ms / 1e3),
         "speedup_whole_job": el_p / el_b, "speedup_sweeps": plain_sweep_ms / br.sweep_ms,
-        "batched_repeat_s": el_b2, "batched_repeat_setup_ms": br2.setup_ms,
         "speedup_whole_job_repeat": el_p / el_b2,
-        "tiles": br.tiles, "graph_used": bool(br.graph_used), "autotune": tuning,
-    }
+    })
+    return out
 
 
 def serve_requests(rate, count, pool, rng):
