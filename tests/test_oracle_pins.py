@@ -463,3 +463,24 @@ def test_f32_centroid_sums_in_float_in_row_order():
     assert r.flags[0, 0] == 1 and r.coords[0].tolist() == [0.25, 0.25]
     r64 = oracle.smooth(m, 1)
     assert r64.flags[0, 0] == 1 and r64.coords[0, 0] == (1 + 3 * t) / 4
+
+
+def test_f64_centroid_sums_in_row_order():
+    """Neighbour x-coordinates 1, 2^-53, 2^-53, 2^-53 in row order: each
+    addition of 2^-53 (half an ulp of 1) to 1 is a tie that rounds back to 1,
+    so the row-order sum is exactly 1 and the centroid's x exactly 0.25.
+    Summed in reverse, sorted or pairwise, the small terms first combine and
+    survive (1 + 2^-51 or 1 + 2^-52), so any other order moves the node
+    somewhere else.  The exact rational decision accepts with a wide margin,
+    so the node lands on the rounded centroid."""
+    t = 2.0 ** -53
+    ring = np.array([[1.0, 0.25], [t, 0.75], [t, 0.25], [t, -0.25]])
+    m = meshgen.star_mesh(np.array([0.1, 0.25]), ring)
+    assert m.nbr_idx[m.nbr_ptr[0]:m.nbr_ptr[1]].tolist() == [1, 2, 3, 4]
+    d = exact_sweep(m.coords, m.tris, m.boundary)[0]
+    assert d.accept_ge and d.rel_margin > Fraction(1, 100)
+    # the other orders give other sums (plain float arithmetic, no oracle)
+    assert ((t + t) + t) + 1.0 == 1.0 + 2.0 ** -51
+    assert (1.0 + t) + (t + t) == 1.0 + 2.0 ** -52
+    r = oracle.smooth(m, 1)
+    assert r.flags[0, 0] == 1 and r.coords[0].tolist() == [0.25, 0.25]
