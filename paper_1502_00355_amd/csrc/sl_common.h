@@ -29,7 +29,7 @@ sl_status fail(sl_status st, const std::string& msg);
 enum : uint32_t {
     VE_PTR = 1u << 0,       // CSR offsets not monotone / out of range          -> EINVAL
     VE_RANGE = 1u << 1,     // node or triangle id out of range                 -> EINVAL
-    VE_COORD = 1u << 2,     // coordinate not finite or |x| >= 2^500            -> EINVAL
+    VE_COORD = 1u << 2,     // coordinate not finite or |x| >= 2^500 (f32: 2^61) -> EINVAL
     VE_SELF = 1u << 3,      // node lists itself as a neighbour                 -> ETOPO
     VE_TRIREP = 1u << 4,    // triangle with a repeated vertex                  -> ETOPO
     VE_NOTIN = 1u << 5,     // incident triangle does not contain its node      -> ETOPO
@@ -37,7 +37,14 @@ enum : uint32_t {
     VE_EMPTY = 1u << 7,     // free node without neighbours                     -> ETOPO
     VE_VALENCE = 1u << 8,   // free node valence > 127                          -> ETOPO
     VE_ASYM = 1u << 9,      // neighbour rows not symmetric (coloured form)     -> ETOPO
+    // Not an error: a triangle listed in a free node's incidence row is
+    // missing from the row of another of its free vertices.  The tile path
+    // lists each triangle once per tile and scores it for every own vertex,
+    // so it needs consistent rows; such a mesh runs on the node path, which
+    // reads each node's own row.
+    VI_INCIDENCE = 1u << 16,
 };
+constexpr uint32_t kValErrors = 0xFFFFu;   // the bits above that reject the input
 constexpr int kMaxValence = 127;   // 7-bit neighbour slots in a fan entry
 
 // Statistics gathered during validation.
@@ -83,6 +90,9 @@ void dfree(T*& p, hipStream_t st)
 // and it is tried once more.
 sl_status block_take(unsigned char** p, size_t bytes, hipStream_t st);
 void block_give(unsigned char*& p, hipStream_t st);
+constexpr size_t kBlockCacheBytes = size_t(16) << 30;   // cached bytes kept per device at most
+// Frees the current device's cached blocks and trims its stream-ordered pool.
+sl_status release_cached_memory();
 
 inline int div_up(int64_t a, int64_t b) { return static_cast<int>((a + b - 1) / b); }
 

@@ -251,6 +251,8 @@ struct ValArgs {
     const uint8_t* boundary;
     int64_t nnz, ninc;
     int check_symmetry;
+    int check_incidence;   // look for incidence rows that disagree between free vertices (tile path)
+    double coord_limit;    // coordinates must be below this in magnitude
 };
 
 constexpr int kRowRegs = 16;
@@ -282,9 +284,10 @@ __global__ __launch_bounds__(kBS) void k_validate_nodes(ValArgs a, ValStats* __r
     int is_free = 0, deg = 0, inc = 0;
     if (i < a.n) {
         const double x = a.coords[2 * static_cast<int64_t>(i)], y = a.coords[2 * static_cast<int64_t>(i) + 1];
-        // finite and below 2^500 in magnitude: squared edge lengths and cross
+        // finite and below the limit in magnitude (2^500 in double, 2^61 in
+        // single precision): squared edge lengths, their sums and cross
         // products cannot overflow, so every quality is a finite number
-        if (!(fabs(x) < 0x1p500) || !(fabs(y) < 0x1p500)) e |= VE_COORD;
+        if (!(fabs(x) < a.coord_limit) || !(fabs(y) < a.coord_limit)) e |= VE_COORD;
         const int32_t b = a.nbr_ptr[i], en = a.nbr_ptr[i + 1];
         const bool row_ok = 0 <= b && b <= en && en <= a.nnz;
         const int32_t tb = a.tri_ptr[i], te = a.tri_ptr[i + 1];
@@ -350,6 +353,16 @@ __global__ __launch_bounds__(kBS) void k_validate_nodes(ValArgs a, ValStats* __r
                     const int32_t o1 = v0 == i ? v1 : (v1 == i ? v2 : v0);
                     const int32_t o2 = v0 == i ? v2 : (v1 == i ? v0 : v1);
                     if (is_free && row_ok && (!in_row(o1) || !in_row(o2))) e |= VE_MISSING;
+                    if (is_free && a.check_incidence) {
+                        // each other free vertex lists t too (offsets out of
+                        // range are reported by that vertex's own check)
+                        auto lists_t = [&](int32_t o) {
+                            if (o < 0 || o >= a.n || a.boundary[o] != 0) return true;
+                            const int32_t ob = a.tri_ptr[o], oe = a.tri_ptr[o + 1];
+                            return !(0 <= ob && ob <= oe && oe <= a.ninc) || row_has(a.tri_idx, ob, oe, t[u]);
+                        };
+                        if (!lists_t(o1) || !lists_t(o2)) e |= VI_INCIDENCE;
+                    }
                 }
             }
         }
@@ -949,7 +962,8 @@ sl_status setup_mesh(const SetupArgs& a, const sl_options& o, DevMesh& m, int32_
     if ((r = scratch.take(&vs, 1)) || (r = scratch.take(&vpart, gb))) return r;
     SL_HIP(hipMemsetAsync(vs, 0, sizeof(ValStats), st));
     ValArgs va{a.coords, n, a.nbr_ptr, a.nbr_idx, a.tri_ptr, a.tri_idx, a.tris, a.n_tris, a.boundary,
-               a.nnz, a.ninc, o.form == SL_INPLACE_COLORED};
+               a.nnz, a.ninc, o.form == SL_INPLACE_COLORED, want_tiles,
+               o.precision == SL_F32 ? 0x1p61 : 0x1p500};
     if (a.n_tris > 0) k_validate_tris<<<div_up(a.n_tris, kBS), kBS, 0, st>>>(a.tris, a.n_tris, n, vs);
     k_validate_nodes<<<gb, kBS, 0, st>>>(va, vpart);
     k_validate_fold<<<1, 1024, 0, st>>>(vpart, gb, vs);
@@ -961,10 +975,12 @@ sl_status setup_mesh(const SetupArgs& a, const sl_options& o, DevMesh& m, int32_
         std::string msg = "invalid input:";
         if (h.err & VE_PTR) msg += " CSR offsets not monotone or out of range;";
         if (h.err & VE_RANGE) msg += " node or triangle id out of range;";
-        if (h.err & VE_COORD) msg += " coordinate not finite or of magnitude >= 2^500;";
+        if (h.err & VE_COORD)
+            msg += o.precision == SL_F32 ? " coordinate not finite or of magnitude >= 2^61 (single precision);"
+                                         : " coordinate not finite or of magnitude >= 2^500;";
         return fail(SL_EINVAL, msg);
     }
-    if (h.err) {
+    if (h.err & kValErrors) {
         std::string msg = "invalid topology:";
         if (h.err & VE_SELF) msg += " node lists itself as a neighbour;";
         if (h.err & VE_TRIREP) msg += " triangle with a repeated vertex;";
@@ -1067,9 +1083,13 @@ sl_status setup_mesh(const SetupArgs& a, const sl_options& o, DevMesh& m, int32_
         k_init_coords<double><<<gb, kBS, 0, st>>>(a.coords, m.perm, n, o.layout == SL_SOA, xd, xd + n2);
     }
     // tile path for Form A; the node path's rows and fans otherwise
-    if (want_tiles && (r = build_tiles(a, m, resolve_tile_nodes(o), mesh, st, persist, scratch))) return r;
+    const bool tiles_ok = (h.err & VI_INCIDENCE) == 0;
+    if (want_tiles && tiles_ok && (r = build_tiles(a, m, resolve_tile_nodes(o), mesh, st, persist, scratch)))
+        return r;
     if (m.tile_nodes == 0 && m.precision == SL_F32 && m.n_free > 0)
-        return fail(SL_EINVAL, "single precision needs the tile path, and this mesh does not fit it");
+        return fail(SL_EINVAL, tiles_ok ? "single precision needs the tile path, and this mesh does not fit it"
+                                        : "single precision needs the tile path, which needs every free vertex of "
+                                          "a listed triangle to list it too");
     if (m.tile_nodes == 0) {
         // (a mesh that did not fit the tile path gave the tile arrays' room back,
         // which bounds this)

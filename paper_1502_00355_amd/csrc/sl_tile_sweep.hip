@@ -54,9 +54,10 @@ struct Real<float> {
 };
 
 // Minimum into an LDS value (one ds_min_f64 / ds_min_f32).  Qualities are
-// finite -- coordinates are validated below 2^500 in magnitude and S == 0
-// gives 0 -- so no NaN reaches it; which zero a min keeps when +0 meets -0
-// does not matter, the accept test compares them equal.
+// finite -- coordinates are validated below 2^500 (single precision: 2^61)
+// in magnitude and S == 0 gives 0 -- so no NaN reaches it; which zero a min
+// keeps when +0 meets -0 does not matter, the accept test compares them
+// equal.
 template <typename R>
 __device__ __forceinline__ void lds_min(R* p, R v)
 {
