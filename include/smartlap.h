@@ -26,9 +26,14 @@
  *     error a message is available from sl_last_error() (per thread), and
  *     output arrays are left untouched.
  *   - Ownership: the caller owns every array it passes.  The library copies
- *     or reads them before the call returns and keeps no pointer to them.
- *     Device memory the library allocates is freed before the call returns
- *     (or in the matching *_destroy call for handles).
+ *     or reads them before the call returns (or, for the *_async calls,
+ *     before the work they queue completes) and keeps no pointer to them.
+ *   - Device memory: what the library allocates for a call is given back
+ *     when the call's work is done (for handles and servers: in the matching
+ *     *_destroy call).  Given-back blocks are kept for reuse by later calls,
+ *     up to 16 GiB per device, and memory the runtime's stream-ordered pool
+ *     frees stays reserved in that pool; sl_release_cached_memory() returns
+ *     both to the device.
  *   - Indices are 0-based int32.  Arrays are dense, no padding.
  */
 #ifndef SMARTLAP_H
@@ -51,7 +56,8 @@ typedef enum {
     SL_OK = 0,
     SL_EINVAL = -1,    /* null pointer, size <= 0, non-monotone ptr, index out of range,
                           iterations < 0, coordinate not finite or of magnitude >= 2^500
-                          (so that no squared length overflows), bad option value */
+                          (2^61 in single precision: so that no squared length or sum
+                          of them overflows), bad option value */
     SL_ETOPO = -2,     /* self neighbour, triangle with a repeated vertex, incident triangle
                           not containing its node, a vertex of an incident triangle missing
                           from the node's neighbour row, free node without neighbours,
@@ -147,7 +153,11 @@ SL_API void sl_options_default(sl_options* opts);
  * nbr_idx   nbr_ptr[n_nodes] neighbour ids; the order within a row is the
  *           summation order of the centroid.
  * tri_ptr   n_nodes+1 offsets into tri_idx (CSR node -> incident triangle).
- * tri_idx   tri_ptr[n_nodes] triangle ids; each must contain its node.
+ * tri_idx   tri_ptr[n_nodes] triangle ids; each must contain its node.  A
+ *           node's tests use the triangles of its own row only.  The tile
+ *           kernel needs each listed triangle to be listed by all of its
+ *           free vertices; a mesh whose rows disagree runs on the node kernel
+ *           (same results).
  * tris      n_tris x 3 vertex ids; the stored order is the evaluation order
  *           of the quality (CCW for a positive quality).
  * n_tris    >= 0.
@@ -221,6 +231,77 @@ typedef struct {
  */
 SL_API sl_status sl_batch_smooth(const sl_mesh_desc* meshes, int32_t n_meshes, int32_t iterations, double tol,
                                  const sl_options* opts, sl_report* reports, sl_batch_report* batch);
+
+/* ---- mesh handles --------------------------------------------------------
+ * A mesh set up once -- validated, reordered and tiled on the device, as the
+ * paper's mesh object holds vertices with their neighbours and incident
+ * triangles (Sec. 3.2) -- and kept resident, so that it can be smoothed any
+ * number of times, alone or batched with other handles, without uploading
+ * or setting it up again.  Sweeps continue where the last call stopped:
+ * k sweeps and then k more give exactly the result of 2k sweeps in one
+ * smooth_mesh call.  Options are fixed at creation (automatic values
+ * resolved then); flags_out is ignored and the resident kernel is not used
+ * (Form B runs on the node kernel).  A handle belongs to the device that
+ * was current at creation, and calls on it must be made with that device
+ * current; it is not thread-safe (one call at a time per handle).  Work on
+ * a handle is ordered across streams: each call's work runs after the
+ * previous call's. */
+typedef struct sl_mesh sl_mesh;
+
+/* Creates a handle from host arrays (as for smooth_mesh; desc->coords gives
+ * the initial positions and is not written).  Synchronous.  Device memory:
+ * about 135 bytes per node in double precision, freed by sl_mesh_destroy. */
+SL_API sl_status sl_mesh_create(const sl_mesh_desc* desc, const sl_options* opts, sl_mesh** out);
+
+/* The same from device arrays (as for smooth_mesh_device), read on `stream`
+ * (a hipStream_t, NULL = the null stream); returns when the handle is ready
+ * and the arrays are no longer needed. */
+SL_API sl_status sl_mesh_create_device(const double* coords, int32_t n_nodes, const int32_t* nbr_ptr,
+                                       const int32_t* nbr_idx, const int32_t* tri_ptr, const int32_t* tri_idx,
+                                       const int32_t* tris, int32_t n_tris, const uint8_t* boundary,
+                                       const sl_options* opts, void* stream, sl_mesh** out);
+
+/* Queues `iterations` more sweeps (>= 0) on `stream`.  tol <= 0: exactly
+ * that many, and the call returns without waiting for the device.  tol > 0:
+ * stop after the first sweep whose largest squared displacement is below
+ * tol*tol; the call then reads the sweep state back after every 32 sweeps
+ * and returns once the mesh has stopped (the device is idle for the mesh). */
+SL_API sl_status sl_mesh_smooth_async(sl_mesh* mesh, int32_t iterations, double tol, void* stream);
+
+/* Sweeps several handles together, `iterations` more sweeps each (tol as
+ * for sl_mesh_smooth_async, each mesh stopping on its own): one launch per
+ * sweep over the tiles of every handle, queued on `stream`.  Every handle
+ * gets exactly the result of sweeping it alone.  The handles must share
+ * form, accept rule, layout and precision, those on the tile path their
+ * tile size; no handle may appear twice.  batch: nullable; filled with what
+ * is known when the call returns (tiles, meshes on the tile path, node
+ * updates, host time of the call; its device times are 0). */
+SL_API sl_status sl_mesh_smooth_batch_async(sl_mesh* const* meshes, int32_t n_meshes, int32_t iterations,
+                                            double tol, void* stream, sl_batch_report* batch);
+
+/* Copies the current positions to host memory (n_nodes x 2 doubles, the
+ * caller's node order) after the handle's queued work; report (nullable) is
+ * filled with the handle's totals: sweeps run since creation, accepted
+ * counts, the setup time and the device time of the last single-handle
+ * smooth call.  Synchronous. */
+SL_API sl_status sl_mesh_download(sl_mesh* mesh, double* coords, sl_report* report);
+
+/* The same into device memory (16-byte aligned), queued on `stream` after
+ * the handle's queued work; returns without waiting. */
+SL_API sl_status sl_mesh_download_device(sl_mesh* mesh, double* coords, void* stream);
+
+/* The handle's totals as for sl_mesh_download, without the positions. */
+SL_API sl_status sl_mesh_get_report(sl_mesh* mesh, sl_report* report);
+
+/* Waits for the handle's queued work and frees its device memory.  NULL is
+ * ignored. */
+SL_API void sl_mesh_destroy(sl_mesh* mesh);
+
+/* Frees the device blocks the library keeps for reuse on the current
+ * device and trims the runtime's stream-ordered pool to what is in use.
+ * Call it when another user of the device needs the memory; later calls
+ * allocate again. */
+SL_API sl_status sl_release_cached_memory(void);
 
 /* ---- adjacency from a triangle list -------------------------------------
  * Builds the inputs the smoothing calls take from a bare triangle list, the
@@ -309,6 +390,7 @@ typedef struct {
     size_t hbm_budget_bytes;    /* admission limit on estimated footprints; 0 = 200 GiB */
     int32_t max_active;         /* requests swept together at most; 0 = 256 */
     int32_t sweeps_per_step;    /* sweeps between two scheduling decisions; 0 = 8 */
+    int32_t setup_threads;      /* threads that upload and set up admitted requests; 0 = 4, at most 64 */
 } sl_server_config;
 
 typedef struct {

@@ -89,7 +89,7 @@ class Tuning(ctypes.Structure):
 
 class ServerConfig(ctypes.Structure):
     _fields_ = [("hbm_budget_bytes", ctypes.c_size_t), ("max_active", ctypes.c_int32),
-                ("sweeps_per_step", ctypes.c_int32)]
+                ("sweeps_per_step", ctypes.c_int32), ("setup_threads", ctypes.c_int32)]
 
 
 class RequestTimes(ctypes.Structure):
@@ -155,6 +155,25 @@ def lib():
         L.sl_server_get_stats.restype = ctypes.c_int
         L.sl_server_destroy.argtypes = [p]
         L.sl_server_destroy.restype = None
+        L.sl_mesh_create.argtypes = [ctypes.POINTER(MeshDesc), ctypes.POINTER(Options), ctypes.POINTER(p)]
+        L.sl_mesh_create.restype = ctypes.c_int
+        L.sl_mesh_create_device.argtypes = [p, i32, p, p, p, p, p, i32, p, ctypes.POINTER(Options), p,
+                                            ctypes.POINTER(p)]
+        L.sl_mesh_create_device.restype = ctypes.c_int
+        L.sl_mesh_smooth_async.argtypes = [p, i32, d, p]
+        L.sl_mesh_smooth_async.restype = ctypes.c_int
+        L.sl_mesh_smooth_batch_async.argtypes = [ctypes.POINTER(p), i32, i32, d, p, ctypes.POINTER(BatchReport)]
+        L.sl_mesh_smooth_batch_async.restype = ctypes.c_int
+        L.sl_mesh_download.argtypes = [p, p, ctypes.POINTER(Report)]
+        L.sl_mesh_download.restype = ctypes.c_int
+        L.sl_mesh_download_device.argtypes = [p, p, p]
+        L.sl_mesh_download_device.restype = ctypes.c_int
+        L.sl_mesh_get_report.argtypes = [p, ctypes.POINTER(Report)]
+        L.sl_mesh_get_report.restype = ctypes.c_int
+        L.sl_mesh_destroy.argtypes = [p]
+        L.sl_mesh_destroy.restype = None
+        L.sl_release_cached_memory.argtypes = []
+        L.sl_release_cached_memory.restype = ctypes.c_int
         _lib = L
     return _lib
 
@@ -336,7 +355,7 @@ class Server:
     The arrays of a submitted mesh are kept referenced here until its
     result has been polled."""
 
-    def __init__(self, hbm_budget_bytes=0, max_active=0, sweeps_per_step=0, **opts):
+    def __init__(self, hbm_budget_bytes=0, max_active=0, sweeps_per_step=0, setup_threads=0, **opts):
         cfg = ServerConfig()
         lib().sl_server_config_default(ctypes.byref(cfg))
         if hbm_budget_bytes:
@@ -345,6 +364,8 @@ class Server:
             cfg.max_active = int(max_active)
         if sweeps_per_step:
             cfg.sweeps_per_step = int(sweeps_per_step)
+        if setup_threads:
+            cfg.setup_threads = int(setup_threads)
         self.config = cfg
         o = make_options(**opts)
         h = ctypes.c_void_p()
@@ -402,6 +423,100 @@ class Server:
 
     def __exit__(self, *exc):
         self.close()
+
+
+class Mesh:
+    """A mesh kept on the device (sl_mesh_* in the C ABI): set up once,
+    smoothed any number of times; sweeps continue where the last call
+    stopped.  ``Mesh(host_mesh, **opts)`` uploads a host mesh;
+    ``Mesh.from_device(tensors, **opts)`` takes device tensors as returned by
+    ``to_device``."""
+
+    def __init__(self, mesh=None, _handle=None, **opts):
+        self._h = None
+        if _handle is not None:
+            self._h, self.n_nodes = _handle
+            return
+        d, keep = _desc(mesh, copy_coords=False)
+        o = make_options(**opts)
+        h = ctypes.c_void_p()
+        _check(lib().sl_mesh_create(ctypes.byref(d), ctypes.byref(o), ctypes.byref(h)))
+        self._h = h
+        self.n_nodes = d.n_nodes
+
+    @classmethod
+    def from_device(cls, tensors, stream=None, **opts):
+        import torch
+        coords, nbr_ptr, nbr_idx, tri_ptr, tri_idx, tris, boundary = tensors
+        if stream is None:
+            stream = torch.cuda.current_stream()
+        o = make_options(**opts)
+        h = ctypes.c_void_p()
+        _check(lib().sl_mesh_create_device(coords.data_ptr(), coords.shape[0], nbr_ptr.data_ptr(),
+                                           nbr_idx.data_ptr(), tri_ptr.data_ptr(), tri_idx.data_ptr(),
+                                           tris.data_ptr(), tris.numel() // 3, boundary.data_ptr(), ctypes.byref(o),
+                                           ctypes.c_void_p(stream.cuda_stream), ctypes.byref(h)))
+        return cls(_handle=(h, coords.shape[0]))
+
+    @staticmethod
+    def _stream(stream):
+        import torch
+        return ctypes.c_void_p((stream or torch.cuda.current_stream()).cuda_stream)
+
+    def smooth_async(self, iterations: int, tol: float = 0.0, stream=None):
+        """Queues sweeps on ``stream`` (default: torch's current stream);
+        returns without waiting when tol <= 0."""
+        _check(lib().sl_mesh_smooth_async(self._h, int(iterations), float(tol), self._stream(stream)))
+
+    def download(self):
+        """(positions (n, 2) float64 in the caller's node order, Report)."""
+        out = np.empty((self.n_nodes, 2), np.float64)
+        rep = Report()
+        _check(lib().sl_mesh_download(self._h, out.ctypes.data, ctypes.byref(rep)))
+        return out, rep
+
+    def download_device(self, out, stream=None):
+        """Queues the positions into the (n, 2) float64 device tensor ``out``."""
+        import torch
+        if not out.is_cuda or out.dtype != torch.float64 or not out.is_contiguous() or out.numel() != 2 * self.n_nodes:
+            raise TypeError("expected a contiguous (n, 2) float64 device tensor")
+        _check(lib().sl_mesh_download_device(self._h, out.data_ptr(), self._stream(stream)))
+
+    def report(self) -> Report:
+        rep = Report()
+        _check(lib().sl_mesh_get_report(self._h, ctypes.byref(rep)))
+        return rep
+
+    def close(self):
+        if self._h:
+            lib().sl_mesh_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+
+def smooth_batch_async(handles, iterations: int, tol: float = 0.0, stream=None) -> BatchReport:
+    """Sweeps several Mesh handles together (sl_mesh_smooth_batch_async)."""
+    arr = (ctypes.c_void_p * len(handles))(*[h._h.value for h in handles])
+    br = BatchReport()
+    _check(lib().sl_mesh_smooth_batch_async(arr, len(handles), int(iterations), float(tol), Mesh._stream(stream),
+                                            ctypes.byref(br)))
+    return br
+
+
+def release_cached_memory():
+    """Returns the device memory the library keeps for reuse (sl_release_cached_memory)."""
+    _check(lib().sl_release_cached_memory())
 
 
 def to_device(mesh, device="cuda"):

@@ -220,7 +220,7 @@ namespace {
 // free costs about 0.24 ms of host time, so the count bound is loose and
 // the byte bound is what limits the cache
 constexpr size_t kCacheBlocks = 4096;
-constexpr size_t kCacheBytes = size_t(16) << 30;         // per device
+constexpr size_t kCacheBytes = kBlockCacheBytes;         // per device
 
 struct Cached {
     unsigned char* ptr;
@@ -332,6 +332,25 @@ void block_give(unsigned char*& p, hipStream_t st)
     g_block_cache[dev].push_back(Cached{q, it->second.second, ev});
     g_block_cached[dev] += it->second.second;
     trim_blocks(dev, false, st);
+}
+
+// Frees every cached block of the current device and gives the runtime's
+// stream-ordered pool back its unused memory; returns once both are done.
+sl_status release_cached_memory()
+{
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return fail(SL_EDEVICE, "no current device");
+    PooledStream ps;
+    sl_status r = ps.init();
+    if (r) return r;
+    {
+        std::lock_guard<std::mutex> lk(g_block_mu);
+        trim_blocks(dev, true, ps.s);
+    }
+    SL_HIP(hipStreamSynchronize(ps.s));
+    hipMemPool_t pool;
+    if (hipDeviceGetDefaultMemPool(&pool, dev) == hipSuccess) SL_HIP(hipMemPoolTrimTo(pool, 0));
+    return SL_OK;
 }
 
 }  // namespace sl
