@@ -1,31 +1,36 @@
 // Scheduling core of the serving loop, independent of the device.
 //
-// Requests wait in a FIFO.  The head of the queue is admitted when a slot is
-// free and its footprint fits what is left of the budget (it waits
-// otherwise, and so does everything behind it); one that can never fit, is
-// cancelled or is past its deadline leaves the queue at once.  The loop
-// thread launches a step over every admitted request, admits queued
-// requests while the step runs (an admitted request joins at the next
-// step), then waits for the step and retires the requests that finished,
-// were cancelled or passed their deadline.  A failed admission fails only
-// that request; a failed step fails the requests in it and stops the
-// server, and everything still queued fails with it.
+// Requests wait in a queue.  Setup threads admit them: a request is admitted
+// when a slot is free and its footprint fits what is left of the budget; a
+// queued request that does not fit may be passed by later ones that do, but
+// at most kMaxBypass times, after which nothing passes it until it is
+// admitted.  One that can never fit, is cancelled or is past its deadline
+// leaves the queue at once.  The setup thread then sets the request up
+// (upload and device setup) and hands it to the loop thread, which joins it
+// at the next step.  The loop thread only steps: it launches a step over
+// every set-up request, collects the results of the requests the previous
+// step finished while this one runs, waits for the step and retires the
+// requests that finished, were cancelled or passed their deadline.  A
+// failed admission fails only that request; a failed step fails every
+// request the server holds and stops it.
 //
-// The executor does the device work.  Requirements, all called from the
-// loop thread except footprint():
+// The executor does the device work.  Requirements:
 //   using Payload = ...;                                 per-request device state
-//   size_t footprint(const sl_mesh_desc&);               budget units of a request
-//   sl_status admit(Request&);                           set up (synchronous); on error keeps nothing
+//   size_t footprint(const sl_mesh_desc&);               budget units of a request (any thread)
+//   sl_status admit(Request&);                           set up, synchronously; called by setup
+//                                                        threads, several at once; on error keeps nothing
 //   sl_status launch(const std::vector<Request*>&, bool changed);
 //                                                        start one step (asynchronous); requests with
 //                                                        !joined join now and must be marked joined;
 //                                                        `changed`: the set differs from the last step
-//   bool busy();                                         the launched step still runs
 //   sl_status wait(const std::vector<Request*>&, std::vector<StepOutcome>&);
 //                                                        finish the step: one outcome per request
-//   sl_status collect(Request&, const StepOutcome&);     result and report of a finished request
-//   void release(Request&);                              free its device state
-// Errors are reported through sl::fail / sl_last_error, as everywhere in the
+//   sl_status collect(Request&, const StepOutcome&);     result and report of a finished request; runs
+//                                                        while the next step may be in flight (the
+//                                                        request is in no step any more)
+//   void release(Request&);                              free its device state (any thread)
+// launch, wait and collect are called from the loop thread only.  Errors
+// are reported through sl::fail / sl_last_error, as everywhere in the
 // library.
 #ifndef SL_SCHED_H
 #define SL_SCHED_H
@@ -54,7 +59,11 @@ namespace sched {
 
 using Clock = std::chrono::steady_clock;
 
-enum class Phase { QUEUED, ACTIVE, DONE };
+// A queued request that does not fit the budget is passed by at most this
+// many later ones before the queue waits for it.
+constexpr int32_t kMaxBypass = 64;
+
+enum class Phase { QUEUED, ADMITTING, ACTIVE, DONE };
 
 // A request's state after a step, as the executor read it back.
 struct StepOutcome {
@@ -76,7 +85,10 @@ struct Request {
     std::string error;
     bool cancel = false;
     int32_t slot = -1;
+    int32_t bypassed = 0;       // later requests admitted while this one waited
     bool joined = false;        // stepped by the executor since admission
+    bool finishing = false;     // finished its sweeps; its result is being collected
+    StepOutcome outcome{};      // of its last step
     std::vector<double> result; // n x 2, filled when done
     sl_report report{};
     sl_request_times times{};
@@ -94,14 +106,27 @@ public:
     }
     ~Scheduler() { stop(); }
 
-    void start() { thread_ = std::thread([this] { loop(); }); }
+    void start()
+    {
+        thread_ = std::thread([this] { loop(); });
+        const int32_t n = std::max<int32_t>(1, cfg_.setup_threads);
+        for (int32_t k = 0; k < n; ++k) setup_.emplace_back([this] { setup_loop(); });
+    }
 
-    // Stops the loop thread and releases every admitted request.
+    // Stops the threads and releases every request that holds a slot.
     void stop()
     {
-        stop_.store(true);
+        {
+            std::lock_guard<std::mutex> lk(mu_);
+            stop_ = true;
+        }
         cv_.notify_all();
+        cv_loop_.notify_all();
         if (thread_.joinable()) thread_.join();
+        for (auto& t : setup_)
+            if (t.joinable()) t.join();
+        setup_.clear();
+        std::lock_guard<std::mutex> lk(mu_);
         for (auto& kv : reqs_)
             if (kv.second->slot >= 0) release(kv.second.get());
     }
@@ -110,16 +135,17 @@ public:
 
     sl_status submit(const sl_mesh_desc& d, int32_t iterations, double tol, double deadline_s, uint64_t* id)
     {
+        const double t = now();   // before any wait for the lock
         auto q = std::make_unique<Req>();
         q->desc = d;
         q->iterations = iterations;
         q->tol = tol;
         q->footprint = ex_.footprint(d);
+        q->times.submitted_s = t;
+        q->deadline_s = deadline_s > 0.0 ? t + deadline_s : 0.0;
         std::lock_guard<std::mutex> lk(mu_);
         if (!fatal_.empty()) return fail(SL_EDEVICE, "server stopped: " + fatal_);
         q->id = next_id_++;
-        q->times.submitted_s = now();
-        q->deadline_s = deadline_s > 0.0 ? q->times.submitted_s + deadline_s : 0.0;
         *id = q->id;
         queue_.push_back(q->id);
         reqs_[q->id] = std::move(q);
@@ -154,7 +180,7 @@ public:
         auto it = reqs_.find(id);
         if (it == reqs_.end()) return fail(SL_EINVAL, "unknown request id");
         it->second->cancel = true;
-        cv_.notify_one();
+        cv_.notify_all();
         return SL_OK;
     }
 
@@ -172,13 +198,7 @@ public:
     }
 
 private:
-    // with mu_ held for a queued request
-    void drop(Req* q, sl_status status, const std::string& err)
-    {
-        queue_.pop_front();
-        finish(q, status, err);
-        stats_.failed++;
-    }
+    // ---- with mu_ held
 
     void finish(Req* q, sl_status status, const std::string& err)
     {
@@ -186,9 +206,10 @@ private:
         q->error = err;
         q->phase = Phase::DONE;
         q->times.done_s = now();
+        if (status == SL_OK) stats_.completed++;
+        else stats_.failed++;
     }
 
-    // with mu_ held
     void release(Req* q)
     {
         ex_.release(*q);
@@ -197,88 +218,153 @@ private:
         q->slot = -1;
     }
 
-    // With mu_ held: the head of the queue if it can be admitted now (the
-    // requests at the head that are cancelled, past their deadline or too
-    // large for the budget are finished on the way); nullptr if the queue
-    // is empty or the head must wait.
+    // A queued request to admit now, with its slot and budget taken, or
+    // nullptr.  Requests that are cancelled, past their deadline or too
+    // large for the budget are finished on the way.
     Req* pop_admissible()
     {
-        while (!queue_.empty()) {
-            Req* q = reqs_[queue_.front()].get();
+        int32_t slot = -1;
+        for (int32_t i = 0; i < cfg_.max_active; ++i)
+            if (!slots_[i]) { slot = i; break; }
+        Req* blocked = nullptr;   // the first queued request that did not fit
+        for (auto it = queue_.begin(); it != queue_.end();) {
+            Req* q = reqs_[*it].get();
+            sl_status drop = SL_OK;
+            const char* why = nullptr;
             if (q->cancel) {
-                drop(q, SL_ECANCELED, "cancelled before admission");
+                drop = SL_ECANCELED;
+                why = "cancelled before admission";
+            } else if (q->deadline_s > 0.0 && now() > q->deadline_s) {
+                drop = SL_ETIMEOUT;
+                why = "deadline passed before admission";
+            } else if (q->footprint > cfg_.hbm_budget_bytes) {
+                drop = SL_ENOMEM;
+                why = "request cannot fit the HBM budget";
+            }
+            if (drop) {
+                it = queue_.erase(it);
+                finish(q, drop, why);
                 continue;
             }
-            if (q->deadline_s > 0.0 && now() > q->deadline_s) {
-                drop(q, SL_ETIMEOUT, "deadline passed before admission");
-                continue;
+            if (slot < 0) return nullptr;
+            if (in_use_ + q->footprint <= cfg_.hbm_budget_bytes) {
+                if (blocked) blocked->bypassed++;
+                queue_.erase(it);
+                q->slot = slot;
+                slots_[slot] = q;
+                in_use_ += q->footprint;
+                q->phase = Phase::ADMITTING;
+                q->times.admitted_s = now();
+                return q;
             }
-            if (q->footprint > cfg_.hbm_budget_bytes) {
-                drop(q, SL_ENOMEM, "request cannot fit the HBM budget");
-                continue;
+            if (!blocked) {
+                blocked = q;
+                if (q->bypassed >= kMaxBypass) return nullptr;   // it waits, and so does everything behind it
             }
-            int32_t slot = -1;
-            for (int32_t i = 0; i < cfg_.max_active; ++i)
-                if (!slots_[i]) { slot = i; break; }
-            if (slot < 0 || in_use_ + q->footprint > cfg_.hbm_budget_bytes) return nullptr;
-            queue_.pop_front();
-            q->slot = slot;
-            slots_[slot] = q;
-            in_use_ += q->footprint;
-            q->times.admitted_s = now();
-            return q;
+            ++it;
         }
         return nullptr;
     }
 
+    // Finishes every request the server still holds (the step that failed
+    // has been dealt with), and everything queued.
+    void fail_all(const std::string& why)
+    {
+        for (Req* q : slots_) {
+            if (!q || q->phase == Phase::ADMITTING) continue;   // its setup thread finishes it
+            release(q);
+            finish(q, SL_EDEVICE, "server stopped: " + why);
+        }
+        while (!queue_.empty()) {
+            Req* q = reqs_[queue_.front()].get();
+            queue_.pop_front();
+            finish(q, SL_EDEVICE, "server stopped: " + why);
+        }
+    }
+
+    // ---- threads
+
+    void setup_loop()
+    {
+        for (;;) {
+            Req* q = nullptr;
+            {
+                std::unique_lock<std::mutex> lk(mu_);
+                for (;;) {
+                    if (stop_ || !fatal_.empty()) return;
+                    q = pop_admissible();
+                    if (q) break;
+                    cv_.wait_for(lk, std::chrono::milliseconds(20));
+                }
+            }
+            const sl_status ar = ex_.admit(*q);
+            const std::string msg = ar ? std::string(sl_last_error()) : std::string();
+            {
+                std::lock_guard<std::mutex> lk(mu_);
+                if (ar || !fatal_.empty() || stop_) {
+                    release(q);
+                    if (ar) finish(q, ar, msg);
+                    else if (!fatal_.empty()) finish(q, SL_EDEVICE, "server stopped: " + fatal_);
+                    else finish(q, SL_ECANCELED, "server stopped");
+                } else {
+                    q->phase = Phase::ACTIVE;
+                    q->joined = false;
+                    q->times.started_s = now();
+                }
+            }
+            cv_loop_.notify_one();
+            cv_.notify_all();   // a released slot or budget may admit others
+        }
+    }
+
+    // Collects the results of requests whose sweeps are done, then retires
+    // them.  Called from the loop thread, without mu_.
+    void collect_all(std::vector<Req*>& done)
+    {
+        for (Req* q : done) {
+            const sl_status cs = ex_.collect(*q, q->outcome);
+            const std::string msg = cs ? std::string(sl_last_error()) : std::string();
+            std::lock_guard<std::mutex> lk(mu_);
+            if (cs == SL_OK) stats_.node_updates += q->outcome.node_updates;
+            release(q);
+            finish(q, cs, msg);
+        }
+        if (!done.empty()) cv_.notify_all();
+        done.clear();
+    }
+
     void loop()
     {
-        bool changed = true;
         std::vector<StepOutcome> out;
-        while (!stop_.load()) {
-            // ---- 1. launch one step over every admitted request
+        std::vector<Req*> to_collect;
+        std::vector<uint64_t> last_ids, ids;   // the requests of the last step and of this one
+        for (;;) {
+            // ---- 1. the set-up requests that still sweep
             std::vector<Req*> in_step;
-            for (Req* q : slots_)
-                if (q && q->phase == Phase::ACTIVE) in_step.push_back(q);
-            sl_status r = SL_OK;
-            if (!in_step.empty()) {
-                r = ex_.launch(in_step, changed);
-                changed = false;
+            {
+                std::unique_lock<std::mutex> lk(mu_);
+                auto ready = [&] {
+                    for (Req* q : slots_)
+                        if (q && q->phase == Phase::ACTIVE && !q->finishing) return true;
+                    return false;
+                };
+                if (to_collect.empty())
+                    cv_loop_.wait_for(lk, std::chrono::milliseconds(20), [&] { return stop_ || ready(); });
+                if (stop_) break;
+                for (Req* q : slots_)
+                    if (q && q->phase == Phase::ACTIVE && !q->finishing) in_step.push_back(q);
             }
-            const bool stepping = !in_step.empty();
-
-            // ---- 2. admissions while the step runs; with no step in
-            // flight, one admission starts the next step
-            for (;;) {
-                Req* q = nullptr;
-                {
-                    std::unique_lock<std::mutex> lk(mu_);
-                    if (!stepping && queue_.empty())
-                        cv_.wait_for(lk, std::chrono::milliseconds(50),
-                                     [&] { return stop_.load() || !queue_.empty(); });
-                    q = pop_admissible();
-                }
-                if (!q) break;
-                const sl_status ar = ex_.admit(*q);
-                {
-                    std::lock_guard<std::mutex> lk(mu_);
-                    if (ar) {
-                        const std::string msg = sl_last_error();
-                        release(q);
-                        finish(q, ar, msg);
-                        stats_.failed++;
-                    } else {
-                        q->phase = Phase::ACTIVE;
-                        q->joined = false;
-                        q->times.started_s = now();
-                        changed = true;
-                    }
-                }
-                if (!stepping || !ex_.busy()) break;
+            if (in_step.empty()) {
+                collect_all(to_collect);
+                continue;
             }
-            if (!stepping) continue;
-
-            // ---- 3. retire the requests that finished in this step
+            // ---- 2. launch; collect the last step's finished requests meanwhile
+            ids.clear();
+            for (Req* q : in_step) ids.push_back(q->id);
+            sl_status r = ex_.launch(in_step, ids != last_ids);
+            last_ids.swap(ids);
+            collect_all(to_collect);
+            // ---- 3. wait and decide
             out.assign(in_step.size(), StepOutcome{});
             if (!r) r = ex_.wait(in_step, out);
             const std::string step_err = r ? std::string(sl_last_error()) : std::string();
@@ -287,44 +373,47 @@ private:
             stats_.steps++;
             for (size_t k = 0; k < in_step.size(); ++k) {
                 Req* q = in_step[k];
+                q->outcome = out[k];
                 sl_status fs = SL_OK;
                 std::string msg;
-                bool done = false;
                 if (r) {
                     fs = r;
                     msg = step_err;
-                    done = true;
                 } else if (!out[k].active) {
-                    done = true;
+                    // done: collected while the next step runs
+                    q->finishing = true;
+                    to_collect.push_back(q);
+                    continue;
                 } else if (q->cancel) {
                     fs = SL_ECANCELED;
                     msg = "cancelled";
-                    done = true;
                 } else if (q->deadline_s > 0.0 && t > q->deadline_s) {
                     fs = SL_ETIMEOUT;
                     msg = "deadline passed";
-                    done = true;
-                }
-                if (!done) continue;
-                if (fs == SL_OK) {
-                    fs = ex_.collect(*q, out[k]);
-                    if (fs) msg = sl_last_error();
-                }
-                if (fs == SL_OK) {
-                    stats_.completed++;
-                    stats_.node_updates += out[k].node_updates;
                 } else {
-                    stats_.failed++;
+                    continue;
                 }
                 release(q);
                 finish(q, fs, msg);
-                changed = true;
             }
             if (r) {
                 fatal_ = step_err.empty() ? "step failed" : step_err;
-                while (!queue_.empty()) drop(reqs_[queue_.front()].get(), SL_EDEVICE, "server stopped: " + fatal_);
+                for (Req* q : to_collect) {   // (none: a failed step finished its requests)
+                    release(q);
+                    finish(q, SL_EDEVICE, "server stopped: " + fatal_);
+                }
+                to_collect.clear();
+                fail_all(fatal_);
+                cv_.notify_all();
                 break;
             }
+            cv_.notify_all();
+        }
+        // stopping: results not collected yet are dropped with their requests
+        std::lock_guard<std::mutex> lk(mu_);
+        for (Req* q : to_collect) {
+            release(q);
+            finish(q, SL_ECANCELED, "server stopped");
         }
     }
 
@@ -332,14 +421,16 @@ private:
     Exec& ex_;
     Clock::time_point t0_;
     std::mutex mu_;
-    std::condition_variable cv_;
-    std::deque<uint64_t> queue_;                       // queued request ids, FIFO
+    std::condition_variable cv_;        // setup threads: queue, slots or budget changed
+    std::condition_variable cv_loop_;   // loop thread: a request is set up
+    std::deque<uint64_t> queue_;                       // queued request ids, in arrival order
     std::map<uint64_t, std::unique_ptr<Req>> reqs_;    // every request not yet polled
     std::vector<Req*> slots_;                          // admitted requests by slot
     size_t in_use_ = 0;
     uint64_t next_id_ = 1;
-    std::atomic<bool> stop_{false};
+    bool stop_ = false;
     std::thread thread_;
+    std::vector<std::thread> setup_;
     sl_server_stats stats_{};
     std::string fatal_;
 };

@@ -3,8 +3,10 @@
 // The scheduling (queue, admission by slot and HBM budget, cancellation,
 // deadlines, the step loop) is the device-independent core in sl_sched.h;
 // this file is its device executor.  Admission uploads a request's mesh and
-// builds its tiles on a setup stream while the current step keeps sweeping
-// on the compute stream.  A step runs a few sweeps over the tiles of all
+// builds its tiles on a stream of the setup thread that admits it, while
+// the current step keeps sweeping on the compute stream; results are
+// un-permuted and copied out on a third stream while the next step runs.
+// A step runs a few sweeps over the tiles of all
 // joined requests with one launch per sweep (continuous batching): a
 // request joins at the first step after its setup, when its sweep state is
 // written on the compute stream, so a step never sees a request that is half
@@ -43,12 +45,16 @@ struct HipPayload {
     DevMesh mesh;
     int32_t parity0 = 0;        // launch parity when it joined
     MeshState state0{};         // the sweep state it joins with
+    MeshState last{};           // its state after the last step it ran
 };
+
+thread_local int t_bound_device = -1;   // the device a setup thread has made current
 
 }  // namespace
 
-// Device side of the server: one compute stream for the steps, one setup
-// stream for admissions, per-slot sweep states with pinned host mirrors.
+// Device side of the server: one compute stream for the steps, one collect
+// stream for results, pooled streams for admissions, per-slot sweep states
+// with pinned host mirrors.
 struct HipExec {
     using Payload = HipPayload;
     using Req = sched::Request<Payload>;
@@ -56,7 +62,7 @@ struct HipExec {
     sl_options opts{};
     int32_t max_active = 0, sweeps_per_step = 0;
     int device = 0;
-    hipStream_t st_compute = nullptr, st_setup = nullptr;
+    hipStream_t st_compute = nullptr, st_collect = nullptr;
     MeshState* states = nullptr;        // [max_active]
     int32_t* sched = nullptr;           // the tile launches' counters
     MeshState* h_states = nullptr;      // [max_active], pinned: read-back after each step
@@ -69,7 +75,6 @@ struct HipExec {
     int32_t n_work = 0, T = 0, hcap = 0, rcap = 0;
     int32_t wg_per_cu = 0, block = 0;
     int32_t wg_auto = 0;                // wg_per_cu came from the automatic choice
-    bool thread_bound = false;
 
     sl_status init(const sl_server_config& cfg, const sl_options& o)
     {
@@ -81,7 +86,7 @@ struct HipExec {
         sl_status r;
         SL_HIP(hipGetDevice(&device));
         SL_HIP(hipStreamCreateWithFlags(&st_compute, hipStreamNonBlocking));
-        SL_HIP(hipStreamCreateWithFlags(&st_setup, hipStreamNonBlocking));
+        SL_HIP(hipStreamCreateWithFlags(&st_collect, hipStreamNonBlocking));
         if ((r = dalloc(&states, static_cast<size_t>(max_active), st_compute))) return r;
         if ((r = dalloc(&sched, kTileSchedInts, st_compute))) return r;
         SL_HIP(hipMemsetAsync(sched, 0, sizeof(int32_t) * kTileSchedInts, st_compute));
@@ -101,8 +106,8 @@ struct HipExec {
         dfree(work, st_compute);
         dfree(states, st_compute);
         dfree(sched, st_compute);
-        dfree(out, st_compute);
-        for (hipStream_t st : {st_compute, st_setup}) {
+        dfree(out, st_collect);
+        for (hipStream_t st : {st_compute, st_collect}) {
             if (!st) continue;
             (void)hipStreamSynchronize(st);
             (void)hipStreamDestroy(st);
@@ -110,28 +115,33 @@ struct HipExec {
         if (h_states) (void)hipHostFree(h_states);
         if (h_join) (void)hipHostFree(h_join);
         h_states = h_join = nullptr;
-        st_compute = st_setup = nullptr;
+        st_compute = st_collect = nullptr;
     }
 
     size_t footprint(const sl_mesh_desc& d) { return estimate_footprint(d); }
 
     void bind_thread()
     {
-        if (!thread_bound) {
+        if (t_bound_device != device) {
             (void)hipSetDevice(device);
-            thread_bound = true;
+            t_bound_device = device;
         }
     }
 
+    // Called by several setup threads at once: each admission runs on a
+    // pooled stream of its own.
     sl_status admit(Req& q)
     {
         bind_thread();
-        const sl_status r = upload_and_prepare(q.desc, opts, q.slot, q.x.mesh, st_setup);
+        PooledStream ps;
+        sl_status r = ps.init();
+        if (r) return r;
+        r = upload_and_prepare(q.desc, opts, q.slot, q.x.mesh, ps.s);
         if (r) {
-            devmesh_free(q.x.mesh, st_setup);
+            devmesh_free(q.x.mesh, ps.s);
             return r;
         }
-        SL_HIP(hipStreamSynchronize(st_setup));
+        SL_HIP(hipStreamSynchronize(ps.s));
         MeshState& h = q.x.state0;
         h = MeshState{};
         h.iters = q.iterations;
@@ -213,13 +223,12 @@ struct HipExec {
         return SL_OK;
     }
 
-    bool busy() { return hipStreamQuery(st_compute) == hipErrorNotReady; }
-
     sl_status wait(const std::vector<Req*>& in_step, std::vector<sched::StepOutcome>& res)
     {
         if (hipStreamSynchronize(st_compute) != hipSuccess) return fail(SL_EDEVICE, "sweep step failed");
         for (size_t k = 0; k < in_step.size(); ++k) {
             const MeshState& ms = h_states[in_step[k]->slot];
+            in_step[k]->x.last = ms;
             res[k].active = ms.active != 0;
             res[k].sweeps = ms.s;
             res[k].node_updates = static_cast<int64_t>(in_step[k]->x.mesh.n_free) * ms.s;
@@ -227,15 +236,17 @@ struct HipExec {
         return SL_OK;
     }
 
-    // Copies a finished request's positions back to host memory.
+    // Copies a finished request's positions back to host memory, on the
+    // collect stream: the request is in no step any more, so this overlaps
+    // the step that runs meanwhile.
     sl_status collect(Req& q, const sched::StepOutcome&)
     {
         const DevMesh& m = q.x.mesh;
-        const MeshState& ms = h_states[q.slot];
+        const MeshState& ms = q.x.last;
         const size_t n = static_cast<size_t>(m.n);
         if (out_cap < 2 * n) {
-            dfree(out, st_compute);
-            sl_status r = dalloc(&out, 2 * n, st_compute);
+            dfree(out, st_collect);
+            sl_status r = dalloc(&out, 2 * n, st_collect);
             if (r) {
                 out_cap = 0;
                 return r;
@@ -244,10 +255,10 @@ struct HipExec {
         }
         const bool jacobi = opts.form == SL_JACOBI;
         const int src = jacobi ? ((q.x.parity0 + ms.s) & 1) : 0;
-        sl_status r = unpermute_coords(m, src, out, st_compute);
+        sl_status r = unpermute_coords(m, src, out, st_collect);
         if (r) return r;
         q.result.resize(2 * n);
-        if ((r = copy_to_host(q.result.data(), out, 2 * n * sizeof(double), st_compute))) return r;
+        if ((r = copy_to_host(q.result.data(), out, 2 * n * sizeof(double), st_collect))) return r;
         sl_report rep{};
         rep.iterations_run = ms.s;
         rep.n_colors = m.n_colors;
@@ -260,7 +271,9 @@ struct HipExec {
         return SL_OK;
     }
 
-    void release(Req& q) { devmesh_free(q.x.mesh, st_compute); }
+    // After its last step and its collection (stream-ordered on the collect
+    // stream, which follows both).
+    void release(Req& q) { devmesh_free(q.x.mesh, st_collect); }
 };
 
 }  // namespace sl
@@ -279,6 +292,7 @@ void sl_server_config_default(sl_server_config* c)
     c->hbm_budget_bytes = static_cast<size_t>(200) << 30;
     c->max_active = 256;
     c->sweeps_per_step = 8;
+    c->setup_threads = 4;
 }
 
 sl_status sl_server_create(const sl_server_config* cfg, const sl_options* opts, sl_server** out)
@@ -293,6 +307,8 @@ sl_status sl_server_create(const sl_server_config* cfg, const sl_options* opts, 
     if (c.hbm_budget_bytes == 0) c.hbm_budget_bytes = static_cast<size_t>(200) << 30;
     if (c.max_active <= 0) c.max_active = 256;
     if (c.sweeps_per_step <= 0) c.sweeps_per_step = 8;
+    if (c.setup_threads <= 0) c.setup_threads = 4;
+    if (c.setup_threads > 64) return fail(SL_EINVAL, "setup_threads must be <= 64");
     if (c.max_active > kMaxActive) return fail(SL_EINVAL, "max_active must be <= 65536");
     sl_options o;
     sl_options_default(&o);

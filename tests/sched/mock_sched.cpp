@@ -48,6 +48,8 @@ struct Mock {
     int32_t sweeps_per_step = 4;
     int step_us = 500;
     int admit_us = 200;
+    int slow_admit_us = 0;              // admission time of the requests in slow_admit
+    std::set<uint64_t> slow_admit;
     std::set<uint64_t> fail_admit;
     int fail_step_at = -1;
     size_t budget = 0;
@@ -59,16 +61,27 @@ struct Mock {
     size_t live_fp = 0, max_live_fp = 0;
     int max_live = 0;
     std::vector<std::string> violations;
+    int admitting = 0, max_admitting = 0;
     Clock::time_point step_end;
     std::vector<Req*> pending;
 
     size_t footprint(const sl_mesh_desc& d) { return static_cast<size_t>(d.n_nodes); }
 
+    // called by several setup threads at once
     sl_status admit(Req& q)
     {
-        std::this_thread::sleep_for(std::chrono::microseconds(admit_us));
-        if (fail_admit.count(q.id)) return sl::fail(SL_ETOPO, "mock: invalid topology");
+        bool slow, fails;
+        {
+            std::lock_guard<std::mutex> lk(mu);
+            slow = slow_admit.count(q.id) != 0;
+            fails = fail_admit.count(q.id) != 0;
+            admitting++;
+            max_admitting = std::max(max_admitting, admitting);
+        }
+        std::this_thread::sleep_for(std::chrono::microseconds(slow ? slow_admit_us : admit_us));
         std::lock_guard<std::mutex> lk(mu);
+        admitting--;
+        if (fails) return sl::fail(SL_ETOPO, "mock: invalid topology");
         if (q.joined) violations.push_back("admitted request already joined");
         live.insert(q.id);
         live_fp += q.footprint;
@@ -143,11 +156,12 @@ struct Server {
     std::vector<int32_t> keep;   // backing for the descriptors (never read by the mock)
     std::mutex nodes_mu;
     std::map<uint64_t, int32_t> nodes_of;   // result buffers are n_nodes x 2
-    Server(size_t budget, int32_t max_active, int32_t sweeps_per_step = 4)
+    Server(size_t budget, int32_t max_active, int32_t sweeps_per_step = 4, int32_t setup_threads = 2)
     {
         cfg.hbm_budget_bytes = budget;
         cfg.max_active = max_active;
         cfg.sweeps_per_step = sweeps_per_step;
+        cfg.setup_threads = setup_threads;
         ex.sweeps_per_step = sweeps_per_step;
         ex.budget = budget;
         keep.assign(4, 0);
@@ -256,17 +270,81 @@ int main()
         no_violations(s, n);
     });
 
-    run("fifo_head_blocks_and_budget", [](const std::string& n) {
-        Server s(100, 8);
+    run("budget_bypass", [](const std::string& n) {
+        Server s(100, 8, 4, 1);
         s.start();
-        const uint64_t a = s.submit(60, 40);
+        const uint64_t a = s.submit(60, 400);
         const uint64_t b = s.submit(50, 4);    // must wait for a (60 + 50 > 100)
-        const uint64_t c = s.submit(30, 4);    // would fit next to a, but b is ahead of it
+        const uint64_t c = s.submit(30, 4);    // fits next to a: passes b
         auto da = s.wait(a), db = s.wait(b), dc = s.wait(c);
         check(da.st == SL_OK && db.st == SL_OK && dc.st == SL_OK, n, "statuses");
         check(db.t.admitted_s >= da.t.done_s - 1e-3, n, "b admitted before a finished");
-        check(dc.t.admitted_s >= db.t.admitted_s, n, "c overtook b");
+        check(dc.t.admitted_s < db.t.admitted_s && dc.t.done_s < da.t.done_s, n, "c waited behind b");
         check(s.ex.max_live_fp <= 100, n, "budget exceeded");
+        s.stop();
+        no_violations(s, n);
+    });
+
+    run("bypass_is_bounded", [](const std::string& n) {
+        // a holds most of the budget for a while; b does not fit next to it;
+        // a stream of small requests fits: at most kMaxBypass of them pass b
+        Server s(100, 200, 4, 2);
+        s.ex.step_us = 300;
+        s.ex.admit_us = 20;
+        s.start();
+        const uint64_t a = s.submit(60, 600);
+        const uint64_t b = s.submit(50, 4);
+        std::vector<uint64_t> small;
+        for (int k = 0; k < 150; ++k) small.push_back(s.submit(1, 1));
+        auto db = s.wait(b);
+        int before = 0;
+        std::vector<Server::Done> ds;
+        for (auto id : small) ds.push_back(s.wait(id));
+        for (auto& d : ds) before += d.t.admitted_s < db.t.admitted_s;
+        auto da = s.wait(a);
+        check(da.st == SL_OK && db.st == SL_OK, n, "statuses");
+        check(before >= 1 && before <= sl::sched::kMaxBypass, n, "passed b: " + std::to_string(before));
+        check(db.t.admitted_s >= da.t.done_s - 1e-3, n, "b admitted next to a");
+        s.stop();
+        no_violations(s, n);
+    });
+
+    run("setup_does_not_stall_steps", [](const std::string& n) {
+        // b's setup takes 40 ms on a setup thread; a keeps stepping meanwhile
+        Server s(1000, 4, 4, 2);
+        s.ex.step_us = 500;
+        s.ex.slow_admit_us = 40000;
+        s.ex.slow_admit.insert(2);
+        s.start();
+        const uint64_t a = s.submit(10, 40);   // 10 steps of 0.5 ms
+        const uint64_t b = s.submit(10, 4);
+        auto da = s.wait(a), db = s.wait(b);
+        check(b == 2 && da.st == SL_OK && db.st == SL_OK, n, "statuses");
+        check(da.t.done_s < db.t.started_s, n, "a waited for b's setup");
+        s.stop();
+        no_violations(s, n);
+    });
+
+    run("step_failure_with_admissions_in_flight", [](const std::string& n) {
+        // c is being set up while the step that fails runs: it fails too, and
+        // the budget comes back
+        Server s(1000, 4, 4, 2);
+        s.ex.fail_step_at = 3;
+        s.ex.step_us = 2000;
+        s.ex.slow_admit_us = 20000;
+        s.ex.slow_admit.insert(3);
+        s.start();
+        const uint64_t a = s.submit(60, 100000);
+        const uint64_t b = s.submit(60, 100000);
+        std::this_thread::sleep_for(std::chrono::milliseconds(3));
+        const uint64_t c = s.submit(60, 4);
+        auto da = s.wait(a), db = s.wait(b), dc = s.wait(c);
+        check(c == 3 && da.st == SL_EDEVICE && db.st == SL_EDEVICE, n, "in-step requests");
+        check(dc.st == SL_EDEVICE, n, "request admitted during the failing step: " + std::to_string(dc.st));
+        sl_server_stats st{};
+        check(s.core->stats(&st) == SL_EDEVICE, n, "stats after the fault");
+        check(st.hbm_in_use == 0 && st.active == 0, n, "budget or slots not returned");
+        check(st.failed == 3, n, "failed " + std::to_string(st.failed));
         s.stop();
         no_violations(s, n);
     });
@@ -437,6 +515,7 @@ int main()
         check(st.submitted == 200 && st.completed + st.failed == 200, n, "counts");
         check(st.hbm_in_use == 0 && st.queued == 0 && st.active == 0, n, "not drained");
         check(s.ex.max_live_fp <= 400 && s.ex.max_live <= 6, n, "limits exceeded");
+        check(s.ex.max_admitting <= 2, n, "more admissions at once than setup threads");
         check(topo == 2, n, "injected admission failures: " + std::to_string(topo));
         s.stop();
         no_violations(s, n);

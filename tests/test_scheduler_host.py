@@ -1,9 +1,11 @@
 """The serving scheduler's host logic (csrc/sl_sched.h) against a mock
-executor, built with g++ and run on the CPU: FIFO admission under slots and
-budget, cancellation and deadlines (queued and active), admission and step
-failures, continuous batching, tolerance stops, poll rules, and a mixed
-multi-threaded load.  Built once with AddressSanitizer + UBSan and once with
-ThreadSanitizer (the scheduler's locking), host code only."""
+executor, built with g++ and run on the CPU: admission under slots and budget
+with bounded bypass, setup on several threads without stalling the steps,
+cancellation and deadlines (queued and active), admission and step failures
+(also with admissions in flight), continuous batching, tolerance stops, poll
+rules, and a mixed multi-threaded load.  Built once with AddressSanitizer +
+UBSan and once with ThreadSanitizer (the scheduler's locking), host code
+only."""
 import os
 import subprocess
 
@@ -32,4 +34,4 @@ def test_scheduler_with_mock_executor(tmp_path, compiler, sanitize):
     print(r.stdout)
     assert r.returncode == 0, r.stdout
     assert "0 failure(s)" in r.stdout
-    assert r.stdout.count("\nok ") + r.stdout.startswith("ok ") == 12
+    assert r.stdout.count("\nok ") + r.stdout.startswith("ok ") == 15
