@@ -106,9 +106,21 @@ def kernel_source_hash() -> str:
     return h.hexdigest()
 
 
-def cpu_baseline(m, seconds: float = 10.0):
+def cpu_model() -> str:
+    try:
+        for ln in open("/proc/cpuinfo"):
+            if ln.startswith("model name"):
+                return ln.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    import platform
+    return platform.processor() or "unknown"
+
+
+def _oracle_rate(m, threads: int, seconds: float):
+    """Whole Jacobi sweeps of the oracle on m with `threads` threads for about
+    `seconds`: (node-updates/s, sweeps, elapsed)."""
     import oracle
-    threads = oracle.max_threads()
     X = m.coords.copy()
     sweeps = 0
     t0 = time.perf_counter()
@@ -118,21 +130,53 @@ def cpu_baseline(m, seconds: float = 10.0):
         el = time.perf_counter() - t0
         if el >= seconds:
             break
-    free = int(np.count_nonzero(m.boundary == 0))
-    return {"value": free * sweeps / el, "unit": "node-updates/s", "cores": threads, "kind": "oracle",
-            "sample": "%d whole Jacobi sweeps of %s (%d free nodes) in %.1f s" % (sweeps, m.name, free, el)}
+    return m.n_interior * sweeps / el, sweeps, el
+
+
+def cpu_baseline(m, seconds: float = 10.0):
+    """The FP64 oracle on the host: all threads (the reported value) and one
+    thread, each for about `seconds` of whole sweeps of the headline mesh."""
+    import oracle
+    threads = oracle.max_threads()
+    v, sweeps, el = _oracle_rate(m, threads, seconds)
+    v1, sweeps1, el1 = _oracle_rate(m, 1, seconds)
+    free = m.n_interior
+    return {"value": v, "unit": "node-updates/s", "cores": threads, "kind": "oracle",
+            "sample": "%d whole Jacobi sweeps of %s (%d free nodes) in %.1f s on %d threads" %
+                      (sweeps, m.name, free, el, threads),
+            "cpu_model": cpu_model(), "host_cpus": os.cpu_count(),
+            "single_thread": {"value": v1, "unit": "node-updates/s", "cores": 1,
+                              "sample": "%d whole Jacobi sweeps in %.1f s on 1 thread" % (sweeps1, el1)}}
 
 
 def tile_opts(args):
     return {"tile_nodes": args.tile_nodes, "tile_wg_per_cu": args.wg_per_cu}
 
 
-def run_single(args, sl, torch):
-    m, iters = workload(args.workload)
+def converge_on(sl, torch, m, dev, X0, work, cap, tol=1e-9):
+    """The mesh already on the device, run from its input positions until the
+    largest displacement of a sweep is below tol (cap sweeps at most)."""
+    work.copy_(X0)
+    r = sl.smooth_mesh_device(work, *dev[1:], iterations=cap, tol=tol)
+    torch.cuda.synchronize()
+    log("converge %s: %d sweeps, last max |dx|^2 %.3e, %.1f ms of sweeps" %
+        (m.name, r.iterations_run, r.max_disp_sq_last, r.sweep_ms))
+    return {"workload": m.name, "tol": tol, "cap": cap, "iterations_run": r.iterations_run,
+            "converged": r.iterations_run < cap, "max_disp_sq_last": r.max_disp_sq_last,
+            "accepted_last": r.accepted_last, "sweep_ms": r.sweep_ms, "setup_ms": r.setup_ms,
+            "sweep_node_updates_per_s": m.n_interior * r.iterations_run / (r.sweep_ms / 1e3)}
+
+
+def run_single(args, sl, torch, name=None, steps=None, warmup=None, f32=None, autotune=None, converge=False):
+    m, iters = workload(name or args.workload)
+    steps = args.steps if steps is None else steps
+    warmup = args.warmup if warmup is None else warmup
+    f32 = args.f32 if f32 is None else f32
+    autotune = args.autotune if autotune is None else autotune
     free = m.n_interior
     alg_bytes = algorithmic_bytes(m)
     tuning = None
-    if args.autotune:
+    if autotune:
         t = sl.autotune([m], layout=args.layout)
         tuning = t.as_dict()
         log("autotune: tile_nodes %d, wg/CU %d in %.0f ms" % (t.tile_nodes, t.tile_wg_per_cu, t.tune_ms))
@@ -148,25 +192,25 @@ def run_single(args, sl, torch):
         return sl.smooth_mesh_device(work, *dev[1:], iterations=iters, layout=args.layout, reorder=args.reorder,
                                      kernel=args.kernel, stream=stream, **tile_opts(args))
 
-    for w in range(args.warmup):
+    for w in range(warmup):
         r = step()
         log("warmup %d: setup %.2f ms, sweeps %.2f ms" % (w, r.setup_ms, r.sweep_ms))
     torch.cuda.synchronize()
     sweep_ms, setup_ms = [], []
     t0 = time.perf_counter()
-    for _ in range(args.steps):
+    for _ in range(steps):
         r = step()
         sweep_ms.append(r.sweep_ms)
         setup_ms.append(r.setup_ms)
         assert r.iterations_run == iters
     torch.cuda.synchronize()
     el = time.perf_counter() - t0
-    log("timed %d steps in %.3f s" % (args.steps, el))
-    f32 = None
-    if args.f32:
+    log("timed %d steps of %s in %.3f s" % (steps, m.name, el))
+    f32_out = None
+    if f32:
         # the same job in single precision (the paper's precision), reported beside the FP64 headline
         f_sweep, f_t = [], []
-        for k in range(args.steps + 1):
+        for k in range(steps + 1):
             torch.cuda.synchronize()
             t = time.perf_counter()
             work.copy_(X0)
@@ -178,21 +222,21 @@ def run_single(args, sl, torch):
                 f_sweep.append(rf.sweep_ms)
         f_sweep_s = float(np.mean(f_sweep)) / 1e3 / iters
         f_bytes = alg_bytes - 16 * free
-        f32 = {"ms_per_step": 1e3 * float(np.mean(f_t)), "node_updates_per_s": free * iters / float(np.mean(f_t)),
+        f32_out = {"ms_per_step": 1e3 * float(np.mean(f_t)), "node_updates_per_s": free * iters / float(np.mean(f_t)),
                "sweep_ms_per_sweep": f_sweep_s * 1e3, "sweep_only_node_updates_per_s": free / f_sweep_s,
                "alg_bytes_per_launch": f_bytes, "hbm_gbs_algorithmic": f_bytes / f_sweep_s / 1e9,
                "hbm_pct_peak": 100.0 * f_bytes / f_sweep_s / 1e9 / HBM_PEAK_GBS}
-        log("f32: %.3f ms per sweep, %.1f%% of HBM peak" % (f_sweep_s * 1e3, f32["hbm_pct_peak"]))
+        log("f32: %.3f ms per sweep, %.1f%% of HBM peak" % (f_sweep_s * 1e3, f32_out["hbm_pct_peak"]))
     avg_sweep_s = float(np.mean(sweep_ms)) / 1e3 / iters
     achieved = alg_bytes / avg_sweep_s / 1e9
     out = {
         "metric": "node-updates/s",
-        "value": free * iters * args.steps / el,
+        "value": free * iters * steps / el,
         "unit": "node-updates/s",
         "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": el * 1e3 / args.steps,
+        "steps": steps,
+        "warmup": warmup,
+        "ms_per_step": el * 1e3 / steps,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -202,7 +246,7 @@ def run_single(args, sl, torch):
                    "sweeps_per_step": iters, "form": "jacobi", "layout": args.layout, "reorder": args.reorder,
                    "kernel": {1: "node", 2: "tile"}.get(r.kernel_used, "?"), "tile_nodes": r.tile_nodes},
         "autotune": tuning,
-        "single_precision": f32,
+        "single_precision": f32_out,
         "sweep_only_node_updates_per_s": free / avg_sweep_s,
         "sweep_ms_per_sweep": avg_sweep_s * 1e3,
         "setup_ms_per_step": float(np.mean(setup_ms)),
@@ -210,9 +254,45 @@ def run_single(args, sl, torch):
         "hbm_pct_peak": 100.0 * achieved / HBM_PEAK_GBS,
         "roofline": {"bound": "hbm", "kernel": SWEEP_KERNELS.get(r.kernel_used, "?"), "achieved": achieved,
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": traffic_from_profile(kernel_source_hash()), "alg_bytes_per_launch": alg_bytes},
+                     "traffic": (traffic_from_profile(kernel_source_hash()) if m.name == "grid4096_random_j0.4_s3"
+                                 else None),
+                     "alg_bytes_per_launch": alg_bytes},
     }
+    if converge:
+        out["converge"] = converge_on(sl, torch, m, dev, X0, work, args.converge_cap)
     return out, m
+
+
+def run_form_b(args, sl, torch, m=None):
+    """Form B (eq. (3): coloured, in place) on the 16.8M-node grid, 100
+    sweeps per step as the headline's Form A, with the per-sweep time of the
+    sweep kernel launches beside Form A's."""
+    if m is None:
+        m, _ = workload("grid4096")
+    iters, steps = 100, max(1, min(args.steps, 5))
+    dev = sl.to_device(m, "cuda:0")
+    X0 = dev[0].clone()
+    work = torch.empty_like(X0)
+    res = {}
+    for form in ("colored", "jacobi"):
+        best = None
+        for k in range(steps + 1):
+            work.copy_(X0)
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            r = sl.smooth_mesh_device(work, *dev[1:], iterations=iters, form=form)
+            torch.cuda.synchronize()
+            el = time.perf_counter() - t
+            if k and (best is None or r.sweep_ms < best[1].sweep_ms):
+                best = (el, r)
+        el, r = best
+        res[form] = {"ms_per_step": el * 1e3, "sweep_ms_per_sweep": r.sweep_ms / iters, "setup_ms": r.setup_ms,
+                     "kernel": {1: "node", 2: "tile", 3: "resident"}.get(r.kernel_used, "?"), "colors": r.n_colors,
+                     "sweep_node_updates_per_s": m.n_interior * iters / (r.sweep_ms / 1e3)}
+        log("%s: %.4f ms per sweep (%s kernel, %d colours), setup %.2f ms" %
+            (form, r.sweep_ms / iters, res[form]["kernel"], r.n_colors, r.setup_ms))
+    return {"workload": m.name, "sweeps": iters, "form_b": res["colored"], "form_a": res["jacobi"],
+            "b_over_a_sweep_time": res["colored"]["sweep_ms_per_sweep"] / res["jacobi"]["sweep_ms_per_sweep"]}
 
 
 def run_layouts(args, sl, torch):
@@ -257,42 +337,71 @@ def run_converge(args, sl, torch):
 
 def run_paper(args, sl, torch):
     """Meshes like the paper's (Sec. 4, Tables 6-9): Delaunay meshes of
-    1K-100K uniformly random points, 100 sweeps of Form A (AoS and SoA) and
-    Form B (and, on meshes small enough, Form A on the resident kernel),
-    GPU against the oracle on one host thread.  GPU time is the whole
-    smooth_mesh call (host arrays in and out) and, separately, the sweep
-    loop; the paper used FP32 and does not state its sweep counts, so its
-    numbers are context only."""
+    1K-100K uniformly random points.  Two runs of each: 100 sweeps of Form A
+    (AoS and SoA) and Form B (and, on meshes small enough, both forms on the
+    resident kernel); and each form run to convergence (largest displacement
+    of a sweep below 1e-9, cap 100,000 sweeps) -- the paper compares the
+    forms to convergence (Sec. 5.2) but states neither its criterion nor its
+    sweep counts.  GPU time is the whole smooth_mesh call (host arrays in and
+    out) and, separately, the sweep loop; the oracle runs the same work on one
+    host thread, as the paper compares against one CPU core.  The paper used
+    FP32 on a GT640: its numbers are context only."""
     import meshgen
     import oracle
+    tol, cap = 1e-9, 100000
     rows = []
+
+    def gpu_best(m, iters, tol_, opts):
+        best = None
+        for _ in range(3):
+            t = time.perf_counter()
+            _, r, _ = sl.smooth_mesh(m.coords, m.nbr_ptr, m.nbr_idx, m.tri_ptr, m.tri_idx, m.tris, m.boundary,
+                                     iters, tol_, **opts)
+            el = (time.perf_counter() - t) * 1e3
+            best = (el, r) if best is None or el < best[0] else best
+        return best
+
     for n in (1000, 5000, 10000, 50000, 100000):
         m = meshgen.make_delaunay(n, 11)
         row = {"points": n, "free_nodes": m.n_interior, "triangles": m.n_tris}
-        variants = [("A_aos", {}), ("A_soa", {"layout": "soa"}), ("B_aos", {"form": "colored"})]
+        variants = [("A_aos", {}), ("A_soa", {"layout": "soa"}), ("B_aos", {"form": "colored"}),
+                    ("B_soa", {"form": "colored", "layout": "soa"})]
         if m.n_nodes <= 2048:        # the resident kernel (opt-in) holds meshes of about this size
             variants += [("A_resident", {"kernel": "resident"}), ("B_resident", {"form": "colored", "kernel": "resident"})]
         for label, opts in variants:
-            best = None
-            for _ in range(3):
-                t = time.perf_counter()
-                _, r, _ = sl.smooth_mesh(m.coords, m.nbr_ptr, m.nbr_idx, m.tri_ptr, m.tri_idx, m.tris, m.boundary,
-                                         100, **opts)
-                el = (time.perf_counter() - t) * 1e3
-                best = (el, r.sweep_ms) if best is None or el < best[0] else best
-            row["gpu_" + label + "_ms"] = best[0]
-            row["gpu_" + label + "_sweep_ms"] = best[1]
+            el, r = gpu_best(m, 100, 0.0, opts)
+            row["gpu_" + label + "_ms"] = el
+            row["gpu_" + label + "_sweep_ms"] = r.sweep_ms
         for label, form in (("A", "jacobi"), ("B", "colored")):
             t = time.perf_counter()
             oracle.smooth(m, 100, threads=1, want_flags=False, form=form)
             row["cpu_" + label + "_ms"] = (time.perf_counter() - t) * 1e3
         row["speedup_A_aos"] = row["cpu_A_ms"] / row["gpu_A_aos_ms"]
         row["speedup_B_aos"] = row["cpu_B_ms"] / row["gpu_B_aos_ms"]
-        log("paper mesh %d: GPU A %.2f ms (sweeps %.2f), CPU A %.0f ms, speedup %.1f" %
-            (n, row["gpu_A_aos_ms"], row["gpu_A_aos_sweep_ms"], row["cpu_A_ms"], row["speedup_A_aos"]))
+        # to convergence
+        for label, opts in (("A_aos", {}), ("A_soa", {"layout": "soa"}), ("B_aos", {"form": "colored"}),
+                            ("B_soa", {"form": "colored", "layout": "soa"})):
+            el, r = gpu_best(m, cap, tol, opts)
+            row["conv_gpu_" + label + "_ms"] = el
+            row["conv_gpu_" + label + "_sweep_ms"] = r.sweep_ms
+            row["iterations_" + label] = r.iterations_run
+        for label, form in (("A", "jacobi"), ("B", "colored")):
+            t = time.perf_counter()
+            ref = oracle.smooth(m, cap, tol=tol, threads=1, want_flags=False, form=form)
+            row["conv_cpu_" + label + "_ms"] = (time.perf_counter() - t) * 1e3
+            row["conv_cpu_iterations_" + label] = ref.iterations_run
+        row["iterations_A"] = row["iterations_A_aos"]
+        row["iterations_B"] = row["iterations_B_aos"]
+        row["conv_speedup_A_aos"] = row["conv_cpu_A_ms"] / row["conv_gpu_A_aos_ms"]
+        row["conv_speedup_B_aos"] = row["conv_cpu_B_ms"] / row["conv_gpu_B_aos_ms"]
+        log("paper mesh %d: 100 sweeps GPU A %.2f ms (sweeps %.2f), CPU A %.0f ms; to 1e-9: A %d sweeps %.2f ms, "
+            "B %d sweeps %.2f ms (CPU A %.0f ms, B %.0f ms)" %
+            (n, row["gpu_A_aos_ms"], row["gpu_A_aos_sweep_ms"], row["cpu_A_ms"], row["iterations_A"],
+             row["conv_gpu_A_aos_ms"], row["iterations_B"], row["conv_gpu_B_aos_ms"], row["conv_cpu_A_ms"],
+             row["conv_cpu_B_ms"]))
         rows.append(row)
-    return {"workload": "delaunay_uniform_points_1K-100K_s11", "sweeps": 100, "dtype": "f64", "cpu_threads": 1,
-            "rows": rows}
+    return {"workload": "delaunay_uniform_points_1K-100K_s11", "sweeps": 100, "converge_tol": tol,
+            "converge_cap": cap, "dtype": "f64", "cpu_threads": 1, "rows": rows}
 
 
 def gen_meshes(specs):
@@ -378,31 +487,37 @@ def _pct(v, p):
 
 
 def serve_server(sl, pool, reqs):
+    """Submits each request at its arrival time.  Latency runs from the
+    scheduled arrival to the result on the host: the server's own
+    completion-minus-submission time plus however late the submission
+    itself was (a submit that waits for the server counts against it)."""
     with sl.Server() as S:
         t0 = time.perf_counter()
-        ids = []
+        ids, late = [], []
         for (at, idx, it, tol) in reqs:
             d = t0 + at - time.perf_counter()
             if d > 0:
                 time.sleep(d)
             m = pool[idx]
+            late.append(time.perf_counter() - (t0 + at))
             ids.append(S.submit(m, it, tol))
         lat, upd = [], 0
         first, last = None, None
-        for rid, (at, idx, it, tol) in zip(ids, reqs):
+        for rid, lt, (at, idx, it, tol) in zip(ids, late, reqs):
             r = S.wait(rid, timeout=300.0)
             if r.status != sl.SL_OK:
                 raise RuntimeError("request failed: " + r.message)
-            lat.append(r.times.done_s - r.times.submitted_s)
+            lat.append(lt + r.times.done_s - r.times.submitted_s)
             upd += pool[idx].n_interior * r.report.iterations_run
-            first = r.times.submitted_s if first is None else min(first, r.times.submitted_s)
+            first = r.times.submitted_s - lt if first is None else min(first, r.times.submitted_s - lt)
             last = r.times.done_s if last is None else max(last, r.times.done_s)
         st = S.stats()
     return lat, upd, last - first, st
 
 
 def serve_plain(sl, pool, reqs):
-    """One smooth_mesh call at a time, in arrival order."""
+    """One smooth_mesh call at a time, in arrival order; latency from the
+    scheduled arrival to the result on the host."""
     q = queue.Queue()
     lat = [None] * len(reqs)
     upd = [0]
@@ -410,14 +525,13 @@ def serve_plain(sl, pool, reqs):
 
     def worker():
         while True:
-            item = q.get()
-            if item is None:
+            k = q.get()
+            if k is None:
                 return
-            k, t_sub = item
             at, idx, it, tol = reqs[k]
             m = pool[idx]
             _, rep, _ = sl.smooth_mesh(m.coords, m.nbr_ptr, m.nbr_idx, m.tri_ptr, m.tri_idx, m.tris, m.boundary, it, tol)
-            lat[k] = time.perf_counter() - t_sub
+            lat[k] = time.perf_counter() - (t0 + at)
             upd[0] += m.n_interior * rep.iterations_run
 
     th = threading.Thread(target=worker)
@@ -426,7 +540,7 @@ def serve_plain(sl, pool, reqs):
         d = t0 + at - time.perf_counter()
         if d > 0:
             time.sleep(d)
-        q.put((k, time.perf_counter()))
+        q.put(k)
     q.put(None)
     th.join()
     return lat, upd[0], time.perf_counter() - t0
@@ -448,7 +562,9 @@ def run_serve(args, sl):
     serve_plain(sl, pool, [(0.0, small, 10, 0.0)])
     rows = []
     for rate in rates:
-        count = int(min(args.serve_max_requests, max(30, rate * args.serve_seconds)))
+        # serve_max_requests arrivals, or as many as arrive in serve_seconds
+        # at the low rates
+        count = int(min(args.serve_max_requests, max(60, rate * args.serve_seconds)))
         reqs = serve_requests(rate, count, pool, rng)
         lat, upd, span, st = serve_server(sl, pool, reqs)
         log("serve rate %g: %d requests, server p50 %.1f ms p99 %.1f ms, %.3g node-updates/s" %
@@ -461,7 +577,8 @@ def run_serve(args, sl):
                      "plain_p50_ms": _pct(plat, 50), "plain_p99_ms": _pct(plat, 99),
                      "plain_node_updates_per_s": pupd / pspan, "server_steps": st.steps})
     return {"workload": "serve_grids_side32-2048_random_j0.4_pool%d" % P,
-            "requests_mix": "half 10-200 sweeps, half tol 1e-8 (cap 10000)", "rates": rows}
+            "requests_mix": "half 10-200 sweeps, half tol 1e-8 (cap 10000)",
+            "latency": "scheduled arrival to the result on the host", "rates": rows}
 
 
 def main():
@@ -469,7 +586,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--mode", default="all", choices=["all", "single", "layouts", "paper", "batch", "serve", "converge"])
+    ap.add_argument("--mode", default="all",
+                    choices=["all", "single", "formb", "layouts", "paper", "batch", "serve", "converge"])
     ap.add_argument("--workload", default="grid4096")
     ap.add_argument("--layout", default="aos")
     ap.add_argument("--reorder", default="hilbert")
@@ -478,14 +596,15 @@ def main():
     ap.add_argument("--wg-per-cu", type=int, default=0)
     ap.add_argument("--no-autotune", dest="autotune", action="store_false")
     ap.add_argument("--no-f32", dest="f32", action="store_false")
-    ap.add_argument("--batch-meshes", type=int, default=1000)
+    ap.add_argument("--batch-meshes", type=int, default=10000)
     ap.add_argument("--no-plain", dest="plain", action="store_false",
                     help="batch mode: skip the separate-calls comparison")
     ap.add_argument("--converge-cap", type=int, default=100000)
-    ap.add_argument("--serve-rates", default="10,100,1000,2000")
+    ap.add_argument("--serve-rates", default="10,30,100,300,1000,2000")
     ap.add_argument("--serve-pool", type=int, default=48)
-    ap.add_argument("--serve-seconds", type=float, default=3.0)
-    ap.add_argument("--serve-max-requests", type=int, default=300)
+    ap.add_argument("--serve-seconds", type=float, default=30.0,
+                    help="arrivals of one rate span at most this long (the low rates)")
+    ap.add_argument("--serve-max-requests", type=int, default=1000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     args = ap.parse_args()
@@ -500,7 +619,17 @@ def main():
     torch.cuda.set_device(0)
     out, m = {}, None
     if args.mode in ("all", "single"):
-        out, m = run_single(args, sl, torch)
+        out, m = run_single(args, sl, torch, converge=args.mode == "all")
+    if args.mode == "all":
+        # the annulus variant of the 16.8M-node mesh: 100 timed sweeps per
+        # step as for the headline, then its run to tol 1e-9
+        an, _ = run_single(args, sl, torch, name="annulus4096", steps=min(args.steps, 10), warmup=1, f32=False,
+                           autotune=False, converge=True)
+        out["annulus"] = {k: an[k] for k in ("value", "unit", "ms_per_step", "steps", "config", "sweep_ms_per_sweep",
+                                              "sweep_only_node_updates_per_s", "setup_ms_per_step",
+                                              "hbm_gbs_algorithmic", "hbm_pct_peak", "roofline", "converge")}
+    if args.mode in ("all", "formb"):
+        out["form_b"] = run_form_b(args, sl, torch, m)
     if args.mode == "converge":
         out["converge"] = run_converge(args, sl, torch)
     if args.mode in ("all", "layouts"):

@@ -43,6 +43,24 @@ def moved(m, coords):
     return c
 
 
+def _many_stars(count, k, seed):
+    """count disjoint ring stars of valence k in one mesh (jittered ring
+    radii): the free nodes are the centres, each with k neighbour entries."""
+    coords, tris, off = [], [], 0
+    for s in range(count):
+        rng = np.random.Generator(np.random.PCG64(seed + s))
+        ang = np.sort(rng.uniform(0, 2 * np.pi, k))
+        ring = np.stack([np.cos(ang), np.sin(ang)], 1) * rng.uniform(0.8, 1.2, (k, 1))
+        st = meshgen.star_mesh(rng.uniform(-0.2, 0.2, 2), ring)
+        coords.append(st.coords + np.array([3.0 * (s % 40), 3.0 * (s // 40)]))
+        tris.append(st.tris + off)
+        off += st.n_nodes
+    coords = np.concatenate(coords)
+    tris = np.concatenate(tris)
+    nbr_ptr, nbr_idx, tri_ptr, tri_idx, bnd = meshgen.build_adjacency(coords.shape[0], tris)
+    return meshgen.Mesh(coords, tris, nbr_ptr, nbr_idx, tri_ptr, tri_idx, bnd, "stars%dx%d" % (count, k))
+
+
 @pytest.mark.parametrize("splits", [(5, 5), (33, 7, 40), (32, 32), (1, 64, 3)])
 def test_calls_continue_where_the_last_stopped(splits):
     """k sweeps, then k' more ... equal one run of k + k' + ... sweeps:
@@ -154,10 +172,7 @@ def test_batch_of_handles_equals_each_alone():
     import torch
     ms = [meshgen.make_grid(n, "random", 0.35, 300 + n) for n in (17, 64, 129, 200)]
     ms.append(meshgen.make_annulus(30, 48, seed=5))
-    dense = meshgen.star_mesh(np.array([0.05, -0.02]),
-                              np.stack([np.cos(np.linspace(0, 2 * np.pi, 60, endpoint=False)),
-                                        np.sin(np.linspace(0, 2 * np.pi, 60, endpoint=False))], 1))
-    ms.append(dense)
+    ms.append(_many_stars(600, 20, 5))   # 20 entries per node on average: too dense for the tiles
     pre = [0, 1, 3, 32, 7, 2]
     hs = [sl.Mesh(m) for m in ms]
     try:
