@@ -81,6 +81,23 @@ struct SweepArgs {
     uint64_t* bits;                 // nullable: this sweep's accept bits (device labels)
 };
 
+// a / d correctly rounded for an integer count d in [1, 127] with y = 1/d
+// correctly rounded, while the quotient is a normal number (Markstein's
+// correction step: q = a*y is within an ulp, the remainder a - q*d is
+// exact, and a normal quotient by an integer below 2^7 lies at least
+// ulp/254 from a rounding midpoint).  Callers divide instead when |a| is
+// below 128 x the smallest normal.
+__device__ __forceinline__ double div_small(double a, double d, double y)
+{
+    const double q = a * y;
+    const double r = fma(-q, d, a);
+    return fma(r, y, q);
+}
+constexpr double kStepMin = 0x1p-1015;   // 128 x the smallest normal double
+
+constexpr int kNodeRow = 8;   // neighbour entries whose loads are in flight together
+constexpr int kNodeFan = 4;   // fan entries read together
+
 template <int BLOCK, int MAXV, bool SOA, bool GT>
 __global__ __launch_bounds__(BLOCK) void k_sweep(SweepArgs a)
 {
@@ -93,35 +110,67 @@ __global__ __launch_bounds__(BLOCK) void k_sweep(SweepArgs a)
     __shared__ double2 nb[MAXV][BLOCK];
     __shared__ double s_d2[BLOCK / 64];
     __shared__ unsigned long long s_acc[BLOCK / 64];
+    __shared__ double s_recip[kMaxValence + 1];
 
     const int tid = threadIdx.x;
+    for (int i = tid; i <= kMaxValence; i += BLOCK) s_recip[i] = i ? 1.0 / static_cast<double>(i) : 0.0;
     const int k = a.k_begin + tile * BLOCK + tid;
+    const bool live = k < a.k_end;
+    // a lane past the range repeats the last node's loads and stores nothing
+    const int kk = live ? k : a.k_end - 1;
+    const int32_t r0 = a.row_ptr[kk], d = a.row_ptr[kk + 1] - r0;   // d >= 1 for a free node
+    const int32_t f0 = a.fan_ptr[kk], f1 = a.fan_ptr[kk + 1];
+    const double2 o = ld<SOA>(a.Xin, a.n, kk);
+    // the row's ids, then its positions, each group's loads in flight
+    // together; the sums run in stored order
+    double sx = 0.0, sy = 0.0;
+    for (int j0 = 0; j0 < d; j0 += kNodeRow) {
+        int32_t id[kNodeRow];
+#pragma unroll
+        for (int u = 0; u < kNodeRow; ++u) id[u] = a.nbr[r0 + min(j0 + u, d - 1)];
+        double2 p[kNodeRow];
+#pragma unroll
+        for (int u = 0; u < kNodeRow; ++u) p[u] = ld<SOA>(a.Xin, a.n, id[u]);
+#pragma unroll
+        for (int u = 0; u < kNodeRow; ++u)
+            if (j0 + u < d) {
+                sx += p[u].x;
+                sy += p[u].y;
+                nb[j0 + u][tid] = p[u];
+            }
+    }
+    __syncthreads();   // the reciprocal table
+    const double dn = static_cast<double>(d), y = s_recip[d];
+    double cx = div_small(sx, dn, y), cy = div_small(sy, dn, y);
+    const bool tiny = !(fabs(sx) >= kStepMin) || !(fabs(sy) >= kStepMin);
+    // a wave-uniform branch: the full division only when some lane needs it
+    if (__builtin_amdgcn_ballot_w64(tiny) != 0ull) {
+        if (tiny) {
+            cx = sx / dn;
+            cy = sy / dn;
+        }
+    }
+    double qo = INFINITY, qn = INFINITY;
+    for (int g0 = f0; g0 < f1; g0 += kNodeFan) {
+        uint32_t e[kNodeFan];
+#pragma unroll
+        for (int u = 0; u < kNodeFan; ++u) e[u] = a.fan[min(g0 + u, f1 - 1)];
+#pragma unroll
+        for (int u = 0; u < kNodeFan; ++u) {
+            if (g0 + u < f1) {
+                const int p = static_cast<int>(e[u] & 3u);
+                const double2 va = nb[(e[u] >> 2) & 127u][tid];
+                const double2 vb = nb[(e[u] >> 9) & 127u][tid];
+                const double v = fan_quality(p, o.x, o.y, va, vb);
+                if (v < qo) qo = v;
+                const double w = fan_quality(p, cx, cy, va, vb);
+                if (w < qn) qn = w;
+            }
+        }
+    }
     bool accepted = false;
     double d2 = 0.0;
-    if (k < a.k_end) {
-        const int32_t r0 = a.row_ptr[k], d = a.row_ptr[k + 1] - r0;
-        double sx = 0.0, sy = 0.0;
-        for (int32_t j = 0; j < d; ++j) {
-            const double2 p = ld<SOA>(a.Xin, a.n, a.nbr[r0 + j]);
-            sx += p.x;
-            sy += p.y;
-            nb[j][tid] = p;
-        }
-        const double dn = static_cast<double>(d);
-        const double cx = sx / dn, cy = sy / dn;
-        const double2 o = ld<SOA>(a.Xin, a.n, k);
-        double qo = INFINITY, qn = INFINITY;
-        const int32_t f1 = a.fan_ptr[k + 1];
-        for (int32_t f = a.fan_ptr[k]; f < f1; ++f) {
-            const uint32_t e = a.fan[f];
-            const int p = static_cast<int>(e & 3u);
-            const double2 va = nb[(e >> 2) & 127u][tid];
-            const double2 vb = nb[(e >> 9) & 127u][tid];
-            const double v = fan_quality(p, o.x, o.y, va, vb);
-            if (v < qo) qo = v;
-            const double w = fan_quality(p, cx, cy, va, vb);
-            if (w < qn) qn = w;
-        }
+    if (live) {
         accepted = GT ? (qn > qo) : (qn >= qo);
         const double nx = accepted ? cx : o.x, ny = accepted ? cy : o.y;
         st<SOA>(a.Xout, a.n, k, nx, ny);
