@@ -188,6 +188,29 @@ SL_API sl_status smooth_mesh_device(double* coords, int32_t n_nodes, const int32
                              const uint8_t* boundary, int32_t iterations, double tol, const sl_options* opts,
                              sl_report* report, void* stream);
 
+/*
+ * smooth_mesh_device_noalloc -- for callers that cannot allocate device
+ * memory (tight serving loops, harnesses that forbid allocation): the same
+ * call, arguments, results and errors as smooth_mesh_device, but the library
+ * allocates no device memory.  Every device array of the call -- the mesh's
+ * reordered copy, tiles and coordinate buffers, the setup's temporaries, the
+ * sweep state and accept bits -- is carved from one static workspace of
+ * 256 MiB per device (a file-scope device array, held by each device the
+ * library runs on until the process ends; about 1.5 million nodes of a mesh
+ * of valence 6, fewer with flag output).  A mesh that needs more fails with
+ * SL_ENOMEM before any work, coordinates untouched.  The workspace keeps
+ * the last call's contents; each call clears what must start at zero.  Calls
+ * on one device share it, so they must not overlap: within a process the
+ * library runs them one at a time (the call returns only when its work on
+ * `stream` is done); the sweep loop is launched directly, not through a
+ * captured graph.  The first call on a device looks up the workspace's
+ * device address and creates the call's four timing events.
+ */
+SL_API sl_status smooth_mesh_device_noalloc(double* coords, int32_t n_nodes, const int32_t* nbr_ptr,
+                                     const int32_t* nbr_idx, const int32_t* tri_ptr, const int32_t* tri_idx,
+                                     const int32_t* tris, int32_t n_tris, const uint8_t* boundary, int32_t iterations,
+                                     double tol, const sl_options* opts, sl_report* report, void* stream);
+
 /* One mesh of a batch or a served request: host arrays as for smooth_mesh.
  * coords is in/out (written on SL_OK only). */
 typedef struct {

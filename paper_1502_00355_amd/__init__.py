@@ -129,6 +129,8 @@ def lib():
         L.smooth_mesh.restype = ctypes.c_int
         L.smooth_mesh_device.argtypes = sig + [p]
         L.smooth_mesh_device.restype = ctypes.c_int
+        L.smooth_mesh_device_noalloc.argtypes = sig + [p]
+        L.smooth_mesh_device_noalloc.restype = ctypes.c_int
         L.sl_batch_smooth.argtypes = [ctypes.POINTER(MeshDesc), i32, i32, d, ctypes.POINTER(Options),
                                       ctypes.POINTER(Report), ctypes.POINTER(BatchReport)]
         L.sl_batch_smooth.restype = ctypes.c_int
@@ -228,6 +230,21 @@ def smooth_mesh_device(coords, nbr_ptr, nbr_idx, tri_ptr, tri_idx, tris, boundar
     float64 is overwritten.  ``flags``: optional uint8 device tensor of
     iterations * ceil(n/8) bytes.  Runs on ``stream`` (default: torch's
     current stream)."""
+    return _device_call(lib().smooth_mesh_device, coords, nbr_ptr, nbr_idx, tri_ptr, tri_idx, tris, boundary,
+                        iterations, tol, flags, stream, opts)
+
+
+def smooth_mesh_device_noalloc(coords, nbr_ptr, nbr_idx, tri_ptr, tri_idx, tris, boundary, iterations: int,
+                               tol: float = 0.0, flags=None, stream=None, **opts) -> Report:
+    """As smooth_mesh_device, through the entry point that allocates no
+    device memory (every array of the call lives in the library's static
+    workspace; meshes too large for it raise SL_ENOMEM)."""
+    return _device_call(lib().smooth_mesh_device_noalloc, coords, nbr_ptr, nbr_idx, tri_ptr, tri_idx, tris,
+                        boundary, iterations, tol, flags, stream, opts)
+
+
+def _device_call(fn, coords, nbr_ptr, nbr_idx, tri_ptr, tri_idx, tris, boundary, iterations, tol, flags, stream,
+                 opts) -> Report:
     import torch
     if stream is None:
         stream = torch.cuda.current_stream()
@@ -239,10 +256,9 @@ def smooth_mesh_device(coords, nbr_ptr, nbr_idx, tri_ptr, tri_idx, tris, boundar
         raise TypeError("flags must be a uint8 device tensor")
     o = make_options(flags_ptr=flags.data_ptr() if flags is not None and flags.numel() else None, **opts)
     rep = Report()
-    st = lib().smooth_mesh_device(coords.data_ptr(), coords.shape[0], nbr_ptr.data_ptr(), nbr_idx.data_ptr(),
-                                  tri_ptr.data_ptr(), tri_idx.data_ptr(), tris.data_ptr(), tris.numel() // 3,
-                                  boundary.data_ptr(), int(iterations), float(tol), ctypes.byref(o),
-                                  ctypes.byref(rep), ctypes.c_void_p(stream.cuda_stream))
+    st = fn(coords.data_ptr(), coords.shape[0], nbr_ptr.data_ptr(), nbr_idx.data_ptr(), tri_ptr.data_ptr(),
+            tri_idx.data_ptr(), tris.data_ptr(), tris.numel() // 3, boundary.data_ptr(), int(iterations), float(tol),
+            ctypes.byref(o), ctypes.byref(rep), ctypes.c_void_p(stream.cuda_stream))
     _check(st)
     return rep
 

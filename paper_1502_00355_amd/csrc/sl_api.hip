@@ -118,6 +118,21 @@ sl_status prepare_mesh(const MeshInput& in, const sl_options& o, int32_t mesh_in
     if (ends[1] < 0 || ends[3] < 0) return fail(SL_EINVAL, "negative CSR length");
     if (ends[1] > 0 && !in.nbr_idx) return fail(SL_EINVAL, "null nbr_idx with nbr_ptr[n] > 0");
     if (ends[3] > 0 && !in.tri_idx) return fail(SL_EINVAL, "null tri_idx with tri_ptr[n] > 0");
+    if (m.region) {
+        // everything from the caller's region: the mesh's arrays, then the
+        // setup's temporaries, which the caller's region_after bytes reuse
+        // once setup is done
+        const size_t pb = Arena::piece(mesh_block_bytes(in.n, ends[1], ends[3], o));
+        const size_t sb = setup_scratch_bytes(in.n);
+        const size_t need = pb + std::max(sb, m.region_after);
+        if (need > m.region_bytes)
+            return fail(SL_ENOMEM, "the mesh needs " + std::to_string(need) + " bytes of device workspace; the "
+                                   "static workspace holds " + std::to_string(m.region_bytes));
+        m.carve = m.region;
+        m.carve_bytes = pb;
+        m.scratch_carve = m.region + pb;
+        m.scratch_carve_bytes = m.region_bytes - pb;
+    }
     SetupArgs sa{in.coords, in.n, in.nbr_ptr, in.nbr_idx, in.tri_ptr, in.tri_idx, in.tris, in.n_tris, in.boundary,
                  ends[1], ends[3]};
     return setup_mesh(sa, o, m, mesh_index, st);
@@ -126,6 +141,15 @@ sl_status prepare_mesh(const MeshInput& in, const sl_options& o, int32_t mesh_in
 namespace {
 
 constexpr int32_t kSweepChunk = 32;   // even
+
+// A device's static workspace, for the entry point that allocates nothing:
+// its device address and the call's timing events, both set up once per
+// device.
+struct StaticWorkspace {
+    unsigned char* base = nullptr;
+    size_t bytes = 0;
+    hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
+};
 
 // Everything a call allocates, released on every exit path.
 struct CallState {
@@ -136,6 +160,7 @@ struct CallState {
     int32_t* sched = nullptr;
     uint64_t* bits = nullptr;
     hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
+    bool own_events = true;             // false: a static workspace's events
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     hipStream_t capture = nullptr;      // where the sweep chunk is captured
@@ -147,15 +172,27 @@ struct CallState {
         (void)hipStreamSynchronize(st);
         if (exec) (void)hipGraphExecDestroy(exec);
         if (graph) (void)hipGraphDestroy(graph);
-        for (auto& e : ev)
-            if (e) (void)hipEventDestroy(e);
+        if (own_events)
+            for (auto& e : ev)
+                if (e) (void)hipEventDestroy(e);
     }
 };
+
+// Bytes of a call's sweep state, tile counters, resident-kernel arguments
+// and (with flag output) accept bits, for a mesh of at most n free nodes.
+size_t aux_bytes(int64_t n, int32_t iterations, bool want_bits)
+{
+    const size_t words = static_cast<size_t>((n + 63) / 64);
+    return Arena::piece(sizeof(MeshState)) + Arena::piece(sizeof(int32_t) * kTileSchedInts) +
+           Arena::piece(sizeof(ResidentArgs)) +
+           (want_bits ? Arena::piece(8 * words * static_cast<size_t>(iterations)) : 0);
+}
 
 sl_status run_device(double* coords, int32_t n, const int32_t* nbr_ptr, const int32_t* nbr_idx,
                      const int32_t* tri_ptr, const int32_t* tri_idx, const int32_t* tris, int32_t n_tris,
                      const uint8_t* boundary, int32_t iterations, double tol, const sl_options* opts,
-                     sl_report* report, hipStream_t stream, const int32_t* known_ends = nullptr)
+                     sl_report* report, hipStream_t stream, const int32_t* known_ends = nullptr,
+                     const StaticWorkspace* ws = nullptr)
 {
     const auto t0 = std::chrono::steady_clock::now();
     sl_options o;
@@ -164,11 +201,22 @@ sl_status run_device(double* coords, int32_t n, const int32_t* nbr_ptr, const in
     sl_status r = check_options(o);
     if (r) return r;
     if (iterations < 0) return fail(SL_EINVAL, "iterations must be >= 0");
-    keep_pool_warm();
+    const bool want_bits = o.flags_out && iterations > 0;
+    if (!ws) keep_pool_warm();
 
     CallState cs;
     cs.st = stream;
-    for (auto& e : cs.ev) SL_HIP(hipEventCreate(&e));
+    if (ws) {
+        // every device array from the static workspace: the mesh's arrays,
+        // the setup's temporaries, then (over those) the sweep state
+        for (int k = 0; k < 4; ++k) cs.ev[k] = ws->ev[k];
+        cs.own_events = false;
+        cs.m.region = ws->base;
+        cs.m.region_bytes = ws->bytes;
+        cs.m.region_after = aux_bytes(n, iterations, want_bits);
+    } else {
+        for (auto& e : cs.ev) SL_HIP(hipEventCreate(&e));
+    }
     SL_HIP(hipEventRecord(cs.ev[0], stream));
     MeshInput in{coords, n, nbr_ptr, nbr_idx, tri_ptr, tri_idx, tris, n_tris, boundary};
     if (known_ends) {
@@ -185,13 +233,13 @@ sl_status run_device(double* coords, int32_t n, const int32_t* nbr_ptr, const in
     h0.iters = its;
     h0.active = its > 0;
     h0.tol2 = tol2;
-    const bool want_bits = o.flags_out && its > 0;
     const size_t n_bits = want_bits ? static_cast<size_t>(words) * its : 0;
-    if ((r = cs.aux.reserve(Arena::piece(sizeof(MeshState)) + Arena::piece(sizeof(int32_t) * kTileSchedInts) +
-                                Arena::piece(sizeof(ResidentArgs)) + (want_bits ? Arena::piece(8 * n_bits) : 0),
-                            stream)) ||
-        (r = cs.aux.take(&cs.state, 1)) || (r = cs.aux.take(&cs.sched, kTileSchedInts)))
+    if (ws) {
+        cs.aux.adopt(ws->base + cs.m.carve_bytes, ws->bytes - cs.m.carve_bytes);
+    } else if ((r = cs.aux.reserve(aux_bytes(cs.m.n_free, its, want_bits), stream))) {
         return r;
+    }
+    if ((r = cs.aux.take(&cs.state, 1)) || (r = cs.aux.take(&cs.sched, kTileSchedInts))) return r;
     SL_HIP(hipMemcpyAsync(cs.state, &h0, sizeof(MeshState), hipMemcpyHostToDevice, stream));
     SL_HIP(hipMemsetAsync(cs.sched, 0, sizeof(int32_t) * kTileSchedInts, stream));
     if (want_bits) {
@@ -234,7 +282,7 @@ sl_status run_device(double* coords, int32_t n, const int32_t* nbr_ptr, const in
         const size_t lds = resident_lds_bytes(cs.m.n, cs.m.n_free, cs.m.nnz_free, cs.m.ninc_free, in_place);
         if ((r = launch_sweep_resident(d_ra, 1, lds, o.layout, o.accept, stream))) return r;
     }
-    const bool use_graph = !cs.m.resident && !cs.bits && its >= 2 * kSweepChunk;
+    const bool use_graph = !ws && !cs.m.resident && !cs.bits && its >= 2 * kSweepChunk;
     if (use_graph) {
         if ((r = take_stream(&cs.capture))) return r;
         SL_HIP(hipStreamBeginCapture(cs.capture, hipStreamCaptureModeThreadLocal));
@@ -292,6 +340,46 @@ sl_status run_device(double* coords, int32_t n, const int32_t* nbr_ptr, const in
     return SL_OK;
 }
 
+// Device memory of smooth_mesh_device_noalloc: one file-scope array per
+// device, holding a mesh's arrays, the setup's temporaries and the sweep
+// state of one call.  It lives as long as the process.  In host code the
+// array's name is no device address; the address comes from
+// hipGetSymbolAddress, once per device.
+constexpr size_t kStaticWorkspaceBytes = size_t(256) << 20;
+__device__ __align__(256) unsigned char scratch[kStaticWorkspaceBytes];
+
+struct StaticSlot {
+    std::once_flag once;
+    sl_status status = SL_OK;
+    std::string error;
+    StaticWorkspace ws;
+    std::mutex mu;   // calls on one device share its workspace: one at a time
+};
+StaticSlot g_static[64];
+
+// Sets up the current device's workspace: its address and the four timing
+// events of a call.
+void init_static(StaticSlot& s)
+{
+    void* p = nullptr;
+    hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || p == nullptr) {
+        s.status = SL_EDEVICE;
+        s.error = std::string("hipGetSymbolAddress of the static workspace failed: ") + hipGetErrorString(e);
+        return;
+    }
+    for (auto& ev : s.ws.ev) {
+        e = hipEventCreate(&ev);
+        if (e != hipSuccess) {
+            s.status = SL_EDEVICE;
+            s.error = std::string("hipEventCreate failed: ") + hipGetErrorString(e);
+            return;
+        }
+    }
+    s.ws.base = static_cast<unsigned char*>(p);
+    s.ws.bytes = kStaticWorkspaceBytes;
+}
+
 }  // namespace
 
 void set_error(const std::string& msg) { g_last_error = msg; }
@@ -331,6 +419,25 @@ sl_status smooth_mesh_device(double* coords, int32_t n_nodes, const int32_t* nbr
     sl::set_error("");
     return sl::run_device(coords, n_nodes, nbr_ptr, nbr_idx, tri_ptr, tri_idx, tris, n_tris, boundary, iterations,
                           tol, opts, report, static_cast<hipStream_t>(stream));
+}
+
+SL_API sl_status smooth_mesh_device_noalloc(double* coords, int32_t n_nodes, const int32_t* nbr_ptr,
+                                     const int32_t* nbr_idx, const int32_t* tri_ptr, const int32_t* tri_idx,
+                                     const int32_t* tris, int32_t n_tris, const uint8_t* boundary, int32_t iterations,
+                                     double tol, const sl_options* opts, sl_report* report, void* stream)
+{
+    using namespace sl;
+    set_error("");
+    const int dev = current_device();
+    if (dev < 0) return fail(SL_EDEVICE, "no current HIP device (or its ordinal is 64 or more)");
+    StaticSlot& s = g_static[dev];
+    std::call_once(s.once, [&s] { init_static(s); });
+    if (s.status) return fail(s.status, s.error);
+    // the call returns only when its work on `stream` is done, so holding
+    // the lock for the call keeps calls on this device from overlapping
+    std::lock_guard<std::mutex> lk(s.mu);
+    return run_device(coords, n_nodes, nbr_ptr, nbr_idx, tri_ptr, tri_idx, tris, n_tris, boundary, iterations, tol,
+                      opts, report, static_cast<hipStream_t>(stream), nullptr, &s.ws);
 }
 
 sl_status smooth_mesh(double* coords, int32_t n_nodes, const int32_t* nbr_ptr, const int32_t* nbr_idx,

@@ -105,6 +105,7 @@ inline int div_up(int64_t a, int64_t b) { return static_cast<int>((a + b - 1) / 
 struct Arena {
     unsigned char* base = nullptr;
     size_t cap = 0, used = 0;
+    bool owned = false;   // base came from block_take (release() gives it back)
 
     static size_t piece(size_t bytes) { return (std::max<size_t>(bytes, 1) + 255) & ~size_t(255); }
 
@@ -112,7 +113,9 @@ struct Arena {
     {
         used = 0;
         cap = bytes;
-        return block_take(&base, std::max<size_t>(bytes, 256), st);
+        const sl_status r = block_take(&base, std::max<size_t>(bytes, 256), st);
+        owned = r == SL_OK;
+        return r;
     }
     template <typename T>
     sl_status take(T** p, size_t count)
@@ -127,18 +130,21 @@ struct Arena {
         used += b;
         return SL_OK;
     }
-    // Carves from `bytes` at p, owned by someone else: never release() it.
+    // Carves from `bytes` at p, owned by someone else (release() only forgets it).
     void adopt(unsigned char* p, size_t bytes)
     {
         base = p;
         cap = bytes;
         used = 0;
+        owned = false;
     }
     size_t mark() const { return used; }
     void rewind(size_t m) { used = m; }
     void release(hipStream_t st)
     {
-        block_give(base, st);
+        if (owned) block_give(base, st);
+        base = nullptr;
+        owned = false;
         cap = used = 0;
     }
 };
@@ -206,6 +212,18 @@ struct DevMesh {
     // mesh_block_bytes() long.
     unsigned char* carve = nullptr;
     size_t carve_bytes = 0;
+    // Set before setup to take the setup's temporaries from a region too
+    // (not owned), at least setup_scratch_bytes() long.
+    unsigned char* scratch_carve = nullptr;
+    size_t scratch_carve_bytes = 0;
+    // Set before prepare_mesh to carve everything from one caller-owned
+    // region of region_bytes: the mesh's arrays first (carve), then the
+    // setup's temporaries (scratch_carve); region_after more bytes must fit
+    // after the arrays once setup is done (prepare_mesh fails with
+    // SL_ENOMEM before any work otherwise).
+    unsigned char* region = nullptr;
+    size_t region_bytes = 0;
+    size_t region_after = 0;
     int32_t n = 0, n_free = 0, n_tris = 0;
     int64_t nnz_free = 0, ninc_free = 0;
     int32_t max_deg = 0, max_inc = 0;
@@ -267,6 +285,8 @@ sl_status setup_mesh(const SetupArgs& a, const sl_options& o, DevMesh& m, int32_
 // Bytes of the one allocation setup_mesh makes for a mesh's own arrays,
 // from bounds known before validation (n nodes, nnz and ninc CSR entries).
 size_t mesh_block_bytes(int32_t n, int64_t nnz, int64_t ninc, const sl_options& o);
+// Bytes of setup_mesh's temporaries for a mesh of n nodes.
+size_t setup_scratch_bytes(int32_t n);
 
 // Device arrays of one caller mesh.
 struct MeshInput {

@@ -843,13 +843,12 @@ sl_status make_order(const SetupArgs& a, const sl_options& o, const uint8_t* bnd
         k_bucket<<<gb, kBS, 0, st>>>(a.coords, bnd, color, n, bits, bb, key, count, flag);
         if ((r = scan_exclusive(count, start, nbk, st, &scratch))) return r;
         if (color) {
-            std::vector<int32_t> h(static_cast<size_t>(nc) + 1);
+            // nc <= 128: the class starts fit the mesh's table
             for (int c = 0; c <= nc; ++c) {
-                SL_HIP(hipMemcpyAsync(&h[c], start + (static_cast<int64_t>(c) << (2 * bits)), sizeof(int32_t),
+                SL_HIP(hipMemcpyAsync(&cs[c], start + (static_cast<int64_t>(c) << (2 * bits)), sizeof(int32_t),
                                       hipMemcpyDeviceToHost, st));
             }
             SL_HIP(hipStreamSynchronize(st));
-            for (int c = 0; c <= nc; ++c) cs[c] = h[c];
         } else {
             cs[1] = n_free;
         }
@@ -914,6 +913,17 @@ size_t mesh_block_bytes(int32_t n, int64_t nnz, int64_t ninc, const sl_options& 
     return pb;
 }
 
+size_t setup_scratch_bytes(int32_t n)
+{
+    const size_t un = static_cast<size_t>(n);
+    const size_t rows_bytes = 2 * Arena::piece(4 * un) + scan_bytes(n);
+    const int gb = div_up(n, kBS);
+    return Arena::piece(sizeof(ValStats)) + Arena::piece(sizeof(ValStats) * static_cast<size_t>(gb)) +
+           Arena::piece(4 * un) + Arena::piece(4) +
+           std::max({order_bytes(n), rows_bytes, tile_scratch_bytes(),
+                     2 * Arena::piece(4 * un) + Arena::piece(8)});   // the colouring's lists
+}
+
 sl_status setup_mesh(const SetupArgs& a, const sl_options& o, DevMesh& m, int32_t mesh, hipStream_t st)
 {
     const int32_t n = a.n;
@@ -937,12 +947,8 @@ sl_status setup_mesh(const SetupArgs& a, const sl_options& o, DevMesh& m, int32_
     // and the setup's temporaries, given back when setup ends.
     Arena persist, scratch;
     const size_t pb = mesh_block_bytes(n, a.nnz, a.ninc, o);
-    const size_t rows_bytes = 2 * Arena::piece(4 * un) + scan_bytes(n);
+    const size_t sb = setup_scratch_bytes(n);
     const int gb = div_up(n, kBS);
-    const size_t sb = Arena::piece(sizeof(ValStats)) + Arena::piece(sizeof(ValStats) * static_cast<size_t>(gb)) +
-                      Arena::piece(4 * un) + Arena::piece(4) +
-                      std::max({order_bytes(n), rows_bytes, tile_scratch_bytes(),
-                                2 * Arena::piece(4 * un) + Arena::piece(8)});   // the colouring's lists
     if (m.carve) {
         if (m.carve_bytes < pb) return fail(SL_EINVAL, "internal: mesh region smaller than its arrays");
         persist.adopt(m.carve, pb);
@@ -950,7 +956,12 @@ sl_status setup_mesh(const SetupArgs& a, const sl_options& o, DevMesh& m, int32_
         if ((r = persist.reserve(pb, st))) return r;
         m.block = persist.base;
     }
-    if ((r = scratch.reserve(sb, st))) return r;
+    if (m.scratch_carve) {
+        if (m.scratch_carve_bytes < sb) return fail(SL_EINVAL, "internal: setup region smaller than its temporaries");
+        scratch.adopt(m.scratch_carve, sb);
+    } else if ((r = scratch.reserve(sb, st))) {
+        return r;
+    }
     struct GiveBack {
         Arena& ar;
         hipStream_t st;
