@@ -88,8 +88,9 @@ sl_status check_options(const sl_options& o)
         return fail(SL_EINVAL, "unknown kernel");
     if (o.kernel == SL_KERNEL_RESIDENT && o.precision != SL_F64)
         return fail(SL_EINVAL, "the resident kernel runs in double precision only");
-    if (o.tile_nodes != 0 && o.tile_nodes != 256 && o.tile_nodes != 512)
-        return fail(SL_EINVAL, "tile_nodes must be 0, 256 or 512");
+    if (o.tile_nodes != 0 && o.tile_nodes != 256 && o.tile_nodes != 512 &&
+        !(o.tile_nodes == 128 && o.form == SL_INPLACE_COLORED))
+        return fail(SL_EINVAL, "tile_nodes must be 0, 256 or 512 (or 128 for the coloured form)");
     if (o.tile_wg_per_cu < 0 || o.tile_wg_per_cu > 8) return fail(SL_EINVAL, "tile_wg_per_cu must be in 0..8");
     if (o.precision != SL_F64 && o.precision != SL_F32) return fail(SL_EINVAL, "unknown precision");
     if (o.precision == SL_F32 && (o.form != SL_JACOBI || o.kernel == SL_KERNEL_NODE))
@@ -122,7 +123,7 @@ sl_status prepare_mesh(const MeshInput& in, const sl_options& o, int32_t mesh_in
         // everything from the caller's region: the mesh's arrays, then the
         // setup's temporaries, which the caller's region_after bytes reuse
         // once setup is done
-        const size_t pb = Arena::piece(mesh_block_bytes(in.n, ends[1], ends[3], o));
+        const size_t pb = Arena::piece(mesh_block_bytes(in.n, ends[1], ends[3], o, m.class_tiles_ok));
         const size_t sb = setup_scratch_bytes(in.n);
         const size_t need = pb + std::max(sb, m.region_after);
         if (need > m.region_bytes)
@@ -206,6 +207,7 @@ sl_status run_device(double* coords, int32_t n, const int32_t* nbr_ptr, const in
 
     CallState cs;
     cs.st = stream;
+    cs.m.class_tiles_ok = true;   // Form B may sweep colour-class tiles
     if (ws) {
         // every device array from the static workspace: the mesh's arrays,
         // the setup's temporaries, then (over those) the sweep state
@@ -246,7 +248,7 @@ sl_status run_device(double* coords, int32_t n, const int32_t* nbr_ptr, const in
         if ((r = cs.aux.take(&cs.bits, n_bits))) return r;
         SL_HIP(hipMemsetAsync(cs.bits, 0, sizeof(uint64_t) * n_bits, stream));
     }
-    const bool tiles = o.form == SL_JACOBI && cs.m.tile_nodes > 0;
+    const bool tiles = cs.m.tile_nodes > 0;
     const int32_t block = resolve_block_size(o);
     // with a tolerance, a launch on a converged mesh returns at once; a tile
     // launch closes its own sweep
@@ -255,6 +257,21 @@ sl_status run_device(double* coords, int32_t n, const int32_t* nbr_ptr, const in
                        o.tile_wg_per_cu == 0 ? 1 : 0};
     auto enqueue = [&](int32_t s, hipStream_t on) -> sl_status {
         uint64_t* bits = cs.bits ? cs.bits + static_cast<int64_t>(s) * words : nullptr;
+        if (tiles && cs.m.n_tile_classes > 0) {
+            // Form B: one launch per colour class, in place in buffer 0; the
+            // last class's launch closes the sweep
+            for (int32_t c = 0; c < cs.m.n_tile_classes; ++c) {
+                TileLaunch Lc = L;
+                Lc.work = cs.m.work + cs.m.class_tile_h[c];
+                Lc.n_work = cs.m.class_tile_h[c + 1] - cs.m.class_tile_h[c];
+                Lc.n_close = c + 1 == cs.m.n_tile_classes ? 1 : 0;
+                Lc.in_place = 1;
+                Lc.wg_per_cu = o.tile_wg_per_cu;   // a count tuned for Form A's tiles does not apply
+                const sl_status rr = launch_sweep_class(Lc, cs.m.fans_max, bits, on);
+                if (rr) return rr;
+            }
+            return SL_OK;
+        }
         if (tiles) return launch_sweep_tiles(L, s & 1, bits, on);
         const sl_status rr = launch_sweep_nodes(cs.m, s & 1, o.form, o.accept, block, cs.state, bits, on);
         return rr ? rr : launch_advance(cs.state, 1, on);

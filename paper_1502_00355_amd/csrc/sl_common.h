@@ -188,6 +188,36 @@ __device__ __forceinline__ void close_state(MeshState* p)
     *p = m;
 }
 
+// Counters of a tile launch: groups done, then one tile counter per XCD.
+constexpr int kSchedStride = 32;                    // one 128-byte line per counter
+constexpr int kTileSchedInts = 9 * kSchedStride;
+
+// The last work-group of a launch to finish closes the sweep of states[0..n)
+// and zeroes the launch's counters for the next launch.  A group's folds into the
+// sweep state are device-scope atomics made by its first work-item; the
+// work-group-scope release waits until they have completed, so they are
+// performed before the group's count.  The closing group reads the folds
+// with device-scope atomic loads after it has seen every count.  No
+// device-scope release or acquire is needed: those would write back or
+// invalidate the XCD's L2, once per work-group.
+template <int BS>
+__device__ __forceinline__ void close_launch(int32_t* sched, MeshState* states, int32_t n)
+{
+    int32_t* const count = sched;
+    __shared__ int s_last;
+    __syncthreads();   // every work-item of the group is done with its tiles
+    if (threadIdx.x == 0) {
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+        const int before = __hip_atomic_fetch_add(count, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        s_last = before == static_cast<int>(gridDim.x) - 1;
+    }
+    __syncthreads();
+    if (!s_last) return;
+    for (int i = threadIdx.x; i < n; i += BS) close_state(states + i);
+    if (threadIdx.x < 9)
+        __hip_atomic_store(sched + kSchedStride * threadIdx.x, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
 // One tile of the tile path: everything a work-group needs to sweep it, with
 // absolute pointers so that tiles of many meshes can share one launch.
 struct alignas(16) TileWork {
@@ -202,6 +232,8 @@ struct alignas(16) TileWork {
     int64_t n;                      // the mesh's node count (buffer stride)
 };
 static_assert(sizeof(TileWork) == 80, "TileWork layout");
+
+constexpr int kMaxTileClasses = 32;   // colour classes the Form B tile path takes at most
 
 // One mesh prepared for sweeping: free nodes occupy [0, n_free) in the
 // device order, fixed nodes [n_free, n).
@@ -240,11 +272,15 @@ struct DevMesh {
     void* X[2] = {nullptr, nullptr};     // one block of 4n elements: X[1] = X[0] + 2n;
                                          // AoS (x,y pairs) or SoA (x[n] then y[n]) inside each
     bool resident = false;               // Form A on the resident kernel (node-path arrays built)
-    // Tile path (Form A)
+    // Tile path: Form A, or Form B on colour-class tiles (n_tile_classes > 0)
     int32_t tile_nodes = 0;              // 0: tile path not built
+    int32_t n_tile_classes = 0;          // Form B: class c sweeps tiles [class_tile_h[c], class_tile_h[c+1])
+    int32_t class_tile_h[kMaxTileClasses + 1] = {0};
+    bool class_tiles_ok = false;         // set before setup: Form B may take colour-class tiles
     int32_t n_tiles = 0;
     int32_t halo_max = 0;                // largest halo over tiles
     int32_t rows_max = 0;                // largest row segment (u16 entries, padded to 4) over tiles
+    int32_t fans_max = 0;                // class tiles: longest fan list over tiles
     TileWork* work = nullptr;            // [n_tiles]
     unsigned char* tile_data = nullptr;  // one contiguous record per tile: row offsets, halo, rows, triangles
 };
@@ -265,14 +301,16 @@ struct SetupArgs {
     int64_t nnz, ninc;      // nbr_ptr[n], tri_ptr[n] (read by the caller of setup)
 };
 
-// Builds the tile path for Form A (tile_nodes free nodes per tile) and
-// writes the tile list to m.work with MeshState index `mesh`.  Leaves
+// Builds the tile path (tile_nodes free nodes per tile) and writes the tile
+// list to m.work with MeshState index `mesh`: tiles of consecutive free
+// nodes (Form A), or, with `classes`, tiles inside each colour class of
+// m.color_start_h (Form B; at most kMaxTileClasses classes).  Leaves
 // m.tile_nodes = 0 (node path) when the mesh does not fit it.
 sl_status build_tiles(const SetupArgs& a, DevMesh& m, int tile_nodes, int mesh, hipStream_t st, Arena& persist,
-                      Arena& scratch);
+                      Arena& scratch, bool classes = false);
 // Bytes build_tiles takes from `persist` for a mesh of at most n free nodes
 // with at most nnz neighbour entries and ninc incidences, and from `scratch`.
-size_t tile_bytes(int64_t n, int64_t nnz, int64_t ninc, int tile_nodes);
+size_t tile_bytes(int64_t n, int64_t nnz, int64_t ninc, int tile_nodes, bool classes = false);
 size_t tile_scratch_bytes();
 // LDS bytes of one sweep work-group, and the most a work-group may use.
 size_t tile_lds_bytes(int tile_nodes, int halo_cap, int rows_cap, int32_t precision);
@@ -284,7 +322,8 @@ constexpr size_t kTileLdsLimit = 160 * 1024 - 4096;
 sl_status setup_mesh(const SetupArgs& a, const sl_options& o, DevMesh& m, int32_t mesh, hipStream_t st);
 // Bytes of the one allocation setup_mesh makes for a mesh's own arrays,
 // from bounds known before validation (n nodes, nnz and ninc CSR entries).
-size_t mesh_block_bytes(int32_t n, int64_t nnz, int64_t ninc, const sl_options& o);
+// class_tiles_ok: as DevMesh::class_tiles_ok.
+size_t mesh_block_bytes(int32_t n, int64_t nnz, int64_t ninc, const sl_options& o, bool class_tiles_ok = false);
 // Bytes of setup_mesh's temporaries for a mesh of n nodes.
 size_t setup_scratch_bytes(int32_t n);
 
@@ -407,11 +446,18 @@ struct TileLaunch {
     // 1: wg_per_cu is the automatic value (tuned, or 0 for the default),
     // which launches of fewer than kSmallLaunchTiles tiles cap at 3
     int32_t wg_auto;
+    // 1: write the buffer read (Form B: the tiles of one colour class, no
+    // two of whose nodes are adjacent)
+    int32_t in_place;
 };
 constexpr int kSmallLaunchTiles = 16384;
-constexpr int kSchedStride = 32;                    // one 128-byte line per counter
-constexpr int kTileSchedInts = 9 * kSchedStride;
 sl_status launch_sweep_tiles(const TileLaunch& L, int32_t parity, uint64_t* bits, hipStream_t st);
+// Queues one class launch of Form B on colour-class tiles (L.work: the
+// class's tiles, whose `tris` are u16 fan entries; fans_cap: the longest fan
+// list of a tile), in place in buffer 0.  L.n_close > 0 on the last class.
+sl_status launch_sweep_class(const TileLaunch& L, int32_t fans_cap, uint64_t* bits, hipStream_t st);
+// LDS bytes of one class-tile work-group.
+size_t class_lds_bytes(int tile_nodes, int halo_cap, int rows_cap, int fans_cap);
 
 // Resident meshes (Form A, double precision): one work-group runs all the
 // sweeps of one mesh with its coordinates, rows and fans in LDS.  One entry

@@ -898,17 +898,34 @@ void devmesh_free(DevMesh& m, hipStream_t st)
     m.tile_data = nullptr;
 }
 
-size_t mesh_block_bytes(int32_t n, int64_t nnz, int64_t ninc, const sl_options& o)
+// Nodes per tile: Form A's tuned or default size; a colour-class tile
+// (Form B) holds 256 unless asked otherwise (its halo is several times
+// longer than a Form A tile's, and 512-node class tiles leave room for only
+// two work-groups per CU).
+static int32_t tile_size_for(const sl_options& o)
+{
+    return o.form == SL_JACOBI ? resolve_tile_nodes(o) : (o.tile_nodes ? o.tile_nodes : 256);
+}
+
+// Whether setup aims for the tile path, decided before validation as
+// setup_mesh decides it.
+static bool wants_tiles(const sl_options& o, bool resident, bool class_tiles_ok)
+{
+    if (o.kernel == SL_KERNEL_NODE || resident) return false;
+    return o.form == SL_JACOBI || (class_tiles_ok && o.precision == SL_F64);
+}
+
+size_t mesh_block_bytes(int32_t n, int64_t nnz, int64_t ninc, const sl_options& o, bool class_tiles_ok)
 {
     // the same kernel choice as setup_mesh makes before validation
     const bool resident = o.kernel == SL_KERNEL_RESIDENT ||
                           (o.kernel == SL_KERNEL_AUTO && o.form == SL_INPLACE_COLORED &&
                            resident_fits(n, nnz, ninc, o.form == SL_INPLACE_COLORED));
-    const bool want_tiles = o.form == SL_JACOBI && o.kernel != SL_KERNEL_NODE && !resident;
+    const bool want_tiles = wants_tiles(o, resident, class_tiles_ok);
     const size_t rb = o.precision == SL_F32 ? 4 : 8;
     const size_t un = static_cast<size_t>(n);
     size_t pb = 2 * Arena::piece(4 * un) + 2 * Arena::piece(4 * (un + 1)) + Arena::piece(4 * un * rb);
-    pb += want_tiles ? tile_bytes(n, nnz, ninc, resolve_tile_nodes(o))
+    pb += want_tiles ? tile_bytes(n, nnz, ninc, tile_size_for(o), o.form != SL_JACOBI)
                      : Arena::piece(4 * static_cast<size_t>(nnz)) + Arena::piece(2 * static_cast<size_t>(ninc));
     return pb;
 }
@@ -940,13 +957,13 @@ sl_status setup_mesh(const SetupArgs& a, const sl_options& o, DevMesh& m, int32_
     if (o.kernel == SL_KERNEL_RESIDENT && !res_fit) return fail(SL_EINVAL, "mesh too large for the resident kernel");
     m.resident = o.kernel == SL_KERNEL_RESIDENT ||
                  (o.kernel == SL_KERNEL_AUTO && o.form == SL_INPLACE_COLORED && res_fit);
-    const bool want_tiles = o.form == SL_JACOBI && o.kernel != SL_KERNEL_NODE && !m.resident;
+    const bool want_tiles = wants_tiles(o, m.resident, m.class_tiles_ok);
     const size_t un = static_cast<size_t>(n);
     // Two reservations: the mesh's own arrays, sized from bounds known before
     // validation (n >= free nodes, a.nnz and a.ninc >= their rows and fans),
     // and the setup's temporaries, given back when setup ends.
     Arena persist, scratch;
-    const size_t pb = mesh_block_bytes(n, a.nnz, a.ninc, o);
+    const size_t pb = mesh_block_bytes(n, a.nnz, a.ninc, o, m.class_tiles_ok);
     const size_t sb = setup_scratch_bytes(n);
     const int gb = div_up(n, kBS);
     if (m.carve) {
@@ -973,7 +990,7 @@ sl_status setup_mesh(const SetupArgs& a, const sl_options& o, DevMesh& m, int32_
     if ((r = scratch.take(&vs, 1)) || (r = scratch.take(&vpart, gb))) return r;
     SL_HIP(hipMemsetAsync(vs, 0, sizeof(ValStats), st));
     ValArgs va{a.coords, n, a.nbr_ptr, a.nbr_idx, a.tri_ptr, a.tri_idx, a.tris, a.n_tris, a.boundary,
-               a.nnz, a.ninc, o.form == SL_INPLACE_COLORED, want_tiles,
+               a.nnz, a.ninc, o.form == SL_INPLACE_COLORED, want_tiles && o.form == SL_JACOBI,
                o.precision == SL_F32 ? 0x1p61 : 0x1p500};
     if (a.n_tris > 0) k_validate_tris<<<div_up(a.n_tris, kBS), kBS, 0, st>>>(a.tris, a.n_tris, n, vs);
     k_validate_nodes<<<gb, kBS, 0, st>>>(va, vpart);
@@ -1093,9 +1110,14 @@ sl_status setup_mesh(const SetupArgs& a, const sl_options& o, DevMesh& m, int32_
         m.X[1] = xd + n2;
         k_init_coords<double><<<gb, kBS, 0, st>>>(a.coords, m.perm, n, o.layout == SL_SOA, xd, xd + n2);
     }
-    // tile path for Form A; the node path's rows and fans otherwise
-    const bool tiles_ok = (h.err & VI_INCIDENCE) == 0;
-    if (want_tiles && tiles_ok && (r = build_tiles(a, m, resolve_tile_nodes(o), mesh, st, persist, scratch)))
+    // tile path for Form A (which needs consistent incidence rows: a tile
+    // lists a triangle once and scores it for every own vertex) and, on
+    // colour-class tiles, for Form B (each listed triangle has one own
+    // vertex, whose row listed it); the node path's rows and fans otherwise
+    const bool jacobi = o.form == SL_JACOBI;
+    const bool tiles_ok = !jacobi || (h.err & VI_INCIDENCE) == 0;
+    if (want_tiles && tiles_ok &&
+        (r = build_tiles(a, m, tile_size_for(o), mesh, st, persist, scratch, !jacobi)))
         return r;
     if (m.tile_nodes == 0 && m.precision == SL_F32 && m.n_free > 0)
         return fail(SL_EINVAL, tiles_ok ? "single precision needs the tile path, and this mesh does not fit it"

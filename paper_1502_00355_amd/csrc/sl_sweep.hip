@@ -496,6 +496,270 @@ sl_status launch_sweep_resident(const ResidentArgs* list, int32_t count, size_t 
     return SL_OK;
 }
 
+namespace {
+
+// ---------------------------------------------------- colour-class tiles --
+//
+// Form B (eq. (3)) on colour-class tiles: the free nodes of one colour class
+// are cut into tiles of T consecutive labels, one work-group per tile and
+// one launch per class, in place (no two nodes of a class are adjacent, so
+// no tile reads a position another tile writes).  A work-group stages its
+// nodes' positions, its halo (every neighbour, all of other classes), its
+// rows in tile-local indices and its nodes' fan entries in LDS, with every
+// global load of the tile in flight together; then each work-item takes one
+// node: the row-order sum and one division by the count (eq. (2)), every
+// incident triangle evaluated twice through the fan slots (Sec. 2.1), the
+// accept test and the write.  The arithmetic is the node kernel's,
+// operation for operation, so results are bit-identical to it and to the
+// oracle's coloured sweep.
+
+constexpr int kClassHalo = 8;    // halo positions per work-item at most (the build's set holds 8 T)
+constexpr int kClassWords = 4;   // row words, and fan words, per work-item at most
+
+struct ClassSweepArgs {
+    const TileWork* work;   // the tiles of one class (TileWork::tris holds the fan entries)
+    int32_t n_work, tiles_per_xcd;
+    int32_t halo_cap, rows_cap, fans_cap;   // LDS: largest halo, padded row segment and fan list
+    MeshState* states;
+    uint64_t* bits;         // nullable: accept bits of this sweep (device labels)
+};
+
+// Folds a work-group's displacement maximum and accepted count into a
+// mesh's sweep state: one pair of device-scope atomics per work-group.
+template <int T>
+__device__ __forceinline__ void fold_state(MeshState* ms, double d2, unsigned long long acc, double* s_d2,
+                                           unsigned long long* s_acc)
+{
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    for (int off = 32; off > 0; off >>= 1) {
+        const double t = __shfl_xor(d2, off);
+        d2 = t > d2 ? t : d2;
+    }
+    if (lane == 0) {
+        s_d2[wv] = d2;
+        s_acc[wv] = acc;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double mx = s_d2[0];
+        unsigned long long c = s_acc[0];
+        for (int q = 1; q < T / 64; ++q) {
+            mx = s_d2[q] > mx ? s_d2[q] : mx;
+            c += s_acc[q];
+        }
+        if (mx > 0.0) atomicMax(&ms->maxd_cur, static_cast<unsigned long long>(__double_as_longlong(mx)));
+        if (c) atomicAdd(&ms->acc_cur, c);
+    }
+    __syncthreads();
+}
+
+// Persistent work-groups: the class's tile list is cut into 8 contiguous
+// ranges, one per XCD (work-groups are dealt to the XCDs round-robin), so
+// that neighbouring tiles share an L2; the work-groups of an XCD take its
+// tiles round-robin.  The displacement maximum and accepted count run per
+// work-item over the group's tiles and are folded into the mesh's state
+// when the mesh changes and at the end: one atomic pair per group and mesh
+// (with a group per tile, tens of thousands of atomics on the same two
+// words per launch queued behind each other).
+template <int T, bool SOA, bool GT>
+__global__ __launch_bounds__(T) void k_sweep_class(ClassSweepArgs a)
+{
+    extern __shared__ double2 cls_lds[];
+    __shared__ double s_d2[T / 64];
+    __shared__ unsigned long long s_acc[T / 64];
+    __shared__ double s_recip[kMaxValence + 1];
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    for (int i = tid; i <= kMaxValence; i += T) s_recip[i] = i ? 1.0 / static_cast<double>(i) : 0.0;
+    const int xcd = static_cast<int>(blockIdx.x & 7), nw = static_cast<int>(gridDim.x >> 3);
+    const int t_begin = xcd * a.tiles_per_xcd;
+    const int t_end = min(t_begin + a.tiles_per_xcd, a.n_work);
+    double2* Xl = cls_lds;                                               // [T + halo_cap]
+    uint16_t* rows = reinterpret_cast<uint16_t*>(Xl + T + a.halo_cap);   // [rows_cap]
+    uint16_t* fans = rows + a.rows_cap;                                  // [fans_cap]
+    uint64_t* rows64 = reinterpret_cast<uint64_t*>(rows);
+    uint64_t* fans64 = reinterpret_cast<uint64_t*>(fans);
+    double run_d2 = 0.0;
+    unsigned long long run_acc = 0;
+    int mesh = -1;
+    for (int tile = t_begin + static_cast<int>(blockIdx.x >> 3); tile < t_end; tile += nw) {
+        const TileWork d = a.work[tile];
+        if (d.mesh != mesh) {
+            if (mesh >= 0) fold_state<T>(a.states + mesh, run_d2, run_acc, s_d2, s_acc);
+            run_d2 = 0.0;
+            run_acc = 0;
+            mesh = d.mesh;
+        }
+        if (!a.states[d.mesh].active) continue;   // uniform: the whole group skips the tile
+        double* X = static_cast<double*>(const_cast<void*>(d.X));   // buffer 0, in place
+        const int nown = d.nown;
+        const int ic = min(tid, nown - 1);   // a work-item past the tile repeats the last node's loads
+        const uint16_t* fr = d.rr + ((2 * T + 2 + 15) & ~15) / 2;   // fan starts follow the row starts
+        // every global load of the tile, then the LDS stores.  The loads
+        // are unconditional, with indices clamped into the tile's lists
+        // (a work-item past a list's end re-loads its last entry and
+        // stores nothing), so that none waits behind a branch: a tile's
+        // halo is at most 8 T long (the build's halo set), its row and
+        // fan words at most 4 T each (16 entries per node on average).
+        const int hc = d.halo_cnt, row_words = d.row_words, fan_words = (d.tri_cnt + 3) >> 2;
+        const int r0 = d.rr[ic], r1 = d.rr[ic + 1], f0 = fr[ic], f1 = fr[ic + 1];
+        const double2 o = ld<SOA>(X, d.n, d.own_start + ic);
+        int32_t hid[kClassHalo];
+#pragma unroll
+        for (int q = 0; q < kClassHalo; ++q) hid[q] = d.halo[min(q * T + tid, max(hc - 1, 0))];
+        uint64_t rwv[kClassWords], fwv[kClassWords];
+#pragma unroll
+        for (int q = 0; q < kClassWords; ++q) {
+            rwv[q] = d.rows[min(q * T + tid, max(row_words - 1, 0))];
+            fwv[q] = d.tris[min(q * T + tid, max(fan_words - 1, 0))];
+        }
+        double2 hp[kClassHalo];
+#pragma unroll
+        for (int q = 0; q < kClassHalo; ++q) hp[q] = ld<SOA>(X, d.n, hid[q]);
+        __syncthreads();   // the previous tile is done with the LDS
+        Xl[tid] = o;
+#pragma unroll
+        for (int q = 0; q < kClassWords; ++q) {
+            if (q * T + tid < row_words) rows64[q * T + tid] = rwv[q];
+            if (q * T + tid < fan_words) fans64[q * T + tid] = fwv[q];
+        }
+#pragma unroll
+        for (int q = 0; q < kClassHalo; ++q)
+            if (q * T + tid < hc) Xl[T + q * T + tid] = hp[q];
+        __syncthreads();
+
+        bool accepted = false;
+        if (tid < nown) {
+            // the row and the fan are read a group of entries at a time,
+            // with clamped indices, so that their dependent LDS loads
+            // overlap; sums and minima still run in stored order
+            const int dg = r1 - r0;   // >= 1 for a free node
+            double sx = 0.0, sy = 0.0;
+            for (int j0 = 0; j0 < dg; j0 += kResRow) {
+                int lab[kResRow];
+#pragma unroll
+                for (int u = 0; u < kResRow; ++u) lab[u] = rows[r0 + min(j0 + u, dg - 1)];
+                double2 p[kResRow];
+#pragma unroll
+                for (int u = 0; u < kResRow; ++u) p[u] = Xl[lab[u]];
+#pragma unroll
+                for (int u = 0; u < kResRow; ++u)
+                    if (j0 + u < dg) {
+                        sx += p[u].x;
+                        sy += p[u].y;
+                    }
+            }
+            const double dn = static_cast<double>(dg), y = s_recip[dg];
+            double cx = div_small(sx, dn, y), cy = div_small(sy, dn, y);
+            const bool tiny = !(fabs(sx) >= kStepMin) || !(fabs(sy) >= kStepMin);
+            if (tiny) {
+                cx = sx / dn;
+                cy = sy / dn;
+            }
+            double qo = INFINITY, qn = INFINITY;
+            for (int g0 = f0; g0 < f1; g0 += kResFan) {
+                uint32_t e[kResFan];
+#pragma unroll
+                for (int u = 0; u < kResFan; ++u) e[u] = fans[min(g0 + u, f1 - 1)];
+                int la[kResFan], lb[kResFan];
+#pragma unroll
+                for (int u = 0; u < kResFan; ++u) {
+                    la[u] = rows[r0 + ((e[u] >> 2) & 127u)];
+                    lb[u] = rows[r0 + ((e[u] >> 9) & 127u)];
+                }
+                double2 va[kResFan], vb[kResFan];
+#pragma unroll
+                for (int u = 0; u < kResFan; ++u) {
+                    va[u] = Xl[la[u]];
+                    vb[u] = Xl[lb[u]];
+                }
+#pragma unroll
+                for (int u = 0; u < kResFan; ++u) {
+                    if (g0 + u >= f1) break;
+                    const int pp = static_cast<int>(e[u] & 3u);
+                    const double v = fan_quality(pp, o.x, o.y, va[u], vb[u]);
+                    if (v < qo) qo = v;
+                    const double w = fan_quality(pp, cx, cy, va[u], vb[u]);
+                    if (w < qn) qn = w;
+                }
+            }
+            accepted = GT ? (qn > qo) : (qn >= qo);
+            const double nx = accepted ? cx : o.x, ny = accepted ? cy : o.y;
+            st<SOA>(X, d.n, d.own_start + tid, nx, ny);
+            const double dx = nx - o.x, dy = ny - o.y;
+            const double t2 = dx * dx + dy * dy;
+            run_d2 = t2 > run_d2 ? t2 : run_d2;
+        }
+        const unsigned long long ball = __ballot(accepted);
+        run_acc += __popcll(ball);
+        if (a.bits != nullptr && lane == 0 && ball != 0ull) {
+            // a class tile starts at any label: the wave's bits may straddle two words
+            const int kw = d.own_start + wv * 64, sh = kw & 63;
+            unsigned long long* word = reinterpret_cast<unsigned long long*>(a.bits) + (kw >> 6);
+            atomicOr(word, ball << sh);
+            if (sh != 0 && (ball >> (64 - sh)) != 0ull) atomicOr(word + 1, ball >> (64 - sh));
+        }
+    }
+    if (mesh >= 0) fold_state<T>(a.states + mesh, run_d2, run_acc, s_d2, s_acc);
+}
+
+template <int T>
+void launch_class_t(const ClassSweepArgs& a, bool soa, bool gt, int grid, size_t lds, hipStream_t st)
+{
+    const void* fn = soa ? (gt ? reinterpret_cast<const void*>(&k_sweep_class<T, true, true>)
+                               : reinterpret_cast<const void*>(&k_sweep_class<T, true, false>))
+                         : (gt ? reinterpret_cast<const void*>(&k_sweep_class<T, false, true>)
+                               : reinterpret_cast<const void*>(&k_sweep_class<T, false, false>));
+    if (lds > 64 * 1024) {
+        (void)hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds));
+        (void)hipGetLastError();
+    }
+    if (soa) {
+        if (gt) k_sweep_class<T, true, true><<<grid, T, lds, st>>>(a);
+        else k_sweep_class<T, true, false><<<grid, T, lds, st>>>(a);
+    } else {
+        if (gt) k_sweep_class<T, false, true><<<grid, T, lds, st>>>(a);
+        else k_sweep_class<T, false, false><<<grid, T, lds, st>>>(a);
+    }
+}
+
+}  // namespace
+
+size_t class_lds_bytes(int tile_nodes, int halo_cap, int rows_cap, int fans_cap)
+{
+    return static_cast<size_t>(tile_nodes + halo_cap) * 16 + static_cast<size_t>(rows_cap) * 2 +
+           static_cast<size_t>((fans_cap + 3) & ~3) * 2;
+}
+
+sl_status launch_sweep_class(const TileLaunch& L, int32_t fans_cap, uint64_t* bits, hipStream_t st)
+{
+    if (L.halo_cap > kClassHalo * L.tile_nodes) return fail(SL_EINVAL, "internal: class tile halo too long");
+    if (L.n_work > 0) {
+        ClassSweepArgs a{};
+        a.work = L.work;
+        a.n_work = L.n_work;
+        a.tiles_per_xcd = div_up(L.n_work, 8);
+        a.halo_cap = L.halo_cap;
+        a.rows_cap = L.rows_cap;
+        a.fans_cap = (fans_cap + 3) & ~3;
+        a.states = L.states;
+        a.bits = bits;
+        const size_t lds = class_lds_bytes(L.tile_nodes, L.halo_cap, L.rows_cap, fans_cap);
+        // persistent: as many groups per CU as the LDS holds (at most
+        // 2048 / T, or the option's count), 32 CUs per XCD, never more
+        // groups on an XCD than it has tiles
+        const int fit = std::max(1, static_cast<int>(kTileLdsLimit / std::max<size_t>(lds, 1)));
+        int per_cu = std::min(fit, 2048 / L.tile_nodes);
+        if (L.wg_per_cu > 0) per_cu = std::min(per_cu, static_cast<int>(L.wg_per_cu));
+        const int grid = 8 * std::min(a.tiles_per_xcd, 32 * per_cu);
+        const bool soa = L.layout == SL_SOA, gt = L.accept == SL_ACCEPT_GT;
+        if (L.tile_nodes == 128) launch_class_t<128>(a, soa, gt, grid, lds, st);
+        else if (L.tile_nodes == 256) launch_class_t<256>(a, soa, gt, grid, lds, st);
+        else launch_class_t<512>(a, soa, gt, grid, lds, st);
+        SL_HIP(hipGetLastError());
+    }
+    return L.n_close > 0 ? launch_advance(L.states, L.n_close, st) : SL_OK;
+}
+
 sl_status launch_advance(MeshState* states, int32_t n, hipStream_t st)
 {
     if (n <= 0) return SL_OK;

@@ -46,12 +46,22 @@ __device__ int block_excl_scan(int v, int* total, int* s_warp)
 
 // Open-addressing set of node labels in LDS (-1 = empty slot), linear
 // probing from the label's low bits: halo labels come in runs of nearby
-// labels, which then land in nearby slots with few collisions.  Probing
-// stops after HS slots, so a full table reports failure instead of looping.
-template <int HS>
+// labels, which then land in nearby slots with few collisions.  A
+// colour-class tile's halo is a run in each of the other classes' label
+// ranges, runs whose low bits overlap: MIX starts the probe at a
+// multiplicative hash of the label instead.  Probing stops after HS slots,
+// so a full table reports failure instead of looping.
+template <int HS, bool MIX>
+__device__ __forceinline__ int set_home(int32_t key)
+{
+    if (!MIX) return key & (HS - 1);
+    return static_cast<int>((static_cast<uint32_t>(key) * 2654435761u) >> (32 - __builtin_ctz(HS)));
+}
+
+template <int HS, bool MIX>
 __device__ bool set_insert(int32_t* tab, int32_t key)
 {
-    int s = key & (HS - 1);
+    int s = set_home<HS, MIX>(key);
     for (int p = 0; p < HS; ++p) {
         const int32_t cur = tab[s];
         if (cur == key) return true;
@@ -64,10 +74,10 @@ __device__ bool set_insert(int32_t* tab, int32_t key)
     return false;
 }
 
-template <int HS>
+template <int HS, bool MIX>
 __device__ int set_find(const int32_t* tab, int32_t key)
 {
-    int s = key & (HS - 1);
+    int s = set_home<HS, MIX>(key);
     for (int p = 0; p < HS; ++p) {
         const int32_t cur = tab[s];
         if (cur == key) return s;
@@ -96,6 +106,13 @@ struct TileBuildArgs {
     unsigned char* data;       // tile k's record at tile_record(k): row offsets, halo, rows, triangles
     TileWork* work;            // [n_tiles]
     int32_t* err;
+    // 0: tile k holds free nodes [k T, k T + T).  Else colour-class tiles:
+    // class c (device labels [cls_start[c], cls_start[c+1])) is cut into
+    // tiles [cls_tile[c], cls_tile[c+1]) of T consecutive labels, the last
+    // one of a class possibly shorter
+    int32_t n_class;
+    int32_t cls_start[kMaxTileClasses + 1];
+    int32_t cls_tile[kMaxTileClasses + 1];
 };
 
 __host__ __device__ __forceinline__ int64_t align16(int64_t b) { return (b + 15) & ~int64_t(15); }
@@ -115,6 +132,16 @@ __host__ __device__ __forceinline__ int64_t tile_record(int32_t row_start, int32
 }
 __host__ __device__ __forceinline__ int64_t halo_at(int T) { return align16(2 * static_cast<int64_t>(T) + 2); }
 
+// A colour-class tile's record holds T + 1 u16 row starts, T + 1 u16 fan
+// starts (node i's fan entries are start[i] .. start[i+1]), room for len
+// halo ids, the rows (len rounded up to 4 u16) and flen u16 fan entries,
+// each part 16-byte aligned: at most 4T + 6 len + 2 flen + 100 bytes.
+__host__ __device__ __forceinline__ int64_t class_record(int32_t row_start, int32_t fan_start, int32_t tile, int T)
+{
+    return static_cast<int64_t>(tile) * (4 * T + 128) +
+           align16(6 * static_cast<int64_t>(row_start) + 2 * static_cast<int64_t>(fan_start));
+}
+
 // One work-group per tile, in one pass: every output of tile k goes to a
 // place fixed by the row and incidence offsets of its first node, so no
 // tile needs another's counts.
@@ -131,20 +158,34 @@ __host__ __device__ __forceinline__ int64_t halo_at(int T) { return align16(2 * 
 // the node offsets (a node has at least one row entry); the small LDS
 // footprint lets more tiles build at once.  Neither the halo order nor the triangle order
 // changes a result: sums run over rows, minima are exact.
-template <int T>
+// CLS: a colour-class tile (Form B).  Its nodes are spread out (no two
+// adjacent), so its halo is several times longer and the halo set has 8 T
+// slots instead of 4 T; and instead of triangle words it gets one fan entry
+// per incidence, in incidence order: the node's position p in the
+// triangle's stored order and the row slots of the vertices at p+1 and
+// p+2 (mod 3), p | slot << 2 | slot << 9, with the fan starts.
+template <int T, bool CLS>
 __global__ __launch_bounds__(kBuildBS) void k_tile_build(TileBuildArgs a)
 {
-    constexpr int BS = kBuildBS, U = kBuildU, CAP = T * kTileMaxDeg, HS = 4 * T, SPT = HS / BS;
+    constexpr int HS = CLS ? 8 * T : 4 * T;
+    constexpr int BS = kBuildBS, U = kBuildU, CAP = T * kTileMaxDeg, SPT = HS / BS;
     __shared__ int32_t htab[HS];
     __shared__ uint16_t hidx[HS];
     __shared__ uint16_t own[CAP / 16];   // owner of entries 16b, 16b+1, ... starts the search
     __shared__ int32_t s_nb[T], s_tb[T], s_rs[T + 1], s_fs[T + 1];
+    __shared__ uint16_t s_seg[CLS ? CAP : 1];   // class tiles: the rows in local indices, for the slot search
     __shared__ int32_t s_warp[BS / 64];
     __shared__ int32_t s_full;
     const int tid = threadIdx.x;
     const int tile = blockIdx.x;
-    const int32_t k0 = tile * T;
-    const int nown = min(T, a.n_free - k0);
+    int32_t k0 = tile * T, kend = a.n_free;
+    if (a.n_class > 0) {
+        int c = 0;
+        while (c + 1 < a.n_class && tile >= a.cls_tile[c + 1]) ++c;
+        k0 = a.cls_start[c] + (tile - a.cls_tile[c]) * T;
+        kend = a.cls_start[c + 1];
+    }
+    const int nown = min(T, kend - k0);
     const int32_t rb = a.row_ptr[k0], fb = a.fan_ptr[k0];
     const int32_t len = a.row_ptr[k0 + nown] - rb, flen = a.fan_ptr[k0 + nown] - fb;
     if (len > CAP || flen > CAP) {   // denser than the LDS maps hold: the mesh takes the node path
@@ -179,9 +220,10 @@ __global__ __launch_bounds__(kBuildBS) void k_tile_build(TileBuildArgs a)
     // ---- halo set; the row entries' device labels are parked in the halo
     // part of the record (room for len entries) until the rows are
     // rewritten below
-    unsigned char* rec = a.data + tile_record(rb, fb, tile, T);
+    unsigned char* rec = a.data + (CLS ? class_record(rb, fb, tile, T) : tile_record(rb, fb, tile, T));
     uint16_t* rr = reinterpret_cast<uint16_t*>(rec);
-    int32_t* halo = reinterpret_cast<int32_t*>(rec + halo_at(T));
+    const int64_t hat = CLS ? 2 * halo_at(T) : halo_at(T);
+    int32_t* halo = reinterpret_cast<int32_t*>(rec + hat);
     bool full = false;
     for (int base = 0; base < len; base += BS * U) {
         int32_t jd[U];
@@ -194,7 +236,7 @@ __global__ __launch_bounds__(kBuildBS) void k_tile_build(TileBuildArgs a)
         for (int u = 0; u < U; ++u) {
             const int j = base + u * BS + tid;
             if (j < len) halo[j] = jd[u];
-            if (!in_tile(jd[u]) && !set_insert<HS>(htab, jd[u])) full = true;
+            if (!in_tile(jd[u]) && !set_insert<HS, CLS>(htab, jd[u])) full = true;
         }
     }
     if (full) s_full = 1;
@@ -219,7 +261,7 @@ __global__ __launch_bounds__(kBuildBS) void k_tile_build(TileBuildArgs a)
     __syncthreads();
     auto local = [&](int32_t jd) -> int {
         if (in_tile(jd)) return jd - k0;
-        const int s = set_find<HS>(htab, jd);
+        const int s = set_find<HS, CLS>(htab, jd);
         if (s < 0) {
             atomicOr(a.err, 1);
             return T;
@@ -229,9 +271,13 @@ __global__ __launch_bounds__(kBuildBS) void k_tile_build(TileBuildArgs a)
 
     // ---- rows in local indices, and their offsets
     const int32_t len4 = (len + 3) & ~3;
-    const int64_t seg_at = align16(halo_at(T) + 4 * static_cast<int64_t>(len));
+    const int64_t seg_at = align16(hat + 4 * static_cast<int64_t>(len));
     uint16_t* seg = reinterpret_cast<uint16_t*>(rec + seg_at);
-    for (int j = tid; j < len; j += BS) seg[j] = static_cast<uint16_t>(local(halo[j]));
+    for (int j = tid; j < len; j += BS) {
+        const uint16_t l = static_cast<uint16_t>(local(halo[j]));
+        seg[j] = l;
+        if (CLS) s_seg[j] = l;
+    }
     for (int j = len + tid; j < len4; j += BS) seg[j] = 0;
     __syncthreads();   // every parked label is read: the halo list takes their place
     {
@@ -248,11 +294,53 @@ __global__ __launch_bounds__(kBuildBS) void k_tile_build(TileBuildArgs a)
         for (int b = (s_fs[i] + 15) >> 4; (b << 4) < s_fs[i + 1]; ++b) own[b] = static_cast<uint16_t>(i);
     __syncthreads();
 
-    // ---- triangles: work-item t takes incidences U*t .. U*t+U-1 of each
-    // chunk, so that a scan of the per-item counts keeps incidence order
     uint64_t* tri = reinterpret_cast<uint64_t*>(rec + align16(seg_at + 2 * static_cast<int64_t>(len4)));
     int R = 0;
-    for (int base = 0; base < flen; base += BS * U) {
+    if (CLS) {
+        // ---- fan entries, one per incidence, and the fan starts
+        uint16_t* fans = reinterpret_cast<uint16_t*>(tri);
+        uint16_t* fr = rr + halo_at(T) / 2;
+        for (int i = tid; i <= T; i += BS) fr[i] = static_cast<uint16_t>(s_fs[min(i, nown)]);
+        for (int base = 0; base < flen; base += BS * U) {
+            int32_t v[U][3], kd[U], i_of[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int f = base + u * BS + tid;
+                int64_t t = 0;
+                kd[u] = k0;
+                i_of[u] = 0;
+                if (f < flen) {
+                    int i = own[f >> 4];
+                    while (s_fs[i + 1] <= f) ++i;
+                    kd[u] = k0 + i;
+                    i_of[u] = i;
+                    t = a.tri_idx[s_tb[i] + (f - s_fs[i])];
+                }
+#pragma unroll
+                for (int q = 0; q < 3; ++q) v[u][q] = f < flen ? a.new_of_old[a.tris[3 * t + q]] : kd[u];
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int f = base + u * BS + tid;
+                if (f >= flen) continue;
+                const int p = v[u][0] == kd[u] ? 0 : (v[u][1] == kd[u] ? 1 : 2);
+                const int la = local(v[u][(p + 1) % 3]), lb = local(v[u][(p + 2) % 3]);
+                const int r0 = s_rs[i_of[u]], r1 = s_rs[i_of[u] + 1];
+                int sa = -1, sb = -1;
+                for (int j = r0; j < r1; ++j) {
+                    const int l = s_seg[j];
+                    if (l == la) sa = j - r0;
+                    if (l == lb) sb = j - r0;
+                }
+                if (sa < 0 || sb < 0) atomicOr(a.err, 1);   // validation rules this out
+                fans[f] = static_cast<uint16_t>(p | (max(sa, 0) << 2) | (max(sb, 0) << 9));
+            }
+        }
+        R = flen;
+    }
+    // ---- triangles: work-item t takes incidences U*t .. U*t+U-1 of each
+    // chunk, so that a scan of the per-item counts keeps incidence order
+    for (int base = 0; !CLS && base < flen; base += BS * U) {
         int32_t v[U][3], kd[U];
         bool keep[U];
 #pragma unroll
@@ -400,30 +488,46 @@ __global__ __launch_bounds__(1024) void k_tile_caps(const TileWork* __restrict__
 
 }  // namespace
 
-size_t tile_bytes(int64_t n, int64_t nnz, int64_t ninc, int tile_nodes)
+size_t tile_bytes(int64_t n, int64_t nnz, int64_t ninc, int tile_nodes, bool classes)
 {
-    if (tile_nodes != 256 && tile_nodes != 512) return 0;   // build_tiles takes nothing then
-    const size_t nt = static_cast<size_t>(div_up(std::max<int64_t>(n, 1), tile_nodes));
+    // build_tiles takes nothing for other sizes
+    if (tile_nodes != 256 && tile_nodes != 512 && !(classes && tile_nodes == 128)) return 0;
+    // colour-class tiles: at most one short tile per class more
+    const size_t nt = static_cast<size_t>(div_up(std::max<int64_t>(n, 1), tile_nodes)) +
+                      (classes ? static_cast<size_t>(kMaxTileClasses) : 0);
     const size_t z = static_cast<size_t>(std::max<int64_t>(nnz, 1)), c = static_cast<size_t>(std::max<int64_t>(ninc, 1));
-    return Arena::piece(sizeof(TileWork) * nt) + Arena::piece(nt * (2 * tile_nodes + 64) + 6 * z + 8 * c + 16);
+    const size_t rec = classes ? nt * (4 * tile_nodes + 128) + 6 * z + 2 * c + 16
+                               : nt * (2 * tile_nodes + 64) + 6 * z + 8 * c + 16;
+    return Arena::piece(sizeof(TileWork) * nt) + Arena::piece(rec);
 }
 
 size_t tile_scratch_bytes() { return Arena::piece(4 * sizeof(int32_t)); }
 
 sl_status build_tiles(const SetupArgs& a, DevMesh& m, int tile_nodes, int mesh, hipStream_t st, Arena& persist,
-                      Arena& scratch)
+                      Arena& scratch, bool classes)
 {
     m.tile_nodes = 0;
-    if ((tile_nodes != 256 && tile_nodes != 512) || m.n_free == 0) return SL_OK;
+    m.n_tile_classes = 0;
+    if ((tile_nodes != 256 && tile_nodes != 512 && !(classes && tile_nodes == 128)) || m.n_free == 0) return SL_OK;
+    if (classes && (m.n_colors < 1 || m.n_colors > kMaxTileClasses)) return SL_OK;
     const int T = tile_nodes;
-    const int nt = div_up(m.n_free, T);
+    int nt = div_up(m.n_free, T);
+    if (classes) {
+        nt = 0;
+        for (int c = 0; c < m.n_colors; ++c) {
+            m.class_tile_h[c] = nt;
+            nt += div_up(m.color_start_h[c + 1] - m.color_start_h[c], T);
+        }
+        m.class_tile_h[m.n_colors] = nt;
+    }
     const size_t pmark = persist.mark(), smark = scratch.mark();
     sl_status r = SL_OK;
     int32_t* flags = nullptr;   // {err, largest halo, largest row segment, largest triangle list}
     if ((r = scratch.take(&flags, 4))) return r;
     SL_HIP(hipMemsetAsync(flags, 0, 4 * sizeof(int32_t), st));
-    const size_t data_bytes = static_cast<size_t>(tile_record(static_cast<int32_t>(m.nnz_free),
-                                                              static_cast<int32_t>(m.ninc_free), nt, T));
+    const size_t data_bytes =
+        static_cast<size_t>(classes ? class_record(static_cast<int32_t>(m.nnz_free), static_cast<int32_t>(m.ninc_free), nt, T)
+                                    : tile_record(static_cast<int32_t>(m.nnz_free), static_cast<int32_t>(m.ninc_free), nt, T));
     if ((r = persist.take(&m.work, nt)) || (r = persist.take(&m.tile_data, data_bytes))) return r;
     TileBuildArgs b{};
     b.perm = m.perm;
@@ -442,8 +546,19 @@ sl_status build_tiles(const SetupArgs& a, DevMesh& m, int tile_nodes, int mesh, 
     b.data = m.tile_data;
     b.work = m.work;
     b.err = flags;
-    if (T == 256) k_tile_build<256><<<nt, kBuildBS, 0, st>>>(b);
-    else k_tile_build<512><<<nt, kBuildBS, 0, st>>>(b);
+    b.n_class = classes ? m.n_colors : 0;
+    for (int c = 0; classes && c <= m.n_colors; ++c) {
+        b.cls_start[c] = m.color_start_h[c];
+        b.cls_tile[c] = m.class_tile_h[c];
+    }
+    if (classes) {
+        if (T == 128) k_tile_build<128, true><<<nt, kBuildBS, 0, st>>>(b);
+        else if (T == 256) k_tile_build<256, true><<<nt, kBuildBS, 0, st>>>(b);
+        else k_tile_build<512, true><<<nt, kBuildBS, 0, st>>>(b);
+    } else {
+        if (T == 256) k_tile_build<256, false><<<nt, kBuildBS, 0, st>>>(b);
+        else k_tile_build<512, false><<<nt, kBuildBS, 0, st>>>(b);
+    }
     k_tile_caps<<<1, 1024, 0, st>>>(m.work, nt, flags + 1);
     SL_HIP(hipGetLastError());
     int32_t h[4] = {0, 0, 0, 0};
@@ -453,13 +568,15 @@ sl_status build_tiles(const SetupArgs& a, DevMesh& m, int tile_nodes, int mesh, 
     if (h[0] & 1) return fail(SL_ETOPO, "triangle vertex outside its tile's neighbourhood");
     // a tile denser than the staging holds, or a halo or row segment too big
     // for LDS: the node path, whose arrays reuse the tile arrays' room
-    if ((h[0] & 2) || tile_lds_bytes(T, h[1], h[2], m.precision) > kTileLdsLimit) {
+    const size_t lds = classes ? class_lds_bytes(T, h[1], h[2], h[3]) : tile_lds_bytes(T, h[1], h[2], m.precision);
+    if ((h[0] & 2) || lds > kTileLdsLimit) {
         m.work = nullptr;
         m.tile_data = nullptr;
         persist.rewind(pmark);
         return SL_OK;
     }
-    const int cap = std::min(h[3], kOrderWords);
+    // (class tiles have fan entries, not triangle words: nothing to group)
+    const int cap = classes ? 0 : std::min(h[3], kOrderWords);
     if (cap > 0) {
         const size_t lds = sizeof(uint64_t) * static_cast<size_t>(cap);
         if (T == 256) k_tile_order<256><<<nt, 256, lds, st>>>(m.work, cap);
@@ -468,8 +585,10 @@ sl_status build_tiles(const SetupArgs& a, DevMesh& m, int tile_nodes, int mesh, 
     SL_HIP(hipGetLastError());
     m.halo_max = h[1];
     m.rows_max = h[2];
+    m.fans_max = h[3];
     m.n_tiles = nt;
     m.tile_nodes = T;
+    m.n_tile_classes = classes ? m.n_colors : 0;
     return SL_OK;
 }
 

@@ -97,6 +97,7 @@ struct TileSweepArgs {
     const TileWork* work;
     int32_t n_work, tiles_per_xcd, halo_cap, rows_cap;
     int32_t parity;            // every mesh of the launch reads buffer `parity`
+    int32_t out_parity;        // and writes buffer `out_parity`: parity ^ 1 (Form A), or parity (Form B in place)
     int32_t exit_if_inactive;  // all tiles are of one mesh: return at once if it has stopped
     MeshState* states;
     uint64_t* bits;            // nullable: accept bits of this sweep (single mesh)
@@ -410,7 +411,7 @@ __device__ __forceinline__ void sweep_tiles(const TileSweepArgs& a)
         if (run) {
             __attribute__((address_space(1))) R* Xout =
                 reinterpret_cast<__attribute__((address_space(1))) R*>(reinterpret_cast<uint64_t>(dcur.X)) +
-                (parity ^ 1) * 2 * dcur.n;
+                a.out_parity * 2 * dcur.n;
             const int k0 = dcur.own_start;
 #pragma unroll
             for (int m = 0; m < NPT; ++m) {
@@ -435,8 +436,13 @@ __device__ __forceinline__ void sweep_tiles(const TileSweepArgs& a)
                 }
                 const unsigned long long ball = __ballot(accepted);
                 run_acc += __popcll(ball);
-                if (a.bits != nullptr && lane == 0 && ball != 0ull)
-                    atomicOr(reinterpret_cast<unsigned long long*>(a.bits) + ((k0 + m * BS + wv * 64) >> 6), ball);
+                if (a.bits != nullptr && lane == 0 && ball != 0ull) {
+                    // a colour-class tile starts at any label: the wave's bits may straddle two words
+                    const int kw = k0 + m * BS + wv * 64, sh = kw & 63;
+                    unsigned long long* word = reinterpret_cast<unsigned long long*>(a.bits) + (kw >> 6);
+                    atomicOr(word, ball << sh);
+                    if (sh != 0 && (ball >> (64 - sh)) != 0ull) atomicOr(word + 1, ball >> (64 - sh));
+                }
             }
         }
         if (!has_next || dnext.mesh != dcur.mesh) {
@@ -472,32 +478,6 @@ __device__ __forceinline__ void sweep_tiles(const TileSweepArgs& a)
         act_cur = act_next;
         __syncthreads();
     }
-}
-
-// The last work-group of a launch to finish closes the sweep of states[0..n)
-// and zeroes the launch's counters for the next launch.  A group's folds into the
-// sweep state are device-scope atomics made by its first work-item; the
-// work-group-scope release waits until they have completed, so they are
-// performed before the group's count.  The closing group reads the folds
-// with device-scope atomic loads after it has seen every count.  No
-// device-scope release or acquire is needed: those would write back or
-// invalidate the XCD's L2, once per work-group.
-template <int BS>
-__device__ __forceinline__ void close_launch(int32_t* sched, MeshState* states, int32_t n)
-{
-    int32_t* const count = sched;
-    __shared__ int s_last;
-    __syncthreads();   // every work-item of the group is done with its tiles
-    if (threadIdx.x == 0) {
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
-        const int before = __hip_atomic_fetch_add(count, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        s_last = before == static_cast<int>(gridDim.x) - 1;
-    }
-    __syncthreads();
-    if (!s_last) return;
-    for (int i = threadIdx.x; i < n; i += BS) close_state(states + i);
-    if (threadIdx.x < 9)
-        __hip_atomic_store(sched + kSchedStride * threadIdx.x, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 template <int T, int BS, bool SOA, bool GT, typename R>
@@ -572,6 +552,7 @@ sl_status launch_sweep_tiles(const TileLaunch& L, int32_t parity, uint64_t* bits
     a.halo_cap = L.halo_cap;
     a.rows_cap = L.rows_cap;
     a.parity = parity;
+    a.out_parity = L.in_place ? parity : parity ^ 1;
     a.exit_if_inactive = L.exit_if_inactive;
     a.states = L.states;
     a.bits = bits;
