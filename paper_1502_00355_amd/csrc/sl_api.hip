@@ -265,7 +265,6 @@ sl_status run_device(double* coords, int32_t n, const int32_t* nbr_ptr, const in
                 Lc.work = cs.m.work + cs.m.class_tile_h[c];
                 Lc.n_work = cs.m.class_tile_h[c + 1] - cs.m.class_tile_h[c];
                 Lc.n_close = c + 1 == cs.m.n_tile_classes ? 1 : 0;
-                Lc.in_place = 1;
                 Lc.wg_per_cu = o.tile_wg_per_cu;   // a count tuned for Form A's tiles does not apply
                 const sl_status rr = launch_sweep_class(Lc, cs.m.fans_max, bits, on);
                 if (rr) return rr;

@@ -446,9 +446,6 @@ struct TileLaunch {
     // 1: wg_per_cu is the automatic value (tuned, or 0 for the default),
     // which launches of fewer than kSmallLaunchTiles tiles cap at 3
     int32_t wg_auto;
-    // 1: write the buffer read (Form B: the tiles of one colour class, no
-    // two of whose nodes are adjacent)
-    int32_t in_place;
 };
 constexpr int kSmallLaunchTiles = 16384;
 sl_status launch_sweep_tiles(const TileLaunch& L, int32_t parity, uint64_t* bits, hipStream_t st);

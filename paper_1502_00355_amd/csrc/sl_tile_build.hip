@@ -1,11 +1,14 @@
-// Tile build of the Form A (Jacobi) sweep.
+// Tile build of the tile sweeps.
 //
-// The free nodes (device order: Hilbert cells) are cut into tiles of T
-// consecutive labels; the sweep runs one work-group per tile.  The tiles are
-// built on the device: one work-group per tile collects the halo (every
-// node an own node reads) in an LDS hash set, lists the incident triangles,
-// and rewrites rows and triangles in tile-local indices (own nodes 0..T-1,
-// halo nodes T..T+H-1).
+// Form A (Jacobi): the free nodes (device order: Hilbert cells) are cut into
+// tiles of T consecutive labels.  Form B (coloured, in place): each colour
+// class (contiguous in device order, Hilbert cells inside) is cut into tiles
+// of T consecutive labels.  The sweeps run one work-group per tile.  The
+// tiles are built on the device: one work-group per tile collects the halo
+// (every node an own node reads) in an LDS hash set and rewrites the rows in
+// tile-local indices (own nodes 0..T-1, halo nodes T..T+H-1); a Form A tile
+// lists its incident triangles in local indices, a colour-class tile gets
+// one fan entry per incidence instead.
 #include <algorithm>
 #include <climits>
 #include <cstdlib>

@@ -96,8 +96,7 @@ __device__ __forceinline__ R div_step(R a, R d, R y)
 struct TileSweepArgs {
     const TileWork* work;
     int32_t n_work, tiles_per_xcd, halo_cap, rows_cap;
-    int32_t parity;            // every mesh of the launch reads buffer `parity`
-    int32_t out_parity;        // and writes buffer `out_parity`: parity ^ 1 (Form A), or parity (Form B in place)
+    int32_t parity;            // every mesh of the launch reads buffer `parity`, writes parity ^ 1
     int32_t exit_if_inactive;  // all tiles are of one mesh: return at once if it has stopped
     MeshState* states;
     uint64_t* bits;            // nullable: accept bits of this sweep (single mesh)
@@ -411,7 +410,7 @@ __device__ __forceinline__ void sweep_tiles(const TileSweepArgs& a)
         if (run) {
             __attribute__((address_space(1))) R* Xout =
                 reinterpret_cast<__attribute__((address_space(1))) R*>(reinterpret_cast<uint64_t>(dcur.X)) +
-                a.out_parity * 2 * dcur.n;
+                (parity ^ 1) * 2 * dcur.n;
             const int k0 = dcur.own_start;
 #pragma unroll
             for (int m = 0; m < NPT; ++m) {
@@ -436,13 +435,8 @@ __device__ __forceinline__ void sweep_tiles(const TileSweepArgs& a)
                 }
                 const unsigned long long ball = __ballot(accepted);
                 run_acc += __popcll(ball);
-                if (a.bits != nullptr && lane == 0 && ball != 0ull) {
-                    // a colour-class tile starts at any label: the wave's bits may straddle two words
-                    const int kw = k0 + m * BS + wv * 64, sh = kw & 63;
-                    unsigned long long* word = reinterpret_cast<unsigned long long*>(a.bits) + (kw >> 6);
-                    atomicOr(word, ball << sh);
-                    if (sh != 0 && (ball >> (64 - sh)) != 0ull) atomicOr(word + 1, ball >> (64 - sh));
-                }
+                if (a.bits != nullptr && lane == 0 && ball != 0ull)
+                    atomicOr(reinterpret_cast<unsigned long long*>(a.bits) + ((k0 + m * BS + wv * 64) >> 6), ball);
             }
         }
         if (!has_next || dnext.mesh != dcur.mesh) {
@@ -552,7 +546,6 @@ sl_status launch_sweep_tiles(const TileLaunch& L, int32_t parity, uint64_t* bits
     a.halo_cap = L.halo_cap;
     a.rows_cap = L.rows_cap;
     a.parity = parity;
-    a.out_parity = L.in_place ? parity : parity ^ 1;
     a.exit_if_inactive = L.exit_if_inactive;
     a.states = L.states;
     a.bits = bits;
