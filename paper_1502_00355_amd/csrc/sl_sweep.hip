@@ -46,11 +46,17 @@ __device__ __forceinline__ double tri_quality(double x0, double y0, double x1, d
 
 // Quality of the triangle whose stored order puts the node at position p,
 // the vertex `a` at p+1 and `b` at p+2 (mod 3), with the node at (ox, oy).
+// The stored order is rebuilt with selects, not branches: the lanes of a
+// wave take different nodes, whose positions p differ, and a branch per p
+// made a wave evaluate all three orders one after the other.
 __device__ __forceinline__ double fan_quality(int p, double ox, double oy, const double2 a, const double2 b)
 {
-    if (p == 0) return tri_quality(ox, oy, a.x, a.y, b.x, b.y);
-    if (p == 1) return tri_quality(b.x, b.y, ox, oy, a.x, a.y);
-    return tri_quality(a.x, a.y, b.x, b.y, ox, oy);
+    // slot k of the stored order holds the node when p == k, else q_k
+    const double2 q0 = p == 1 ? b : a, q1 = p == 0 ? a : b, q2 = p == 0 ? b : a;
+    const double x0 = p == 0 ? ox : q0.x, y0 = p == 0 ? oy : q0.y;
+    const double x1 = p == 1 ? ox : q1.x, y1 = p == 1 ? oy : q1.y;
+    const double x2 = p == 2 ? ox : q2.x, y2 = p == 2 ? oy : q2.y;
+    return tri_quality(x0, y0, x1, y1, x2, y2);
 }
 
 template <bool SOA>
