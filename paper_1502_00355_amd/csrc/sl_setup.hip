@@ -251,7 +251,6 @@ struct ValArgs {
     const uint8_t* boundary;
     int64_t nnz, ninc;
     int check_symmetry;
-    int check_incidence;   // look for incidence rows that disagree between free vertices (tile path)
     double coord_limit;    // coordinates must be below this in magnitude
 };
 
@@ -275,6 +274,61 @@ __global__ __launch_bounds__(kBS) void k_validate_tris(const int32_t* __restrict
         if (a == b || b == c || a == c) e |= VE_TRIREP;
     }
     if (e) atomicOr(&vs->err, e);
+}
+
+// Incidence rows that disagree (for the Form A tile path, which lists a
+// triangle once per tile and scores it for every own vertex): a triangle
+// listed by some of its free vertices but not by all of them.  One
+// work-item per triangle looks for it in its free vertices' rows, the three
+// rows' offsets and first kIncRegs entries loaded together.  Vertices out of
+// range and offsets out of order are left to the other checks.
+constexpr int kIncRegs = 8;
+__global__ __launch_bounds__(kBS) void k_validate_incidence(const int32_t* __restrict__ tris, int32_t n_tris, int32_t n,
+                                                            const uint8_t* __restrict__ bnd,
+                                                            const int32_t* __restrict__ tri_ptr,
+                                                            const int32_t* __restrict__ tri_idx, int64_t ninc,
+                                                            ValStats* __restrict__ vs)
+{
+    const int64_t t = static_cast<int64_t>(blockIdx.x) * kBS + threadIdx.x;
+    if (t >= n_tris) return;
+    int32_t v[3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) v[k] = tris[3 * t + k];
+#pragma unroll
+    for (int k = 0; k < 3; ++k)
+        if (v[k] < 0 || v[k] >= n) return;
+    int32_t ob[3], oe[3];
+    uint8_t fl[3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        fl[k] = bnd[v[k]];
+        ob[k] = tri_ptr[v[k]];
+        oe[k] = tri_ptr[v[k] + 1];
+    }
+    bool use[3];
+    int32_t len[3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        use[k] = fl[k] == 0 && 0 <= ob[k] && ob[k] <= oe[k] && oe[k] <= ninc;
+        len[k] = use[k] ? oe[k] - ob[k] : 0;
+    }
+    int32_t x[3][kIncRegs];
+#pragma unroll
+    for (int k = 0; k < 3; ++k)
+#pragma unroll
+        for (int q = 0; q < kIncRegs; ++q) x[k][q] = tri_idx[len[k] > 0 ? ob[k] + min(q, len[k] - 1) : 0];
+    int lists = 0, free_v = 0;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        if (!use[k]) continue;
+        ++free_v;
+        bool found = false;
+#pragma unroll
+        for (int q = 0; q < kIncRegs; ++q) found |= q < len[k] && x[k][q] == static_cast<int32_t>(t);
+        if (!found && len[k] > kIncRegs) found = row_has(tri_idx, ob[k] + kIncRegs, oe[k], static_cast<int32_t>(t));
+        lists += found;
+    }
+    if (lists > 0 && lists < free_v) atomicOr(&vs->err, static_cast<uint32_t>(VI_INCIDENCE));
 }
 
 __global__ __launch_bounds__(kBS) void k_validate_nodes(ValArgs a, ValStats* __restrict__ part)
@@ -353,16 +407,6 @@ __global__ __launch_bounds__(kBS) void k_validate_nodes(ValArgs a, ValStats* __r
                     const int32_t o1 = v0 == i ? v1 : (v1 == i ? v2 : v0);
                     const int32_t o2 = v0 == i ? v2 : (v1 == i ? v0 : v1);
                     if (is_free && row_ok && (!in_row(o1) || !in_row(o2))) e |= VE_MISSING;
-                    if (is_free && a.check_incidence) {
-                        // each other free vertex lists t too (offsets out of
-                        // range are reported by that vertex's own check)
-                        auto lists_t = [&](int32_t o) {
-                            if (o < 0 || o >= a.n || a.boundary[o] != 0) return true;
-                            const int32_t ob = a.tri_ptr[o], oe = a.tri_ptr[o + 1];
-                            return !(0 <= ob && ob <= oe && oe <= a.ninc) || row_has(a.tri_idx, ob, oe, t[u]);
-                        };
-                        if (!lists_t(o1) || !lists_t(o2)) e |= VI_INCIDENCE;
-                    }
                 }
             }
         }
@@ -990,9 +1034,11 @@ sl_status setup_mesh(const SetupArgs& a, const sl_options& o, DevMesh& m, int32_
     if ((r = scratch.take(&vs, 1)) || (r = scratch.take(&vpart, gb))) return r;
     SL_HIP(hipMemsetAsync(vs, 0, sizeof(ValStats), st));
     ValArgs va{a.coords, n, a.nbr_ptr, a.nbr_idx, a.tri_ptr, a.tri_idx, a.tris, a.n_tris, a.boundary,
-               a.nnz, a.ninc, o.form == SL_INPLACE_COLORED, want_tiles && o.form == SL_JACOBI,
-               o.precision == SL_F32 ? 0x1p61 : 0x1p500};
+               a.nnz, a.ninc, o.form == SL_INPLACE_COLORED, o.precision == SL_F32 ? 0x1p61 : 0x1p500};
     if (a.n_tris > 0) k_validate_tris<<<div_up(a.n_tris, kBS), kBS, 0, st>>>(a.tris, a.n_tris, n, vs);
+    if (want_tiles && o.form == SL_JACOBI && a.n_tris > 0 && a.ninc > 0)
+        k_validate_incidence<<<div_up(a.n_tris, kBS), kBS, 0, st>>>(a.tris, a.n_tris, n, a.boundary, a.tri_ptr,
+                                                                  a.tri_idx, a.ninc, vs);
     k_validate_nodes<<<gb, kBS, 0, st>>>(va, vpart);
     k_validate_fold<<<1, 1024, 0, st>>>(vpart, gb, vs);
     SL_HIP(hipGetLastError());
