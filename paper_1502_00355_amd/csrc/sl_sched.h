@@ -19,10 +19,11 @@
 //   size_t footprint(const sl_mesh_desc&);               budget units of a request (any thread)
 //   sl_status admit(Request&);                           set up, synchronously; called by setup
 //                                                        threads, several at once; on error keeps nothing
-//   sl_status launch(const std::vector<Request*>&, bool changed);
-//                                                        start one step (asynchronous); requests with
-//                                                        !joined join now and must be marked joined;
-//                                                        `changed`: the set differs from the last step
+//   sl_status launch(const std::vector<Request*>&, bool changed, int32_t sweeps);
+//                                                        start one step of `sweeps` sweeps (asynchronous);
+//                                                        requests with !joined join now and must be
+//                                                        marked joined; `changed`: the set differs from
+//                                                        the last step
 //   sl_status wait(const std::vector<Request*>&, std::vector<StepOutcome>&);
 //                                                        finish the step: one outcome per request
 //   sl_status collect(Request&, const StepOutcome&);     result and report of a finished request; runs
@@ -62,6 +63,9 @@ using Clock = std::chrono::steady_clock;
 // A queued request that does not fit the budget is passed by at most this
 // many later ones before the queue waits for it.
 constexpr int32_t kMaxBypass = 64;
+// A step of a lone request (nothing queued, nothing being set up) runs this
+// many times the configured sweeps.
+constexpr int32_t kAloneStepFactor = 4;
 
 enum class Phase { QUEUED, ADMITTING, ACTIVE, DONE };
 
@@ -341,6 +345,7 @@ private:
         for (;;) {
             // ---- 1. the set-up requests that still sweep
             std::vector<Req*> in_step;
+            bool alone = false;
             {
                 std::unique_lock<std::mutex> lk(mu_);
                 auto ready = [&] {
@@ -351,8 +356,14 @@ private:
                 if (to_collect.empty())
                     cv_loop_.wait_for(lk, std::chrono::milliseconds(20), [&] { return stop_ || ready(); });
                 if (stop_) break;
-                for (Req* q : slots_)
+                bool admitting = false;
+                for (Req* q : slots_) {
                     if (q && q->phase == Phase::ACTIVE && !q->finishing) in_step.push_back(q);
+                    if (q && q->phase == Phase::ADMITTING) admitting = true;
+                }
+                // a lone request with nothing queued or being set up runs
+                // longer steps: fewer host round trips, and no one waits to join
+                alone = in_step.size() == 1 && queue_.empty() && !admitting;
             }
             if (in_step.empty()) {
                 collect_all(to_collect);
@@ -361,7 +372,8 @@ private:
             // ---- 2. launch; collect the last step's finished requests meanwhile
             ids.clear();
             for (Req* q : in_step) ids.push_back(q->id);
-            sl_status r = ex_.launch(in_step, ids != last_ids);
+            const int32_t sweeps = cfg_.sweeps_per_step * (alone ? kAloneStepFactor : 1);
+            sl_status r = ex_.launch(in_step, ids != last_ids, sweeps);
             last_ids.swap(ids);
             collect_all(to_collect);
             // ---- 3. wait and decide

@@ -183,7 +183,7 @@ struct HipExec {
         return SL_OK;
     }
 
-    sl_status launch(const std::vector<Req*>& in_step, bool changed)
+    sl_status launch(const std::vector<Req*>& in_step, bool changed, int32_t sweeps)
     {
         bind_thread();
         sl_status r = SL_OK;
@@ -207,7 +207,7 @@ struct HipExec {
         for (Req* q : in_step) all_tiles = all_tiles && q->x.mesh.tile_nodes > 0;
         const TileLaunch L{work,       n_work, T, hcap, rcap, opts.layout, opts.accept, states, wg_per_cu, 0,
                            opts.precision, sched, all_tiles ? max_active : 0, wg_auto};
-        for (int32_t k = 0; k < sweeps_per_step && !r; ++k) {
+        for (int32_t k = 0; k < sweeps && !r; ++k) {
             if (jacobi && n_work > 0) r = launch_sweep_tiles(L, parity, nullptr, st_compute);
             for (Req* q : in_step) {
                 if (r) break;

@@ -57,6 +57,7 @@ struct Mock {
     // observations (loop thread writes, test thread reads after stop)
     std::mutex mu;
     std::vector<std::vector<uint64_t>> steps;
+    std::vector<int32_t> step_sweeps;   // sweeps of each step launched
     std::set<uint64_t> live;
     size_t live_fp = 0, max_live_fp = 0;
     int max_live = 0;
@@ -94,9 +95,10 @@ struct Mock {
         return SL_OK;
     }
 
-    sl_status launch(const std::vector<Req*>& in_step, bool)
+    sl_status launch(const std::vector<Req*>& in_step, bool, int32_t sweeps)
     {
         std::lock_guard<std::mutex> lk(mu);
+        step_sweeps.push_back(sweeps);
         std::vector<uint64_t> ids;
         for (Req* q : in_step) {
             if (!live.count(q->id)) violations.push_back("stepped a request that is not admitted");
@@ -123,7 +125,7 @@ struct Mock {
         if (idx == fail_step_at) return sl::fail(SL_EDEVICE, "mock: device fault in step");
         for (size_t k = 0; k < in_step.size(); ++k) {
             MockPayload& x = in_step[k]->x;
-            for (int32_t j = 0; j < sweeps_per_step && x.active; ++j) {
+            for (int32_t j = 0; j < step_sweeps.back() && x.active; ++j) {
                 ++x.sweeps;
                 x.active = x.sweeps < in_step[k]->iterations && !(x.converge_at >= 0 && x.sweeps >= x.converge_at);
             }
@@ -266,6 +268,32 @@ int main()
         check(st.submitted == 5 && st.completed == 5 && st.failed == 0, n, "counts");
         check(st.node_updates == 10 * (0 + 1 + 4 + 9 + 30), n, "node updates " + std::to_string(st.node_updates));
         check(st.hbm_in_use == 0 && st.active == 0 && st.queued == 0, n, "budget not returned");
+        s.stop();
+        no_violations(s, n);
+    });
+
+    run("lone_request_takes_longer_steps", [](const std::string& n) {
+        // alone, with nothing queued or being set up, a request steps
+        // kAloneStepFactor times the configured sweeps; once another is
+        // set up next to it, steps go back to the configured length
+        Server s(1000, 8, 4, 1);
+        s.ex.step_us = 2000;
+        s.start();
+        const uint64_t a = s.submit(10, 64);
+        auto da = s.wait(a);
+        check(da.st == SL_OK && da.rep.iterations_run == 64, n, "a");
+        const size_t k0 = s.ex.steps.size();
+        check(k0 == 4, n, "lone request took " + std::to_string(k0) + " steps, not 4");
+        for (size_t k = 0; k < k0; ++k)
+            check(s.ex.step_sweeps[k] == 4 * sl::sched::kAloneStepFactor, n, "short lone step");
+        const uint64_t b = s.submit(10, 400), c = s.submit(10, 8);
+        auto db = s.wait(b), dc = s.wait(c);
+        check(db.st == SL_OK && dc.st == SL_OK && db.rep.iterations_run == 400 && dc.rep.iterations_run == 8, n,
+              "b and c");
+        bool together_short = false;
+        for (size_t k = k0; k < s.ex.steps.size(); ++k)
+            if (s.ex.steps[k].size() == 2) together_short = together_short || s.ex.step_sweeps[k] == 4;
+        check(together_short, n, "no configured-length step with both requests");
         s.stop();
         no_violations(s, n);
     });
