@@ -112,12 +112,31 @@ class ServerStats(ctypes.Structure):
 _lib = None
 
 
+def _check_current():
+    """Raises if the in-tree library was built from other sources than the
+    ones beside it (a library older than its sources would test old code)."""
+    from . import build as _build
+    if not os.path.isdir(_build.CSRC):
+        return
+    try:
+        with open(_build.DIGEST) as f:
+            have = f.read().strip()
+    except OSError:
+        have = None
+    if have != _build.source_digest():
+        raise RuntimeError("libsmartlap.so was not built from the sources in csrc/ "
+                           "(rebuild: python -m paper_1502_00355_amd.build)")
+
+
 def lib():
-    """The loaded library; raises if it has not been built."""
+    """The loaded library; raises if it has not been built, or was built from
+    other sources than the package holds."""
     global _lib
     if _lib is None:
         if not os.path.exists(LIB_PATH):
             raise RuntimeError("libsmartlap.so is not built (python -m paper_1502_00355_amd.build)")
+        if os.path.abspath(LIB_PATH) == os.path.join(_HERE, "libsmartlap.so"):
+            _check_current()
         L = ctypes.CDLL(LIB_PATH)
         p, i32, d = ctypes.c_void_p, ctypes.c_int32, ctypes.c_double
         L.sl_options_default.argtypes = [ctypes.POINTER(Options)]

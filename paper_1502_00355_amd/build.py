@@ -9,6 +9,7 @@ fast-math, and with packed FP32 instructions disabled.
 from __future__ import annotations
 
 import concurrent.futures as cf
+import hashlib
 import os
 import subprocess
 import sys
@@ -17,6 +18,8 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(PKG, "csrc")
 BUILD = os.path.join(PKG, "_build")
 LIB = os.path.join(PKG, "libsmartlap.so")
+HEADER = os.path.join(os.path.dirname(PKG), "include", "smartlap.h")
+DIGEST = LIB + ".srcsha"   # digest of the sources the library was built from
 ARCH = os.environ.get("SMARTLAP_ARCH", "gfx950")
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
@@ -32,6 +35,19 @@ FLAGS = [
     "-Wall",
     "-Wno-unused-function",
 ]
+
+
+def source_digest() -> str:
+    """sha256 over the name and contents of every file under csrc/ and of the
+    public header."""
+    h = hashlib.sha256()
+    paths = [os.path.join(CSRC, f) for f in sorted(os.listdir(CSRC))] + [HEADER]
+    for p in paths:
+        if os.path.isfile(p):
+            h.update(os.path.basename(p).encode() + b"\0")
+            with open(p, "rb") as f:
+                h.update(f.read())
+    return h.hexdigest()
 
 
 def sources():
@@ -61,7 +77,10 @@ def build(verbose: bool = True) -> str:
     p = subprocess.run(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT, text=True)
     if p.returncode != 0:
         raise RuntimeError("link failed:\n" + p.stdout)
+    digest = source_digest()
     os.replace(tmp, LIB)
+    with open(DIGEST, "w") as f:
+        f.write(digest + "\n")
     if verbose:
         print("built", LIB)
     return LIB

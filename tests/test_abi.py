@@ -30,6 +30,16 @@ def test_header_symbols_are_exported(L):
         getattr(L, n)
 
 
+def test_library_built_from_other_sources_is_refused(L, monkeypatch):
+    """The binding refuses an in-tree library whose recorded source digest
+    differs from the sources beside it, so that no test runs old code."""
+    from paper_1502_00355_amd import build
+    monkeypatch.setattr(sl, "_lib", None)
+    monkeypatch.setattr(build, "source_digest", lambda: "0" * 64)
+    with pytest.raises(RuntimeError, match="not built from the sources"):
+        sl.lib()
+
+
 def test_only_the_c_abi_is_exported():
     out = subprocess.run(["nm", "-D", "--defined-only", sl.LIB_PATH], stdout=subprocess.PIPE, text=True).stdout
     exported = {ln.split()[-1] for ln in out.splitlines() if " T " in ln}
