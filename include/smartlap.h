@@ -111,9 +111,11 @@ typedef struct {
     int32_t reorder;     /* sl_reorder: node order used on the device; results do not depend on it */
     int32_t block_size;  /* node kernel work-group size: 0 = automatic, else 64/128/256 */
     int32_t kernel;      /* sl_kernel; results do not depend on it */
-    int32_t tile_nodes;      /* free nodes per tile on the tile path: 0 = automatic (the value
-                              * sl_autotune chose on this device, else 512), or 256 or 512;
-                              * results do not depend on it */
+    int32_t tile_nodes;      /* free nodes per tile on the tile path.  Form A: 0 = automatic (the
+                              * value sl_autotune chose on this device, else 512), or 256 or 512.
+                              * Form B's colour-class tiles: 0 = automatic (512 on meshes of at
+                              * least 2^20 nodes, else 256), or 128, 256 or 512.  Results do not
+                              * depend on it */
     int32_t tile_wg_per_cu;  /* tile-kernel work-groups per compute unit: 0 = automatic (the
                               * value sl_autotune chose, else as many as fit, at most 4; at
                               * most 3 on launches of fewer than 16384 tiles), or 1..8, capped
@@ -369,9 +371,10 @@ SL_API sl_status sl_build_adjacency_device(const int32_t* tris, int32_t n_tris, 
  * the automatic choice of the current device -- or the default shape (512
  * nodes, 4 work-groups per CU; block size 256) when it is within 1% of the
  * fastest -- for the rest of the process: later calls whose options
- * leave tile_nodes / tile_wg_per_cu at 0 use it.  Form B (coloured) runs on
- * the node kernel; for it the node-kernel work-group size is tuned and used
- * where block_size is 0.  Meshes are read, not written.  The caller's opts
+ * leave tile_nodes / tile_wg_per_cu at 0 use it.  For Form B (coloured) the
+ * node kernel's work-group size is tuned and used where block_size is 0 (the
+ * node kernel runs the Form B meshes that do not take colour-class tiles);
+ * colour-class tiles are not tuned.  Meshes are read, not written.  The caller's opts
  * give form, accept and layout; their tile fields are ignored.
  * out: nullable.  Thread-safe; a later call replaces the device's choice. */
 typedef struct {

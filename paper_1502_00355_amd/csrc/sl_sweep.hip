@@ -31,32 +31,38 @@ namespace {
 // 2*sqrt(3) rounded to double: q = 4*sqrt(3)*A / sum(l^2) = (2*sqrt(3)*cr) / S.
 constexpr double kTwoSqrt3 = 0x1.bb67ae8584caap+1;
 
-// Triangle quality in stored vertex order (p0, p1, p2); every operation is a
-// single rounded double operation, no contraction.
-__device__ __forceinline__ double tri_quality(double x0, double y0, double x1, double y1, double x2, double y2)
+// Old and new quality of the triangle whose stored order puts the node at
+// position p, the vertex `a` at p+1 and `b` at p+2 (mod 3): the node at o,
+// then at its candidate c.  With u = a - node, v = b - node and w = b - a,
+// the stored order's edge vectors p1 - p0, p2 - p0, p2 - p1 are (u, v, w)
+// for p = 0, (-v, -w, u) for p = 1 and (w, -u, -v) for p = 2.  A negation
+// is exact and fl(y - x) = -fl(x - y), so the cross product is
+// P.x Q.y - Q.x P.y with (P, Q) = (u, v), (v, w) or (u, w), and the sum of
+// squared lengths (|p1-p0|^2 + |p2-p1|^2) + |p2-p0|^2 is (Lu + Lw) + Lv,
+// (Lv + Lu) + Lw or (Lw + Lv) + Lu: the same roundings as evaluating the
+// stored order directly, every operation one rounded double operation
+// without contraction.  w and its length are shared by the
+// two evaluations, and selects pick operands instead of rebuilding the
+// order (the lanes of a wave hold different p: a branch per p made a wave
+// run all three orders one after the other).
+__device__ __forceinline__ void fan_qualities(int p, const double2 o, const double2 c, const double2 a,
+                                              const double2 b, double& qold, double& qnew)
 {
-    const double ax = x1 - x0, ay = y1 - y0;
-    const double bx = x2 - x0, by = y2 - y0;
-    const double cx = x2 - x1, cy = y2 - y1;
-    const double cr = ax * by - bx * ay;
-    const double S = ((ax * ax + ay * ay) + (cx * cx + cy * cy)) + (bx * bx + by * by);
-    const double q = (kTwoSqrt3 * cr) / S;
-    return S == 0.0 ? 0.0 : q;
-}
-
-// Quality of the triangle whose stored order puts the node at position p,
-// the vertex `a` at p+1 and `b` at p+2 (mod 3), with the node at (ox, oy).
-// The stored order is rebuilt with selects, not branches: the lanes of a
-// wave take different nodes, whose positions p differ, and a branch per p
-// made a wave evaluate all three orders one after the other.
-__device__ __forceinline__ double fan_quality(int p, double ox, double oy, const double2 a, const double2 b)
-{
-    // slot k of the stored order holds the node when p == k, else q_k
-    const double2 q0 = p == 1 ? b : a, q1 = p == 0 ? a : b, q2 = p == 0 ? b : a;
-    const double x0 = p == 0 ? ox : q0.x, y0 = p == 0 ? oy : q0.y;
-    const double x1 = p == 1 ? ox : q1.x, y1 = p == 1 ? oy : q1.y;
-    const double x2 = p == 2 ? ox : q2.x, y2 = p == 2 ? oy : q2.y;
-    return tri_quality(x0, y0, x1, y1, x2, y2);
+    const double wx = b.x - a.x, wy = b.y - a.y;
+    const double Lw = wx * wx + wy * wy;
+    auto one = [&](double px, double py) {
+        const double ux = a.x - px, uy = a.y - py, vx = b.x - px, vy = b.y - py;
+        const double Lu = ux * ux + uy * uy, Lv = vx * vx + vy * vy;
+        const double Px = p == 1 ? vx : ux, Py = p == 1 ? vy : uy;
+        const double Qx = p == 0 ? vx : wx, Qy = p == 0 ? vy : wy;
+        const double X = p == 2 ? Lv : Lu, Y = p == 1 ? Lv : Lw, Z = p == 0 ? Lv : (p == 1 ? Lw : Lu);
+        const double cr = Px * Qy - Qx * Py;
+        const double S = (X + Y) + Z;
+        const double q = (kTwoSqrt3 * cr) / S;
+        return S == 0.0 ? 0.0 : q;
+    };
+    qold = one(o.x, o.y);
+    qnew = one(c.x, c.y);
 }
 
 template <bool SOA>
@@ -167,9 +173,9 @@ __global__ __launch_bounds__(BLOCK) void k_sweep(SweepArgs a)
                 const int p = static_cast<int>(e[u] & 3u);
                 const double2 va = nb[(e[u] >> 2) & 127u][tid];
                 const double2 vb = nb[(e[u] >> 9) & 127u][tid];
-                const double v = fan_quality(p, o.x, o.y, va, vb);
+                double v, w;
+                fan_qualities(p, o, make_double2(cx, cy), va, vb, v, w);
                 if (v < qo) qo = v;
-                const double w = fan_quality(p, cx, cy, va, vb);
                 if (w < qn) qn = w;
             }
         }
@@ -325,9 +331,9 @@ __device__ __forceinline__ bool resident_node(int i, const double2* cur, double2
         for (int u = 0; u < kResFan; ++u) {
             if (f0 + u >= f1) break;
             const int p = static_cast<int>(e[u] & 3u);
-            const double v = fan_quality(p, o.x, o.y, va[u], vb[u]);
+            double v, w;
+            fan_qualities(p, o, make_double2(cx, cy), va[u], vb[u], v, w);
             if (v < qo) qo = v;
-            const double w = fan_quality(p, cx, cy, va[u], vb[u]);
             if (w < qn) qn = w;
         }
     }
@@ -682,9 +688,9 @@ __global__ __launch_bounds__(T) void k_sweep_class(ClassSweepArgs a)
                 for (int u = 0; u < kResFan; ++u) {
                     if (g0 + u >= f1) break;
                     const int pp = static_cast<int>(e[u] & 3u);
-                    const double v = fan_quality(pp, o.x, o.y, va[u], vb[u]);
+                    double v, w;
+                    fan_qualities(pp, o, make_double2(cx, cy), va[u], vb[u], v, w);
                     if (v < qo) qo = v;
-                    const double w = fan_quality(pp, cx, cy, va[u], vb[u]);
                     if (w < qn) qn = w;
                 }
             }
