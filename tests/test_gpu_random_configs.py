@@ -1,0 +1,113 @@
+"""GPU parity over a seeded sample of the option space.
+
+Each case draws a small mesh (a jittered grid with random or Union-Jack
+diagonals, an annulus, a Delaunay triangulation of random points, or a
+randomly relabelled copy of one of these, with a share of its free nodes
+sometimes marked fixed) and a set of options (form, accept rule, layout,
+reorder, kernel, precision, tile shape, node-kernel block size, sweeps,
+tolerance), runs it through the C ABI and compares sweep by sweep with the
+oracle: accept flags, accepted counts, displacement maxima and coordinates
+bit for bit.  The draws are fixed by the case number, so a failure names a
+reproducible case.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import meshgen
+import oracle
+import paper_1502_00355_amd as sl
+
+pytestmark = pytest.mark.gpu
+
+N_CASES = 200
+
+
+@pytest.fixture(scope="module", autouse=True)
+def gpu():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    torch.cuda.set_device(0)
+    sl.lib()
+    yield
+
+
+def draw_mesh(rng):
+    kind = rng.choice(["grid", "unionjack", "annulus", "delaunay"])
+    seed = int(rng.integers(1 << 20))
+    if kind == "grid":
+        m = meshgen.make_grid(int(rng.integers(3, 90)), "random", float(rng.uniform(0.0, 0.45)), seed)
+    elif kind == "unionjack":
+        m = meshgen.make_grid(int(rng.integers(3, 90)), "unionjack", float(rng.uniform(0.0, 0.45)), seed)
+    elif kind == "annulus":
+        m = meshgen.make_annulus(int(rng.integers(3, 40)), int(rng.integers(6, 120)), seed=seed)
+    else:
+        m = meshgen.make_delaunay(int(rng.integers(20, 6000)), seed)
+    if rng.uniform() < 0.3:
+        m = meshgen.permute_mesh(m, seed + 1)
+    if rng.uniform() < 0.2:
+        # some interior nodes held fixed as well
+        free = np.flatnonzero(m.boundary == 0)
+        pick = rng.choice(free, size=len(free) // 5, replace=False) if len(free) else free
+        m.boundary = m.boundary.copy()
+        m.boundary[pick] = 1
+    return m, kind
+
+
+def draw_options(rng, n_nodes):
+    form = "colored" if rng.uniform() < 0.35 else "jacobi"
+    o = {"form": form,
+         "accept": "gt" if rng.uniform() < 0.3 else "ge",
+         "layout": "soa" if rng.uniform() < 0.4 else "aos",
+         "reorder": "none" if rng.uniform() < 0.3 else "hilbert"}
+    kernels = ["auto", "auto", "node", "tile"] + (["resident"] if n_nodes <= 1500 else [])
+    o["kernel"] = str(rng.choice(kernels))
+    if o["kernel"] == "node":
+        o["block_size"] = int(rng.choice([0, 64, 128, 256]))
+    if o["kernel"] in ("auto", "tile"):
+        sizes = [0, 256, 512] + ([128] if form == "colored" else [])
+        o["tile_nodes"] = int(rng.choice(sizes))
+        o["tile_wg_per_cu"] = int(rng.integers(0, 9))
+    if form == "jacobi" and o["kernel"] in ("auto", "tile") and rng.uniform() < 0.25:
+        o["precision"] = "f32"
+    return o
+
+
+@pytest.mark.parametrize("case", range(N_CASES))
+def test_random_config(case):
+    import torch
+    rng = np.random.Generator(np.random.PCG64(7_000_000 + case))
+    m, kind = draw_mesh(rng)
+    opts = draw_options(rng, m.n_nodes)
+    iters = int(rng.integers(1, 25))
+    tol = float(10.0 ** rng.uniform(-9, -3)) if rng.uniform() < 0.3 else 0.0
+    prec = opts.get("precision", "f64")
+    print("case %d: %s %s, %d nodes, %d sweeps, tol %g, %s" % (case, kind, m.name, m.n_nodes, iters, tol, opts),
+          flush=True)
+    sys.stdout.flush()
+    dev = sl.to_device(m, "cuda:0")
+    nbytes = (m.n_nodes + 7) // 8
+    flags = torch.zeros(iters * nbytes, dtype=torch.uint8, device="cuda:0")
+    try:
+        rep = sl.smooth_mesh_device(*dev, iterations=iters, tol=tol, flags=flags, **opts)
+    except sl.SmartlapError as e:
+        # an explicit tile or resident kernel, and single precision, need a
+        # mesh that path takes; they refuse others with SL_EINVAL
+        assert e.status == sl.SL_EINVAL and (opts["kernel"] in ("tile", "resident") or prec == "f32"), str(e)
+        return
+    torch.cuda.synchronize()
+    X = dev[0].cpu().numpy()
+    F = sl.unpack_flags(flags.cpu().numpy().reshape(iters, nbytes), m.n_nodes)
+    ref = oracle.smooth(m, iters, tol=tol, accept_gt=(opts["accept"] == "gt"), threads=oracle.max_threads(),
+                        form=opts["form"], precision=prec)
+    k = ref.iterations_run
+    assert rep.iterations_run == k
+    assert (F[:k] == (ref.flags == 1)).all(), "flags differ in sweeps %s" % np.flatnonzero(
+        (F[:k] != (ref.flags == 1)).any(axis=1))
+    assert (F[k:] == 0).all()
+    assert np.array_equal(X, ref.coords), float(np.abs(X - ref.coords).max())
+    if k:
+        assert rep.accepted_last == ref.accepted[-1]
+        assert rep.accepted_total == int(ref.accepted.sum())
+        assert rep.max_disp_sq_last == ref.disp[-1]
