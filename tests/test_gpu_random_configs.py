@@ -111,3 +111,37 @@ def test_random_config(case):
         assert rep.accepted_last == ref.accepted[-1]
         assert rep.accepted_total == int(ref.accepted.sum())
         assert rep.max_disp_sq_last == ref.disp[-1]
+
+
+N_BATCHES = 24
+
+
+@pytest.mark.parametrize("case", range(N_BATCHES))
+def test_random_batch(case):
+    """Batches of 1-24 random meshes under one random option set: every
+    mesh's result, sweep count and accepted counts equal the oracle's."""
+    rng = np.random.Generator(np.random.PCG64(8_000_000 + case))
+    meshes = [draw_mesh(rng)[0] for _ in range(int(rng.integers(1, 25)))]
+    opts = draw_options(rng, max(m.n_nodes for m in meshes))
+    opts.pop("tile_nodes", None)          # a batch takes the automatic tile shape
+    opts.pop("tile_wg_per_cu", None)
+    if opts["kernel"] == "tile":
+        opts["kernel"] = "auto"
+    iters = int(rng.integers(1, 25))
+    tol = float(10.0 ** rng.uniform(-9, -3)) if rng.uniform() < 0.3 else 0.0
+    prec = opts.get("precision", "f64")
+    print("batch %d: %d meshes (%d nodes), %d sweeps, tol %g, %s" %
+          (case, len(meshes), sum(m.n_nodes for m in meshes), iters, tol, opts), flush=True)
+    try:
+        outs, reps, br = sl.batch_smooth(meshes, iters, tol=tol, **opts)
+    except sl.SmartlapError as e:
+        assert e.status == sl.SL_EINVAL and (opts["kernel"] == "resident" or prec == "f32"), str(e)
+        return
+    for m, X, rep in zip(meshes, outs, reps):
+        ref = oracle.smooth(m, iters, tol=tol, accept_gt=(opts["accept"] == "gt"), threads=oracle.max_threads(),
+                            form=opts["form"], precision=prec)
+        assert rep.iterations_run == ref.iterations_run, m.name
+        assert np.array_equal(X, ref.coords), (m.name, float(np.abs(X - ref.coords).max()))
+        if ref.iterations_run:
+            assert rep.accepted_last == ref.accepted[-1], m.name
+            assert rep.accepted_total == int(ref.accepted.sum()), m.name
