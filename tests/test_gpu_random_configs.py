@@ -145,3 +145,56 @@ def test_random_batch(case):
         if ref.iterations_run:
             assert rep.accepted_last == ref.accepted[-1], m.name
             assert rep.accepted_total == int(ref.accepted.sum()), m.name
+
+
+N_HANDLE_CASES = 24
+
+
+@pytest.mark.parametrize("case", range(N_HANDLE_CASES))
+def test_random_handles(case):
+    """1-6 mesh handles under one drawn option set: smoothed alone, then
+    together, then alone again, each call with its own sweep count and
+    tolerance; every handle ends where the oracle does after the same three
+    calls, with the same accepted total."""
+    import torch
+    rng = np.random.Generator(np.random.PCG64(9_000_000 + case))
+    meshes = [draw_mesh(rng)[0] for _ in range(int(rng.integers(1, 7)))]
+    opts = draw_options(rng, 10 ** 9)                 # no resident kernel: handles do not run it
+    opts.pop("tile_wg_per_cu", None)
+    calls = [(int(rng.integers(0, 16)), float(10.0 ** rng.uniform(-8, -3)) if rng.uniform() < 0.3 else 0.0)
+             for _ in range(3)]
+    on_device = bool(rng.uniform() < 0.5)
+    prec = opts.get("precision", "f64")
+    print("handles %d: %d meshes, calls %s, %s, from device %s" % (case, len(meshes), calls, opts, on_device),
+          flush=True)
+    hs = []
+    try:
+        for m in meshes:
+            hs.append(sl.Mesh.from_device(sl.to_device(m, "cuda:0"), **opts) if on_device else sl.Mesh(m, **opts))
+    except sl.SmartlapError as e:
+        assert e.status == sl.SL_EINVAL and (opts["kernel"] == "tile" or prec == "f32"), str(e)
+        for h in hs:
+            h.close()
+        return
+    try:
+        (k1, t1), (k2, t2), (k3, t3) = calls
+        for h in hs:
+            h.smooth_async(k1, t1)
+        sl.smooth_batch_async(hs, max(k2, 1), t2)
+        for h in hs:
+            h.smooth_async(k3, t3)
+        torch.cuda.synchronize()
+        for m, h in zip(meshes, hs):
+            X, rep = h.download()
+            cur, acc = m, 0
+            for k, t in ((k1, t1), (max(k2, 1), t2), (k3, t3)):
+                ref = oracle.smooth(cur, k, tol=t, accept_gt=(opts["accept"] == "gt"),
+                                    threads=oracle.max_threads(), form=opts["form"], precision=prec)
+                acc += int(ref.accepted.sum())
+                cur = cur.copy()
+                cur.coords = ref.coords
+            assert np.array_equal(X, cur.coords), (m.name, float(np.abs(X - cur.coords).max()))
+            assert rep.accepted_total == acc, m.name
+    finally:
+        for h in hs:
+            h.close()
