@@ -198,3 +198,44 @@ def test_random_handles(case):
     finally:
         for h in hs:
             h.close()
+
+
+N_SERVER_CASES = 8
+
+
+@pytest.mark.parametrize("case", range(N_SERVER_CASES))
+def test_random_server(case):
+    """A server with a drawn configuration (HBM budget, active-request cap,
+    sweeps per step, setup threads) and option set takes 8-40 random
+    requests submitted at once, each with its own sweep count and tolerance;
+    every result equals the oracle's for that request alone."""
+    rng = np.random.Generator(np.random.PCG64(10_000_000 + case))
+    opts = draw_options(rng, 10 ** 9)
+    opts.pop("tile_nodes", None)
+    opts.pop("tile_wg_per_cu", None)
+    if opts["kernel"] == "tile":
+        opts["kernel"] = "auto"
+    cfg = {"hbm_budget_bytes": int(rng.choice([0, 64 << 20, 256 << 20])),
+           "max_active": int(rng.choice([0, 1, 3, 16])),
+           "sweeps_per_step": int(rng.choice([0, 1, 3, 8])),
+           "setup_threads": int(rng.choice([0, 1, 4]))}
+    reqs = []
+    for _ in range(int(rng.integers(8, 41))):
+        m = draw_mesh(rng)[0]
+        reqs.append((m, int(rng.integers(0, 30)), float(10.0 ** rng.uniform(-8, -3)) if rng.uniform() < 0.4 else 0.0))
+    prec = opts.get("precision", "f64")
+    print("server %d: %s, %s, %d requests" % (case, cfg, opts, len(reqs)), flush=True)
+    with sl.Server(**cfg, **opts) as srv:
+        ids = [srv.submit(m, k, tol=t) for m, k, t in reqs]
+        for (m, k, t), rid in zip(reqs, ids):
+            r = srv.wait(rid, timeout=100.0)
+            if r.status != sl.SL_OK:
+                # single precision needs a mesh the tile path takes
+                assert r.status == sl.SL_EINVAL and prec == "f32", r.message
+                continue
+            ref = oracle.smooth(m, k, tol=t, accept_gt=(opts["accept"] == "gt"), threads=oracle.max_threads(),
+                                form=opts["form"], precision=prec)
+            assert r.report.iterations_run == ref.iterations_run, m.name
+            assert np.array_equal(r.coords, ref.coords), (m.name, float(np.abs(r.coords - ref.coords).max()))
+            if ref.iterations_run:
+                assert r.report.accepted_total == int(ref.accepted.sum()), m.name
