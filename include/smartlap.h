@@ -149,7 +149,8 @@ SL_API void sl_options_default(sl_options* opts);
 /*
  * smooth_mesh -- iterated Smart Laplacian on one mesh, host arrays.
  *
- * coords    in/out, n_nodes x 2 doubles, (x, y) interleaved.  Written only on SL_OK.
+ * coords    in/out, n_nodes x 2 doubles, (x, y) interleaved.  Written only on SL_OK
+ *           (a device failure during the final copy may leave it partly written).
  * n_nodes   >= 1.
  * nbr_ptr   n_nodes+1 offsets into nbr_idx (CSR node -> neighbour), nbr_ptr[0] = 0.
  * nbr_idx   nbr_ptr[n_nodes] neighbour ids; the order within a row is the
@@ -308,7 +309,8 @@ SL_API sl_status sl_mesh_smooth_batch_async(sl_mesh* const* meshes, int32_t n_me
  * caller's node order) after the handle's queued work; report (nullable) is
  * filled with the handle's totals: sweeps run since creation, accepted
  * counts, the setup time and the device time of the last single-handle
- * smooth call.  Synchronous. */
+ * smooth call.  Synchronous.  On an error coords is not written, except
+ * that a device failure during the copy may leave it partly written. */
 SL_API sl_status sl_mesh_download(sl_mesh* mesh, double* coords, sl_report* report);
 
 /* The same into device memory (16-byte aligned), queued on `stream` after

@@ -418,20 +418,19 @@ sl_status sl_mesh_download(sl_mesh* h, double* coords, sl_report* report)
     if (!coords) return fail(SL_EINVAL, "null coords");
     if ((r = h->after_last(h->own))) return r;
     const size_t n = static_cast<size_t>(h->m.n);
-    std::vector<double> host(2 * n);
     unsigned char* buf = nullptr;
     if ((r = block_take(&buf, 2 * n * sizeof(double), h->own))) return r;
     double* d = reinterpret_cast<double*>(buf);
+    MeshState ms{};
     do {
         if ((r = unpermute_coords(h->m, h->o.form == SL_JACOBI ? h->cur : 0, d, h->own))) break;
-        if ((r = copy_to_host(host.data(), d, 2 * n * sizeof(double), h->own))) break;
-        MeshState ms{};
         if ((r = read_state(h, &ms, h->own))) break;
-        if (report) fill_report(h, ms, report);
+        // straight into the caller's array, last
+        if ((r = copy_to_host(coords, d, 2 * n * sizeof(double), h->own))) break;
     } while (false);
     block_give(buf, h->own);
     if (r) return r;
-    std::memcpy(coords, host.data(), 2 * n * sizeof(double));
+    if (report) fill_report(h, ms, report);
     return h->mark(h->own);
 }
 

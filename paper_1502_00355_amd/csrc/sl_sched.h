@@ -26,7 +26,8 @@
 //                                                        the last step
 //   sl_status wait(const std::vector<Request*>&, std::vector<StepOutcome>&);
 //                                                        finish the step: one outcome per request
-//   sl_status collect(Request&, const StepOutcome&);     result and report of a finished request; runs
+//   sl_status collect(Request&, const StepOutcome&);     result and report of a finished request, into
+//                                                        its `result` (already n_nodes x 2 long); runs
 //                                                        while the next step may be in flight (the
 //                                                        request is in no step any more)
 //   void release(Request&);                              free its device state (any thread)
@@ -93,7 +94,7 @@ struct Request {
     bool joined = false;        // stepped by the executor since admission
     bool finishing = false;     // finished its sweeps; its result is being collected
     StepOutcome outcome{};      // of its last step
-    std::vector<double> result; // n x 2, filled when done
+    std::vector<double> result; // n x 2, filled when done (sized by the core before collect)
     sl_report report{};
     sl_request_times times{};
     Payload x;
@@ -175,6 +176,7 @@ public:
         if (coords_out && !q->result.empty())
             std::memcpy(coords_out, q->result.data(), q->result.size() * sizeof(double));
         if (report) *report = q->report;
+        give_result(std::move(q->result));
         return SL_OK;
     }
 
@@ -326,6 +328,7 @@ private:
     void collect_all(std::vector<Req*>& done)
     {
         for (Req* q : done) {
+            q->result = take_result(2 * static_cast<size_t>(std::max(q->desc.n_nodes, 0)));
             const sl_status cs = ex_.collect(*q, q->outcome);
             const std::string msg = cs ? std::string(sl_last_error()) : std::string();
             std::lock_guard<std::mutex> lk(mu_);
@@ -427,6 +430,46 @@ private:
             release(q);
             finish(q, SL_ECANCELED, "server stopped");
         }
+    }
+
+    // Result buffers of polled requests, kept for later results (at most
+    // kResultPoolBytes): a fresh buffer costs its zero fill and the first
+    // touch of every page again (about 10 ms for a mesh of 4M nodes), a
+    // reused one neither.
+    static constexpr size_t kResultPoolBytes = size_t(1) << 30;
+    std::mutex pool_mu_;
+    std::vector<std::vector<double>> pool_;
+    size_t pool_bytes_ = 0;
+
+    // A buffer of n doubles: the smallest pooled one that holds n, else a new one.
+    std::vector<double> take_result(size_t n)
+    {
+        std::vector<double> v;
+        {
+            std::lock_guard<std::mutex> lk(pool_mu_);
+            size_t best = pool_.size();
+            for (size_t k = 0; k < pool_.size(); ++k)
+                if (pool_[k].capacity() >= n && (best == pool_.size() || pool_[k].capacity() < pool_[best].capacity()))
+                    best = k;
+            if (best < pool_.size()) {
+                v = std::move(pool_[best]);
+                pool_[best] = std::move(pool_.back());
+                pool_.pop_back();
+                pool_bytes_ -= v.capacity() * sizeof(double);
+            }
+        }
+        v.resize(n);
+        return v;
+    }
+
+    void give_result(std::vector<double>&& v)
+    {
+        const size_t b = v.capacity() * sizeof(double);
+        if (b == 0) return;
+        std::lock_guard<std::mutex> lk(pool_mu_);
+        if (pool_bytes_ + b > kResultPoolBytes) return;   // dropped (freed by the caller's scope)
+        pool_bytes_ += b;
+        pool_.push_back(std::move(v));
     }
 
     sl_server_config cfg_;

@@ -272,6 +272,24 @@ int main()
         no_violations(s, n);
     });
 
+    run("result_buffers_reused_across_sizes", [](const std::string& n) {
+        // polled results go back to the core's pool and serve later, smaller
+        // or larger, requests: each result must be its own, whole
+        Server s(1000, 8);
+        s.start();
+        const int32_t nodes[] = {50, 10, 200, 30, 200, 1, 120};
+        for (int32_t nn : nodes) {
+            const uint64_t id = s.submit(nn, 3);
+            auto d = s.wait(id);
+            check(d.st == SL_OK, n, "status " + std::to_string(d.st));
+            bool whole = d.out.size() == 2 * static_cast<size_t>(nn);
+            for (double v : d.out) whole = whole && v == static_cast<double>(id);
+            check(whole, n, "result of " + std::to_string(nn) + " nodes not its own");
+        }
+        s.stop();
+        no_violations(s, n);
+    });
+
     run("lone_request_takes_longer_steps", [](const std::string& n) {
         // alone, with nothing queued or being set up, a request steps
         // kAloneStepFactor times the configured sweeps; once another is

@@ -34,4 +34,4 @@ def test_scheduler_with_mock_executor(tmp_path, compiler, sanitize):
     print(r.stdout)
     assert r.returncode == 0, r.stdout
     assert "0 failure(s)" in r.stdout
-    assert r.stdout.count("\nok ") + r.stdout.startswith("ok ") == 16
+    assert r.stdout.count("\nok ") + r.stdout.startswith("ok ") == 17
