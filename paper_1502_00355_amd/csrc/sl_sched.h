@@ -433,10 +433,11 @@ private:
     }
 
     // Result buffers of polled requests, kept for later results (at most
-    // kResultPoolBytes): a fresh buffer costs its zero fill and the first
-    // touch of every page again (about 10 ms for a mesh of 4M nodes), a
-    // reused one neither.
+    // kResultPoolBytes in kResultPoolCount buffers): a fresh buffer costs its
+    // zero fill and the first touch of every page again (about 10 ms for a
+    // mesh of 4M nodes), a reused one neither.
     static constexpr size_t kResultPoolBytes = size_t(1) << 30;
+    static constexpr size_t kResultPoolCount = 256;
     std::mutex pool_mu_;
     std::vector<std::vector<double>> pool_;
     size_t pool_bytes_ = 0;
@@ -453,7 +454,7 @@ private:
                     best = k;
             if (best < pool_.size()) {
                 v = std::move(pool_[best]);
-                pool_[best] = std::move(pool_.back());
+                if (best + 1 != pool_.size()) pool_[best] = std::move(pool_.back());
                 pool_.pop_back();
                 pool_bytes_ -= v.capacity() * sizeof(double);
             }
@@ -467,7 +468,8 @@ private:
         const size_t b = v.capacity() * sizeof(double);
         if (b == 0) return;
         std::lock_guard<std::mutex> lk(pool_mu_);
-        if (pool_bytes_ + b > kResultPoolBytes) return;   // dropped (freed by the caller's scope)
+        if (pool_bytes_ + b > kResultPoolBytes || pool_.size() >= kResultPoolCount)
+            return;   // not kept: freed with the request
         pool_bytes_ += b;
         pool_.push_back(std::move(v));
     }
