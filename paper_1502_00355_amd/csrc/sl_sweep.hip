@@ -65,6 +65,35 @@ __device__ __forceinline__ void fan_qualities(int p, const double2 o, const doub
     qnew = one(c.x, c.y);
 }
 
+// The same for a stored position P known at compile time (the colour-class
+// tiles list each node's fan entries grouped by position): no selects.
+template <int P>
+__device__ __forceinline__ void fan_qualities_p(const double2 o, const double2 c, const double2 a, const double2 b,
+                                                double& qold, double& qnew)
+{
+    const double wx = b.x - a.x, wy = b.y - a.y;
+    const double Lw = wx * wx + wy * wy;
+    auto one = [&](double px, double py) {
+        const double ux = a.x - px, uy = a.y - py, vx = b.x - px, vy = b.y - py;
+        const double Lu = ux * ux + uy * uy, Lv = vx * vx + vy * vy;
+        double cr, S;
+        if (P == 0) {
+            cr = ux * vy - vx * uy;
+            S = (Lu + Lw) + Lv;
+        } else if (P == 1) {
+            cr = vx * wy - wx * vy;
+            S = (Lu + Lv) + Lw;
+        } else {
+            cr = ux * wy - wx * uy;
+            S = (Lv + Lw) + Lu;
+        }
+        const double q = (kTwoSqrt3 * cr) / S;
+        return S == 0.0 ? 0.0 : q;
+    };
+    qold = one(o.x, o.y);
+    qnew = one(c.x, c.y);
+}
+
 template <bool SOA>
 __device__ __forceinline__ double2 ld(const double* X, int64_t n, int64_t i)
 {
@@ -573,6 +602,43 @@ __device__ __forceinline__ void fold_state(MeshState* ms, double d2, unsigned lo
 // when the mesh changes and at the end: one atomic pair per group and mesh
 // (with a group per tile, tens of thousands of atomics on the same two
 // words per launch queued behind each other).
+// Old and new quality over the fan entries [g_begin, g_end) of one node,
+// all with stored position P, folded into the running minima.  Entries are
+// read a group at a time with clamped indices so that their dependent LDS
+// loads overlap; minima are exact, so the order of the entries does not
+// matter.
+template <int P>
+__device__ __forceinline__ void class_fan_range(int g_begin, int g_end, const uint16_t* fans, const uint16_t* rows,
+                                                int r0, const double2* Xl, const double2 o, const double2 c,
+                                                double& qo, double& qn)
+{
+    for (int g0 = g_begin; g0 < g_end; g0 += kResFan) {
+        uint32_t e[kResFan];
+#pragma unroll
+        for (int u = 0; u < kResFan; ++u) e[u] = fans[min(g0 + u, g_end - 1)];
+        int la[kResFan], lb[kResFan];
+#pragma unroll
+        for (int u = 0; u < kResFan; ++u) {
+            la[u] = rows[r0 + ((e[u] >> 2) & 127u)];
+            lb[u] = rows[r0 + ((e[u] >> 9) & 127u)];
+        }
+        double2 va[kResFan], vb[kResFan];
+#pragma unroll
+        for (int u = 0; u < kResFan; ++u) {
+            va[u] = Xl[la[u]];
+            vb[u] = Xl[lb[u]];
+        }
+#pragma unroll
+        for (int u = 0; u < kResFan; ++u) {
+            if (g0 + u >= g_end) break;
+            double v, w;
+            fan_qualities_p<P>(o, c, va[u], vb[u], v, w);
+            if (v < qo) qo = v;
+            if (w < qn) qn = w;
+        }
+    }
+}
+
 template <int T, bool SOA, bool GT>
 __global__ __launch_bounds__(T) void k_sweep_class(ClassSweepArgs a)
 {
@@ -606,6 +672,7 @@ __global__ __launch_bounds__(T) void k_sweep_class(ClassSweepArgs a)
         const int nown = d.nown;
         const int ic = min(tid, nown - 1);   // a work-item past the tile repeats the last node's loads
         const uint16_t* fr = d.rr + ((2 * T + 2 + 15) & ~15) / 2;   // fan starts follow the row starts
+        const uint32_t* pc = reinterpret_cast<const uint32_t*>(fr + ((2 * T + 2 + 15) & ~15) / 2);   // then the splits
         // every global load of the tile, then the LDS stores.  The loads
         // are unconditional, with indices clamped into the tile's lists
         // (a work-item past a list's end re-loads its last entry and
@@ -614,6 +681,9 @@ __global__ __launch_bounds__(T) void k_sweep_class(ClassSweepArgs a)
         // fan words at most 4 T each (16 entries per node on average).
         const int hc = d.halo_cnt, row_words = d.row_words, fan_words = (d.tri_cnt + 3) >> 2;
         const int r0 = d.rr[ic], r1 = d.rr[ic + 1], f0 = fr[ic], f1 = fr[ic + 1];
+        // the node's fan entries come grouped by stored position: p = 0 in
+        // [f0, f0 + lo16), p = 1 up to f0 + hi16, p = 2 up to f1
+        const uint32_t pcv = pc[ic];
         const double2 o = ld<SOA>(X, d.n, d.own_start + ic);
         int32_t hid[kClassHalo];
 #pragma unroll
@@ -668,32 +738,11 @@ __global__ __launch_bounds__(T) void k_sweep_class(ClassSweepArgs a)
                 cy = sy / dn;
             }
             double qo = INFINITY, qn = INFINITY;
-            for (int g0 = f0; g0 < f1; g0 += kResFan) {
-                uint32_t e[kResFan];
-#pragma unroll
-                for (int u = 0; u < kResFan; ++u) e[u] = fans[min(g0 + u, f1 - 1)];
-                int la[kResFan], lb[kResFan];
-#pragma unroll
-                for (int u = 0; u < kResFan; ++u) {
-                    la[u] = rows[r0 + ((e[u] >> 2) & 127u)];
-                    lb[u] = rows[r0 + ((e[u] >> 9) & 127u)];
-                }
-                double2 va[kResFan], vb[kResFan];
-#pragma unroll
-                for (int u = 0; u < kResFan; ++u) {
-                    va[u] = Xl[la[u]];
-                    vb[u] = Xl[lb[u]];
-                }
-#pragma unroll
-                for (int u = 0; u < kResFan; ++u) {
-                    if (g0 + u >= f1) break;
-                    const int pp = static_cast<int>(e[u] & 3u);
-                    double v, w;
-                    fan_qualities(pp, o, make_double2(cx, cy), va[u], vb[u], v, w);
-                    if (v < qo) qo = v;
-                    if (w < qn) qn = w;
-                }
-            }
+            const double2 cc = make_double2(cx, cy);
+            const int b1 = f0 + static_cast<int>(pcv & 0xFFFFu), b2 = f0 + static_cast<int>(pcv >> 16);
+            class_fan_range<0>(f0, b1, fans, rows, r0, Xl, o, cc, qo, qn);
+            class_fan_range<1>(b1, b2, fans, rows, r0, Xl, o, cc, qo, qn);
+            class_fan_range<2>(b2, f1, fans, rows, r0, Xl, o, cc, qo, qn);
             accepted = GT ? (qn > qo) : (qn >= qo);
             const double nx = accepted ? cx : o.x, ny = accepted ? cy : o.y;
             st<SOA>(X, d.n, d.own_start + tid, nx, ny);

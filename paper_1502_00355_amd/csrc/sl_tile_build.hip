@@ -136,14 +136,17 @@ __host__ __device__ __forceinline__ int64_t tile_record(int32_t row_start, int32
 __host__ __device__ __forceinline__ int64_t halo_at(int T) { return align16(2 * static_cast<int64_t>(T) + 2); }
 
 // A colour-class tile's record holds T + 1 u16 row starts, T + 1 u16 fan
-// starts (node i's fan entries are start[i] .. start[i+1]), room for len
-// halo ids, the rows (len rounded up to 4 u16) and flen u16 fan entries,
-// each part 16-byte aligned: at most 4T + 6 len + 2 flen + 100 bytes.
+// starts (node i's fan entries are start[i] .. start[i+1]), T u32 splits of
+// each fan by stored position (low half: entries with p = 0, high half:
+// those with p <= 1), room for len halo ids, the rows (len rounded up to 4
+// u16) and flen u16 fan entries, each part 16-byte aligned: at most 8T +
+// 6 len + 2 flen + 100 bytes.
 __host__ __device__ __forceinline__ int64_t class_record(int32_t row_start, int32_t fan_start, int32_t tile, int T)
 {
-    return static_cast<int64_t>(tile) * (4 * T + 128) +
+    return static_cast<int64_t>(tile) * (8 * T + 128) +
            align16(6 * static_cast<int64_t>(row_start) + 2 * static_cast<int64_t>(fan_start));
 }
+__host__ __device__ __forceinline__ int64_t class_halo_at(int T) { return 2 * halo_at(T) + align16(4 * static_cast<int64_t>(T)); }
 
 // One work-group per tile, in one pass: every output of tile k goes to a
 // place fixed by the row and incidence offsets of its first node, so no
@@ -225,7 +228,7 @@ __global__ __launch_bounds__(kBuildBS) void k_tile_build(TileBuildArgs a)
     // rewritten below
     unsigned char* rec = a.data + (CLS ? class_record(rb, fb, tile, T) : tile_record(rb, fb, tile, T));
     uint16_t* rr = reinterpret_cast<uint16_t*>(rec);
-    const int64_t hat = CLS ? 2 * halo_at(T) : halo_at(T);
+    const int64_t hat = CLS ? class_halo_at(T) : halo_at(T);
     int32_t* halo = reinterpret_cast<int32_t*>(rec + hat);
     bool full = false;
     for (int base = 0; base < len; base += BS * U) {
@@ -454,6 +457,38 @@ __global__ __launch_bounds__(256) void k_tile_order(const TileWork* __restrict__
     }
 }
 
+// Colour-class tiles: each node's fan entries grouped by the node's stored
+// position p (0, then 1, then 2), in incidence order inside a group, and the
+// group bounds written beside the fan starts, so that the sweep evaluates
+// each group with the stored order fixed at compile time.  The minima over a
+// fan are exact, so the order of its entries changes no result.  One
+// work-group per tile; the tile's entries (at most T * kTileMaxDeg, the
+// build's limit) are read into LDS first and written back grouped.
+template <int T>
+__global__ __launch_bounds__(256) void k_class_fan_sort(const TileWork* __restrict__ work)
+{
+    __shared__ uint16_t s_f[T * kTileMaxDeg];
+    const TileWork d = work[blockIdx.x];
+    uint16_t* const rr = const_cast<uint16_t*>(d.rr);
+    const uint16_t* const fr = rr + halo_at(T) / 2;
+    uint32_t* const pc = reinterpret_cast<uint32_t*>(reinterpret_cast<unsigned char*>(rr) + 2 * halo_at(T));
+    uint16_t* const fans = reinterpret_cast<uint16_t*>(const_cast<uint64_t*>(d.tris));
+    const int flen = d.tri_cnt;
+    for (int j = threadIdx.x; j < flen; j += 256) s_f[j] = fans[j];
+    __syncthreads();
+    for (int i = threadIdx.x; i < d.nown; i += 256) {
+        const int b = fr[i], e = fr[i + 1];
+        int c[4] = {0, 0, 0, 0};
+        for (int j = b; j < e; ++j) ++c[s_f[j] & 3u];
+        int pos[4] = {b, b + c[0], b + c[0] + c[1], e};
+        for (int j = b; j < e; ++j) {
+            const uint16_t v = s_f[j];
+            fans[pos[v & 3u]++] = v;
+        }
+        pc[i] = static_cast<uint32_t>(c[0]) | (static_cast<uint32_t>(c[0] + c[1]) << 16);
+    }
+}
+
 // Largest halo, padded row segment and triangle list over the tiles (one
 // work-group).
 __global__ __launch_bounds__(1024) void k_tile_caps(const TileWork* __restrict__ work, int32_t nt,
@@ -499,7 +534,7 @@ size_t tile_bytes(int64_t n, int64_t nnz, int64_t ninc, int tile_nodes, bool cla
     const size_t nt = static_cast<size_t>(div_up(std::max<int64_t>(n, 1), tile_nodes)) +
                       (classes ? static_cast<size_t>(kMaxTileClasses) : 0);
     const size_t z = static_cast<size_t>(std::max<int64_t>(nnz, 1)), c = static_cast<size_t>(std::max<int64_t>(ninc, 1));
-    const size_t rec = classes ? nt * (4 * tile_nodes + 128) + 6 * z + 2 * c + 16
+    const size_t rec = classes ? nt * (8 * tile_nodes + 128) + 6 * z + 2 * c + 16
                                : nt * (2 * tile_nodes + 64) + 6 * z + 8 * c + 16;
     return Arena::piece(sizeof(TileWork) * nt) + Arena::piece(rec);
 }
@@ -577,6 +612,11 @@ sl_status build_tiles(const SetupArgs& a, DevMesh& m, int tile_nodes, int mesh, 
         m.tile_data = nullptr;
         persist.rewind(pmark);
         return SL_OK;
+    }
+    if (classes) {
+        if (T == 128) k_class_fan_sort<128><<<nt, 256, 0, st>>>(m.work);
+        else if (T == 256) k_class_fan_sort<256><<<nt, 256, 0, st>>>(m.work);
+        else k_class_fan_sort<512><<<nt, 256, 0, st>>>(m.work);
     }
     // (class tiles have fan entries, not triangle words: nothing to group)
     const int cap = classes ? 0 : std::min(h[3], kOrderWords);
