@@ -267,7 +267,8 @@ SL_API sl_status sl_batch_smooth(const sl_mesh_desc* meshes, int32_t n_meshes, i
  * k sweeps and then k more give exactly the result of 2k sweeps in one
  * smooth_mesh call.  Options are fixed at creation (automatic values
  * resolved then); flags_out is ignored and the resident kernel is not used
- * (Form B runs on the node kernel).  A handle belongs to the device that
+ * (Form B runs on colour-class tiles where the mesh fits them, else on the
+ * node kernel).  A handle belongs to the device that
  * was current at creation, and calls on it must be made with that device
  * current; it is not thread-safe (one call at a time per handle).  Work on
  * a handle is ordered across streams: each call's work runs after the

@@ -8,7 +8,8 @@
 // current positions: a call with no tolerance runs exactly its sweeps, and a
 // call with a tolerance reads the sweep state back between chunks of sweeps,
 // as smooth_mesh does.  A handle never takes the resident kernel, which
-// expects a mesh at its first sweep.
+// expects a mesh at its first sweep.  Form B handles sweep colour-class
+// tiles where the mesh fits them, else the node kernel.
 #include <algorithm>
 #include <chrono>
 #include <cstring>
@@ -167,6 +168,24 @@ struct sl_mesh {
     }
 
     bool tiles() const { return o.form == SL_JACOBI && m.tile_nodes > 0; }
+    bool class_tiles() const { return o.form != SL_JACOBI && m.tile_nodes > 0 && m.n_tile_classes > 0; }
+
+    // Form B on colour-class tiles: one launch per class, in place, with the
+    // sweep state at `st_state`; the last class closes the sweep when `close`.
+    sl_status sweep_classes(sl::MeshState* st_state, bool close, hipStream_t st) const
+    {
+        for (int32_t c = 0; c < m.n_tile_classes; ++c) {
+            sl::TileLaunch Lc = launch();
+            Lc.work = m.work + m.class_tile_h[c];
+            Lc.n_work = m.class_tile_h[c + 1] - m.class_tile_h[c];
+            Lc.states = st_state;
+            Lc.n_close = close && c + 1 == m.n_tile_classes ? 1 : 0;
+            Lc.wg_per_cu = wg_auto ? 0 : o.tile_wg_per_cu;   // a count tuned for Form A's tiles does not apply
+            const sl_status r = sl::launch_sweep_class(Lc, m.fans_max, nullptr, st);
+            if (r) return r;
+        }
+        return SL_OK;
+    }
 
     sl::TileLaunch launch() const
     {
@@ -179,6 +198,7 @@ struct sl_mesh {
     sl_status sweep(int32_t parity, hipStream_t st) const
     {
         if (tiles()) return sl::launch_sweep_tiles(launch(), parity, nullptr, st);
+        if (class_tiles()) return sweep_classes(state, true, st);
         const sl_status r = sl::launch_sweep_nodes(m, parity, o.form, o.accept, block, state, nullptr, st);
         return r ? r : sl::launch_advance(state, 1, st);
     }
@@ -248,9 +268,12 @@ sl_status handle_options(const sl_options* opts, sl_options* out, int32_t* wg_au
     sl_status r = check_options(o);
     if (r) return r;
     if (o.kernel == SL_KERNEL_RESIDENT) return fail(SL_EINVAL, "mesh handles do not run the resident kernel");
-    if (o.kernel == SL_KERNEL_AUTO && o.form == SL_INPLACE_COLORED) o.kernel = SL_KERNEL_NODE;
+    // automatic Form B: colour-class tiles where the mesh fits them, else
+    // the node kernel (the automatic choice of a one-call smooth would also
+    // consider the resident kernel)
+    if (o.kernel == SL_KERNEL_AUTO && o.form == SL_INPLACE_COLORED) o.kernel = SL_KERNEL_TILE;
     *wg_auto = o.tile_wg_per_cu == 0 ? 1 : 0;
-    o.tile_nodes = resolve_tile_nodes(o);
+    if (o.form == SL_JACOBI) o.tile_nodes = resolve_tile_nodes(o);   // colour-class tiles size themselves
     o.tile_wg_per_cu = resolve_wg_per_cu(o);
     o.block_size = resolve_block_size(o);
     *out = o;
@@ -344,7 +367,7 @@ void fill_report(const sl_mesh* h, const MeshState& ms, sl_report* rep)
         if (hipEventElapsedTime(&ms_, h->t0, h->t1) == hipSuccess) r.sweep_ms = ms_;
         else (void)hipGetLastError();
     }
-    r.kernel_used = h->tiles() ? SL_KERNEL_TILE : SL_KERNEL_NODE;
+    r.kernel_used = h->m.tile_nodes > 0 ? SL_KERNEL_TILE : SL_KERNEL_NODE;
     r.tile_nodes = h->m.tile_nodes;
     *rep = r;
 }
@@ -370,6 +393,7 @@ sl_status sl_mesh_create(const sl_mesh_desc* desc, const sl_options* opts, sl_me
     SL_HIP(hipGetDevice(&h->device));
     keep_pool_warm();
     if ((r = take_stream(&h->own))) return r;
+    h->m.class_tiles_ok = true;
     if ((r = upload_and_prepare(*desc, h->o, 0, h->m, h->own))) return r;
     if ((r = finish_create(h.get(), t0))) return r;
     *out = h.release();
@@ -396,6 +420,7 @@ sl_status sl_mesh_create_device(const double* coords, int32_t n_nodes, const int
     // the caller's arrays are read on the caller's stream, in its order
     hipStream_t st = static_cast<hipStream_t>(stream);
     MeshInput in{coords, n_nodes, nbr_ptr, nbr_idx, tri_ptr, tri_idx, tris, n_tris, boundary};
+    h->m.class_tiles_ok = true;
     if ((r = prepare_mesh(in, h->o, 0, h->m, st))) return r;
     SL_HIP(hipStreamSynchronize(st));
     if ((r = finish_create(h.get(), t0))) return r;
@@ -587,6 +612,11 @@ sl_status sl_mesh_smooth_batch_async(sl_mesh* const* meshes, int32_t n_meshes, i
             for (int32_t i = 0; i < n_meshes; ++i) {
                 const sl_mesh* h = meshes[i];
                 if (jacobi && h->tiles()) continue;
+                // Form B on class tiles: the handle's own launches, closed below with the others
+                if (h->class_tiles()) {
+                    if ((r = h->sweep_classes(states + i, false, st))) return r;
+                    continue;
+                }
                 if ((r = launch_sweep_nodes(h->m, parity, o.form, o.accept, h->block, states + i, nullptr, st)))
                     return r;
             }

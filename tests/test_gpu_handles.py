@@ -97,7 +97,30 @@ def test_options(opts):
     assert rep.iterations_run == 21
     assert (X == r.coords).all()
     if opts.get("form") == "colored":
-        assert rep.kernel_used == sl.KERNELS["node"] and rep.n_colors > 0
+        assert rep.kernel_used == sl.KERNELS["tile"] and rep.n_colors > 0
+
+
+def test_form_b_handles_on_class_tiles_and_node_kernel_batched():
+    """Form B handles: a grid on colour-class tiles, a Delaunay mesh, and a
+    mesh of stars too dense for tiles on the node kernel, smoothed alone and
+    batched; every one equals the oracle's coloured sweeps."""
+    ms = [meshgen.make_grid(70, "random", 0.4, 31), meshgen.make_delaunay(4000, 32), _many_stars(300, 20, 33)]
+    hs = [sl.Mesh(m, form="colored") for m in ms]
+    try:
+        kinds = [h.report().kernel_used for h in hs]
+        assert kinds == [sl.KERNELS["tile"], sl.KERNELS["tile"], sl.KERNELS["node"]], kinds
+        for h in hs:
+            h.smooth_async(5)
+        sl.smooth_batch_async(hs, 7)
+        hs[0].smooth_async(3)
+        for m, h, k in zip(ms, hs, (15, 12, 12)):
+            X, rep = h.download()
+            r = ref(m, k, form="colored")
+            assert rep.iterations_run == k and (X == r.coords).all(), m.name
+            assert rep.accepted_total == int(r.accepted.sum()), m.name
+    finally:
+        for h in hs:
+            h.close()
 
 
 def test_async_returns_before_the_work_and_overlaps_a_caller_kernel():
