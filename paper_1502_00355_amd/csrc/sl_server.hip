@@ -136,6 +136,7 @@ struct HipExec {
         PooledStream ps;
         sl_status r = ps.init();
         if (r) return r;
+        q.x.mesh.class_tiles_ok = true;   // Form B: colour-class tiles where the mesh fits them
         r = upload_and_prepare(q.desc, opts, q.slot, q.x.mesh, ps.s);
         if (r) {
             devmesh_free(q.x.mesh, ps.s);
@@ -153,10 +154,13 @@ struct HipExec {
     // Concatenates the tile lists of the requests of the step.
     sl_status rebuild_work(const std::vector<Req*>& in_step)
     {
+        // Form A's tiles only: a Form B request on colour-class tiles keeps
+        // its own launches, one per class
+        const bool jacobi = opts.form == SL_JACOBI;
         int64_t total = 0;
         T = hcap = rcap = 0;
         for (Req* q : in_step)
-            if (q->x.mesh.tile_nodes > 0) total += q->x.mesh.n_tiles;
+            if (jacobi && q->x.mesh.tile_nodes > 0) total += q->x.mesh.n_tiles;
         if (total > INT32_MAX) return fail(SL_ENOMEM, "too many tiles in flight");
         if (total > work_cap) {
             dfree(work, st_compute);
@@ -170,7 +174,7 @@ struct HipExec {
         int64_t off = 0;
         for (Req* q : in_step) {
             const DevMesh& m = q->x.mesh;
-            if (m.tile_nodes == 0) continue;
+            if (!jacobi || m.tile_nodes == 0) continue;
             if (T != 0 && m.tile_nodes != T) return fail(SL_EINVAL, "requests with different tile sizes");
             SL_HIP(hipMemcpyAsync(work + off, m.work, sizeof(TileWork) * m.n_tiles, hipMemcpyDeviceToDevice,
                                   st_compute));
@@ -211,8 +215,20 @@ struct HipExec {
             if (jacobi && n_work > 0) r = launch_sweep_tiles(L, parity, nullptr, st_compute);
             for (Req* q : in_step) {
                 if (r) break;
-                if (jacobi && q->x.mesh.tile_nodes > 0) continue;
-                r = launch_sweep_nodes(q->x.mesh, parity, opts.form, opts.accept, block, states + q->slot, nullptr,
+                const DevMesh& m = q->x.mesh;
+                if (jacobi && m.tile_nodes > 0) continue;
+                if (!jacobi && m.tile_nodes > 0 && m.n_tile_classes > 0) {
+                    // Form B on colour-class tiles: its tiles name its slot's
+                    // state; the sweep is closed below with the others
+                    for (int32_t c = 0; c < m.n_tile_classes && !r; ++c) {
+                        TileLaunch Lc{m.work + m.class_tile_h[c], m.class_tile_h[c + 1] - m.class_tile_h[c],
+                                      m.tile_nodes, m.halo_max, m.rows_max, opts.layout, opts.accept, states,
+                                      wg_auto ? 0 : wg_per_cu, 0, opts.precision, sched, 0, wg_auto};
+                        r = launch_sweep_class(Lc, m.fans_max, nullptr, st_compute);
+                    }
+                    continue;
+                }
+                r = launch_sweep_nodes(m, parity, opts.form, opts.accept, block, states + q->slot, nullptr,
                                        st_compute);
             }
             if (!r && !all_tiles) r = launch_advance(states, max_active, st_compute);
@@ -265,7 +281,7 @@ struct HipExec {
         std::memcpy(&rep.max_disp_sq_last, &ms.maxd_last, sizeof(double));
         rep.accepted_last = static_cast<int64_t>(ms.acc_last);
         rep.accepted_total = static_cast<int64_t>(ms.acc_total);
-        rep.kernel_used = (jacobi && m.tile_nodes > 0) ? SL_KERNEL_TILE : SL_KERNEL_NODE;
+        rep.kernel_used = m.tile_nodes > 0 ? SL_KERNEL_TILE : SL_KERNEL_NODE;
         rep.tile_nodes = m.tile_nodes;
         q.report = rep;
         return SL_OK;
@@ -319,11 +335,14 @@ sl_status sl_server_create(const sl_server_config* cfg, const sl_options* opts, 
     // requests join a shared step of a few sweeps; the resident kernel runs
     // a mesh's sweeps all at once, which this schedule has no place for
     if (o.kernel == SL_KERNEL_RESIDENT) return fail(SL_EINVAL, "a server does not run the resident kernel");
-    if (o.kernel == SL_KERNEL_AUTO) o.kernel = o.form == SL_JACOBI ? SL_KERNEL_TILE : SL_KERNEL_NODE;
+    // automatic: the tile path where a request fits it (Form B: colour-class
+    // tiles), else the node kernel
+    if (o.kernel == SL_KERNEL_AUTO) o.kernel = SL_KERNEL_TILE;
     // automatic launch shapes are fixed when the server starts: every
-    // request of one work list has the same tile size
+    // request of one work list has the same tile size (colour-class tiles
+    // size themselves per request)
     const int32_t wg_auto = o.tile_wg_per_cu == 0 ? 1 : 0;
-    o.tile_nodes = resolve_tile_nodes(o);
+    if (o.form == SL_JACOBI) o.tile_nodes = resolve_tile_nodes(o);
     o.tile_wg_per_cu = resolve_wg_per_cu(o);
     o.block_size = resolve_block_size(o);
     keep_pool_warm();

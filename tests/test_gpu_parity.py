@@ -691,6 +691,26 @@ def test_server_mix_equals_single_and_oracle():
         assert t.submitted_s <= t.admitted_s <= t.started_s <= t.done_s
 
 
+def test_server_form_b_mix():
+    """Form B requests: meshes on colour-class tiles of both automatic sizes
+    (256 below 2^20 nodes) and a mesh on the node kernel, sharing steps:
+    each result and accepted count equals the oracle's coloured sweeps."""
+    ms = [meshgen.make_grid(n, "random", 0.4, 900 + n) for n in (30, 90, 200)]
+    ms.append(meshgen.make_delaunay(3000, 91))
+    ms.append(_ring_star(24, 5))                                   # node kernel
+    jobs = [(7, 0.0), (12, 0.0), (20, 0.0), (400, 1e-6), (5, 0.0)]
+    with sl.Server(form="colored", sweeps_per_step=4) as srv:
+        ids = [srv.submit(m, it, tol) for m, (it, tol) in zip(ms, jobs)]
+        res = [srv.wait(i) for i in ids]
+    for m, (it, tol), r in zip(ms, jobs, res):
+        assert r.status == sl.SL_OK, r.message
+        ref = oracle.smooth(m, it, tol=tol, form="colored")
+        assert r.report.iterations_run == ref.iterations_run, m.name
+        assert (r.coords == ref.coords).all(), m.name
+        assert r.report.accepted_total == int(ref.accepted.sum()), m.name
+    assert [r.report.kernel_used for r in res[:4]] == [sl.KERNELS["tile"]] * 4
+
+
 def test_server_cancel_deadline_budget_and_bad_input():
     big = meshgen.make_grid(300, "random", 0.4, 1)
     ok = meshgen.make_grid(30, "random", 0.4, 2)
