@@ -110,7 +110,7 @@ sl_status sl_batch_smooth(const sl_mesh_desc* meshes, int32_t n_meshes, int32_t 
     // automatic launch shapes are fixed once for the whole batch: every
     // mesh of one work list has the same tile size
     const int32_t wg_auto = o.tile_wg_per_cu == 0 ? 1 : 0;
-    o.tile_nodes = resolve_tile_nodes(o);
+    if (o.form == SL_JACOBI) o.tile_nodes = resolve_tile_nodes(o);   // colour-class tiles size themselves
     o.tile_wg_per_cu = resolve_wg_per_cu(o);
     o.block_size = resolve_block_size(o);
     keep_pool_warm();
@@ -141,7 +141,7 @@ sl_status sl_batch_smooth(const sl_mesh_desc* meshes, int32_t n_meshes, int32_t 
         for (int32_t i = 0; i < n_meshes && ok; ++i) {
             const sl_mesh_desc& d = meshes[i];
             ok = d.nbr_ptr && d.tri_ptr && d.n_nodes > 0 && d.nbr_ptr[d.n_nodes] >= 0 && d.tri_ptr[d.n_nodes] >= 0;
-            if (ok) sz[i] = mesh_block_bytes(d.n_nodes, d.nbr_ptr[d.n_nodes], d.tri_ptr[d.n_nodes], o);
+            if (ok) sz[i] = mesh_block_bytes(d.n_nodes, d.nbr_ptr[d.n_nodes], d.tri_ptr[d.n_nodes], o, true);
             total += sz[i];
         }
         if (ok && block_take(&bs.block, total, st) == SL_OK) {
@@ -170,6 +170,7 @@ sl_status sl_batch_smooth(const sl_mesh_desc* meshes, int32_t n_meshes, int32_t 
         for (;;) {
             const int32_t i = next.fetch_add(1);
             if (i >= n_meshes || failed.load()) break;
+            bs.meshes[i].class_tiles_ok = true;   // Form B: colour-class tiles where a mesh fits them
             const sl_status rr = upload_and_prepare(meshes[i], o, i, bs.meshes[i], ts);
             if (rr) {
                 t_status[t] = rr;
@@ -200,13 +201,15 @@ sl_status sl_batch_smooth(const sl_mesh_desc* meshes, int32_t n_meshes, int32_t 
         const DevMesh& m = bs.meshes[i];
         sum_nodes += static_cast<size_t>(m.n);
         max_nodes = std::max(max_nodes, static_cast<size_t>(m.n));
-        if (m.tile_nodes > 0) {
+        if (m.tile_nodes > 0) ++on_tiles;
+        // Form A's tiles go into one work list; a Form B mesh on colour-class
+        // tiles keeps its own launches, one per class
+        if (o.form == SL_JACOBI && m.tile_nodes > 0) {
             if (T != 0 && m.tile_nodes != T) return fail(SL_EINVAL, "meshes of one batch with different tile sizes");
             T = m.tile_nodes;
             total_tiles += m.n_tiles;
             halo_cap = std::max(halo_cap, m.halo_max);
             rows_cap = std::max(rows_cap, m.rows_max);
-            ++on_tiles;
         }
     }
     if (total_tiles > INT32_MAX) return fail(SL_EINVAL, "batch has more than 2^31 tiles");
@@ -215,7 +218,7 @@ sl_status sl_batch_smooth(const sl_mesh_desc* meshes, int32_t n_meshes, int32_t 
     if ((r = dalloc(&bs.work, static_cast<size_t>(std::max<int64_t>(total_tiles, 1)), st))) return r;
     int64_t off = 0;
     for (auto& m : bs.meshes) {
-        if (m.tile_nodes == 0) continue;
+        if (o.form != SL_JACOBI || m.tile_nodes == 0) continue;
         SL_HIP(hipMemcpyAsync(bs.work + off, m.work, sizeof(TileWork) * m.n_tiles, hipMemcpyDeviceToDevice, st));
         off += m.n_tiles;
     }
@@ -277,6 +280,17 @@ sl_status sl_batch_smooth(const sl_mesh_desc* meshes, int32_t n_meshes, int32_t 
             for (int32_t i = 0; i < n_meshes && !rr; ++i) {
                 const DevMesh& m = bs.meshes[i];
                 if (m.resident || (jacobi && m.tile_nodes > 0)) continue;
+                if (!jacobi && m.tile_nodes > 0 && m.n_tile_classes > 0) {
+                    // Form B on colour-class tiles: its tiles name its state;
+                    // the sweep is closed below with the others
+                    for (int32_t c = 0; c < m.n_tile_classes && !rr; ++c) {
+                        TileLaunch Lc{m.work + m.class_tile_h[c], m.class_tile_h[c + 1] - m.class_tile_h[c],
+                                      m.tile_nodes, m.halo_max, m.rows_max, o.layout, o.accept, bs.states,
+                                      wg_auto ? 0 : o.tile_wg_per_cu, 0, o.precision, bs.sched, 0, wg_auto};
+                        rr = launch_sweep_class(Lc, m.fans_max, nullptr, st);
+                    }
+                    continue;
+                }
                 rr = launch_sweep_nodes(m, s & 1, o.form, o.accept, block, bs.states + i, nullptr, st);
             }
             if (!rr && !all_tiles) rr = launch_advance(bs.states, n_meshes, st);
@@ -378,8 +392,7 @@ sl_status sl_batch_smooth(const sl_mesh_desc* meshes, int32_t n_meshes, int32_t 
             std::memcpy(&rep.max_disp_sq_last, &hs[i].maxd_last, sizeof(double));
             rep.accepted_last = static_cast<int64_t>(hs[i].acc_last);
             rep.accepted_total = static_cast<int64_t>(hs[i].acc_total);
-            rep.kernel_used = m.resident ? SL_KERNEL_RESIDENT
-                                         : (jacobi && m.tile_nodes > 0) ? SL_KERNEL_TILE : SL_KERNEL_NODE;
+            rep.kernel_used = m.resident ? SL_KERNEL_RESIDENT : m.tile_nodes > 0 ? SL_KERNEL_TILE : SL_KERNEL_NODE;
             rep.tile_nodes = m.tile_nodes;
             reports[i] = rep;
         }

@@ -691,6 +691,21 @@ def test_server_mix_equals_single_and_oracle():
         assert t.submitted_s <= t.admitted_s <= t.started_s <= t.done_s
 
 
+def test_batch_form_b_on_class_tiles_resident_and_node():
+    """A Form B batch: meshes on colour-class tiles, a small mesh on the
+    resident kernel and a mesh too dense for tiles on the node kernel, in
+    one call; every one equals the oracle's coloured sweeps."""
+    ms = [meshgen.make_grid(70, "random", 0.4, 41), meshgen.make_delaunay(5000, 42),
+          meshgen.make_grid(20, "random", 0.4, 43), _many_stars(300, 20, 44)]
+    outs, reps, br = sl.batch_smooth(ms, 9, form="colored")
+    assert [r.kernel_used for r in reps] == [sl.KERNELS[k] for k in ("tile", "tile", "resident", "node")]
+    assert br.meshes_resident == 1
+    for m, X, rep in zip(ms, outs, reps):
+        ref = oracle.smooth(m, 9, form="colored")
+        assert (X == ref.coords).all(), m.name
+        assert rep.accepted_total == int(ref.accepted.sum()), m.name
+
+
 def test_server_form_b_mix():
     """Form B requests: meshes on colour-class tiles of both automatic sizes
     (256 below 2^20 nodes) and a mesh on the node kernel, sharing steps:
