@@ -87,13 +87,17 @@ typedef enum {
 typedef enum { SL_REORDER_NONE = 0, SL_REORDER_HILBERT = 1 } sl_reorder;
 typedef enum {
     SL_KERNEL_AUTO = 0,  /* Form A: the tile kernel when the mesh fits it, else the node kernel.
-                            Form B: the resident kernel when the mesh fits it (in a server:
-                            never), else the node kernel */
+                            Form B: the resident kernel when the mesh fits it (never in a
+                            server or on a handle), else colour-class tiles when the mesh fits
+                            them, else the node kernel */
     SL_KERNEL_NODE = 1,  /* one work-item per free node, neighbours gathered from HBM/L2 */
-    SL_KERNEL_TILE = 2,  /* work-group per tile of free nodes staged in LDS (Form A only; at
-                            most 16 neighbour entries and 16 incidences per node on average
-                            over a tile, at most 4 distinct outside neighbours per tile node,
-                            and its halo and rows must fit in LDS), else the node kernel */
+    SL_KERNEL_TILE = 2,  /* work-group per tile of free nodes staged in LDS: Form A's tiles of
+                            consecutive free nodes, or Form B's tiles of one colour class each
+                            (one launch per class, in place; double precision, at most 32
+                            classes).  At most 16 neighbour entries and 16 incidences per node
+                            on average over a tile, at most 4 (colour-class tiles: 8) distinct
+                            outside neighbours per tile node, and the halo and rows must fit
+                            in LDS; else the node kernel */
     SL_KERNEL_RESIDENT = 3  /* one work-group runs every sweep of the mesh in one launch, with
                                the coordinates, rows and fans in LDS (double precision, not in a
                                server): Form A keeps both buffers, Form B one, updated class by
