@@ -98,7 +98,7 @@ typedef enum {
                             on average over a tile, at most 4 (colour-class tiles: 8) distinct
                             outside neighbours per tile node, and the halo and rows must fit
                             in LDS; else the node kernel */
-    SL_KERNEL_RESIDENT = 3  /* one work-group runs every sweep of the mesh in one launch, with
+    SL_KERNEL_RESIDENT = 3, /* one work-group runs every sweep of the mesh in one launch, with
                                the coordinates, rows and fans in LDS (double precision, not in a
                                server): Form A keeps both buffers, Form B one, updated class by
                                class.  (32 or 16) n + 4 (n + 1) + 2 nbr_ptr[n] + 2 tri_ptr[n]
@@ -106,6 +106,13 @@ typedef enum {
                                Form B has at most 32 colour classes; SL_EINVAL otherwise.  For
                                Form A one compute unit outpaces the tile kernel only on meshes
                                of a few hundred nodes, so it is never chosen automatically */
+    SL_KERNEL_LANES = 4     /* a lane group of lane_width work-items of one wave per free node:
+                               the group's lanes gather the node's neighbours and evaluate its
+                               incident triangles side by side, and DPP moves inside the group
+                               fold their minima; neighbours come from L2/HBM, no tiles.  Double
+                               precision, either form (Form B: one launch per colour class).  It
+                               issues each wave instruction for 64 / lane_width nodes instead of
+                               64, so the tile kernel outruns it; never chosen automatically */
 } sl_kernel;
 
 typedef struct {
@@ -125,6 +132,9 @@ typedef struct {
                               * most 3 on launches of fewer than 16384 tiles), or 1..8, capped
                               * by what fits in LDS; results do not depend on it */
     int32_t precision;       /* sl_precision */
+    int32_t lane_width;      /* SL_KERNEL_LANES: work-items per free node, 0 = automatic (the
+                              * value sl_autotune chose on this device, else 8), or 4, 8 or 16;
+                              * results do not depend on it */
     /* Optional accept flags, nullable.  Size iterations * ((n_nodes + 7) / 8)
      * bytes; sweep k occupies bytes [k*((n+7)/8), (k+1)*((n+7)/8)); bit (i % 8)
      * of byte (i / 8) is 1 iff free node i accepted its move in sweep k
@@ -142,7 +152,7 @@ typedef struct {
     double setup_ms;            /* device time: validation, reorder, relabel, fan build */
     double sweep_ms;            /* device time of the sweep loop only */
     double total_ms;            /* host wall time of the whole call */
-    int32_t kernel_used;        /* SL_KERNEL_NODE, SL_KERNEL_TILE or SL_KERNEL_RESIDENT */
+    int32_t kernel_used;        /* SL_KERNEL_NODE, SL_KERNEL_TILE, SL_KERNEL_RESIDENT or SL_KERNEL_LANES */
     int32_t tile_nodes;         /* free nodes per tile on the tile path, else 0 */
 } sl_report;
 
@@ -381,8 +391,11 @@ SL_API sl_status sl_build_adjacency_device(const int32_t* tris, int32_t n_tris, 
  * leave tile_nodes / tile_wg_per_cu at 0 use it.  For Form B (coloured) the
  * node kernel's work-group size is tuned and used where block_size is 0 (the
  * node kernel runs the Form B meshes that do not take colour-class tiles);
- * colour-class tiles are not tuned.  Meshes are read, not written.  The caller's opts
- * give form, accept and layout; their tile fields are ignored.
+ * colour-class tiles are not tuned.  With opts->kernel == SL_KERNEL_LANES
+ * (either form) the lane-group width (4, 8, 16; default 8) is tuned instead
+ * and used where lane_width is 0.  Meshes are read, not written.  The
+ * caller's opts give form, accept, layout and kernel; their tile, block and
+ * lane fields are ignored.
  * out: nullable.  Thread-safe; a later call replaces the device's choice. */
 typedef struct {
     int32_t tile_nodes;          /* chosen, 0 if no sampled mesh fits the tile path */
@@ -390,13 +403,14 @@ typedef struct {
     int32_t block_size;          /* chosen node-kernel work-group size (Form B), else 0 */
     int32_t n_candidates;        /* entries of the table below that were timed */
     struct {
-        int32_t tile_nodes;      /* 0 for a node-kernel candidate */
-        int32_t wg_per_cu;       /* or the node-kernel work-group size */
+        int32_t tile_nodes;      /* 0 for a node-kernel or lane-group candidate */
+        int32_t wg_per_cu;       /* or the node-kernel work-group size, or the lane-group width */
         double ns_per_update;    /* device time per free-node update */
     } candidates[16];
     int32_t sampled_meshes;
     int64_t sampled_free_nodes;
     double tune_ms;              /* host wall time of the call */
+    int32_t lane_width;          /* chosen lane-group width (kernel SL_KERNEL_LANES), else 0 */
 } sl_tuning;
 
 SL_API sl_status sl_autotune(const sl_mesh_desc* meshes, int32_t n_meshes, const sl_options* opts, sl_tuning* out);

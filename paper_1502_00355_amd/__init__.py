@@ -25,7 +25,7 @@ FORMS = {"jacobi": 0, "colored": 1}
 ACCEPT = {"ge": 0, "gt": 1}
 LAYOUTS = {"aos": 0, "soa": 1}
 REORDER = {"none": 0, "hilbert": 1}
-KERNELS = {"auto": 0, "node": 1, "tile": 2, "resident": 3}
+KERNELS = {"auto": 0, "node": 1, "tile": 2, "resident": 3, "lanes": 4}
 PRECISIONS = {"f64": 0, "f32": 1}
 
 
@@ -39,7 +39,7 @@ class Options(ctypes.Structure):
     _fields_ = [("form", ctypes.c_int32), ("accept", ctypes.c_int32), ("layout", ctypes.c_int32),
                 ("reorder", ctypes.c_int32), ("block_size", ctypes.c_int32), ("kernel", ctypes.c_int32),
                 ("tile_nodes", ctypes.c_int32), ("tile_wg_per_cu", ctypes.c_int32), ("precision", ctypes.c_int32),
-                ("flags_out", ctypes.c_void_p)]
+                ("lane_width", ctypes.c_int32), ("flags_out", ctypes.c_void_p)]
 
 
 class Report(ctypes.Structure):
@@ -77,10 +77,11 @@ class Tuning(ctypes.Structure):
     _fields_ = [("tile_nodes", ctypes.c_int32), ("tile_wg_per_cu", ctypes.c_int32), ("block_size", ctypes.c_int32),
                 ("n_candidates", ctypes.c_int32), ("candidates", TuneCandidate * 16),
                 ("sampled_meshes", ctypes.c_int32), ("sampled_free_nodes", ctypes.c_int64),
-                ("tune_ms", ctypes.c_double)]
+                ("tune_ms", ctypes.c_double), ("lane_width", ctypes.c_int32)]
 
     def as_dict(self):
         return {"tile_nodes": self.tile_nodes, "tile_wg_per_cu": self.tile_wg_per_cu, "block_size": self.block_size,
+                "lane_width": self.lane_width,
                 "candidates": [(c.tile_nodes, c.wg_per_cu, c.ns_per_update)
                                for c in self.candidates[: self.n_candidates]],
                 "sampled_meshes": self.sampled_meshes, "sampled_free_nodes": self.sampled_free_nodes,
@@ -205,7 +206,7 @@ def _check(status: int):
 
 
 def make_options(form="jacobi", accept="ge", layout="aos", reorder="hilbert", block_size=0, kernel="auto",
-                 tile_nodes=0, tile_wg_per_cu=0, precision="f64", flags_ptr=None):
+                 tile_nodes=0, tile_wg_per_cu=0, precision="f64", lane_width=0, flags_ptr=None):
     o = Options()
     lib().sl_options_default(ctypes.byref(o))
     o.form = FORMS[form] if isinstance(form, str) else int(form)
@@ -217,6 +218,7 @@ def make_options(form="jacobi", accept="ge", layout="aos", reorder="hilbert", bl
     o.tile_nodes = int(tile_nodes)
     o.tile_wg_per_cu = int(tile_wg_per_cu)
     o.precision = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
+    o.lane_width = int(lane_width)
     o.flags_out = flags_ptr
     return o
 

@@ -27,7 +27,7 @@ int current_device()
 TunedShape tuned_shape()
 {
     const int dev = current_device();
-    if (dev < 0) return TunedShape{0, 0, 0};
+    if (dev < 0) return TunedShape{0, 0, 0, 0};
     std::lock_guard<std::mutex> lk(g_tune_mu);
     return g_tuned[dev];
 }
@@ -40,7 +40,7 @@ void set_tuned_shape(const TunedShape& t)
     g_tuned[dev] = t;
 }
 
-void clear_tuned_shape() { set_tuned_shape(TunedShape{0, 0, 0}); }
+void clear_tuned_shape() { set_tuned_shape(TunedShape{0, 0, 0, 0}); }
 
 int32_t resolve_tile_nodes(const sl_options& o)
 {
@@ -59,6 +59,13 @@ int32_t resolve_block_size(const sl_options& o)
 {
     if (o.block_size) return o.block_size;
     return tuned_shape().block_size;
+}
+
+int32_t resolve_lane_width(const sl_options& o)
+{
+    if (o.lane_width) return o.lane_width;
+    const TunedShape t = tuned_shape();
+    return t.lane_width ? t.lane_width : 8;
 }
 
 // Freed device memory stays in the stream-ordered pool for the next call.
@@ -84,8 +91,10 @@ sl_status check_options(const sl_options& o)
     if (o.block_size != 0 && o.block_size != 64 && o.block_size != 128 && o.block_size != 256)
         return fail(SL_EINVAL, "block_size must be 0, 64, 128 or 256");
     if (o.kernel != SL_KERNEL_AUTO && o.kernel != SL_KERNEL_NODE && o.kernel != SL_KERNEL_TILE &&
-        o.kernel != SL_KERNEL_RESIDENT)
+        o.kernel != SL_KERNEL_RESIDENT && o.kernel != SL_KERNEL_LANES)
         return fail(SL_EINVAL, "unknown kernel");
+    if (o.lane_width != 0 && o.lane_width != 4 && o.lane_width != 8 && o.lane_width != 16)
+        return fail(SL_EINVAL, "lane_width must be 0, 4, 8 or 16");
     if (o.kernel == SL_KERNEL_RESIDENT && o.precision != SL_F64)
         return fail(SL_EINVAL, "the resident kernel runs in double precision only");
     if (o.tile_nodes != 0 && o.tile_nodes != 256 && o.tile_nodes != 512 &&
@@ -93,7 +102,7 @@ sl_status check_options(const sl_options& o)
         return fail(SL_EINVAL, "tile_nodes must be 0, 256 or 512 (or 128 for the coloured form)");
     if (o.tile_wg_per_cu < 0 || o.tile_wg_per_cu > 8) return fail(SL_EINVAL, "tile_wg_per_cu must be in 0..8");
     if (o.precision != SL_F64 && o.precision != SL_F32) return fail(SL_EINVAL, "unknown precision");
-    if (o.precision == SL_F32 && (o.form != SL_JACOBI || o.kernel == SL_KERNEL_NODE))
+    if (o.precision == SL_F32 && (o.form != SL_JACOBI || o.kernel == SL_KERNEL_NODE || o.kernel == SL_KERNEL_LANES))
         return fail(SL_EINVAL, "single precision runs Form A on the tile kernel only");
     return SL_OK;
 }
@@ -349,7 +358,7 @@ sl_status run_device(double* coords, int32_t n, const int32_t* nbr_ptr, const in
         SL_HIP(hipEventElapsedTime(&ms, cs.ev[2], cs.ev[3]));
         rep.sweep_ms = ms;
         rep.total_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
-        rep.kernel_used = cs.m.resident ? SL_KERNEL_RESIDENT : cs.m.tile_nodes > 0 ? SL_KERNEL_TILE : SL_KERNEL_NODE;
+        rep.kernel_used = kernel_used(cs.m);
         rep.tile_nodes = cs.m.tile_nodes;
         *report = rep;
     }

@@ -392,7 +392,7 @@ sl_status sl_batch_smooth(const sl_mesh_desc* meshes, int32_t n_meshes, int32_t 
             std::memcpy(&rep.max_disp_sq_last, &hs[i].maxd_last, sizeof(double));
             rep.accepted_last = static_cast<int64_t>(hs[i].acc_last);
             rep.accepted_total = static_cast<int64_t>(hs[i].acc_total);
-            rep.kernel_used = m.resident ? SL_KERNEL_RESIDENT : m.tile_nodes > 0 ? SL_KERNEL_TILE : SL_KERNEL_NODE;
+            rep.kernel_used = kernel_used(m);
             rep.tile_nodes = m.tile_nodes;
             reports[i] = rep;
         }

@@ -272,6 +272,7 @@ struct DevMesh {
     void* X[2] = {nullptr, nullptr};     // one block of 4n elements: X[1] = X[0] + 2n;
                                          // AoS (x,y pairs) or SoA (x[n] then y[n]) inside each
     bool resident = false;               // Form A on the resident kernel (node-path arrays built)
+    int32_t lane_width = 0;              // node path: > 0 sweeps with lane groups of this width
     // Tile path: Form A, or Form B on colour-class tiles (n_tile_classes > 0)
     int32_t tile_nodes = 0;              // 0: tile path not built
     int32_t n_tile_classes = 0;          // Form B: class c sweeps tiles [class_tile_h[c], class_tile_h[c+1])
@@ -287,6 +288,14 @@ struct DevMesh {
 
 // Frees every device array of m (stream-ordered).
 void devmesh_free(DevMesh& m, hipStream_t st);
+
+// The sweep kernel a set-up mesh runs (sl_report::kernel_used).
+inline int32_t kernel_used(const DevMesh& m)
+{
+    if (m.resident) return SL_KERNEL_RESIDENT;
+    if (m.tile_nodes > 0) return SL_KERNEL_TILE;
+    return m.lane_width > 0 ? SL_KERNEL_LANES : SL_KERNEL_NODE;
+}
 
 struct SetupArgs {
     const double* coords;   // caller layout, n x 2
@@ -394,7 +403,7 @@ sl_status upload_and_prepare(const sl_mesh_desc& d, const sl_options& o, int32_t
 
 // Launch shapes that sl_autotune chose for a device (zeros: none chosen).
 struct TunedShape {
-    int32_t tile_nodes, wg_per_cu, block_size;
+    int32_t tile_nodes, wg_per_cu, block_size, lane_width;
 };
 TunedShape tuned_shape();                       // of the current device
 void set_tuned_shape(const TunedShape& t);      // for the current device
@@ -405,6 +414,7 @@ void clear_tuned_shape();
 int32_t resolve_tile_nodes(const sl_options& o);
 int32_t resolve_wg_per_cu(const sl_options& o);
 int32_t resolve_block_size(const sl_options& o);
+int32_t resolve_lane_width(const sl_options& o);   // lane groups: option, else tuned, else 8
 
 // Writes the positions of buffer `src` -- or, when `runs` is given, of
 // buffer (runs->s % 2), read on the device -- back to the caller's layout

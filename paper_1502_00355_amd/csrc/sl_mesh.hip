@@ -367,7 +367,7 @@ void fill_report(const sl_mesh* h, const MeshState& ms, sl_report* rep)
         if (hipEventElapsedTime(&ms_, h->t0, h->t1) == hipSuccess) r.sweep_ms = ms_;
         else (void)hipGetLastError();
     }
-    r.kernel_used = h->m.tile_nodes > 0 ? SL_KERNEL_TILE : SL_KERNEL_NODE;
+    r.kernel_used = kernel_used(h->m);
     r.tile_nodes = h->m.tile_nodes;
     *rep = r;
 }

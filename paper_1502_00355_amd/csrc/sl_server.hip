@@ -281,7 +281,7 @@ struct HipExec {
         std::memcpy(&rep.max_disp_sq_last, &ms.maxd_last, sizeof(double));
         rep.accepted_last = static_cast<int64_t>(ms.acc_last);
         rep.accepted_total = static_cast<int64_t>(ms.acc_total);
-        rep.kernel_used = m.tile_nodes > 0 ? SL_KERNEL_TILE : SL_KERNEL_NODE;
+        rep.kernel_used = kernel_used(m);
         rep.tile_nodes = m.tile_nodes;
         q.report = rep;
         return SL_OK;

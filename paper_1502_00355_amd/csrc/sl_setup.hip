@@ -965,7 +965,7 @@ static int32_t tile_size_for(const sl_options& o, int32_t n)
 // setup_mesh decides it.
 static bool wants_tiles(const sl_options& o, bool resident, bool class_tiles_ok)
 {
-    if (o.kernel == SL_KERNEL_NODE || resident) return false;
+    if (o.kernel == SL_KERNEL_NODE || o.kernel == SL_KERNEL_LANES || resident) return false;
     return o.form == SL_JACOBI || (class_tiles_ok && o.precision == SL_F64);
 }
 
@@ -1011,6 +1011,7 @@ sl_status setup_mesh(const SetupArgs& a, const sl_options& o, DevMesh& m, int32_
     if (o.kernel == SL_KERNEL_RESIDENT && !res_fit) return fail(SL_EINVAL, "mesh too large for the resident kernel");
     m.resident = o.kernel == SL_KERNEL_RESIDENT ||
                  (o.kernel == SL_KERNEL_AUTO && o.form == SL_INPLACE_COLORED && res_fit);
+    m.lane_width = o.kernel == SL_KERNEL_LANES ? resolve_lane_width(o) : 0;
     const bool want_tiles = wants_tiles(o, m.resident, m.class_tiles_ok);
     const size_t un = static_cast<size_t>(n);
     // Two reservations: the mesh's own arrays, sized from bounds known before

@@ -21,6 +21,7 @@
 // Form B (eq. (3)): one launch per colour class, in place; no two nodes of a
 // class are adjacent, so no work-item reads a position another writes.
 #include <cmath>
+#include <type_traits>
 
 #include "sl_common.h"
 
@@ -290,6 +291,184 @@ void launch_range(SweepArgs a, int max_deg, int requested_block, bool soa, bool 
     } else {
         launch_variant<64, 128>(a, soa, gt, grid, st);
     }
+}
+
+// ----------------------------------------------------------- lane groups --
+//
+// A lane group of W consecutive work-items of one wave (W = 4, 8 or 16)
+// takes one free node.  Lane j gathers the node's neighbour slots j, j + W,
+// ... from L2/HBM and parks them in the group's LDS row; every lane of the
+// group then forms the row-order sum from that row and divides once by the
+// count (eq. (2)); lane j evaluates fan entries j, j + W, ... with the node
+// at its position and at the candidate (Sec. 2.1); DPP moves inside the
+// group fold the lanes' minima (a minimum is exact, so the fold order
+// changes nothing), and the group's first lane takes the accept test and the
+// write.  The arithmetic is the node kernel's, operation for operation.
+// Several lanes share one node's latency chains, at the price of issuing a
+// wave instruction for 64 / W nodes instead of 64.
+
+// Work-group size of the lane-group variant for W and the largest valence
+// MAXV: 256, or 16 groups when one group's LDS row is 129 positions long.
+template <int W, int MAXV>
+constexpr int lane_block() { return MAXV <= 32 ? 256 : 16 * W; }
+
+// The minimum over the W lanes of each group (every lane of the wave
+// active): swaps of neighbouring lanes and of lane pairs inside each quad,
+// then the mirror inside each half row (8 lanes) and each row (16 lanes).
+template <int W>
+__device__ __forceinline__ double group_min(double v)
+{
+    auto fold = [&v](auto ctrl) {
+        constexpr int c = decltype(ctrl)::value;
+        const long long b = __double_as_longlong(v);
+        const int lo = __builtin_amdgcn_update_dpp(0, static_cast<int>(b), c, 0xF, 0xF, false);
+        const int hi = __builtin_amdgcn_update_dpp(0, static_cast<int>(b >> 32), c, 0xF, 0xF, false);
+        const double t = __longlong_as_double((static_cast<long long>(hi) << 32) | static_cast<uint32_t>(lo));
+        v = t < v ? t : v;
+    };
+    fold(std::integral_constant<int, 0xB1>{});                   // quad_perm [1,0,3,2]
+    fold(std::integral_constant<int, 0x4E>{});                   // quad_perm [2,3,0,1]
+    if (W >= 8) fold(std::integral_constant<int, 0x141>{});      // row_half_mirror
+    if (W >= 16) fold(std::integral_constant<int, 0x140>{});     // row_mirror
+    return v;
+}
+
+template <int W, int MAXV, bool SOA, bool GT>
+__global__ __launch_bounds__((lane_block<W, MAXV>())) void k_sweep_lanes(SweepArgs a)
+{
+    constexpr int BS = lane_block<W, MAXV>(), G = BS / W, NPW = 64 / W;   // groups per work-group, per wave
+    if (!a.state->active) return;
+    // a contiguous run of tiles per XCD, as in the node kernel
+    const int tile = static_cast<int>(blockIdx.x % 8) * a.tiles_per_xcd + static_cast<int>(blockIdx.x / 8);
+    if (tile >= a.n_tiles) return;
+
+    __shared__ double2 nb[G][MAXV + 1];   // one row per group; the pad spreads the rows over the banks
+    __shared__ double s_d2[BS / 64];
+    __shared__ unsigned long long s_acc[BS / 64];
+    __shared__ double s_recip[kMaxValence + 1];
+
+    const int tid = threadIdx.x, g = tid / W, j = tid % W;
+    for (int i = tid; i <= kMaxValence; i += BS) s_recip[i] = i ? 1.0 / static_cast<double>(i) : 0.0;
+    const int k = a.k_begin + tile * G + g;
+    const bool live = k < a.k_end;
+    // a group past the range repeats the last node's loads and stores nothing
+    const int kk = live ? k : a.k_end - 1;
+    const int32_t r0 = a.row_ptr[kk], d = a.row_ptr[kk + 1] - r0;   // d >= 1 for a free node
+    const int32_t f0 = a.fan_ptr[kk], f1 = a.fan_ptr[kk + 1];
+    const double2 o = ld<SOA>(a.Xin, a.n, kk);
+    // lane j: slots j, j + W, ..., two per step with their loads in flight together
+    for (int s0 = j; s0 < d; s0 += 2 * W) {
+        const int32_t id0 = a.nbr[r0 + s0], id1 = a.nbr[r0 + min(s0 + W, d - 1)];
+        const double2 p0 = ld<SOA>(a.Xin, a.n, id0), p1 = ld<SOA>(a.Xin, a.n, id1);
+        nb[g][s0] = p0;
+        if (s0 + W < d) nb[g][s0 + W] = p1;
+    }
+    __syncthreads();   // the group's row and the reciprocal table
+
+    // the row-order sum, on every lane of the group (the same LDS reads)
+    double sx = 0.0, sy = 0.0;
+    for (int s = 0; s < d; ++s) {
+        const double2 p = nb[g][s];
+        sx += p.x;
+        sy += p.y;
+    }
+    const double dn = static_cast<double>(d), y = s_recip[d];
+    double cx = div_small(sx, dn, y), cy = div_small(sy, dn, y);
+    const bool tiny = !(fabs(sx) >= kStepMin) || !(fabs(sy) >= kStepMin);
+    if (__builtin_amdgcn_ballot_w64(tiny) != 0ull) {
+        if (tiny) {
+            cx = sx / dn;
+            cy = sy / dn;
+        }
+    }
+    const double2 c = make_double2(cx, cy);
+    double qo = INFINITY, qn = INFINITY;
+    for (int f = f0 + j; f < f1; f += W) {
+        const uint32_t e = a.fan[f];
+        const double2 va = nb[g][(e >> 2) & 127u], vb = nb[g][(e >> 9) & 127u];
+        double v, w;
+        fan_qualities(static_cast<int>(e & 3u), o, c, va, vb, v, w);
+        if (v < qo) qo = v;
+        if (w < qn) qn = w;
+    }
+    qo = group_min<W>(qo);
+    qn = group_min<W>(qn);
+
+    bool accepted = false;
+    double d2 = 0.0;
+    if (live && j == 0) {
+        accepted = GT ? (qn > qo) : (qn >= qo);
+        const double nx = accepted ? cx : o.x, ny = accepted ? cy : o.y;
+        st<SOA>(a.Xout, a.n, k, nx, ny);
+        const double dx = nx - o.x, dy = ny - o.y;
+        d2 = dx * dx + dy * dy;
+    }
+
+    // wave reductions: accepted count, accept bits (one per group), max displacement
+    const unsigned long long ball = __ballot(accepted);
+    const int lane = tid & 63, wv = tid >> 6;
+    if (a.bits != nullptr && lane == 0 && ball != 0ull) {
+        unsigned long long nodes = 0;   // bit q: the wave's group q accepted
+#pragma unroll
+        for (int q = 0; q < NPW; ++q) nodes |= ((ball >> (q * W)) & 1ull) << q;
+        const int kw = a.k_begin + tile * G + wv * NPW, sh = kw & 63;
+        unsigned long long* word = reinterpret_cast<unsigned long long*>(a.bits) + (kw >> 6);
+        atomicOr(word, nodes << sh);
+        if (sh != 0 && (nodes >> (64 - sh)) != 0ull) atomicOr(word + 1, nodes >> (64 - sh));
+    }
+    for (int off = 32; off > 0; off >>= 1) {
+        const double t = __shfl_xor(d2, off);
+        d2 = t > d2 ? t : d2;
+    }
+    if (lane == 0) {
+        s_d2[wv] = d2;
+        s_acc[wv] = __popcll(ball);
+    }
+    __syncthreads();
+    if (tid == 0) {
+        double m = s_d2[0];
+        unsigned long long cnt = s_acc[0];
+        for (int q = 1; q < BS / 64; ++q) {
+            m = s_d2[q] > m ? s_d2[q] : m;
+            cnt += s_acc[q];
+        }
+        if (m > 0.0) atomicMax(&a.state->maxd_cur, static_cast<unsigned long long>(__double_as_longlong(m)));
+        if (cnt) atomicAdd(&a.state->acc_cur, cnt);
+    }
+}
+
+template <int W, int MAXV>
+void launch_lanes_v(SweepArgs a, int64_t cnt, bool soa, bool gt, hipStream_t st)
+{
+    constexpr int BS = lane_block<W, MAXV>(), G = BS / W;
+    a.n_tiles = static_cast<int32_t>(div_up(cnt, G));
+    a.tiles_per_xcd = div_up(a.n_tiles, 8);
+    const int grid = 8 * a.tiles_per_xcd;
+    if (soa) {
+        if (gt) k_sweep_lanes<W, MAXV, true, true><<<grid, BS, 0, st>>>(a);
+        else k_sweep_lanes<W, MAXV, true, false><<<grid, BS, 0, st>>>(a);
+    } else {
+        if (gt) k_sweep_lanes<W, MAXV, false, true><<<grid, BS, 0, st>>>(a);
+        else k_sweep_lanes<W, MAXV, false, false><<<grid, BS, 0, st>>>(a);
+    }
+}
+
+template <int W>
+void launch_lanes_w(const SweepArgs& a, int64_t cnt, int max_deg, bool soa, bool gt, hipStream_t st)
+{
+    if (max_deg <= 8) launch_lanes_v<W, 8>(a, cnt, soa, gt, st);
+    else if (max_deg <= 16) launch_lanes_v<W, 16>(a, cnt, soa, gt, st);
+    else if (max_deg <= 32) launch_lanes_v<W, 32>(a, cnt, soa, gt, st);
+    else launch_lanes_v<W, 128>(a, cnt, soa, gt, st);
+}
+
+void launch_lanes(const SweepArgs& a, int max_deg, int width, bool soa, bool gt, hipStream_t st)
+{
+    const int64_t cnt = static_cast<int64_t>(a.k_end) - a.k_begin;
+    if (cnt <= 0) return;
+    if (width == 4) launch_lanes_w<4>(a, cnt, max_deg, soa, gt, st);
+    else if (width == 16) launch_lanes_w<16>(a, cnt, max_deg, soa, gt, st);
+    else launch_lanes_w<8>(a, cnt, max_deg, soa, gt, st);
 }
 
 // ------------------------------------------------------- resident meshes --
@@ -846,14 +1025,16 @@ sl_status launch_sweep_nodes(const DevMesh& m, int32_t parity, int32_t form, int
         a.Xout = static_cast<double*>(m.X[(parity + 1) & 1]);
         a.k_begin = 0;
         a.k_end = m.n_free;
-        launch_range(a, m.max_deg, block, soa, gt, st);
+        if (m.lane_width > 0) launch_lanes(a, m.max_deg, m.lane_width, soa, gt, st);
+        else launch_range(a, m.max_deg, block, soa, gt, st);
     } else {
         a.Xin = static_cast<const double*>(m.X[0]);
         a.Xout = static_cast<double*>(m.X[0]);
         for (int c = 0; c < m.n_colors; ++c) {
             a.k_begin = m.color_start_h[c];
             a.k_end = m.color_start_h[c + 1];
-            launch_range(a, m.max_deg, block, soa, gt, st);
+            if (m.lane_width > 0) launch_lanes(a, m.max_deg, m.lane_width, soa, gt, st);
+            else launch_range(a, m.max_deg, block, soa, gt, st);
         }
     }
     SL_HIP(hipGetLastError());

@@ -7,7 +7,8 @@
 // the batched tile kernel for each work-group count (twice, interleaved,
 // keeping the faster time), and keeps the fastest shape as the automatic
 // choice of the device, unless the default shape is within 1% of it.  For
-// Form B (node kernel) it times the node kernel's work-group sizes instead.
+// Form B (node kernel) it times the node kernel's work-group sizes instead,
+// and for the lane-group kernel the width of a node's lane group.
 #include <algorithm>
 #include <chrono>
 #include <climits>
@@ -188,6 +189,50 @@ sl_status tune_nodes(const sl_mesh_desc* meshes, const std::vector<int32_t>& sam
     return SL_OK;
 }
 
+sl_status tune_lanes(const sl_mesh_desc* meshes, const std::vector<int32_t>& sample, const sl_options& base,
+                     hipStream_t st, std::vector<Candidate>& out, int64_t* free_nodes)
+{
+    // one setup per width: the width is fixed in each mesh at setup
+    const int32_t widths[3] = {4, 8, 16};
+    std::vector<TunePass> passes(3);
+    int64_t nfree = 0;
+    for (int w = 0; w < 3; ++w) {
+        sl_options o = base;
+        o.kernel = SL_KERNEL_LANES;
+        o.lane_width = widths[w];
+        passes[w].st = st;
+        const sl_status r = setup_pass(passes[w], meshes, sample, o);
+        if (r) return r;
+        if (w == 0)
+            for (const auto& m : passes[w].meshes) nfree += m.n_free;
+    }
+    if (nfree == 0) return SL_OK;
+    *free_nodes = nfree;
+    const size_t first = out.size();
+    for (int32_t pass = 0; pass < kPasses; ++pass) {
+        for (int w = 0; w < 3; ++w) {
+            TunePass& p = passes[w];
+            float ms = 0.f;
+            const sl_status r = time_sweeps(p, static_cast<int32_t>(p.meshes.size()),
+                                            [&](int32_t parity) {
+                                                for (size_t k = 0; k < p.meshes.size(); ++k) {
+                                                    const sl_status rr =
+                                                        launch_sweep_nodes(p.meshes[k], parity, base.form, base.accept,
+                                                                           0, p.states + k, nullptr, st);
+                                                    if (rr) return rr;
+                                                }
+                                                return SL_OK;
+                                            },
+                                            &ms);
+            if (r) return r;
+            const double ns = 1e6 * ms / (static_cast<double>(kTimedSweeps) * nfree);
+            if (pass == 0) out.push_back(Candidate{0, widths[w], ns});
+            else out[first + static_cast<size_t>(w)].ns = std::min(out[first + static_cast<size_t>(w)].ns, ns);
+        }
+    }
+    return SL_OK;
+}
+
 }  // namespace
 
 }  // namespace sl
@@ -207,6 +252,7 @@ sl_status sl_autotune(const sl_mesh_desc* meshes, int32_t n_meshes, const sl_opt
     o.tile_nodes = 0;
     o.tile_wg_per_cu = 0;
     o.block_size = 0;
+    o.lane_width = 0;
     sl_status r = check_options(o);
     if (r) return r;
     size_t total = 0;
@@ -224,43 +270,54 @@ sl_status sl_autotune(const sl_mesh_desc* meshes, int32_t n_meshes, const sl_opt
     SL_HIP(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
     std::vector<Candidate> cands;
     int64_t free_nodes = 0;
-    r = o.form == SL_JACOBI ? tune_tiles(meshes, sample, o, st, cands, &free_nodes)
-                            : tune_nodes(meshes, sample, o, st, cands, &free_nodes);
+    // what is tuned: the lane-group width when the lane-group kernel is asked
+    // for, else the tile shape (Form A) or the node kernel's block (Form B)
+    const bool lanes = o.kernel == SL_KERNEL_LANES;
+    r = lanes ? tune_lanes(meshes, sample, o, st, cands, &free_nodes)
+              : o.form == SL_JACOBI ? tune_tiles(meshes, sample, o, st, cands, &free_nodes)
+                                    : tune_nodes(meshes, sample, o, st, cands, &free_nodes);
     (void)hipStreamSynchronize(st);
     (void)hipStreamDestroy(st);
     if (r) return r;
 
-    TunedShape best{0, 0, 0};
+    auto shape_of = [&](const Candidate& c) {
+        if (lanes) return TunedShape{0, 0, 0, c.shape};
+        return c.tile_nodes ? TunedShape{c.tile_nodes, c.shape, 0, 0} : TunedShape{0, 0, c.shape, 0};
+    };
+    TunedShape best{0, 0, 0, 0};
     double best_ns = 0.0;
     for (const auto& c : cands) {
         if (best_ns == 0.0 || c.ns < best_ns) {
             best_ns = c.ns;
-            best = c.tile_nodes ? TunedShape{c.tile_nodes, c.shape, 0} : TunedShape{0, 0, c.shape};
+            best = shape_of(c);
         }
     }
     // near-ties go to the default shape (512 nodes and 4 work-groups per CU;
-    // block size 256), whose speed holds across meshes and devices
+    // block size 256; lane width 8), whose speed holds across meshes and devices
     for (const auto& c : cands) {
-        const bool dflt = c.tile_nodes ? (c.tile_nodes == 512 && c.shape == 4) : c.shape == 256;
-        if (dflt && c.ns <= best_ns * kPreferDefault)
-            best = c.tile_nodes ? TunedShape{c.tile_nodes, c.shape, 0} : TunedShape{0, 0, c.shape};
+        const bool dflt = lanes ? c.shape == 8 : c.tile_nodes ? (c.tile_nodes == 512 && c.shape == 4) : c.shape == 256;
+        if (dflt && c.ns <= best_ns * kPreferDefault) best = shape_of(c);
     }
     if (!cands.empty()) {
-        // a Form B tuning leaves the tile shape as it was, and vice versa
+        // each tuning sets its own fields and leaves the others as they were
         const TunedShape prev = tuned_shape();
-        if (o.form == SL_JACOBI) best.block_size = prev.block_size;
-        else {
-            best.tile_nodes = prev.tile_nodes;
-            best.wg_per_cu = prev.wg_per_cu;
+        TunedShape next = prev;
+        if (lanes) next.lane_width = best.lane_width;
+        else if (o.form == SL_JACOBI) {
+            next.tile_nodes = best.tile_nodes;
+            next.wg_per_cu = best.wg_per_cu;
+        } else {
+            next.block_size = best.block_size;
         }
-        set_tuned_shape(best);
+        set_tuned_shape(next);
     }
     if (out) {
         sl_tuning t;
         std::memset(&t, 0, sizeof(t));
-        t.tile_nodes = o.form == SL_JACOBI ? best.tile_nodes : 0;
-        t.tile_wg_per_cu = o.form == SL_JACOBI ? best.wg_per_cu : 0;
-        t.block_size = o.form == SL_JACOBI ? 0 : best.block_size;
+        t.tile_nodes = !lanes && o.form == SL_JACOBI ? best.tile_nodes : 0;
+        t.tile_wg_per_cu = !lanes && o.form == SL_JACOBI ? best.wg_per_cu : 0;
+        t.block_size = !lanes && o.form != SL_JACOBI ? best.block_size : 0;
+        t.lane_width = lanes ? best.lane_width : 0;
         const int32_t cap = static_cast<int32_t>(sizeof(t.candidates) / sizeof(t.candidates[0]));
         t.n_candidates = std::min(cap, static_cast<int32_t>(cands.size()));
         for (int32_t k = 0; k < t.n_candidates; ++k) {

@@ -50,7 +50,7 @@ def test_option_defaults(L):
     o = sl.Options()
     L.sl_options_default(ctypes.byref(o))
     assert (o.form, o.accept, o.layout, o.reorder, o.block_size, o.kernel) == (0, 0, 0, 1, 0, 0)
-    assert (o.tile_nodes, o.tile_wg_per_cu) == (0, 0)
+    assert (o.tile_nodes, o.tile_wg_per_cu, o.lane_width) == (0, 0, 0)
     assert not o.flags_out
     assert L.sl_version().startswith(b"smartlap")
 
@@ -85,6 +85,7 @@ def test_tile_option_errors_before_device_work(L):
     idx = np.zeros(1, np.int32)
     b = np.ones(4, np.uint8)
     for kw in ({"tile_nodes": 384}, {"tile_wg_per_cu": 9}, {"tile_wg_per_cu": -1}, {"block_size": 96},
+               {"lane_width": 6}, {"lane_width": 32}, {"kernel": "lanes", "precision": "f32"},
                {"kernel": 7}, {"form": 5}):
         o = sl.make_options(**kw)
         st = L.smooth_mesh(X.ctypes.data, 4, ptr.ctypes.data, idx.ctypes.data, ptr.ctypes.data, idx.ctypes.data,
@@ -121,3 +122,31 @@ def test_adjacency_argument_errors_before_device_work(L):
                                 ctypes.byref(nnz)) == sl.SL_EINVAL
     assert b"null output" in L.sl_last_error()
     assert nnz.value == -1
+
+
+STRUCTS = {"Options": "sl_options", "Report": "sl_report", "MeshDesc": "sl_mesh_desc",
+           "BatchReport": "sl_batch_report", "Tuning": "sl_tuning", "ServerConfig": "sl_server_config",
+           "RequestTimes": "sl_request_times", "ServerStats": "sl_server_stats"}
+
+
+def test_binding_structs_match_the_header(tmp_path):
+    """Every struct the binding marshals has the header's size and field
+    offsets (a C program built from include/smartlap.h prints them)."""
+    lines = ["#include <stdio.h>", "#include <stddef.h>", '#include "smartlap.h"', "int main(void) {"]
+    want = {}
+    for py, c in STRUCTS.items():
+        cls = getattr(sl, py)
+        lines.append('printf("%%s %%zu\\n", "%s", sizeof(%s));' % (py, c))
+        want[py] = ctypes.sizeof(cls)
+        for name, _ in cls._fields_:
+            lines.append('printf("%%s %%zu\\n", "%s.%s", offsetof(%s, %s));' % (py, name, c, name))
+            want[py + "." + name] = getattr(cls, name).offset
+    lines += ["return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    inc = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "include")
+    subprocess.run(["gcc", "-std=c99", "-I", inc, str(src), "-o", str(exe)], check=True)
+    got = dict(ln.split() for ln in subprocess.run([str(exe)], stdout=subprocess.PIPE, text=True,
+                                                    check=True).stdout.splitlines())
+    assert {k: int(v) for k, v in got.items()} == want

@@ -4,8 +4,8 @@ Each case draws a small mesh (a jittered grid with random or Union-Jack
 diagonals, an annulus, a Delaunay triangulation of random points, or a
 randomly relabelled copy of one of these, with a share of its free nodes
 sometimes marked fixed) and a set of options (form, accept rule, layout,
-reorder, kernel, precision, tile shape, node-kernel block size, sweeps,
-tolerance), runs it through the C ABI and compares sweep by sweep with the
+reorder, kernel, precision, tile shape, node-kernel block size or
+lane-group width, sweeps, tolerance), runs it through the C ABI and compares sweep by sweep with the
 oracle: accept flags, accepted counts, displacement maxima and coordinates
 bit for bit.  The draws are fixed by the case number, so a failure names a
 reproducible case.
@@ -65,6 +65,10 @@ def draw_options(rng, n_nodes):
     o["kernel"] = str(rng.choice(kernels))
     if o["kernel"] == "node":
         o["block_size"] = int(rng.choice([0, 64, 128, 256]))
+        if o["block_size"] in (64, 128):
+            # the lane-group kernel instead, its width taken from the same draw
+            o["kernel"] = "lanes"
+            o["lane_width"] = 4 if o.pop("block_size") == 64 else 16
     if o["kernel"] in ("auto", "tile"):
         sizes = [0, 256, 512] + ([128] if form == "colored" else [])
         o["tile_nodes"] = int(rng.choice(sizes))
