@@ -188,9 +188,13 @@ __device__ __forceinline__ void close_state(MeshState* p)
     *p = m;
 }
 
-// Counters of a tile launch: groups done, then one tile counter per XCD.
+// Counters of a tile launch: groups done, then one tile counter per XCD,
+// then (launches over one mesh) one slot per work-group for its
+// displacement maximum and accepted count (two u64).
 constexpr int kSchedStride = 32;                    // one 128-byte line per counter
-constexpr int kTileSchedInts = 9 * kSchedStride;
+constexpr int kTileMaxGroups = 8 * 32 * 8;           // 8 XCDs x 32 CUs x at most 8 groups per CU
+constexpr int kTileSlotsAt = 9 * kSchedStride;      // int offset of the slots
+constexpr int kTileSchedInts = kTileSlotsAt + 4 * kTileMaxGroups;
 
 // The last work-group of a launch to finish closes the sweep of states[0..n)
 // and zeroes the launch's counters for the next launch.  A group's folds into the
@@ -456,6 +460,10 @@ struct TileLaunch {
     // 1: wg_per_cu is the automatic value (tuned, or 0 for the default),
     // which launches of fewer than kSmallLaunchTiles tiles cap at 3
     int32_t wg_auto;
+    // 1: every tile is of one mesh; its work-groups hand their folds to the
+    // closing group through per-group slots instead of atomics on the one
+    // state (atomics on one address are serialised)
+    int32_t one_mesh = 0;
 };
 constexpr int kSmallLaunchTiles = 16384;
 sl_status launch_sweep_tiles(const TileLaunch& L, int32_t parity, uint64_t* bits, hipStream_t st);

@@ -191,7 +191,7 @@ struct sl_mesh {
     {
         // one mesh per launch: a launch on a mesh that has stopped returns at once
         return sl::TileLaunch{m.work, m.n_tiles, m.tile_nodes, m.halo_max, m.rows_max, o.layout, o.accept,
-                              state,  sl::resolve_wg_per_cu(o), 1, o.precision, sched, 1, wg_auto};
+                              state,  sl::resolve_wg_per_cu(o), 1, o.precision, sched, 1, wg_auto, 1};
     }
 
     // One sweep reading buffer `parity` (Form A) and closing it.

@@ -140,120 +140,153 @@ constexpr double kStepMin = 0x1p-1015;   // 128 x the smallest normal double
 constexpr int kNodeRow = 8;   // neighbour entries whose loads are in flight together
 constexpr int kNodeFan = 4;   // fan entries read together
 
-template <int BLOCK, int MAXV, bool SOA, bool GT>
-__global__ __launch_bounds__(BLOCK) void k_sweep(SweepArgs a)
+// The displacement maximum and accepted count of one work-group, folded
+// into the mesh's state with one atomic pair: every atomic on the state's
+// one address is serialised, so a group folds once per launch, not per tile.
+template <int BS>
+__device__ __forceinline__ void fold_group(MeshState* state, double d2, unsigned long long acc, double* s_d2,
+                                           unsigned long long* s_acc)
 {
-    if (!a.state->active) return;
-    // Work-groups are handed to the 8 XCDs round-robin; give each XCD a
-    // contiguous run of tiles so that neighbouring tiles share its L2.
-    const int tile = static_cast<int>(blockIdx.x % 8) * a.tiles_per_xcd + static_cast<int>(blockIdx.x / 8);
-    if (tile >= a.n_tiles) return;
-
-    __shared__ double2 nb[MAXV][BLOCK];
-    __shared__ double s_d2[BLOCK / 64];
-    __shared__ unsigned long long s_acc[BLOCK / 64];
-    __shared__ double s_recip[kMaxValence + 1];
-
-    const int tid = threadIdx.x;
-    for (int i = tid; i <= kMaxValence; i += BLOCK) s_recip[i] = i ? 1.0 / static_cast<double>(i) : 0.0;
-    const int k = a.k_begin + tile * BLOCK + tid;
-    const bool live = k < a.k_end;
-    // a lane past the range repeats the last node's loads and stores nothing
-    const int kk = live ? k : a.k_end - 1;
-    const int32_t r0 = a.row_ptr[kk], d = a.row_ptr[kk + 1] - r0;   // d >= 1 for a free node
-    const int32_t f0 = a.fan_ptr[kk], f1 = a.fan_ptr[kk + 1];
-    const double2 o = ld<SOA>(a.Xin, a.n, kk);
-    // the row's ids, then its positions, each group's loads in flight
-    // together; the sums run in stored order
-    double sx = 0.0, sy = 0.0;
-    for (int j0 = 0; j0 < d; j0 += kNodeRow) {
-        int32_t id[kNodeRow];
-#pragma unroll
-        for (int u = 0; u < kNodeRow; ++u) id[u] = a.nbr[r0 + min(j0 + u, d - 1)];
-        double2 p[kNodeRow];
-#pragma unroll
-        for (int u = 0; u < kNodeRow; ++u) p[u] = ld<SOA>(a.Xin, a.n, id[u]);
-#pragma unroll
-        for (int u = 0; u < kNodeRow; ++u)
-            if (j0 + u < d) {
-                sx += p[u].x;
-                sy += p[u].y;
-                nb[j0 + u][tid] = p[u];
-            }
-    }
-    __syncthreads();   // the reciprocal table
-    const double dn = static_cast<double>(d), y = s_recip[d];
-    double cx = div_small(sx, dn, y), cy = div_small(sy, dn, y);
-    const bool tiny = !(fabs(sx) >= kStepMin) || !(fabs(sy) >= kStepMin);
-    // a wave-uniform branch: the full division only when some lane needs it
-    if (__builtin_amdgcn_ballot_w64(tiny) != 0ull) {
-        if (tiny) {
-            cx = sx / dn;
-            cy = sy / dn;
-        }
-    }
-    double qo = INFINITY, qn = INFINITY;
-    for (int g0 = f0; g0 < f1; g0 += kNodeFan) {
-        uint32_t e[kNodeFan];
-#pragma unroll
-        for (int u = 0; u < kNodeFan; ++u) e[u] = a.fan[min(g0 + u, f1 - 1)];
-#pragma unroll
-        for (int u = 0; u < kNodeFan; ++u) {
-            if (g0 + u < f1) {
-                const int p = static_cast<int>(e[u] & 3u);
-                const double2 va = nb[(e[u] >> 2) & 127u][tid];
-                const double2 vb = nb[(e[u] >> 9) & 127u][tid];
-                double v, w;
-                fan_qualities(p, o, make_double2(cx, cy), va, vb, v, w);
-                if (v < qo) qo = v;
-                if (w < qn) qn = w;
-            }
-        }
-    }
-    bool accepted = false;
-    double d2 = 0.0;
-    if (live) {
-        accepted = GT ? (qn > qo) : (qn >= qo);
-        const double nx = accepted ? cx : o.x, ny = accepted ? cy : o.y;
-        st<SOA>(a.Xout, a.n, k, nx, ny);
-        const double dx = nx - o.x, dy = ny - o.y;
-        d2 = dx * dx + dy * dy;
-    }
-
-    // wave reductions: accepted count, accept bits, max displacement
-    const unsigned long long ball = __ballot(accepted);
-    const int lane = tid & 63, w = tid >> 6;
-    if (a.bits != nullptr && lane == 0 && ball != 0ull) {
-        const int kw = a.k_begin + tile * BLOCK + w * 64;
-        const int sh = kw & 63;
-        unsigned long long* word = reinterpret_cast<unsigned long long*>(a.bits) + (kw >> 6);
-        atomicOr(word, ball << sh);
-        if (sh != 0 && (ball >> (64 - sh)) != 0ull) atomicOr(word + 1, ball >> (64 - sh));
-    }
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     for (int off = 32; off > 0; off >>= 1) {
         const double t = __shfl_xor(d2, off);
         d2 = t > d2 ? t : d2;
     }
     if (lane == 0) {
         s_d2[w] = d2;
-        s_acc[w] = __popcll(ball);
+        s_acc[w] = acc;
     }
     __syncthreads();
     if (tid == 0) {
         double m = s_d2[0];
         unsigned long long c = s_acc[0];
-        for (int q = 1; q < BLOCK / 64; ++q) {
+        for (int q = 1; q < BS / 64; ++q) {
             m = s_d2[q] > m ? s_d2[q] : m;
             c += s_acc[q];
         }
-        if (m > 0.0) atomicMax(&a.state->maxd_cur, static_cast<unsigned long long>(__double_as_longlong(m)));
-        if (c) atomicAdd(&a.state->acc_cur, c);
+        if (m > 0.0) atomicMax(&state->maxd_cur, static_cast<unsigned long long>(__double_as_longlong(m)));
+        if (c) atomicAdd(&state->acc_cur, c);
     }
 }
 
-template <int BLOCK, int MAXV>
-void launch_variant(const SweepArgs& a, bool soa, bool gt, int grid, hipStream_t st)
+// Persistent work-groups over the launch's tiles (BLOCK consecutive nodes
+// each): the tiles are cut into 8 contiguous runs, one per XCD (work-groups
+// are dealt to the XCDs round-robin), so that neighbouring tiles share an L2.
+template <int BLOCK, int MAXV, bool SOA, bool GT>
+__global__ __launch_bounds__(BLOCK) void k_sweep(SweepArgs a)
 {
+    if (!a.state->active) return;
+    const int xcd = static_cast<int>(blockIdx.x & 7), nw = static_cast<int>(gridDim.x >> 3);
+    const int t_begin = xcd * a.tiles_per_xcd, t_end = min(t_begin + a.tiles_per_xcd, a.n_tiles);
+    if (t_begin + static_cast<int>(blockIdx.x >> 3) >= t_end) return;
+
+    __shared__ double2 nb[MAXV][BLOCK];   // column tid: this work-item's neighbours
+    __shared__ double s_d2[BLOCK / 64];
+    __shared__ unsigned long long s_acc[BLOCK / 64];
+    __shared__ double s_recip[kMaxValence + 1];
+
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    for (int i = tid; i <= kMaxValence; i += BLOCK) s_recip[i] = i ? 1.0 / static_cast<double>(i) : 0.0;
+    __syncthreads();   // the reciprocal table
+    double run_d2 = 0.0;
+    unsigned long long run_acc = 0;
+    for (int tile = t_begin + static_cast<int>(blockIdx.x >> 3); tile < t_end; tile += nw) {
+        const int k = a.k_begin + tile * BLOCK + tid;
+        const bool live = k < a.k_end;
+        // a lane past the range repeats the last node's loads and stores nothing
+        const int kk = live ? k : a.k_end - 1;
+        const int32_t r0 = a.row_ptr[kk], d = a.row_ptr[kk + 1] - r0;   // d >= 1 for a free node
+        const int32_t f0 = a.fan_ptr[kk], f1 = a.fan_ptr[kk + 1];
+        const double2 o = ld<SOA>(a.Xin, a.n, kk);
+        // the row's ids, then its positions, each group's loads in flight
+        // together; the sums run in stored order
+        double sx = 0.0, sy = 0.0;
+        for (int j0 = 0; j0 < d; j0 += kNodeRow) {
+            int32_t id[kNodeRow];
+#pragma unroll
+            for (int u = 0; u < kNodeRow; ++u) id[u] = a.nbr[r0 + min(j0 + u, d - 1)];
+            double2 p[kNodeRow];
+#pragma unroll
+            for (int u = 0; u < kNodeRow; ++u) p[u] = ld<SOA>(a.Xin, a.n, id[u]);
+#pragma unroll
+            for (int u = 0; u < kNodeRow; ++u)
+                if (j0 + u < d) {
+                    sx += p[u].x;
+                    sy += p[u].y;
+                    nb[j0 + u][tid] = p[u];
+                }
+        }
+        const double dn = static_cast<double>(d), y = s_recip[d];
+        double cx = div_small(sx, dn, y), cy = div_small(sy, dn, y);
+        const bool tiny = !(fabs(sx) >= kStepMin) || !(fabs(sy) >= kStepMin);
+        // a wave-uniform branch: the full division only when some lane needs it
+        if (__builtin_amdgcn_ballot_w64(tiny) != 0ull) {
+            if (tiny) {
+                cx = sx / dn;
+                cy = sy / dn;
+            }
+        }
+        double qo = INFINITY, qn = INFINITY;
+        for (int g0 = f0; g0 < f1; g0 += kNodeFan) {
+            uint32_t e[kNodeFan];
+#pragma unroll
+            for (int u = 0; u < kNodeFan; ++u) e[u] = a.fan[min(g0 + u, f1 - 1)];
+#pragma unroll
+            for (int u = 0; u < kNodeFan; ++u) {
+                if (g0 + u < f1) {
+                    const int p = static_cast<int>(e[u] & 3u);
+                    const double2 va = nb[(e[u] >> 2) & 127u][tid];
+                    const double2 vb = nb[(e[u] >> 9) & 127u][tid];
+                    double v, wq;
+                    fan_qualities(p, o, make_double2(cx, cy), va, vb, v, wq);
+                    if (v < qo) qo = v;
+                    if (wq < qn) qn = wq;
+                }
+            }
+        }
+        bool accepted = false;
+        if (live) {
+            accepted = GT ? (qn > qo) : (qn >= qo);
+            const double nx = accepted ? cx : o.x, ny = accepted ? cy : o.y;
+            st<SOA>(a.Xout, a.n, k, nx, ny);
+            const double dx = nx - o.x, dy = ny - o.y;
+            const double d2 = dx * dx + dy * dy;
+            run_d2 = d2 > run_d2 ? d2 : run_d2;
+        }
+        const unsigned long long ball = __ballot(accepted);
+        run_acc += __popcll(ball);
+        if (a.bits != nullptr && lane == 0 && ball != 0ull) {
+            const int kw = a.k_begin + tile * BLOCK + w * 64;
+            const int sh = kw & 63;
+            unsigned long long* word = reinterpret_cast<unsigned long long*>(a.bits) + (kw >> 6);
+            atomicOr(word, ball << sh);
+            if (sh != 0 && (ball >> (64 - sh)) != 0ull) atomicOr(word + 1, ball >> (64 - sh));
+        }
+    }
+    fold_group<BLOCK>(a.state, run_d2, run_acc, s_d2, s_acc);
+}
+
+// Persistent grid: 8 XCDs x 32 CUs x the work-groups a CU holds (by the
+// group's static LDS; at most 32 waves per CU), never more work-groups on
+// an XCD than it has tiles.  Every group takes an equal share of tiles, so
+// an estimate that is too high only runs the shares in two rounds.
+int persistent_grid(int tiles_per_xcd, int block, size_t lds_bytes)
+{
+    const int by_lds = static_cast<int>((160 * 1024) / std::max<size_t>(lds_bytes, 1));
+    const int per_cu = std::max(1, std::min(by_lds, 2048 / block));
+    return 8 * std::min(tiles_per_xcd, 32 * per_cu);
+}
+
+// Static LDS of a node-kernel work-group.
+constexpr size_t node_lds(int block, int maxv)
+{
+    return static_cast<size_t>(maxv) * block * 16 + (block / 64) * 16 + (kMaxValence + 1) * 8;
+}
+
+template <int BLOCK, int MAXV>
+void launch_variant(const SweepArgs& a, bool soa, bool gt, hipStream_t st)
+{
+    const int grid = persistent_grid(a.tiles_per_xcd, BLOCK, node_lds(BLOCK, MAXV));
     if (soa) {
         if (gt) k_sweep<BLOCK, MAXV, true, true><<<grid, BLOCK, 0, st>>>(a);
         else k_sweep<BLOCK, MAXV, true, false><<<grid, BLOCK, 0, st>>>(a);
@@ -279,17 +312,16 @@ void launch_range(SweepArgs a, int max_deg, int requested_block, bool soa, bool 
     const int block = block_for(max_deg, requested_block);
     a.n_tiles = div_up(cnt, block);
     a.tiles_per_xcd = div_up(a.n_tiles, 8);
-    const int grid = 8 * a.tiles_per_xcd;
     if (max_deg <= 8) {
-        if (block == 64) launch_variant<64, 8>(a, soa, gt, grid, st);
-        else if (block == 128) launch_variant<128, 8>(a, soa, gt, grid, st);
-        else launch_variant<256, 8>(a, soa, gt, grid, st);
+        if (block == 64) launch_variant<64, 8>(a, soa, gt, st);
+        else if (block == 128) launch_variant<128, 8>(a, soa, gt, st);
+        else launch_variant<256, 8>(a, soa, gt, st);
     } else if (max_deg <= 16) {
-        launch_variant<256, 16>(a, soa, gt, grid, st);
+        launch_variant<256, 16>(a, soa, gt, st);
     } else if (max_deg <= 32) {
-        launch_variant<128, 32>(a, soa, gt, grid, st);
+        launch_variant<128, 32>(a, soa, gt, st);
     } else {
-        launch_variant<64, 128>(a, soa, gt, grid, st);
+        launch_variant<64, 128>(a, soa, gt, st);
     }
 }
 
@@ -338,103 +370,91 @@ __global__ __launch_bounds__((lane_block<W, MAXV>())) void k_sweep_lanes(SweepAr
 {
     constexpr int BS = lane_block<W, MAXV>(), G = BS / W, NPW = 64 / W;   // groups per work-group, per wave
     if (!a.state->active) return;
-    // a contiguous run of tiles per XCD, as in the node kernel
-    const int tile = static_cast<int>(blockIdx.x % 8) * a.tiles_per_xcd + static_cast<int>(blockIdx.x / 8);
-    if (tile >= a.n_tiles) return;
+    // persistent work-groups over tiles of G nodes, a contiguous run of
+    // tiles per XCD, as in the node kernel
+    const int xcd = static_cast<int>(blockIdx.x & 7), nw = static_cast<int>(gridDim.x >> 3);
+    const int t_begin = xcd * a.tiles_per_xcd, t_end = min(t_begin + a.tiles_per_xcd, a.n_tiles);
+    if (t_begin + static_cast<int>(blockIdx.x >> 3) >= t_end) return;
 
     __shared__ double2 nb[G][MAXV + 1];   // one row per group; the pad spreads the rows over the banks
     __shared__ double s_d2[BS / 64];
     __shared__ unsigned long long s_acc[BS / 64];
     __shared__ double s_recip[kMaxValence + 1];
 
-    const int tid = threadIdx.x, g = tid / W, j = tid % W;
+    const int tid = threadIdx.x, g = tid / W, j = tid % W, lane = tid & 63, wv = tid >> 6;
     for (int i = tid; i <= kMaxValence; i += BS) s_recip[i] = i ? 1.0 / static_cast<double>(i) : 0.0;
-    const int k = a.k_begin + tile * G + g;
-    const bool live = k < a.k_end;
-    // a group past the range repeats the last node's loads and stores nothing
-    const int kk = live ? k : a.k_end - 1;
-    const int32_t r0 = a.row_ptr[kk], d = a.row_ptr[kk + 1] - r0;   // d >= 1 for a free node
-    const int32_t f0 = a.fan_ptr[kk], f1 = a.fan_ptr[kk + 1];
-    const double2 o = ld<SOA>(a.Xin, a.n, kk);
-    // lane j: slots j, j + W, ..., two per step with their loads in flight together
-    for (int s0 = j; s0 < d; s0 += 2 * W) {
-        const int32_t id0 = a.nbr[r0 + s0], id1 = a.nbr[r0 + min(s0 + W, d - 1)];
-        const double2 p0 = ld<SOA>(a.Xin, a.n, id0), p1 = ld<SOA>(a.Xin, a.n, id1);
-        nb[g][s0] = p0;
-        if (s0 + W < d) nb[g][s0 + W] = p1;
-    }
-    __syncthreads();   // the group's row and the reciprocal table
-
-    // the row-order sum, on every lane of the group (the same LDS reads)
-    double sx = 0.0, sy = 0.0;
-    for (int s = 0; s < d; ++s) {
-        const double2 p = nb[g][s];
-        sx += p.x;
-        sy += p.y;
-    }
-    const double dn = static_cast<double>(d), y = s_recip[d];
-    double cx = div_small(sx, dn, y), cy = div_small(sy, dn, y);
-    const bool tiny = !(fabs(sx) >= kStepMin) || !(fabs(sy) >= kStepMin);
-    if (__builtin_amdgcn_ballot_w64(tiny) != 0ull) {
-        if (tiny) {
-            cx = sx / dn;
-            cy = sy / dn;
+    double run_d2 = 0.0;
+    unsigned long long run_acc = 0;
+    for (int tile = t_begin + static_cast<int>(blockIdx.x >> 3); tile < t_end; tile += nw) {
+        const int k = a.k_begin + tile * G + g;
+        const bool live = k < a.k_end;
+        // a group past the range repeats the last node's loads and stores nothing
+        const int kk = live ? k : a.k_end - 1;
+        const int32_t r0 = a.row_ptr[kk], d = a.row_ptr[kk + 1] - r0;   // d >= 1 for a free node
+        const int32_t f0 = a.fan_ptr[kk], f1 = a.fan_ptr[kk + 1];
+        const double2 o = ld<SOA>(a.Xin, a.n, kk);
+        __syncthreads();   // the previous tile's rows are read (and, first, the reciprocal table written)
+        // lane j: slots j, j + W, ..., two per step with their loads in flight together
+        for (int s0 = j; s0 < d; s0 += 2 * W) {
+            const int32_t id0 = a.nbr[r0 + s0], id1 = a.nbr[r0 + min(s0 + W, d - 1)];
+            const double2 p0 = ld<SOA>(a.Xin, a.n, id0), p1 = ld<SOA>(a.Xin, a.n, id1);
+            nb[g][s0] = p0;
+            if (s0 + W < d) nb[g][s0 + W] = p1;
         }
-    }
-    const double2 c = make_double2(cx, cy);
-    double qo = INFINITY, qn = INFINITY;
-    for (int f = f0 + j; f < f1; f += W) {
-        const uint32_t e = a.fan[f];
-        const double2 va = nb[g][(e >> 2) & 127u], vb = nb[g][(e >> 9) & 127u];
-        double v, w;
-        fan_qualities(static_cast<int>(e & 3u), o, c, va, vb, v, w);
-        if (v < qo) qo = v;
-        if (w < qn) qn = w;
-    }
-    qo = group_min<W>(qo);
-    qn = group_min<W>(qn);
+        __syncthreads();   // the group's row
 
-    bool accepted = false;
-    double d2 = 0.0;
-    if (live && j == 0) {
-        accepted = GT ? (qn > qo) : (qn >= qo);
-        const double nx = accepted ? cx : o.x, ny = accepted ? cy : o.y;
-        st<SOA>(a.Xout, a.n, k, nx, ny);
-        const double dx = nx - o.x, dy = ny - o.y;
-        d2 = dx * dx + dy * dy;
-    }
+        // the row-order sum, on every lane of the group (the same LDS reads)
+        double sx = 0.0, sy = 0.0;
+        for (int s = 0; s < d; ++s) {
+            const double2 p = nb[g][s];
+            sx += p.x;
+            sy += p.y;
+        }
+        const double dn = static_cast<double>(d), y = s_recip[d];
+        double cx = div_small(sx, dn, y), cy = div_small(sy, dn, y);
+        const bool tiny = !(fabs(sx) >= kStepMin) || !(fabs(sy) >= kStepMin);
+        if (__builtin_amdgcn_ballot_w64(tiny) != 0ull) {
+            if (tiny) {
+                cx = sx / dn;
+                cy = sy / dn;
+            }
+        }
+        const double2 c = make_double2(cx, cy);
+        double qo = INFINITY, qn = INFINITY;
+        for (int f = f0 + j; f < f1; f += W) {
+            const uint32_t e = a.fan[f];
+            const double2 va = nb[g][(e >> 2) & 127u], vb = nb[g][(e >> 9) & 127u];
+            double v, w;
+            fan_qualities(static_cast<int>(e & 3u), o, c, va, vb, v, w);
+            if (v < qo) qo = v;
+            if (w < qn) qn = w;
+        }
+        qo = group_min<W>(qo);
+        qn = group_min<W>(qn);
 
-    // wave reductions: accepted count, accept bits (one per group), max displacement
-    const unsigned long long ball = __ballot(accepted);
-    const int lane = tid & 63, wv = tid >> 6;
-    if (a.bits != nullptr && lane == 0 && ball != 0ull) {
-        unsigned long long nodes = 0;   // bit q: the wave's group q accepted
+        bool accepted = false;
+        if (live && j == 0) {
+            accepted = GT ? (qn > qo) : (qn >= qo);
+            const double nx = accepted ? cx : o.x, ny = accepted ? cy : o.y;
+            st<SOA>(a.Xout, a.n, k, nx, ny);
+            const double dx = nx - o.x, dy = ny - o.y;
+            const double d2 = dx * dx + dy * dy;
+            run_d2 = d2 > run_d2 ? d2 : run_d2;
+        }
+        // accept bits: one per group, gathered from the wave's ballot
+        const unsigned long long ball = __ballot(accepted);
+        run_acc += __popcll(ball);
+        if (a.bits != nullptr && lane == 0 && ball != 0ull) {
+            unsigned long long nodes = 0;   // bit q: the wave's group q accepted
 #pragma unroll
-        for (int q = 0; q < NPW; ++q) nodes |= ((ball >> (q * W)) & 1ull) << q;
-        const int kw = a.k_begin + tile * G + wv * NPW, sh = kw & 63;
-        unsigned long long* word = reinterpret_cast<unsigned long long*>(a.bits) + (kw >> 6);
-        atomicOr(word, nodes << sh);
-        if (sh != 0 && (nodes >> (64 - sh)) != 0ull) atomicOr(word + 1, nodes >> (64 - sh));
-    }
-    for (int off = 32; off > 0; off >>= 1) {
-        const double t = __shfl_xor(d2, off);
-        d2 = t > d2 ? t : d2;
-    }
-    if (lane == 0) {
-        s_d2[wv] = d2;
-        s_acc[wv] = __popcll(ball);
-    }
-    __syncthreads();
-    if (tid == 0) {
-        double m = s_d2[0];
-        unsigned long long cnt = s_acc[0];
-        for (int q = 1; q < BS / 64; ++q) {
-            m = s_d2[q] > m ? s_d2[q] : m;
-            cnt += s_acc[q];
+            for (int q = 0; q < NPW; ++q) nodes |= ((ball >> (q * W)) & 1ull) << q;
+            const int kw = a.k_begin + tile * G + wv * NPW, sh = kw & 63;
+            unsigned long long* word = reinterpret_cast<unsigned long long*>(a.bits) + (kw >> 6);
+            atomicOr(word, nodes << sh);
+            if (sh != 0 && (nodes >> (64 - sh)) != 0ull) atomicOr(word + 1, nodes >> (64 - sh));
         }
-        if (m > 0.0) atomicMax(&a.state->maxd_cur, static_cast<unsigned long long>(__double_as_longlong(m)));
-        if (cnt) atomicAdd(&a.state->acc_cur, cnt);
     }
+    fold_group<BS>(a.state, run_d2, run_acc, s_d2, s_acc);
 }
 
 template <int W, int MAXV>
@@ -443,7 +463,8 @@ void launch_lanes_v(SweepArgs a, int64_t cnt, bool soa, bool gt, hipStream_t st)
     constexpr int BS = lane_block<W, MAXV>(), G = BS / W;
     a.n_tiles = static_cast<int32_t>(div_up(cnt, G));
     a.tiles_per_xcd = div_up(a.n_tiles, 8);
-    const int grid = 8 * a.tiles_per_xcd;
+    const size_t lds = static_cast<size_t>(G) * (MAXV + 1) * 16 + (BS / 64) * 16 + (kMaxValence + 1) * 8;
+    const int grid = persistent_grid(a.tiles_per_xcd, BS, lds);
     if (soa) {
         if (gt) k_sweep_lanes<W, MAXV, true, true><<<grid, BS, 0, st>>>(a);
         else k_sweep_lanes<W, MAXV, true, false><<<grid, BS, 0, st>>>(a);

@@ -102,6 +102,7 @@ struct TileSweepArgs {
     uint64_t* bits;            // nullable: accept bits of this sweep (single mesh)
     int32_t* sched;            // [kTileSchedInts]: groups done, then one tile counter per XCD, kSchedStride apart
     int32_t n_close;           // the last work-group closes the sweep of states[0..n_close)
+    int32_t one_mesh;          // every tile is of one mesh: groups fold through their slots
 };
 
 // Old quality of one triangle and the new quality for each own vertex,
@@ -267,9 +268,14 @@ __device__ __forceinline__ void stage_b(TileStage<R, NPT, RPRE, KPRE>& s, const 
 // per XCD (work-groups are dealt to the XCDs round-robin), shared round-robin
 // by the work-groups that XCD runs; each work-group computes one tile while
 // the next one's data is on its way.
+// (one_mesh: the group's displacement maximum and accepted count are left
+// in out_d2 / out_acc, per work-item as the fold below takes them, for
+// close_one_mesh; otherwise they are folded into the states here.)
 template <int T, int BS, bool SOA, bool GT, typename R>
-__device__ __forceinline__ void sweep_tiles(const TileSweepArgs& a)
+__device__ __forceinline__ void sweep_tiles(const TileSweepArgs& a, double& out_d2, unsigned long long& out_acc)
 {
+    out_d2 = 0.0;
+    out_acc = 0;
     using V2 = typename Real<R>::V2;
     constexpr int NPT = T / BS;   // own nodes per work-item
     // per work-item register budget for the next tile: about 2.4 triangles
@@ -439,7 +445,10 @@ __device__ __forceinline__ void sweep_tiles(const TileSweepArgs& a)
                     atomicOr(reinterpret_cast<unsigned long long*>(a.bits) + ((k0 + m * BS + wv * 64) >> 6), ball);
             }
         }
-        if (!has_next || dnext.mesh != dcur.mesh) {
+        if (a.one_mesh && !has_next) {
+            out_d2 = run_d2;
+            out_acc = run_acc;
+        } else if (!has_next || dnext.mesh != dcur.mesh) {
             double d2 = run_d2;
             for (int off = 32; off > 0; off >>= 1) {
                 const double t = __shfl_xor(d2, off);
@@ -474,11 +483,78 @@ __device__ __forceinline__ void sweep_tiles(const TileSweepArgs& a)
     }
 }
 
+// The end of a launch over one mesh: each work-group writes its
+// displacement maximum and accepted count to its own slot (device-scope
+// stores, completed before the group's count, as close_launch's folds are),
+// and the last group to finish folds every slot into the mesh's state and
+// closes the sweep.  Thousands of atomics on the state's one address, which
+// the device serialises, become one per launch.
+template <int BS>
+__device__ __forceinline__ void close_one_mesh(const TileSweepArgs& a, double d2, unsigned long long acc)
+{
+    __shared__ double s_d2[BS / 64];
+    __shared__ unsigned long long s_acc[BS / 64];
+    __shared__ int s_last;
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    unsigned long long* const slots = reinterpret_cast<unsigned long long*>(a.sched + kTileSlotsAt);
+    auto block_fold = [&](double& m, unsigned long long& c) {
+        for (int off = 32; off > 0; off >>= 1) {
+            const double t = __shfl_xor(m, off);
+            m = t > m ? t : m;
+            c += __shfl_xor(c, off);
+        }
+        __syncthreads();   // s_d2 / s_acc free
+        if (lane == 0) {
+            s_d2[wv] = m;
+            s_acc[wv] = c;
+        }
+        __syncthreads();
+        m = s_d2[0];
+        c = s_acc[0];
+        for (int q = 1; q < BS / 64; ++q) {
+            m = s_d2[q] > m ? s_d2[q] : m;
+            c += s_acc[q];
+        }
+    };
+    // acc is the wave's count on every lane: one lane per wave contributes
+    unsigned long long c = lane == 0 ? acc : 0ull;
+    block_fold(d2, c);
+    if (tid == 0) {
+        __hip_atomic_store(slots + 2 * blockIdx.x, static_cast<unsigned long long>(__double_as_longlong(d2)),
+                           __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_store(slots + 2 * blockIdx.x + 1, c, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+        const int before = __hip_atomic_fetch_add(a.sched, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        s_last = before == static_cast<int>(gridDim.x) - 1;
+    }
+    __syncthreads();
+    if (!s_last) return;
+    double m = 0.0;
+    unsigned long long cnt = 0;
+    for (int g = tid; g < static_cast<int>(gridDim.x); g += BS) {
+        const double mg = __longlong_as_double(static_cast<long long>(
+            __hip_atomic_load(slots + 2 * g, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)));
+        m = mg > m ? mg : m;
+        cnt += __hip_atomic_load(slots + 2 * g + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    block_fold(m, cnt);
+    if (tid == 0) {
+        MeshState* ms = a.states + a.work[0].mesh;
+        if (m > 0.0) atomicMax(&ms->maxd_cur, static_cast<unsigned long long>(__double_as_longlong(m)));
+        if (cnt) atomicAdd(&ms->acc_cur, cnt);
+        for (int i = 0; i < a.n_close; ++i) close_state(a.states + i);
+    }
+    if (tid < 9) __hip_atomic_store(a.sched + kSchedStride * tid, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
 template <int T, int BS, bool SOA, bool GT, typename R>
 __global__ __launch_bounds__(BS) void k_sweep_tile(TileSweepArgs a)
 {
-    sweep_tiles<T, BS, SOA, GT, R>(a);
-    close_launch<BS>(a.sched, a.states, a.n_close);
+    double d2;
+    unsigned long long acc;
+    sweep_tiles<T, BS, SOA, GT, R>(a, d2, acc);
+    if (a.one_mesh) close_one_mesh<BS>(a, d2, acc);
+    else close_launch<BS>(a.sched, a.states, a.n_close);
 }
 
 constexpr int kTileBS = 256;
@@ -551,8 +627,10 @@ sl_status launch_sweep_tiles(const TileLaunch& L, int32_t parity, uint64_t* bits
     a.bits = bits;
     a.sched = L.sched;
     a.n_close = L.n_close;
+    a.one_mesh = L.one_mesh;
     const size_t lds = tile_lds_bytes(L.tile_nodes, L.halo_cap, L.rows_cap, L.precision);
     const int grid = tile_grid(L.n_work, L.tile_nodes, L.halo_cap, L.rows_cap, L.wg_per_cu, L.precision, L.wg_auto != 0);
+    if (grid > kTileMaxGroups) return fail(SL_EINVAL, "internal: tile launch of more groups than slots");
     const bool soa = L.layout == SL_SOA, gt = L.accept == SL_ACCEPT_GT;
     if (L.precision == SL_F32) {
         if (L.tile_nodes == 256) launch_tile_t<256, float>(a, soa, gt, grid, lds, st);
