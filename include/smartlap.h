@@ -88,8 +88,8 @@ typedef enum { SL_REORDER_NONE = 0, SL_REORDER_HILBERT = 1 } sl_reorder;
 typedef enum {
     SL_KERNEL_AUTO = 0,  /* Form A: the tile kernel when the mesh fits it, else the node kernel.
                             Form B: the resident kernel when the mesh fits it (never in a
-                            server or on a handle), else colour-class tiles when the mesh fits
-                            them, else the node kernel */
+                            server or on a handle), else the node kernel (faster there than
+                            colour-class tiles, which SL_KERNEL_TILE asks for) */
     SL_KERNEL_NODE = 1,  /* one work-item per free node, neighbours gathered from HBM/L2 */
     SL_KERNEL_TILE = 2,  /* work-group per tile of free nodes staged in LDS: Form A's tiles of
                             consecutive free nodes, or Form B's tiles of one colour class each
@@ -281,8 +281,8 @@ SL_API sl_status sl_batch_smooth(const sl_mesh_desc* meshes, int32_t n_meshes, i
  * k sweeps and then k more give exactly the result of 2k sweeps in one
  * smooth_mesh call.  Options are fixed at creation (automatic values
  * resolved then); flags_out is ignored and the resident kernel is not used
- * (Form B runs on colour-class tiles where the mesh fits them, else on the
- * node kernel).  A handle belongs to the device that
+ * (Form B runs on the node kernel, or on colour-class tiles where the mesh
+ * fits them when SL_KERNEL_TILE asks for them).  A handle belongs to the device that
  * was current at creation, and calls on it must be made with that device
  * current; it is not thread-safe (one call at a time per handle).  Work on
  * a handle is ordered across streams: each call's work runs after the
@@ -390,7 +390,7 @@ SL_API sl_status sl_build_adjacency_device(const int32_t* tris, int32_t n_tris, 
  * fastest -- for the rest of the process: later calls whose options
  * leave tile_nodes / tile_wg_per_cu at 0 use it.  For Form B (coloured) the
  * node kernel's work-group size is tuned and used where block_size is 0 (the
- * node kernel runs the Form B meshes that do not take colour-class tiles);
+ * node kernel is Form B's automatic choice beyond the resident kernel);
  * colour-class tiles are not tuned.  With opts->kernel == SL_KERNEL_LANES
  * (either form) the lane-group width (4, 8, 16; default 8) is tuned instead
  * and used where lane_width is 0.  Meshes are read, not written.  The

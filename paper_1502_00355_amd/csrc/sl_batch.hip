@@ -170,7 +170,7 @@ sl_status sl_batch_smooth(const sl_mesh_desc* meshes, int32_t n_meshes, int32_t 
         for (;;) {
             const int32_t i = next.fetch_add(1);
             if (i >= n_meshes || failed.load()) break;
-            bs.meshes[i].class_tiles_ok = true;   // Form B: colour-class tiles where a mesh fits them
+            bs.meshes[i].class_tiles_ok = true;   // Form B: colour-class tiles, when asked for, where a mesh fits them
             const sl_status rr = upload_and_prepare(meshes[i], o, i, bs.meshes[i], ts);
             if (rr) {
                 t_status[t] = rr;
@@ -291,7 +291,7 @@ sl_status sl_batch_smooth(const sl_mesh_desc* meshes, int32_t n_meshes, int32_t 
                     }
                     continue;
                 }
-                rr = launch_sweep_nodes(m, s & 1, o.form, o.accept, block, bs.states + i, nullptr, st);
+                rr = launch_sweep_nodes(m, s & 1, o.form, o.accept, block, bs.states + i, nullptr, bs.sched, st);
             }
             if (!rr && !all_tiles) rr = launch_advance(bs.states, n_meshes, st);
             if (rr) return rr;

@@ -188,13 +188,129 @@ __device__ __forceinline__ void close_state(MeshState* p)
     *p = m;
 }
 
-// Counters of a tile launch: groups done, then one tile counter per XCD,
-// then (launches over one mesh) one slot per work-group for its
+// Counters of a tile launch, one 128-byte line each: [0] XCDs whose groups
+// are all done, [1..8] one tile counter per XCD, [9..16] groups done per
+// XCD; then (launches over one mesh) one slot per work-group for its
 // displacement maximum and accepted count (two u64).
 constexpr int kSchedStride = 32;                    // one 128-byte line per counter
+constexpr int kSchedCounters = 17;
 constexpr int kTileMaxGroups = 8 * 32 * 8;           // 8 XCDs x 32 CUs x at most 8 groups per CU
-constexpr int kTileSlotsAt = 9 * kSchedStride;      // int offset of the slots
+constexpr int kTileSlotsAt = kSchedCounters * kSchedStride;   // int offset of the slots
 constexpr int kTileSchedInts = kTileSlotsAt + 4 * kTileMaxGroups;
+
+// Work-item 0 of a group counts the group done and learns whether it is the
+// launch's last: the groups of each XCD count on their own line and the last
+// of them counts the XCD on the launch's line, so no line takes more than
+// gridDim.x / 8 atomics (atomics on one address are serialised).  The
+// launch's grid is a multiple of 8, group g on XCD g % 8.  The group's
+// earlier device-scope writes are performed before its count (the
+// work-group-scope release waits for them).
+// Launches of at most kDirectFoldGroups groups count on the launch's line
+// alone and fold straight into the state: so few atomics cost less than
+// the longer chain of the two-level count and the slots.
+constexpr int kDirectFoldGroups = 64;
+
+__device__ __forceinline__ bool count_group_done(int32_t* sched)
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    if (static_cast<int>(gridDim.x) <= kDirectFoldGroups)
+        return __hip_atomic_fetch_add(sched, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) ==
+               static_cast<int>(gridDim.x) - 1;
+    const int xcd = static_cast<int>(blockIdx.x & 7), per_xcd = static_cast<int>(gridDim.x >> 3);
+    const int b = __hip_atomic_fetch_add(sched + kSchedStride * (9 + xcd), 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (b != per_xcd - 1) return false;
+    return __hip_atomic_fetch_add(sched, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 7;
+}
+
+// The launch's last group leaves the counters zeroed for the next launch.
+__device__ __forceinline__ void reset_sched(int32_t* sched)
+{
+    if (threadIdx.x < kSchedCounters)
+        __hip_atomic_store(sched + kSchedStride * threadIdx.x, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// A launch over one mesh folds its work-groups' displacement maxima and
+// accepted counts through per-group slots: each group writes its own slot
+// (device-scope stores, performed before its count, as the folds below
+// are), and the last group to finish folds every slot into the mesh's state
+// with one atomic pair.  Thousands of atomics on the state's one address,
+// which the device serialises, become one pair per launch.  (A launch of at
+// most kDirectFoldGroups groups folds straight into the state, and counts
+// its groups only when the caller needs the last one.)  d2: the
+// work-item's maximum; acc: its wave's count (the same on every lane).
+// Returns, on every work-item, whether the group was the launch's last
+// (always false for a direct fold without NEED_LAST); that group has also
+// zeroed the launch's counters.
+template <int BS, bool NEED_LAST>
+__device__ __forceinline__ bool fold_through_slots(int32_t* sched, MeshState* ms, double d2, unsigned long long acc)
+{
+    __shared__ double s_d2[BS / 64];
+    __shared__ unsigned long long s_acc[BS / 64];
+    __shared__ int s_last;
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    unsigned long long* const slots = reinterpret_cast<unsigned long long*>(sched + kTileSlotsAt);
+    auto block_fold = [&](double& m, unsigned long long& c) {
+        for (int off = 32; off > 0; off >>= 1) {
+            const double t = __shfl_xor(m, off);
+            m = t > m ? t : m;
+            c += __shfl_xor(c, off);
+        }
+        __syncthreads();   // s_d2 / s_acc free
+        if (lane == 0) {
+            s_d2[wv] = m;
+            s_acc[wv] = c;
+        }
+        __syncthreads();
+        m = s_d2[0];
+        c = s_acc[0];
+        for (int q = 1; q < BS / 64; ++q) {
+            m = s_d2[q] > m ? s_d2[q] : m;
+            c += s_acc[q];
+        }
+    };
+    unsigned long long c = lane == 0 ? acc : 0ull;   // one lane per wave contributes
+    block_fold(d2, c);
+    const bool direct = static_cast<int>(gridDim.x) <= kDirectFoldGroups;
+    if (direct && !NEED_LAST) {
+        if (tid == 0) {
+            if (d2 > 0.0) atomicMax(&ms->maxd_cur, static_cast<unsigned long long>(__double_as_longlong(d2)));
+            if (c) atomicAdd(&ms->acc_cur, c);
+        }
+        return false;
+    }
+    if (tid == 0) {
+        if (direct) {
+            if (d2 > 0.0) atomicMax(&ms->maxd_cur, static_cast<unsigned long long>(__double_as_longlong(d2)));
+            if (c) atomicAdd(&ms->acc_cur, c);
+        } else {
+            __hip_atomic_store(slots + 2 * blockIdx.x, static_cast<unsigned long long>(__double_as_longlong(d2)),
+                               __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_store(slots + 2 * blockIdx.x + 1, c, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+        s_last = count_group_done(sched);
+    }
+    __syncthreads();
+    if (!s_last) return false;
+    if (direct) {
+        reset_sched(sched);
+        return true;
+    }
+    double m = 0.0;
+    unsigned long long cnt = 0;
+    for (int g = tid; g < static_cast<int>(gridDim.x); g += BS) {
+        const double mg = __longlong_as_double(static_cast<long long>(
+            __hip_atomic_load(slots + 2 * g, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)));
+        m = mg > m ? mg : m;
+        cnt += __hip_atomic_load(slots + 2 * g + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    block_fold(m, cnt);
+    if (tid == 0) {
+        if (m > 0.0) atomicMax(&ms->maxd_cur, static_cast<unsigned long long>(__double_as_longlong(m)));
+        if (cnt) atomicAdd(&ms->acc_cur, cnt);
+    }
+    reset_sched(sched);
+    return true;
+}
 
 // The last work-group of a launch to finish closes the sweep of states[0..n)
 // and zeroes the launch's counters for the next launch.  A group's folds into the
@@ -207,19 +323,13 @@ constexpr int kTileSchedInts = kTileSlotsAt + 4 * kTileMaxGroups;
 template <int BS>
 __device__ __forceinline__ void close_launch(int32_t* sched, MeshState* states, int32_t n)
 {
-    int32_t* const count = sched;
     __shared__ int s_last;
     __syncthreads();   // every work-item of the group is done with its tiles
-    if (threadIdx.x == 0) {
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
-        const int before = __hip_atomic_fetch_add(count, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        s_last = before == static_cast<int>(gridDim.x) - 1;
-    }
+    if (threadIdx.x == 0) s_last = count_group_done(sched);
     __syncthreads();
     if (!s_last) return;
     for (int i = threadIdx.x; i < n; i += BS) close_state(states + i);
-    if (threadIdx.x < 9)
-        __hip_atomic_store(sched + kSchedStride * threadIdx.x, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    reset_sched(sched);
 }
 
 // One tile of the tile path: everything a work-group needs to sweep it, with
@@ -437,7 +547,7 @@ sl_status unpermute_flags(const DevMesh& m, const uint64_t* bits, int32_t iterat
 // X[0]).  Skipped on the device when the mesh's state is inactive.  bits:
 // nullable accept bits of this sweep (device labels, 64-bit words).
 sl_status launch_sweep_nodes(const DevMesh& m, int32_t parity, int32_t form, int32_t accept, int32_t block,
-                             MeshState* state, uint64_t* bits, hipStream_t st);
+                             MeshState* state, uint64_t* bits, int32_t* sched, hipStream_t st);
 
 // Queues one sweep of every tile in work[0..n_work) (any number of meshes,
 // all reading X[parity]).  bits: nullable, single-mesh runs only.

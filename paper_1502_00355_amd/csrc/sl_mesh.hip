@@ -199,7 +199,7 @@ struct sl_mesh {
     {
         if (tiles()) return sl::launch_sweep_tiles(launch(), parity, nullptr, st);
         if (class_tiles()) return sweep_classes(state, true, st);
-        const sl_status r = sl::launch_sweep_nodes(m, parity, o.form, o.accept, block, state, nullptr, st);
+        const sl_status r = sl::launch_sweep_nodes(m, parity, o.form, o.accept, block, state, nullptr, sched, st);
         return r ? r : sl::launch_advance(state, 1, st);
     }
 
@@ -268,10 +268,9 @@ sl_status handle_options(const sl_options* opts, sl_options* out, int32_t* wg_au
     sl_status r = check_options(o);
     if (r) return r;
     if (o.kernel == SL_KERNEL_RESIDENT) return fail(SL_EINVAL, "mesh handles do not run the resident kernel");
-    // automatic Form B: colour-class tiles where the mesh fits them, else
-    // the node kernel (the automatic choice of a one-call smooth would also
-    // consider the resident kernel)
-    if (o.kernel == SL_KERNEL_AUTO && o.form == SL_INPLACE_COLORED) o.kernel = SL_KERNEL_TILE;
+    // automatic Form B: the node kernel (the automatic choice of a one-call
+    // smooth would also consider the resident kernel, which handles do not run)
+    if (o.kernel == SL_KERNEL_AUTO && o.form == SL_INPLACE_COLORED) o.kernel = SL_KERNEL_NODE;
     *wg_auto = o.tile_wg_per_cu == 0 ? 1 : 0;
     if (o.form == SL_JACOBI) o.tile_nodes = resolve_tile_nodes(o);   // colour-class tiles size themselves
     o.tile_wg_per_cu = resolve_wg_per_cu(o);
@@ -617,7 +616,7 @@ sl_status sl_mesh_smooth_batch_async(sl_mesh* const* meshes, int32_t n_meshes, i
                     if ((r = h->sweep_classes(states + i, false, st))) return r;
                     continue;
                 }
-                if ((r = launch_sweep_nodes(h->m, parity, o.form, o.accept, h->block, states + i, nullptr, st)))
+                if ((r = launch_sweep_nodes(h->m, parity, o.form, o.accept, h->block, states + i, nullptr, sched, st)))
                     return r;
             }
             if (!all_tiles && (r = launch_advance(states, n_meshes, st))) return r;

@@ -229,7 +229,7 @@ struct HipExec {
                     continue;
                 }
                 r = launch_sweep_nodes(m, parity, opts.form, opts.accept, block, states + q->slot, nullptr,
-                                       st_compute);
+                                       sched, st_compute);
             }
             if (!r && !all_tiles) r = launch_advance(states, max_active, st_compute);
             parity ^= 1;
@@ -335,9 +335,9 @@ sl_status sl_server_create(const sl_server_config* cfg, const sl_options* opts, 
     // requests join a shared step of a few sweeps; the resident kernel runs
     // a mesh's sweeps all at once, which this schedule has no place for
     if (o.kernel == SL_KERNEL_RESIDENT) return fail(SL_EINVAL, "a server does not run the resident kernel");
-    // automatic: the tile path where a request fits it (Form B: colour-class
-    // tiles), else the node kernel
-    if (o.kernel == SL_KERNEL_AUTO) o.kernel = SL_KERNEL_TILE;
+    // automatic: Form A's tiles where a request fits them, else (and for
+    // Form B) the node kernel
+    if (o.kernel == SL_KERNEL_AUTO) o.kernel = o.form == SL_JACOBI ? SL_KERNEL_TILE : SL_KERNEL_NODE;
     // automatic launch shapes are fixed when the server starts: every
     // request of one work list has the same tile size (colour-class tiles
     // size themselves per request)

@@ -966,7 +966,10 @@ static int32_t tile_size_for(const sl_options& o, int32_t n)
 static bool wants_tiles(const sl_options& o, bool resident, bool class_tiles_ok)
 {
     if (o.kernel == SL_KERNEL_NODE || o.kernel == SL_KERNEL_LANES || resident) return false;
-    return o.form == SL_JACOBI || (class_tiles_ok && o.precision == SL_F64);
+    // Form B takes its colour-class tiles on request only: the node kernel
+    // sweeps it faster (each class phase gathers its neighbours through L2
+    // instead of staging halos several times longer than the class tile)
+    return o.form == SL_JACOBI || (o.kernel == SL_KERNEL_TILE && class_tiles_ok && o.precision == SL_F64);
 }
 
 size_t mesh_block_bytes(int32_t n, int64_t nnz, int64_t ninc, const sl_options& o, bool class_tiles_ok)

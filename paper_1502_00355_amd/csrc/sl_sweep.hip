@@ -121,6 +121,7 @@ struct SweepArgs {
     int32_t n_tiles, tiles_per_xcd; // work-group tiles; XCD-contiguous mapping
     MeshState* state;               // skip unless active; max displacement and count fold here
     uint64_t* bits;                 // nullable: this sweep's accept bits (device labels)
+    int32_t* sched;                 // [kTileSchedInts]: the launch's counters and per-group slots
 };
 
 // a / d correctly rounded for an integer count d in [1, 127] with y = 1/d
@@ -140,49 +141,17 @@ constexpr double kStepMin = 0x1p-1015;   // 128 x the smallest normal double
 constexpr int kNodeRow = 8;   // neighbour entries whose loads are in flight together
 constexpr int kNodeFan = 4;   // fan entries read together
 
-// The displacement maximum and accepted count of one work-group, folded
-// into the mesh's state with one atomic pair: every atomic on the state's
-// one address is serialised, so a group folds once per launch, not per tile.
-template <int BS>
-__device__ __forceinline__ void fold_group(MeshState* state, double d2, unsigned long long acc, double* s_d2,
-                                           unsigned long long* s_acc)
-{
-    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-    for (int off = 32; off > 0; off >>= 1) {
-        const double t = __shfl_xor(d2, off);
-        d2 = t > d2 ? t : d2;
-    }
-    if (lane == 0) {
-        s_d2[w] = d2;
-        s_acc[w] = acc;
-    }
-    __syncthreads();
-    if (tid == 0) {
-        double m = s_d2[0];
-        unsigned long long c = s_acc[0];
-        for (int q = 1; q < BS / 64; ++q) {
-            m = s_d2[q] > m ? s_d2[q] : m;
-            c += s_acc[q];
-        }
-        if (m > 0.0) atomicMax(&state->maxd_cur, static_cast<unsigned long long>(__double_as_longlong(m)));
-        if (c) atomicAdd(&state->acc_cur, c);
-    }
-}
-
 // Persistent work-groups over the launch's tiles (BLOCK consecutive nodes
 // each): the tiles are cut into 8 contiguous runs, one per XCD (work-groups
 // are dealt to the XCDs round-robin), so that neighbouring tiles share an L2.
 template <int BLOCK, int MAXV, bool SOA, bool GT>
 __global__ __launch_bounds__(BLOCK) void k_sweep(SweepArgs a)
 {
-    if (!a.state->active) return;
+    if (!a.state->active) return;   // the whole launch returns: no group counts
     const int xcd = static_cast<int>(blockIdx.x & 7), nw = static_cast<int>(gridDim.x >> 3);
     const int t_begin = xcd * a.tiles_per_xcd, t_end = min(t_begin + a.tiles_per_xcd, a.n_tiles);
-    if (t_begin + static_cast<int>(blockIdx.x >> 3) >= t_end) return;
 
     __shared__ double2 nb[MAXV][BLOCK];   // column tid: this work-item's neighbours
-    __shared__ double s_d2[BLOCK / 64];
-    __shared__ unsigned long long s_acc[BLOCK / 64];
     __shared__ double s_recip[kMaxValence + 1];
 
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
@@ -263,7 +232,8 @@ __global__ __launch_bounds__(BLOCK) void k_sweep(SweepArgs a)
             if (sh != 0 && (ball >> (64 - sh)) != 0ull) atomicOr(word + 1, ball >> (64 - sh));
         }
     }
-    fold_group<BLOCK>(a.state, run_d2, run_acc, s_d2, s_acc);
+    // every group folds, those without a tile too: the last one counts them all
+    fold_through_slots<BLOCK, false>(a.sched, a.state, run_d2, run_acc);
 }
 
 // Persistent grid: 8 XCDs x 32 CUs x the work-groups a CU holds (by the
@@ -273,7 +243,7 @@ __global__ __launch_bounds__(BLOCK) void k_sweep(SweepArgs a)
 int persistent_grid(int tiles_per_xcd, int block, size_t lds_bytes)
 {
     const int by_lds = static_cast<int>((160 * 1024) / std::max<size_t>(lds_bytes, 1));
-    const int per_cu = std::max(1, std::min(by_lds, 2048 / block));
+    const int per_cu = std::max(1, std::min({by_lds, 2048 / block, kTileMaxGroups / 256}));
     return 8 * std::min(tiles_per_xcd, 32 * per_cu);
 }
 
@@ -369,16 +339,13 @@ template <int W, int MAXV, bool SOA, bool GT>
 __global__ __launch_bounds__((lane_block<W, MAXV>())) void k_sweep_lanes(SweepArgs a)
 {
     constexpr int BS = lane_block<W, MAXV>(), G = BS / W, NPW = 64 / W;   // groups per work-group, per wave
-    if (!a.state->active) return;
+    if (!a.state->active) return;   // the whole launch returns: no group counts
     // persistent work-groups over tiles of G nodes, a contiguous run of
     // tiles per XCD, as in the node kernel
     const int xcd = static_cast<int>(blockIdx.x & 7), nw = static_cast<int>(gridDim.x >> 3);
     const int t_begin = xcd * a.tiles_per_xcd, t_end = min(t_begin + a.tiles_per_xcd, a.n_tiles);
-    if (t_begin + static_cast<int>(blockIdx.x >> 3) >= t_end) return;
 
     __shared__ double2 nb[G][MAXV + 1];   // one row per group; the pad spreads the rows over the banks
-    __shared__ double s_d2[BS / 64];
-    __shared__ unsigned long long s_acc[BS / 64];
     __shared__ double s_recip[kMaxValence + 1];
 
     const int tid = threadIdx.x, g = tid / W, j = tid % W, lane = tid & 63, wv = tid >> 6;
@@ -454,7 +421,7 @@ __global__ __launch_bounds__((lane_block<W, MAXV>())) void k_sweep_lanes(SweepAr
             if (sh != 0 && (nodes >> (64 - sh)) != 0ull) atomicOr(word + 1, nodes >> (64 - sh));
         }
     }
-    fold_group<BS>(a.state, run_d2, run_acc, s_d2, s_acc);
+    fold_through_slots<BS, false>(a.sched, a.state, run_d2, run_acc);
 }
 
 template <int W, int MAXV>
@@ -758,41 +725,13 @@ constexpr int kClassHalo = 8;    // halo positions per work-item at most (the bu
 constexpr int kClassWords = 4;   // row words, and fan words, per work-item at most
 
 struct ClassSweepArgs {
-    const TileWork* work;   // the tiles of one class (TileWork::tris holds the fan entries)
+    const TileWork* work;   // the tiles of one class of one mesh (TileWork::tris holds the fan entries)
     int32_t n_work, tiles_per_xcd;
     int32_t halo_cap, rows_cap, fans_cap;   // LDS: largest halo, padded row segment and fan list
-    MeshState* states;
+    MeshState* states;      // the mesh's state is states[work[0].mesh]
     uint64_t* bits;         // nullable: accept bits of this sweep (device labels)
+    int32_t* sched;         // [kTileSchedInts]: the launch's counters and per-group slots
 };
-
-// Folds a work-group's displacement maximum and accepted count into a
-// mesh's sweep state: one pair of device-scope atomics per work-group.
-template <int T>
-__device__ __forceinline__ void fold_state(MeshState* ms, double d2, unsigned long long acc, double* s_d2,
-                                           unsigned long long* s_acc)
-{
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    for (int off = 32; off > 0; off >>= 1) {
-        const double t = __shfl_xor(d2, off);
-        d2 = t > d2 ? t : d2;
-    }
-    if (lane == 0) {
-        s_d2[wv] = d2;
-        s_acc[wv] = acc;
-    }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        double mx = s_d2[0];
-        unsigned long long c = s_acc[0];
-        for (int q = 1; q < T / 64; ++q) {
-            mx = s_d2[q] > mx ? s_d2[q] : mx;
-            c += s_acc[q];
-        }
-        if (mx > 0.0) atomicMax(&ms->maxd_cur, static_cast<unsigned long long>(__double_as_longlong(mx)));
-        if (c) atomicAdd(&ms->acc_cur, c);
-    }
-    __syncthreads();
-}
 
 // Persistent work-groups: the class's tile list is cut into 8 contiguous
 // ranges, one per XCD (work-groups are dealt to the XCDs round-robin), so
@@ -843,8 +782,6 @@ template <int T, bool SOA, bool GT>
 __global__ __launch_bounds__(T) void k_sweep_class(ClassSweepArgs a)
 {
     extern __shared__ double2 cls_lds[];
-    __shared__ double s_d2[T / 64];
-    __shared__ unsigned long long s_acc[T / 64];
     __shared__ double s_recip[kMaxValence + 1];
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     for (int i = tid; i <= kMaxValence; i += T) s_recip[i] = i ? 1.0 / static_cast<double>(i) : 0.0;
@@ -858,15 +795,8 @@ __global__ __launch_bounds__(T) void k_sweep_class(ClassSweepArgs a)
     uint64_t* fans64 = reinterpret_cast<uint64_t*>(fans);
     double run_d2 = 0.0;
     unsigned long long run_acc = 0;
-    int mesh = -1;
     for (int tile = t_begin + static_cast<int>(blockIdx.x >> 3); tile < t_end; tile += nw) {
         const TileWork d = a.work[tile];
-        if (d.mesh != mesh) {
-            if (mesh >= 0) fold_state<T>(a.states + mesh, run_d2, run_acc, s_d2, s_acc);
-            run_d2 = 0.0;
-            run_acc = 0;
-            mesh = d.mesh;
-        }
         if (!a.states[d.mesh].active) continue;   // uniform: the whole group skips the tile
         double* X = static_cast<double*>(const_cast<void*>(d.X));   // buffer 0, in place
         const int nown = d.nown;
@@ -960,7 +890,7 @@ __global__ __launch_bounds__(T) void k_sweep_class(ClassSweepArgs a)
             if (sh != 0 && (ball >> (64 - sh)) != 0ull) atomicOr(word + 1, ball >> (64 - sh));
         }
     }
-    if (mesh >= 0) fold_state<T>(a.states + mesh, run_d2, run_acc, s_d2, s_acc);
+    fold_through_slots<T, false>(a.sched, a.states + a.work[0].mesh, run_d2, run_acc);
 }
 
 template <int T>
@@ -1004,6 +934,8 @@ sl_status launch_sweep_class(const TileLaunch& L, int32_t fans_cap, uint64_t* bi
         a.fans_cap = (fans_cap + 3) & ~3;
         a.states = L.states;
         a.bits = bits;
+        a.sched = L.sched;
+        if (!a.sched) return fail(SL_EINVAL, "internal: class tile launch without its counters");
         const size_t lds = class_lds_bytes(L.tile_nodes, L.halo_cap, L.rows_cap, fans_cap);
         // persistent: as many groups per CU as the LDS holds (at most
         // 2048 / T, or the option's count), 32 CUs per XCD, never more
@@ -1012,6 +944,7 @@ sl_status launch_sweep_class(const TileLaunch& L, int32_t fans_cap, uint64_t* bi
         int per_cu = std::min(fit, 2048 / L.tile_nodes);
         if (L.wg_per_cu > 0) per_cu = std::min(per_cu, static_cast<int>(L.wg_per_cu));
         const int grid = 8 * std::min(a.tiles_per_xcd, 32 * per_cu);
+        if (grid > kTileMaxGroups) return fail(SL_EINVAL, "internal: class launch of more groups than slots");
         const bool soa = L.layout == SL_SOA, gt = L.accept == SL_ACCEPT_GT;
         if (L.tile_nodes == 128) launch_class_t<128>(a, soa, gt, grid, lds, st);
         else if (L.tile_nodes == 256) launch_class_t<256>(a, soa, gt, grid, lds, st);
@@ -1030,9 +963,11 @@ sl_status launch_advance(MeshState* states, int32_t n, hipStream_t st)
 }
 
 sl_status launch_sweep_nodes(const DevMesh& m, int32_t parity, int32_t form, int32_t accept, int32_t block,
-                             MeshState* state, uint64_t* bits, hipStream_t st)
+                             MeshState* state, uint64_t* bits, int32_t* sched, hipStream_t st)
 {
+    if (!sched) return fail(SL_EINVAL, "internal: node launch without its counters");
     SweepArgs a{};
+    a.sched = sched;
     a.n = m.n;
     a.row_ptr = m.row_ptr;
     a.nbr = m.nbr;

@@ -100,7 +100,7 @@ struct TileSweepArgs {
     int32_t exit_if_inactive;  // all tiles are of one mesh: return at once if it has stopped
     MeshState* states;
     uint64_t* bits;            // nullable: accept bits of this sweep (single mesh)
-    int32_t* sched;            // [kTileSchedInts]: groups done, then one tile counter per XCD, kSchedStride apart
+    int32_t* sched;            // [kTileSchedInts]: the launch's counters and slots (sl_common.h)
     int32_t n_close;           // the last work-group closes the sweep of states[0..n_close)
     int32_t one_mesh;          // every tile is of one mesh: groups fold through their slots
 };
@@ -483,78 +483,18 @@ __device__ __forceinline__ void sweep_tiles(const TileSweepArgs& a, double& out_
     }
 }
 
-// The end of a launch over one mesh: each work-group writes its
-// displacement maximum and accepted count to its own slot (device-scope
-// stores, completed before the group's count, as close_launch's folds are),
-// and the last group to finish folds every slot into the mesh's state and
-// closes the sweep.  Thousands of atomics on the state's one address, which
-// the device serialises, become one per launch.
-template <int BS>
-__device__ __forceinline__ void close_one_mesh(const TileSweepArgs& a, double d2, unsigned long long acc)
-{
-    __shared__ double s_d2[BS / 64];
-    __shared__ unsigned long long s_acc[BS / 64];
-    __shared__ int s_last;
-    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-    unsigned long long* const slots = reinterpret_cast<unsigned long long*>(a.sched + kTileSlotsAt);
-    auto block_fold = [&](double& m, unsigned long long& c) {
-        for (int off = 32; off > 0; off >>= 1) {
-            const double t = __shfl_xor(m, off);
-            m = t > m ? t : m;
-            c += __shfl_xor(c, off);
-        }
-        __syncthreads();   // s_d2 / s_acc free
-        if (lane == 0) {
-            s_d2[wv] = m;
-            s_acc[wv] = c;
-        }
-        __syncthreads();
-        m = s_d2[0];
-        c = s_acc[0];
-        for (int q = 1; q < BS / 64; ++q) {
-            m = s_d2[q] > m ? s_d2[q] : m;
-            c += s_acc[q];
-        }
-    };
-    // acc is the wave's count on every lane: one lane per wave contributes
-    unsigned long long c = lane == 0 ? acc : 0ull;
-    block_fold(d2, c);
-    if (tid == 0) {
-        __hip_atomic_store(slots + 2 * blockIdx.x, static_cast<unsigned long long>(__double_as_longlong(d2)),
-                           __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        __hip_atomic_store(slots + 2 * blockIdx.x + 1, c, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
-        const int before = __hip_atomic_fetch_add(a.sched, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        s_last = before == static_cast<int>(gridDim.x) - 1;
-    }
-    __syncthreads();
-    if (!s_last) return;
-    double m = 0.0;
-    unsigned long long cnt = 0;
-    for (int g = tid; g < static_cast<int>(gridDim.x); g += BS) {
-        const double mg = __longlong_as_double(static_cast<long long>(
-            __hip_atomic_load(slots + 2 * g, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)));
-        m = mg > m ? mg : m;
-        cnt += __hip_atomic_load(slots + 2 * g + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    }
-    block_fold(m, cnt);
-    if (tid == 0) {
-        MeshState* ms = a.states + a.work[0].mesh;
-        if (m > 0.0) atomicMax(&ms->maxd_cur, static_cast<unsigned long long>(__double_as_longlong(m)));
-        if (cnt) atomicAdd(&ms->acc_cur, cnt);
-        for (int i = 0; i < a.n_close; ++i) close_state(a.states + i);
-    }
-    if (tid < 9) __hip_atomic_store(a.sched + kSchedStride * tid, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-
 template <int T, int BS, bool SOA, bool GT, typename R>
 __global__ __launch_bounds__(BS) void k_sweep_tile(TileSweepArgs a)
 {
     double d2;
     unsigned long long acc;
     sweep_tiles<T, BS, SOA, GT, R>(a, d2, acc);
-    if (a.one_mesh) close_one_mesh<BS>(a, d2, acc);
-    else close_launch<BS>(a.sched, a.states, a.n_close);
+    if (!a.one_mesh) {
+        close_launch<BS>(a.sched, a.states, a.n_close);
+    } else if (fold_through_slots<BS, true>(a.sched, a.states + a.work[0].mesh, d2, acc) && threadIdx.x == 0) {
+        // the last group (its fold into the state came from work-item 0)
+        for (int i = 0; i < a.n_close; ++i) close_state(a.states + i);
+    }
 }
 
 constexpr int kTileBS = 256;

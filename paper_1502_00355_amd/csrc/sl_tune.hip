@@ -173,7 +173,7 @@ sl_status tune_nodes(const sl_mesh_desc* meshes, const std::vector<int32_t>& sam
                             [&](int32_t parity) {
                                 for (size_t k = 0; k < p.meshes.size(); ++k) {
                                     const sl_status rr = launch_sweep_nodes(p.meshes[k], parity, o.form, o.accept,
-                                                                            bs, p.states + k, nullptr, st);
+                                                                            bs, p.states + k, nullptr, p.sched, st);
                                     if (rr) return rr;
                                 }
                                 return SL_OK;
@@ -218,7 +218,7 @@ sl_status tune_lanes(const sl_mesh_desc* meshes, const std::vector<int32_t>& sam
                                                 for (size_t k = 0; k < p.meshes.size(); ++k) {
                                                     const sl_status rr =
                                                         launch_sweep_nodes(p.meshes[k], parity, base.form, base.accept,
-                                                                           0, p.states + k, nullptr, st);
+                                                                           0, p.states + k, nullptr, p.sched, st);
                                                     if (rr) return rr;
                                                 }
                                                 return SL_OK;

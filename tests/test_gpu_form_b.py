@@ -47,7 +47,7 @@ def run_gpu(m, iters, tol=0.0, **opts):
 
 def check(m, iters, tol=0.0, accept="ge", kernel="tile", **opts):
     note("form B %s iters=%d tol=%g accept=%s %s" % (m.name, iters, tol, accept, opts))
-    X, rep, F = run_gpu(m, iters, tol, accept=accept, **opts)
+    X, rep, F = run_gpu(m, iters, tol, accept=accept, kernel=kernel, **opts)
     assert rep.kernel_used == sl.KERNELS[kernel]
     ref = oracle.smooth(m, iters, tol=tol, accept_gt=accept == "gt", form="colored")
     assert rep.n_colors == int(ref.colors.max()) + 1
@@ -125,7 +125,7 @@ def test_form_b_class_tiles_invariants():
     mm = m.copy()
     prev = worst(mm.coords)
     for _ in range(5):
-        X, rep, _ = run_gpu(mm, 1)
+        X, rep, _ = run_gpu(mm, 1, kernel="tile")
         assert rep.kernel_used == sl.KERNELS["tile"]
         assert (X[b] == m.coords[b]).all() and np.isfinite(X).all()
         mm.coords = X

@@ -79,8 +79,8 @@ def test_calls_continue_where_the_last_stopped(splits):
     assert rep.kernel_used == sl.KERNELS["tile"]
 
 
-@pytest.mark.parametrize("opts", [{"layout": "soa"}, {"form": "colored"}, {"precision": "f32"},
-                                  {"kernel": "node"}, {"accept": "gt"}, {"reorder": "none"}])
+@pytest.mark.parametrize("opts", [{"layout": "soa"}, {"form": "colored"}, {"form": "colored", "kernel": "tile"},
+                                  {"precision": "f32"}, {"kernel": "node"}, {"accept": "gt"}, {"reorder": "none"}])
 def test_options(opts):
     m = meshgen.permute_mesh(meshgen.make_grid(45, "random", 0.4, 202), 3)
     note("handle options %s" % opts)
@@ -97,15 +97,17 @@ def test_options(opts):
     assert rep.iterations_run == 21
     assert (X == r.coords).all()
     if opts.get("form") == "colored":
-        assert rep.kernel_used == sl.KERNELS["tile"] and rep.n_colors > 0
+        # automatic Form B: the node kernel; colour-class tiles on request
+        assert rep.kernel_used == sl.KERNELS[opts.get("kernel", "node")] and rep.n_colors > 0
 
 
 def test_form_b_handles_on_class_tiles_and_node_kernel_batched():
-    """Form B handles: a grid on colour-class tiles, a Delaunay mesh, and a
-    mesh of stars too dense for tiles on the node kernel, smoothed alone and
-    batched; every one equals the oracle's coloured sweeps."""
+    """Form B handles asking for colour-class tiles: a grid and a Delaunay
+    mesh on them, and a mesh of stars too dense for tiles on the node kernel,
+    smoothed alone and batched; every one equals the oracle's coloured
+    sweeps."""
     ms = [meshgen.make_grid(70, "random", 0.4, 31), meshgen.make_delaunay(4000, 32), _many_stars(300, 20, 33)]
-    hs = [sl.Mesh(m, form="colored") for m in ms]
+    hs = [sl.Mesh(m, form="colored", kernel="tile") for m in ms]
     try:
         kinds = [h.report().kernel_used for h in hs]
         assert kinds == [sl.KERNELS["tile"], sl.KERNELS["tile"], sl.KERNELS["node"]], kinds

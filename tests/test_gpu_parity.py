@@ -691,30 +691,34 @@ def test_server_mix_equals_single_and_oracle():
         assert t.submitted_s <= t.admitted_s <= t.started_s <= t.done_s
 
 
-def test_batch_form_b_on_class_tiles_resident_and_node():
-    """A Form B batch: meshes on colour-class tiles, a small mesh on the
-    resident kernel and a mesh too dense for tiles on the node kernel, in
+@pytest.mark.parametrize("kernel,kinds,resident", [("auto", ("node", "node", "resident", "node"), 1),
+                                                   ("tile", ("tile", "tile", "tile", "node"), 0)])
+def test_batch_form_b_on_class_tiles_resident_and_node(kernel, kinds, resident):
+    """A Form B batch: automatically, the small mesh on the resident kernel
+    and the others on the node kernel; asking for tiles, meshes on
+    colour-class tiles and a mesh too dense for them on the node kernel, in
     one call; every one equals the oracle's coloured sweeps."""
     ms = [meshgen.make_grid(70, "random", 0.4, 41), meshgen.make_delaunay(5000, 42),
           meshgen.make_grid(20, "random", 0.4, 43), _many_stars(300, 20, 44)]
-    outs, reps, br = sl.batch_smooth(ms, 9, form="colored")
-    assert [r.kernel_used for r in reps] == [sl.KERNELS[k] for k in ("tile", "tile", "resident", "node")]
-    assert br.meshes_resident == 1
+    outs, reps, br = sl.batch_smooth(ms, 9, form="colored", kernel=kernel)
+    assert [r.kernel_used for r in reps] == [sl.KERNELS[k] for k in kinds]
+    assert br.meshes_resident == resident
     for m, X, rep in zip(ms, outs, reps):
         ref = oracle.smooth(m, 9, form="colored")
         assert (X == ref.coords).all(), m.name
         assert rep.accepted_total == int(ref.accepted.sum()), m.name
 
 
-def test_server_form_b_mix():
-    """Form B requests: meshes on colour-class tiles of both automatic sizes
-    (256 below 2^20 nodes) and a mesh on the node kernel, sharing steps:
-    each result and accepted count equals the oracle's coloured sweeps."""
+@pytest.mark.parametrize("kernel", ["auto", "tile"])
+def test_server_form_b_mix(kernel):
+    """Form B requests sharing steps, on the node kernel (automatic) or on
+    colour-class tiles of both automatic sizes (asked for): each result and
+    accepted count equals the oracle's coloured sweeps."""
     ms = [meshgen.make_grid(n, "random", 0.4, 900 + n) for n in (30, 90, 200)]
     ms.append(meshgen.make_delaunay(3000, 91))
-    ms.append(_ring_star(24, 5))                                   # node kernel
+    ms.append(_ring_star(24, 5))                                   # one node of valence 24
     jobs = [(7, 0.0), (12, 0.0), (20, 0.0), (400, 1e-6), (5, 0.0)]
-    with sl.Server(form="colored", sweeps_per_step=4) as srv:
+    with sl.Server(form="colored", sweeps_per_step=4, kernel=kernel) as srv:
         ids = [srv.submit(m, it, tol) for m, (it, tol) in zip(ms, jobs)]
         res = [srv.wait(i) for i in ids]
     for m, (it, tol), r in zip(ms, jobs, res):
@@ -723,7 +727,8 @@ def test_server_form_b_mix():
         assert r.report.iterations_run == ref.iterations_run, m.name
         assert (r.coords == ref.coords).all(), m.name
         assert r.report.accepted_total == int(ref.accepted.sum()), m.name
-    assert [r.report.kernel_used for r in res[:4]] == [sl.KERNELS["tile"]] * 4
+    want = "tile" if kernel == "tile" else "node"
+    assert [r.report.kernel_used for r in res] == [sl.KERNELS[want]] * 5
 
 
 def test_server_cancel_deadline_budget_and_bad_input():
