@@ -263,36 +263,52 @@ def run_single(args, sl, torch, name=None, steps=None, warmup=None, f32=None, au
     return out, m
 
 
+KERNEL_NAMES = {1: "node", 2: "tile", 3: "resident", 4: "lanes"}
+
+
 def run_form_b(args, sl, torch, m=None):
     """Form B (eq. (3): coloured, in place) on the 16.8M-node grid, 100
     sweeps per step as the headline's Form A, with the per-sweep time of the
-    sweep kernel launches beside Form A's."""
+    sweep kernel launches beside Form A's; then every sweep kernel the
+    library has on the same mesh and job: Form A's tile kernel, the node
+    kernel, the lane-group kernel at widths 4, 8 and 16, and Form B's
+    automatic choice (the node kernel) beside its colour-class tiles."""
     if m is None:
         m, _ = workload("grid4096")
     iters, steps = 100, max(1, min(args.steps, 5))
     dev = sl.to_device(m, "cuda:0")
     X0 = dev[0].clone()
     work = torch.empty_like(X0)
+    cases = [("form_b", "colored", {}), ("form_a", "jacobi", {}),
+             ("form_b_class_tiles", "colored", {"kernel": "tile"}),
+             ("form_a_node", "jacobi", {"kernel": "node"}),
+             ("form_a_lanes4", "jacobi", {"kernel": "lanes", "lane_width": 4}),
+             ("form_a_lanes8", "jacobi", {"kernel": "lanes", "lane_width": 8}),
+             ("form_a_lanes16", "jacobi", {"kernel": "lanes", "lane_width": 16}),
+             ("form_b_lanes4", "colored", {"kernel": "lanes", "lane_width": 4})]
     res = {}
-    for form in ("colored", "jacobi"):
+    for name, form, kw in cases:
         best = None
         for k in range(steps + 1):
             work.copy_(X0)
             torch.cuda.synchronize()
             t = time.perf_counter()
-            r = sl.smooth_mesh_device(work, *dev[1:], iterations=iters, form=form)
+            r = sl.smooth_mesh_device(work, *dev[1:], iterations=iters, form=form, **kw)
             torch.cuda.synchronize()
             el = time.perf_counter() - t
             if k and (best is None or r.sweep_ms < best[1].sweep_ms):
                 best = (el, r)
         el, r = best
-        res[form] = {"ms_per_step": el * 1e3, "sweep_ms_per_sweep": r.sweep_ms / iters, "setup_ms": r.setup_ms,
-                     "kernel": {1: "node", 2: "tile", 3: "resident"}.get(r.kernel_used, "?"), "colors": r.n_colors,
+        res[name] = {"ms_per_step": el * 1e3, "sweep_ms_per_sweep": r.sweep_ms / iters, "setup_ms": r.setup_ms,
+                     "kernel": KERNEL_NAMES.get(r.kernel_used, "?"), "colors": r.n_colors,
                      "sweep_node_updates_per_s": m.n_interior * iters / (r.sweep_ms / 1e3)}
+        if kw.get("lane_width"):
+            res[name]["lane_width"] = kw["lane_width"]
         log("%s: %.4f ms per sweep (%s kernel, %d colours), setup %.2f ms" %
-            (form, r.sweep_ms / iters, res[form]["kernel"], r.n_colors, r.setup_ms))
-    return {"workload": m.name, "sweeps": iters, "form_b": res["colored"], "form_a": res["jacobi"],
-            "b_over_a_sweep_time": res["colored"]["sweep_ms_per_sweep"] / res["jacobi"]["sweep_ms_per_sweep"]}
+            (name, r.sweep_ms / iters, res[name]["kernel"], r.n_colors, r.setup_ms))
+    return {"workload": m.name, "sweeps": iters, "form_b": res["form_b"], "form_a": res["form_a"],
+            "b_over_a_sweep_time": res["form_b"]["sweep_ms_per_sweep"] / res["form_a"]["sweep_ms_per_sweep"],
+            "kernels": {k: v for k, v in res.items() if k not in ("form_a", "form_b")}}
 
 
 def run_layouts(args, sl, torch):
