@@ -281,8 +281,8 @@ sl_status run_device(double* coords, int32_t n, const int32_t* nbr_ptr, const in
             return SL_OK;
         }
         if (tiles) return launch_sweep_tiles(L, s & 1, bits, on);
-        const sl_status rr = launch_sweep_nodes(cs.m, s & 1, o.form, o.accept, block, cs.state, bits, cs.sched, on);
-        return rr ? rr : launch_advance(cs.state, 1, on);
+        // the sweep's last launch closes it
+        return launch_sweep_nodes(cs.m, s & 1, o.form, o.accept, block, cs.state, bits, cs.sched, on, true);
     };
 
     // The sweep loop runs in chunks of kSweepChunk sweeps; a whole chunk is

@@ -545,9 +545,11 @@ sl_status unpermute_flags(const DevMesh& m, const uint64_t* bits, int32_t iterat
 // Queues one Jacobi or coloured sweep of a single mesh on the node path
 // (Form A reads X[parity], writes X[parity^1]; Form B works in place in
 // X[0]).  Skipped on the device when the mesh's state is inactive.  bits:
-// nullable accept bits of this sweep (device labels, 64-bit words).
+// nullable accept bits of this sweep (device labels, 64-bit words).  close:
+// the sweep's last launch also closes it (no k_advance after it); else the
+// caller closes it.
 sl_status launch_sweep_nodes(const DevMesh& m, int32_t parity, int32_t form, int32_t accept, int32_t block,
-                             MeshState* state, uint64_t* bits, int32_t* sched, hipStream_t st);
+                             MeshState* state, uint64_t* bits, int32_t* sched, hipStream_t st, bool close = false);
 
 // Queues one sweep of every tile in work[0..n_work) (any number of meshes,
 // all reading X[parity]).  bits: nullable, single-mesh runs only.

@@ -199,8 +199,7 @@ struct sl_mesh {
     {
         if (tiles()) return sl::launch_sweep_tiles(launch(), parity, nullptr, st);
         if (class_tiles()) return sweep_classes(state, true, st);
-        const sl_status r = sl::launch_sweep_nodes(m, parity, o.form, o.accept, block, state, nullptr, sched, st);
-        return r ? r : sl::launch_advance(state, 1, st);
+        return sl::launch_sweep_nodes(m, parity, o.form, o.accept, block, state, nullptr, sched, st, true);
     }
 
     // A chunk of kHandleChunk sweeps starting from buffer p, captured once.

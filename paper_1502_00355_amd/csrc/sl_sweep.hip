@@ -122,7 +122,20 @@ struct SweepArgs {
     MeshState* state;               // skip unless active; max displacement and count fold here
     uint64_t* bits;                 // nullable: this sweep's accept bits (device labels)
     int32_t* sched;                 // [kTileSchedInts]: the launch's counters and per-group slots
+    int32_t close;                  // 1: the launch's last group closes the sweep of *state
 };
+
+// The end of a node-path launch: the groups' folds, and, when the launch
+// closes the sweep, the close by its last group (in place of a k_advance).
+template <int BS>
+__device__ __forceinline__ void finish_node_launch(const SweepArgs& a, double d2, unsigned long long acc)
+{
+    if (a.close) {
+        if (fold_through_slots<BS, true>(a.sched, a.state, d2, acc) && threadIdx.x == 0) close_state(a.state);
+    } else {
+        fold_through_slots<BS, false>(a.sched, a.state, d2, acc);
+    }
+}
 
 // a / d correctly rounded for an integer count d in [1, 127] with y = 1/d
 // correctly rounded, while the quotient is a normal number (Markstein's
@@ -233,7 +246,7 @@ __global__ __launch_bounds__(BLOCK) void k_sweep(SweepArgs a)
         }
     }
     // every group folds, those without a tile too: the last one counts them all
-    fold_through_slots<BLOCK, false>(a.sched, a.state, run_d2, run_acc);
+    finish_node_launch<BLOCK>(a, run_d2, run_acc);
 }
 
 // Persistent grid: 8 XCDs x 32 CUs x the work-groups a CU holds (by the
@@ -421,7 +434,7 @@ __global__ __launch_bounds__((lane_block<W, MAXV>())) void k_sweep_lanes(SweepAr
             if (sh != 0 && (nodes >> (64 - sh)) != 0ull) atomicOr(word + 1, nodes >> (64 - sh));
         }
     }
-    fold_through_slots<BS, false>(a.sched, a.state, run_d2, run_acc);
+    finish_node_launch<BS>(a, run_d2, run_acc);
 }
 
 template <int W, int MAXV>
@@ -938,10 +951,10 @@ sl_status launch_sweep_class(const TileLaunch& L, int32_t fans_cap, uint64_t* bi
         if (!a.sched) return fail(SL_EINVAL, "internal: class tile launch without its counters");
         const size_t lds = class_lds_bytes(L.tile_nodes, L.halo_cap, L.rows_cap, fans_cap);
         // persistent: as many groups per CU as the LDS holds (at most
-        // 2048 / T, or the option's count), 32 CUs per XCD, never more
-        // groups on an XCD than it has tiles
+        // 2048 / T, at most the 8 a launch has slots for, or the option's
+        // count), 32 CUs per XCD, never more groups on an XCD than it has tiles
         const int fit = std::max(1, static_cast<int>(kTileLdsLimit / std::max<size_t>(lds, 1)));
-        int per_cu = std::min(fit, 2048 / L.tile_nodes);
+        int per_cu = std::min({fit, 2048 / L.tile_nodes, kTileMaxGroups / 256});
         if (L.wg_per_cu > 0) per_cu = std::min(per_cu, static_cast<int>(L.wg_per_cu));
         const int grid = 8 * std::min(a.tiles_per_xcd, 32 * per_cu);
         if (grid > kTileMaxGroups) return fail(SL_EINVAL, "internal: class launch of more groups than slots");
@@ -963,9 +976,16 @@ sl_status launch_advance(MeshState* states, int32_t n, hipStream_t st)
 }
 
 sl_status launch_sweep_nodes(const DevMesh& m, int32_t parity, int32_t form, int32_t accept, int32_t block,
-                             MeshState* state, uint64_t* bits, int32_t* sched, hipStream_t st)
+                             MeshState* state, uint64_t* bits, int32_t* sched, hipStream_t st, bool close)
 {
     if (!sched) return fail(SL_EINVAL, "internal: node launch without its counters");
+    // the launch that closes the sweep: Form A's one, or Form B's last
+    // non-empty class; with no free node, a k_advance
+    int last = -1;
+    if (form == SL_JACOBI) last = m.n_free > 0 ? 0 : -1;
+    else
+        for (int c = 0; c < m.n_colors; ++c)
+            if (m.color_start_h[c + 1] > m.color_start_h[c]) last = c;
     SweepArgs a{};
     a.sched = sched;
     a.n = m.n;
@@ -981,6 +1001,7 @@ sl_status launch_sweep_nodes(const DevMesh& m, int32_t parity, int32_t form, int
         a.Xout = static_cast<double*>(m.X[(parity + 1) & 1]);
         a.k_begin = 0;
         a.k_end = m.n_free;
+        a.close = close && last == 0 ? 1 : 0;
         if (m.lane_width > 0) launch_lanes(a, m.max_deg, m.lane_width, soa, gt, st);
         else launch_range(a, m.max_deg, block, soa, gt, st);
     } else {
@@ -989,11 +1010,13 @@ sl_status launch_sweep_nodes(const DevMesh& m, int32_t parity, int32_t form, int
         for (int c = 0; c < m.n_colors; ++c) {
             a.k_begin = m.color_start_h[c];
             a.k_end = m.color_start_h[c + 1];
+            a.close = close && c == last ? 1 : 0;
             if (m.lane_width > 0) launch_lanes(a, m.max_deg, m.lane_width, soa, gt, st);
             else launch_range(a, m.max_deg, block, soa, gt, st);
         }
     }
     SL_HIP(hipGetLastError());
+    if (close && last < 0) return launch_advance(state, 1, st);
     return SL_OK;
 }
 

@@ -111,6 +111,15 @@ def test_form_b_class_tiles_1024_permuted():
     check(m, 30)
 
 
+def test_form_b_small_class_tiles_on_a_large_mesh():
+    """128-node class tiles on a 1200 x 1200 grid: its largest class has
+    more tiles than a launch has work-groups (at most 2,048), so the groups
+    take several tiles each and fold once per launch."""
+    m = meshgen.make_grid(1200, "random", 0.4, 70)
+    X, rep = check(m, 3, tile_nodes=128)
+    assert rep.tile_nodes == 128
+
+
 def test_form_b_class_tiles_invariants():
     """Boundary fixed, connectivity untouched, and the mesh-wide worst
     quality never drops over a coloured sweep."""
