@@ -46,6 +46,16 @@ enum : uint32_t {
 };
 constexpr uint32_t kValErrors = 0xFFFFu;   // the bits above that reject the input
 constexpr int kMaxValence = 127;   // 7-bit neighbour slots in a fan entry
+// A node-path fan longer than kGroupFan entries keeps its incidence order:
+// its bounds read kFanUngrouped.
+constexpr int kGroupFan = 32;
+constexpr uint32_t kFanUngrouped = 0xFFFFFFFFu;
+// Meshes of at least this many free nodes keep their fans ungrouped (no
+// bounds array): there the 4 bytes per node of bounds cost the sweep more
+// than the grouping saves (4096^2 grid, Form B: 0.830 against 0.812 ms per
+// sweep; 1024^2: 0.097 against 0.101 ms; 100K Delaunay points: 0.081
+// against 0.084 ms).
+constexpr int32_t kGroupFansBelow = 1 << 22;
 
 // Statistics gathered during validation.
 struct ValStats {
@@ -380,7 +390,8 @@ struct DevMesh {
     int32_t* row_ptr = nullptr;     // [n_free+1]
     int32_t* nbr = nullptr;         // [nnz_free] device labels (node path)
     int32_t* fan_ptr = nullptr;     // [n_free+1]
-    uint16_t* fan = nullptr;        // [ninc_free] (node path)
+    uint16_t* fan = nullptr;        // [ninc_free] (node path), grouped by stored position where fan_split is set
+    uint32_t* fan_split = nullptr;  // [n_free] (node path, below kGroupFansBelow free nodes): the groups' bounds, or kFanUngrouped
     int32_t color_start_h[130] = {0};    // colour class c: device labels [cs[c], cs[c+1])
     int32_t precision = SL_F64;          // element type of X: double, or float for SL_F32
     void* X[2] = {nullptr, nullptr};     // one block of 4n elements: X[1] = X[0] + 2n;

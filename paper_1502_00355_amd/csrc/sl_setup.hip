@@ -778,6 +778,42 @@ __global__ __launch_bounds__(kBS) void k_rows_fans(const int32_t* __restrict__ p
     }
 }
 
+// Groups each free node's fan entries by the node's position p in the
+// triangle's stored order (0, then 1, then 2; incidence order inside a
+// group) and stores the groups' bounds, c0 | (c0 + c1) << 16 for c_p entries
+// of position p, so that the node kernel evaluates each group with the
+// position fixed at compile time.  A minimum over a fan is exact, so the
+// order of its entries changes no result.  Fans longer than kGroupFan keep
+// their order and get kFanUngrouped.  The entries are held in registers.
+__global__ __launch_bounds__(kBS) void k_fan_group(const int32_t* __restrict__ fan_ptr, uint16_t* __restrict__ fan,
+                                                   uint32_t* __restrict__ split, int32_t n_free)
+{
+    const int64_t k = static_cast<int64_t>(blockIdx.x) * kBS + threadIdx.x;
+    if (k >= n_free) return;
+    const int32_t f0 = fan_ptr[k], n = fan_ptr[k + 1] - f0;
+    if (n > kGroupFan) {
+        split[k] = kFanUngrouped;
+        return;
+    }
+    uint32_t e[kGroupFan];
+    int c0 = 0, c1 = 0;
+#pragma unroll
+    for (int j = 0; j < kGroupFan; ++j) {
+        e[j] = j < n ? fan[f0 + j] : 3u;   // 3: no entry
+        c0 += (e[j] & 3u) == 0u;
+        c1 += (e[j] & 3u) == 1u;
+    }
+    int q0 = f0, q1 = f0 + c0, q2 = f0 + c0 + c1;
+#pragma unroll
+    for (int j = 0; j < kGroupFan; ++j) {
+        const uint32_t p = e[j] & 3u;
+        if (p == 3u) continue;
+        const int at = p == 0u ? q0++ : (p == 1u ? q1++ : q2++);
+        fan[at] = static_cast<uint16_t>(e[j]);
+    }
+    split[k] = static_cast<uint32_t>(c0) | (static_cast<uint32_t>(c0 + c1) << 16);
+}
+
 // Both buffers of the ping-pong pair start at the caller's positions,
 // rounded to R (float for the single-precision form).
 template <typename R>
@@ -983,7 +1019,8 @@ size_t mesh_block_bytes(int32_t n, int64_t nnz, int64_t ninc, const sl_options& 
     const size_t un = static_cast<size_t>(n);
     size_t pb = 2 * Arena::piece(4 * un) + 2 * Arena::piece(4 * (un + 1)) + Arena::piece(4 * un * rb);
     pb += want_tiles ? tile_bytes(n, nnz, ninc, tile_size_for(o, n), o.form != SL_JACOBI)
-                     : Arena::piece(4 * static_cast<size_t>(nnz)) + Arena::piece(2 * static_cast<size_t>(ninc));
+                     : Arena::piece(4 * static_cast<size_t>(nnz)) + Arena::piece(2 * static_cast<size_t>(ninc)) +
+                           Arena::piece(4 * un);
     return pb;
 }
 
@@ -1186,10 +1223,14 @@ sl_status setup_mesh(const SetupArgs& a, const sl_options& o, DevMesh& m, int32_
     if (m.tile_nodes == 0) {
         // (a mesh that did not fit the tile path gave the tile arrays' room back,
         // which bounds this)
-        if ((r = persist.take(&m.nbr, m.nnz_free)) || (r = persist.take(&m.fan, m.ninc_free))) return r;
+        const bool group = m.n_free > 0 && m.n_free < kGroupFansBelow;
+        if ((r = persist.take(&m.nbr, m.nnz_free)) || (r = persist.take(&m.fan, m.ninc_free)) ||
+            (group && (r = persist.take(&m.fan_split, m.n_free))))
+            return r;
         if (m.n_free > 0)
             k_rows_fans<<<gf, kBS, 0, st>>>(m.perm, m.new_of_old, m.n_free, a.nbr_ptr, a.nbr_idx, a.tri_ptr,
                                             a.tri_idx, a.tris, m.row_ptr, m.nbr, m.fan_ptr, m.fan);
+        if (group) k_fan_group<<<gf, kBS, 0, st>>>(m.fan_ptr, m.fan, m.fan_split, m.n_free);
     }
     SL_HIP(hipGetLastError());
     return SL_OK;

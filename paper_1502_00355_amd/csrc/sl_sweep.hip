@@ -116,7 +116,8 @@ struct SweepArgs {
     const int32_t* row_ptr;
     const int32_t* nbr;
     const int32_t* fan_ptr;
-    const uint16_t* fan;
+    const uint16_t* fan;            // each node's entries grouped by stored position
+    const uint32_t* fan_split;      // nullable: the groups' bounds per node, or kFanUngrouped
     int32_t k_begin, k_end;         // device labels handled by this launch
     int32_t n_tiles, tiles_per_xcd; // work-group tiles; XCD-contiguous mapping
     MeshState* state;               // skip unless active; max displacement and count fold here
@@ -153,6 +154,32 @@ constexpr double kStepMin = 0x1p-1015;   // 128 x the smallest normal double
 
 constexpr int kNodeRow = 8;   // neighbour entries whose loads are in flight together
 constexpr int kNodeFan = 4;   // fan entries read together
+
+// The fan entries [g_begin, g_end) of one node, all of stored position P,
+// a few at a time with clamped indices so that their loads overlap; the
+// vertices come from the work-item's LDS column.
+template <int P, int MAXV, int BLOCK>
+__device__ __forceinline__ void node_fan_range(int g_begin, int g_end, const uint16_t* fan,
+                                               const double2 (*nb)[BLOCK], int tid, const double2 o, const double2 c,
+                                               double& qo, double& qn)
+{
+    for (int g0 = g_begin; g0 < g_end; g0 += kNodeFan) {
+        uint32_t e[kNodeFan];
+#pragma unroll
+        for (int u = 0; u < kNodeFan; ++u) e[u] = fan[min(g0 + u, g_end - 1)];
+#pragma unroll
+        for (int u = 0; u < kNodeFan; ++u) {
+            if (g0 + u < g_end) {
+                const double2 va = nb[(e[u] >> 2) & 127u][tid];
+                const double2 vb = nb[(e[u] >> 9) & 127u][tid];
+                double v, w;
+                fan_qualities_p<P>(o, c, va, vb, v, w);
+                if (v < qo) qo = v;
+                if (w < qn) qn = w;
+            }
+        }
+    }
+}
 
 // Persistent work-groups over the launch's tiles (BLOCK consecutive nodes
 // each): the tiles are cut into 8 contiguous runs, one per XCD (work-groups
@@ -209,20 +236,30 @@ __global__ __launch_bounds__(BLOCK) void k_sweep(SweepArgs a)
             }
         }
         double qo = INFINITY, qn = INFINITY;
-        for (int g0 = f0; g0 < f1; g0 += kNodeFan) {
-            uint32_t e[kNodeFan];
+        const double2 c = make_double2(cx, cy);
+        const uint32_t sp = a.fan_split ? a.fan_split[kk] : kFanUngrouped;   // a uniform test
+        if (sp != kFanUngrouped) {
+            // entries with p = 0 in [f0, b1), p = 1 in [b1, b2), p = 2 in [b2, f1)
+            const int b1 = f0 + static_cast<int>(sp & 0xFFFFu), b2 = f0 + static_cast<int>(sp >> 16);
+            node_fan_range<0, MAXV, BLOCK>(f0, b1, a.fan, nb, tid, o, c, qo, qn);
+            node_fan_range<1, MAXV, BLOCK>(b1, b2, a.fan, nb, tid, o, c, qo, qn);
+            node_fan_range<2, MAXV, BLOCK>(b2, f1, a.fan, nb, tid, o, c, qo, qn);
+        } else {
+            for (int g0 = f0; g0 < f1; g0 += kNodeFan) {
+                uint32_t e[kNodeFan];
 #pragma unroll
-            for (int u = 0; u < kNodeFan; ++u) e[u] = a.fan[min(g0 + u, f1 - 1)];
+                for (int u = 0; u < kNodeFan; ++u) e[u] = a.fan[min(g0 + u, f1 - 1)];
 #pragma unroll
-            for (int u = 0; u < kNodeFan; ++u) {
-                if (g0 + u < f1) {
-                    const int p = static_cast<int>(e[u] & 3u);
-                    const double2 va = nb[(e[u] >> 2) & 127u][tid];
-                    const double2 vb = nb[(e[u] >> 9) & 127u][tid];
-                    double v, wq;
-                    fan_qualities(p, o, make_double2(cx, cy), va, vb, v, wq);
-                    if (v < qo) qo = v;
-                    if (wq < qn) qn = wq;
+                for (int u = 0; u < kNodeFan; ++u) {
+                    if (g0 + u < f1) {
+                        const int p = static_cast<int>(e[u] & 3u);
+                        const double2 va = nb[(e[u] >> 2) & 127u][tid];
+                        const double2 vb = nb[(e[u] >> 9) & 127u][tid];
+                        double v, wq;
+                        fan_qualities(p, o, c, va, vb, v, wq);
+                        if (v < qo) qo = v;
+                        if (wq < qn) qn = wq;
+                    }
                 }
             }
         }
@@ -993,6 +1030,7 @@ sl_status launch_sweep_nodes(const DevMesh& m, int32_t parity, int32_t form, int
     a.nbr = m.nbr;
     a.fan_ptr = m.fan_ptr;
     a.fan = m.fan;
+    a.fan_split = m.fan_split;
     a.state = state;
     a.bits = bits;
     const bool soa = m.layout == SL_SOA, gt = accept == SL_ACCEPT_GT;

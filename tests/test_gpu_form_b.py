@@ -120,6 +120,15 @@ def test_form_b_small_class_tiles_on_a_large_mesh():
     assert rep.tile_nodes == 128
 
 
+@pytest.mark.parametrize("side", [1024, 2100])
+def test_form_b_node_kernel_grouped_and_ungrouped_fans(side):
+    """Form B's automatic choice, the node kernel: on the 1024 x 1024 grid
+    with each node's fan grouped by stored position, on the 2100 x 2100 grid
+    (4.4M free nodes, above the grouping's limit) in incidence order."""
+    m = meshgen.make_grid(side, "random", 0.4, 71)
+    X, rep = check(m, 3, kernel="node")
+
+
 def test_form_b_class_tiles_invariants():
     """Boundary fixed, connectivity untouched, and the mesh-wide worst
     quality never drops over a coloured sweep."""
