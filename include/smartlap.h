@@ -123,7 +123,8 @@ typedef struct {
     int32_t block_size;  /* node kernel work-group size: 0 = automatic, else 64/128/256 */
     int32_t kernel;      /* sl_kernel; results do not depend on it */
     int32_t tile_nodes;      /* free nodes per tile on the tile path.  Form A: 0 = automatic (the
-                              * value sl_autotune chose on this device, else 512), or 256 or 512.
+                              * value sl_autotune chose on this device, else 512; a one-call
+                              * smooth takes 256 on meshes of fewer than 2^19 nodes), or 256 or 512.
                               * Form B's colour-class tiles: 0 = automatic (512 on meshes of at
                               * least 2^20 nodes, else 256), or 128, 256 or 512.  Results do not
                               * depend on it */

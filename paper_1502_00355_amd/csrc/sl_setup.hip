@@ -990,9 +990,21 @@ void devmesh_free(DevMesh& m, hipStream_t st)
 // against 0.096 and 0.100 ms).
 constexpr int32_t kLargeClassMesh = 1 << 20;
 
+// Form A tiles of 512 nodes from this many mesh nodes up, else 256, when
+// neither the options nor sl_autotune fix the size (batches, servers and
+// handles fix it before setup, so that one work list has one size).  A
+// small mesh's sweep is one round of tiles, so smaller tiles finish sooner:
+// Delaunay meshes of 10K, 30K and 100K points took 8.3, 9.4 and 11.2 us per
+// sweep with 256 against 10.4, 10.8 and 12.1 with 512; the 1024^2 grid
+// 0.033 ms with either.
+constexpr int32_t kLargeTileMesh = 1 << 19;
+
 static int32_t tile_size_for(const sl_options& o, int32_t n)
 {
-    if (o.form == SL_JACOBI) return resolve_tile_nodes(o);
+    if (o.form == SL_JACOBI) {
+        if (o.tile_nodes || tuned_shape().tile_nodes) return resolve_tile_nodes(o);
+        return n >= kLargeTileMesh ? 512 : 256;
+    }
     if (o.tile_nodes) return o.tile_nodes;
     return n >= kLargeClassMesh ? 512 : 256;
 }
