@@ -787,10 +787,9 @@ struct ClassSweepArgs {
 // ranges, one per XCD (work-groups are dealt to the XCDs round-robin), so
 // that neighbouring tiles share an L2; the work-groups of an XCD take its
 // tiles round-robin.  The displacement maximum and accepted count run per
-// work-item over the group's tiles and are folded into the mesh's state
-// when the mesh changes and at the end: one atomic pair per group and mesh
-// (with a group per tile, tens of thousands of atomics on the same two
-// words per launch queued behind each other).
+// work-item over the group's tiles and are folded once per launch through
+// the per-group slots (with a group per tile, tens of thousands of atomics
+// on the same two words per launch queued behind each other).
 // Old and new quality over the fan entries [g_begin, g_end) of one node,
 // all with stored position P, folded into the running minima.  Entries are
 // read a group at a time with clamped indices so that their dependent LDS
