@@ -129,9 +129,8 @@ typedef struct {
                               * least 2^20 nodes, else 256), or 128, 256 or 512.  Results do not
                               * depend on it */
     int32_t tile_wg_per_cu;  /* tile-kernel work-groups per compute unit: 0 = automatic (the
-                              * value sl_autotune chose, else as many as fit, at most 4; at
-                              * most 3 on launches of fewer than 16384 tiles), or 1..8, capped
-                              * by what fits in LDS; results do not depend on it */
+                              * value sl_autotune chose, else as many as fit, at most 4), or
+                              * 1..8, capped by what fits in LDS; results do not depend on it */
     int32_t precision;       /* sl_precision */
     int32_t lane_width;      /* SL_KERNEL_LANES: work-items per free node, 0 = automatic (the
                               * value sl_autotune chose on this device, else 8), or 4, 8 or 16;

@@ -262,8 +262,7 @@ sl_status run_device(double* coords, int32_t n, const int32_t* nbr_ptr, const in
     // with a tolerance, a launch on a converged mesh returns at once; a tile
     // launch closes its own sweep
     const TileLaunch L{cs.m.work, cs.m.n_tiles, cs.m.tile_nodes, cs.m.halo_max, cs.m.rows_max, o.layout, o.accept,
-                       cs.state, resolve_wg_per_cu(o), tol2 > 0.0 ? 1 : 0, o.precision, cs.sched, 1,
-                       o.tile_wg_per_cu == 0 ? 1 : 0, 1};
+                       cs.state, resolve_wg_per_cu(o), tol2 > 0.0 ? 1 : 0, o.precision, cs.sched, 1, 1};
     auto enqueue = [&](int32_t s, hipStream_t on) -> sl_status {
         uint64_t* bits = cs.bits ? cs.bits + static_cast<int64_t>(s) * words : nullptr;
         if (tiles && cs.m.n_tile_classes > 0) {

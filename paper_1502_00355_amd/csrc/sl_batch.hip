@@ -270,7 +270,7 @@ sl_status sl_batch_smooth(const sl_mesh_desc* meshes, int32_t n_meshes, int32_t 
     // ---- the sweep loop, captured once and replayed
     const TileLaunch L{bs.work, static_cast<int32_t>(total_tiles), T, halo_cap, rows_cap, o.layout, o.accept,
                        bs.states, resolve_wg_per_cu(o), (n_meshes == 1 && tol2 > 0.0) ? 1 : 0, o.precision,
-                       bs.sched, all_tiles ? n_meshes : 0, wg_auto};
+                       bs.sched, all_tiles ? n_meshes : 0};
     const int32_t block = resolve_block_size(o);
     const int32_t chunk = iterations <= 128 ? iterations + (iterations & 1) : 64;   // even: parity repeats
     auto enqueue_chunk = [&]() -> sl_status {
@@ -286,7 +286,7 @@ sl_status sl_batch_smooth(const sl_mesh_desc* meshes, int32_t n_meshes, int32_t 
                     for (int32_t c = 0; c < m.n_tile_classes && !rr; ++c) {
                         TileLaunch Lc{m.work + m.class_tile_h[c], m.class_tile_h[c + 1] - m.class_tile_h[c],
                                       m.tile_nodes, m.halo_max, m.rows_max, o.layout, o.accept, bs.states,
-                                      wg_auto ? 0 : o.tile_wg_per_cu, 0, o.precision, bs.sched, 0, wg_auto};
+                                      wg_auto ? 0 : o.tile_wg_per_cu, 0, o.precision, bs.sched, 0};
                         rr = launch_sweep_class(Lc, m.fans_max, nullptr, st);
                     }
                     continue;

@@ -580,15 +580,11 @@ struct TileLaunch {
     // > 0: the launch's last work-group closes the sweep of
     // states[0..n_close), in place of a launch_advance after it
     int32_t n_close;
-    // 1: wg_per_cu is the automatic value (tuned, or 0 for the default),
-    // which launches of fewer than kSmallLaunchTiles tiles cap at 3
-    int32_t wg_auto;
     // 1: every tile is of one mesh; its work-groups hand their folds to the
     // closing group through per-group slots instead of atomics on the one
     // state (atomics on one address are serialised)
     int32_t one_mesh = 0;
 };
-constexpr int kSmallLaunchTiles = 16384;
 sl_status launch_sweep_tiles(const TileLaunch& L, int32_t parity, uint64_t* bits, hipStream_t st);
 // Queues one class launch of Form B on colour-class tiles (L.work: the
 // class's tiles, whose `tris` are u16 fan entries; fans_cap: the longest fan
@@ -635,7 +631,7 @@ sl_status launch_sweep_resident(const ResidentArgs* list, int32_t count, size_t 
 sl_status launch_advance(MeshState* states, int32_t n, hipStream_t st);
 
 // Work-group count of a tile launch (persistent work-groups, XCD-aware).
-int tile_grid(int n_work, int tile_nodes, int halo_cap, int rows_cap, int wg_per_cu, int32_t precision, bool wg_auto);
+int tile_grid(int n_work, int tile_nodes, int halo_cap, int rows_cap, int wg_per_cu, int32_t precision);
 
 // Exclusive scan of n int32 values; out[n] receives the total (out has n+1).
 // Temporaries come from `scratch` when given (and are given back before

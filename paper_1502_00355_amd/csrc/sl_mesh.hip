@@ -191,7 +191,7 @@ struct sl_mesh {
     {
         // one mesh per launch: a launch on a mesh that has stopped returns at once
         return sl::TileLaunch{m.work, m.n_tiles, m.tile_nodes, m.halo_max, m.rows_max, o.layout, o.accept,
-                              state,  sl::resolve_wg_per_cu(o), 1, o.precision, sched, 1, wg_auto, 1};
+                              state,  sl::resolve_wg_per_cu(o), 1, o.precision, sched, 1, 1};
     }
 
     // One sweep reading buffer `parity` (Form A) and closing it.
@@ -598,8 +598,7 @@ sl_status sl_mesh_smooth_batch_async(sl_mesh* const* meshes, int32_t n_meshes, i
     const bool all_tiles = jacobi && total_tiles > 0 && !any_node;
     const sl_options& o = first->o;
     const TileLaunch L{work,  static_cast<int32_t>(total_tiles), T, halo_cap, rows_cap, o.layout, o.accept,
-                       states, resolve_wg_per_cu(o), 0, o.precision, sched, all_tiles ? n_meshes : 0,
-                       first->wg_auto};
+                       states, resolve_wg_per_cu(o), 0, o.precision, sched, all_tiles ? n_meshes : 0};
     int32_t done = 0;
     std::vector<MeshState> back;
     while (done < iterations) {

@@ -210,7 +210,7 @@ struct HipExec {
         bool all_tiles = jacobi && n_work > 0;
         for (Req* q : in_step) all_tiles = all_tiles && q->x.mesh.tile_nodes > 0;
         const TileLaunch L{work,       n_work, T, hcap, rcap, opts.layout, opts.accept, states, wg_per_cu, 0,
-                           opts.precision, sched, all_tiles ? max_active : 0, wg_auto};
+                           opts.precision, sched, all_tiles ? max_active : 0};
         for (int32_t k = 0; k < sweeps && !r; ++k) {
             if (jacobi && n_work > 0) r = launch_sweep_tiles(L, parity, nullptr, st_compute);
             for (Req* q : in_step) {
@@ -223,7 +223,7 @@ struct HipExec {
                     for (int32_t c = 0; c < m.n_tile_classes && !r; ++c) {
                         TileLaunch Lc{m.work + m.class_tile_h[c], m.class_tile_h[c + 1] - m.class_tile_h[c],
                                       m.tile_nodes, m.halo_max, m.rows_max, opts.layout, opts.accept, states,
-                                      wg_auto ? 0 : wg_per_cu, 0, opts.precision, sched, 0, wg_auto};
+                                      wg_auto ? 0 : wg_per_cu, 0, opts.precision, sched, 0};
                         r = launch_sweep_class(Lc, m.fans_max, nullptr, st_compute);
                     }
                     continue;

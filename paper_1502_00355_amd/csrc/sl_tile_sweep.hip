@@ -533,18 +533,17 @@ size_t tile_lds_bytes(int tile_nodes, int halo_cap, int rows_cap, int32_t precis
            static_cast<size_t>(rows_cap) * 2;
 }
 
-int tile_grid(int n_work, int tile_nodes, int halo_cap, int rows_cap, int wg_per_cu, int32_t precision, bool wg_auto)
+int tile_grid(int n_work, int tile_nodes, int halo_cap, int rows_cap, int wg_per_cu, int32_t precision)
 {
     const size_t lds = tile_lds_bytes(tile_nodes, halo_cap, rows_cap, precision);
     // work-groups per CU: as requested (else 4), no more than fit the LDS;
-    // 32 CUs per XCD; never more work-groups than tiles on an XCD.  An
-    // automatic count is capped at 3 below kSmallLaunchTiles tiles: with
-    // only a few tiles per group, 4 groups per CU were slower (1024^2 grid:
-    // 0.062 against 0.040 ms; 2048^2: 0.123 against 0.104 ms; 4096^2: 0.339
-    // against 0.348 ms, where 4 stays).
+    // 32 CUs per XCD; never more work-groups than tiles on an XCD.  (Small
+    // launches were capped at 3 per CU while every group ended with atomics
+    // on the mesh's state; with the folds through slots 4 is faster there
+    // too: 1024^2 grid 0.0305 against 0.0325 ms, 2048^2 0.0842 against
+    // 0.0889 ms.)
     const int fit = std::max(1, static_cast<int>(kTileLdsLimit / std::max<size_t>(lds, 1)));
-    int want = wg_per_cu > 0 ? wg_per_cu : 4;
-    if (wg_auto && n_work < kSmallLaunchTiles) want = std::min(want, 3);
+    const int want = wg_per_cu > 0 ? wg_per_cu : 4;
     const int per_cu = std::min(want, fit);
     const int tpx = div_up(std::max(n_work, 1), 8);
     const int nw = std::min(tpx, 32 * per_cu);
@@ -569,7 +568,7 @@ sl_status launch_sweep_tiles(const TileLaunch& L, int32_t parity, uint64_t* bits
     a.n_close = L.n_close;
     a.one_mesh = L.one_mesh;
     const size_t lds = tile_lds_bytes(L.tile_nodes, L.halo_cap, L.rows_cap, L.precision);
-    const int grid = tile_grid(L.n_work, L.tile_nodes, L.halo_cap, L.rows_cap, L.wg_per_cu, L.precision, L.wg_auto != 0);
+    const int grid = tile_grid(L.n_work, L.tile_nodes, L.halo_cap, L.rows_cap, L.wg_per_cu, L.precision);
     if (grid > kTileMaxGroups) return fail(SL_EINVAL, "internal: tile launch of more groups than slots");
     const bool soa = L.layout == SL_SOA, gt = L.accept == SL_ACCEPT_GT;
     if (L.precision == SL_F32) {

@@ -128,7 +128,7 @@ sl_status tune_tiles(const sl_mesh_desc* meshes, const std::vector<int32_t>& sam
         std::vector<int32_t> shapes;
         int last_grid = -1;
         for (int32_t w = 1; w <= 8; ++w) {
-            const int grid = tile_grid(static_cast<int>(tiles), T, hcap, rcap, w, o.precision, false);
+            const int grid = tile_grid(static_cast<int>(tiles), T, hcap, rcap, w, o.precision);
             if (grid == last_grid) continue;   // capped by LDS or by the tile count: same launch
             last_grid = grid;
             shapes.push_back(w);
